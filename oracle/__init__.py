@@ -1,0 +1,313 @@
+"""FP64 CPU oracle for the batched RayCast of the Voronoi Graph method
+(Sikorski & Heida, arXiv 2405.10050).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library (``paper_2405_10050_amd``) and never imports it.
+
+The arithmetic lives in ``vgoracle.c`` (plain C, FP64, OpenMP over independent
+rays); this module compiles it with gcc, loads it with ctypes and adds the
+Monte-Carlo sums of Sec. 3.1 / Algorithm 3 with NumPy in FP64.
+
+Inputs are the float32 arrays the GPU receives, promoted exactly to float64.
+
+Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
+  raycast / raycast_cells   bisection of nearest-generator membership along the
+                            ray; incircle criterion of the hit (equidistant to
+                            g and j, no node closer); Algorithm 1
+                            (``raycast_incircle``); a lone generator exits
+                            through a face of the cube.
+  explore                   brute-force enumeration of empty circumspheres on
+                            tiny inputs; 2-D Euler relation with an
+                            independently computed hull; every edge seen by
+                            exactly two vertices or once with an unbounded
+                            ray; simplex volumes sum to the hull volume;
+                            scipy's Delaunay on the 2-D workload.
+  mc_volume_area            volume-from-areas identity of Sec. 3.3 per ray;
+                            volumes sum to 1 within Monte-Carlo error; exact
+                            2-D polygon areas and edge lengths from half-plane
+                            clipping; the jittered cubic lattice.
+  mc_adjoint                central finite differences of the FP64 estimator
+                            with frozen directions; the centroidal-energy
+                            gradient identity 2 V (x - c).
+No oracle function is unpinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vgoracle.c")
+_LIB = os.path.join(_HERE, "libvgoracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile ``vgoracle.c`` with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-Wall", "-Wno-unused-function", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        lib.vgo_raycast.argtypes = [i32, i64, P, i64, P, P, P, P, i32, i32, P, P, P]
+        lib.vgo_raycast_cells.argtypes = [i32, i64, P, i64, P, i32, P, P, P, P]
+        lib.vgo_raycast_incircle.argtypes = [i32, i64, P, i64, P, P, P, i32, i32, P, P, P]
+        lib.vgo_explore.argtypes = [i32, i64, P, P, i32, i32]
+        lib.vgo_explore.restype = P
+        for f in ("vgo_mesh_nv", "vgo_mesh_nb", "vgo_mesh_raycasts", "vgo_mesh_nn_calls",
+                  "vgo_mesh_duplicates"):
+            getattr(lib, f).argtypes = [P]
+            getattr(lib, f).restype = i64
+        lib.vgo_mesh_copy.argtypes = [P, P, P, P, P]
+        lib.vgo_mesh_free.argtypes = [P]
+        lib.vgo_circumcentre.argtypes = [i32, P, P, P]
+        lib.vgo_search_direction.argtypes = [i32, P, P, i32, P]
+        lib.vgo_mc_ray_weights.argtypes = [i32, i64, P, i64, P, i32, P, P, P, P, P, P]
+        lib.vgo_mc_adjoint.argtypes = [i32, i64, P, i64, P, i32, P, P, P, dbl, P, P, P, P]
+        lib.vgo_num_threads.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def num_threads() -> int:
+    return int(_load().vgo_num_threads())
+
+
+def sphere_area(d: int) -> float:
+    """S_{d-1} = 2 pi^{d/2} / Gamma(d/2), the area of the unit sphere in R^d
+    (Sec. 3.1)."""
+    return 2.0 * math.pi ** (d / 2.0) / math.gamma(d / 2.0)
+
+
+# --------------------------------------------------------------------------
+# O1: RayCast by definition
+# --------------------------------------------------------------------------
+def raycast(nodes, origin, direction, gen, excl=None, clip=True):
+    """Brute-force RayCast of arbitrary rays (eq. (t) with the half-space
+    restriction of Algorithm 1).  Returns float64 ``t`` (inf: no hit), int32
+    ``idx`` and the second-smallest candidate ``t2``."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    O = _f64(origin).reshape(-1, d)
+    U = _f64(direction).reshape(-1, d)
+    m = O.shape[0]
+    g = _i32(gen).reshape(m)
+    if excl is None:
+        E, ne = None, 0
+    else:
+        E = _i32(excl).reshape(m, -1)
+        ne = E.shape[1]
+    t = np.empty(m)
+    idx = np.empty(m, dtype=np.int32)
+    t2 = np.empty(m)
+    rc = lib.vgo_raycast(d, n, _p(X), m, _p(O), _p(U), _p(g), _p(E), ne, int(bool(clip)),
+                         _p(t), _p(idx), _p(t2))
+    assert rc == 0
+    return t, idx, t2
+
+
+def raycast_cells(nodes, cells, dirs):
+    """Monte-Carlo rays of Algorithm 3: ray k of listed cell c starts at
+    x_{cells[c]} with eta = {cells[c]} and is clipped to the unit cube.
+    ``dirs`` is ``[len(cells)][n_rays][d]``.  Returns flat arrays of
+    ``len(cells) * n_rays`` entries (cell-major)."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())
+    D = _f64(dirs).reshape(cells.size, -1, d)
+    nr = D.shape[1]
+    m = cells.size * nr
+    t = np.empty(m)
+    idx = np.empty(m, dtype=np.int32)
+    t2 = np.empty(m)
+    rc = lib.vgo_raycast_cells(d, n, _p(X), cells.size, _p(cells), nr, _p(D), _p(t), _p(idx),
+                               _p(t2))
+    assert rc == 0
+    return t, idx, t2
+
+
+def raycast_incircle(nodes, origin, direction, eta, heuristic=False):
+    """Algorithm 1 (iterative incircle RayCast) with a brute-force ``nn``;
+    clipping off.  ``eta`` is ``[m][n_eta]`` with ``eta[:,0]`` the generator
+    x_0 of eq. (t).  Returns ``t``, ``idx`` and the number of ``nn`` calls."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    O = _f64(origin).reshape(-1, d)
+    U = _f64(direction).reshape(-1, d)
+    m = O.shape[0]
+    E = _i32(eta).reshape(m, -1)
+    t = np.empty(m)
+    idx = np.empty(m, dtype=np.int32)
+    calls = np.empty(m, dtype=np.int64)
+    rc = lib.vgo_raycast_incircle(d, n, _p(X), m, _p(O), _p(U), _p(E), E.shape[1],
+                                  int(bool(heuristic)), _p(t), _p(idx), _p(calls))
+    assert rc == 0
+    return t, idx, calls
+
+
+def near_tie(t, t2, rel: float = 1e-9):
+    """Rays whose best and second-best candidates are within ``rel`` of each
+    other: several answers are correct there, so argmin parity excuses them."""
+    t = np.asarray(t)
+    t2 = np.asarray(t2)
+    with np.errstate(invalid="ignore"):
+        return np.isfinite(t2) & ((t2 - t) <= rel * np.abs(t))
+
+
+# --------------------------------------------------------------------------
+# O2: Algorithm 2
+# --------------------------------------------------------------------------
+def explore(nodes, draws, mode: int = 0):
+    """Exhaustive VoronoiGraph search (Algorithm 2) of the unbounded diagram.
+
+    ``mode`` 0 casts rays by definition, 1 and 2 with Algorithm 1 without and
+    with InitialHeuristic (then ``nn_calls`` counts its nearest-neighbour
+    calls).  Returns a dict with ``sigma`` ``[V][d+1]`` (sorted tuples, in
+    discovery order), ``coord`` ``[V][d]``, ``b_sigma``, ``b_omit`` and the
+    counters ``raycasts``, ``nn_calls``, ``duplicates``."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    W = _f64(draws).reshape(-1, d)
+    h = lib.vgo_explore(d, n, _p(X), _p(W), W.shape[0], int(mode))
+    if not h:
+        raise RuntimeError("oracle explore failed (descent exhausted or singular vertex)")
+    try:
+        nv, nb = lib.vgo_mesh_nv(h), lib.vgo_mesh_nb(h)
+        sig = np.empty((nv, d + 1), dtype=np.int32)
+        coord = np.empty((nv, d))
+        bsig = np.empty((nb, d + 1), dtype=np.int32)
+        bomit = np.empty(nb, dtype=np.int32)
+        lib.vgo_mesh_copy(h, _p(sig), _p(coord), _p(bsig), _p(bomit))
+        return dict(sigma=sig, coord=coord, b_sigma=bsig, b_omit=bomit,
+                    raycasts=int(lib.vgo_mesh_raycasts(h)), nn_calls=int(lib.vgo_mesh_nn_calls(h)),
+                    duplicates=int(lib.vgo_mesh_duplicates(h)))
+    finally:
+        lib.vgo_mesh_free(h)
+
+
+def circumcentre(nodes, sigma):
+    lib = _load()
+    X = _f64(nodes)
+    d = X.shape[1]
+    s = _i32(sigma)
+    v = np.empty(d)
+    assert lib.vgo_circumcentre(d, _p(X), _p(s), _p(v)) == 0
+    return v
+
+
+def search_direction(nodes, eta, omit):
+    lib = _load()
+    X = _f64(nodes)
+    d = X.shape[1]
+    e = _i32(eta)
+    u = np.empty(d)
+    assert lib.vgo_search_direction(d, _p(X), _p(e), int(omit), _p(u)) == 0
+    return u
+
+
+def sorted_rows(a):
+    """Rows of an integer array in lexicographic order (for set comparison)."""
+    a = np.asarray(a)
+    if a.size == 0:
+        return a.reshape(0, a.shape[1] if a.ndim == 2 else 0)
+    order = np.lexsort(a.T[::-1])
+    return a[order]
+
+
+# --------------------------------------------------------------------------
+# O3: Monte-Carlo estimators (Sec. 3.1, Algorithm 3 with f = 1, m = 0)
+# --------------------------------------------------------------------------
+def mc_volume_area(nodes, cells, dirs, rays=None):
+    """Monte-Carlo volume, interface areas and second moment of the listed
+    cells.
+
+    With ``l`` = t* and ``S = S_{d-1}``:
+      volume_i  = S/(d n) sum_k l_k^d
+      area_ij   = S/n     sum_{k: j_k = j} l_k^{d-1} / |n_ij . u_k|
+      energy2_i = S/((d+2) n) sum_k l_k^{d+2}     (= int_{C_i} |y - x_i|^2 dy)
+    Facets toward the cube are keyed by the negative face code of the ray
+    result.  Returns a dict with ``volume``, ``energy2`` (per listed cell),
+    ``facets`` (dict ``(i, j) -> area``) and the per-ray ``t``, ``idx``,
+    ``t2`` and ``w_vol``, ``w_area``, ``w_energy``.
+    """
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())
+    D = _f64(dirs).reshape(cells.size, -1, d)
+    nr = D.shape[1]
+    if rays is None:
+        t, idx, t2 = raycast_cells(X, cells, D)
+    else:
+        t, idx, t2 = rays
+        t = _f64(t)
+        idx = _i32(idx)
+    m = t.size
+    wv, wa, we = np.empty(m), np.empty(m), np.empty(m)
+    rc = lib.vgo_mc_ray_weights(d, n, _p(X), cells.size, _p(cells), nr, _p(D), _p(t), _p(idx),
+                                _p(wv), _p(wa), _p(we))
+    assert rc == 0, "ray without a hit in a Monte-Carlo cell"
+    S = sphere_area(d)
+    volume = S / (d * nr) * wv.reshape(cells.size, nr).sum(axis=1)
+    energy2 = S / ((d + 2) * nr) * we.reshape(cells.size, nr).sum(axis=1)
+    facets = {}
+    cell_of_ray = np.repeat(cells, nr)
+    for k in range(m):
+        key = (int(cell_of_ray[k]), int(idx[k]))
+        facets[key] = facets.get(key, 0.0) + wa[k]
+    for key in facets:
+        facets[key] *= S / nr
+    return dict(volume=volume, energy2=energy2, facets=facets, t=t, idx=idx, t2=t2,
+                w_vol=wv, w_area=wa, w_energy=we)
+
+
+def mc_adjoint(nodes, cells, dirs, t, idx, g_volume=None, g_energy2=None, g_area_ray=None):
+    """Closed-form gradient, with respect to all generator positions, of
+    ``sum_c g_volume[c] volume_c + g_energy2[c] energy2_c + sum_k g_area_ray[k]
+    area-term_k`` with frozen directions.  ``g_area_ray[k]`` is the upstream
+    weight of the facet ray ``k`` contributes to.  Returns ``[n][d]`` float64."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())
+    D = _f64(dirs).reshape(cells.size, -1, d)
+    nr = D.shape[1]
+    grad = np.zeros((n, d))
+    gv = None if g_volume is None else _f64(g_volume)
+    ge = None if g_energy2 is None else _f64(g_energy2)
+    ga = None if g_area_ray is None else _f64(g_area_ray)
+    rc = lib.vgo_mc_adjoint(d, n, _p(X), cells.size, _p(cells), nr, _p(D), _p(_f64(t)),
+                            _p(_i32(idx)), sphere_area(d), _p(gv), _p(ge), _p(ga), _p(grad))
+    assert rc == 0
+    return grad
