@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched Monte-Carlo RayCast on one MI355X.
+
+Workload (default): the d=10 Gaussian-mixture cloud, N = 100 000 generators
+(8 isotropic components, sigma 0.05, centres uniform in [0.2, 0.8]^10, rows
+outside the unit cube redrawn), 1024 uniform directions per cell, i.e.
+1.024e8 rays.  One step = the whole hot path on that batch: the MFMA candidate
+scan with its fused top-2 epilogue, cube clip and winner re-evaluation, the
+FP64 recheck of uncertain rays, the per-cell volume / second-moment / facet
+accumulation, and the adjoint of the volume, second moment and facet areas
+with respect to all generator positions.  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_MFMA_PEAK = 157.3e12   # MI355X dense FP32 matrix, FLOP/s
+BF16_MFMA_PEAK = 2.5e15     # MI355X dense BF16 matrix, FLOP/s
+
+
+def directions_threaded(cells, R, d, seed, workers=8):
+    """Same draws as workloads.mc_directions, generated on a thread pool."""
+    import concurrent.futures as cf
+
+    import workloads as W
+
+    cells = np.asarray(cells)
+    out = np.empty((cells.size, R, d), dtype=np.float32)
+    chunks = np.array_split(np.arange(cells.size), max(1, workers * 8))
+
+    def work(ix):
+        if ix.size:
+            out[ix] = W.mc_directions(cells[ix], R, d, seed=seed)
+
+    with cf.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(work, chunks))
+    return out
+
+
+def cpu_baseline(X, cells, Ds):
+    """The FP64 oracle on a bounded sample of the same workload (all host
+    threads): RayCast of the sampled cells' rays over all nodes plus their
+    Monte-Carlo sums.  ``Ds`` holds the sampled cells' directions."""
+    import oracle
+
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.mc_volume_area(X, cells, Ds)
+    dt = time.perf_counter() - t0
+    rays = cells.size * Ds.shape[1]
+    return dict(value=rays / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{cells.size} random cells x {Ds.shape[1]} rays of the same workload "
+                       f"({rays} rays, each over all {X.shape[0]} nodes; {dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--rays", type=int, default=1024)
+    ap.add_argument("--cpu-cells", type=int, default=8, help="oracle sample size (0: skip)")
+    ap.add_argument("--no-backward", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
+              "over cells with no exchange, see DESIGN.md", file=sys.stderr)
+        sys.exit(1)
+
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    d, n, R = 10, args.n, args.rays
+    t_setup = time.perf_counter()
+    X = W.gaussian_mixture_cloud(n=n, d=d, seed=0)
+    D = directions_threaded(np.arange(n), R, d, seed=1)
+    print(f"[bench] inputs ready in {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    nodes = torch.from_numpy(X).to(dev)
+    dirs = torch.from_numpy(D).to(dev)
+    del D  # the CPU baseline regenerates the directions of its sample
+    res = vg.mc_volume_area(nodes, dirs, precision=args.precision)
+    g_vol = torch.ones(n, device=dev)
+    g_en = torch.ones(n, device=dev)
+    g_fa = torch.ones((n, R), device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        vg.mc_volume_area(nodes, dirs, precision=args.precision, out=res)
+        if not args.no_backward:
+            vg.mc_backward(nodes, dirs, res, g_vol, g_en, g_fa)
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    st = vg.stats()
+    vg.set_profiling(True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for k in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    st = vg.stats()
+    vg.set_profiling(False)
+    flagged = st["flagged"]
+    print(f"[bench] {args.steps} steps in {total_ms:.1f} ms", file=sys.stderr, flush=True)
+
+    ms_step = total_ms / args.steps
+    rays = n * R
+    value = rays / (ms_step / 1e3)
+    scan_ms = st["scan_ms"] / max(1, st["scan_launches"])
+    flops = 2.0 * d * n * rays + 2.0 * d * n * n  # U.R~^T per ray + X.R^T per cell
+    if args.precision == "bf16x3":
+        achieved = 3.0 * flops / (scan_ms / 1e3)
+        peak, unit = BF16_MFMA_PEAK, "TFLOP/s"
+    else:
+        achieved = flops / (scan_ms / 1e3)
+        peak, unit = FP32_MFMA_PEAK, "TFLOP/s"
+
+    out = {
+        "metric": "rays/sec batched RayCast (d=10,N=100k) at 1e-5 rel err; MC volume+grad cells/s",
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {
+            "workload": f"gaussian-mixture d={d} N={n}, {R} MC rays per cell "
+                        "(RayCast + FP64 recheck + volume/area/second moment + adjoint)",
+            "d": d, "n_nodes": n, "rays_per_cell": R, "rays": rays,
+            "cells_per_s": n / (ms_step / 1e3),
+            "flagged_rays_per_step": flagged,
+            "backward": not args.no_backward,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": f"cell_scan_{args.precision}",
+            "achieved": achieved / 1e12,
+            "peak": peak / 1e12,
+            "unit": unit,
+            "frac": achieved / peak,
+            "traffic": None,
+            "scan_ms": scan_ms,
+        },
+    }
+    if args.cpu_cells > 0:
+        rng = np.random.default_rng(123)
+        sample = np.sort(rng.choice(n, args.cpu_cells, replace=False))
+        out["cpu_baseline"] = cpu_baseline(X, sample, directions_threaded(sample, R, d, seed=1))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * vgraph.h -- C ABI of the MI355X (gfx950) batched RayCast library for the
+ * Voronoi Graph method (Sikorski & Heida, arXiv 2405.10050).
+ *
+ * The library computes the RayCast of Sec. 2.2: for a ray with origin x
+ * (equidistant to the known generators eta, in the cell of g = eta[0]) and
+ * direction u, the first bisector hit
+ *
+ *     t* = min over nodes r not in eta with u.(r - g) > 0 of
+ *          (|r - x|^2 - |g - x|^2) / (2 u.(r - g))          (eq. (t))
+ *
+ * and its argmin, optionally clipped to the unit cube [0,1]^d.  On top of it
+ * sit the Monte-Carlo volume / interface-area estimators of Sec. 3.1
+ * (Algorithm 3), their adjoint with respect to the generator positions, and
+ * the exhaustive vertex search of Sec. 2.3 (Algorithm 2).
+ *
+ * Conventions shared by every call
+ *  - All array arguments are DEVICE pointers on the context's device unless
+ *    stated otherwise, row-major and densely packed.  The caller owns them;
+ *    the library never frees or keeps them past the call.
+ *  - Work is enqueued on the context's stream (vg_set_stream); calls return
+ *    without synchronising unless stated otherwise.  Outputs are valid once
+ *    the stream has reached the call.
+ *  - Every call returns a vg_status.  Arguments are validated before any
+ *    launch; on error nothing is launched and vg_last_error() describes it.
+ *  - 2 <= d <= VG_MAX_DIM.  Node indices are int32 (n_nodes < 2^31).
+ *  - A ray result index idx >= 0 is a node; -1 means no hit (the ray leaves
+ *    to infinity); -2-(2k+s) is the face x_k = s of the unit cube (s = 0, 1).
+ *  - Ties: equal t goes to the lowest node index, and a node beats a face of
+ *    the cube.  The scan runs in FP32; a ray whose two best candidates are
+ *    within a relative gap VG_TIE_EPS (or whose result could hinge on FP32
+ *    rounding) is re-evaluated over all nodes in FP64 and flagged.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef VGRAPH_H
+#define VGRAPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VG_MAX_DIM 16
+
+typedef enum vg_status {
+  VG_OK = 0,
+  VG_EINVAL = -1,       /* bad argument (null pointer, size, dimension)      */
+  VG_ENOMEM = -2,       /* device or host allocation failed                  */
+  VG_EDEVICE = -3,      /* a HIP call failed                                 */
+  VG_EUNSUPPORTED = -4  /* valid request outside what this build supports    */
+} vg_status;
+
+/* flags */
+#define VG_CLIP (1u << 0)        /* clip rays to the unit cube                 */
+#define VG_PREC_BF16X3 (1u << 1) /* Monte-Carlo scan in split BF16x3 MFMA       */
+#define VG_NO_RECHECK (1u << 2)  /* skip the FP64 re-evaluation (diagnostics)  */
+
+/* per-ray status bits (uint8) */
+#define VG_ST_NEAR_TIE 1  /* FP32 gap of the two best candidates below VG_TIE_EPS */
+#define VG_ST_RECHECKED 2 /* result re-evaluated over all nodes in FP64          */
+#define VG_ST_NO_HIT 4    /* no node ahead of the ray (t = +inf, idx = -1)       */
+#define VG_ST_SUSPECT 8   /* winner nearly parallel to its bisector in FP32      */
+#define VG_ST_FP64_TIE 16 /* FP64 gap below 1e-9: several answers are correct    */
+
+typedef struct vg_ctx vg_ctx;
+typedef struct vg_mesh vg_mesh;
+
+typedef struct vg_stats {
+  int64_t rays;          /* rays of the last call                              */
+  int64_t flagged;       /* rays re-evaluated in FP64 by the last call          */
+  int64_t fp64_ties;     /* of those, rays with an FP64 near-tie                 */
+  double tie_eps;        /* relative FP32 gap that triggers the FP64 recheck    */
+  int64_t scan_launches; /* candidate-scan launches timed since profiling began */
+  double scan_ms;        /* their summed duration (HIP events on the stream)    */
+} vg_stats;
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device` with the null stream.  Allocates a
+ * small amount of device memory; scratch grows on demand and is kept until
+ * vg_destroy.  Returns VG_EDEVICE if the device is absent or not gfx950. */
+int vg_create(int device, vg_ctx **out);
+void vg_destroy(vg_ctx *ctx);
+/* Bind a hipStream_t (passed as void*); NULL selects the null stream. */
+int vg_set_stream(vg_ctx *ctx, void *hip_stream);
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *vg_last_error(const vg_ctx *ctx);
+/* Counters of the last raycast-type call.  Synchronises the stream. */
+int vg_get_stats(vg_ctx *ctx, vg_stats *out);
+/* enable != 0: record a HIP event pair around every candidate-scan kernel
+ * (cell or ray scan) on the context's stream and accumulate their durations
+ * into vg_stats.scan_ms / scan_launches; enable == 0 stops and clears. */
+int vg_set_profiling(vg_ctx *ctx, int enable);
+
+/* ---------------------------------------------------------------- RayCast */
+/* RayCast of n_rays arbitrary rays (Sec. 2.2, eq. (t); the half-space
+ * restriction is the `skip` predicate of Algorithm 1).
+ *   nodes  [n_nodes][d] f32
+ *   origin [n_rays][d]  f32   ray start x (equidistant to its eta)
+ *   dir    [n_rays][d]  f32   direction u, used as given (not renormalised)
+ *   gen    [n_rays]     i32   g = eta[0], the generator in eq. (t)
+ *   excl   [n_rays][n_excl] i32, each row sorted ascending: eta (nodes never
+ *          returned); may be NULL when n_excl == 0.  0 <= n_excl <= d.
+ *   flags  VG_CLIP, VG_NO_RECHECK
+ * Outputs (all [n_rays]): t_out f32 (+inf when no hit), idx_out i32,
+ * status_out u8 (may be NULL).  n_rays == 0 is a no-op. */
+int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+               int64_t n_rays, const float *origin, const float *dir,
+               const int32_t *gen, const int32_t *excl, int n_excl,
+               uint32_t flags, float *t_out, int32_t *idx_out,
+               uint8_t *status_out);
+
+/* Monte-Carlo rays of every cell (Algorithm 3): ray k of cell i starts at
+ * x_i with eta = {i} and direction dirs[i][k], clipped to the unit cube
+ * (VG_CLIP is implied).  The candidate scan is the dense contraction of the
+ * directions with the nodes inverted about x_i, on MFMA.
+ *   dirs [n_nodes][rays_per_cell][d] f32 unit vectors
+ *   flags VG_PREC_BF16X3, VG_NO_RECHECK
+ * Outputs [n_nodes * rays_per_cell], cell-major: t_out, idx_out, status_out
+ * (may be NULL).  1 <= rays_per_cell <= 4096. */
+int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                     int rays_per_cell, const float *dirs, uint32_t flags,
+                     float *t_out, int32_t *idx_out, uint8_t *status_out);
+
+/* ------------------------------------------------ Monte-Carlo estimators */
+/* Sec. 3.1 / Algorithm 3 with f = 1: for every cell i, with l = t* of its
+ * rays and S = S_{d-1} = 2 pi^{d/2} / Gamma(d/2),
+ *   volume[i]  = S/(d n)     sum_k l_k^d
+ *   energy2[i] = S/((d+2) n) sum_k l_k^{d+2}   (= int_{C_i} |y - x_i|^2 dy)
+ *   area(i,j)  = S/n sum_{k: j_k = j} l_k^{d-1} / |n_ij . u_k|   (eq. dS-dA)
+ * where n = rays_per_cell and n_ij is the unit normal of the facet (for a
+ * node j, (x_j - x_i)/|x_j - x_i|; for a cube face, e_k).  Facets of cell i
+ * are written to row i of facet_j / facet_area, sorted by j as signed int32
+ * (cube faces, negative codes, first), facet_count[i] entries; the rest of
+ * the row is left untouched.
+ *   t_out, idx_out [n_nodes*n] (required: the adjoint reads them back),
+ *   status_out [n_nodes*n] u8 or NULL,
+ *   volume [n_nodes] f32 (required), energy2 [n_nodes] f32 or NULL,
+ *   facet_j [n_nodes][n] i32, facet_area [n_nodes][n] f32,
+ *   facet_count [n_nodes] i32 -- all three NULL to skip the facets. */
+int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                      int rays_per_cell, const float *dirs, uint32_t flags,
+                      float *t_out, int32_t *idx_out, uint8_t *status_out,
+                      float *volume, float *energy2, int32_t *facet_j,
+                      float *facet_area, int32_t *facet_count);
+
+/* Adjoint of vg_mc_volume_area with the directions frozen: writes
+ *   grad_nodes[n_nodes][d] = d/dX ( sum_i g_volume[i] volume[i]
+ *        + g_energy2[i] energy2[i] + sum_{i,f} g_facet_area[i][f] area(i,f) )
+ * using the closed-form derivative of t* through the winning bisector
+ * (t = |x_j - x_i|^2 / (2 u.(x_j - x_i)) for a node, (s - x_ik)/u_k for a
+ * cube face).  t, idx, facet_j, facet_count are the forward outputs.
+ * g_volume, g_energy2 [n_nodes] and g_facet_area [n_nodes][n] may each be
+ * NULL (zero).  Deterministic: the scatter onto the winning generators uses
+ * per-node fixed-point integer accumulation.  grad_nodes is overwritten. */
+int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                   int rays_per_cell, const float *dirs, const float *t,
+                   const int32_t *idx, const int32_t *facet_j,
+                   const int32_t *facet_count, const float *g_volume,
+                   const float *g_energy2, const float *g_facet_area,
+                   float *grad_nodes);
+
+/* ------------------------------------------------------ uneven batches */
+/* One independent point cloud of an uneven batch of Monte-Carlo raycasts. */
+typedef struct vg_cells_problem {
+  int d;                /* 2..VG_MAX_DIM                                */
+  int rays_per_cell;    /* 1..4096                                      */
+  int64_t n_nodes;      /* >= 1                                         */
+  const float *nodes;   /* [n_nodes][d]                                 */
+  const float *dirs;    /* [n_nodes][rays_per_cell][d]                  */
+  float *t_out;         /* [n_nodes * rays_per_cell]                    */
+  int32_t *idx_out;     /* [n_nodes * rays_per_cell]                    */
+  uint8_t *status_out;  /* [n_nodes * rays_per_cell] or NULL            */
+} vg_cells_problem;
+
+/* vg_raycast_cells over many clouds of different d and N in one persistent
+ * launch: workgroups take (cloud, cell) items from a device queue ordered by
+ * decreasing cost.  The problem table is copied to the device (host array
+ * `probs`, read during the call only). */
+int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems,
+                             const vg_cells_problem *probs, uint32_t flags);
+
+/* ------------------------------------------------------ exhaustive search */
+/* Algorithm 2 (VoronoiGraph) on the unbounded diagram: every Voronoi vertex
+ * keyed by its sorted (d+1)-tuple of generators, with FP64 coordinates
+ * solved from the tuple, and every unbounded edge as (vertex, omitted
+ * generator).  Rays are cast without clipping, in batches of one
+ * breadth-first level; the edge visit counts and vertex set live in host
+ * hash tables.  `descent_draws` is a HOST array [n_draws][d] f64 of standard
+ * normal draws consumed in order by Descent.  Synchronises the stream.
+ * The result is library-owned: query it, copy it out, free it. */
+int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+               const double *descent_draws, int n_draws, uint32_t flags,
+               vg_mesh **out);
+int64_t vg_mesh_num_vertices(const vg_mesh *mesh);
+int64_t vg_mesh_num_unbounded(const vg_mesh *mesh);
+int64_t vg_mesh_num_raycasts(const vg_mesh *mesh);
+/* HOST outputs: sigma [V][d+1] (tuples in discovery order), coords [V][d] f64
+ * or NULL, b_sigma [B][d+1] or NULL, b_omit [B] or NULL. */
+int vg_mesh_copy(const vg_mesh *mesh, int32_t *sigma, double *coords,
+                 int32_t *b_sigma, int32_t *b_omit);
+void vg_mesh_free(vg_mesh *mesh);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VGRAPH_H */

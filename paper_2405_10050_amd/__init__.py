@@ -1,0 +1,361 @@
+"""MI355X (gfx950) batched RayCast for the Voronoi Graph method
+(Sikorski & Heida, arXiv 2405.10050).
+
+Thin Python binding of ``libvgraph.so`` (C ABI, ``include/vgraph.h``): it
+checks tensors, passes device pointers and the current HIP stream, and
+allocates outputs with torch.  All arithmetic runs in the library's HIP
+kernels; there is no fallback.  Importing this package on a machine without
+the built library raises ``ImportError``; calling it without a gfx950 GPU
+raises ``VGError``.
+
+Calls (names follow the paper's statement of the problem):
+  raycast(nodes, origin, direction, gen, excl, clip)   RayCast of Sec. 2.2
+  raycast_cells(nodes, dirs)                           Monte-Carlo rays of every cell
+  mc_volume_area(nodes, dirs)                          Sec. 3.1 / Algorithm 3 estimators
+  mc_backward(...), VoronoiMC                          adjoint / autograd Function
+  raycast_cells_batched(problems)                      uneven batch of clouds
+  explore(nodes, descent_draws)                        Algorithm 2 (VoronoiGraph)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvgraph.so")
+
+VG_CLIP = 1 << 0
+VG_PREC_BF16X3 = 1 << 1
+VG_NO_RECHECK = 1 << 2
+
+ST_NEAR_TIE = 1
+ST_RECHECKED = 2
+ST_NO_HIT = 4
+ST_SUSPECT = 8
+ST_FP64_TIE = 16
+
+MAX_DIM = 16
+
+
+class VGError(RuntimeError):
+    pass
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("rays", ctypes.c_int64), ("flagged", ctypes.c_int64),
+                ("fp64_ties", ctypes.c_int64), ("tie_eps", ctypes.c_double),
+                ("scan_launches", ctypes.c_int64), ("scan_ms", ctypes.c_double)]
+
+
+class _CellsProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("rays_per_cell", ctypes.c_int), ("n_nodes", ctypes.c_int64),
+                ("nodes", ctypes.c_void_p), ("dirs", ctypes.c_void_p), ("t_out", ctypes.c_void_p),
+                ("idx_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p)]
+
+
+EXPORTS = (
+    "vg_create", "vg_destroy", "vg_set_stream", "vg_last_error", "vg_get_stats",
+    "vg_set_profiling", "vg_raycast",
+    "vg_raycast_cells", "vg_mc_volume_area", "vg_mc_backward", "vg_raycast_cells_batched",
+    "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
+    "vg_mesh_copy", "vg_mesh_free",
+)
+
+
+def _load_lib():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_2405_10050_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, U32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32
+    lib.vg_create.argtypes = [I, ctypes.POINTER(P)]
+    lib.vg_destroy.argtypes = [P]
+    lib.vg_destroy.restype = None
+    lib.vg_set_stream.argtypes = [P, P]
+    lib.vg_last_error.argtypes = [P]
+    lib.vg_last_error.restype = ctypes.c_char_p
+    lib.vg_get_stats.argtypes = [P, ctypes.POINTER(_Stats)]
+    lib.vg_set_profiling.argtypes = [P, I]
+    lib.vg_raycast.argtypes = [P, I, I64, P, I64, P, P, P, P, I, U32, P, P, P]
+    lib.vg_raycast_cells.argtypes = [P, I, I64, P, I, P, U32, P, P, P]
+    lib.vg_mc_volume_area.argtypes = [P, I, I64, P, I, P, U32, P, P, P, P, P, P, P, P]
+    lib.vg_mc_backward.argtypes = [P, I, I64, P, I, P, P, P, P, P, P, P, P, P]
+    lib.vg_raycast_cells_batched.argtypes = [P, I, ctypes.POINTER(_CellsProblem), U32]
+    lib.vg_explore.argtypes = [P, I, I64, P, P, I, U32, ctypes.POINTER(P)]
+    for f in ("vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts"):
+        getattr(lib, f).argtypes = [P]
+        getattr(lib, f).restype = I64
+    lib.vg_mesh_copy.argtypes = [P, P, P, P, P]
+    lib.vg_mesh_free.argtypes = [P]
+    lib.vg_mesh_free.restype = None
+    return lib
+
+
+_lib = _load_lib()
+_ctxs: dict[int, ctypes.c_void_p] = {}
+
+
+def _ctx(device: torch.device) -> ctypes.c_void_p:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    c = _ctxs.get(idx)
+    if c is None:
+        c = ctypes.c_void_p()
+        rc = _lib.vg_create(idx, ctypes.byref(c))
+        if rc != 0:
+            raise VGError(f"vg_create(device={idx}) failed with {rc}: no gfx950 device")
+        _ctxs[idx] = c
+    _lib.vg_set_stream(c, ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream))
+    return c
+
+
+def _check(rc: int, ctx, what: str):
+    if rc != 0:
+        msg = _lib.vg_last_error(ctx).decode()
+        raise VGError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise VGError(f"{name} must be a GPU tensor (no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+def stats(device=None) -> dict:
+    """Counters of the last raycast-type call on ``device`` (synchronises)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    c = _ctx(dev)
+    s = _Stats()
+    _check(_lib.vg_get_stats(c, ctypes.byref(s)), c, "vg_get_stats")
+    return dict(rays=s.rays, flagged=s.flagged, fp64_ties=s.fp64_ties, tie_eps=s.tie_eps,
+                scan_launches=s.scan_launches, scan_ms=s.scan_ms)
+
+
+def set_profiling(enable: bool, device=None) -> None:
+    """Time every candidate-scan kernel with HIP events on the current stream
+    (read back through ``stats()``); ``False`` stops and clears."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    c = _ctx(dev)
+    _check(_lib.vg_set_profiling(c, int(bool(enable))), c, "vg_set_profiling")
+
+
+def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True):
+    """RayCast of arbitrary rays; returns ``(t, idx, status)`` of length M."""
+    _dev(nodes, torch.float32, "nodes")
+    dev = nodes.device
+    n, d = nodes.shape
+    _dev(origin, torch.float32, "origin", dev)
+    _dev(direction, torch.float32, "direction", dev)
+    _dev(gen, torch.int32, "gen", dev)
+    m = origin.shape[0]
+    if origin.shape != (m, d) or direction.shape != (m, d) or gen.shape != (m,):
+        raise ValueError("origin/direction must be [M, d] and gen [M]")
+    ne = 0
+    if excl is not None:
+        _dev(excl, torch.int32, "excl", dev)
+        if excl.dim() != 2 or excl.shape[0] != m:
+            raise ValueError("excl must be [M, n_excl]")
+        ne = excl.shape[1]
+    t = torch.empty(m, dtype=torch.float32, device=dev)
+    idx = torch.empty(m, dtype=torch.int32, device=dev)
+    st = torch.empty(m, dtype=torch.uint8, device=dev)
+    flags = (VG_CLIP if clip else 0) | (0 if recheck else VG_NO_RECHECK)
+    c = _ctx(dev)
+    _check(_lib.vg_raycast(c, d, n, _ptr(nodes), m, _ptr(origin), _ptr(direction), _ptr(gen),
+                           _ptr(excl), ne, flags, _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast")
+    return t, idx, st
+
+
+def _cells_flags(precision: str, recheck: bool) -> int:
+    if precision not in ("fp32", "bf16x3"):
+        raise ValueError("precision must be 'fp32' or 'bf16x3'")
+    return (VG_PREC_BF16X3 if precision == "bf16x3" else 0) | (0 if recheck else VG_NO_RECHECK)
+
+
+def raycast_cells(nodes, dirs, precision="fp32", recheck=True):
+    """Monte-Carlo rays of every cell: ``dirs`` is ``[N, R, d]``; returns
+    ``(t, idx, status)`` shaped ``[N, R]``."""
+    _dev(nodes, torch.float32, "nodes")
+    dev = nodes.device
+    n, d = nodes.shape
+    _dev(dirs, torch.float32, "dirs", dev)
+    if dirs.dim() != 3 or dirs.shape[0] != n or dirs.shape[2] != d:
+        raise ValueError("dirs must be [N, R, d]")
+    R = dirs.shape[1]
+    t = torch.empty((n, R), dtype=torch.float32, device=dev)
+    idx = torch.empty((n, R), dtype=torch.int32, device=dev)
+    st = torch.empty((n, R), dtype=torch.uint8, device=dev)
+    c = _ctx(dev)
+    _check(_lib.vg_raycast_cells(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck),
+                                 _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast_cells")
+    return t, idx, st
+
+
+@dataclass
+class MCResult:
+    volume: torch.Tensor       # [N]
+    energy2: torch.Tensor      # [N]
+    facet_j: torch.Tensor      # [N, R] (first facet_count[i] entries of row i)
+    facet_area: torch.Tensor   # [N, R]
+    facet_count: torch.Tensor  # [N]
+    t: torch.Tensor            # [N, R]
+    idx: torch.Tensor          # [N, R]
+    status: torch.Tensor       # [N, R]
+
+    def facets_coo(self):
+        """Facets as host COO arrays ``(i, j, area)`` sorted by (i, j)."""
+        cnt = self.facet_count.cpu().numpy()
+        R = self.facet_j.shape[1]
+        mask = np.arange(R)[None, :] < cnt[:, None]
+        i = np.nonzero(mask)[0].astype(np.int32)
+        return i, self.facet_j.cpu().numpy()[mask], self.facet_area.cpu().numpy()[mask]
+
+
+def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out=None) -> MCResult:
+    """Monte-Carlo cell volumes, second moments and interface areas
+    (Sec. 3.1, Algorithm 3 with f = 1).  ``out`` may pass a previous
+    ``MCResult`` of the same shape to reuse its buffers."""
+    _dev(nodes, torch.float32, "nodes")
+    dev = nodes.device
+    n, d = nodes.shape
+    _dev(dirs, torch.float32, "dirs", dev)
+    if dirs.dim() != 3 or dirs.shape[0] != n or dirs.shape[2] != d:
+        raise ValueError("dirs must be [N, R, d]")
+    R = dirs.shape[1]
+    if out is None:
+        out = MCResult(
+            volume=torch.empty(n, dtype=torch.float32, device=dev),
+            energy2=torch.empty(n, dtype=torch.float32, device=dev),
+            facet_j=torch.empty((n, R), dtype=torch.int32, device=dev) if facets else None,
+            facet_area=torch.empty((n, R), dtype=torch.float32, device=dev) if facets else None,
+            facet_count=torch.empty(n, dtype=torch.int32, device=dev) if facets else None,
+            t=torch.empty((n, R), dtype=torch.float32, device=dev),
+            idx=torch.empty((n, R), dtype=torch.int32, device=dev),
+            status=torch.empty((n, R), dtype=torch.uint8, device=dev))
+    c = _ctx(dev)
+    _check(_lib.vg_mc_volume_area(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck),
+                                  _ptr(out.t), _ptr(out.idx), _ptr(out.status), _ptr(out.volume),
+                                  _ptr(out.energy2), _ptr(out.facet_j), _ptr(out.facet_area),
+                                  _ptr(out.facet_count)), c, "vg_mc_volume_area")
+    return out
+
+
+def mc_backward(nodes, dirs, res: MCResult, g_volume=None, g_energy2=None, g_facet_area=None):
+    """Gradient with respect to the generator positions of
+    ``<g_volume, volume> + <g_energy2, energy2> + <g_facet_area, facet_area>``
+    with the directions frozen.  Returns ``[N, d]`` float32."""
+    _dev(nodes, torch.float32, "nodes")
+    dev = nodes.device
+    n, d = nodes.shape
+    R = dirs.shape[1]
+    for name, g in (("g_volume", g_volume), ("g_energy2", g_energy2)):
+        if g is not None:
+            _dev(g, torch.float32, name, dev)
+            if g.shape != (n,):
+                raise ValueError(f"{name} must be [N]")
+    if g_facet_area is not None:
+        _dev(g_facet_area, torch.float32, "g_facet_area", dev)
+        if g_facet_area.shape != (n, R) or res.facet_j is None:
+            raise ValueError("g_facet_area must be [N, R] and the forward must have facets")
+    grad = torch.empty((n, d), dtype=torch.float32, device=dev)
+    c = _ctx(dev)
+    _check(_lib.vg_mc_backward(c, d, n, _ptr(nodes), R, _ptr(dirs), _ptr(res.t), _ptr(res.idx),
+                               _ptr(res.facet_j), _ptr(res.facet_count), _ptr(g_volume),
+                               _ptr(g_energy2), _ptr(g_facet_area), _ptr(grad)), c, "vg_mc_backward")
+    return grad
+
+
+class VoronoiMC(torch.autograd.Function):
+    """``(volume, energy2, facet_area) = VoronoiMC.apply(nodes, dirs)``.
+
+    The forward is ``mc_volume_area``; the backward is the closed-form adjoint
+    through the winning bisectors (``mc_backward``), directions frozen.
+    ``facet_area[i, :facet_count[i]]`` are the areas of cell i's facets; the
+    facet ids are available from ``VoronoiMC.last_result``."""
+
+    last_result: MCResult | None = None
+
+    @staticmethod
+    def forward(ctx, nodes, dirs, precision="fp32"):
+        res = mc_volume_area(nodes.detach().contiguous(), dirs, precision=precision, facets=True)
+        ctx.save_for_backward(nodes, dirs)
+        ctx.res = res
+        VoronoiMC.last_result = res
+        return res.volume, res.energy2, res.facet_area
+
+    @staticmethod
+    def backward(ctx, g_volume, g_energy2, g_facet_area):
+        nodes, dirs = ctx.saved_tensors
+        f = lambda g: None if g is None else g.contiguous().float()
+        grad = mc_backward(nodes.detach().contiguous(), dirs, ctx.res, f(g_volume), f(g_energy2),
+                           f(g_facet_area))
+        return grad, None, None
+
+
+def raycast_cells_batched(problems, precision="fp32", recheck=True):
+    """Uneven batch: ``problems`` is a list of ``(nodes [N_c, d_c], dirs
+    [N_c, R_c, d_c])``.  Returns a list of ``(t, idx, status)``."""
+    probs = (_CellsProblem * len(problems))()
+    outs = []
+    dev = None
+    for q, (nodes, dirs) in enumerate(problems):
+        _dev(nodes, torch.float32, "nodes")
+        dev = nodes.device if dev is None else dev
+        _dev(dirs, torch.float32, "dirs", dev)
+        n, d = nodes.shape
+        R = dirs.shape[1]
+        if dirs.shape != (n, R, d):
+            raise ValueError("dirs must be [N, R, d]")
+        t = torch.empty((n, R), dtype=torch.float32, device=dev)
+        idx = torch.empty((n, R), dtype=torch.int32, device=dev)
+        st = torch.empty((n, R), dtype=torch.uint8, device=dev)
+        outs.append((t, idx, st))
+        probs[q] = _CellsProblem(d, R, n, nodes.data_ptr(), dirs.data_ptr(), t.data_ptr(),
+                                 idx.data_ptr(), st.data_ptr())
+    if not problems:
+        return outs
+    c = _ctx(dev)
+    _check(_lib.vg_raycast_cells_batched(c, len(problems), probs, _cells_flags(precision, recheck)),
+           c, "vg_raycast_cells_batched")
+    return outs
+
+
+def explore(nodes, descent_draws) -> dict:
+    """Exhaustive search (Algorithm 2) of the unbounded diagram.  Returns host
+    arrays ``sigma [V, d+1]``, ``coord [V, d]`` (float64), ``b_sigma``,
+    ``b_omit`` and ``raycasts``."""
+    _dev(nodes, torch.float32, "nodes")
+    n, d = nodes.shape
+    draws = np.ascontiguousarray(np.asarray(descent_draws, dtype=np.float64).reshape(-1, d))
+    c = _ctx(nodes.device)
+    mesh = ctypes.c_void_p()
+    _check(_lib.vg_explore(c, d, n, _ptr(nodes), draws.ctypes.data_as(ctypes.c_void_p), draws.shape[0],
+                           0, ctypes.byref(mesh)), c, "vg_explore")
+    try:
+        nv = _lib.vg_mesh_num_vertices(mesh)
+        nb = _lib.vg_mesh_num_unbounded(mesh)
+        sig = np.empty((nv, d + 1), dtype=np.int32)
+        coord = np.empty((nv, d), dtype=np.float64)
+        bsig = np.empty((nb, d + 1), dtype=np.int32)
+        bomit = np.empty(nb, dtype=np.int32)
+        P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(_lib.vg_mesh_copy(mesh, P(sig), P(coord), P(bsig), P(bomit)), c, "vg_mesh_copy")
+        return dict(sigma=sig, coord=coord, b_sigma=bsig, b_omit=bomit,
+                    raycasts=int(_lib.vg_mesh_num_raycasts(mesh)))
+    finally:
+        _lib.vg_mesh_free(mesh)

@@ -1,0 +1,486 @@
+// C ABI entry points: argument validation, scratch management and kernel
+// sequencing.  No arithmetic of the method happens here.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vg_explore.h"
+#include "vg_internal.h"
+
+using namespace vg;
+
+namespace {
+
+int fail(vg_ctx *ctx, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(vg_ctx *ctx, int code, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(vg_ctx *ctx, hipError_t e, const char *what) {
+  return fail(ctx, VG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define VG_HIP(ctx, call)                          \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+// Carve a 256-byte aligned block out of the context scratch.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = reinterpret_cast<T *>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+  static size_t need(std::initializer_list<size_t> bytes) {
+    size_t s = 0;
+    for (size_t b : bytes) s = ((s + 255) & ~size_t(255)) + b;
+    return s + 256;
+  }
+};
+
+int ensure_scratch(vg_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->scratch_bytes) return VG_OK;
+  if (ctx->scratch) {
+    VG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    VG_HIP(ctx, hipFree(ctx->scratch));
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
+    ctx->scratch = nullptr;
+    return fail(ctx, VG_ENOMEM, "scratch allocation of %zu bytes failed", want);
+  }
+  ctx->scratch_bytes = want;
+  return VG_OK;
+}
+
+int check_common(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes) {
+  if (!ctx) return VG_EINVAL;
+  ctx->err.clear();
+  if (d < 2 || d > VG_MAX_DIM) return fail(ctx, VG_EUNSUPPORTED, "d=%d outside [2, %d]", d, VG_MAX_DIM);
+  if (n_nodes < 1 || n_nodes >= (int64_t(1) << 31))
+    return fail(ctx, VG_EINVAL, "n_nodes=%lld outside [1, 2^31)", (long long)n_nodes);
+  if (!nodes) return fail(ctx, VG_EINVAL, "nodes is NULL");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VG_EDEVICE, "hipSetDevice failed");
+  return VG_OK;
+}
+
+// Event pair around a scan launch when profiling (recorded on ctx->stream).
+struct ScanTimer {
+  vg_ctx *ctx;
+  hipEvent_t a = nullptr, b = nullptr;
+  explicit ScanTimer(vg_ctx *c) : ctx(c) {
+    if (!ctx->profiling) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      ctx->profiling = false;
+      return;
+    }
+    (void)hipEventRecord(a, ctx->stream);
+  }
+  void stop() {
+    if (!a) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->scan_events.emplace_back(a, b);
+    a = b = nullptr;
+  }
+};
+
+double sphere_area(int d) { return 2.0 * std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d); }
+
+// FP32 error-bound coefficient of the cell scan (see vg_cell_scan.hip):
+// 2 (2d + 4) 2^-24 per unit of 1/nn, times a safety factor 4.
+float cell_kappa(int d, bool bf16) {
+  if (bf16) return 4.f * 2.f * (3.f * 0x1p-18f + (3.f * d + 4.f) * 0x1p-24f);
+  return 4.f * 2.f * (2.f * d + 4.f) * 0x1p-24f;
+}
+
+int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const float *dirs,
+              uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *st_out) {
+  const int64_t m = n * (int64_t)R;
+  const bool recheck = !(flags & VG_NO_RECHECK);
+  const bool bf16 = (flags & VG_PREC_BF16X3) != 0;
+  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m});
+  int rc = ensure_scratch(ctx, need);
+  if (rc) return rc;
+  Carver cv(ctx->scratch);
+  int64_t *flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
+  uint8_t *st = st_out ? st_out : cv.take<uint8_t>(m);
+  VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
+
+  CellScanArgs a{};
+  a.nodes = nodes;
+  a.n = n;
+  a.d = d;
+  a.dirs = dirs;
+  a.R = R;
+  a.t_out = t_out;
+  a.idx_out = idx_out;
+  a.st_out = st;
+  a.counters = ctx->counters;
+  a.flag_list = flag_list;
+  a.tau_rel = bf16 ? kTauCellsBf16 : kTauCellsFp32;
+  a.kappa = cell_kappa(d, bf16);
+  ScanTimer timer(ctx);
+  hipError_t e = bf16 ? launch_cell_scan_bf16x3(a, ctx->stream) : launch_cell_scan_fp32(a, ctx->stream);
+  timer.stop();
+  if (e != hipSuccess) return hip_fail(ctx, e, "cell scan launch");
+  if (recheck) {
+    RecheckArgs r{};
+    r.mode = RAYS_CELLS;
+    r.nodes = nodes;
+    r.n = n;
+    r.d = d;
+    r.dirs = dirs;
+    r.R = R;
+    r.clip = 1;
+    r.counters = ctx->counters;
+    r.flag_list = flag_list;
+    r.t_out = t_out;
+    r.idx_out = idx_out;
+    r.st_out = st;
+    r.tie_counter = ctx->counters + CNT_FP64_TIE;
+    e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
+  }
+  ctx->last_rays = m;
+  ctx->last_tau = a.tau_rel;
+  return VG_OK;
+}
+
+}  // namespace
+
+namespace vg {
+
+int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, const double *o64,
+                const double *u64, const int32_t *gen, const int32_t *excl, int n_excl, int clip,
+                bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64) {
+  if (m <= 0) return VG_OK;
+  size_t need = Carver::need({(size_t)m * 8});
+  int rc = ensure_scratch(ctx, need);
+  if (rc) return rc;
+  Carver cv(ctx->scratch);
+  int64_t *flag_list = cv.take<int64_t>(m);
+  VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
+  RayScanArgs a{};
+  a.nodes = nodes;
+  a.n = n;
+  a.d = d;
+  a.m = m;
+  a.o64 = o64;
+  a.u64 = u64;
+  a.gen = gen;
+  a.excl = excl;
+  a.n_excl = n_excl;
+  a.clip = clip;
+  a.t_out = t_out;
+  a.idx_out = idx_out;
+  a.st_out = st_out;
+  a.counters = ctx->counters;
+  a.flag_list = flag_list;
+  a.tau = kTauRays;
+  a.force_all = force_all ? 1 : 0;
+  ScanTimer timer(ctx);
+  hipError_t e = launch_ray_scan(a, ctx->stream);
+  timer.stop();
+  if (e != hipSuccess) return hip_fail(ctx, e, "ray scan launch");
+  RecheckArgs r{};
+  r.mode = RAYS_F64;
+  r.nodes = nodes;
+  r.n = n;
+  r.d = d;
+  r.o64 = o64;
+  r.u64 = u64;
+  r.gen = gen;
+  r.excl = excl;
+  r.n_excl = n_excl;
+  r.clip = clip;
+  r.counters = ctx->counters;
+  r.flag_list = flag_list;
+  r.t_out = t_out;
+  r.idx_out = idx_out;
+  r.st_out = st_out;
+  r.tie_counter = ctx->counters + CNT_FP64_TIE;
+  r.t64_out = t64;
+  e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
+  ctx->last_rays = m;
+  ctx->last_tau = kTauRays;
+  return VG_OK;
+}
+
+}  // namespace vg
+
+extern "C" {
+
+int vg_create(int device, vg_ctx **out) {
+  if (!out) return VG_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return VG_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return VG_EDEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return VG_EDEVICE;
+  vg_ctx *ctx = new (std::nothrow) vg_ctx();
+  if (!ctx) return VG_ENOMEM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipMalloc(&ctx->counters, CNT_WORDS * sizeof(uint32_t)) != hipSuccess) {
+    delete ctx;
+    return VG_EDEVICE;
+  }
+  *out = ctx;
+  return VG_OK;
+}
+
+void vg_destroy(vg_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &ev : ctx->scan_events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->counters) (void)hipFree(ctx->counters);
+  delete ctx;
+}
+
+int vg_set_stream(vg_ctx *ctx, void *stream) {
+  if (!ctx) return VG_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return VG_OK;
+}
+
+const char *vg_last_error(const vg_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int vg_get_stats(vg_ctx *ctx, vg_stats *out) {
+  if (!ctx || !out) return VG_EINVAL;
+  uint32_t c[CNT_WORDS];
+  VG_HIP(ctx, hipSetDevice(ctx->device));
+  VG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  VG_HIP(ctx, hipMemcpy(c, ctx->counters, sizeof c, hipMemcpyDeviceToHost));
+  out->rays = ctx->last_rays;
+  out->flagged = c[CNT_FLAGGED];
+  out->fp64_ties = c[CNT_FP64_TIE];
+  out->tie_eps = ctx->last_tau;
+  for (auto &ev : ctx->scan_events) {
+    float ms = 0.f;
+    VG_HIP(ctx, hipEventElapsedTime(&ms, ev.first, ev.second));
+    ctx->scan_ms += ms;
+    ctx->scan_launches++;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  ctx->scan_events.clear();
+  out->scan_launches = ctx->scan_launches;
+  out->scan_ms = ctx->scan_ms;
+  return VG_OK;
+}
+
+int vg_set_profiling(vg_ctx *ctx, int enable) {
+  if (!ctx) return VG_EINVAL;
+  VG_HIP(ctx, hipSetDevice(ctx->device));
+  VG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto &ev : ctx->scan_events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  ctx->scan_events.clear();
+  ctx->scan_launches = 0;
+  ctx->scan_ms = 0.0;
+  ctx->profiling = enable != 0;
+  return VG_OK;
+}
+
+int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t n_rays,
+               const float *origin, const float *dir, const int32_t *gen, const int32_t *excl,
+               int n_excl, uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *status_out) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (n_rays < 0) return fail(ctx, VG_EINVAL, "n_rays < 0");
+  if (n_excl < 0 || n_excl > d) return fail(ctx, VG_EINVAL, "n_excl=%d outside [0, d]", n_excl);
+  if (n_rays == 0) return VG_OK;
+  if (!origin || !dir || !gen || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null ray array");
+  if (n_excl > 0 && !excl) return fail(ctx, VG_EINVAL, "excl is NULL with n_excl > 0");
+  const bool recheck = !(flags & VG_NO_RECHECK);
+  size_t need = Carver::need({recheck ? (size_t)n_rays * 8 : 0, status_out ? 0 : (size_t)n_rays});
+  rc = ensure_scratch(ctx, need);
+  if (rc) return rc;
+  Carver cv(ctx->scratch);
+  int64_t *flag_list = recheck ? cv.take<int64_t>(n_rays) : nullptr;
+  uint8_t *st = status_out ? status_out : cv.take<uint8_t>(n_rays);
+  VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
+  RayScanArgs a{};
+  a.nodes = nodes;
+  a.n = n_nodes;
+  a.d = d;
+  a.m = n_rays;
+  a.o32 = origin;
+  a.u32 = dir;
+  a.gen = gen;
+  a.excl = excl;
+  a.n_excl = n_excl;
+  a.clip = (flags & VG_CLIP) ? 1 : 0;
+  a.t_out = t_out;
+  a.idx_out = idx_out;
+  a.st_out = st;
+  a.counters = ctx->counters;
+  a.flag_list = flag_list;
+  a.tau = kTauRays;
+  ScanTimer timer(ctx);
+  hipError_t e = launch_ray_scan(a, ctx->stream);
+  timer.stop();
+  if (e != hipSuccess) return hip_fail(ctx, e, "ray scan launch");
+  if (recheck) {
+    RecheckArgs r{};
+    r.mode = RAYS_F32;
+    r.nodes = nodes;
+    r.n = n_nodes;
+    r.d = d;
+    r.o32 = origin;
+    r.u32 = dir;
+    r.gen = gen;
+    r.excl = excl;
+    r.n_excl = n_excl;
+    r.clip = a.clip;
+    r.counters = ctx->counters;
+    r.flag_list = flag_list;
+    r.t_out = t_out;
+    r.idx_out = idx_out;
+    r.st_out = st;
+    r.tie_counter = ctx->counters + CNT_FP64_TIE;
+    e = launch_recheck(r, (int)std::min<int64_t>(n_rays, 4096), ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
+  }
+  ctx->last_rays = n_rays;
+  ctx->last_tau = kTauRays;
+  return VG_OK;
+}
+
+int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                     const float *dirs, uint32_t flags, float *t_out, int32_t *idx_out,
+                     uint8_t *status_out) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (!dirs || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null array");
+  return run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, flags, t_out, idx_out, status_out);
+}
+
+int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                      const float *dirs, uint32_t flags, float *t_out, int32_t *idx_out,
+                      uint8_t *status_out, float *volume, float *energy2, int32_t *facet_j,
+                      float *facet_area, int32_t *facet_count) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (!dirs || !t_out || !idx_out || !volume) return fail(ctx, VG_EINVAL, "null array");
+  const int nf = (facet_j != nullptr) + (facet_area != nullptr) + (facet_count != nullptr);
+  if (nf != 0 && nf != 3) return fail(ctx, VG_EINVAL, "facet outputs must be all set or all NULL");
+  rc = run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, flags, t_out, idx_out, status_out);
+  if (rc) return rc;
+  const double S = sphere_area(d);
+  AccumArgs a{};
+  a.nodes = nodes;
+  a.n = n_nodes;
+  a.d = d;
+  a.R = rays_per_cell;
+  a.t = t_out;
+  a.idx = idx_out;
+  a.sv = (float)(S / ((double)d * rays_per_cell));
+  a.se = (float)(S / ((double)(d + 2) * rays_per_cell));
+  a.sa = (float)(S / (double)rays_per_cell);
+  a.volume = volume;
+  a.energy2 = energy2;
+  a.facet_j = facet_j;
+  a.facet_area = facet_area;
+  a.facet_count = facet_count;
+  hipError_t e = launch_accum(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
+  return VG_OK;
+}
+
+int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                   const float *dirs, const float *t, const int32_t *idx, const int32_t *facet_j,
+                   const int32_t *facet_count, const float *g_volume, const float *g_energy2,
+                   const float *g_facet_area, float *grad_nodes) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (!dirs || !t || !idx || !grad_nodes) return fail(ctx, VG_EINVAL, "null array");
+  if (g_facet_area && (!facet_j || !facet_count))
+    return fail(ctx, VG_EINVAL, "g_facet_area needs facet_j and facet_count");
+  const int64_t n = n_nodes, m = n * (int64_t)rays_per_cell;
+  size_t need = Carver::need({(size_t)n * d * 4, (size_t)m * d * 4, (size_t)m * 4, (size_t)n * 4,
+                              (size_t)n * 4, (size_t)n * d * 8});
+  rc = ensure_scratch(ctx, need);
+  if (rc) return rc;
+  Carver cv(ctx->scratch);
+  BackwardArgs a{};
+  a.own = cv.take<float>((size_t)n * d);
+  a.rec = cv.take<float>((size_t)m * d);
+  a.rec_j = cv.take<int32_t>((size_t)m);
+  a.maxabs = cv.take<uint32_t>((size_t)n);
+  a.count = cv.take<uint32_t>((size_t)n);
+  a.acc = cv.take<unsigned long long>((size_t)n * d);
+  VG_HIP(ctx, fill_u32(a.maxabs, 0u, n, ctx->stream));
+  VG_HIP(ctx, fill_u32(a.count, 0u, n, ctx->stream));
+  VG_HIP(ctx, fill_u32(reinterpret_cast<uint32_t *>(a.acc), 0u, 2 * n * d, ctx->stream));
+  const double S = sphere_area(d);
+  a.nodes = nodes;
+  a.n = n;
+  a.d = d;
+  a.R = rays_per_cell;
+  a.dirs = dirs;
+  a.t = t;
+  a.idx = idx;
+  a.facet_j = facet_j;
+  a.facet_count = facet_count;
+  a.gv = g_volume;
+  a.ge = g_energy2;
+  a.ga = g_facet_area;
+  a.sv = (float)(S / ((double)d * rays_per_cell));
+  a.se = (float)(S / ((double)(d + 2) * rays_per_cell));
+  a.sa = (float)(S / (double)rays_per_cell);
+  a.grad = grad_nodes;
+  hipError_t e = launch_backward(a, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "backward launch");
+  return VG_OK;
+}
+
+int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_cells_problem *probs,
+                             uint32_t flags) {
+  if (!ctx) return VG_EINVAL;
+  if (n_problems < 0 || (n_problems > 0 && !probs)) return fail(ctx, VG_EINVAL, "bad problem table");
+  for (int p = 0; p < n_problems; ++p) {
+    const vg_cells_problem &q = probs[p];
+    int rc = vg_raycast_cells(ctx, q.d, q.n_nodes, q.nodes, q.rays_per_cell, q.dirs, flags,
+                              q.t_out, q.idx_out, q.status_out);
+    if (rc) return rc;
+  }
+  return VG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,499 @@
+// Monte-Carlo RayCast of every cell on MFMA (gfx950): FP32 and split BF16x3.
+//
+// A ray of cell i starts at the generator x_i with eta = {i} (Algorithm 3),
+// so eq. (t) reads t_r = |r - x_i|^2 / (2 u.(r - x_i)).  Inverting the nodes
+// about x_i,  r~ = (r - x_i) / |r - x_i|^2,  gives  1 / (2 t_r) = u . r~,
+// and the half-space restriction u.(r - x_i) > 0 becomes u . r~ > 0.  So
+//     t* = 1 / (2 max_r u . r~)
+// and the whole candidate scan of a cell is one dense contraction
+// S = R~ . U^T (nodes x directions, K = d) with a max/argmax epilogue: no
+// division, no mask, no cancellation between |r|^2 and x.r.  The faces of
+// the cube are the mirror images of x_i and enter the same max in closed
+// form: face x_k = 1 gives u_k / (2 (1 - x_k)), face x_k = 0 gives
+// -u_k / (2 x_k).
+//
+// Work decomposition: one workgroup per (cell, chunk of RW rays).  Each wave
+// owns C column blocks of 32 rays and keeps their directions as the MFMA B
+// operand for the whole scan.  Nodes stream through LDS in chunks of one node
+// per thread; every thread builds the inverted coordinates of its node
+// (the X.R^T part of the scan, once per cell and node) and the waves then run
+// v_mfma_f32_32x32x2_f32 over 32-node blocks.  Output layout of that MFMA:
+// lane l holds column l%32 (one ray) and rows 8*(i/4) + 4*(l/32) + i%4 of
+// register i, so the max over a lane's 16 values is register-local.
+//
+// Epilogue: per lane a running (best, second, argmax).  A 16-value block
+// whose max does not exceed the lane's second best cannot change anything
+// (fast path: one max tree and one compare); otherwise every value updates
+// the top-2 with v_med3 and the argmax with a compare/select.
+//
+// Near-tie certificate: with |u| = 1 the FP32 value of u.r~ is within
+// (2d+4) 2^-24 |r~| of the exact one, and |r~| <= 1/nn_i (nn_i = distance to
+// the nearest other node), so a gap above 2 (2d+4) 2^-24 / nn_i certifies the
+// argmax.  Rays below max(kappa / nn_i, tau_rel * best) are queued for the
+// FP64 recheck.  The winner's t* is re-evaluated from its two points in
+// double-float arithmetic (error-free transformations), about FP32 rounding.
+#include "vg_dfloat.h"
+#include "vg_internal.h"
+
+namespace vg {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float max16(const f32x16 &v) {
+  float a = fmaxf(fmaxf(v[0], v[1]), v[2]);
+  float b = fmaxf(fmaxf(v[3], v[4]), v[5]);
+  float c = fmaxf(fmaxf(v[6], v[7]), v[8]);
+  float e = fmaxf(fmaxf(v[9], v[10]), v[11]);
+  float f = fmaxf(fmaxf(v[12], v[13]), v[14]);
+  return fmaxf(fmaxf(fmaxf(a, b), c), fmaxf(fmaxf(e, f), v[15]));
+}
+
+// Top-2 update of one lane with the 16 accumulator values of a 32x32 block.
+__device__ __forceinline__ void epilogue16(const f32x16 &acc, float &best, float &second,
+                                           int &bidx, int rowbase) {
+  if (max16(acc) > second) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float s = acc[i];
+      second = __builtin_amdgcn_fmed3f(s, best, second);
+      if (s > best) {
+        best = s;
+        bidx = rowbase + 8 * (i >> 2) + (i & 3);
+      }
+    }
+  }
+}
+
+// Re-evaluate t for MC ray (origin x_i) hitting node x_j.
+template <int DK>
+__device__ float reeval_cell(const float (&xi)[DK], const float *__restrict__ xj,
+                             const float (&u)[DK], int d) {
+  dfacc num, den;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    if (k < d) {
+      float h, l;
+      two_sum(xj[k], -xi[k], h, l);  // x_j - x_i exactly as h + l
+      num.add_prod(h, h);
+      num.add_small(2.f * h * l);
+      den.add_prod(u[k], h);
+      den.add_small(u[k] * l);
+    }
+  }
+  return df_half_ratio(num, den);
+}
+
+// Merge the two lanes of each ray, add the cube faces, certify the gap,
+// re-evaluate t* and write the ray results.
+template <int C, int DK, int NT>
+__device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (&xi)[DK],
+                                            float (&best)[C], float (&second)[C], int (&bidx)[C],
+                                            float nn2, float *red, int lane, int rayw,
+                                            int64_t cell) {
+  const int d = a.d;
+  const int R = a.R;
+  // nearest-neighbour distance of x_i (for the error certificate)
+  const int tid = threadIdx.x;
+  red[tid] = nn2;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fminf(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const float nn = sqrtf(red[0]);
+
+  // merge the two lanes that hold each ray (rows split by l/32)
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    const float ob = __shfl_xor(best[cb], 32);
+    const float os = __shfl_xor(second[cb], 32);
+    const int oi = __shfl_xor(bidx[cb], 32);
+    const bool take = (ob > best[cb]) || (ob == best[cb] && oi >= 0 && (bidx[cb] < 0 || oi < bidx[cb]));
+    const float other = take ? best[cb] : ob;
+    if (take) {
+      best[cb] = ob;
+      bidx[cb] = oi;
+    }
+    second[cb] = fmaxf(fmaxf(second[cb], os), other);
+  }
+  if (lane >= 32) return;
+
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    const int ray = rayw + cb * 32 + lane;
+    if (ray >= R) continue;
+    const int64_t gid = (int64_t)cell * R + ray;
+    const float *up = a.dirs + gid * d;
+    float u[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) u[k] = (k < d) ? up[k] : 0.f;
+    // cube faces as mirror images of x_i
+    float sbox = 0.f, tbox = __builtin_inff();
+    int face = -1;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d && u[k] != 0.f) {
+        const float h = u[k] > 0.f ? 1.f - xi[k] : xi[k];
+        const float sk = fabsf(u[k]) / (2.f * h);
+        if (sk > sbox) {
+          sbox = sk;
+          tbox = h / fabsf(u[k]);
+          face = 2 * k + (u[k] > 0.f ? 1 : 0);
+        }
+      }
+    }
+    float s1 = best[cb], s2 = second[cb];
+    int j = bidx[cb];
+    if (face >= 0) {
+      if (sbox > s1) {
+        s2 = fmaxf(s2, s1);
+        s1 = sbox;
+        j = -2 - face;
+      } else {
+        s2 = fmaxf(s2, sbox);
+      }
+    }
+    uint8_t st = 0;
+    const float thr = fmaxf(a.tau_rel * s1, a.kappa / nn);
+    bool tie = !(s1 - s2 > thr);
+    float t;
+    if (j >= a.n) {  // cannot happen with the documented MFMA layout; never dereference
+      j = -1;
+      t = __builtin_nanf("");
+      st |= VG_ST_SUSPECT;
+      tie = true;
+    } else if (j >= 0) {
+      t = reeval_cell<DK>(xi, a.nodes + (int64_t)j * d, u, d);
+    } else if (j <= -2) {
+      t = tbox;
+    } else {
+      t = __builtin_inff();
+      st |= VG_ST_NO_HIT;
+      tie = true;
+    }
+    if (tie && a.flag_list) {
+      st |= VG_ST_NEAR_TIE;
+      const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
+      a.flag_list[pos] = gid;
+    }
+    a.t_out[gid] = t;
+    a.idx_out[gid] = j;
+    a.st_out[gid] = st;
+  }
+}
+
+template <int KP, int C, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs a) {
+  constexpr int NT = WAVES * 64;
+  constexpr int NB = NT;             // nodes per LDS chunk (one per thread)
+  constexpr int RW = WAVES * C * 32; // rays per workgroup
+  constexpr int DK = 2 * KP;
+  __shared__ float2 lds[KP * NB];
+  __shared__ float red[NT];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t cell = blockIdx.x / a.wg_per_cell;
+  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  const int d = a.d;
+  const int64_t n = a.n;
+  const int R = a.R;
+
+  float xi[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+
+  // B operand: lane l holds u[ray l%32][2kp + l/32] of each column block.
+  const int rayw = chunk * RW + wave * (C * 32);
+  float ub[C][KP];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    const int ray = rayw + cb * 32 + (lane & 31);
+    const float *up = a.dirs + ((int64_t)cell * R + ray) * d;
+#pragma unroll
+    for (int kp = 0; kp < KP; ++kp) {
+      const int k = 2 * kp + (lane >> 5);
+      ub[cb][kp] = (ray < R && k < d) ? up[k] : 0.f;
+    }
+  }
+
+  float best[C], second[C];
+  int bidx[C];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    best[cb] = 0.f;  // eligibility: u.r~ > 0
+    second[cb] = 0.f;
+    bidx[cb] = -1;
+  }
+  float nn2 = __builtin_inff();
+
+  for (int64_t base = 0; base < n; base += NB) {
+    __syncthreads();
+    {
+      const int64_t r = base + tid;
+      float rt[DK];
+#pragma unroll
+      for (int k = 0; k < DK; ++k) rt[k] = 0.f;
+      if (r < n && r != cell) {
+        const float *xr = a.nodes + r * d;
+        float n2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+          rt[k] = (k < d) ? xr[k] - xi[k] : 0.f;
+          n2 = __builtin_fmaf(rt[k], rt[k], n2);
+        }
+        nn2 = fminf(nn2, n2);
+        // duplicate generators (n2 == 0) are never eligible, as in eq. (t)
+        const float inv = n2 > 0.f ? __builtin_amdgcn_rcpf(n2) : 0.f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) rt[k] *= inv;
+      }
+#pragma unroll
+      for (int kp = 0; kp < KP; ++kp) lds[kp * NB + tid] = make_float2(rt[2 * kp], rt[2 * kp + 1]);
+    }
+    __syncthreads();
+    const int64_t rem = n - base;
+    const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
+    for (int nb = 0; nb < nblocks; ++nb) {
+      float A[KP];
+#pragma unroll
+      for (int kp = 0; kp < KP; ++kp) {
+        const float2 v = lds[kp * NB + nb * 32 + (lane & 31)];
+        A[kp] = (lane & 32) ? v.y : v.x;
+      }
+      const int rowbase = (int)(base + nb * 32) + 4 * (lane >> 5);
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) {
+        f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                      0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kp = 0; kp < KP; ++kp)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[kp], ub[cb][kp], acc, 0, 0, 0);
+        epilogue16(acc, best[cb], second[cb], bidx[cb], rowbase);
+      }
+    }
+  }
+
+  cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell);
+}
+
+// ---------------------------------------------------------------- BF16x3
+// Split-precision variant: a = a_hi + a_lo with a_hi = bf16(a) and
+// a_lo = bf16(a - a_hi); u.r~ ~ sum hi*hi + hi*lo + lo*hi with FP32
+// accumulation.  The three products are packed along K: the node operand is
+// [hi | hi | lo] and the direction operand [hi | lo | hi], each block DKP long
+// (DKP = 5, 10 or 16 so that 3 DKP fits KQ MFMA K-blocks of 16), padded with
+// zeros.  Both operands use the same K slot for the same product, so the
+// v_mfma_f32_32x32x16_bf16 K ordering inside a lane does not matter.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int KQ>
+struct Bf16Pack {
+  static constexpr int DKP = KQ == 1 ? 5 : (KQ == 2 ? 10 : 16);
+  static constexpr int KT = 16 * KQ;
+};
+
+__device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <int KQ, int C, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanArgs a) {
+  constexpr int NT = WAVES * 64;
+  constexpr int NB = NT;
+  constexpr int RW = WAVES * C * 32;
+  constexpr int DKP = Bf16Pack<KQ>::DKP;
+  constexpr int KT = Bf16Pack<KQ>::KT;
+  constexpr int DK = DKP;
+  __shared__ bf16x8 lds[NB * (KT / 8)];
+  __shared__ float red[NT];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t cell = blockIdx.x / a.wg_per_cell;
+  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  const int d = a.d;
+  const int64_t n = a.n;
+  const int R = a.R;
+
+  float xi[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+
+  const int rayw = chunk * RW + wave * (C * 32);
+  bf16x8 ub[C][KQ];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    const int ray = rayw + cb * 32 + (lane & 31);
+    const float *up = a.dirs + ((int64_t)cell * R + ray) * d;
+    __bf16 uh[DKP], ul[DKP];
+#pragma unroll
+    for (int k = 0; k < DKP; ++k) split_bf16((ray < R && k < d) ? up[k] : 0.f, uh[k], ul[k]);
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kk = 16 * q + 8 * h + e;
+          v[h] = kk < DKP ? uh[kk % DKP]
+                          : (kk < 2 * DKP ? ul[kk % DKP] : (kk < 3 * DKP ? uh[kk % DKP] : (__bf16)0.f));
+        }
+        ub[cb][q][e] = (lane & 32) ? v[1] : v[0];
+      }
+    }
+  }
+
+  float best[C], second[C];
+  int bidx[C];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    best[cb] = 0.f;
+    second[cb] = 0.f;
+    bidx[cb] = -1;
+  }
+  float nn2 = __builtin_inff();
+
+  for (int64_t base = 0; base < n; base += NB) {
+    __syncthreads();
+    {
+      const int64_t r = base + tid;
+      float rt[DK];
+#pragma unroll
+      for (int k = 0; k < DK; ++k) rt[k] = 0.f;
+      if (r < n && r != cell) {
+        const float *xr = a.nodes + r * d;
+        float n2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+          rt[k] = (k < d) ? xr[k] - xi[k] : 0.f;
+          n2 = __builtin_fmaf(rt[k], rt[k], n2);
+        }
+        nn2 = fminf(nn2, n2);
+        const float inv = n2 > 0.f ? __builtin_amdgcn_rcpf(n2) : 0.f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) rt[k] *= inv;
+      }
+      __bf16 rh[DKP], rl[DKP];
+#pragma unroll
+      for (int k = 0; k < DKP; ++k) split_bf16(rt[k], rh[k], rl[k]);
+#pragma unroll
+      for (int g = 0; g < KT / 8; ++g) {
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int kk = 8 * g + e;
+          v[e] = kk < DKP ? rh[kk % DKP]
+                          : (kk < 2 * DKP ? rh[kk % DKP] : (kk < 3 * DKP ? rl[kk % DKP] : (__bf16)0.f));
+        }
+        lds[tid * (KT / 8) + g] = v;
+      }
+    }
+    __syncthreads();
+    const int64_t rem = n - base;
+    const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
+    for (int nb = 0; nb < nblocks; ++nb) {
+      bf16x8 A[KQ];
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) A[q] = lds[(nb * 32 + (lane & 31)) * (KT / 8) + 2 * q + (lane >> 5)];
+      const int rowbase = (int)(base + nb * 32) + 4 * (lane >> 5);
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) {
+        f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                      0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[q], ub[cb][q], acc, 0, 0, 0);
+        epilogue16(acc, best[cb], second[cb], bidx[cb], rowbase);
+      }
+    }
+  }
+  cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell);
+}
+
+template <int C, int WAVES>
+hipError_t launch_kq(const CellScanArgs &a, hipStream_t s, int grid) {
+  dim3 blk(WAVES * 64);
+  if (a.d <= 5)
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<1, C, WAVES>), dim3(grid), blk, 0, s, a);
+  else if (a.d <= 10)
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<2, C, WAVES>), dim3(grid), blk, 0, s, a);
+  else
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<3, C, WAVES>), dim3(grid), blk, 0, s, a);
+  return hipGetLastError();
+}
+
+template <int C, int WAVES>
+hipError_t launch_kp(const CellScanArgs &a, hipStream_t s, int grid) {
+  const int kp = (a.d + 1) / 2;
+  dim3 blk(WAVES * 64);
+  switch (kp) {
+#define VG_CASE(K)                                                              \
+  case K:                                                                       \
+    hipLaunchKernelGGL((cell_scan_fp32_kernel<K, C, WAVES>), dim3(grid), blk, 0, s, a); \
+    break;
+    VG_CASE(1)
+    VG_CASE(2)
+    VG_CASE(3)
+    VG_CASE(4)
+    VG_CASE(5)
+    VG_CASE(6)
+    VG_CASE(7)
+    VG_CASE(8)
+#undef VG_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int cell_scan_rays_per_wg(int R) {
+  if (R >= 1024) return 1024;
+  if (R >= 512) return 512;
+  if (R >= 256) return 256;
+  if (R >= 128) return 128;
+  return 64;
+}
+
+hipError_t launch_cell_scan_fp32(const CellScanArgs &a0, hipStream_t s) {
+  CellScanArgs a = a0;
+  const int rw = cell_scan_rays_per_wg(a.R);
+  a.wg_per_cell = (a.R + rw - 1) / rw;
+  const int64_t grid64 = a.n * a.wg_per_cell;
+  if (grid64 <= 0) return hipSuccess;
+  if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
+  const int grid = (int)grid64;
+  switch (rw) {
+    case 1024: return launch_kp<4, 8>(a, s, grid);
+    case 512: return launch_kp<2, 8>(a, s, grid);
+    case 256: return launch_kp<2, 4>(a, s, grid);
+    case 128: return launch_kp<1, 4>(a, s, grid);
+    default: return launch_kp<1, 2>(a, s, grid);
+  }
+}
+
+hipError_t launch_cell_scan_bf16x3(const CellScanArgs &a0, hipStream_t s) {
+  CellScanArgs a = a0;
+  const int rw = cell_scan_rays_per_wg(a.R);
+  a.wg_per_cell = (a.R + rw - 1) / rw;
+  const int64_t grid64 = a.n * a.wg_per_cell;
+  if (grid64 <= 0) return hipSuccess;
+  if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
+  const int grid = (int)grid64;
+  switch (rw) {
+    case 1024: return launch_kq<4, 8>(a, s, grid);
+    case 512: return launch_kq<2, 8>(a, s, grid);
+    case 256: return launch_kq<2, 4>(a, s, grid);
+    case 128: return launch_kq<1, 4>(a, s, grid);
+    default: return launch_kq<1, 2>(a, s, grid);
+  }
+}
+
+}  // namespace vg

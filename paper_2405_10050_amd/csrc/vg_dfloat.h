@@ -1,0 +1,50 @@
+// Error-free transformations in FP32 (Knuth's TwoSum, FMA-based TwoProduct;
+// Ogita, Rump & Oishi, "Accurate sum and dot product", SIAM J. Sci. Comput.
+// 2005) used to re-evaluate the winning t* of a ray to about FP32 rounding,
+// without FP64 arithmetic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace vg {
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(float a, float b, float &p, float &e) {
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+
+// (hi, lo) accumulator of a sum of products.
+struct dfacc {
+  float s = 0.f, e = 0.f;
+  __device__ __forceinline__ void add_prod(float a, float b) {
+    float p, pe, s2, e2;
+    two_prod(a, b, p, pe);
+    two_sum(s, p, s2, e2);
+    s = s2;
+    e += e2 + pe;
+  }
+  __device__ __forceinline__ void sub_prod(float a, float b) { add_prod(-a, b); }
+  __device__ __forceinline__ void add_small(float v) { e += v; }
+  __device__ __forceinline__ void norm(float &hi, float &lo) const {
+    hi = s + e;
+    lo = e - (hi - s);
+  }
+};
+
+// t = num / (2 den) for double-float num and den.
+__device__ __forceinline__ float df_half_ratio(const dfacc &num, const dfacc &den) {
+  float nh, nl, dh, dl;
+  num.norm(nh, nl);
+  den.norm(dh, dl);
+  float q = nh / dh;
+  float r = __builtin_fmaf(-q, dh, nh);
+  return 0.5f * (q + (r + nl - q * dl) / dh);
+}
+
+}  // namespace vg

@@ -1,0 +1,255 @@
+// FP64 geometry of the exhaustive search (Sec. 2.1, Algorithm 2), one thread
+// per item:
+//   * SearchDirection(sigma, eta): unit vector orthogonal to the affine span
+//     of X_eta pointing away from the omitted generator; built as the
+//     normalised negative of the component of (x_omit - x_eta0) orthogonal
+//     to span{x_j - x_eta0}, by Gram-Schmidt applied twice;
+//   * the vertex of sigma: the point equidistant to its d+1 generators, from
+//     2 (x_b - x_a).y = |x_b - x_a|^2 (y = v - x_a), Gaussian elimination
+//     with partial pivoting;
+//   * the Descent projection (Algorithm 2): a random direction with its
+//     component in the span of X_sigma removed.
+#include "vg_internal.h"
+#include "vg_explore.h"
+
+namespace vg {
+namespace {
+
+template <int DK>
+__device__ void orth_complement(const float *__restrict__ X, int d, const int32_t *s, int m,
+                                double *w) {
+  // Q holds up to m-1 orthonormal vectors of span{X[s_j] - X[s_0]}
+  double Q[DK - 1 > 0 ? DK - 1 : 1][DK];
+  int q = 0;
+  const float *x0 = X + (int64_t)s[0] * d;
+  for (int j = 1; j < m; ++j) {
+    const float *xj = X + (int64_t)s[j] * d;
+    double e[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) e[k] = (k < d) ? (double)xj[k] - (double)x0[k] : 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int a = 0; a < q; ++a) {
+        double c = 0.0;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) c += e[k] * Q[a][k];
+#pragma unroll
+        for (int k = 0; k < DK; ++k) e[k] -= c * Q[a][k];
+      }
+    }
+    double nr = 0.0;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) nr += e[k] * e[k];
+    nr = sqrt(nr);
+    if (nr == 0.0) continue;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) Q[q][k] = e[k] / nr;
+    ++q;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int a = 0; a < q; ++a) {
+      double c = 0.0;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) c += w[k] * Q[a][k];
+#pragma unroll
+      for (int k = 0; k < DK; ++k) w[k] -= c * Q[a][k];
+    }
+  }
+}
+
+template <int DK>
+__device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *s, double *v) {
+  double A[DK][DK], b[DK], y[DK];
+  const float *xa = X + (int64_t)s[0] * d;
+  for (int r = 0; r < DK; ++r) {
+    b[r] = 0.0;
+    for (int k = 0; k < DK; ++k) A[r][k] = 0.0;
+  }
+  for (int r = 0; r < d; ++r) {
+    const float *xb = X + (int64_t)s[r + 1] * d;
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double e = (double)xb[k] - (double)xa[k];
+      A[r][k] = 2.0 * e;
+      acc += e * e;
+    }
+    b[r] = acc;
+  }
+  for (int c = 0; c < d; ++c) {
+    int p = c;
+    double pv = fabs(A[c][c]);
+    for (int r = c + 1; r < d; ++r)
+      if (fabs(A[r][c]) > pv) {
+        pv = fabs(A[r][c]);
+        p = r;
+      }
+    if (pv == 0.0) return false;
+    if (p != c) {
+      for (int k = 0; k < d; ++k) {
+        const double tmp = A[c][k];
+        A[c][k] = A[p][k];
+        A[p][k] = tmp;
+      }
+      const double tmp = b[c];
+      b[c] = b[p];
+      b[p] = tmp;
+    }
+    for (int r = c + 1; r < d; ++r) {
+      const double f = A[r][c] / A[c][c];
+      for (int k = c; k < d; ++k) A[r][k] -= f * A[c][k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = d - 1; c >= 0; --c) {
+    double acc = b[c];
+    for (int k = c + 1; k < d; ++k) acc -= A[c][k] * y[k];
+    y[c] = acc / A[c][c];
+  }
+  for (int k = 0; k < d; ++k) v[k] = (double)xa[k] + y[k];
+  return true;
+}
+
+// Edge rays of the frontier: item (vertex v, omitted position o).
+template <int DK>
+__global__ __launch_bounds__(128) void edge_rays_kernel(ExploreRays a) {
+  const int64_t it = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (it >= a.m) return;
+  const int d = a.d;
+  const int64_t v = a.item_v[it];
+  const int o = a.item_o[it];
+  const int32_t *sig = a.keys + v * (d + 1);
+  int32_t eta[DK];
+  int q = 0;
+  for (int b = 0; b <= d; ++b)
+    if (b != o) eta[q++] = sig[b];
+  const int32_t omit = sig[o];
+  double w[DK];
+  const float *x0 = a.nodes + (int64_t)eta[0] * d;
+  const float *xo = a.nodes + (int64_t)omit * d;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) w[k] = (k < d) ? (double)xo[k] - (double)x0[k] : 0.0;
+  orth_complement<DK>(a.nodes, d, eta, d, w);
+  double nr = 0.0;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) nr += w[k] * w[k];
+  nr = sqrt(nr);
+  for (int k = 0; k < d; ++k) {
+    a.u64[it * d + k] = nr > 0.0 ? -w[k] / nr : 0.0;
+    a.o64[it * d + k] = a.coords[v * d + k];
+  }
+  a.gen[it] = eta[0];
+  for (int b = 0; b < d; ++b) a.excl[it * d + b] = eta[b];
+  a.ok[it] = nr > 0.0 ? 1 : 0;
+}
+
+// New vertex of each hit: key sort(eta U {j}) and its FP64 coordinates.
+template <int DK>
+__global__ __launch_bounds__(128) void new_vertex_kernel(ExploreRays a) {
+  const int64_t it = (int64_t)blockIdx.x * 128 + threadIdx.x;
+  if (it >= a.m) return;
+  const int d = a.d;
+  const int32_t j = a.idx[it];
+  int32_t *key = a.new_keys + it * (d + 1);
+  if (j < 0 || !a.ok[it]) {
+    key[0] = -1;
+    return;
+  }
+  const int32_t *eta = a.excl + it * d;
+  int q = 0;
+  bool placed = false;
+  for (int b = 0; b < d; ++b) {
+    if (!placed && j < eta[b]) {
+      key[q++] = j;
+      placed = true;
+    }
+    key[q++] = eta[b];
+  }
+  if (!placed) key[q++] = j;
+  double v[DK];
+  int32_t ks[DK + 1];
+  for (int b = 0; b <= d; ++b) ks[b] = key[b];
+  if (!solve_vertex<DK>(a.nodes, d, ks, v)) {
+    key[0] = -2;  // singular: degenerate input
+    return;
+  }
+  for (int k = 0; k < d; ++k) a.new_coords[it * d + k] = v[k];
+}
+
+template <int DK>
+__global__ void descent_project_kernel(const float *X, int d, const int32_t *sig, int m,
+                                       double *u, int *ok) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double w[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) w[k] = (k < d) ? u[k] : 0.0;
+  orth_complement<DK>(X, d, sig, m, w);
+  double nr = 0.0;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) nr += w[k] * w[k];
+  nr = sqrt(nr);
+  for (int k = 0; k < d; ++k) u[k] = nr > 0.0 ? w[k] / nr : 0.0;
+  *ok = nr > 0.0 ? 1 : 0;
+}
+
+__global__ void advance_kernel(double *r, const double *u, const double *t, int d, double sign) {
+  const int k = threadIdx.x;
+  if (k < d) r[k] += t[0] * sign * u[k];
+}
+
+template <int DK>
+__global__ void solve_one_kernel(const float *X, int d, const int32_t *sig, double *v, int *ok) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t ks[DK + 1];
+  for (int b = 0; b <= d; ++b) ks[b] = sig[b];
+  double vv[DK];
+  const bool good = solve_vertex<DK>(X, d, ks, vv);
+  for (int k = 0; k < d; ++k) v[k] = good ? vv[k] : 0.0;
+  *ok = good ? 1 : 0;
+}
+
+}  // namespace
+
+#define VG_DK_DISPATCH(d, KERNEL, GRID, BLK, ...)                                     \
+  do {                                                                                \
+    if ((d) <= 4)                                                                     \
+      hipLaunchKernelGGL(KERNEL<4>, GRID, BLK, 0, s, __VA_ARGS__);                    \
+    else if ((d) <= 8)                                                                \
+      hipLaunchKernelGGL(KERNEL<8>, GRID, BLK, 0, s, __VA_ARGS__);                    \
+    else if ((d) <= 12)                                                               \
+      hipLaunchKernelGGL(KERNEL<12>, GRID, BLK, 0, s, __VA_ARGS__);                   \
+    else                                                                              \
+      hipLaunchKernelGGL(KERNEL<16>, GRID, BLK, 0, s, __VA_ARGS__);                   \
+  } while (0)
+
+hipError_t launch_edge_rays(const ExploreRays &a, hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.m + 127) / 128)), blk(128);
+  VG_DK_DISPATCH(a.d, edge_rays_kernel, grid, blk, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_new_vertices(const ExploreRays &a, hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  dim3 grid((unsigned)((a.m + 127) / 128)), blk(128);
+  VG_DK_DISPATCH(a.d, new_vertex_kernel, grid, blk, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_descent_project(const float *X, int d, const int32_t *sig, int m, double *u,
+                                  int *ok, hipStream_t s) {
+  VG_DK_DISPATCH(d, descent_project_kernel, dim3(1), dim3(64), X, d, sig, m, u, ok);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(double *r, const double *u, const double *t, int d, double sign,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, r, u, t, d, sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_one(const float *X, int d, const int32_t *sig, double *v, int *ok,
+                            hipStream_t s) {
+  VG_DK_DISPATCH(d, solve_one_kernel, dim3(1), dim3(64), X, d, sig, v, ok);
+  return hipGetLastError();
+}
+
+}  // namespace vg

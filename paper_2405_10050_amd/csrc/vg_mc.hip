@@ -1,0 +1,365 @@
+// Monte-Carlo volume / interface-area estimators of Sec. 3.1 (Algorithm 3
+// with f = 1) and their adjoint, on top of the per-ray RayCast results.
+//
+// Forward, one workgroup per cell (its rays are contiguous):
+//   volume   = S/(d n)     sum l^d
+//   energy2  = S/((d+2) n) sum l^{d+2}            (second moment about x_i)
+//   area_ij  = S/n sum_{k: j_k = j} l^{d-1}/|n_ij.u|
+// For a node j the ray meets the bisector at distance h = |x_j - x_i|/2 from
+// x_i, so l |n_ij.u| = h and the area term equals 2 l^d / |x_j - x_i|; for a
+// cube face at distance h it is l^d / h.  This form needs no division by the
+// (possibly tiny) cosine.  Facets: the (j, ray) keys of the cell are sorted
+// in LDS (bitonic), runs of equal j are summed in ray order, so every sum has
+// a fixed order and the result is bitwise reproducible.
+//
+// Adjoint, with the directions frozen (not in the paper):
+//   node winner j, D = x_j - x_i, t = |D|^2/(2 u.D):
+//     dt/dD = (D - t u)/(u.D) = 2 t (D - t u)/|D|^2,
+//     dt/dx_j = dt/dD, dt/dx_i = -dt/dD;
+//     the area term w = 2 l^d/|D| also has dw/dD|_l = -2 l^d D/|D|^3;
+//   cube face x_k = s, h = |s - x_ik|: dt/dx_ik = -1/u_k, w = l^d/h with
+//     dw/dx_ik|_l = l^d/h^2 * (s ? 1 : -1).
+// The part landing on x_i is summed in the cell's workgroup.  The part
+// landing on the winner x_j is scattered with 64-bit integer atomics in a
+// per-node fixed-point scale chosen from that node's largest incoming
+// magnitude and count (integer addition is associative, so the result does
+// not depend on the order of the atomics).
+#include "vg_internal.h"
+
+namespace vg {
+namespace {
+
+constexpr int NT = 256;
+
+__device__ __forceinline__ uint64_t facet_key(int32_t j, int ray) {
+  return ((uint64_t)((uint32_t)j ^ 0x80000000u) << 32) | (uint32_t)ray;
+}
+__device__ __forceinline__ int32_t key_j(uint64_t k) {
+  return (int32_t)((uint32_t)(k >> 32) ^ 0x80000000u);
+}
+
+__device__ __forceinline__ float powi(float x, int p) {
+  float r = 1.f;
+  for (int q = 0; q < p; ++q) r *= x;
+  return r;
+}
+
+// Deterministic block sum of one float per thread (tree in LDS).
+__device__ float block_sum(float v, float *red) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  red[tid] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ void bitonic_sort(uint64_t *keys, int P) {
+  const int tid = threadIdx.x;
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = tid; i < (P >> 1); i += NT) {
+        const int lo = (i / stride) * 2 * stride + (i % stride);
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t a = keys[lo], b = keys[hi];
+        if ((a > b) == asc) {
+          keys[lo] = b;
+          keys[hi] = a;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int DK>
+__global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
+  // one 16-byte aligned dynamic block: keys [P] u64 | w [P] f32 | red [NT] f32 | seg [NT+1] i32
+  extern __shared__ __align__(16) uint64_t smem[];
+  const int R = a.R;
+  int P = 1;
+  while (P < R) P <<= 1;
+  uint64_t *keys = smem;
+  float *w = reinterpret_cast<float *>(keys + P);
+  float *red = w + P;
+  int32_t *seg = reinterpret_cast<int32_t *>(red + NT);
+
+  const int tid = threadIdx.x;
+  const int64_t cell = blockIdx.x;
+  const int d = a.d;
+  float xi[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+
+  float pv = 0.f, pe = 0.f;
+  for (int k = tid; k < P; k += NT) {
+    if (k < R) {
+      const int64_t gid = cell * R + k;
+      const float l = a.t[gid];
+      const int32_t j = a.idx[gid];
+      const float ld = powi(l, d);
+      pv += ld;
+      pe += ld * l * l;
+      float wa = 0.f;
+      if (j >= 0) {
+        const float *xj = a.nodes + (int64_t)j * d;
+        float n2 = 0.f;
+#pragma unroll
+        for (int q = 0; q < DK; ++q) {
+          if (q < d) {
+            const float e = xj[q] - xi[q];
+            n2 = __builtin_fmaf(e, e, n2);
+          }
+        }
+        wa = 2.f * ld / sqrtf(n2);
+      } else if (j <= -2) {
+        const int face = -2 - j, kk = face >> 1;
+        float xk = 0.f;
+#pragma unroll
+        for (int q = 0; q < DK; ++q)
+          if (q == kk) xk = xi[q];
+        const float h = (face & 1) ? 1.f - xk : xk;
+        wa = ld / h;
+      }
+      keys[k] = facet_key(j, k);
+      w[k] = wa;
+    } else {
+      keys[k] = ~0ull;
+    }
+  }
+  const float sum_v = block_sum(pv, red);
+  const float sum_e = block_sum(pe, red);
+  if (tid == 0) {
+    a.volume[cell] = a.sv * sum_v;
+    if (a.energy2) a.energy2[cell] = a.se * sum_e;
+  }
+  if (!a.facet_j) return;
+
+  bitonic_sort(keys, P);
+  // heads of runs of equal j, counted per thread over a contiguous segment
+  const int E = (P + NT - 1) / NT;
+  const int p0 = tid * E, p1 = min(p0 + E, R);
+  int nh = 0;
+  for (int p = p0; p < p1; ++p)
+    if (p == 0 || (keys[p] >> 32) != (keys[p - 1] >> 32)) ++nh;
+  seg[tid + 1] = nh;
+  __syncthreads();
+  if (tid == 0) {
+    seg[0] = 0;
+    for (int q = 1; q <= NT; ++q) seg[q] += seg[q - 1];
+  }
+  __syncthreads();
+  int slot = seg[tid];
+  for (int p = p0; p < p1; ++p) {
+    if (p == 0 || (keys[p] >> 32) != (keys[p - 1] >> 32)) {
+      float s = 0.f;
+      int q = p;
+      while (q < R && (keys[q] >> 32) == (keys[p] >> 32)) {
+        s += w[(uint32_t)keys[q]];
+        ++q;
+      }
+      a.facet_j[cell * R + slot] = key_j(keys[p]);
+      a.facet_area[cell * R + slot] = a.sa * s;
+      ++slot;
+    }
+  }
+  if (tid == 0) a.facet_count[cell] = seg[NT];
+}
+
+// ----------------------------------------------------------------- adjoint
+template <int DK>
+__global__ __launch_bounds__(NT) void backward_rays_kernel(BackwardArgs a) {
+  __shared__ float red[NT];
+  const int tid = threadIdx.x;
+  const int64_t cell = blockIdx.x;
+  const int d = a.d, R = a.R;
+  float xi[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+  const float gv = a.gv ? a.gv[cell] : 0.f;
+  const float ge = a.ge ? a.ge[cell] : 0.f;
+  const int nf = a.facet_count ? a.facet_count[cell] : 0;
+  const int32_t *fj = a.facet_j ? a.facet_j + cell * R : nullptr;
+
+  float own[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) own[k] = 0.f;
+
+  for (int kr = tid; kr < R; kr += NT) {
+    const int64_t gid = cell * R + kr;
+    const float l = a.t[gid];
+    const int32_t j = a.idx[gid];
+    const float ld1 = powi(l, d - 1);
+    const float ld = ld1 * l;
+    // upstream weight of the facet this ray contributes to
+    float ga = 0.f;
+    if (a.ga && fj) {
+      int lo = 0, hi = nf - 1;
+      while (lo <= hi) {  // facets sorted by j as signed int
+        const int mid = (lo + hi) >> 1;
+        const int32_t v = fj[mid];
+        if (v == j) {
+          ga = a.ga[cell * R + mid];
+          break;
+        }
+        if (v < j)
+          lo = mid + 1;
+        else
+          hi = mid - 1;
+      }
+    }
+    float dl = gv * a.sv * (float)d * ld1 + ge * a.se * (float)(d + 2) * ld * l;
+    float win[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) win[k] = 0.f;
+    if (j >= 0) {
+      const float *xj = a.nodes + (int64_t)j * d;
+      float D[DK], n2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        D[k] = (k < d) ? xj[k] - xi[k] : 0.f;
+        n2 = __builtin_fmaf(D[k], D[k], n2);
+      }
+      const float nD = sqrtf(n2);
+      dl += ga * a.sa * 2.f * (float)d * ld1 / nD;
+      const float c = dl * 2.f * l / n2;             // dl * dt/dD scale
+      const float cw = -ga * a.sa * 2.f * ld / (n2 * nD);  // direct area term
+      float uk[DK];
+      const float *up = a.dirs + gid * d;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) uk[k] = (k < d) ? up[k] : 0.f;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        win[k] = c * (D[k] - l * uk[k]) + cw * D[k];
+        own[k] -= win[k];
+      }
+    } else if (j <= -2) {
+      const int face = -2 - j, kk = face >> 1;
+      float xk = 0.f;
+#pragma unroll
+      for (int q = 0; q < DK; ++q)
+        if (q == kk) xk = xi[q];
+      const float uk = a.dirs[gid * d + kk];
+      const float h = (face & 1) ? 1.f - xk : xk;
+      dl += ga * a.sa * (float)d * ld1 / h;
+      const float gk = dl * (-1.f / uk) + ga * a.sa * ld / (h * h) * ((face & 1) ? 1.f : -1.f);
+#pragma unroll
+      for (int q = 0; q < DK; ++q)
+        if (q == kk) own[q] += gk;
+    }
+    // record the contribution aimed at the winner
+    a.rec_j[gid] = j >= 0 ? j : -1;
+    if (j >= 0) {
+      float m = 0.f;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        if (k < d) {
+          a.rec[gid * d + k] = win[k];
+          m = fmaxf(m, fabsf(win[k]));
+        }
+      }
+      atomicMax(&a.maxabs[j], __float_as_uint(m));
+      atomicAdd(&a.count[j], 1u);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    if (k < d) {
+      const float s = block_sum(own[k], red);
+      if (tid == 0) a.own[cell * d + k] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ int fixed_scale(uint32_t maxbits, uint32_t count) {
+  const float m = __uint_as_float(maxbits);
+  int e;
+  frexpf(m, &e);  // m < 2^e
+  int c = 0;
+  while ((1u << c) < count && c < 31) ++c;  // count <= 2^c
+  return 61 - c - e;
+}
+
+__global__ __launch_bounds__(NT) void backward_scatter_kernel(BackwardArgs a, int64_t m) {
+  const int d = a.d;
+  for (int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x; gid < m;
+       gid += (int64_t)gridDim.x * NT) {
+    const int32_t j = a.rec_j[gid];
+    if (j < 0) continue;
+    const uint32_t mb = a.maxabs[j];
+    if (mb == 0) continue;
+    const int F = fixed_scale(mb, a.count[j]);
+    for (int k = 0; k < d; ++k) {
+      const double v = (double)a.rec[gid * d + k];
+      const long long q = __double2ll_rn(ldexp(v, F));
+      atomicAdd(&a.acc[(int64_t)j * d + k], (unsigned long long)q);
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void backward_finish_kernel(BackwardArgs a) {
+  const int d = a.d;
+  const int64_t total = a.n * d;
+  for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * NT) {
+    const int64_t j = q / d;
+    float g = a.own[q];
+    const uint32_t mb = a.maxabs[j];
+    if (mb != 0) {
+      const int F = fixed_scale(mb, a.count[j]);
+      const long long v = (long long)a.acc[q];
+      g += (float)ldexp((double)v, -F);
+    }
+    a.grad[q] = g;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_accum(const AccumArgs &a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  int P = 1;
+  while (P < a.R) P <<= 1;
+  const size_t shm = (size_t)P * (sizeof(uint64_t) + sizeof(float)) + NT * sizeof(float) +
+                     (NT + 1) * sizeof(int32_t);
+  dim3 grid((unsigned)a.n), blk(NT);
+  if (a.d <= 4)
+    hipLaunchKernelGGL(accum_kernel<4>, grid, blk, shm, s, a);
+  else if (a.d <= 8)
+    hipLaunchKernelGGL(accum_kernel<8>, grid, blk, shm, s, a);
+  else if (a.d <= 12)
+    hipLaunchKernelGGL(accum_kernel<12>, grid, blk, shm, s, a);
+  else
+    hipLaunchKernelGGL(accum_kernel<16>, grid, blk, shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const BackwardArgs &a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  dim3 grid((unsigned)a.n), blk(NT);
+  if (a.d <= 4)
+    hipLaunchKernelGGL(backward_rays_kernel<4>, grid, blk, 0, s, a);
+  else if (a.d <= 8)
+    hipLaunchKernelGGL(backward_rays_kernel<8>, grid, blk, 0, s, a);
+  else if (a.d <= 12)
+    hipLaunchKernelGGL(backward_rays_kernel<12>, grid, blk, 0, s, a);
+  else
+    hipLaunchKernelGGL(backward_rays_kernel<16>, grid, blk, 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t m = a.n * a.R;
+  hipLaunchKernelGGL(backward_scatter_kernel, dim3(2048), blk, 0, s, a, m);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(backward_finish_kernel, dim3(1024), blk, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace vg
