@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
-    ap.add_argument("--cpu-cells", type=int, default=8, help="oracle sample size (0: skip)")
+    ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
     ap.add_argument("--no-backward", action="store_true")
     args = ap.parse_args()
 

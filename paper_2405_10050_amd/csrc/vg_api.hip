@@ -106,10 +106,14 @@ struct ScanTimer {
 
 double sphere_area(int d) { return 2.0 * std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d); }
 
-// FP32 error-bound coefficient of the cell scan (see vg_cell_scan.hip):
-// 2 (2d + 4) 2^-24 per unit of 1/nn, times a safety factor 4.
+// Error-bound coefficient of the cell scan's near-tie certificate: the
+// computed u.r~ of any node is within c |r~| <= c / nn of the exact value, so
+// a gap above 2 c / nn certifies the argmax; kappa = 4 (safety) * 2 c.
+//   FP32:    c = (2d + 4) 2^-24   (inverted node (d+4) ulps, K = d products)
+//   BF16x3:  c = 3 * 2^-18 + (4d + 4) 2^-24   (dropped lo*lo and split
+//            remainders of both operands, plus FP32 accumulation of 3d terms)
 float cell_kappa(int d, bool bf16) {
-  if (bf16) return 4.f * 2.f * (3.f * 0x1p-18f + (3.f * d + 4.f) * 0x1p-24f);
+  if (bf16) return 4.f * 2.f * (3.f * 0x1p-18f + (4.f * d + 4.f) * 0x1p-24f);
   return 4.f * 2.f * (2.f * d + 4.f) * 0x1p-24f;
 }
 

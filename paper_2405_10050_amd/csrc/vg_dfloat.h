@@ -1,7 +1,9 @@
 // Error-free transformations in FP32 (Knuth's TwoSum, FMA-based TwoProduct;
 // Ogita, Rump & Oishi, "Accurate sum and dot product", SIAM J. Sci. Comput.
 // 2005) used to re-evaluate the winning t* of a ray to about FP32 rounding,
-// without FP64 arithmetic.
+// without FP64 arithmetic.  Every body turns FP contraction off: fusing the
+// product of TwoProduct into the following sum (allowed by the default
+// -ffp-contract=fast) silently breaks the transformation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,12 +11,14 @@
 namespace vg {
 
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+#pragma clang fp contract(off)
   s = a + b;
   float bb = s - a;
   e = (a - (s - bb)) + (b - bb);
 }
 
 __device__ __forceinline__ void two_prod(float a, float b, float &p, float &e) {
+#pragma clang fp contract(off)
   p = a * b;
   e = __builtin_fmaf(a, b, -p);
 }
@@ -23,6 +27,7 @@ __device__ __forceinline__ void two_prod(float a, float b, float &p, float &e) {
 struct dfacc {
   float s = 0.f, e = 0.f;
   __device__ __forceinline__ void add_prod(float a, float b) {
+#pragma clang fp contract(off)
     float p, pe, s2, e2;
     two_prod(a, b, p, pe);
     two_sum(s, p, s2, e2);
@@ -30,8 +35,12 @@ struct dfacc {
     e += e2 + pe;
   }
   __device__ __forceinline__ void sub_prod(float a, float b) { add_prod(-a, b); }
-  __device__ __forceinline__ void add_small(float v) { e += v; }
+  __device__ __forceinline__ void add_small(float v) {
+#pragma clang fp contract(off)
+    e += v;
+  }
   __device__ __forceinline__ void norm(float &hi, float &lo) const {
+#pragma clang fp contract(off)
     hi = s + e;
     lo = e - (hi - s);
   }
@@ -39,6 +48,7 @@ struct dfacc {
 
 // t = num / (2 den) for double-float num and den.
 __device__ __forceinline__ float df_half_ratio(const dfacc &num, const dfacc &den) {
+#pragma clang fp contract(off)
   float nh, nl, dh, dl;
   num.norm(nh, nl);
   den.norm(dh, dl);

@@ -129,10 +129,13 @@ hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // Cell-scan tile choice: rays per workgroup for a given rays-per-cell.
 int cell_scan_rays_per_wg(int R);
 
-// Relative gap floors of the near-tie test.
-constexpr float kTauCellsFp32 = 1.0f / 8192.0f;  // 2^-13
-constexpr float kTauCellsBf16 = 1.0f / 1024.0f;  // 2^-10
-constexpr float kTauRays = 1.0f / 1024.0f;       // 2^-10
+// Relative gap floors of the near-tie test.  The cell scan certifies its
+// argmax with an absolute FP32/BF16x3 error bound (kappa / nn-distance); the
+// floors below only keep a margin of a few ulps on top of it.  General rays
+// use a wider floor plus their own per-candidate bound.
+constexpr float kTauCellsFp32 = 1.0f / 1048576.0f;  // 2^-20
+constexpr float kTauCellsBf16 = 1.0f / 16384.0f;    // 2^-14
+constexpr float kTauRays = 1.0f / 1024.0f;          // 2^-10
 
 }  // namespace vg
 

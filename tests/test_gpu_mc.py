@@ -114,3 +114,24 @@ def test_autograd_function_centroidal_energy(vg):
     g_ref = oracle.mc_adjoint(X, np.arange(n), D, t, idx, None, np.ones(n), None)
     g = nodes.grad.cpu().numpy()
     assert np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref) < 1e-4
+
+
+def test_backward_d4_512_rays_full_gradient(vg):
+    """The d=4 / 512-rays shape of the differentiation workload at N = 2000,
+    small enough for the oracle's closed-form gradient over every ray."""
+    d, n, R = 4, 2000, 512
+    X = W.uniform_cloud(n, d, seed=0)
+    D = W.mc_directions(range(n), R, d, seed=1)
+    dev = torch.device("cuda", 0)
+    nodes = torch.from_numpy(X).to(dev)
+    dirs = torch.from_numpy(D).to(dev)
+    res = vg.mc_volume_area(nodes, dirs)
+    grad = vg.mc_backward(nodes, dirs, res, None, torch.ones(n, device=dev), None).cpu().numpy()
+    ref = oracle.mc_volume_area(X, np.arange(n), D)
+    g_ref = oracle.mc_adjoint(X, np.arange(n), D, ref["t"], ref["idx"], None, np.ones(n), None)
+    err = np.linalg.norm(grad - g_ref) / np.linalg.norm(g_ref)
+    assert err < 1e-4, err
+    # the 32 finite-difference generators of the workload, component-wise
+    pick = W.fd_generators(n, 32, seed=1)
+    scale = np.abs(g_ref).max()
+    assert np.allclose(grad[pick], g_ref[pick], rtol=1e-3, atol=1e-4 * scale)
