@@ -50,6 +50,25 @@ def directions_threaded(cells, R, d, seed, workers=8):
     return out
 
 
+def measured_traffic(name, n, R):
+    """HBM bytes per launch of the scan kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken (or
+    the workload differs)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        doc = json.load(open(path))
+        src = open(os.path.join(ROOT, doc["kernel_source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != doc["kernel_source_sha256"]:
+        return None
+    if n != 100_000 or R != 1024:
+        return None
+    return float(doc["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(X, cells, Ds):
     """The FP64 oracle on a bounded sample of the same workload (all host
     threads): RayCast of the sampled cells' rays over all nodes plus their
@@ -76,6 +95,11 @@ def main():
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a profiler run)")
+    ap.add_argument("--compare-bf16", type=int, default=1,
+                    help="also time the split-BF16x3 form of the step (extra field)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -98,6 +122,13 @@ def main():
     nodes = torch.from_numpy(X).to(dev)
     dirs = torch.from_numpy(D).to(dev)
     del D  # the CPU baseline regenerates the directions of its sample
+    if args.copy_probe_mib > 0:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     res = vg.mc_volume_area(nodes, dirs, precision=args.precision)
     g_vol = torch.ones(n, device=dev)
     g_en = torch.ones(n, device=dev)
@@ -142,6 +173,9 @@ def main():
         achieved = flops / (scan_ms / 1e3)
         peak, unit = FP32_MFMA_PEAK, "TFLOP/s"
 
+    traffic = None
+    if args.precision == "fp32":
+        traffic = measured_traffic("cell_scan_fp32_gmm8_d10_n100000_traffic.json", n, R)
     out = {
         "metric": "rays/sec batched RayCast (d=10,N=100k) at 1e-5 rel err; MC volume+grad cells/s",
         "value": value,
@@ -170,10 +204,43 @@ def main():
             "peak": peak / 1e12,
             "unit": unit,
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes": float(rays * d * 4 + n * d * 4 + rays * 9),
             "scan_ms": scan_ms,
         },
     }
+    if args.compare_bf16 and args.precision == "fp32":
+        # the split-precision form of the same step, timed on the same inputs
+        res_b = vg.mc_volume_area(nodes, dirs, precision="bf16x3")
+
+        def step_b():
+            vg.mc_volume_area(nodes, dirs, precision="bf16x3", out=res_b)
+            if not args.no_backward:
+                vg.mc_backward(nodes, dirs, res_b, g_vol, g_en, g_fa)
+
+        step_b()
+        torch.cuda.synchronize()
+        vg.set_profiling(True)
+        ev0.record(stream)
+        for k in range(args.steps):
+            step_b()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        sb = vg.stats()
+        vg.set_profiling(False)
+        ms_b = ev0.elapsed_time(ev1) / args.steps
+        scan_b = sb["scan_ms"] / max(1, sb["scan_launches"])
+        same = float((res_b.idx == res.idx).float().mean().item())
+        rel_t = float(((res_b.t - res.t).abs() / res.t).max().item())
+        out["bf16x3"] = {
+            "ms_per_step": ms_b, "rays_per_s": rays / (ms_b / 1e3), "speedup_vs_fp32": ms_step / ms_b,
+            "scan_ms": scan_b, "flagged_rays_per_step": sb["flagged"],
+            "roofline_frac_bf16_peak": 3.0 * flops / (scan_b / 1e3) / BF16_MFMA_PEAK,
+            "fp32_equivalent_tflops": flops / (scan_b / 1e3) / 1e12,
+            "argmin_agreement_with_fp32": same, "max_rel_t_diff_vs_fp32": rel_t,
+        }
+        print(f"[bench] bf16x3: {ms_b:.1f} ms/step", file=sys.stderr, flush=True)
     if args.cpu_cells > 0:
         rng = np.random.default_rng(123)
         sample = np.sort(rng.choice(n, args.cpu_cells, replace=False))

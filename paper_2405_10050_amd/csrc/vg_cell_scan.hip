@@ -65,6 +65,39 @@ __device__ __forceinline__ void epilogue16(const f32x16 &acc, float &best, float
   }
 }
 
+// Coordinates of node r (zero beyond n or d).
+template <int DK>
+__device__ __forceinline__ void load_node(const float *__restrict__ nodes, int64_t n, int d,
+                                          int64_t r, float (&x)[DK]) {
+  const bool ok = r < n;
+  const float *xr = nodes + (ok ? r : 0) * d;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) x[k] = (ok && k < d) ? xr[k] : 0.f;
+}
+
+// Inverted coordinates r~ = (x_r - x_i)/|x_r - x_i|^2 of node r about x_i (zero
+// for r = i, beyond n, and for a duplicate of x_i, which eq. (t) never makes
+// eligible).  Returns |x_r - x_i|^2 (or +inf when not a node).
+template <int DK>
+__device__ __forceinline__ float invert_node(const float (&xr)[DK], const float (&xi)[DK],
+                                             int64_t r, int64_t n, int64_t cell, float (&rt)[DK]) {
+  if (r >= n || r == cell) {
+#pragma unroll
+    for (int k = 0; k < DK; ++k) rt[k] = 0.f;
+    return __builtin_inff();
+  }
+  float n2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    rt[k] = xr[k] - xi[k];
+    n2 = __builtin_fmaf(rt[k], rt[k], n2);
+  }
+  const float inv = n2 > 0.f ? __builtin_amdgcn_rcpf(n2) : 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) rt[k] *= inv;
+  return n2;
+}
+
 // Re-evaluate t for MC ray (origin x_i) hitting node x_j.
 template <int DK>
 __device__ float reeval_cell(const float (&xi)[DK], const float *__restrict__ xj,
@@ -229,30 +262,17 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs
   }
   float nn2 = __builtin_inff();
 
+  // the coordinates of the next chunk's node are loaded one chunk ahead, so
+  // their latency hides behind the MFMA loop of the current chunk
+  float pre[DK];
+  load_node<DK>(a.nodes, n, d, tid, pre);
   for (int64_t base = 0; base < n; base += NB) {
-    __syncthreads();
-    {
-      const int64_t r = base + tid;
-      float rt[DK];
+    float rt[DK];
+    nn2 = fminf(nn2, invert_node<DK>(pre, xi, base + tid, n, cell, rt));
+    load_node<DK>(a.nodes, n, d, base + NB + tid, pre);
+    __syncthreads();  // the previous chunk is consumed
 #pragma unroll
-      for (int k = 0; k < DK; ++k) rt[k] = 0.f;
-      if (r < n && r != cell) {
-        const float *xr = a.nodes + r * d;
-        float n2 = 0.f;
-#pragma unroll
-        for (int k = 0; k < DK; ++k) {
-          rt[k] = (k < d) ? xr[k] - xi[k] : 0.f;
-          n2 = __builtin_fmaf(rt[k], rt[k], n2);
-        }
-        nn2 = fminf(nn2, n2);
-        // duplicate generators (n2 == 0) are never eligible, as in eq. (t)
-        const float inv = n2 > 0.f ? __builtin_amdgcn_rcpf(n2) : 0.f;
-#pragma unroll
-        for (int k = 0; k < DK; ++k) rt[k] *= inv;
-      }
-#pragma unroll
-      for (int kp = 0; kp < KP; ++kp) lds[kp * NB + tid] = make_float2(rt[2 * kp], rt[2 * kp + 1]);
-    }
+    for (int kp = 0; kp < KP; ++kp) lds[kp * NB + tid] = make_float2(rt[2 * kp], rt[2 * kp + 1]);
     __syncthreads();
     const int64_t rem = n - base;
     const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
@@ -359,26 +379,14 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanAr
   }
   float nn2 = __builtin_inff();
 
+  float pre[DK];
+  load_node<DK>(a.nodes, n, d, tid, pre);
   for (int64_t base = 0; base < n; base += NB) {
-    __syncthreads();
     {
-      const int64_t r = base + tid;
       float rt[DK];
-#pragma unroll
-      for (int k = 0; k < DK; ++k) rt[k] = 0.f;
-      if (r < n && r != cell) {
-        const float *xr = a.nodes + r * d;
-        float n2 = 0.f;
-#pragma unroll
-        for (int k = 0; k < DK; ++k) {
-          rt[k] = (k < d) ? xr[k] - xi[k] : 0.f;
-          n2 = __builtin_fmaf(rt[k], rt[k], n2);
-        }
-        nn2 = fminf(nn2, n2);
-        const float inv = n2 > 0.f ? __builtin_amdgcn_rcpf(n2) : 0.f;
-#pragma unroll
-        for (int k = 0; k < DK; ++k) rt[k] *= inv;
-      }
+      nn2 = fminf(nn2, invert_node<DK>(pre, xi, base + tid, n, cell, rt));
+      load_node<DK>(a.nodes, n, d, base + NB + tid, pre);
+      __syncthreads();  // the previous chunk is consumed
       __bf16 rh[DKP], rl[DKP];
 #pragma unroll
       for (int k = 0; k < DKP; ++k) split_bf16(rt[k], rh[k], rl[k]);
