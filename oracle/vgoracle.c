@@ -111,7 +111,6 @@ static void raycast_one(int d, int64_t n, const double *X, const double *x,
                         int n_excl, int clip, double *t1, int32_t *i1,
                         double *t2) {
   const double *xg = X + (int64_t)g * d;
-  double rho2 = dist2(xg, x, d);
   double best = VGO_INF, second = VGO_INF;
   int32_t bi = -1;
   for (int64_t r = 0; r < n; ++r) {
@@ -120,7 +119,11 @@ static void raycast_one(int d, int64_t n, const double *X, const double *x,
     double den = 0.0;
     for (int k = 0; k < d; ++k) den += u[k] * (xr[k] - xg[k]);
     if (!(den > 0.0)) continue;
-    double num = dist2(xr, x, d) - rho2;
+    /* |r - x|^2 - |g - x|^2 written as the difference of squares
+     * (r - g).((r - x) + (g - x)): the same quantity, without cancelling two
+     * |x|^2-sized terms when the origin is a far vertex of the diagram */
+    double num = 0.0;
+    for (int k = 0; k < d; ++k) num += (xr[k] - xg[k]) * ((xr[k] - x[k]) + (xg[k] - x[k]));
     double t = num / (2.0 * den);
     if (t < best) {
       second = best;
