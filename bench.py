@@ -85,12 +85,131 @@ def cpu_baseline(X, cells, Ds):
                        f"({rays} rays, each over all {X.shape[0]} nodes; {dt:.1f} s)")
 
 
+def _timed(stream, fn, steps):
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_uneven(args):
+    """64 uniform clouds, d in {3,4,6,8,12,16}, N log-uniform in [1e3, 2e5],
+    256 rays per cell, one persistent graph-captured launch per step; also
+    timed as 64 separate single-cloud launches."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    spec = W.uneven_batch_spec(64, seed=0)
+    R = 256
+    probs = []
+    for c, (dc, nc, sc) in enumerate(spec):
+        X = torch.from_numpy(W.uniform_cloud(nc, dc, seed=sc)).to(dev)
+        D = W.mc_directions_device(nc, R, dc, seed=5000 + c, device=dev)
+        probs.append((X, D))
+    print("[bench] uneven batch ready", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    outs = vg.raycast_cells_batched(probs)  # tunes, captures
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        vg.raycast_cells_batched(probs, out=outs)
+    ms = _timed(stream, lambda: vg.raycast_cells_batched(probs, out=outs), args.steps)
+    st = vg.stats()
+    ms_sep = _timed(stream, lambda: [vg.raycast_cells(X, D) for X, D in probs], 1)
+    rays = sum(nc * R for _, nc, _ in spec)
+    flops = sum(2.0 * dc * nc * nc * R + 2.0 * dc * nc * nc for dc, nc, _ in spec)
+    return {
+        "metric": "rays/sec batched uneven RayCast (64 clouds, d in {3..16}, N in [1e3, 2e5])",
+        "value": rays / (ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uneven64: 64 uniform clouds, 256 MC rays per cell, one persistent "
+                               "hipGraph-captured launch + FP64 recheck",
+                   "clouds": len(spec), "cells": sum(nc for _, nc, _ in spec), "rays": rays,
+                   "flagged_rays_per_step": st["flagged"],
+                   "separate_launches_ms": ms_sep, "speedup_vs_separate": ms_sep / ms},
+        "roofline": {"bound": "mfma", "achieved": flops / (ms / 1e3) / 1e12, "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / FP32_MFMA_PEAK,
+                     "traffic": None, "note": "weighted over clouds: sum 2 d N (N R + N) / time"},
+    }
+
+
+def bench_grad(args):
+    """d=4, N=50 000 uniform, 512 rays per cell: forward (volume, second
+    moment, facets) and forward + adjoint of the centroidal energy."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    d, n, R = 4, 50_000, 512
+    dev = torch.device("cuda", 0)
+    X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).to(dev)
+    D = torch.from_numpy(directions_threaded(np.arange(n), R, d, seed=1)).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    res = vg.mc_volume_area(X, D)
+    ones = torch.ones(n, device=dev)
+    fwd = lambda: vg.mc_volume_area(X, D, out=res)
+    both = lambda: (vg.mc_volume_area(X, D, out=res), vg.mc_backward(X, D, res, None, ones, None))
+    for _ in range(args.warmup):
+        both()
+    ms_f = _timed(stream, fwd, args.steps)
+    ms_b = _timed(stream, both, args.steps)
+    return {
+        "metric": "MC volume+grad cells/s (d=4, N=50k, 512 rays/cell, centroidal energy)",
+        "value": n / (ms_b / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uniform d=4 N=50000, 512 MC rays per cell, loss = sum of second moments",
+                   "forward_ms": ms_f, "forward_cells_per_s": n / (ms_f / 1e3),
+                   "adjoint_over_forward": (ms_b - ms_f) / ms_f, "rays": n * R},
+    }
+
+
+def bench_explore(args):
+    """Exhaustive vertex search (Algorithm 2) of a uniform cloud."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    n, d = (1000, 2) if args.workload == "uniform_d2_n1000" else (10_000, 6)
+    X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).cuda()
+    draws = W.descent_draws(d)
+    if args.warmup:
+        vg.explore(X, draws)
+    t0 = time.perf_counter()
+    m = vg.explore(X, draws)
+    dt = time.perf_counter() - t0
+    nv = m["sigma"].shape[0]
+    return {
+        "metric": "vertices/sec exhaustive Voronoi vertex search",
+        "value": nv / dt, "unit": "vertices/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"uniform d={d} N={n}, unbounded diagram", "vertices": nv,
+                   "unbounded_edges": int(m["b_sigma"].shape[0]), "raycasts": m["raycasts"]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--workload", default="gmm8_d10_n100000",
+                    choices=["gmm8_d10_n100000", "uneven64", "uniform_d4_n50000",
+                             "uniform_d2_n1000", "uniform_d6_n10000"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -111,6 +230,12 @@ def main():
 
     import paper_2405_10050_amd as vg
     import workloads as W
+
+    if args.workload != "gmm8_d10_n100000":
+        other = {"uneven64": bench_uneven, "uniform_d4_n50000": bench_grad,
+                 "uniform_d2_n1000": bench_explore, "uniform_d6_n10000": bench_explore}
+        print(json.dumps(other[args.workload](args)), flush=True)
+        return
 
     d, n, R = 10, args.n, args.rays
     t_setup = time.perf_counter()

@@ -307,9 +307,12 @@ class VoronoiMC(torch.autograd.Function):
         return grad, None, None
 
 
-def raycast_cells_batched(problems, precision="fp32", recheck=True):
-    """Uneven batch: ``problems`` is a list of ``(nodes [N_c, d_c], dirs
-    [N_c, R_c, d_c])``.  Returns a list of ``(t, idx, status)``."""
+def raycast_cells_batched(problems, precision="fp32", out=None):
+    """Uneven batch in one persistent (graph-captured) launch: ``problems`` is
+    a list of ``(nodes [N_c, d_c], dirs [N_c, R_c, d_c])``.  Returns a list of
+    ``(t, idx, status)`` shaped ``[N_c, R_c]``; ``out`` may pass a previous
+    result of the same batch to reuse its buffers (a repeated call on the same
+    buffers replays the captured graph)."""
     probs = (_CellsProblem * len(problems))()
     outs = []
     dev = None
@@ -321,16 +324,21 @@ def raycast_cells_batched(problems, precision="fp32", recheck=True):
         R = dirs.shape[1]
         if dirs.shape != (n, R, d):
             raise ValueError("dirs must be [N, R, d]")
-        t = torch.empty((n, R), dtype=torch.float32, device=dev)
-        idx = torch.empty((n, R), dtype=torch.int32, device=dev)
-        st = torch.empty((n, R), dtype=torch.uint8, device=dev)
+        if out is not None:
+            t, idx, st = out[q]
+            if t.shape != (n, R) or idx.shape != (n, R) or st.shape != (n, R):
+                raise ValueError("out does not match the batch")
+        else:
+            t = torch.empty((n, R), dtype=torch.float32, device=dev)
+            idx = torch.empty((n, R), dtype=torch.int32, device=dev)
+            st = torch.empty((n, R), dtype=torch.uint8, device=dev)
         outs.append((t, idx, st))
         probs[q] = _CellsProblem(d, R, n, nodes.data_ptr(), dirs.data_ptr(), t.data_ptr(),
                                  idx.data_ptr(), st.data_ptr())
     if not problems:
         return outs
     c = _ctx(dev)
-    _check(_lib.vg_raycast_cells_batched(c, len(problems), probs, _cells_flags(precision, recheck)),
+    _check(_lib.vg_raycast_cells_batched(c, len(problems), probs, _cells_flags(precision, True)),
            c, "vg_raycast_cells_batched")
     return outs
 

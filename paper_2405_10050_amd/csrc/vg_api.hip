@@ -106,17 +106,6 @@ struct ScanTimer {
 
 double sphere_area(int d) { return 2.0 * std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d); }
 
-// Error-bound coefficient of the cell scan's near-tie certificate: the
-// computed u.r~ of any node is within c |r~| <= c / nn of the exact value, so
-// a gap above 2 c / nn certifies the argmax; kappa = 4 (safety) * 2 c.
-//   FP32:    c = (2d + 4) 2^-24   (inverted node (d+4) ulps, K = d products)
-//   BF16x3:  c = 3 * 2^-18 + (4d + 4) 2^-24   (dropped lo*lo and split
-//            remainders of both operands, plus FP32 accumulation of 3d terms)
-float cell_kappa(int d, bool bf16) {
-  if (bf16) return 4.f * 2.f * (3.f * 0x1p-18f + (4.f * d + 4.f) * 0x1p-24f);
-  return 4.f * 2.f * (2.f * d + 4.f) * 0x1p-24f;
-}
-
 int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const float *dirs,
               uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *st_out) {
   const int64_t m = n * (int64_t)R;
@@ -128,6 +117,7 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   Carver cv(ctx->scratch);
   int64_t *flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
   uint8_t *st = st_out ? st_out : cv.take<uint8_t>(m);
+  ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
 
   CellScanArgs a{};
@@ -183,6 +173,7 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = cv.take<int64_t>(m);
+  ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
   RayScanArgs a{};
   a.nodes = nodes;
@@ -263,6 +254,7 @@ void vg_destroy(vg_ctx *ctx) {
     (void)hipEventDestroy(ev.first);
     (void)hipEventDestroy(ev.second);
   }
+  batch_state_free(ctx);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   if (ctx->counters) (void)hipFree(ctx->counters);
   delete ctx;
@@ -281,7 +273,8 @@ int vg_get_stats(vg_ctx *ctx, vg_stats *out) {
   uint32_t c[CNT_WORDS];
   VG_HIP(ctx, hipSetDevice(ctx->device));
   VG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  VG_HIP(ctx, hipMemcpy(c, ctx->counters, sizeof c, hipMemcpyDeviceToHost));
+  VG_HIP(ctx, hipMemcpy(c, ctx->last_counters ? ctx->last_counters : ctx->counters, sizeof c,
+                        hipMemcpyDeviceToHost));
   out->rays = ctx->last_rays;
   out->flagged = c[CNT_FLAGGED];
   out->fp64_ties = c[CNT_FP64_TIE];
@@ -332,6 +325,7 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t 
   Carver cv(ctx->scratch);
   int64_t *flag_list = recheck ? cv.take<int64_t>(n_rays) : nullptr;
   uint8_t *st = status_out ? status_out : cv.take<uint8_t>(n_rays);
+  ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
   RayScanArgs a{};
   a.nodes = nodes;
@@ -471,19 +465,6 @@ int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int 
   a.grad = grad_nodes;
   hipError_t e = launch_backward(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "backward launch");
-  return VG_OK;
-}
-
-int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_cells_problem *probs,
-                             uint32_t flags) {
-  if (!ctx) return VG_EINVAL;
-  if (n_problems < 0 || (n_problems > 0 && !probs)) return fail(ctx, VG_EINVAL, "bad problem table");
-  for (int p = 0; p < n_problems; ++p) {
-    const vg_cells_problem &q = probs[p];
-    int rc = vg_raycast_cells(ctx, q.d, q.n_nodes, q.nodes, q.rays_per_cell, q.dirs, flags,
-                              q.t_out, q.idx_out, q.status_out);
-    if (rc) return rc;
-  }
   return VG_OK;
 }
 

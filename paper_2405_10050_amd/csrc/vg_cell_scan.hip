@@ -208,7 +208,7 @@ __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (
     if (tie && a.flag_list) {
       st |= VG_ST_NEAR_TIE;
       const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
-      a.flag_list[pos] = gid;
+      a.flag_list[pos] = gid | a.flag_tag;
     }
     a.t_out[gid] = t;
     a.idx_out[gid] = j;
@@ -216,20 +216,19 @@ __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (
   }
 }
 
+// One work item of the FP32 scan: rays [chunk*RW, chunk*RW + RW) of `cell`.
+// lds holds KP * WAVES*64 float2, red WAVES*64 floats.
 template <int KP, int C, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs a) {
+__device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t cell, int chunk,
+                                               float2 *__restrict__ lds, float *red) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = NT;             // nodes per LDS chunk (one per thread)
   constexpr int RW = WAVES * C * 32; // rays per workgroup
   constexpr int DK = 2 * KP;
-  __shared__ float2 lds[KP * NB];
-  __shared__ float red[NT];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int64_t cell = blockIdx.x / a.wg_per_cell;
-  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
   const int d = a.d;
   const int64_t n = a.n;
   const int R = a.R;
@@ -299,6 +298,15 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs
   cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell);
 }
 
+template <int KP, int C, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs a) {
+  __shared__ float2 lds[KP * WAVES * 64];
+  __shared__ float red[WAVES * 64];
+  const int64_t cell = blockIdx.x / a.wg_per_cell;
+  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  scan_fp32_item<KP, C, WAVES>(a, cell, chunk, lds, red);
+}
+
 // ---------------------------------------------------------------- BF16x3
 // Split-precision variant: a = a_hi + a_lo with a_hi = bf16(a) and
 // a_lo = bf16(a - a_hi); u.r~ ~ sum hi*hi + hi*lo + lo*hi with FP32
@@ -320,22 +328,20 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
+// One work item of the BF16x3 scan; lds holds WAVES*64 * KT/8 bf16x8.
 template <int KQ, int C, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanArgs a) {
+__device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t cell, int chunk,
+                                                 bf16x8 *__restrict__ lds, float *red) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = NT;
   constexpr int RW = WAVES * C * 32;
   constexpr int DKP = Bf16Pack<KQ>::DKP;
   constexpr int KT = Bf16Pack<KQ>::KT;
   constexpr int DK = DKP;
-  __shared__ bf16x8 lds[NB * (KT / 8)];
-  __shared__ float red[NT];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int64_t cell = blockIdx.x / a.wg_per_cell;
-  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
   const int d = a.d;
   const int64_t n = a.n;
   const int R = a.R;
@@ -424,6 +430,72 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanAr
   cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell);
 }
 
+template <int KQ, int C, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanArgs a) {
+  __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
+  __shared__ float red[WAVES * 64];
+  const int64_t cell = blockIdx.x / a.wg_per_cell;
+  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  scan_bf16x3_item<KQ, C, WAVES>(a, cell, chunk, lds, red);
+}
+
+// ------------------------------------------------------- persistent batches
+// Uneven batches of clouds: workgroups take (cloud, cell, ray chunk) items
+// from a device counter, in the order of the item table (largest clouds
+// first), until the counter passes the end.  Every instantiation of the
+// single-cloud item for the cloud's K extent is reachable from one kernel.
+template <int C, int WAVES, bool BF16>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_batched_kernel(const BatchProblem *probs,
+                                                                      int np, int64_t total,
+                                                                      unsigned long long *next) {
+  constexpr int NT = WAVES * 64;
+  constexpr size_t FP32_LDS = 8 * NT * sizeof(float2);
+  constexpr size_t BF16_LDS = NT * (Bf16Pack<3>::KT / 8) * sizeof(bf16x8);
+  __shared__ __align__(16) unsigned char raw[BF16 ? BF16_LDS : FP32_LDS];
+  __shared__ float red[NT];
+  __shared__ long long item_s;
+  for (;;) {
+    __syncthreads();  // the previous item is finished
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(next, 1ull);
+    __syncthreads();
+    const long long item = item_s;
+    if (item >= total) break;
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (probs[mid].item_begin <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const CellScanArgs a = probs[lo].a;
+    const int64_t local = item - probs[lo].item_begin;
+    const int64_t cell = local / a.wg_per_cell;
+    const int chunk = (int)(local - cell * a.wg_per_cell);
+    if (BF16) {
+      bf16x8 *l = reinterpret_cast<bf16x8 *>(raw);
+      if (a.d <= 5)
+        scan_bf16x3_item<1, C, WAVES>(a, cell, chunk, l, red);
+      else if (a.d <= 10)
+        scan_bf16x3_item<2, C, WAVES>(a, cell, chunk, l, red);
+      else
+        scan_bf16x3_item<3, C, WAVES>(a, cell, chunk, l, red);
+    } else {
+      float2 *l = reinterpret_cast<float2 *>(raw);
+      switch ((a.d + 1) >> 1) {
+        case 1: scan_fp32_item<1, C, WAVES>(a, cell, chunk, l, red); break;
+        case 2: scan_fp32_item<2, C, WAVES>(a, cell, chunk, l, red); break;
+        case 3: scan_fp32_item<3, C, WAVES>(a, cell, chunk, l, red); break;
+        case 4: scan_fp32_item<4, C, WAVES>(a, cell, chunk, l, red); break;
+        case 5: scan_fp32_item<5, C, WAVES>(a, cell, chunk, l, red); break;
+        case 6: scan_fp32_item<6, C, WAVES>(a, cell, chunk, l, red); break;
+        case 7: scan_fp32_item<7, C, WAVES>(a, cell, chunk, l, red); break;
+        default: scan_fp32_item<8, C, WAVES>(a, cell, chunk, l, red); break;
+      }
+    }
+  }
+}
+
 template <int C, int WAVES>
 hipError_t launch_kq(const CellScanArgs &a, hipStream_t s, int grid) {
   dim3 blk(WAVES * 64);
@@ -502,6 +574,51 @@ hipError_t launch_cell_scan_bf16x3(const CellScanArgs &a0, hipStream_t s) {
     case 128: return launch_kq<1, 4>(a, s, grid);
     default: return launch_kq<1, 2>(a, s, grid);
   }
+}
+
+// Shapes of the persistent batched scan (rays per item = 32 * C * WAVES).
+const BatchShape kBatchShapes[kNumBatchShapes] = {{1, 8}, {2, 4}, {4, 8}};
+
+hipError_t launch_cell_scan_batched(const BatchProblem *probs_dev, int np, int64_t total,
+                                    unsigned long long *next, int shape, bool bf16, int grid,
+                                    hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+#define VG_BATCH(Cc, Ww)                                                                      \
+  do {                                                                                        \
+    if (bf16)                                                                                 \
+      hipLaunchKernelGGL((cell_scan_batched_kernel<Cc, Ww, true>), dim3(grid), dim3(Ww * 64), \
+                         0, s, probs_dev, np, total, next);                                   \
+    else                                                                                      \
+      hipLaunchKernelGGL((cell_scan_batched_kernel<Cc, Ww, false>), dim3(grid),               \
+                         dim3(Ww * 64), 0, s, probs_dev, np, total, next);                    \
+  } while (0)
+  switch (shape) {
+    case 0: VG_BATCH(1, 8); break;
+    case 1: VG_BATCH(2, 4); break;
+    default: VG_BATCH(4, 8); break;
+  }
+#undef VG_BATCH
+  return hipGetLastError();
+}
+
+int batched_blocks_per_cu(int shape, bool bf16) {
+  int nb = 0;
+  hipError_t e;
+  switch (shape) {
+    case 0:
+      e = bf16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<1, 8, true>, 512, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<1, 8, false>, 512, 0);
+      break;
+    case 1:
+      e = bf16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<2, 4, true>, 256, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<2, 4, false>, 256, 0);
+      break;
+    default:
+      e = bf16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<4, 8, true>, 512, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<4, 8, false>, 512, 0);
+      break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 }  // namespace vg

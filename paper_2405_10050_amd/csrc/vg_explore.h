@@ -20,7 +20,10 @@ struct ExploreRays {
   const int32_t *idx;      // [m] raycast result
   int32_t *new_keys;       // [m][d+1] (key[0] < 0: no vertex)
   double *new_coords;      // [m][d]
+  int64_t n_nodes;         // nodes (for the sphere check)
 };
+
+hipError_t launch_sphere_check(const ExploreRays &a, double *viol, hipStream_t s);
 
 hipError_t launch_edge_rays(const ExploreRays &a, hipStream_t s);
 hipError_t launch_new_vertices(const ExploreRays &a, hipStream_t s);

@@ -14,6 +14,9 @@
 // order of discovery (and may discover a vertex twice in one level, which the
 // set absorbs).
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -146,7 +149,7 @@ struct Explorer {
 
   DevBuf keys_d, coords_d;  // device mirror of the vertex table
   int64_t dev_count = 0;    // vertices mirrored on the device
-  DevBuf item_v, item_o, o64, u64, gen, excl, ok, tb, idx, st, nkeys, ncoords;
+  DevBuf item_v, item_o, o64, u64, gen, excl, ok, tb, idx, st, nkeys, ncoords, viol;
 
   bool hip(hipError_t e, const char *what) {
     if (e != hipSuccess) {
@@ -307,6 +310,10 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     *V.find_or_insert(M->sig.data(), 0, ins) = 0;
     count_edges(M->sig.data());
     int64_t level_begin = 0, level_end = 1;
+    const bool verbose = std::getenv("VG_VERBOSE") != nullptr;
+    const bool validate = std::getenv("VG_VALIDATE") != nullptr;
+    const auto t_start = std::chrono::steady_clock::now();
+    int level = 0;
     std::vector<int64_t> iv;
     std::vector<int32_t> io, jh, kh;
     std::vector<double> ch;
@@ -371,11 +378,50 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       er.idx = X.idx.as<int32_t>();
       er.new_keys = X.nkeys.as<int32_t>();
       er.new_coords = X.ncoords.as<double>();
+      er.n_nodes = n_nodes;
       EX_HIP(launch_edge_rays(er, X.s));
       EX_RC(raycast_f64(ctx, d, n_nodes, nodes, m, er.o64, er.u64, er.gen, er.excl, d, 0, false,
                         X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr));
       M->raycasts += m;
       EX_HIP(launch_new_vertices(er, X.s));
+      if (validate) {
+        // report the edge rays whose new vertex has a node inside its sphere
+        EX_HIP(X.viol.reserve(sizeof(double) * m, false, X.s));
+        EX_HIP(launch_sphere_check(er, X.viol.as<double>(), X.s));
+        std::vector<double> vh(m);
+        std::vector<float> th(m);
+        std::vector<uint8_t> sh(m);
+        EX_HIP(hipMemcpyAsync(vh.data(), X.viol.p, sizeof(double) * m, hipMemcpyDeviceToHost, X.s));
+        EX_HIP(hipMemcpyAsync(th.data(), X.tb.p, sizeof(float) * m, hipMemcpyDeviceToHost, X.s));
+        EX_HIP(hipMemcpyAsync(sh.data(), X.st.p, m, hipMemcpyDeviceToHost, X.s));
+        std::vector<int32_t> jj(m);
+        EX_HIP(hipMemcpyAsync(jj.data(), X.idx.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, X.s));
+        EX_HIP(hipStreamSynchronize(X.s));
+        int shown = 0;
+        int64_t bad = 0;
+        for (int64_t it = 0; it < m; ++it) {
+          if (vh[it] < -1e-9) {
+            ++bad;
+            if (shown < 8) {
+              ++shown;
+              const int32_t *vk = &M->sig[iv[it] * L];
+              std::fprintf(stderr, "[explore] level %d item %lld: vertex %lld omit %d hit %d t=%.9g status=%u violation=%.3e coord0=",
+                           level + 1, (long long)it, (long long)iv[it], vk[io[it]], jj[it], th[it],
+                           (unsigned)sh[it], vh[it]);
+              for (int k = 0; k < d; ++k) std::fprintf(stderr, "%.6g ", M->coord[iv[it] * d + k]);
+              std::fprintf(stderr, "\n");
+            }
+          }
+        }
+        if (bad) {
+          std::fprintf(stderr, "[explore] level %d: %lld new vertices violate the empty sphere\n",
+                       level + 1, (long long)bad);
+          std::fflush(stderr);
+          ctx->err = "explore validation failed";
+          rc = VG_EINVAL;
+          goto fail;
+        }
+      }
       jh.resize(m);
       kh.resize(m * L);
       ch.resize(m * d);
@@ -409,6 +455,14 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
         count_edges(nk);
       }
       level_end = (int64_t)M->sig.size() / L;
+      ++level;
+      if (verbose) {
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        std::fprintf(stderr, "[explore] level %d: %lld rays, %lld new vertices, %lld total, %.2f s\n",
+                     level, (long long)m, (long long)(level_end - level_begin),
+                     (long long)level_end, el);
+        std::fflush(stderr);
+      }
     }
   }
   *out = M;

@@ -206,7 +206,51 @@ __global__ void solve_one_kernel(const float *X, int d, const int32_t *sig, doub
   *ok = good ? 1 : 0;
 }
 
+// Empty-circumsphere check of new vertices (Sec. 2.2 incircle criterion):
+// viol[it] = min over nodes r not in the key of (|r - v|^2 - rho^2) / rho^2,
+// negative when a node lies strictly inside the vertex's sphere.
+__global__ __launch_bounds__(256) void sphere_check_kernel(ExploreRays a, double *viol) {
+  const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (it >= a.m) return;
+  const int d = a.d;
+  const int32_t *key = a.new_keys + it * (d + 1);
+  if (key[0] < 0) {
+    viol[it] = 0.0;
+    return;
+  }
+  const double *v = a.new_coords + it * d;
+  const float *x0 = a.nodes + (int64_t)key[0] * d;
+  double rho2 = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double e = (double)x0[k] - v[k];
+    rho2 += e * e;
+  }
+  double worst = __builtin_inf();
+  int kp = 0;
+  for (int64_t r = 0; r < a.n_nodes; ++r) {
+    if (kp <= d && key[kp] == (int32_t)r) {
+      ++kp;
+      continue;
+    }
+    const float *xr = a.nodes + r * d;
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double e = (double)xr[k] - v[k];
+      s += e * e;
+    }
+    worst = fmin(worst, (s - rho2) / rho2);
+  }
+  viol[it] = worst;
+}
+
 }  // namespace
+
+hipError_t launch_sphere_check(const ExploreRays &a, double *viol, hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sphere_check_kernel, dim3((unsigned)((a.m + 255) / 256)), dim3(256), 0, s, a,
+                     viol);
+  return hipGetLastError();
+}
 
 #define VG_DK_DISPATCH(d, KERNEL, GRID, BLK, ...)                                     \
   do {                                                                                \

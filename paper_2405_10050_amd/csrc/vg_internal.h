@@ -58,7 +58,21 @@ struct CellScanArgs {
   int64_t *flag_list;
   float tau_rel;      // relative gap floor
   float kappa;        // absolute FP32 error bound coefficient (times 1/nn-distance)
+  int64_t flag_tag;   // ORed into queued ray ids (batched mode: problem << 40)
 };
+
+// One cloud of a persistent batch: its scan arguments and the first global
+// item of its (cell, ray-chunk) items.
+struct BatchProblem {
+  CellScanArgs a;
+  int64_t item_begin;
+};
+
+struct BatchShape {
+  int C, waves;
+};
+constexpr int kNumBatchShapes = 3;
+extern const BatchShape kBatchShapes[kNumBatchShapes];
 
 struct RecheckArgs {
   int mode;
@@ -126,6 +140,27 @@ hipError_t launch_accum(const AccumArgs &a, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
+hipError_t launch_cell_scan_batched(const BatchProblem *probs_dev, int np, int64_t total,
+                                    unsigned long long *next, int shape, bool bf16, int grid,
+                                    hipStream_t s);
+int batched_blocks_per_cu(int shape, bool bf16);
+hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t *counters,
+                                  const int64_t *flag_list, uint32_t *tie_counter, int grid,
+                                  hipStream_t s);
+
+// Error-bound coefficient of the cell scan's near-tie certificate: the
+// computed u.r~ of any node is within c |r~| <= c / nn of the exact value, so
+// a gap above 2 c / nn certifies the argmax; kappa = 4 (safety) * 2 c.
+//   FP32:    c = (2d + 4) 2^-24   (inverted node (d+4) ulps, K = d products)
+//   BF16x3:  c = 3 * 2^-18 + (4d + 4) 2^-24   (dropped lo*lo and split
+//            remainders of both operands, plus FP32 accumulation of 3d terms)
+inline float cell_kappa(int d, bool bf16) {
+  if (bf16) return 4.f * 2.f * (3.f * 0x1p-18f + (4.f * d + 4.f) * 0x1p-24f);
+  return 4.f * 2.f * (2.f * d + 4.f) * 0x1p-24f;
+}
+
+void batch_state_free(vg_ctx *ctx);
+
 // Cell-scan tile choice: rays per workgroup for a given rays-per-cell.
 int cell_scan_rays_per_wg(int R);
 
@@ -148,6 +183,8 @@ struct vg_ctx {
   uint32_t *counters = nullptr;  // device [CNT_WORDS]
   int64_t last_rays = 0;
   double last_tau = 0.0;
+  uint32_t *last_counters = nullptr;  // counters written by the last call (stats)
+  void *batch_state = nullptr;         // graphs, tuner cache of the batched path
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> scan_events;  // pending timings
   int64_t scan_launches = 0;

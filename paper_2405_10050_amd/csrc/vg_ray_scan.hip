@@ -2,19 +2,25 @@
 //
 // Each ray has its own origin x (a Voronoi vertex during the exhaustive
 // search), so the contraction X.R^T has no reuse across rays; the scan
-// evaluates eq. (t) directly in difference form,
-//     num = sum_k (r_k - x_k)^2 - |g - x|^2,   den = sum_k u_k (r_k - g_k),
-// which is exact up to FP32 rounding of the differences (the expanded form
-// |r|^2 - 2 x.r would cancel when |r - x| << |r|).  Eligible nodes have
-// den > 0 and are not in eta (sorted, walked alongside the ascending node
-// index).  One thread per ray; nodes stream through LDS in tiles of 256 and
-// are broadcast to the 64 lanes of a wave.
+// evaluates eq. (t) directly, with the numerator as a difference of squares
+// in factored form,
+//     num = |r - x|^2 - |g - x|^2 = sum_k (r_k - g_k) ((r_k - x_k) + (g_k - x_k)),
+//     den = sum_k u_k (r_k - g_k),
+// which stays accurate when the origin is far from the nodes (hull vertices
+// of the unbounded diagram reach |x| ~ 1e6): no |x|^2-sized terms cancel.
+// Eligible nodes have den > 0 and are not in eta (sorted, walked alongside
+// the ascending node index).  One thread per ray; nodes stream through LDS in
+// tiles of 256 and are broadcast to the 64 lanes of a wave.
 //
 // The running top-2 avoids a division per pair: a node can only enter the
 // top-2 if num < t2 * den (den > 0); only then is t = num/den formed.
-// A ray is queued for the FP64 recheck when its two best candidates are
-// within a relative gap tau, when it has no hit, or when the winner's
-// bisector is nearly parallel to the ray (den tiny relative to |u||r - g|).
+// A ray is queued for the FP64 recheck when
+//   * its two best candidates are within their FP32 error bounds (or a
+//     relative gap tau),
+//   * the winner's own FP32 error bound exceeds tau t (far origins),
+//   * some nearly grazing node (|den| within its rounding bound, so its true
+//     eligibility is unknown) could still beat the winner,
+//   * the winner's bisector is nearly parallel to the ray, or it has no hit.
 #include "vg_dfloat.h"
 #include "vg_internal.h"
 
@@ -55,12 +61,17 @@ __global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
 #pragma unroll
     for (int k = 0; k < DK; ++k) x[k] = u[k] = g[k] = 0.f;
   }
-  float rho2 = 0.f;
+  float rho2 = 0.f, gx[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
-    const float e = g[k] - x[k];
-    rho2 = __builtin_fmaf(e, e, rho2);
+    gx[k] = g[k] - x[k];
+    rho2 = __builtin_fmaf(gx[k], gx[k], rho2);
   }
+  // grazing test: den^2 <= kd^2 |r - g|^2 with |r - g|^2 <= 2 num + 4 rho^2
+  const float kd = (4.f * (float)(d + 4)) * 0x1p-24f;
+  const float kd2 = kd * kd;
+  const float rho4 = 4.f * rho2;
+  float gmin = __builtin_inff();  // smallest num of a nearly grazing node
   const int32_t *ex = (active && a.n_excl > 0) ? a.excl + ray * a.n_excl : nullptr;
   int ep = 0;
   int32_t next_ex = ex ? ex[0] : -1;
@@ -80,19 +91,20 @@ __global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
     const int cnt = (int)((n - base) < TILE ? (n - base) : TILE);
     for (int q = 0; q < cnt; ++q) {
       const int32_t r = (int32_t)(base + q);
-      float num = -rho2, den = 0.f;
+      float num = 0.f, den = 0.f;
 #pragma unroll
       for (int k = 0; k < DK; ++k) {
         const float xr = sx[q * DK + k];
-        const float dx = xr - x[k];
-        num = __builtin_fmaf(dx, dx, num);
-        den = __builtin_fmaf(u[k], xr - g[k], den);
+        const float a_k = xr - g[k];
+        num = __builtin_fmaf(a_k, (xr - x[k]) + gx[k], num);
+        den = __builtin_fmaf(u[k], a_k, den);
       }
       if (r == next_ex) {
         ++ep;
         next_ex = ep < a.n_excl ? ex[ep] : -1;
         continue;
       }
+      if (den * den <= kd2 * __builtin_fmaf(2.f, num, rho4)) gmin = fminf(gmin, num);
       if (den > 0.f && num < t2 * den) {
         const float t = num / den;
         if (t < t1) {
@@ -122,8 +134,8 @@ __global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
   const float rho = sqrtf(rho2);
   auto tbound = [&](float tc, float dc) {
     const float rx2 = tc * dc + rho2;
-    const float rg = sqrtf(fmaxf(rx2, 0.f)) + rho;
-    float en = kap * (rx2 + rho2);
+    const float rg = sqrtf(fmaxf(rx2, 0.f)) + rho;  // bounds |r - g| and |(r-x)+(g-x)|
+    float en = kap * rg * rg;
     float ed = kap * rg;
     if (rounded) {
       en += 2.f * rg * 0x1p-24f * sqrtf(xn2);
@@ -131,9 +143,17 @@ __global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
     }
     return (en + tc * ed) / dc;
   };
-  float eb = 0.f;
-  if (i1 >= 0) eb += 0.5f * tbound(t1, den1);
+  float eb = 0.f, eb1 = 0.f;
+  if (i1 >= 0) eb += eb1 = 0.5f * tbound(t1, den1);
   if (i1 >= 0 && t2 < __builtin_inff()) eb += 0.5f * tbound(t2, den2);
+  // a nearly grazing node with true den up to 2 kd |r-g| beats t1' when
+  // num < 2 kd |r-g| t1'; in squares: num^2 <= 4 kd^2 (2 num + 4 rho^2) t1'^2
+  bool grazing = false;
+  if (gmin < __builtin_inff()) {
+    grazing = gmin < 0.f ||
+              gmin * gmin <= 4.f * kd2 * __builtin_fmaf(2.f, gmin, rho4) * t1 * t1 ||
+              i1 < 0;
+  }
 
   float T1 = 0.5f * t1, T2 = 0.5f * t2;
   int32_t j = i1;
@@ -162,7 +182,8 @@ __global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
     }
   }
   uint8_t st = 0;
-  bool flag = a.force_all || !(T2 - T1 > fmaxf(a.tau * T1, 4.f * eb));
+  bool flag = a.force_all || grazing || !(T2 - T1 > fmaxf(a.tau * T1, 4.f * eb)) ||
+              !(4.f * eb1 <= a.tau * T1);
   float t = T1;
   if (j >= 0) {
     // re-evaluate the winner in double-float; check it is not grazing

@@ -1,9 +1,10 @@
 // FP64 re-evaluation of the rays whose FP32 scan could not certify its
 // argmin (near-ties, no hit, grazing winners).
 //
-// For each queued ray every node is evaluated in FP64 with eq. (t) in
-// difference form, t = (|r - x|^2 - |g - x|^2) / (2 u.(r - g)) over nodes with
-// u.(r - g) > 0 not in eta; the smallest t wins (lowest index on equality),
+// For each queued ray every node is evaluated in FP64 with eq. (t),
+// t = (|r - x|^2 - |g - x|^2) / (2 u.(r - g)) over nodes with u.(r - g) > 0
+// not in eta, the numerator in the factored form (r - g).((r - x) + (g - x))
+// (no |x|^2-sized cancellation for far origins); the smallest t wins (lowest index on equality),
 // then the cube clip applies, and the ray's result is overwritten.  FP
 // contraction is off so that each t is the same IEEE expression as a plain
 // sequential evaluation.
@@ -82,12 +83,6 @@ __global__ __launch_bounds__(NT) void recheck_kernel(RecheckArgs a) {
       if (lane < d) sg[w][lane] = (double)a.nodes[(int64_t)gi * d + lane];
     }
     __syncthreads();
-    double rho2 = 0.0;
-    if (live)
-      for (int k = 0; k < d; ++k) {
-        const double e = sg[w][k] - sx[w][k];
-        rho2 += e * e;
-      }
     Top2 tp{__builtin_inf(), __builtin_inf(), -1};
     for (int64_t base = 0; base < n; base += TILE) {
       const int cntn = (int)((n - base) < TILE ? (n - base) : TILE);
@@ -104,12 +99,10 @@ __global__ __launch_bounds__(NT) void recheck_kernel(RecheckArgs a) {
         double den = 0.0;
         for (int k = 0; k < d; ++k) den += su[w][k] * ((double)xr[k] - sg[w][k]);
         if (!(den > 0.0)) continue;
+        // |r - x|^2 - |g - x|^2 as (r - g).((r - x) + (g - x))
         double num = 0.0;
-        for (int k = 0; k < d; ++k) {
-          const double e = (double)xr[k] - sx[w][k];
-          num += e * e;
-        }
-        num -= rho2;
+        for (int k = 0; k < d; ++k)
+          num += ((double)xr[k] - sg[w][k]) * (((double)xr[k] - sx[w][k]) + (sg[w][k] - sx[w][k]));
         // cheap filter (relaxed by 1e-12 so no candidate within rounding is lost)
         if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) continue;
         const double t = num / (2.0 * den);
@@ -178,7 +171,109 @@ __global__ __launch_bounds__(NT) void recheck_kernel(RecheckArgs a) {
   }
 }
 
+// Batched Monte-Carlo rays: a queue entry is (problem << 40 | ray); each wave
+// takes one entry and reads that cloud's nodes directly (entries of one
+// workgroup may belong to different clouds, so no LDS tile is shared).
+__global__ __launch_bounds__(NT) void recheck_batched_kernel(const BatchProblem *probs,
+                                                             const uint32_t *counters,
+                                                             const int64_t *flag_list,
+                                                             uint32_t *tie_counter) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t cnt = counters[CNT_FLAGGED];
+  const uint32_t nw = gridDim.x * WAVES;
+  for (uint32_t f = blockIdx.x * WAVES + (threadIdx.x >> 6); f < cnt; f += nw) {
+    const int64_t code = flag_list[f];
+    const int p = (int)(code >> 40);
+    const int64_t ray = code & ((int64_t(1) << 40) - 1);
+    const CellScanArgs &a = probs[p].a;
+    const int d = a.d;
+    const int64_t cell = ray / a.R;
+    double x[VG_MAX_DIM], u[VG_MAX_DIM];
+    for (int k = 0; k < d; ++k) {
+      x[k] = (double)a.nodes[cell * d + k];
+      u[k] = (double)a.dirs[ray * d + k];
+    }
+    Top2 tp{__builtin_inf(), __builtin_inf(), -1};
+    for (int64_t r = lane; r < a.n; r += 64) {
+      if (r == cell) continue;
+      const float *xr = a.nodes + r * d;
+      double den = 0.0;
+      for (int k = 0; k < d; ++k) den += u[k] * ((double)xr[k] - x[k]);
+      if (!(den > 0.0)) continue;
+      double num = 0.0;  // (r - g).((r - x) + (g - x)) with x = g
+      for (int k = 0; k < d; ++k)
+        num += ((double)xr[k] - x[k]) * (((double)xr[k] - x[k]) + (x[k] - x[k]));
+      if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) continue;
+      const double t = num / (2.0 * den);
+      if (t < tp.t1) {
+        tp.t2 = tp.t1;
+        tp.t1 = t;
+        tp.i1 = (int32_t)r;
+      } else if (t < tp.t2) {
+        tp.t2 = t;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      Top2 o;
+      o.t1 = __shfl_xor(tp.t1, off);
+      o.t2 = __shfl_xor(tp.t2, off);
+      o.i1 = __shfl_xor(tp.i1, off);
+      tp = merge(tp, o);
+    }
+    if (lane == 0) {
+      double t1 = tp.t1, t2 = tp.t2;
+      int32_t i1 = tp.i1;
+      double tb = __builtin_inf();
+      int face = -1;
+      for (int k = 0; k < d; ++k) {
+        double tk;
+        int fc;
+        if (u[k] > 0.0) {
+          tk = (1.0 - x[k]) / u[k];
+          fc = 2 * k + 1;
+        } else if (u[k] < 0.0) {
+          tk = (0.0 - x[k]) / u[k];
+          fc = 2 * k;
+        } else {
+          continue;
+        }
+        if (tk < tb) {
+          tb = tk;
+          face = fc;
+        }
+      }
+      if (face >= 0) {
+        if (tb < t1) {
+          t2 = t1;
+          t1 = tb;
+          i1 = -2 - face;
+        } else if (tb < t2) {
+          t2 = tb;
+        }
+      }
+      uint8_t st = (uint8_t)((a.st_out[ray] & ~VG_ST_NO_HIT) | VG_ST_RECHECKED);
+      if (i1 == -1) st |= VG_ST_NO_HIT;
+      if (t2 - t1 <= 1e-9 * fabs(t1)) {
+        st |= VG_ST_FP64_TIE;
+        atomicAdd(tie_counter, 1u);
+      }
+      a.t_out[ray] = (float)t1;
+      a.idx_out[ray] = i1;
+      a.st_out[ray] = st;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t *counters,
+                                  const int64_t *flag_list, uint32_t *tie_counter, int grid,
+                                  hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(recheck_batched_kernel, dim3(grid), dim3(NT), 0, s, probs_dev, counters,
+                     flag_list, tie_counter);
+  return hipGetLastError();
+}
 
 hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
   if (max_grid <= 0) return hipSuccess;

@@ -2,7 +2,9 @@
 
 This module only draws random numbers.  It holds none of the method's
 arithmetic: no ray casting, no estimator, no geometry.  Everything it returns
-is a NumPy array on the host; callers move it to the device themselves.
+is a NumPy array on the host (callers move it to the device themselves),
+except ``mc_directions_device``, which draws very large direction sets on the
+GPU with torch's seeded generator.
 
 Conventions
 -----------
@@ -31,6 +33,7 @@ __all__ = [
     "gaussian_mixture_cloud",
     "jittered_lattice",
     "mc_directions",
+    "mc_directions_device",
     "descent_draws",
     "uneven_batch_spec",
     "fd_generators",
@@ -119,6 +122,26 @@ def mc_directions(cells, n_rays: int, d: int, seed: int = 1) -> np.ndarray:
     out = np.empty((cells.size, n_rays, d), dtype=np.float32)
     for a, c in enumerate(cells):
         out[a] = _cell_directions(seed, c, n_rays, d)
+    return out
+
+
+def mc_directions_device(n_cells: int, n_rays: int, d: int, seed: int, device):
+    """Unit directions ``[n_cells][n_rays][d]`` float32 drawn on a GPU with
+    torch's seeded Philox generator (standard normal in float64, normalised,
+    rounded to float32).  Used where the host draw would be too slow (the
+    uneven batch holds about 6e9 numbers); the oracle reads host copies of
+    the cells it checks."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = torch.empty((n_cells, n_rays, d), dtype=torch.float32, device=device)
+    step = max(1, (1 << 26) // max(1, n_rays * d))
+    for c0 in range(0, n_cells, step):
+        c1 = min(n_cells, c0 + step)
+        z = torch.randn((c1 - c0, n_rays, d), generator=g, dtype=torch.float64, device=device)
+        z /= torch.sqrt((z * z).sum(dim=-1, keepdim=True))
+        out[c0:c1] = z.float()
     return out
 
 
