@@ -37,3 +37,47 @@ def test_explore_matches_oracle(vg, d, n):
     assert np.array_equal(bg, br)
     if d == 2 and n == 1000:
         assert a.shape[0] == 1980 and bg.shape[0] == 18
+
+
+def test_explore_d6_n1000_equals_sequential_oracle(vg):
+    d, n = 6, 1000
+    X = W.uniform_cloud(n, d, seed=0)
+    draws = W.descent_draws(d)
+    got = vg.explore(torch.from_numpy(X).cuda(), draws)
+    ref = oracle.explore(X, draws)
+    assert np.array_equal(oracle.sorted_rows(got["sigma"]), oracle.sorted_rows(ref["sigma"]))
+    bg = oracle.sorted_rows(np.column_stack([got["b_sigma"], got["b_omit"]]))
+    br = oracle.sorted_rows(np.column_stack([ref["b_sigma"], ref["b_omit"]]))
+    assert np.array_equal(bg, br)
+
+
+def test_explore_d6_n10000_full_size_properties(vg):
+    """The d=6, N=10 000 exhaustive search at full size: the simplices of the
+    vertex keys tile the convex hull (volumes sum to its volume), every hull
+    facet carries exactly one unbounded edge, and sampled vertices satisfy the
+    incircle criterion by brute force."""
+    from math import factorial
+
+    from scipy.spatial import ConvexHull
+
+    d, n = 6, 10_000
+    X = W.uniform_cloud(n, d, seed=0)
+    X64 = X.astype(np.float64)
+    got = vg.explore(torch.from_numpy(X).cuda(), W.descent_draws(d))
+    sig = got["sigma"]
+    print(f"d=6 N=10000: {sig.shape[0]} vertices, {got['b_sigma'].shape[0]} unbounded edges",
+          flush=True)
+    # no duplicate keys
+    assert np.unique(sig, axis=0).shape[0] == sig.shape[0]
+    P = X64[sig]
+    vol = np.abs(np.linalg.det(P[:, 1:] - P[:, :1])).sum() / factorial(d)
+    hull = ConvexHull(X64)
+    assert vol == pytest.approx(hull.volume, rel=1e-9)
+    assert got["b_sigma"].shape[0] == hull.simplices.shape[0]
+    rng = np.random.default_rng(0)
+    for v in rng.choice(sig.shape[0], 2000, replace=False):
+        c = got["coord"][v]
+        d2 = ((X64 - c) ** 2).sum(axis=1)
+        r2 = d2[sig[v]]
+        assert np.allclose(r2, r2[0], rtol=1e-7)
+        assert d2.min() >= r2[0] * (1 - 1e-9)
