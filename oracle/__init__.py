@@ -30,6 +30,8 @@ Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
   mc_adjoint                central finite differences of the FP64 estimator
                             with frozen directions; the centroidal-energy
                             gradient identity 2 V (x - c).
+  star                      equals the vertices of ``explore`` that contain the
+                            generator.
 No oracle function is unpinned.
 """
 from __future__ import annotations
@@ -80,6 +82,8 @@ def _load():
         lib.vgo_mc_ray_weights.argtypes = [i32, i64, P, i64, P, i32, P, P, P, P, P, P]
         lib.vgo_mc_adjoint.argtypes = [i32, i64, P, i64, P, i32, P, P, P, dbl, P, P, P, P]
         lib.vgo_num_threads.restype = i32
+        lib.vgo_star.argtypes = [i32, i64, P, i32, P, i32, P, i64]
+        lib.vgo_star.restype = i64
         _lib = lib
     return _lib
 
@@ -214,6 +218,21 @@ def explore(nodes, draws, mode: int = 0):
                     duplicates=int(lib.vgo_mesh_duplicates(h)))
     finally:
         lib.vgo_mesh_free(h)
+
+
+def star(nodes, i, draws, cap=200_000):
+    """Vertices of the unbounded diagram whose generators include ``i``
+    (sorted tuples ``[V_i][d+1]``): Algorithm 2 restricted to the edges that
+    keep ``i``.  ``neighbours(star)`` are the Voronoi neighbours of ``i``."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    W = _f64(draws).reshape(-1, d)
+    out = np.empty((cap, d + 1), dtype=np.int32)
+    nv = lib.vgo_star(d, n, _p(X), int(i), _p(W), W.shape[0], _p(out), cap)
+    if nv < 0:
+        raise RuntimeError("oracle star failed")
+    return out[:nv].copy()
 
 
 def circumcentre(nodes, sigma):

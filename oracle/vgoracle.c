@@ -672,6 +672,94 @@ fail:
   return NULL;
 }
 
+/* The star of generator i: every vertex of the unbounded diagram whose
+ * generators include i, found by Algorithm 2 restricted to the edges that
+ * keep i (a Descent from sigma = {i}, r = x_i starts it).  Its vertices'
+ * other generators are the Voronoi neighbours of i.  Returns the number of
+ * vertices written to sig_out ([cap][d+1], sorted tuples), or -1. */
+int64_t vgo_star(int d, int64_t n, const double *X, int32_t i, const double *draws,
+                 int n_draws, int32_t *sig_out, int64_t cap) {
+  if (d < 1 || d > 63 || n < d + 1) return -1;
+  /* Descent from sigma = {i}, r = x_i (the steps of Algorithm 2's Descent) */
+  vgo_mesh tmp;
+  memset(&tmp, 0, sizeof tmp);
+  tmp.d = d;
+  int32_t sigma[64];
+  double r[64], u[64], v[64];
+  int m = 1, used = 0;
+  sigma[0] = i;
+  for (int k = 0; k < d; ++k) r[k] = X[(int64_t)i * d + k];
+  while (m < d + 1) {
+    if (used >= n_draws) return -1;
+    for (int k = 0; k < d; ++k) u[k] = draws[used * d + k];
+    used++;
+    project_out_span(d, X, sigma, m, u);
+    double nr = sqrt(dot(u, u, d));
+    if (!(nr > 0.0)) continue;
+    for (int k = 0; k < d; ++k) u[k] /= nr;
+    double t;
+    int32_t j = cast(d, n, X, sigma, m, r, u, 0, &t, &tmp);
+    if (j < 0) {
+      for (int k = 0; k < d; ++k) u[k] = -u[k];
+      j = cast(d, n, X, sigma, m, r, u, 0, &t, &tmp);
+    }
+    if (j < 0) continue;
+    for (int k = 0; k < d; ++k) r[k] += t * u[k];
+    sigma[m++] = j;
+  }
+  sort_small(sigma, d + 1);
+  if (circumcentre(d, X, sigma, v)) return -1;
+  tmap V;
+  if (tmap_init(&V, d + 1, 1 << 10)) return -1;
+  int cr;
+  int64_t nv = 0;
+  double *coord = (double *)malloc(sizeof(double) * (size_t)(cap * d));
+  if (!coord || cap < 1) {
+    free(coord);
+    tmap_free(&V);
+    return -1;
+  }
+  memcpy(sig_out, sigma, sizeof(int32_t) * (d + 1));
+  memcpy(coord, v, sizeof(double) * d);
+  *tmap_slot(&V, sigma, 1, &cr) = 0;
+  nv = 1;
+  for (int64_t head = 0; head < nv; ++head) {
+    int32_t sig[64], eta[64], key[64];
+    memcpy(sig, sig_out + head * (d + 1), sizeof(int32_t) * (d + 1));
+    memcpy(r, coord + head * d, sizeof(double) * d);
+    for (int o = 0; o <= d; ++o) {
+      if (sig[o] == i) continue; /* keep i in the edge */
+      int a = 0;
+      for (int b = 0; b <= d; ++b)
+        if (b != o) eta[a++] = sig[b];
+      if (search_direction(d, X, eta, sig[o], u)) continue;
+      double t;
+      int32_t j = cast(d, n, X, eta, d, r, u, 0, &t, &tmp);
+      if (j < 0) continue;
+      for (int b = 0; b < d; ++b) key[b] = eta[b];
+      key[d] = j;
+      sort_small(key, d + 1);
+      int64_t *vs = tmap_slot(&V, key, 1, &cr);
+      if (!vs || !cr) continue;
+      if (nv >= cap) {
+        nv = -1;
+        break;
+      }
+      *vs = nv;
+      memcpy(sig_out + nv * (d + 1), key, sizeof(int32_t) * (d + 1));
+      if (circumcentre(d, X, key, coord + nv * d)) {
+        nv = -1;
+        break;
+      }
+      nv++;
+    }
+    if (nv < 0) break;
+  }
+  free(coord);
+  tmap_free(&V);
+  return nv;
+}
+
 int64_t vgo_mesh_nv(const void *h) { return ((const vgo_mesh *)h)->nv; }
 int64_t vgo_mesh_nb(const void *h) { return ((const vgo_mesh *)h)->nb; }
 int64_t vgo_mesh_raycasts(const void *h) { return ((const vgo_mesh *)h)->raycasts; }

@@ -142,3 +142,12 @@ def test_search_direction_and_circumcentre(oracle_mod):
         rr = np.linalg.norm(X[eta] - p, axis=1)
         assert np.allclose(rr, rr[0], rtol=1e-12)
         assert np.linalg.norm(X[s[o]] - p) > rr[0]
+
+
+@pytest.mark.parametrize("d,n,i", [(2, 300, 7), (3, 200, 11), (4, 150, 3), (4, 150, 149)])
+def test_star_equals_vertices_of_full_search_containing_i(oracle_mod, d, n, i):
+    X = W.uniform_cloud(n, d, seed=31)
+    full = oracle_mod.explore(X, W.descent_draws(d))
+    want = full["sigma"][np.any(full["sigma"] == i, axis=1)]
+    got = oracle_mod.star(X, i, W.descent_draws(d, seed=9))
+    assert np.array_equal(oracle_mod.sorted_rows(got), oracle_mod.sorted_rows(want))
