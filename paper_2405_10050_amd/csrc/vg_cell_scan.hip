@@ -23,8 +23,10 @@
 //
 // Epilogue: per lane a running (best, second, argmax).  A 16-value block
 // whose max does not exceed the lane's second best cannot change anything
-// (fast path: one max tree and one compare); otherwise every value updates
-// the top-2 with v_med3 and the argmax with a compare/select.
+// (fast path: an integer v_max3 tree over the bit patterns and one compare;
+// best and second are never negative, and non-negative floats order like
+// their bit patterns); otherwise every value updates the top-2 with v_med3
+// and the argmax with a compare/select.
 //
 // Near-tie certificate: with |u| = 1 the FP32 value of u.r~ is within
 // (2d+4) 2^-24 |r~| of the exact one, and |r~| <= 1/nn_i (nn_i = distance to
@@ -40,29 +42,41 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ float max16(const f32x16 &v) {
-  float a = fmaxf(fmaxf(v[0], v[1]), v[2]);
-  float b = fmaxf(fmaxf(v[3], v[4]), v[5]);
-  float c = fmaxf(fmaxf(v[6], v[7]), v[8]);
-  float e = fmaxf(fmaxf(v[9], v[10]), v[11]);
-  float f = fmaxf(fmaxf(v[12], v[13]), v[14]);
-  return fmaxf(fmaxf(fmaxf(a, b), c), fmaxf(fmaxf(e, f), v[15]));
+__device__ __forceinline__ int imax3(int a, int b, int c) { return max(max(a, b), c); }
+// Maximum of the 16 values' bit patterns as signed integers: for a maximum
+// >= +0 it is the bit pattern of the float maximum; otherwise it is negative.
+__device__ __forceinline__ int max16_bits(const f32x16 &v) {
+  int b[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) b[i] = __float_as_int(v[i]);
+  const int m1 = imax3(b[0], b[1], b[2]), m2 = imax3(b[3], b[4], b[5]);
+  const int m3 = imax3(b[6], b[7], b[8]), m4 = imax3(b[9], b[10], b[11]);
+  const int m5 = imax3(b[12], b[13], b[14]);
+  return max(imax3(m1, m2, m3), imax3(m4, m5, b[15]));
 }
 
 // Top-2 update of one lane with the 16 accumulator values of a 32x32 block.
+// The argmax is kept encoded as (32-row block << 4) | register (decoded by
+// decode_row), so the update needs no per-row index arithmetic.
 __device__ __forceinline__ void epilogue16(const f32x16 &acc, float &best, float &second,
-                                           int &bidx, int rowbase) {
-  if (max16(acc) > second) {
+                                           int &bidx, int blk16) {
+  if (max16_bits(acc) > __float_as_int(second)) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const float s = acc[i];
       second = __builtin_amdgcn_fmed3f(s, best, second);
       if (s > best) {
         best = s;
-        bidx = rowbase + 8 * (i >> 2) + (i & 3);
+        bidx = blk16 | i;
       }
     }
   }
+}
+
+// Node row of an encoded argmax held by `lane` (MFMA output layout above).
+__device__ __forceinline__ int decode_row(int e, int lane) {
+  if (e < 0) return e;
+  return (e >> 4) * 32 + 8 * ((e & 15) >> 2) + (e & 3) + 4 * (lane >> 5);
 }
 
 // Coordinates of node r (zero beyond n or d).
@@ -139,6 +153,7 @@ __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (
   // merge the two lanes that hold each ray (rows split by l/32)
 #pragma unroll
   for (int cb = 0; cb < C; ++cb) {
+    bidx[cb] = decode_row(bidx[cb], lane);
     const float ob = __shfl_xor(best[cb], 32);
     const float os = __shfl_xor(second[cb], 32);
     const int oi = __shfl_xor(bidx[cb], 32);
@@ -216,14 +231,36 @@ __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (
   }
 }
 
+// LDS tile of the FP32 scan: row k holds coordinate k of the chunk's NB
+// inverted nodes; rows are NB + 32 floats apart so that the two K halves of
+// an MFMA operand (lanes 0-31 and 32-63) fall in different bank halves.
+template <int KP, int WAVES>
+struct Fp32Tile {
+  static constexpr int NB = WAVES * 64;
+  static constexpr int LS = NB + 32;
+  static constexpr int FLOATS = 2 * KP * LS;
+};
+
+// Accumulators of one column block of a 32-node block.
+template <int KP>
+__device__ __forceinline__ f32x16 scan_block(const float (&A)[KP], const float (&ub)[KP]) {
+  f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kp = 0; kp < KP; ++kp) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[kp], ub[kp], acc, 0, 0, 0);
+  return acc;
+}
+
 // One work item of the FP32 scan: rays [chunk*RW, chunk*RW + RW) of `cell`.
-// lds holds KP * WAVES*64 float2, red WAVES*64 floats.
+// lds holds Fp32Tile<KP, WAVES>::FLOATS floats, red WAVES*64 floats.  One
+// accumulator set per wave is reused by the column blocks in turn: separate
+// sets would cost the occupancy that hides each block's epilogue.
 template <int KP, int C, int WAVES>
 __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t cell, int chunk,
-                                               float2 *__restrict__ lds, float *red) {
+                                               float *__restrict__ lds, float *red) {
   constexpr int NT = WAVES * 64;
-  constexpr int NB = NT;             // nodes per LDS chunk (one per thread)
-  constexpr int RW = WAVES * C * 32; // rays per workgroup
+  constexpr int NB = Fp32Tile<KP, WAVES>::NB;  // nodes per LDS chunk (one per thread)
+  constexpr int LS = Fp32Tile<KP, WAVES>::LS;
+  constexpr int RW = WAVES * C * 32;           // rays per workgroup
   constexpr int DK = 2 * KP;
 
   const int tid = threadIdx.x;
@@ -261,6 +298,9 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   }
   float nn2 = __builtin_inff();
 
+  // A operand: lane l reads row 2kp + l/32, column l%32 of each node block
+  const float *lrow = lds + (lane >> 5) * LS + (lane & 31);
+
   // the coordinates of the next chunk's node are loaded one chunk ahead, so
   // their latency hides behind the MFMA loop of the current chunk
   float pre[DK];
@@ -271,26 +311,20 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
     load_node<DK>(a.nodes, n, d, base + NB + tid, pre);
     __syncthreads();  // the previous chunk is consumed
 #pragma unroll
-    for (int kp = 0; kp < KP; ++kp) lds[kp * NB + tid] = make_float2(rt[2 * kp], rt[2 * kp + 1]);
+    for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
     __syncthreads();
     const int64_t rem = n - base;
     const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
+    const int blk0 = (int)(base >> 5);
     for (int nb = 0; nb < nblocks; ++nb) {
       float A[KP];
 #pragma unroll
-      for (int kp = 0; kp < KP; ++kp) {
-        const float2 v = lds[kp * NB + nb * 32 + (lane & 31)];
-        A[kp] = (lane & 32) ? v.y : v.x;
-      }
-      const int rowbase = (int)(base + nb * 32) + 4 * (lane >> 5);
+      for (int kp = 0; kp < KP; ++kp) A[kp] = lrow[2 * kp * LS + nb * 32];
+      const int blk16 = (blk0 + nb) << 4;
 #pragma unroll
       for (int cb = 0; cb < C; ++cb) {
-        f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                      0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kp = 0; kp < KP; ++kp)
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[kp], ub[cb][kp], acc, 0, 0, 0);
-        epilogue16(acc, best[cb], second[cb], bidx[cb], rowbase);
+        const f32x16 acc = scan_block<KP>(A, ub[cb]);
+        epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
       }
     }
   }
@@ -300,7 +334,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 
 template <int KP, int C, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs a) {
-  __shared__ float2 lds[KP * WAVES * 64];
+  __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS];
   __shared__ float red[WAVES * 64];
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
@@ -415,7 +449,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
       bf16x8 A[KQ];
 #pragma unroll
       for (int q = 0; q < KQ; ++q) A[q] = lds[(nb * 32 + (lane & 31)) * (KT / 8) + 2 * q + (lane >> 5)];
-      const int rowbase = (int)(base + nb * 32) + 4 * (lane >> 5);
+      const int blk16 = (int)((base >> 5) + nb) << 4;
 #pragma unroll
       for (int cb = 0; cb < C; ++cb) {
         f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
@@ -423,7 +457,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
 #pragma unroll
         for (int q = 0; q < KQ; ++q)
           acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[q], ub[cb][q], acc, 0, 0, 0);
-        epilogue16(acc, best[cb], second[cb], bidx[cb], rowbase);
+        epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
       }
     }
   }
@@ -449,7 +483,7 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_batched_kernel(const Bat
                                                                       int np, int64_t total,
                                                                       unsigned long long *next) {
   constexpr int NT = WAVES * 64;
-  constexpr size_t FP32_LDS = 8 * NT * sizeof(float2);
+  constexpr size_t FP32_LDS = Fp32Tile<8, WAVES>::FLOATS * sizeof(float);
   constexpr size_t BF16_LDS = NT * (Bf16Pack<3>::KT / 8) * sizeof(bf16x8);
   __shared__ __align__(16) unsigned char raw[BF16 ? BF16_LDS : FP32_LDS];
   __shared__ float red[NT];
@@ -481,7 +515,7 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_batched_kernel(const Bat
       else
         scan_bf16x3_item<3, C, WAVES>(a, cell, chunk, l, red);
     } else {
-      float2 *l = reinterpret_cast<float2 *>(raw);
+      float *l = reinterpret_cast<float *>(raw);
       switch ((a.d + 1) >> 1) {
         case 1: scan_fp32_item<1, C, WAVES>(a, cell, chunk, l, red); break;
         case 2: scan_fp32_item<2, C, WAVES>(a, cell, chunk, l, red); break;
