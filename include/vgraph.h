@@ -161,6 +161,36 @@ int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
                    float *grad_nodes);
 
 /* ------------------------------------------------------ uneven batches */
+/* One independent RayCast problem of vg_raycast_batched: the arguments of
+ * vg_raycast (same layouts and meanings; status_out may be NULL, excl may be
+ * NULL when n_excl == 0). */
+typedef struct vg_rays_problem {
+  int d;                /* 2..VG_MAX_DIM                                */
+  int n_excl;           /* 0..d                                         */
+  int64_t n_nodes;      /* >= 1                                         */
+  const float *nodes;   /* [n_nodes][d]                                 */
+  int64_t n_rays;       /* >= 0                                         */
+  const float *origin;  /* [n_rays][d]                                  */
+  const float *dir;     /* [n_rays][d]                                  */
+  const int32_t *gen;   /* [n_rays]                                     */
+  const int32_t *excl;  /* [n_rays][n_excl], rows sorted ascending      */
+  float *t_out;         /* [n_rays]                                     */
+  int32_t *idx_out;     /* [n_rays]                                     */
+  uint8_t *status_out;  /* [n_rays] or NULL                             */
+} vg_rays_problem;
+
+/* vg_raycast (Sec. 2.2, eq. (t); the half-space restriction of Algorithm 1)
+ * over many independent problems of different d, node set and ray count in
+ * one persistent scan launch: workgroups take (problem, 256-ray tile) items
+ * from a device counter, largest problems first; then one FP64 re-evaluation
+ * pass over the flagged rays of every problem.  Each ray's result equals
+ * what vg_raycast returns for it.  flags: VG_CLIP (applies to every problem);
+ * VG_NO_RECHECK is not supported here (VG_EUNSUPPORTED).  The table `probs`
+ * is a HOST array read during the call only; the launches are captured into
+ * a hipGraph per distinct table and replayed when the same table recurs. */
+int vg_raycast_batched(vg_ctx *ctx, int n_problems, const vg_rays_problem *probs,
+                       uint32_t flags);
+
 /* One independent point cloud of an uneven batch of Monte-Carlo raycasts. */
 typedef struct vg_cells_problem {
   int d;                /* 2..VG_MAX_DIM                                */

@@ -13,6 +13,7 @@ Calls (names follow the paper's statement of the problem):
   raycast_cells(nodes, dirs)                           Monte-Carlo rays of every cell
   mc_volume_area(nodes, dirs)                          Sec. 3.1 / Algorithm 3 estimators
   mc_backward(...), VoronoiMC                          adjoint / autograd Function
+  raycast_batched(problems, clip)                      many RayCast problems, one launch
   raycast_cells_batched(problems)                      uneven batch of clouds
   explore(nodes, descent_draws)                        Algorithm 2 (VoronoiGraph)
 """
@@ -57,10 +58,19 @@ class _CellsProblem(ctypes.Structure):
                 ("idx_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p)]
 
 
+class _RaysProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n_excl", ctypes.c_int), ("n_nodes", ctypes.c_int64),
+                ("nodes", ctypes.c_void_p), ("n_rays", ctypes.c_int64), ("origin", ctypes.c_void_p),
+                ("dir", ctypes.c_void_p), ("gen", ctypes.c_void_p), ("excl", ctypes.c_void_p),
+                ("t_out", ctypes.c_void_p), ("idx_out", ctypes.c_void_p),
+                ("status_out", ctypes.c_void_p)]
+
+
 EXPORTS = (
     "vg_create", "vg_destroy", "vg_set_stream", "vg_last_error", "vg_get_stats",
     "vg_set_profiling", "vg_raycast",
     "vg_raycast_cells", "vg_mc_volume_area", "vg_mc_backward", "vg_raycast_cells_batched",
+    "vg_raycast_batched",
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
     "vg_mesh_copy", "vg_mesh_free",
 )
@@ -85,6 +95,7 @@ def _load_lib():
     lib.vg_mc_volume_area.argtypes = [P, I, I64, P, I, P, U32, P, P, P, P, P, P, P, P]
     lib.vg_mc_backward.argtypes = [P, I, I64, P, I, P, P, P, P, P, P, P, P, P]
     lib.vg_raycast_cells_batched.argtypes = [P, I, ctypes.POINTER(_CellsProblem), U32]
+    lib.vg_raycast_batched.argtypes = [P, I, ctypes.POINTER(_RaysProblem), U32]
     lib.vg_explore.argtypes = [P, I, I64, P, P, I, U32, ctypes.POINTER(P)]
     for f in ("vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts"):
         getattr(lib, f).argtypes = [P]
@@ -340,6 +351,58 @@ def raycast_cells_batched(problems, precision="fp32", out=None):
     c = _ctx(dev)
     _check(_lib.vg_raycast_cells_batched(c, len(problems), probs, _cells_flags(precision, True)),
            c, "vg_raycast_cells_batched")
+    return outs
+
+
+def raycast_batched(problems, clip=True, out=None):
+    """Many independent RayCast problems in one persistent (graph-captured)
+    launch plus one FP64 recheck.  ``problems`` is a list of tuples
+    ``(nodes [N, d], origin [M, d], direction [M, d], gen [M], excl [M, n_excl]
+    or None)``, each as in :func:`raycast` (problems may differ in d, N, M and
+    n_excl).  Returns a list of ``(t, idx, status)`` of length M; ``out`` may
+    pass a previous result of the same batch to reuse its buffers (a repeated
+    call on the same buffers replays the captured graph)."""
+    probs = (_RaysProblem * len(problems))()
+    outs = []
+    dev = None
+    for q, pr in enumerate(problems):
+        nodes, origin, direction, gen = pr[:4]
+        excl = pr[4] if len(pr) > 4 else None
+        _dev(nodes, torch.float32, "nodes")
+        dev = nodes.device if dev is None else dev
+        if nodes.device != dev:
+            raise ValueError("all problems must be on one device")
+        n, d = nodes.shape
+        _dev(origin, torch.float32, "origin", dev)
+        _dev(direction, torch.float32, "direction", dev)
+        _dev(gen, torch.int32, "gen", dev)
+        m = origin.shape[0]
+        if origin.shape != (m, d) or direction.shape != (m, d) or gen.shape != (m,):
+            raise ValueError("origin/direction must be [M, d] and gen [M]")
+        ne = 0
+        if excl is not None:
+            _dev(excl, torch.int32, "excl", dev)
+            if excl.dim() != 2 or excl.shape[0] != m:
+                raise ValueError("excl must be [M, n_excl]")
+            ne = excl.shape[1]
+        if out is not None:
+            t, idx, st = out[q]
+            if t.shape != (m,) or idx.shape != (m,) or st.shape != (m,):
+                raise ValueError("out does not match the batch")
+        else:
+            t = torch.empty(m, dtype=torch.float32, device=dev)
+            idx = torch.empty(m, dtype=torch.int32, device=dev)
+            st = torch.empty(m, dtype=torch.uint8, device=dev)
+        outs.append((t, idx, st))
+        probs[q] = _RaysProblem(d, ne, n, nodes.data_ptr(), m, origin.data_ptr(),
+                                direction.data_ptr(), gen.data_ptr(),
+                                excl.data_ptr() if excl is not None else None,
+                                t.data_ptr(), idx.data_ptr(), st.data_ptr())
+    if not problems:
+        return outs
+    c = _ctx(dev)
+    _check(_lib.vg_raycast_batched(c, len(problems), probs, VG_CLIP if clip else 0), c,
+           "vg_raycast_batched")
     return outs
 
 

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <string>
@@ -199,6 +200,100 @@ int persistent_grid(vg_ctx *ctx, int shape, bool bf16) {
   return S.cus * batched_blocks_per_cu(shape, bf16);
 }
 
+// Device buffers of one batch: problem table, FP64 recheck queue, counters
+// (CNT_WORDS u32, then the u64 item counter at byte 32), status scratch.
+struct BatchBuffers {
+  void *table;
+  int64_t *flags;
+  uint32_t *counters;
+  uint8_t *status;
+};
+
+// Runs the launches of one batch.  The first call with a given key allocates
+// the buffers, fills and uploads the table, and captures the launches into a
+// hipGraph on a private capture stream; later calls with the same key replay
+// that graph on the context's stream (at most 8 graphs are kept, least
+// recently used first out).  With VG_NO_GRAPH set, the launches run directly
+// and the buffers are freed after a stream synchronisation.
+int run_batch(vg_ctx *ctx, uint64_t key, int64_t rays, bool need_status, size_t table_bytes,
+              const std::function<void(const BatchBuffers &, std::vector<char> &)> &fill,
+              const std::function<hipError_t(const BatchBuffers &, hipStream_t)> &enqueue,
+              float tau) {
+  BatchState &S = state(ctx);
+  const bool use_graph = std::getenv("VG_NO_GRAPH") == nullptr;
+  GraphEntry *g = nullptr;
+  for (auto &e : S.graphs)
+    if (e.key == key && e.exec) g = &e;
+  if (!g || !use_graph) {
+    GraphEntry ne;
+    ne.key = key;
+    ne.rays = rays;
+    if (hipMalloc(&ne.flags, (size_t)std::max<int64_t>(rays, 1) * 8) != hipSuccess ||
+        hipMalloc(&ne.counters, 64) != hipSuccess ||
+        (need_status && hipMalloc(&ne.status, (size_t)std::max<int64_t>(rays, 1)) != hipSuccess) ||
+        hipMalloc(&ne.table, table_bytes) != hipSuccess) {
+      free_entry(ne);
+      return err(ctx, VG_ENOMEM, "batch buffers allocation failed");
+    }
+    const BatchBuffers b{ne.table, static_cast<int64_t *>(ne.flags), static_cast<uint32_t *>(ne.counters),
+                         static_cast<uint8_t *>(ne.status)};
+    std::vector<char> bytes;
+    fill(b, bytes);
+    if (bytes.size() != table_bytes ||
+        hipMemcpy(ne.table, bytes.data(), table_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      free_entry(ne);
+      return err(ctx, VG_EDEVICE, "batch table upload failed");
+    }
+    if (!use_graph) {
+      hipError_t e = enqueue(b, ctx->stream);
+      // keep the buffers alive until the work is done, then drop them
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      if (e == hipSuccess) {
+        uint32_t c[CNT_WORDS];
+        e = hipMemcpy(c, ne.counters, sizeof c, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) (void)hipMemcpy(ctx->counters, c, sizeof c, hipMemcpyHostToDevice);
+      }
+      free_entry(ne);
+      ctx->last_rays = rays;
+      ctx->last_tau = tau;
+      ctx->last_counters = ctx->counters;
+      if (e != hipSuccess) return err(ctx, VG_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+      return VG_OK;
+    }
+    if (!S.capture && hipStreamCreateWithFlags(&S.capture, hipStreamNonBlocking) != hipSuccess) {
+      free_entry(ne);
+      return err(ctx, VG_EDEVICE, "capture stream creation failed");
+    }
+    hipError_t e = hipStreamBeginCapture(S.capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = enqueue(b, S.capture);
+      e = hipStreamEndCapture(S.capture, &ne.graph);
+      if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ne.exec, ne.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      free_entry(ne);
+      return err(ctx, VG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    if (S.graphs.size() >= 8) {
+      auto lru = std::min_element(S.graphs.begin(), S.graphs.end(),
+                                  [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
+      (void)hipStreamSynchronize(ctx->stream);
+      free_entry(*lru);
+      S.graphs.erase(lru);
+    }
+    S.graphs.push_back(ne);
+    g = &S.graphs.back();
+  }
+  g->last_use = ++S.clock;
+  hipError_t e = hipGraphLaunch(g->exec, ctx->stream);
+  if (e != hipSuccess) return err(ctx, VG_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  ctx->last_rays = g->rays;
+  ctx->last_tau = tau;
+  ctx->last_counters = static_cast<uint32_t *>(g->counters);
+  return VG_OK;
+}
+
 // Time every shape on a probe of each bucket missing from the cache.
 int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16) {
   BatchState &S = state(ctx);
@@ -335,7 +430,6 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
 
-  BatchState &S = state(ctx);
   int shape = 0;
   if (const char *e = std::getenv("VG_BATCH_SHAPE")) {
     shape = std::max(0, std::min(kNumBatchShapes - 1, std::atoi(e)));
@@ -347,8 +441,6 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
       if (shape < 0) return VG_EDEVICE;
     }
   }
-  const bool use_graph = std::getenv("VG_NO_GRAPH") == nullptr;
-
   // key: everything the launches depend on
   int64_t items0, rays0;
   std::vector<BatchProblem> probe =
@@ -356,93 +448,145 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
   uint64_t key = fnv(probe.data(), probe.size() * sizeof(BatchProblem));
   key = fnv(&shape, sizeof shape, key);
   key = fnv(&flags, sizeof flags, key);
-
-  GraphEntry *g = nullptr;
-  for (auto &e : S.graphs)
-    if (e.key == key && e.exec) g = &e;
-  if (!g || !use_graph) {
-    GraphEntry ne;
-    ne.key = key;
-    ne.rays = rays0;
-    bool need_status = false;
-    for (auto &p : pr) need_status |= p.status_out == nullptr;
-    if (hipMalloc(&ne.flags, (size_t)rays0 * 8) != hipSuccess ||
-        hipMalloc(&ne.counters, 64) != hipSuccess ||
-        (need_status && hipMalloc(&ne.status, (size_t)rays0) != hipSuccess) ||
-        hipMalloc(&ne.table, probe.size() * sizeof(BatchProblem)) != hipSuccess) {
-      free_entry(ne);
-      return err(ctx, VG_ENOMEM, "batch buffers allocation failed");
-    }
+  bool need_status = false;
+  for (auto &p : pr) need_status |= p.status_out == nullptr;
+  const int grid = persistent_grid(ctx, shape, bf16);
+  auto fill = [&](const BatchBuffers &b, std::vector<char> &bytes) {
     int64_t items, rays;
-    std::vector<BatchProblem> T = make_table(pr, order, shape, bf16, (uint32_t *)ne.counters,
-                                             (int64_t *)ne.flags, (uint8_t *)ne.status, items, rays);
-    if (hipMemcpy(ne.table, T.data(), T.size() * sizeof(BatchProblem), hipMemcpyHostToDevice) !=
-        hipSuccess) {
-      free_entry(ne);
-      return err(ctx, VG_EDEVICE, "batch table upload failed");
+    std::vector<BatchProblem> T =
+        make_table(pr, order, shape, bf16, b.counters, b.flags, b.status, items, rays);
+    bytes.assign(reinterpret_cast<const char *>(T.data()),
+                 reinterpret_cast<const char *>(T.data() + T.size()));
+  };
+  auto enqueue = [&](const BatchBuffers &b, hipStream_t s) -> hipError_t {
+    const int rgrid = (int)std::min<int64_t>((rays0 + 3) / 4, 2048);
+    unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)b.counters + 32);
+    hipError_t e = fill_u32(b.counters, 0u, 16, s);
+    if (e == hipSuccess)
+      e = launch_cell_scan_batched((const BatchProblem *)b.table, n_problems, items0, next, shape,
+                                   bf16, grid, s);
+    if (e == hipSuccess)
+      e = launch_recheck_batched((const BatchProblem *)b.table, b.counters, b.flags,
+                                 b.counters + CNT_FP64_TIE, std::max(rgrid, 1), s);
+    return e;
+  };
+  return run_batch(ctx, key, rays0, need_status, probe.size() * sizeof(BatchProblem), fill, enqueue,
+                   bf16 ? kTauCellsBf16 : kTauCellsFp32);
+}
+
+
+// Problems with rays, largest first (n_rays * n_nodes * d), as a device
+// table; items are 256-ray tiles.
+static std::vector<RayBatchProblem> make_rays_table(const std::vector<vg_rays_problem> &pr,
+                                                    const std::vector<int> &order, int clip,
+                                                    uint32_t *counters, int64_t *flags,
+                                                    uint8_t *status, int64_t &total_items,
+                                                    int64_t &total_rays) {
+  std::vector<RayBatchProblem> T(order.size());
+  total_items = 0;
+  total_rays = 0;
+  int64_t status_off = 0;
+  for (size_t q = 0; q < order.size(); ++q) {
+    const vg_rays_problem &p = pr[order[q]];
+    RayScanArgs &a = T[q].a;
+    a = RayScanArgs{};
+    a.nodes = p.nodes;
+    a.n = p.n_nodes;
+    a.d = p.d;
+    a.m = p.n_rays;
+    a.o32 = p.origin;
+    a.u32 = p.dir;
+    a.gen = p.gen;
+    a.excl = p.n_excl > 0 ? p.excl : nullptr;
+    a.n_excl = p.n_excl;
+    a.clip = clip;
+    a.t_out = p.t_out;
+    a.idx_out = p.idx_out;
+    if (p.status_out) {
+      a.st_out = p.status_out;
+    } else {
+      a.st_out = status ? status + status_off : nullptr;
+      status_off += p.n_rays;
     }
-    const int grid = persistent_grid(ctx, shape, bf16);
-    const int rgrid = (int)std::min<int64_t>((rays + 3) / 4, 2048);
-    unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)ne.counters + 32);
-    auto enqueue = [&](hipStream_t s) -> hipError_t {
-      hipError_t e = fill_u32((uint32_t *)ne.counters, 0u, 16, s);
-      if (e == hipSuccess)
-        e = launch_cell_scan_batched((const BatchProblem *)ne.table, n_problems, items, next, shape,
-                                     bf16, grid, s);
-      if (e == hipSuccess)
-        e = launch_recheck_batched((const BatchProblem *)ne.table, (const uint32_t *)ne.counters,
-                                   (const int64_t *)ne.flags,
-                                   (uint32_t *)ne.counters + CNT_FP64_TIE, std::max(rgrid, 1), s);
-      return e;
-    };
-    if (!use_graph) {
-      hipError_t e = enqueue(ctx->stream);
-      // keep the buffers alive until the work is done, then drop them
-      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-      if (e == hipSuccess) {
-        uint32_t c[CNT_WORDS];
-        e = hipMemcpy(c, ne.counters, sizeof c, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) {
-          (void)hipMemcpy(ctx->counters, c, sizeof c, hipMemcpyHostToDevice);
-        }
-      }
-      free_entry(ne);
-      ctx->last_rays = rays;
-      ctx->last_tau = bf16 ? kTauCellsBf16 : kTauCellsFp32;
-      if (e != hipSuccess) return err(ctx, VG_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
-      return VG_OK;
-    }
-    if (!S.capture && hipStreamCreateWithFlags(&S.capture, hipStreamNonBlocking) != hipSuccess) {
-      free_entry(ne);
-      return err(ctx, VG_EDEVICE, "capture stream creation failed");
-    }
-    hipError_t e = hipStreamBeginCapture(S.capture, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      hipError_t e2 = enqueue(S.capture);
-      e = hipStreamEndCapture(S.capture, &ne.graph);
-      if (e2 != hipSuccess) e = e2;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&ne.exec, ne.graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      free_entry(ne);
-      return err(ctx, VG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    }
-    // keep at most 8 graphs: evict the least recently used
-    if (S.graphs.size() >= 8) {
-      auto lru = std::min_element(S.graphs.begin(), S.graphs.end(),
-                                  [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
-      (void)hipStreamSynchronize(ctx->stream);
-      free_entry(*lru);
-      S.graphs.erase(lru);
-    }
-    S.graphs.push_back(ne);
-    g = &S.graphs.back();
+    a.counters = counters;
+    a.flag_list = flags;
+    a.tau = kTauRays;
+    a.flag_tag = (int64_t)q << 40;
+    T[q].item_begin = total_items;
+    total_items += (p.n_rays + kRayTile - 1) / kRayTile;
+    total_rays += p.n_rays;
   }
-  g->last_use = ++S.clock;
-  hipError_t e = hipGraphLaunch(g->exec, ctx->stream);
-  if (e != hipSuccess) return err(ctx, VG_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
-  ctx->last_rays = g->rays;
-  ctx->last_tau = bf16 ? kTauCellsBf16 : kTauCellsFp32;
-  ctx->last_counters = static_cast<uint32_t *>(g->counters);
-  return VG_OK;
+  return T;
+}
+
+extern "C" int vg_raycast_batched(vg_ctx *ctx, int n_problems, const vg_rays_problem *probs,
+                                  uint32_t flags) {
+  if (!ctx) return VG_EINVAL;
+  ctx->err.clear();
+  if (n_problems < 0 || (n_problems > 0 && !probs)) return err(ctx, VG_EINVAL, "bad problem table");
+  if (n_problems >= (1 << 22)) return err(ctx, VG_EINVAL, "too many problems");
+  if (flags & VG_NO_RECHECK) return err(ctx, VG_EUNSUPPORTED, "batched calls always recheck");
+  if (flags & VG_PREC_BF16X3) return err(ctx, VG_EUNSUPPORTED, "general rays scan in FP32 only");
+  std::vector<vg_rays_problem> pr(probs, probs + n_problems);
+  std::vector<int> order;
+  for (int i = 0; i < n_problems; ++i) {
+    const vg_rays_problem &p = pr[i];
+    if (p.d < 2 || p.d > VG_MAX_DIM) return err(ctx, VG_EUNSUPPORTED, "problem d outside [2, 16]");
+    if (p.n_nodes < 1 || p.n_nodes >= (int64_t(1) << 31))
+      return err(ctx, VG_EINVAL, "problem n_nodes outside [1, 2^31)");
+    if (!p.nodes) return err(ctx, VG_EINVAL, "null problem nodes");
+    if (p.n_rays < 0 || p.n_rays >= (int64_t(1) << 40))
+      return err(ctx, VG_EINVAL, "problem n_rays outside [0, 2^40)");
+    if (p.n_excl < 0 || p.n_excl > p.d) return err(ctx, VG_EINVAL, "problem n_excl outside [0, d]");
+    if (p.n_rays == 0) continue;
+    if (!p.origin || !p.dir || !p.gen || !p.t_out || !p.idx_out)
+      return err(ctx, VG_EINVAL, "null problem ray array");
+    if (p.n_excl > 0 && !p.excl) return err(ctx, VG_EINVAL, "problem excl is NULL with n_excl > 0");
+    order.push_back(i);
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return err(ctx, VG_EDEVICE, "hipSetDevice failed");
+  if (order.empty()) {
+    ctx->last_rays = 0;
+    return VG_OK;
+  }
+  auto cost = [&](int i) { return (double)pr[i].n_rays * (double)pr[i].n_nodes * pr[i].d; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  const int clip = (flags & VG_CLIP) ? 1 : 0;
+  const int np = (int)order.size();
+
+  int64_t items0, rays0;
+  std::vector<RayBatchProblem> probe =
+      make_rays_table(pr, order, clip, nullptr, nullptr, nullptr, items0, rays0);
+  static const char tag[] = "general rays";
+  uint64_t key = fnv(tag, sizeof tag);
+  key = fnv(probe.data(), probe.size() * sizeof(RayBatchProblem), key);
+  key = fnv(&flags, sizeof flags, key);
+  bool need_status = false;
+  for (int i : order) need_status |= pr[i].status_out == nullptr;
+  BatchState &S = state(ctx);
+  if (!S.cus) {
+    hipDeviceProp_t prop;
+    S.cus = (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ? prop.multiProcessorCount : 256;
+  }
+  const int grid = (int)std::min<int64_t>(items0, (int64_t)S.cus * ray_scan_batched_blocks_per_cu());
+  auto fill = [&](const BatchBuffers &b, std::vector<char> &bytes) {
+    int64_t items, rays;
+    std::vector<RayBatchProblem> T =
+        make_rays_table(pr, order, clip, b.counters, b.flags, b.status, items, rays);
+    bytes.assign(reinterpret_cast<const char *>(T.data()),
+                 reinterpret_cast<const char *>(T.data() + T.size()));
+  };
+  auto enqueue = [&](const BatchBuffers &b, hipStream_t s) -> hipError_t {
+    const int rgrid = (int)std::min<int64_t>((rays0 + 3) / 4, 2048);
+    unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)b.counters + 32);
+    hipError_t e = fill_u32(b.counters, 0u, 16, s);
+    if (e == hipSuccess)
+      e = launch_ray_scan_batched((const RayBatchProblem *)b.table, np, items0, next, grid, s);
+    if (e == hipSuccess)
+      e = launch_recheck_rays_batched((const RayBatchProblem *)b.table, b.counters, b.flags,
+                                      b.counters + CNT_FP64_TIE, std::max(rgrid, 1), s);
+    return e;
+  };
+  return run_batch(ctx, key, rays0, need_status, probe.size() * sizeof(RayBatchProblem), fill,
+                   enqueue, kTauRays);
 }

@@ -41,7 +41,15 @@ struct RayScanArgs {
   uint32_t *counters;
   int64_t *flag_list;
   float tau;
-  int force_all;  // queue every ray for the FP64 recheck
+  int force_all;     // queue every ray for the FP64 recheck
+  int64_t flag_tag;  // ORed into queued ray ids (batched mode: problem << 40)
+};
+
+// One problem of a persistent batch of general rays: its scan arguments and
+// the first global item (256-ray tile) of its rays.
+struct RayBatchProblem {
+  RayScanArgs a;
+  int64_t item_begin;
 };
 
 struct CellScanArgs {
@@ -135,6 +143,13 @@ struct BackwardArgs {
 hipError_t launch_cell_scan_fp32(const CellScanArgs &a, hipStream_t s);
 hipError_t launch_cell_scan_bf16x3(const CellScanArgs &a, hipStream_t s);
 hipError_t launch_ray_scan(const RayScanArgs &a, hipStream_t s);
+constexpr int kRayTile = 256;  // rays per workgroup (and per batched item) of the ray scan
+hipError_t launch_ray_scan_batched(const RayBatchProblem *probs_dev, int np, int64_t total,
+                                   unsigned long long *next, int grid, hipStream_t s);
+int ray_scan_batched_blocks_per_cu();
+hipError_t launch_recheck_rays_batched(const RayBatchProblem *probs_dev, const uint32_t *counters,
+                                       const int64_t *flag_list, uint32_t *tie_counter, int grid,
+                                       hipStream_t s);
 hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s);
 hipError_t launch_accum(const AccumArgs &a, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);

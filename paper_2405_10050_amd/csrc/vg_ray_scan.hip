@@ -27,13 +27,14 @@
 namespace vg {
 namespace {
 
-constexpr int TILE = 256;
+constexpr int TILE = kRayTile;
 
+// Rays [blk*TILE, blk*TILE + TILE) of one problem; sx holds TILE*DK floats.
+// Every thread of the workgroup must call it (it contains barriers).
 template <int DK>
-__global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
-  __shared__ float sx[TILE * DK];
+__device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk, float *sx) {
   const int tid = threadIdx.x;
-  const int64_t ray = (int64_t)blockIdx.x * TILE + tid;
+  const int64_t ray = blk * TILE + tid;
   const int d = a.d;
   const int64_t n = a.n;
   int32_t gidx = ray < a.m ? a.gen[ray] : 0;
@@ -224,11 +225,51 @@ __global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
   if (flag && a.flag_list) {
     st |= VG_ST_NEAR_TIE;
     const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
-    a.flag_list[pos] = ray;
+    a.flag_list[pos] = ray | a.flag_tag;
   }
   a.t_out[ray] = t;
   a.idx_out[ray] = j;
   a.st_out[ray] = st;
+}
+
+template <int DK>
+__global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
+  __shared__ float sx[TILE * DK];
+  ray_scan_tile<DK>(a, blockIdx.x, sx);
+}
+
+// Uneven batches of problems: workgroups take (problem, ray tile) items from
+// a device counter in the order of the item table until it passes the end.
+__global__ __launch_bounds__(TILE) void ray_scan_batched_kernel(const RayBatchProblem *probs, int np,
+                                                                int64_t total,
+                                                                unsigned long long *next) {
+  __shared__ float sx[TILE * VG_MAX_DIM];
+  __shared__ long long item_s;
+  for (;;) {
+    __syncthreads();  // the previous item is finished
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(next, 1ull);
+    __syncthreads();
+    const long long item = item_s;
+    if (item >= total) break;
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (probs[mid].item_begin <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const RayScanArgs a = probs[lo].a;
+    const int64_t blk = item - probs[lo].item_begin;
+    if (a.d <= 4)
+      ray_scan_tile<4>(a, blk, sx);
+    else if (a.d <= 8)
+      ray_scan_tile<8>(a, blk, sx);
+    else if (a.d <= 12)
+      ray_scan_tile<12>(a, blk, sx);
+    else
+      ray_scan_tile<16>(a, blk, sx);
+  }
 }
 
 }  // namespace
@@ -247,6 +288,19 @@ hipError_t launch_ray_scan(const RayScanArgs &a, hipStream_t s) {
   else
     hipLaunchKernelGGL(ray_scan_kernel<16>, grid, blk, 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_ray_scan_batched(const RayBatchProblem *probs_dev, int np, int64_t total,
+                                   unsigned long long *next, int grid, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ray_scan_batched_kernel, dim3(grid), dim3(TILE), 0, s, probs_dev, np, total, next);
+  return hipGetLastError();
+}
+
+int ray_scan_batched_blocks_per_cu() {
+  int nb = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ray_scan_batched_kernel, TILE, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 }  // namespace vg

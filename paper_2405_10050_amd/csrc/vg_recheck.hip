@@ -264,6 +264,114 @@ __global__ __launch_bounds__(NT) void recheck_batched_kernel(const BatchProblem 
   }
 }
 
+
+// Batched general rays: a queue entry is (problem << 40 | ray); each wave
+// takes one entry and evaluates every node of that problem in FP64 with the
+// same expressions, filter and clip rule as recheck_kernel (loops unrolled
+// over VG_MAX_DIM with a k < d guard, so the order of the sums is the same).
+__global__ __launch_bounds__(NT) void recheck_rays_batched_kernel(const RayBatchProblem *probs,
+                                                                  const uint32_t *counters,
+                                                                  const int64_t *flag_list,
+                                                                  uint32_t *tie_counter) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t cnt = counters[CNT_FLAGGED];
+  const uint32_t nw = gridDim.x * WAVES;
+  for (uint32_t f = blockIdx.x * WAVES + (threadIdx.x >> 6); f < cnt; f += nw) {
+    const int64_t code = flag_list[f];
+    const int p = (int)(code >> 40);
+    const int64_t ray = code & ((int64_t(1) << 40) - 1);
+    const RayScanArgs &a = probs[p].a;
+    const int d = a.d;
+    const int n_excl = a.n_excl;
+    const int32_t gi = a.gen[ray];  // in range: rays with a bad generator are never queued
+    double x[VG_MAX_DIM], u[VG_MAX_DIM], g[VG_MAX_DIM];
+    int32_t ex[VG_MAX_DIM];
+#pragma unroll
+    for (int k = 0; k < VG_MAX_DIM; ++k) {
+      x[k] = k < d ? (double)a.o32[ray * d + k] : 0.0;
+      u[k] = k < d ? (double)a.u32[ray * d + k] : 0.0;
+      g[k] = k < d ? (double)a.nodes[(int64_t)gi * d + k] : 0.0;
+      ex[k] = k < n_excl ? a.excl[ray * n_excl + k] : -1;
+    }
+    Top2 tp{__builtin_inf(), __builtin_inf(), -1};
+    for (int64_t r = lane; r < a.n; r += 64) {
+      bool skip = false;
+#pragma unroll
+      for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
+      if (skip) continue;
+      const float *xr = a.nodes + r * d;
+      double den = 0.0;
+#pragma unroll
+      for (int k = 0; k < VG_MAX_DIM; ++k)
+        if (k < d) den += u[k] * ((double)xr[k] - g[k]);
+      if (!(den > 0.0)) continue;
+      double num = 0.0;
+#pragma unroll
+      for (int k = 0; k < VG_MAX_DIM; ++k)
+        if (k < d) num += ((double)xr[k] - g[k]) * (((double)xr[k] - x[k]) + (g[k] - x[k]));
+      if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) continue;
+      const double t = num / (2.0 * den);
+      if (t < tp.t1) {
+        tp.t2 = tp.t1;
+        tp.t1 = t;
+        tp.i1 = (int32_t)r;
+      } else if (t < tp.t2) {
+        tp.t2 = t;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      Top2 o;
+      o.t1 = __shfl_xor(tp.t1, off);
+      o.t2 = __shfl_xor(tp.t2, off);
+      o.i1 = __shfl_xor(tp.i1, off);
+      tp = merge(tp, o);
+    }
+    if (lane == 0) {
+      double t1 = tp.t1, t2 = tp.t2;
+      int32_t i1 = tp.i1;
+      if (a.clip) {
+        double tb = __builtin_inf();
+        int face = -1;
+        for (int k = 0; k < d; ++k) {
+          double tk;
+          int fc;
+          if (u[k] > 0.0) {
+            tk = (1.0 - x[k]) / u[k];
+            fc = 2 * k + 1;
+          } else if (u[k] < 0.0) {
+            tk = (0.0 - x[k]) / u[k];
+            fc = 2 * k;
+          } else {
+            continue;
+          }
+          if (tk < tb) {
+            tb = tk;
+            face = fc;
+          }
+        }
+        if (face >= 0) {
+          if (tb < t1) {
+            t2 = t1;
+            t1 = tb;
+            i1 = -2 - face;
+          } else if (tb < t2) {
+            t2 = tb;
+          }
+        }
+      }
+      uint8_t st = (uint8_t)((a.st_out[ray] & ~VG_ST_NO_HIT) | VG_ST_RECHECKED);
+      if (i1 == -1) st |= VG_ST_NO_HIT;
+      if (t2 - t1 <= 1e-9 * fabs(t1)) {
+        st |= VG_ST_FP64_TIE;
+        atomicAdd(tie_counter, 1u);
+      }
+      a.t_out[ray] = (float)t1;
+      a.idx_out[ray] = i1;
+      a.st_out[ray] = st;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t *counters,
@@ -279,6 +387,15 @@ hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
   if (max_grid <= 0) return hipSuccess;
   const int grid = (max_grid + WAVES - 1) / WAVES;
   hipLaunchKernelGGL(recheck_kernel, dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_recheck_rays_batched(const RayBatchProblem *probs_dev, const uint32_t *counters,
+                                       const int64_t *flag_list, uint32_t *tie_counter, int grid,
+                                       hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(recheck_rays_batched_kernel, dim3(grid), dim3(NT), 0, s, probs_dev, counters,
+                     flag_list, tie_counter);
   return hipGetLastError();
 }
 
