@@ -144,6 +144,41 @@ int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
                       float *volume, float *energy2, int32_t *facet_j,
                       float *facet_area, int32_t *facet_count);
 
+/* vg_mc_volume_area with each cell's candidate scan restricted to a list of
+ * its neighbours: once the Voronoi diagram is known, a ray of cell i can only
+ * leave through a facet shared with a neighbouring cell (the remark closing
+ * Sec. 3.1), so t* over the list equals t* over all nodes whenever the list
+ * of every cell holds all generators whose cells share a facet with it (a
+ * superset is fine; vg_tuple_neighbors builds it from vg_explore's vertices).
+ * Rays the FP32 certificate cannot settle are re-evaluated over ALL nodes in
+ * FP64, as in vg_mc_volume_area.  Same flags and outputs.
+ *   nbr_offsets [n_nodes+1] i64, nondecreasing, nbr_offsets[0] = 0;
+ *   nbr [nbr_offsets[n_nodes]] i32: row i lists cell i's candidates (any
+ *   order, without i).  Entries outside [0, n_nodes) are ignored; a missing
+ *   neighbour gives wrong t* for the rays that leave through its facet. */
+int vg_mc_volume_area_nbr(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                          const int64_t *nbr_offsets, const int32_t *nbr,
+                          int rays_per_cell, const float *dirs, uint32_t flags,
+                          float *t_out, int32_t *idx_out, uint8_t *status_out,
+                          float *volume, float *energy2, int32_t *facet_j,
+                          float *facet_area, int32_t *facet_count);
+
+/* Generator adjacency of a set of Voronoi vertices (Sec. 2.1: a vertex is
+ * equidistant to its d+1 generators), as CSR: j is listed in row i when some
+ * tuple holds both i and j.  For the vertex set of vg_explore these are the
+ * neighbouring cells of each generator.
+ *   sigma [n_tuples][d+1] i32 (DEVICE; entries in [0, n_nodes), else
+ *         VG_EINVAL);
+ *   offsets [n_nodes+1] i64 and nbr [nbr_capacity] i32 (DEVICE outputs, both
+ *         NULL to count only); rows sorted ascending, no duplicates;
+ *   *nnz (HOST) receives the number of entries; nbr_capacity < *nnz is
+ *         VG_EINVAL (n_tuples*(d+1)*d always suffices).
+ * At most 2^31 - 1 ordered tuple pairs (VG_EUNSUPPORTED beyond).  Allocates
+ * temporary device memory and synchronises the stream. */
+int vg_tuple_neighbors(vg_ctx *ctx, int d, int64_t n_nodes, int64_t n_tuples,
+                       const int32_t *sigma, int64_t *offsets, int32_t *nbr,
+                       int64_t nbr_capacity, int64_t *nnz);
+
 /* Adjoint of vg_mc_volume_area with the directions frozen: writes
  *   grad_nodes[n_nodes][d] = d/dX ( sum_i g_volume[i] volume[i]
  *        + g_energy2[i] energy2[i] + sum_{i,f} g_facet_area[i][f] area(i,f) )

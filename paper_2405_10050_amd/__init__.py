@@ -11,7 +11,8 @@ raises ``VGError``.
 Calls (names follow the paper's statement of the problem):
   raycast(nodes, origin, direction, gen, excl, clip)   RayCast of Sec. 2.2
   raycast_cells(nodes, dirs)                           Monte-Carlo rays of every cell
-  mc_volume_area(nodes, dirs)                          Sec. 3.1 / Algorithm 3 estimators
+  mc_volume_area(nodes, dirs, neighbors=None)          Sec. 3.1 / Algorithm 3 estimators
+  tuple_neighbors(sigma, n)                            cell adjacency from vertex tuples
   mc_backward(...), VoronoiMC                          adjoint / autograd Function
   raycast_batched(problems, clip)                      many RayCast problems, one launch
   raycast_cells_batched(problems)                      uneven batch of clouds
@@ -70,7 +71,7 @@ EXPORTS = (
     "vg_create", "vg_destroy", "vg_set_stream", "vg_last_error", "vg_get_stats",
     "vg_set_profiling", "vg_raycast",
     "vg_raycast_cells", "vg_mc_volume_area", "vg_mc_backward", "vg_raycast_cells_batched",
-    "vg_raycast_batched",
+    "vg_raycast_batched", "vg_mc_volume_area_nbr", "vg_tuple_neighbors",
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
     "vg_mesh_copy", "vg_mesh_free",
 )
@@ -96,6 +97,8 @@ def _load_lib():
     lib.vg_mc_backward.argtypes = [P, I, I64, P, I, P, P, P, P, P, P, P, P, P]
     lib.vg_raycast_cells_batched.argtypes = [P, I, ctypes.POINTER(_CellsProblem), U32]
     lib.vg_raycast_batched.argtypes = [P, I, ctypes.POINTER(_RaysProblem), U32]
+    lib.vg_mc_volume_area_nbr.argtypes = [P, I, I64, P, P, P, I, P, U32, P, P, P, P, P, P, P, P]
+    lib.vg_tuple_neighbors.argtypes = [P, I, I64, I64, P, P, P, I64, ctypes.POINTER(I64)]
     lib.vg_explore.argtypes = [P, I, I64, P, P, I, U32, ctypes.POINTER(P)]
     for f in ("vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts"):
         getattr(lib, f).argtypes = [P]
@@ -237,10 +240,13 @@ class MCResult:
         return i, self.facet_j.cpu().numpy()[mask], self.facet_area.cpu().numpy()[mask]
 
 
-def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out=None) -> MCResult:
+def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out=None,
+                   neighbors=None) -> MCResult:
     """Monte-Carlo cell volumes, second moments and interface areas
     (Sec. 3.1, Algorithm 3 with f = 1).  ``out`` may pass a previous
-    ``MCResult`` of the same shape to reuse its buffers."""
+    ``MCResult`` of the same shape to reuse its buffers.  ``neighbors`` =
+    ``(offsets [N+1] int64, nbr [nnz] int32)`` (e.g. from
+    :func:`tuple_neighbors`) restricts each cell's scan to its neighbours."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
     n, d = nodes.shape
@@ -259,11 +265,43 @@ def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out
             idx=torch.empty((n, R), dtype=torch.int32, device=dev),
             status=torch.empty((n, R), dtype=torch.uint8, device=dev))
     c = _ctx(dev)
-    _check(_lib.vg_mc_volume_area(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck),
-                                  _ptr(out.t), _ptr(out.idx), _ptr(out.status), _ptr(out.volume),
-                                  _ptr(out.energy2), _ptr(out.facet_j), _ptr(out.facet_area),
-                                  _ptr(out.facet_count)), c, "vg_mc_volume_area")
+    if neighbors is None:
+        _check(_lib.vg_mc_volume_area(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck),
+                                      _ptr(out.t), _ptr(out.idx), _ptr(out.status), _ptr(out.volume),
+                                      _ptr(out.energy2), _ptr(out.facet_j), _ptr(out.facet_area),
+                                      _ptr(out.facet_count)), c, "vg_mc_volume_area")
+        return out
+    off, nbr = neighbors
+    _dev(off, torch.int64, "neighbor offsets", dev)
+    _dev(nbr, torch.int32, "neighbor list", dev)
+    if off.shape != (n + 1,) or nbr.dim() != 1:
+        raise ValueError("neighbors must be (offsets [N+1], nbr [nnz])")
+    _check(_lib.vg_mc_volume_area_nbr(c, d, n, _ptr(nodes), _ptr(off), _ptr(nbr), R, _ptr(dirs),
+                                      _cells_flags(precision, recheck), _ptr(out.t), _ptr(out.idx),
+                                      _ptr(out.status), _ptr(out.volume), _ptr(out.energy2),
+                                      _ptr(out.facet_j), _ptr(out.facet_area), _ptr(out.facet_count)),
+           c, "vg_mc_volume_area_nbr")
     return out
+
+
+def tuple_neighbors(sigma, n_nodes):
+    """Cell adjacency from Voronoi vertex tuples: ``sigma`` is a device int32
+    tensor ``[V, d+1]`` (e.g. ``explore(...)["sigma"]`` moved to the GPU).
+    Returns device tensors ``(offsets [n_nodes+1] int64, nbr [nnz] int32)``;
+    row i lists, ascending, every generator that shares a vertex with i."""
+    _dev(sigma, torch.int32, "sigma")
+    if sigma.dim() != 2:
+        raise ValueError("sigma must be [V, d+1]")
+    dev = sigma.device
+    V, L = sigma.shape
+    off = torch.empty(n_nodes + 1, dtype=torch.int64, device=dev)
+    cap = max(V * L * (L - 1), 1)
+    nbr = torch.empty(cap, dtype=torch.int32, device=dev)
+    nnz = ctypes.c_int64(0)
+    c = _ctx(dev)
+    _check(_lib.vg_tuple_neighbors(c, L - 1, n_nodes, V, _ptr(sigma), _ptr(off), _ptr(nbr), cap,
+                                   ctypes.byref(nnz)), c, "vg_tuple_neighbors")
+    return off, nbr[:nnz.value].clone()
 
 
 def mc_backward(nodes, dirs, res: MCResult, g_volume=None, g_energy2=None, g_facet_area=None):

@@ -107,7 +107,8 @@ struct ScanTimer {
 double sphere_area(int d) { return 2.0 * std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d); }
 
 int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const float *dirs,
-              uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *st_out) {
+              uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *st_out,
+              const int64_t *nbr_off = nullptr, const int32_t *nbr = nullptr) {
   const int64_t m = n * (int64_t)R;
   const bool recheck = !(flags & VG_NO_RECHECK);
   const bool bf16 = (flags & VG_PREC_BF16X3) != 0;
@@ -133,6 +134,8 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   a.flag_list = flag_list;
   a.tau_rel = bf16 ? kTauCellsBf16 : kTauCellsFp32;
   a.kappa = cell_kappa(d, bf16);
+  a.nbr_off = nbr_off;
+  a.nbr = nbr;
   ScanTimer timer(ctx);
   hipError_t e = bf16 ? launch_cell_scan_bf16x3(a, ctx->stream) : launch_cell_scan_fp32(a, ctx->stream);
   timer.stop();
@@ -385,10 +388,14 @@ int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, in
   return run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, flags, t_out, idx_out, status_out);
 }
 
-int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
-                      const float *dirs, uint32_t flags, float *t_out, int32_t *idx_out,
-                      uint8_t *status_out, float *volume, float *energy2, int32_t *facet_j,
-                      float *facet_area, int32_t *facet_count) {
+}  // extern "C"
+
+namespace {
+
+int mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const int64_t *nbr_off,
+                   const int32_t *nbr, int rays_per_cell, const float *dirs, uint32_t flags,
+                   float *t_out, int32_t *idx_out, uint8_t *status_out, float *volume,
+                   float *energy2, int32_t *facet_j, float *facet_area, int32_t *facet_count) {
   int rc = check_common(ctx, d, n_nodes, nodes);
   if (rc) return rc;
   if (rays_per_cell < 1 || rays_per_cell > 4096)
@@ -396,7 +403,8 @@ int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, i
   if (!dirs || !t_out || !idx_out || !volume) return fail(ctx, VG_EINVAL, "null array");
   const int nf = (facet_j != nullptr) + (facet_area != nullptr) + (facet_count != nullptr);
   if (nf != 0 && nf != 3) return fail(ctx, VG_EINVAL, "facet outputs must be all set or all NULL");
-  rc = run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, flags, t_out, idx_out, status_out);
+  rc = run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, flags, t_out, idx_out, status_out,
+                 nbr_off, nbr);
   if (rc) return rc;
   const double S = sphere_area(d);
   AccumArgs a{};
@@ -417,6 +425,43 @@ int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, i
   hipError_t e = launch_accum(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "accumulate launch");
   return VG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                      const float *dirs, uint32_t flags, float *t_out, int32_t *idx_out,
+                      uint8_t *status_out, float *volume, float *energy2, int32_t *facet_j,
+                      float *facet_area, int32_t *facet_count) {
+  return mc_volume_area(ctx, d, n_nodes, nodes, nullptr, nullptr, rays_per_cell, dirs, flags, t_out,
+                        idx_out, status_out, volume, energy2, facet_j, facet_area, facet_count);
+}
+
+int vg_mc_volume_area_nbr(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                          const int64_t *nbr_offsets, const int32_t *nbr, int rays_per_cell,
+                          const float *dirs, uint32_t flags, float *t_out, int32_t *idx_out,
+                          uint8_t *status_out, float *volume, float *energy2, int32_t *facet_j,
+                          float *facet_area, int32_t *facet_count) {
+  if (!ctx) return VG_EINVAL;
+  if (!nbr_offsets || !nbr) return fail(ctx, VG_EINVAL, "nbr_offsets and nbr are required");
+  return mc_volume_area(ctx, d, n_nodes, nodes, nbr_offsets, nbr, rays_per_cell, dirs, flags, t_out,
+                        idx_out, status_out, volume, energy2, facet_j, facet_area, facet_count);
+}
+
+int vg_tuple_neighbors(vg_ctx *ctx, int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sigma,
+                       int64_t *offsets, int32_t *nbr, int64_t nbr_capacity, int64_t *nnz) {
+  if (!ctx) return VG_EINVAL;
+  ctx->err.clear();
+  if (d < 2 || d > VG_MAX_DIM) return fail(ctx, VG_EUNSUPPORTED, "d=%d outside [2, %d]", d, VG_MAX_DIM);
+  if (n_nodes < 1 || n_nodes >= (int64_t(1) << 31))
+    return fail(ctx, VG_EINVAL, "n_nodes=%lld outside [1, 2^31)", (long long)n_nodes);
+  if (n_tuples < 0 || (n_tuples > 0 && !sigma)) return fail(ctx, VG_EINVAL, "bad tuple array");
+  if (!nnz) return fail(ctx, VG_EINVAL, "nnz is NULL");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VG_EDEVICE, "hipSetDevice failed");
+  return tuple_neighbors(d, n_nodes, n_tuples, sigma, offsets, nbr, nbr_capacity, nnz, ctx->stream,
+                         ctx->err);
 }
 
 int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,

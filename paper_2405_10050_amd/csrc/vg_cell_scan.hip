@@ -112,6 +112,18 @@ __device__ __forceinline__ float invert_node(const float (&xr)[DK], const float 
   return n2;
 }
 
+// Node scanned as row r of `cell`: the row itself, or the r-th entry of the
+// cell's candidate list.  Rows past the end and entries outside [0, n) give
+// n, which load_node and invert_node treat as padding (a zero row never wins:
+// the eligibility threshold is u.r~ > 0).
+__device__ __forceinline__ int64_t row_node(const CellScanArgs &a, int64_t nb0, int64_t n_scan,
+                                            int64_t r) {
+  if (!a.nbr) return r;
+  if (r >= n_scan) return a.n;
+  const int32_t j = a.nbr[nb0 + r];
+  return (j >= 0 && j < a.n) ? j : a.n;
+}
+
 // Re-evaluate t for MC ray (origin x_i) hitting node x_j.
 template <int DK>
 __device__ float reeval_cell(const float (&xi)[DK], const float *__restrict__ xj,
@@ -137,7 +149,7 @@ template <int C, int DK, int NT>
 __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (&xi)[DK],
                                             float (&best)[C], float (&second)[C], int (&bidx)[C],
                                             float nn2, float *red, int lane, int rayw,
-                                            int64_t cell) {
+                                            int64_t cell, int64_t nb0, int64_t n_scan) {
   const int d = a.d;
   const int R = a.R;
   // nearest-neighbour distance of x_i (for the error certificate)
@@ -206,13 +218,15 @@ __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (
     const float thr = fmaxf(a.tau_rel * s1, a.kappa / nn);
     bool tie = !(s1 - s2 > thr);
     float t;
-    if (j >= a.n) {  // cannot happen with the documented MFMA layout; never dereference
+    const int64_t node = (j >= 0 && j < n_scan) ? row_node(a, nb0, n_scan, j) : a.n;
+    if (j >= 0 && node >= a.n) {  // cannot happen with the documented MFMA layout; never dereference
       j = -1;
       t = __builtin_nanf("");
       st |= VG_ST_SUSPECT;
       tie = true;
     } else if (j >= 0) {
-      t = reeval_cell<DK>(xi, a.nodes + (int64_t)j * d, u, d);
+      j = (int)node;
+      t = reeval_cell<DK>(xi, a.nodes + node * d, u, d);
     } else if (j <= -2) {
       t = tbox;
     } else {
@@ -303,17 +317,19 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 
   // the coordinates of the next chunk's node are loaded one chunk ahead, so
   // their latency hides behind the MFMA loop of the current chunk
+  const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
+  const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
   float pre[DK];
-  load_node<DK>(a.nodes, n, d, tid, pre);
-  for (int64_t base = 0; base < n; base += NB) {
+  load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, tid), pre);
+  for (int64_t base = 0; base < n_scan; base += NB) {
     float rt[DK];
-    nn2 = fminf(nn2, invert_node<DK>(pre, xi, base + tid, n, cell, rt));
-    load_node<DK>(a.nodes, n, d, base + NB + tid, pre);
+    nn2 = fminf(nn2, invert_node<DK>(pre, xi, row_node(a, nb0, n_scan, base + tid), n, cell, rt));
+    load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, base + NB + tid), pre);
     __syncthreads();  // the previous chunk is consumed
 #pragma unroll
     for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
     __syncthreads();
-    const int64_t rem = n - base;
+    const int64_t rem = n_scan - base;
     const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
     const int blk0 = (int)(base >> 5);
     for (int nb = 0; nb < nblocks; ++nb) {
@@ -329,7 +345,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
     }
   }
 
-  cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell);
+  cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
 }
 
 template <int KP, int C, int WAVES>
@@ -419,13 +435,15 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
   }
   float nn2 = __builtin_inff();
 
+  const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
+  const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
   float pre[DK];
-  load_node<DK>(a.nodes, n, d, tid, pre);
-  for (int64_t base = 0; base < n; base += NB) {
+  load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, tid), pre);
+  for (int64_t base = 0; base < n_scan; base += NB) {
     {
       float rt[DK];
-      nn2 = fminf(nn2, invert_node<DK>(pre, xi, base + tid, n, cell, rt));
-      load_node<DK>(a.nodes, n, d, base + NB + tid, pre);
+      nn2 = fminf(nn2, invert_node<DK>(pre, xi, row_node(a, nb0, n_scan, base + tid), n, cell, rt));
+      load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, base + NB + tid), pre);
       __syncthreads();  // the previous chunk is consumed
       __bf16 rh[DKP], rl[DKP];
 #pragma unroll
@@ -443,7 +461,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
       }
     }
     __syncthreads();
-    const int64_t rem = n - base;
+    const int64_t rem = n_scan - base;
     const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
     for (int nb = 0; nb < nblocks; ++nb) {
       bf16x8 A[KQ];
@@ -461,7 +479,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
       }
     }
   }
-  cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell);
+  cell_finish<C, DK, NT>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
 }
 
 template <int KQ, int C, int WAVES>

@@ -67,6 +67,10 @@ struct CellScanArgs {
   float tau_rel;      // relative gap floor
   float kappa;        // absolute FP32 error bound coefficient (times 1/nn-distance)
   int64_t flag_tag;   // ORed into queued ray ids (batched mode: problem << 40)
+  // optional candidate lists (CSR): cell i scans only nodes nbr[nbr_off[i] ..
+  // nbr_off[i+1]); null scans every node
+  const int64_t *nbr_off;
+  const int32_t *nbr;
 };
 
 // One cloud of a persistent batch: its scan arguments and the first global
@@ -142,6 +146,12 @@ struct BackwardArgs {
 // Launchers (return a hipError_t of the launch).
 hipError_t launch_cell_scan_fp32(const CellScanArgs &a, hipStream_t s);
 hipError_t launch_cell_scan_bf16x3(const CellScanArgs &a, hipStream_t s);
+// Directed generator adjacency (CSR) of a set of vertex tuples; synchronises
+// the stream.  Defined in vg_nbr.hip.
+int tuple_neighbors(int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sigma,
+                    int64_t *offsets, int32_t *nbr, int64_t nbr_capacity, int64_t *nnz_out,
+                    hipStream_t s, std::string &err);
+
 hipError_t launch_ray_scan(const RayScanArgs &a, hipStream_t s);
 constexpr int kRayTile = 256;  // rays per workgroup (and per batched item) of the ray scan
 hipError_t launch_ray_scan_batched(const RayBatchProblem *probs_dev, int np, int64_t total,
