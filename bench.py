@@ -132,8 +132,8 @@ def bench_uneven(args):
         "value": rays / (ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "uneven64: 64 uniform clouds, 256 MC rays per cell, one persistent "
-                               "hipGraph-captured launch + FP64 recheck",
+        "config": {"workload": "uneven64: 64 uniform clouds, 256 MC rays per cell, one graph of "
+                               "persistent launches (one per register class) + FP64 recheck",
                    "clouds": len(spec), "cells": sum(nc for _, nc, _ in spec), "rays": rays,
                    "flagged_rays_per_step": st["flagged"],
                    "separate_launches_ms": ms_sep, "speedup_vs_separate": ms_sep / ms},
@@ -175,6 +175,62 @@ def bench_grad(args):
     }
 
 
+def bench_nbr(args):
+    """Neighbour-restricted Monte-Carlo after the exhaustive search (the
+    remark closing Sec. 3.1): uniform d=4 N=50 000 (or d=6 N=10 000), 512 rays
+    per cell.  The search and the adjacency build are timed once; a step is
+    the estimators over each cell's neighbour list plus the adjoint of the
+    centroidal energy.  The same step over all nodes is timed beside it."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    d, n = (4, 50_000) if args.workload == "nbr_d4_n50000" else (6, 10_000)
+    R = 512
+    dev = torch.device("cuda", 0)
+    X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).to(dev)
+    D = torch.from_numpy(directions_threaded(np.arange(n), R, d, seed=1)).to(dev)
+    t0 = time.perf_counter()
+    mesh = vg.explore(X, W.descent_draws(d))
+    t_explore = time.perf_counter() - t0
+    print(f"[bench] explore: {mesh['sigma'].shape[0]} vertices in {t_explore:.1f} s", file=sys.stderr,
+          flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nb = vg.tuple_neighbors(torch.from_numpy(mesh["sigma"]).to(dev), n)
+    torch.cuda.synchronize()
+    t_nbr = time.perf_counter() - t0
+    stream = torch.cuda.current_stream(dev)
+    ones = torch.ones(n, device=dev)
+    res = vg.mc_volume_area(X, D, neighbors=nb)
+    full = vg.mc_volume_area(X, D)
+    step = lambda: (vg.mc_volume_area(X, D, neighbors=nb, out=res),  # noqa: E731
+                    vg.mc_backward(X, D, res, None, ones, None))
+    step_full = lambda: (vg.mc_volume_area(X, D, out=full),  # noqa: E731
+                         vg.mc_backward(X, D, full, None, ones, None))
+    for _ in range(args.warmup):
+        step()
+    ms = _timed(stream, step, args.steps)
+    st = vg.stats()
+    ms_full = _timed(stream, step_full, 1)
+    agree = float((res.idx == full.idx).float().mean().item())
+    nnz = int(nb[1].numel())
+    return {
+        "metric": f"MC volume+grad cells/s over neighbour lists (d={d}, N={n}, 512 rays/cell)",
+        "value": n / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"uniform d={d} N={n}, 512 MC rays per cell, scan over each cell's "
+                               "neighbours from the exhaustive search, loss = sum of second moments",
+                   "explore_s": t_explore, "vertices": int(mesh["sigma"].shape[0]),
+                   "neighbors_s": t_nbr, "neighbor_entries": nnz, "neighbors_per_cell": nnz / n,
+                   "rays": n * R, "flagged_rays_per_step": st["flagged"],
+                   "full_scan_ms_per_step": ms_full, "speedup_vs_full_scan": ms_full / ms,
+                   "argmin_agreement_with_full_scan": agree},
+    }
+
+
 def bench_explore(args):
     """Exhaustive vertex search (Algorithm 2) of a uniform cloud."""
     import torch
@@ -209,7 +265,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--workload", default="gmm8_d10_n100000",
                     choices=["gmm8_d10_n100000", "uneven64", "uniform_d4_n50000",
-                             "uniform_d2_n1000", "uniform_d6_n10000"])
+                             "uniform_d2_n1000", "uniform_d6_n10000", "nbr_d4_n50000",
+                             "nbr_d6_n10000"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -222,8 +279,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
-              "over cells with no exchange, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Monte-Carlo "
+              "path shards over cells with no exchange, and this build measures one GPU's share",
+              file=sys.stderr)
         sys.exit(1)
 
     import torch
@@ -233,7 +291,8 @@ def main():
 
     if args.workload != "gmm8_d10_n100000":
         other = {"uneven64": bench_uneven, "uniform_d4_n50000": bench_grad,
-                 "uniform_d2_n1000": bench_explore, "uniform_d6_n10000": bench_explore}
+                 "uniform_d2_n1000": bench_explore, "uniform_d6_n10000": bench_explore,
+                 "nbr_d4_n50000": bench_nbr, "nbr_d6_n10000": bench_nbr}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 

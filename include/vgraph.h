@@ -238,10 +238,18 @@ typedef struct vg_cells_problem {
   uint8_t *status_out;  /* [n_nodes * rays_per_cell] or NULL            */
 } vg_cells_problem;
 
-/* vg_raycast_cells over many clouds of different d and N in one persistent
- * launch: workgroups take (cloud, cell) items from a device queue ordered by
- * decreasing cost.  The problem table is copied to the device (host array
- * `probs`, read during the call only). */
+/* vg_raycast_cells (the Monte-Carlo rays of Algorithm 3) over many clouds of
+ * different d, N and rays_per_cell: one persistent launch per register class
+ * of d (d <= 4, <= 8, <= 12, <= 16; BF16x3: <= 5, <= 10, <= 16) in which
+ * workgroups take (cloud, cell, ray chunk) items from a device counter,
+ * largest clouds first; then one FP64 recheck of the flagged rays of every
+ * cloud.  Each ray's result equals what vg_raycast_cells returns for it.
+ * flags: VG_PREC_BF16X3; VG_NO_RECHECK is VG_EUNSUPPORTED.  The problem table
+ * is a HOST array read during the call only; the launches are captured into
+ * a hipGraph per distinct table and replayed when the same table recurs.
+ * With every status_out set, a tuner picks the tile shape per (d, N) bucket
+ * on first sight (timings cached in $VG_TUNE_CACHE, default
+ * $HOME/.cache/vgraph_tune.txt). */
 int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems,
                              const vg_cells_problem *probs, uint32_t flags);
 

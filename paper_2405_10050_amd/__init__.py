@@ -357,7 +357,8 @@ class VoronoiMC(torch.autograd.Function):
 
 
 def raycast_cells_batched(problems, precision="fp32", out=None):
-    """Uneven batch in one persistent (graph-captured) launch: ``problems`` is
+    """Uneven batch in persistent launches (one per register class of d,
+    captured into one graph): ``problems`` is
     a list of ``(nodes [N_c, d_c], dirs [N_c, R_c, d_c])``.  Returns a list of
     ``(t, idx, status)`` shaped ``[N_c, R_c]``; ``out`` may pass a previous
     result of the same batch to reuse its buffers (a repeated call on the same

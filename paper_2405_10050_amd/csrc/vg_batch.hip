@@ -1,14 +1,18 @@
-// Uneven batches of Monte-Carlo RayCasts in one persistent launch.
+// Uneven batches of RayCast problems in persistent launches.
 //
-// vg_raycast_cells_batched orders the clouds by decreasing cost
-// (N^2 R ceil(d/2): pairs times MFMA K-steps), lays their (cell, ray-chunk)
-// items out in that order, and runs one persistent scan kernel that takes
-// items from a device counter, then one batched FP64 recheck.  The three
-// launches (counter fill, scan, recheck) are captured once into a hipGraph per
-// distinct problem table and replayed on later calls with the same table.
+// vg_raycast_cells_batched groups the clouds by register class of their K
+// extent (one persistent kernel per class keeps the occupancy of the small
+// extents), orders them by decreasing cost within a class (N^2 R ceil(d/2):
+// pairs times MFMA K-steps), lays their (cell, ray-chunk) items out in that
+// order, and runs per class one persistent scan kernel that takes items from
+// a device counter; then one batched FP64 recheck.  vg_raycast_batched does
+// the same for general rays (one persistent kernel over 256-ray tiles of all
+// problems).  The launches (counter fill, scans, recheck) are captured once
+// into a hipGraph per distinct problem table and replayed on later calls with
+// the same table.
 //
-// Tile shape: the persistent kernel exists in a few shapes (rays per item,
-// waves per workgroup).  A tuner times every shape on a probe of each
+// Tile shape: the persistent cell kernels exist in a few shapes (rays per
+// item, waves per workgroup).  A tuner times every shape on a probe of each
 // (K-steps, log2 N, rays-per-cell, precision) bucket present in a batch --
 // the first items of that bucket's clouds -- records nanoseconds per
 // ray-node pair, and picks the shape with the smallest predicted batch time.
@@ -191,17 +195,18 @@ BatchState &state(vg_ctx *ctx) {
   return *static_cast<BatchState *>(ctx->batch_state);
 }
 
-int persistent_grid(vg_ctx *ctx, int shape, bool bf16) {
+int persistent_grid(vg_ctx *ctx, int shape, bool bf16, int cls) {
   BatchState &S = state(ctx);
   if (!S.cus) {
     hipDeviceProp_t prop;
     S.cus = (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ? prop.multiProcessorCount : 256;
   }
-  return S.cus * batched_blocks_per_cu(shape, bf16);
+  return S.cus * batched_blocks_per_cu(shape, bf16, cls);
 }
 
 // Device buffers of one batch: problem table, FP64 recheck queue, counters
-// (CNT_WORDS u32, then the u64 item counter at byte 32), status scratch.
+// (CNT_WORDS u32, then from byte 32 one u64 item counter per launch, at most
+// four), status scratch.
 struct BatchBuffers {
   void *table;
   int64_t *flags;
@@ -351,14 +356,15 @@ int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16) {
         rc = err(ctx, VG_EDEVICE, "tuner upload failed");
         break;
       }
-      const int grid = persistent_grid(ctx, sh, bf16);
+      const int cls = batched_class(pr[big].d, bf16);
+      const int grid = persistent_grid(ctx, sh, bf16, cls);
       unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)counters + 32);
       // warm-up, then timed run of the probe
-      if (launch_cell_scan_batched((const BatchProblem *)tab, 1, std::min<int64_t>(probe_items, grid),
-                                   next, sh, bf16, grid, ctx->stream) != hipSuccess ||
+      if (launch_cell_scan_batched((const BatchProblem *)tab, 1, 0, std::min<int64_t>(probe_items, grid),
+                                   next, sh, bf16, cls, grid, ctx->stream) != hipSuccess ||
           fill_u32((uint32_t *)counters, 0u, 16, ctx->stream) != hipSuccess ||
           hipEventRecord(e0, ctx->stream) != hipSuccess ||
-          launch_cell_scan_batched((const BatchProblem *)tab, 1, probe_items, next, sh, bf16, grid,
+          launch_cell_scan_batched((const BatchProblem *)tab, 1, 0, probe_items, next, sh, bf16, cls, grid,
                                    ctx->stream) != hipSuccess ||
           hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
         rc = err(ctx, VG_EDEVICE, "tuner probe launch failed");
@@ -422,13 +428,16 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
     if (p.n_nodes * (int64_t)p.rays_per_cell >= (int64_t(1) << 40))
       return err(ctx, VG_EINVAL, "problem too large");
   }
-  // largest clouds first
+  // grouped by register class, largest clouds first within a class
   std::vector<int> order(n_problems);
   std::iota(order.begin(), order.end(), 0);
   auto cost = [&](int i) {
     return (double)pr[i].n_nodes * pr[i].n_nodes * pr[i].rays_per_cell * ((pr[i].d + 1) / 2);
   };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ca = batched_class(pr[a].d, bf16), cb = batched_class(pr[b].d, bf16);
+    return ca != cb ? ca < cb : cost(a) > cost(b);
+  });
 
   int shape = 0;
   if (const char *e = std::getenv("VG_BATCH_SHAPE")) {
@@ -450,7 +459,16 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
   key = fnv(&flags, sizeof flags, key);
   bool need_status = false;
   for (auto &p : pr) need_status |= p.status_out == nullptr;
-  const int grid = persistent_grid(ctx, shape, bf16);
+  // item range of each register class (the table is grouped by class)
+  int64_t cls_first[kNumBatchClasses], cls_last[kNumBatchClasses];
+  for (int c = 0; c < kNumBatchClasses; ++c) cls_first[c] = cls_last[c] = 0;
+  for (size_t q = 0; q < probe.size(); ++q) {
+    const int c = batched_class(probe[q].a.d, bf16);
+    const int64_t b0 = probe[q].item_begin;
+    const int64_t b1 = q + 1 < probe.size() ? probe[q + 1].item_begin : items0;
+    if (cls_last[c] == cls_first[c]) cls_first[c] = b0;
+    cls_last[c] = b1;
+  }
   auto fill = [&](const BatchBuffers &b, std::vector<char> &bytes) {
     int64_t items, rays;
     std::vector<BatchProblem> T =
@@ -462,9 +480,12 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
     const int rgrid = (int)std::min<int64_t>((rays0 + 3) / 4, 2048);
     unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)b.counters + 32);
     hipError_t e = fill_u32(b.counters, 0u, 16, s);
-    if (e == hipSuccess)
-      e = launch_cell_scan_batched((const BatchProblem *)b.table, n_problems, items0, next, shape,
-                                   bf16, grid, s);
+    for (int c = 0; c < kNumBatchClasses && e == hipSuccess; ++c) {
+      if (cls_last[c] <= cls_first[c]) continue;
+      const int grid = (int)std::min<int64_t>(cls_last[c] - cls_first[c], persistent_grid(ctx, shape, bf16, c));
+      e = launch_cell_scan_batched((const BatchProblem *)b.table, n_problems, cls_first[c], cls_last[c],
+                                   next + c, shape, bf16, c, grid, s);
+    }
     if (e == hipSuccess)
       e = launch_recheck_batched((const BatchProblem *)b.table, b.counters, b.flags,
                                  b.counters + CNT_FP64_TIE, std::max(rgrid, 1), s);

@@ -494,24 +494,42 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanAr
 // ------------------------------------------------------- persistent batches
 // Uneven batches of clouds: workgroups take (cloud, cell, ray chunk) items
 // from a device counter, in the order of the item table (largest clouds
-// first), until the counter passes the end.  Every instantiation of the
-// single-cloud item for the cloud's K extent is reachable from one kernel.
-template <int C, int WAVES, bool BF16>
-__global__ __launch_bounds__(WAVES * 64) void cell_scan_batched_kernel(const BatchProblem *probs,
-                                                                      int np, int64_t total,
+// first), until the counter passes the end of the launch's item range.  One
+// launch serves one register class of K extents (FP32: K pairs {1,2}, {3,4},
+// {5,6}, {7,8}; BF16x3: each K group alone): a kernel that inlined every
+// extent would be allocated the registers of the largest and lose occupancy
+// on the small ones.
+template <int K, int KHI, int C, int WAVES>
+__device__ __forceinline__ void dispatch_fp32(int kp, const CellScanArgs &a, int64_t cell, int chunk,
+                                              float *l, float *red) {
+  if constexpr (K < KHI) {
+    if (kp == K) {
+      scan_fp32_item<K, C, WAVES>(a, cell, chunk, l, red);
+      return;
+    }
+    dispatch_fp32<K + 1, KHI, C, WAVES>(kp, a, cell, chunk, l, red);
+  } else {
+    scan_fp32_item<K, C, WAVES>(a, cell, chunk, l, red);
+  }
+}
+
+template <int C, int WAVES, bool BF16, int KLO, int KHI>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_batched_kernel(const BatchProblem *__restrict__ probs,
+                                                                      int np, int64_t first,
+                                                                      int64_t last,
                                                                       unsigned long long *next) {
   constexpr int NT = WAVES * 64;
-  constexpr size_t FP32_LDS = Fp32Tile<8, WAVES>::FLOATS * sizeof(float);
-  constexpr size_t BF16_LDS = NT * (Bf16Pack<3>::KT / 8) * sizeof(bf16x8);
+  constexpr size_t FP32_LDS = Fp32Tile<KHI, WAVES>::FLOATS * sizeof(float);
+  constexpr size_t BF16_LDS = NT * (Bf16Pack<KHI>::KT / 8) * sizeof(bf16x8);
   __shared__ __align__(16) unsigned char raw[BF16 ? BF16_LDS : FP32_LDS];
   __shared__ float red[NT];
   __shared__ long long item_s;
   for (;;) {
     __syncthreads();  // the previous item is finished
-    if (threadIdx.x == 0) item_s = (long long)atomicAdd(next, 1ull);
+    if (threadIdx.x == 0) item_s = first + (long long)atomicAdd(next, 1ull);
     __syncthreads();
     const long long item = item_s;
-    if (item >= total) break;
+    if (item >= last) break;
     int lo = 0, hi = np - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -524,26 +542,11 @@ __global__ __launch_bounds__(WAVES * 64) void cell_scan_batched_kernel(const Bat
     const int64_t local = item - probs[lo].item_begin;
     const int64_t cell = local / a.wg_per_cell;
     const int chunk = (int)(local - cell * a.wg_per_cell);
-    if (BF16) {
-      bf16x8 *l = reinterpret_cast<bf16x8 *>(raw);
-      if (a.d <= 5)
-        scan_bf16x3_item<1, C, WAVES>(a, cell, chunk, l, red);
-      else if (a.d <= 10)
-        scan_bf16x3_item<2, C, WAVES>(a, cell, chunk, l, red);
-      else
-        scan_bf16x3_item<3, C, WAVES>(a, cell, chunk, l, red);
+    if constexpr (BF16) {
+      scan_bf16x3_item<KHI, C, WAVES>(a, cell, chunk, reinterpret_cast<bf16x8 *>(raw), red);
     } else {
-      float *l = reinterpret_cast<float *>(raw);
-      switch ((a.d + 1) >> 1) {
-        case 1: scan_fp32_item<1, C, WAVES>(a, cell, chunk, l, red); break;
-        case 2: scan_fp32_item<2, C, WAVES>(a, cell, chunk, l, red); break;
-        case 3: scan_fp32_item<3, C, WAVES>(a, cell, chunk, l, red); break;
-        case 4: scan_fp32_item<4, C, WAVES>(a, cell, chunk, l, red); break;
-        case 5: scan_fp32_item<5, C, WAVES>(a, cell, chunk, l, red); break;
-        case 6: scan_fp32_item<6, C, WAVES>(a, cell, chunk, l, red); break;
-        case 7: scan_fp32_item<7, C, WAVES>(a, cell, chunk, l, red); break;
-        default: scan_fp32_item<8, C, WAVES>(a, cell, chunk, l, red); break;
-      }
+      dispatch_fp32<KLO, KHI, C, WAVES>((a.d + 1) >> 1, a, cell, chunk, reinterpret_cast<float *>(raw),
+                                        red);
     }
   }
 }
@@ -631,46 +634,78 @@ hipError_t launch_cell_scan_bf16x3(const CellScanArgs &a0, hipStream_t s) {
 // Shapes of the persistent batched scan (rays per item = 32 * C * WAVES).
 const BatchShape kBatchShapes[kNumBatchShapes] = {{1, 8}, {2, 4}, {4, 8}};
 
-hipError_t launch_cell_scan_batched(const BatchProblem *probs_dev, int np, int64_t total,
-                                    unsigned long long *next, int shape, bool bf16, int grid,
-                                    hipStream_t s) {
-  if (total <= 0) return hipSuccess;
-#define VG_BATCH(Cc, Ww)                                                                      \
-  do {                                                                                        \
-    if (bf16)                                                                                 \
-      hipLaunchKernelGGL((cell_scan_batched_kernel<Cc, Ww, true>), dim3(grid), dim3(Ww * 64), \
-                         0, s, probs_dev, np, total, next);                                   \
-    else                                                                                      \
-      hipLaunchKernelGGL((cell_scan_batched_kernel<Cc, Ww, false>), dim3(grid),               \
-                         dim3(Ww * 64), 0, s, probs_dev, np, total, next);                    \
-  } while (0)
-  switch (shape) {
-    case 0: VG_BATCH(1, 8); break;
-    case 1: VG_BATCH(2, 4); break;
-    default: VG_BATCH(4, 8); break;
+int batched_class(int d, bool bf16) {
+  if (bf16) return d <= 5 ? 0 : (d <= 10 ? 1 : 2);
+  return (((d + 1) >> 1) - 1) >> 1;  // K pairs {1,2} -> 0, {3,4} -> 1, {5,6} -> 2, {7,8} -> 3
+}
+
+namespace {
+
+template <int C, int WAVES, bool BF16>
+hipError_t launch_class(const BatchProblem *probs, int np, int64_t first, int64_t last,
+                        unsigned long long *next, int cls, int grid, hipStream_t s) {
+  dim3 g(grid), b(WAVES * 64);
+  if constexpr (BF16) {
+    switch (cls) {
+      case 0: hipLaunchKernelGGL((cell_scan_batched_kernel<C, WAVES, true, 1, 1>), g, b, 0, s, probs, np, first, last, next); break;
+      case 1: hipLaunchKernelGGL((cell_scan_batched_kernel<C, WAVES, true, 2, 2>), g, b, 0, s, probs, np, first, last, next); break;
+      default: hipLaunchKernelGGL((cell_scan_batched_kernel<C, WAVES, true, 3, 3>), g, b, 0, s, probs, np, first, last, next); break;
+    }
+  } else {
+    switch (cls) {
+      case 0: hipLaunchKernelGGL((cell_scan_batched_kernel<C, WAVES, false, 1, 2>), g, b, 0, s, probs, np, first, last, next); break;
+      case 1: hipLaunchKernelGGL((cell_scan_batched_kernel<C, WAVES, false, 3, 4>), g, b, 0, s, probs, np, first, last, next); break;
+      case 2: hipLaunchKernelGGL((cell_scan_batched_kernel<C, WAVES, false, 5, 6>), g, b, 0, s, probs, np, first, last, next); break;
+      default: hipLaunchKernelGGL((cell_scan_batched_kernel<C, WAVES, false, 7, 8>), g, b, 0, s, probs, np, first, last, next); break;
+    }
   }
-#undef VG_BATCH
   return hipGetLastError();
 }
 
-int batched_blocks_per_cu(int shape, bool bf16) {
+template <int C, int WAVES, bool BF16>
+int class_blocks_per_cu(int cls) {
   int nb = 0;
   hipError_t e;
-  switch (shape) {
-    case 0:
-      e = bf16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<1, 8, true>, 512, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<1, 8, false>, 512, 0);
-      break;
-    case 1:
-      e = bf16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<2, 4, true>, 256, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<2, 4, false>, 256, 0);
-      break;
-    default:
-      e = bf16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<4, 8, true>, 512, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<4, 8, false>, 512, 0);
-      break;
+  constexpr int NT = WAVES * 64;
+  if constexpr (BF16) {
+    switch (cls) {
+      case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<C, WAVES, true, 1, 1>, NT, 0); break;
+      case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<C, WAVES, true, 2, 2>, NT, 0); break;
+      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<C, WAVES, true, 3, 3>, NT, 0); break;
+    }
+  } else {
+    switch (cls) {
+      case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<C, WAVES, false, 1, 2>, NT, 0); break;
+      case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<C, WAVES, false, 3, 4>, NT, 0); break;
+      case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<C, WAVES, false, 5, 6>, NT, 0); break;
+      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cell_scan_batched_kernel<C, WAVES, false, 7, 8>, NT, 0); break;
+    }
   }
   return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+}  // namespace
+
+hipError_t launch_cell_scan_batched(const BatchProblem *probs_dev, int np, int64_t first, int64_t last,
+                                    unsigned long long *next, int shape, bool bf16, int cls, int grid,
+                                    hipStream_t s) {
+  if (last <= first) return hipSuccess;
+  switch (shape) {
+    case 0: return bf16 ? launch_class<1, 8, true>(probs_dev, np, first, last, next, cls, grid, s)
+                        : launch_class<1, 8, false>(probs_dev, np, first, last, next, cls, grid, s);
+    case 1: return bf16 ? launch_class<2, 4, true>(probs_dev, np, first, last, next, cls, grid, s)
+                        : launch_class<2, 4, false>(probs_dev, np, first, last, next, cls, grid, s);
+    default: return bf16 ? launch_class<4, 8, true>(probs_dev, np, first, last, next, cls, grid, s)
+                         : launch_class<4, 8, false>(probs_dev, np, first, last, next, cls, grid, s);
+  }
+}
+
+int batched_blocks_per_cu(int shape, bool bf16, int cls) {
+  switch (shape) {
+    case 0: return bf16 ? class_blocks_per_cu<1, 8, true>(cls) : class_blocks_per_cu<1, 8, false>(cls);
+    case 1: return bf16 ? class_blocks_per_cu<2, 4, true>(cls) : class_blocks_per_cu<2, 4, false>(cls);
+    default: return bf16 ? class_blocks_per_cu<4, 8, true>(cls) : class_blocks_per_cu<4, 8, false>(cls);
+  }
 }
 
 }  // namespace vg

@@ -165,10 +165,14 @@ hipError_t launch_accum(const AccumArgs &a, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 
-hipError_t launch_cell_scan_batched(const BatchProblem *probs_dev, int np, int64_t total,
-                                    unsigned long long *next, int shape, bool bf16, int grid,
+// Persistent batched scan over items [first, last) of the table, all of one
+// register class (batched_class); `next` is that launch's item counter.
+hipError_t launch_cell_scan_batched(const BatchProblem *probs_dev, int np, int64_t first, int64_t last,
+                                    unsigned long long *next, int shape, bool bf16, int cls, int grid,
                                     hipStream_t s);
-int batched_blocks_per_cu(int shape, bool bf16);
+int batched_blocks_per_cu(int shape, bool bf16, int cls);
+int batched_class(int d, bool bf16);
+constexpr int kNumBatchClasses = 4;
 hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t *counters,
                                   const int64_t *flag_list, uint32_t *tie_counter, int grid,
                                   hipStream_t s);
