@@ -9,10 +9,12 @@
 // contraction is off so that each t is the same IEEE expression as a plain
 // sequential evaluation.
 //
-// Layout: a workgroup of 4 waves takes 4 queued rays at a time, one per wave;
-// node tiles of 256 nodes are staged in LDS with coalesced loads and shared
-// by the 4 rays.  Lane l of a wave evaluates nodes l, l+64, ... of each tile
-// and keeps a running top-2; the wave reduces it with cross-lane shuffles.
+// Layout: a workgroup of 8 waves takes 8 queued rays at a time, one per wave,
+// the ray's vectors held in registers; node tiles of 512 nodes (one per
+// thread) are staged in LDS as [coordinate][node] and shared by the 8 rays.
+// Lane l of a wave evaluates nodes l, l+64, ... of each tile and keeps a
+// running top-2; the wave reduces it with cross-lane shuffles.  The batched
+// variants below take one ray per wave and read their clouds directly.
 // The list length is read on the device, so the launch needs no host sync: a
 // fixed grid strides over the list.
 #include "vg_internal.h"
@@ -44,65 +46,110 @@ __device__ __forceinline__ Top2 merge(const Top2 &a, const Top2 &b) {
   return r;
 }
 
+// Single-problem recheck: 8 waves, one queued ray per wave; each thread
+// stages one node of a 512-node tile.
+constexpr int NT1 = 512;
+constexpr int WAVES1 = NT1 / 64;
+
 #pragma clang fp contract(off)
-__global__ __launch_bounds__(NT) void recheck_kernel(RecheckArgs a) {
-  __shared__ float tile[TILE * VG_MAX_DIM];
-  __shared__ double sx[WAVES][VG_MAX_DIM], su[WAVES][VG_MAX_DIM], sg[WAVES][VG_MAX_DIM];
-  __shared__ int32_t sex[WAVES][VG_MAX_DIM];
+// DK: the dimension rounded up to 4, 8, 12 or 16 (loops guard k < d, so the
+// order of every FP64 sum is the plain k = 0 .. d-1 order).  CELLS: the
+// Monte-Carlo rays of a cell, x = g = x_i and eta = {i}; there the numerator
+// (r - g).((r - x) + (g - x)) is exactly sum_k (r_k - g_k)^2, since
+// (r_k - g_k) + 0 = r_k - g_k.
+template <int DK, bool CELLS>
+__global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
+  __shared__ float tile[DK * NT1];  // [k][node]: lane-contiguous reads
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int d = a.d;
   const int64_t n = a.n;
   const uint32_t cnt = a.counters[CNT_FLAGGED];
-  for (uint32_t f0 = blockIdx.x * WAVES; f0 < cnt; f0 += gridDim.x * WAVES) {
+  for (uint32_t f0 = blockIdx.x * WAVES1; f0 < cnt; f0 += gridDim.x * WAVES1) {
     const uint32_t f = f0 + w;
     const bool live = f < cnt;
     const int64_t ray = live ? a.flag_list[f] : 0;
     int n_excl = 0, clip = 0;
     int32_t gi = 0;
+    // the wave's ray: origin x, direction u, generator g (x = g for CELLS)
+    double x[DK], u[DK], g[DK];
+    int32_t ex[VG_MAX_DIM];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) x[k] = u[k] = g[k] = 0.0;
+#pragma unroll
+    for (int e = 0; e < VG_MAX_DIM; ++e) ex[e] = -1;
     if (live) {
-      if (a.mode == RAYS_CELLS) {
-        const int64_t cell = ray / a.R;
-        gi = (int32_t)cell;
-        n_excl = 1;
+      if (CELLS) {
+        gi = (int32_t)(ray / a.R);
         clip = 1;
-        if (lane < d) {
-          sx[w][lane] = (double)a.nodes[cell * d + lane];
-          su[w][lane] = (double)a.dirs[ray * d + lane];
-        }
-        if (lane == 0) sex[w][0] = gi;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) u[k] = k < d ? (double)a.dirs[ray * d + k] : 0.0;
       } else {
         gi = a.gen[ray];
         n_excl = a.n_excl;
         clip = a.clip;
-        if (lane < d) {
-          sx[w][lane] = a.mode == RAYS_F64 ? a.o64[ray * d + lane] : (double)a.o32[ray * d + lane];
-          su[w][lane] = a.mode == RAYS_F64 ? a.u64[ray * d + lane] : (double)a.u32[ray * d + lane];
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+          if (k < d) {
+            x[k] = a.mode == RAYS_F64 ? a.o64[ray * d + k] : (double)a.o32[ray * d + k];
+            u[k] = a.mode == RAYS_F64 ? a.u64[ray * d + k] : (double)a.u32[ray * d + k];
+          }
         }
-        if (lane < n_excl) sex[w][lane] = a.excl[ray * n_excl + lane];
+#pragma unroll
+        for (int e = 0; e < VG_MAX_DIM; ++e)
+          if (e < n_excl) ex[e] = a.excl[ray * n_excl + e];
       }
-      if (lane < d) sg[w][lane] = (double)a.nodes[(int64_t)gi * d + lane];
+#pragma unroll
+      for (int k = 0; k < DK; ++k) g[k] = k < d ? (double)a.nodes[(int64_t)gi * d + k] : 0.0;
     }
-    __syncthreads();
+    if (CELLS) {
+#pragma unroll
+      for (int k = 0; k < DK; ++k) x[k] = g[k];
+    }
+    double gx[DK];  // g - x, the same value the expression forms per node
+#pragma unroll
+    for (int k = 0; k < DK; ++k) gx[k] = g[k] - x[k];
     Top2 tp{__builtin_inf(), __builtin_inf(), -1};
-    for (int64_t base = 0; base < n; base += TILE) {
-      const int cntn = (int)((n - base) < TILE ? (n - base) : TILE);
+    for (int64_t base = 0; base < n; base += NT1) {
+      const int cntn = (int)((n - base) < NT1 ? (n - base) : NT1);
       __syncthreads();
-      for (int q = tid; q < cntn * d; q += NT) tile[q] = a.nodes[base * d + q];
+      if (tid < cntn) {
+        const float *src = a.nodes + (base + tid) * d;
+#pragma unroll
+        for (int k = 0; k < DK; ++k)
+          if (k < d) tile[k * NT1 + tid] = src[k];
+      }
       __syncthreads();
       if (!live) continue;
       for (int q = lane; q < cntn; q += 64) {
         const int32_t r = (int32_t)(base + q);
-        bool skip = false;
-        for (int e = 0; e < n_excl; ++e) skip |= (sex[w][e] == r);
+        bool skip;
+        if (CELLS) {
+          skip = r == gi;
+        } else {
+          skip = false;
+#pragma unroll
+          for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
+        }
         if (skip) continue;
-        const float *xr = tile + q * d;
+        double e[DK];
+#pragma unroll
+        for (int k = 0; k < DK; ++k) e[k] = k < d ? (double)tile[k * NT1 + q] - g[k] : 0.0;
         double den = 0.0;
-        for (int k = 0; k < d; ++k) den += su[w][k] * ((double)xr[k] - sg[w][k]);
+#pragma unroll
+        for (int k = 0; k < DK; ++k)
+          if (k < d) den += u[k] * e[k];
         if (!(den > 0.0)) continue;
         // |r - x|^2 - |g - x|^2 as (r - g).((r - x) + (g - x))
         double num = 0.0;
-        for (int k = 0; k < d; ++k)
-          num += ((double)xr[k] - sg[w][k]) * (((double)xr[k] - sx[w][k]) + (sg[w][k] - sx[w][k]));
+        if (CELLS) {
+#pragma unroll
+          for (int k = 0; k < DK; ++k)
+            if (k < d) num += e[k] * e[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < DK; ++k)
+            if (k < d) num += e[k] * (((double)tile[k * NT1 + q] - x[k]) + gx[k]);
+        }
         // cheap filter (relaxed by 1e-12 so no candidate within rounding is lost)
         if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) continue;
         const double t = num / (2.0 * den);
@@ -129,14 +176,16 @@ __global__ __launch_bounds__(NT) void recheck_kernel(RecheckArgs a) {
         if (clip) {
           double tb = __builtin_inf();
           int face = -1;
-          for (int k = 0; k < d; ++k) {
+#pragma unroll
+          for (int k = 0; k < DK; ++k) {
+            if (k >= d) continue;
             double tk;
             int fc;
-            if (su[w][k] > 0.0) {
-              tk = (1.0 - sx[w][k]) / su[w][k];
+            if (u[k] > 0.0) {
+              tk = (1.0 - x[k]) / u[k];
               fc = 2 * k + 1;
-            } else if (su[w][k] < 0.0) {
-              tk = (0.0 - sx[w][k]) / su[w][k];
+            } else if (u[k] < 0.0) {
+              tk = (0.0 - x[k]) / u[k];
               fc = 2 * k;
             } else {
               continue;
@@ -171,6 +220,7 @@ __global__ __launch_bounds__(NT) void recheck_kernel(RecheckArgs a) {
   }
 }
 
+#pragma clang fp contract(off)
 // Batched Monte-Carlo rays: a queue entry is (problem << 40 | ray); each wave
 // takes one entry and reads that cloud's nodes directly (entries of one
 // workgroup may belong to different clouds, so no LDS tile is shared).
@@ -385,8 +435,24 @@ hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t 
 
 hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
   if (max_grid <= 0) return hipSuccess;
-  const int grid = (max_grid + WAVES - 1) / WAVES;
-  hipLaunchKernelGGL(recheck_kernel, dim3(grid), dim3(NT), 0, s, a);
+  const dim3 grid((max_grid + WAVES1 - 1) / WAVES1), blk(NT1);
+  const bool cells = a.mode == RAYS_CELLS;
+#define VG_RECHECK(DKV)                                                      \
+  do {                                                                      \
+    if (cells)                                                              \
+      hipLaunchKernelGGL((recheck_kernel<DKV, true>), grid, blk, 0, s, a);  \
+    else                                                                    \
+      hipLaunchKernelGGL((recheck_kernel<DKV, false>), grid, blk, 0, s, a); \
+  } while (0)
+  if (a.d <= 4)
+    VG_RECHECK(4);
+  else if (a.d <= 8)
+    VG_RECHECK(8);
+  else if (a.d <= 12)
+    VG_RECHECK(12);
+  else
+    VG_RECHECK(16);
+#undef VG_RECHECK
   return hipGetLastError();
 }
 
