@@ -25,6 +25,52 @@ struct ExploreRays {
 
 hipError_t launch_sphere_check(const ExploreRays &a, double *viol, hipStream_t s);
 
+// ---- device bookkeeping of the search (vg_vset.hip)
+enum : uint32_t { VSET_FULL = 1, VSET_COLLISION = 2, VSET_SINGULAR = 4 };
+
+// Discovered vertices: slot fingerprint (0 = empty), owner (smallest global
+// item index that claimed it; -1 for vertices of earlier levels), key
+// [cap][L] with L = d + 1.  cap is a power of two.
+struct VSet {
+  uint64_t *fp;
+  int64_t *owner;
+  int32_t *key;
+  int64_t cap;
+  int L;
+};
+
+// Edge visit counts: fingerprint, count, key [cap][d].
+struct ESet {
+  uint64_t *fp;
+  uint32_t *cnt;
+  int32_t *key;
+  int64_t cap;
+};
+
+hipError_t vset_clear(VSet V, hipStream_t s);
+hipError_t eset_clear(ESet E, hipStream_t s);
+// Insert vertices [0, nv) into V and/or count their edges into E.
+hipError_t vset_rebuild(VSet V, ESet E, const int32_t *vkeys, int64_t nv, int d, bool vertices,
+                        bool edges, uint32_t *err, hipStream_t s);
+// flags[(v - lb)(d+1) + o] = 1 when the edge of vertex v omitting position o
+// has been seen fewer than two times.
+hipError_t frontier_flags(const int32_t *vkeys, int64_t lb, int64_t le, int d, ESet E, uint8_t *flags,
+                          uint32_t *err, hipStream_t s);
+hipError_t frontier_items(const int64_t *sel, int64_t m, int64_t lb, int d, int64_t *item_v,
+                          int32_t *item_o, hipStream_t s);
+// Claim, settle and verify the new tuples of a level; is_new marks the items
+// that own a new vertex, is_unb the items without a hit.
+hipError_t vset_insert(VSet V, const int32_t *nkeys, const int32_t *idx, int64_t m, int64_t item_base,
+                       int64_t *slot, uint8_t *is_new, uint8_t *is_unb, uint32_t *err, hipStream_t s);
+hipError_t append_vertices(const int64_t *sel, int64_t nn, int64_t nv, int d, const int32_t *nkeys,
+                           const double *ncoords, int32_t *vkeys, double *vcoords, ESet E, int64_t *eslot,
+                           uint32_t *err, hipStream_t s);
+hipError_t append_unbounded(const int64_t *sel, int64_t nb, int64_t b0, int d, const int64_t *item_v,
+                            const int32_t *item_o, const int32_t *vkeys, int32_t *bsig, int32_t *bomit,
+                            hipStream_t s);
+hipError_t select_flagged(void *temp, size_t &temp_bytes, const uint8_t *flags, int64_t n, int64_t *out,
+                          int64_t *count_dev, hipStream_t s);
+
 hipError_t launch_edge_rays(const ExploreRays &a, hipStream_t s);
 hipError_t launch_new_vertices(const ExploreRays &a, hipStream_t s);
 hipError_t launch_descent_project(const float *X, int d, const int32_t *sig, int m, double *u,

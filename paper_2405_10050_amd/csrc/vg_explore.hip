@@ -6,13 +6,14 @@
 // discoveries of the previous level form one batch of rays, cast on the GPU
 // (FP32 scan, FP64 recheck of uncertain rays, no clipping).  New vertices are
 // keyed by the sorted (d+1)-tuple sort(eta U {j}); their FP64 coordinates are
-// solved on the GPU from the tuple.  The host keeps the vertex set and the
-// edge counts in open-addressing hash tables and counts, for every newly
-// discovered vertex, each of its d+1 edges (the start vertex included).  A ray
-// with no hit is an unbounded edge, recorded as (vertex, omitted generator).
-// The vertex set equals the sequential algorithm's: batching only changes the
-// order of discovery (and may discover a vertex twice in one level, which the
-// set absorbs).
+// solved on the GPU from the tuple.  The vertex set and the edge counts are
+// device hash tables (vg_vset.hip); every newly discovered vertex counts each
+// of its d+1 edges (the start vertex included).  A ray with no hit is an
+// unbounded edge, recorded as (vertex, omitted generator).  Frontiers and new
+// vertices are compacted in item order, so the vertex order is that of a
+// sequential sweep over each level.  The vertex set equals the sequential
+// algorithm's: batching only changes the order of discovery (and may
+// discover a vertex twice in one level, which the set absorbs).
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -30,82 +31,11 @@ struct vg_mesh {
   std::vector<double> coord;
   std::vector<int32_t> bsig, bomit;
   int64_t raycasts = 0;
-  int64_t duplicates = 0;
 };
 
 using namespace vg;
 
 namespace {
-
-// Open-addressing table from fixed-length int32 tuples to a value.
-template <typename V>
-class TupleTable {
- public:
-  explicit TupleTable(int L) : L_(L) { rehash(1 << 12); }
-  size_t size() const { return size_; }
-  // Returns the value slot of key, inserting `init` if absent.
-  V *find_or_insert(const int32_t *key, V init, bool &inserted) {
-    if (2 * (size_ + 1) > cap_) rehash(cap_ * 2);
-    size_t s = hash(key) & (cap_ - 1);
-    for (;;) {
-      if (!used_[s]) {
-        used_[s] = 1;
-        std::memcpy(&keys_[s * L_], key, sizeof(int32_t) * L_);
-        vals_[s] = init;
-        ++size_;
-        inserted = true;
-        return &vals_[s];
-      }
-      if (!std::memcmp(&keys_[s * L_], key, sizeof(int32_t) * L_)) {
-        inserted = false;
-        return &vals_[s];
-      }
-      s = (s + 1) & (cap_ - 1);
-    }
-  }
-  const V *find(const int32_t *key) const {
-    size_t s = hash(key) & (cap_ - 1);
-    for (;;) {
-      if (!used_[s]) return nullptr;
-      if (!std::memcmp(&keys_[s * L_], key, sizeof(int32_t) * L_)) return &vals_[s];
-      s = (s + 1) & (cap_ - 1);
-    }
-  }
-
- private:
-  uint64_t hash(const int32_t *k) const {
-    uint64_t h = 0x243F6A8885A308D3ull ^ (uint64_t)L_;
-    for (int a = 0; a < L_; ++a) {
-      h = (h ^ (uint32_t)k[a]) * 0x9E3779B97F4A7C15ull;
-      h ^= h >> 29;
-    }
-    return h ^ (h >> 32);
-  }
-  void rehash(size_t cap) {
-    std::vector<int32_t> ok;
-    std::vector<V> ov;
-    std::vector<uint8_t> ou;
-    ok.swap(keys_);
-    ov.swap(vals_);
-    ou.swap(used_);
-    const size_t ocap = cap_;
-    cap_ = cap;
-    keys_.assign(cap_ * L_, 0);
-    vals_.assign(cap_, V());
-    used_.assign(cap_, 0);
-    size_ = 0;
-    for (size_t s = 0; s < ocap; ++s)
-      if (ou[s]) {
-        bool ins;
-        *find_or_insert(&ok[s * L_], ov[s], ins) = ov[s];
-      }
-  }
-  int L_;
-  size_t cap_ = 0, size_ = 0;
-  std::vector<int32_t> keys_;
-  std::vector<V> vals_;
-  std::vector<uint8_t> used_;
-};
 
 // Device buffer that grows by reallocation (contents not kept unless asked).
 struct DevBuf {
@@ -147,8 +77,10 @@ struct Explorer {
   hipStream_t s;
   std::string err;
 
-  DevBuf keys_d, coords_d;  // device mirror of the vertex table
-  int64_t dev_count = 0;    // vertices mirrored on the device
+  DevBuf keys_d, coords_d;                 // vertex list: keys [V][d+1], coordinates [V][d]
+  DevBuf vfp, vowner, vkey, efp, ecnt, ekey;  // vertex set and edge counts (VSet, ESet)
+  DevBuf bsig_d, bomit_d;                  // unbounded edges
+  DevBuf counters, cub, flags, sel, sel2, slot, is_new, is_unb, eslot;
   DevBuf item_v, item_o, o64, u64, gen, excl, ok, tb, idx, st, nkeys, ncoords, viol;
 
   bool hip(hipError_t e, const char *what) {
@@ -293,59 +225,99 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
 
   {
     // ------------------------------------------------- breadth-first levels
-    TupleTable<int64_t> V(L);
-    TupleTable<uint8_t> G(d);
-    std::vector<int32_t> eta(d);
-    auto count_edges = [&](const int32_t *key) {
-      for (int o = 0; o <= d; ++o) {
-        int q = 0;
-        for (int b = 0; b <= d; ++b)
-          if (b != o) eta[q++] = key[b];
-        bool ins;
-        uint8_t *c = G.find_or_insert(eta.data(), 0, ins);
-        if (*c < 255) ++*c;
-      }
+    // The vertex set, the edge counts, the frontier and the unbounded edges
+    // all live on the device; per level the host reads three counts.
+    int64_t nv = 1, nb_total = 0, item_base = 0, vcap = 0, ecap = 0;
+    uint32_t *errd = nullptr;
+    int64_t *cntd = nullptr;
+    EX_HIP(X.counters.reserve(64, false, X.s));
+    errd = X.counters.as<uint32_t>();
+    cntd = reinterpret_cast<int64_t *>(X.counters.as<char>() + 16);
+    EX_HIP(fill_u32(errd, 0u, 16, X.s));
+    EX_HIP(X.keys_d.reserve(sizeof(int32_t) * L * 1024, false, X.s));
+    EX_HIP(X.coords_d.reserve(sizeof(double) * d * 1024, false, X.s));
+    EX_HIP(hipMemcpyAsync(X.keys_d.p, M->sig.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, X.s));
+    EX_HIP(hipMemcpyAsync(X.coords_d.p, M->coord.data(), sizeof(double) * d, hipMemcpyHostToDevice, X.s));
+    // tables at most half full: (re)built from the vertex list when they grow
+    auto vset = [&]() {
+      return VSet{X.vfp.as<uint64_t>(), X.vowner.as<int64_t>(), X.vkey.as<int32_t>(), vcap, L};
     };
-    bool ins;
-    *V.find_or_insert(M->sig.data(), 0, ins) = 0;
-    count_edges(M->sig.data());
+    auto eset = [&]() { return ESet{X.efp.as<uint64_t>(), X.ecnt.as<uint32_t>(), X.ekey.as<int32_t>(), ecap}; };
+    auto grow_v = [&](int64_t need) -> hipError_t {
+      if (2 * need <= vcap) return hipSuccess;
+      int64_t c = int64_t(1) << 16;
+      while (c < 4 * need) c <<= 1;
+      hipError_t e = X.vfp.reserve(sizeof(uint64_t) * c, false, X.s);
+      if (e == hipSuccess) e = X.vowner.reserve(sizeof(int64_t) * c, false, X.s);
+      if (e == hipSuccess) e = X.vkey.reserve(sizeof(int32_t) * L * c, false, X.s);
+      if (e != hipSuccess) return e;
+      vcap = c;
+      e = vset_clear(vset(), X.s);
+      if (e == hipSuccess) e = vset_rebuild(vset(), eset(), X.keys_d.as<int32_t>(), nv, d, true, false, errd, X.s);
+      return e;
+    };
+    auto grow_e = [&](int64_t need) -> hipError_t {
+      if (2 * need <= ecap) return hipSuccess;
+      int64_t c = int64_t(1) << 18;
+      while (c < 4 * need) c <<= 1;
+      hipError_t e = X.efp.reserve(sizeof(uint64_t) * c, false, X.s);
+      if (e == hipSuccess) e = X.ecnt.reserve(sizeof(uint32_t) * c, false, X.s);
+      if (e == hipSuccess) e = X.ekey.reserve(sizeof(int32_t) * d * c, false, X.s);
+      if (e != hipSuccess) return e;
+      ecap = c;
+      e = eset_clear(eset(), X.s);
+      if (e == hipSuccess) e = vset_rebuild(vset(), eset(), X.keys_d.as<int32_t>(), nv, d, false, true, errd, X.s);
+      return e;
+    };
+    // stable compaction of the flagged indices into `out`; returns the count
+    auto compact = [&](DevBuf &flags, int64_t n, DevBuf &out, int64_t &count) -> hipError_t {
+      size_t tb = 0;
+      hipError_t e = select_flagged(nullptr, tb, flags.as<uint8_t>(), n, out.as<int64_t>(), cntd, X.s);
+      if (e == hipSuccess) e = X.cub.reserve(std::max<size_t>(tb, 16), false, X.s);
+      if (e == hipSuccess) e = select_flagged(X.cub.p, tb, flags.as<uint8_t>(), n, out.as<int64_t>(), cntd, X.s);
+      if (e == hipSuccess) e = hipMemcpyAsync(&count, cntd, sizeof(int64_t), hipMemcpyDeviceToHost, X.s);
+      if (e == hipSuccess) e = hipStreamSynchronize(X.s);
+      return e;
+    };
+    auto check_err = [&]() -> int {
+      uint32_t eh = 0;
+      if (hipMemcpyAsync(&eh, errd, sizeof eh, hipMemcpyDeviceToHost, X.s) != hipSuccess ||
+          hipStreamSynchronize(X.s) != hipSuccess) {
+        ctx->err = "explore: reading the error word failed";
+        return VG_EDEVICE;
+      }
+      if (eh & VSET_SINGULAR) {
+        ctx->err = "singular vertex (degenerate input)";
+        return VG_EINVAL;
+      }
+      if (eh & VSET_COLLISION) {
+        ctx->err = "explore: two different tuples share a 64-bit fingerprint";
+        return VG_EUNSUPPORTED;
+      }
+      if (eh & VSET_FULL) {
+        ctx->err = "explore: a device table ran full";
+        return VG_EDEVICE;
+      }
+      return VG_OK;
+    };
+    EX_HIP(grow_v(1));
+    EX_HIP(grow_e((int64_t)L));
     int64_t level_begin = 0, level_end = 1;
     const bool verbose = std::getenv("VG_VERBOSE") != nullptr;
     const bool validate = std::getenv("VG_VALIDATE") != nullptr;
     const auto t_start = std::chrono::steady_clock::now();
     int level = 0;
-    std::vector<int64_t> iv;
-    std::vector<int32_t> io, jh, kh;
-    std::vector<double> ch;
     while (level_begin < level_end) {
-      // frontier: edges of the vertices of this level with G < 2
-      iv.clear();
-      io.clear();
-      for (int64_t v = level_begin; v < level_end; ++v) {
-        const int32_t *key = &M->sig[v * L];
-        for (int o = 0; o <= d; ++o) {
-          int q = 0;
-          for (int b = 0; b <= d; ++b)
-            if (b != o) eta[q++] = key[b];
-          const uint8_t *c = G.find(eta.data());
-          if (c && *c >= 2) continue;
-          iv.push_back(v);
-          io.push_back(o);
-        }
-      }
-      const int64_t m = (int64_t)iv.size();
-      // mirror this level's vertices on the device
-      const int64_t nv = (int64_t)M->sig.size() / L;
-      if (nv > X.dev_count) {
-        EX_HIP(X.keys_d.reserve(sizeof(int32_t) * nv * L, true, X.s));
-        EX_HIP(X.coords_d.reserve(sizeof(double) * nv * d, true, X.s));
-        EX_HIP(hipMemcpyAsync(X.keys_d.as<int32_t>() + X.dev_count * L, &M->sig[X.dev_count * L],
-                              sizeof(int32_t) * (nv - X.dev_count) * L, hipMemcpyHostToDevice, X.s));
-        EX_HIP(hipMemcpyAsync(X.coords_d.as<double>() + X.dev_count * d,
-                              &M->coord[X.dev_count * d],
-                              sizeof(double) * (nv - X.dev_count) * d, hipMemcpyHostToDevice, X.s));
-        X.dev_count = nv;
-      }
+      // frontier: edges of this level's vertices seen fewer than two times
+      const int64_t lb = level_begin;
+      const int64_t cand = (level_end - level_begin) * L;
+      EX_HIP(X.flags.reserve(cand, false, X.s));
+      EX_HIP(X.sel.reserve(sizeof(int64_t) * cand, false, X.s));
+      EX_HIP(frontier_flags(X.keys_d.as<int32_t>(), level_begin, level_end, d, eset(), X.flags.as<uint8_t>(),
+                            errd, X.s));
+      int64_t m = 0;
+      EX_HIP(compact(X.flags, cand, X.sel, m));
+      EX_RC(check_err());
       level_begin = level_end;
       if (m == 0) break;
       EX_HIP(X.item_v.reserve(sizeof(int64_t) * m, false, X.s));
@@ -360,8 +332,12 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       EX_HIP(X.st.reserve(m, false, X.s));
       EX_HIP(X.nkeys.reserve(sizeof(int32_t) * m * L, false, X.s));
       EX_HIP(X.ncoords.reserve(sizeof(double) * m * d, false, X.s));
-      EX_HIP(hipMemcpyAsync(X.item_v.p, iv.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, X.s));
-      EX_HIP(hipMemcpyAsync(X.item_o.p, io.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, X.s));
+      EX_HIP(X.slot.reserve(sizeof(int64_t) * m, false, X.s));
+      EX_HIP(X.is_new.reserve(m, false, X.s));
+      EX_HIP(X.is_unb.reserve(m, false, X.s));
+      EX_HIP(X.sel2.reserve(sizeof(int64_t) * m, false, X.s));
+      EX_HIP(frontier_items(X.sel.as<int64_t>(), m, lb, d, X.item_v.as<int64_t>(), X.item_o.as<int32_t>(),
+                            X.s));
       ExploreRays er{};
       er.nodes = nodes;
       er.d = d;
@@ -385,85 +361,72 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       M->raycasts += m;
       EX_HIP(launch_new_vertices(er, X.s));
       if (validate) {
-        // report the edge rays whose new vertex has a node inside its sphere
+        // count the edge rays whose new vertex has a node inside its sphere
         EX_HIP(X.viol.reserve(sizeof(double) * m, false, X.s));
         EX_HIP(launch_sphere_check(er, X.viol.as<double>(), X.s));
         std::vector<double> vh(m);
-        std::vector<float> th(m);
-        std::vector<uint8_t> sh(m);
         EX_HIP(hipMemcpyAsync(vh.data(), X.viol.p, sizeof(double) * m, hipMemcpyDeviceToHost, X.s));
-        EX_HIP(hipMemcpyAsync(th.data(), X.tb.p, sizeof(float) * m, hipMemcpyDeviceToHost, X.s));
-        EX_HIP(hipMemcpyAsync(sh.data(), X.st.p, m, hipMemcpyDeviceToHost, X.s));
-        std::vector<int32_t> jj(m);
-        EX_HIP(hipMemcpyAsync(jj.data(), X.idx.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, X.s));
         EX_HIP(hipStreamSynchronize(X.s));
-        int shown = 0;
-        int64_t bad = 0;
-        for (int64_t it = 0; it < m; ++it) {
-          if (vh[it] < -1e-9) {
-            ++bad;
-            if (shown < 8) {
-              ++shown;
-              const int32_t *vk = &M->sig[iv[it] * L];
-              std::fprintf(stderr, "[explore] level %d item %lld: vertex %lld omit %d hit %d t=%.9g status=%u violation=%.3e coord0=",
-                           level + 1, (long long)it, (long long)iv[it], vk[io[it]], jj[it], th[it],
-                           (unsigned)sh[it], vh[it]);
-              for (int k = 0; k < d; ++k) std::fprintf(stderr, "%.6g ", M->coord[iv[it] * d + k]);
-              std::fprintf(stderr, "\n");
-            }
-          }
-        }
+        int64_t bad = 0, first = -1;
+        for (int64_t it = 0; it < m; ++it)
+          if (vh[it] < -1e-9 && bad++ == 0) first = it;
         if (bad) {
-          std::fprintf(stderr, "[explore] level %d: %lld new vertices violate the empty sphere\n",
-                       level + 1, (long long)bad);
+          std::fprintf(stderr, "[explore] level %d: %lld new vertices violate the empty sphere (first: item %lld, %.3e)\n",
+                       level + 1, (long long)bad, (long long)first, vh[first]);
           std::fflush(stderr);
           ctx->err = "explore validation failed";
           rc = VG_EINVAL;
           goto fail;
         }
       }
-      jh.resize(m);
-      kh.resize(m * L);
-      ch.resize(m * d);
-      EX_HIP(hipMemcpyAsync(jh.data(), X.idx.p, sizeof(int32_t) * m, hipMemcpyDeviceToHost, X.s));
-      EX_HIP(hipMemcpyAsync(kh.data(), X.nkeys.p, sizeof(int32_t) * m * L, hipMemcpyDeviceToHost, X.s));
-      EX_HIP(hipMemcpyAsync(ch.data(), X.ncoords.p, sizeof(double) * m * d, hipMemcpyDeviceToHost,
-                            X.s));
-      EX_HIP(hipStreamSynchronize(X.s));
-      for (int64_t it = 0; it < m; ++it) {
-        const int32_t *vkey = &M->sig[iv[it] * L];
-        if (jh[it] < 0) {
-          M->bsig.insert(M->bsig.end(), vkey, vkey + L);
-          M->bomit.push_back(vkey[io[it]]);
-          continue;
-        }
-        const int32_t *nk = &kh[it * L];
-        if (nk[0] == -2) {
-          ctx->err = "singular vertex (degenerate input)";
-          rc = VG_EINVAL;
-          goto fail;
-        }
-        if (nk[0] < 0) continue;
-        int64_t *slot = V.find_or_insert(nk, 0, ins);
-        if (!ins) {
-          M->duplicates++;
-          continue;
-        }
-        *slot = (int64_t)M->sig.size() / L;
-        M->sig.insert(M->sig.end(), nk, nk + L);
-        M->coord.insert(M->coord.end(), &ch[it * d], &ch[it * d] + d);
-        count_edges(nk);
+      // insert the new tuples, then append the new vertices and unbounded edges
+      EX_HIP(grow_v(nv + m));
+      EX_HIP(vset_insert(vset(), X.nkeys.as<int32_t>(), X.idx.as<int32_t>(), m, item_base, X.slot.as<int64_t>(),
+                         X.is_new.as<uint8_t>(), X.is_unb.as<uint8_t>(), errd, X.s));
+      int64_t nn = 0, nb = 0;
+      EX_HIP(compact(X.is_new, m, X.sel, nn));
+      EX_HIP(compact(X.is_unb, m, X.sel2, nb));
+      EX_RC(check_err());
+      EX_HIP(X.keys_d.reserve(sizeof(int32_t) * L * (nv + nn), true, X.s));
+      EX_HIP(X.coords_d.reserve(sizeof(double) * d * (nv + nn), true, X.s));
+      EX_HIP(grow_e((int64_t)L * (nv + nn)));
+      EX_HIP(X.eslot.reserve(sizeof(int64_t) * L * std::max<int64_t>(nn, 1), false, X.s));
+      EX_HIP(append_vertices(X.sel.as<int64_t>(), nn, nv, d, X.nkeys.as<int32_t>(), X.ncoords.as<double>(),
+                             X.keys_d.as<int32_t>(), X.coords_d.as<double>(), eset(), X.eslot.as<int64_t>(),
+                             errd, X.s));
+      if (nb > 0) {
+        EX_HIP(X.bsig_d.reserve(sizeof(int32_t) * L * (nb_total + nb), true, X.s));
+        EX_HIP(X.bomit_d.reserve(sizeof(int32_t) * (nb_total + nb), true, X.s));
+        EX_HIP(append_unbounded(X.sel2.as<int64_t>(), nb, nb_total, d, X.item_v.as<int64_t>(),
+                                X.item_o.as<int32_t>(), X.keys_d.as<int32_t>(), X.bsig_d.as<int32_t>(),
+                                X.bomit_d.as<int32_t>(), X.s));
       }
-      level_end = (int64_t)M->sig.size() / L;
+      item_base += m;
+      nb_total += nb;
+      nv += nn;
+      level_end = nv;
       ++level;
       if (verbose) {
         const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
         std::fprintf(stderr, "[explore] level %d: %lld rays, %lld new vertices, %lld total, %.2f s\n",
-                     level, (long long)m, (long long)(level_end - level_begin),
-                     (long long)level_end, el);
+                     level, (long long)m, (long long)nn, (long long)nv, el);
         std::fflush(stderr);
       }
     }
+    EX_RC(check_err());
+    // the mesh is returned in host memory
+    M->sig.resize((size_t)nv * L);
+    M->coord.resize((size_t)nv * d);
+    M->bsig.resize((size_t)nb_total * L);
+    M->bomit.resize((size_t)nb_total);
+    EX_HIP(hipMemcpyAsync(M->sig.data(), X.keys_d.p, sizeof(int32_t) * L * nv, hipMemcpyDeviceToHost, X.s));
+    EX_HIP(hipMemcpyAsync(M->coord.data(), X.coords_d.p, sizeof(double) * d * nv, hipMemcpyDeviceToHost, X.s));
+    if (nb_total > 0) {
+      EX_HIP(hipMemcpyAsync(M->bsig.data(), X.bsig_d.p, sizeof(int32_t) * L * nb_total, hipMemcpyDeviceToHost,
+                            X.s));
+      EX_HIP(hipMemcpyAsync(M->bomit.data(), X.bomit_d.p, sizeof(int32_t) * nb_total, hipMemcpyDeviceToHost, X.s));
+    }
+    EX_HIP(hipStreamSynchronize(X.s));
   }
   *out = M;
   return VG_OK;
