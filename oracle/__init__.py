@@ -32,6 +32,11 @@ Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
                             gradient identity 2 V (x - c).
   star                      equals the vertices of ``explore`` that contain the
                             generator.
+  mc_integrals              f = 1 gives the facet areas, and t = 1 (t = 1/2)
+                            gives d (d 2^{1-d}) times the volume, exactly;
+                            2-D: exact cell and edge integrals of a linear f
+                            (area times f at the centroid, length times f at
+                            the midpoint) within Monte-Carlo error.
 No oracle function is unpinned.
 """
 from __future__ import annotations
@@ -309,6 +314,54 @@ def mc_volume_area(nodes, cells, dirs, rays=None):
         facets[key] *= S / nr
     return dict(volume=volume, energy2=energy2, facets=facets, t=t, idx=idx, t2=t2,
                 w_vol=wv, w_area=wa, w_energy=we)
+
+
+def mc_integrals(nodes, cells, dirs, tsamp, f, rays=None):
+    """Integrals of a function ``f`` over the listed cells and their facets,
+    following Algorithm 3 (Sec. 3.1) with its inner loop of ``m`` draws:
+
+      F_V[i]  = S/(n m) sum_k sum_s f((1 - t_ks) x_i + t_ks r_k) t_ks^{d-1} l_k^d
+      F(i, j) = S/n     sum_{k: j_k = j} f(r_k) l_k^{d-1} / |n_ij . u_k|
+
+    with ``l_k`` = t* of ray k, ``r_k = x_i + l_k u_k`` its hit point and
+    ``t_ks = tsamp[c][k][s]`` in (0, 1) (``m = tsamp.shape[-1]``, possibly 0).
+    The normalisation S/(n m) is Algorithm 3's: in polar coordinates about
+    x_i the volume element is t^{d-1} l^d dt dS with t uniform on (0, 1), so
+    no factor 1/d enters (the displayed equation for the integral of f
+    carries one; with f = 1 and uniform t both agree only in expectation
+    through E[t^{d-1}] = 1/d).
+    ``f`` maps a float64 array [P, d] of points to [P] values.  Returns a
+    dict with ``F_V`` (per listed cell, None when m = 0), ``F`` (dict
+    ``(i, j) -> integral``) and the per-ray ``f_hit``."""
+    base = mc_volume_area(nodes, cells, dirs, rays)
+    X = _f64(nodes)
+    n, d = X.shape
+    cells = np.asarray(cells, dtype=np.int64).ravel()
+    nc = cells.size
+    D = _f64(dirs).reshape(nc, -1, d)
+    nr = D.shape[1]
+    t = base["t"].reshape(nc, nr)
+    xi = X[cells][:, None, :]
+    r = xi + t[..., None] * D  # hit points
+    f_hit = np.asarray(f(r.reshape(-1, d)), dtype=np.float64).reshape(nc, nr)
+    S = sphere_area(d)
+    F = {}
+    cell_of_ray = np.repeat(cells, nr)
+    contrib = (f_hit.ravel() * base["w_area"])
+    for k in range(contrib.size):
+        key = (int(cell_of_ray[k]), int(base["idx"][k]))
+        F[key] = F.get(key, 0.0) + contrib[k]
+    for key in F:
+        F[key] *= S / nr
+    T = np.asarray(tsamp, dtype=np.float64).reshape(nc, nr, -1)
+    m = T.shape[2]
+    F_V = None
+    if m > 0:
+        pts = (1.0 - T[..., None]) * xi[:, :, None, :] + T[..., None] * r[:, :, None, :]
+        fv = np.asarray(f(pts.reshape(-1, d)), dtype=np.float64).reshape(nc, nr, m)
+        F_V = S / (nr * m) * (fv * T ** (d - 1) * (t ** d)[..., None]).sum(axis=(1, 2))
+    return dict(F_V=F_V, F=F, f_hit=f_hit, volume=base["volume"], facets=base["facets"],
+                t=base["t"], idx=base["idx"], t2=base["t2"], w_area=base["w_area"])
 
 
 def mc_adjoint(nodes, cells, dirs, t, idx, g_volume=None, g_energy2=None, g_area_ray=None):

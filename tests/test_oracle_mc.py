@@ -247,3 +247,84 @@ def test_centroidal_energy_gradient_identity(oracle_mod):
     # unbiased: the discrepancy is sampling noise and halves when the rays quadruple
     assert errs[1] < 0.08
     assert 1.5 < errs[0] / errs[1] < 2.7
+
+
+# ---------------------------------------------------------------------------
+# integrals of a function f (Algorithm 3 with its inner loop)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d,n", [(2, 60), (3, 80), (5, 60)])
+def test_function_integrals_reduce_to_volume_and_areas(oracle_mod, d, n):
+    """f = 1 turns the facet integrals into the facet areas; with every draw
+    t = 1 (t = 1/2) the volume integral is d (d 2^{1-d}) times the volume
+    estimator, since t^{d-1} l^d then equals d times (2^{1-d} d times) the
+    volume term l^d / d of the same ray."""
+    X = W.uniform_cloud(n, d, seed=20 + d)
+    cells = np.arange(0, n, 3)
+    R, m = 128, 3
+    D = W.mc_directions(cells, R, d, seed=21)
+    one = lambda p: np.ones(p.shape[0])  # noqa: E731
+    for tval, factor in ((1.0, d), (0.5, d * 0.5 ** (d - 1))):
+        T = np.full((cells.size, R, m), tval)
+        r = oracle_mod.mc_integrals(X, cells, D, T, one)
+        assert np.allclose(r["F_V"], factor * r["volume"], rtol=1e-12)
+        assert set(r["F"]) == set(r["facets"])
+        for key, A in r["facets"].items():
+            assert r["F"][key] == pytest.approx(A, rel=1e-12)
+
+
+def _exact_linear_2d(X, i, c0, c):
+    """Exact integrals of f(y) = c0 + c.y over cell i (area f(centroid)) and
+    over its edges (per label: sum of segment length times f(midpoint))."""
+    sq = [(np.array([0.0, 0.0]), -2 - 2), (np.array([1.0, 0.0]), -2 - 1),
+          (np.array([1.0, 1.0]), -2 - 3), (np.array([0.0, 1.0]), -2 - 0)]
+    poly = sq
+    xi = X[i]
+    for j in range(X.shape[0]):
+        if j != i:
+            poly = _clip(poly, X[j] - xi, 0.5 * (X[j] @ X[j] - xi @ xi), j)
+    P = np.array([p for p, _ in poly])
+    cross = P[:, 0] * np.roll(P[:, 1], -1) - np.roll(P[:, 0], -1) * P[:, 1]
+    area = 0.5 * cross.sum()
+    cen = np.array([((P[:, 0] + np.roll(P[:, 0], -1)) * cross).sum(),
+                    ((P[:, 1] + np.roll(P[:, 1], -1)) * cross).sum()]) / (6.0 * area)
+    cell = abs(area) * (c0 + c @ cen)
+    edges = {}
+    for q, (p0, lab) in enumerate(poly):
+        p1 = poly[(q + 1) % len(poly)][0]
+        L = np.linalg.norm(p1 - p0)
+        if L > 0:
+            edges[lab] = edges.get(lab, 0.0) + L * (c0 + c @ (0.5 * (p0 + p1)))
+    return cell, edges
+
+
+def test_function_integrals_2d_exact_polygons(oracle_mod):
+    n, R, m = 30, 1024, 4
+    X = W.uniform_cloud(n, 2, seed=9)
+    X64 = X.astype(np.float64)
+    cells = np.arange(n)
+    D = W.mc_directions(cells, R, 2, seed=5)
+    rng = np.random.default_rng(7)
+    T = rng.random((n, R, m))
+    c0, c = 0.3, np.array([1.7, -0.9])
+    f = lambda p: c0 + p @ c  # noqa: E731
+    r = oracle_mod.mc_integrals(X, cells, D, T, f)
+    S = oracle_mod.sphere_area(2)
+    # per-ray contributions, for the Monte-Carlo standard errors
+    t = r["t"].reshape(n, R)
+    pts = (1 - T[..., None]) * X64[:, None, None, :] + T[..., None] * (X64[:, None, :] + t[..., None] * D)[:, :, None, :]
+    vol_ray = S * (f(pts.reshape(-1, 2)).reshape(n, R, m) * T * (t ** 2)[..., None]).mean(axis=2)
+    se_v = _sample_se(vol_ray)
+    idx = r["idx"].reshape(n, R)
+    fa = (r["f_hit"] * r["w_area"].reshape(n, R)) * S
+    checked = 0
+    for i in range(n):
+        cell, edges = _exact_linear_2d(X64, i, c0, c)
+        assert vol_ray[i].mean() == pytest.approx(r["F_V"][i], rel=1e-12)
+        assert abs(r["F_V"][i] - cell) <= 5 * se_v[i] + 1e-12, (i, r["F_V"][i], cell, se_v[i])
+        for lab, val in edges.items():
+            per_ray = fa[i] * (idx[i] == lab)
+            assert per_ray.mean() == pytest.approx(r["F"].get((i, lab), 0.0), rel=1e-12, abs=1e-15)
+            if (idx[i] == lab).sum() > 30:
+                assert abs(per_ray.mean() - val) <= 5 * _sample_se(per_ray) + 1e-12, (i, lab)
+                checked += 1
+    assert checked > 2 * n
