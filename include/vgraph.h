@@ -179,6 +179,33 @@ int vg_tuple_neighbors(vg_ctx *ctx, int d, int64_t n_nodes, int64_t n_tuples,
                        const int32_t *sigma, int64_t *offsets, int32_t *nbr,
                        int64_t nbr_capacity, int64_t *nnz);
 
+/* Integrals of a function f over the cells and their facets, following
+ * Algorithm 3 (Sec. 3.1) with its inner loop of m draws per ray.  Two calls,
+ * with the caller evaluating f in between:
+ *
+ * vg_mc_sample_points writes, for every ray k of cell i (l = t*, from
+ * vg_mc_volume_area or vg_mc_volume_area_nbr with the same dirs), the hit
+ * point x_i + l u followed by the interior points x_i + t_s l u:
+ *   t [n_nodes*n] f32, tsamp [n_nodes][n][m] f32 in (0, 1) (the draws; may be
+ *   NULL when m == 0), points [n_nodes][n][m+1][d] f32 (output).
+ *
+ * vg_mc_integrals takes fvals [n_nodes][n][m+1] f32 = f at those points and
+ * writes, with S = S_{d-1},
+ *   fint_volume[i] = S/(n m) sum_k sum_s f(x_i + t_ks l_k u_k) t_ks^{d-1} l_k^d
+ *   F(i, j)        = S/n sum_{k: j_k = j} f(x_i + l_k u_k) l_k^{d-1} / |n_ij . u_k|
+ * The normalisation S/(n m) is Algorithm 3's (the volume element in polar
+ * coordinates is t^{d-1} l^d dt dS).  F(i, j) goes to fint_facet [n_nodes][n]
+ * in the row layout of vg_mc_volume_area: facet_j / facet_count are written
+ * too, with the same values.  fint_volume may be NULL when m == 0; the three
+ * facet arrays are all set or all NULL.  0 <= m <= 1024. */
+int vg_mc_sample_points(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                        int rays_per_cell, const float *dirs, const float *t, int m,
+                        const float *tsamp, float *points);
+int vg_mc_integrals(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                    int rays_per_cell, const float *t, const int32_t *idx, int m,
+                    const float *tsamp, const float *fvals, float *fint_volume,
+                    int32_t *facet_j, float *fint_facet, int32_t *facet_count);
+
 /* Adjoint of vg_mc_volume_area with the directions frozen: writes
  *   grad_nodes[n_nodes][d] = d/dX ( sum_i g_volume[i] volume[i]
  *        + g_energy2[i] energy2[i] + sum_{i,f} g_facet_area[i][f] area(i,f) )

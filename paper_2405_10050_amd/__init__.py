@@ -13,6 +13,7 @@ Calls (names follow the paper's statement of the problem):
   raycast_cells(nodes, dirs)                           Monte-Carlo rays of every cell
   mc_volume_area(nodes, dirs, neighbors=None)          Sec. 3.1 / Algorithm 3 estimators
   tuple_neighbors(sigma, n)                            cell adjacency from vertex tuples
+  mc_integrals(nodes, dirs, res, f, tsamp)             integrals of f over cells and facets
   mc_backward(...), VoronoiMC                          adjoint / autograd Function
   raycast_batched(problems, clip)                      many RayCast problems, one launch
   raycast_cells_batched(problems)                      uneven batch of clouds
@@ -71,7 +72,8 @@ EXPORTS = (
     "vg_create", "vg_destroy", "vg_set_stream", "vg_last_error", "vg_get_stats",
     "vg_set_profiling", "vg_raycast",
     "vg_raycast_cells", "vg_mc_volume_area", "vg_mc_backward", "vg_raycast_cells_batched",
-    "vg_raycast_batched", "vg_mc_volume_area_nbr", "vg_tuple_neighbors",
+    "vg_raycast_batched", "vg_mc_volume_area_nbr", "vg_tuple_neighbors", "vg_mc_sample_points",
+    "vg_mc_integrals",
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
     "vg_mesh_copy", "vg_mesh_free",
 )
@@ -99,6 +101,8 @@ def _load_lib():
     lib.vg_raycast_batched.argtypes = [P, I, ctypes.POINTER(_RaysProblem), U32]
     lib.vg_mc_volume_area_nbr.argtypes = [P, I, I64, P, P, P, I, P, U32, P, P, P, P, P, P, P, P]
     lib.vg_tuple_neighbors.argtypes = [P, I, I64, I64, P, P, P, I64, ctypes.POINTER(I64)]
+    lib.vg_mc_sample_points.argtypes = [P, I, I64, P, I, P, P, I, P, P]
+    lib.vg_mc_integrals.argtypes = [P, I, I64, P, I, P, P, I, P, P, P, P, P, P]
     lib.vg_explore.argtypes = [P, I, I64, P, P, I, U32, ctypes.POINTER(P)]
     for f in ("vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts"):
         getattr(lib, f).argtypes = [P]
@@ -302,6 +306,55 @@ def tuple_neighbors(sigma, n_nodes):
     _check(_lib.vg_tuple_neighbors(c, L - 1, n_nodes, V, _ptr(sigma), _ptr(off), _ptr(nbr), cap,
                                    ctypes.byref(nnz)), c, "vg_tuple_neighbors")
     return off, nbr[:nnz.value].clone()
+
+
+@dataclass
+class MCIntegrals:
+    volume: torch.Tensor | None  # [N] integral of f over each cell (None without draws)
+    facet_j: torch.Tensor        # [N, R] facet rows, as in MCResult
+    facet: torch.Tensor          # [N, R] integral of f over each facet of the row
+    facet_count: torch.Tensor    # [N]
+
+
+def mc_integrals(nodes, dirs, res: MCResult, f, tsamp=None) -> MCIntegrals:
+    """Integrals of ``f`` over every cell and facet (Algorithm 3, Sec. 3.1),
+    from a forward result ``res`` of :func:`mc_volume_area` on the same
+    ``dirs``.  ``f`` maps a float32 GPU tensor ``[P, d]`` of points to ``[P]``
+    values; it is the integrand, called once between the library's two calls
+    (sample points, then the weighted sums).  ``tsamp`` ``[N, R, m]`` float32
+    in (0, 1) holds the draws of the inner loop (None: facet integrals
+    only)."""
+    _dev(nodes, torch.float32, "nodes")
+    dev = nodes.device
+    n, d = nodes.shape
+    _dev(dirs, torch.float32, "dirs", dev)
+    R = dirs.shape[1]
+    if dirs.shape != (n, R, d) or res.t.shape != (n, R):
+        raise ValueError("dirs must be [N, R, d] and res the forward result on them")
+    m = 0
+    if tsamp is not None:
+        _dev(tsamp, torch.float32, "tsamp", dev)
+        if tsamp.dim() != 3 or tsamp.shape[:2] != (n, R):
+            raise ValueError("tsamp must be [N, R, m]")
+        m = tsamp.shape[2]
+    points = torch.empty((n, R, m + 1, d), dtype=torch.float32, device=dev)
+    c = _ctx(dev)
+    _check(_lib.vg_mc_sample_points(c, d, n, _ptr(nodes), R, _ptr(dirs), _ptr(res.t), m, _ptr(tsamp),
+                                    _ptr(points)), c, "vg_mc_sample_points")
+    fvals = f(points.view(-1, d))
+    if not isinstance(fvals, torch.Tensor) or fvals.numel() != n * R * (m + 1):
+        raise ValueError("f must return one value per point")
+    fvals = fvals.to(device=dev, dtype=torch.float32).contiguous()
+    out = MCIntegrals(
+        volume=torch.empty(n, dtype=torch.float32, device=dev) if m > 0 else None,
+        facet_j=torch.empty((n, R), dtype=torch.int32, device=dev),
+        facet=torch.empty((n, R), dtype=torch.float32, device=dev),
+        facet_count=torch.empty(n, dtype=torch.int32, device=dev))
+    c = _ctx(dev)
+    _check(_lib.vg_mc_integrals(c, d, n, _ptr(nodes), R, _ptr(res.t), _ptr(res.idx), m, _ptr(tsamp),
+                                _ptr(fvals), _ptr(out.volume), _ptr(out.facet_j), _ptr(out.facet),
+                                _ptr(out.facet_count)), c, "vg_mc_integrals")
+    return out
 
 
 def mc_backward(nodes, dirs, res: MCResult, g_volume=None, g_energy2=None, g_facet_area=None):

@@ -450,6 +450,51 @@ int vg_mc_volume_area_nbr(vg_ctx *ctx, int d, int64_t n_nodes, const float *node
                         idx_out, status_out, volume, energy2, facet_j, facet_area, facet_count);
 }
 
+int vg_mc_sample_points(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                        const float *dirs, const float *t, int m, const float *tsamp, float *points) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (m < 0 || m > 1024) return fail(ctx, VG_EINVAL, "m=%d outside [0, 1024]", m);
+  if (!dirs || !t || !points || (m > 0 && !tsamp)) return fail(ctx, VG_EINVAL, "null array");
+  VG_HIP(ctx, launch_sample_points(nodes, n_nodes, d, rays_per_cell, dirs, t, m, tsamp, points, ctx->stream));
+  return VG_OK;
+}
+
+int vg_mc_integrals(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                    const float *t, const int32_t *idx, int m, const float *tsamp, const float *fvals,
+                    float *fint_volume, int32_t *facet_j, float *fint_facet, int32_t *facet_count) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (m < 0 || m > 1024) return fail(ctx, VG_EINVAL, "m=%d outside [0, 1024]", m);
+  if (!t || !idx || !fvals || (m > 0 && !tsamp)) return fail(ctx, VG_EINVAL, "null array");
+  const int nf = (facet_j != nullptr) + (fint_facet != nullptr) + (facet_count != nullptr);
+  if (nf != 0 && nf != 3) return fail(ctx, VG_EINVAL, "facet outputs must be all set or all NULL");
+  if (m > 0 && !fint_volume) return fail(ctx, VG_EINVAL, "fint_volume is NULL with m > 0");
+  const double S = sphere_area(d);
+  AccumArgs a{};
+  a.nodes = nodes;
+  a.n = n_nodes;
+  a.d = d;
+  a.R = rays_per_cell;
+  a.t = t;
+  a.idx = idx;
+  a.sa = (float)(S / (double)rays_per_cell);
+  a.facet_j = facet_j;
+  a.facet_count = facet_count;
+  a.m = m;
+  a.tsamp = tsamp;
+  a.fvals = fvals;
+  a.sf = m > 0 ? (float)(S / ((double)rays_per_cell * m)) : 0.f;
+  a.fint_volume = m > 0 ? fint_volume : nullptr;
+  a.fint_facet = fint_facet;
+  VG_HIP(ctx, launch_accum(a, ctx->stream));
+  return VG_OK;
+}
+
 int vg_tuple_neighbors(vg_ctx *ctx, int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sigma,
                        int64_t *offsets, int32_t *nbr, int64_t nbr_capacity, int64_t *nnz) {
   if (!ctx) return VG_EINVAL;

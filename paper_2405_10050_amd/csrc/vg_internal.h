@@ -115,11 +115,18 @@ struct AccumArgs {
   const float *t;
   const int32_t *idx;
   float sv, se, sa;  // scales S/(dn), S/((d+2)n), S/n
-  float *volume;
-  float *energy2;
-  int32_t *facet_j;
-  float *facet_area;
+  float *volume;      // or null
+  float *energy2;     // or null
+  int32_t *facet_j;   // facet rows (null: no facets)
+  float *facet_area;  // or null
   int32_t *facet_count;
+  // integrals of a function f (Algorithm 3's F_V and F), when fvals is set
+  int m;                // draws per ray for the volume integral (0: none)
+  const float *tsamp;   // [n][R][m] draws t in (0, 1)
+  const float *fvals;   // [n][R][m+1]: f at the hit point, then at the m interior points
+  float sf;             // S/(n m)
+  float *fint_volume;   // [n] or null
+  float *fint_facet;    // [n][R], aligned with facet_j, or null
 };
 
 struct BackwardArgs {
@@ -162,6 +169,10 @@ hipError_t launch_recheck_rays_batched(const RayBatchProblem *probs_dev, const u
                                        hipStream_t s);
 hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s);
 hipError_t launch_accum(const AccumArgs &a, hipStream_t s);
+// Sample points of Algorithm 3 per ray: the hit point x_i + l u, then the m
+// interior points x_i + t_s l u.  points [n][R][m+1][d].
+hipError_t launch_sample_points(const float *nodes, int64_t n, int d, int R, const float *dirs, const float *t,
+                                int m, const float *tsamp, float *points, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 

@@ -1,5 +1,6 @@
-// Monte-Carlo volume / interface-area estimators of Sec. 3.1 (Algorithm 3
-// with f = 1) and their adjoint, on top of the per-ray RayCast results.
+// Monte-Carlo volume / interface-area estimators of Sec. 3.1 (Algorithm 3),
+// the integrals of a function f over cells and facets, and the adjoint of
+// the f = 1 estimators, on top of the per-ray RayCast results.
 //
 // Forward, one workgroup per cell (its rays are contiguous):
 //   volume   = S/(d n)     sum l^d
@@ -10,7 +11,10 @@
 // cube face at distance h it is l^d / h.  This form needs no division by the
 // (possibly tiny) cosine.  Facets: the (j, ray) keys of the cell are sorted
 // in LDS (bitonic), runs of equal j are summed in ray order, so every sum has
-// a fixed order and the result is bitwise reproducible.
+// a fixed order and the result is bitwise reproducible.  Integrals of f:
+//   F_V[i]  = S/(n m) sum_k l^d sum_s f(x_i + t_s l u) t_s^{d-1}
+//   F(i, j) = S/n sum_{k: j_k = j} f(x_i + l u) * (area term of ray k)
+// with f evaluated by the caller at the points of sample_points_kernel.
 //
 // Adjoint, with the directions frozen (not in the paper):
 //   node winner j, D = x_j - x_i, t = |D|^2/(2 u.D):
@@ -98,7 +102,8 @@ __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
 #pragma unroll
   for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
 
-  float pv = 0.f, pe = 0.f;
+  float pv = 0.f, pe = 0.f, pf = 0.f;
+  const int M1 = a.m + 1;
   for (int k = tid; k < P; k += NT) {
     if (k < R) {
       const int64_t gid = cell * R + k;
@@ -107,6 +112,11 @@ __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
       const float ld = powi(l, d);
       pv += ld;
       pe += ld * l * l;
+      if (a.fvals && a.m > 0) {  // volume integral of f: sum_s f(x_i + t_s l u) t_s^{d-1} l^d
+        float g = 0.f;
+        for (int q = 0; q < a.m; ++q) g += a.fvals[gid * M1 + 1 + q] * powi(a.tsamp[gid * a.m + q], d - 1);
+        pf += g * ld;
+      }
       float wa = 0.f;
       if (j >= 0) {
         const float *xj = a.nodes + (int64_t)j * d;
@@ -136,9 +146,11 @@ __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
   }
   const float sum_v = block_sum(pv, red);
   const float sum_e = block_sum(pe, red);
+  const float sum_f = a.fint_volume ? block_sum(pf, red) : 0.f;  // uniform condition
   if (tid == 0) {
-    a.volume[cell] = a.sv * sum_v;
+    if (a.volume) a.volume[cell] = a.sv * sum_v;
     if (a.energy2) a.energy2[cell] = a.se * sum_e;
+    if (a.fint_volume) a.fint_volume[cell] = a.sf * sum_f;
   }
   if (!a.facet_j) return;
 
@@ -156,21 +168,59 @@ __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
     for (int q = 1; q <= NT; ++q) seg[q] += seg[q - 1];
   }
   __syncthreads();
-  int slot = seg[tid];
-  for (int p = p0; p < p1; ++p) {
-    if (p == 0 || (keys[p] >> 32) != (keys[p - 1] >> 32)) {
-      float s = 0.f;
-      int q = p;
-      while (q < R && (keys[q] >> 32) == (keys[p] >> 32)) {
-        s += w[(uint32_t)keys[q]];
-        ++q;
+  // run sums of the ray weights: the areas, then (weights times f at the
+  // hit point) the facet integrals of f
+  for (int pass = 0; pass < 2; ++pass) {
+    float *out = pass == 0 ? a.facet_area : a.fint_facet;
+    if (pass == 1) {
+      if (!a.fint_facet) break;
+      __syncthreads();
+      for (int k = tid; k < R; k += NT) w[k] *= a.fvals[(cell * R + k) * M1];
+      __syncthreads();
+    }
+    int slot = seg[tid];
+    for (int p = p0; p < p1; ++p) {
+      if (p == 0 || (keys[p] >> 32) != (keys[p - 1] >> 32)) {
+        float s = 0.f;
+        int q = p;
+        while (q < R && (keys[q] >> 32) == (keys[p] >> 32)) {
+          s += w[(uint32_t)keys[q]];
+          ++q;
+        }
+        if (pass == 0) a.facet_j[cell * R + slot] = key_j(keys[p]);
+        if (out) out[cell * R + slot] = a.sa * s;
+        ++slot;
       }
-      a.facet_j[cell * R + slot] = key_j(keys[p]);
-      a.facet_area[cell * R + slot] = a.sa * s;
-      ++slot;
     }
   }
   if (tid == 0) a.facet_count[cell] = seg[NT];
+}
+
+// Algorithm 3's sample points of every ray: the hit point, then the interior
+// points at the draws t_s (x_i + t_s l u, the same point as (1-t) x_i + t r).
+template <int DK>
+__global__ __launch_bounds__(NT) void sample_points_kernel(const float *__restrict__ nodes, int64_t n, int d,
+                                                           int R, const float *__restrict__ dirs,
+                                                           const float *__restrict__ t, int m,
+                                                           const float *__restrict__ tsamp,
+                                                           float *__restrict__ points) {
+  const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (gid >= n * R) return;
+  const int64_t cell = gid / R;
+  const float l = t[gid];
+  float xi[DK], u[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    xi[k] = k < d ? nodes[cell * d + k] : 0.f;
+    u[k] = k < d ? dirs[gid * d + k] : 0.f;
+  }
+  float *out = points + gid * (m + 1) * d;
+  for (int s = 0; s <= m; ++s) {
+    const float tl = s == 0 ? l : tsamp[gid * m + s - 1] * l;
+#pragma unroll
+    for (int k = 0; k < DK; ++k)
+      if (k < d) out[s * d + k] = __builtin_fmaf(tl, u[k], xi[k]);
+  }
 }
 
 // ----------------------------------------------------------------- adjoint
@@ -338,6 +388,22 @@ hipError_t launch_accum(const AccumArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(accum_kernel<12>, grid, blk, shm, s, a);
   else
     hipLaunchKernelGGL(accum_kernel<16>, grid, blk, shm, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_points(const float *nodes, int64_t n, int d, int R, const float *dirs, const float *t,
+                                int m, const float *tsamp, float *points, hipStream_t s) {
+  const int64_t rays = n * R;
+  if (rays <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((rays + NT - 1) / NT)), blk(NT);
+  if (d <= 4)
+    hipLaunchKernelGGL(sample_points_kernel<4>, grid, blk, 0, s, nodes, n, d, R, dirs, t, m, tsamp, points);
+  else if (d <= 8)
+    hipLaunchKernelGGL(sample_points_kernel<8>, grid, blk, 0, s, nodes, n, d, R, dirs, t, m, tsamp, points);
+  else if (d <= 12)
+    hipLaunchKernelGGL(sample_points_kernel<12>, grid, blk, 0, s, nodes, n, d, R, dirs, t, m, tsamp, points);
+  else
+    hipLaunchKernelGGL(sample_points_kernel<16>, grid, blk, 0, s, nodes, n, d, R, dirs, t, m, tsamp, points);
   return hipGetLastError();
 }
 

@@ -145,6 +145,23 @@ def mc_directions_device(n_cells: int, n_rays: int, d: int, seed: int, device):
     return out
 
 
+def mc_radial_draws(cells, n_rays: int, m: int, seed: int = 3) -> np.ndarray:
+    """The draws t ~ U(0, 1) of Algorithm 3's inner loop, ``m`` per ray, as
+    float32 ``[len(cells)][n_rays][m]``; the block of cell ``i`` depends on
+    ``(seed, i)`` only.  Values that round to 0 or 1 are redrawn."""
+    cells = np.asarray(cells, dtype=np.int64).ravel()
+    out = np.empty((cells.size, n_rays, m), dtype=np.float32)
+    for a, c in enumerate(cells):
+        rng = np.random.default_rng(np.random.SeedSequence([seed, int(c), 7]))
+        v = rng.random((n_rays, m)).astype(np.float32)
+        bad = (v <= 0) | (v >= 1)
+        while bad.any():
+            v[bad] = rng.random(int(bad.sum())).astype(np.float32)
+            bad = (v <= 0) | (v >= 1)
+        out[a] = v
+    return out
+
+
 def descent_draws(d: int, count: int = 64, seed: int = 2) -> np.ndarray:
     """Standard-normal float64 vectors ``[count][d]`` consumed, in order, by the
     ``Descent`` start of the exhaustive search (Algorithm 2): each step takes
