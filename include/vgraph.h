@@ -55,6 +55,8 @@ typedef enum vg_status {
 #define VG_CLIP (1u << 0)        /* clip rays to the unit cube                 */
 #define VG_PREC_BF16X3 (1u << 1) /* Monte-Carlo scan in split BF16x3 MFMA       */
 #define VG_NO_RECHECK (1u << 2)  /* skip the FP64 re-evaluation (diagnostics)  */
+#define VG_INCIRCLE (1u << 3)    /* Monte-Carlo rays by the incircle RayCast of
+                                    Algorithm 1 with a grid index (d <= 6)     */
 
 /* per-ray status bits (uint8) */
 #define VG_ST_NEAR_TIE 1  /* FP32 gap of the two best candidates below VG_TIE_EPS */
@@ -73,6 +75,7 @@ typedef struct vg_stats {
   double tie_eps;        /* relative FP32 gap that triggers the FP64 recheck    */
   int64_t scan_launches; /* candidate-scan launches timed since profiling began */
   double scan_ms;        /* their summed duration (HIP events on the stream)    */
+  int64_t nn_calls;      /* nearest-neighbour queries of the last VG_INCIRCLE call */
 } vg_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -113,9 +116,14 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
 /* Monte-Carlo rays of every cell (Algorithm 3): ray k of cell i starts at
  * x_i with eta = {i} and direction dirs[i][k], clipped to the unit cube
  * (VG_CLIP is implied).  The candidate scan is the dense contraction of the
- * directions with the nodes inverted about x_i, on MFMA.
+ * directions with the nodes inverted about x_i, on MFMA.  With VG_INCIRCLE
+ * the rays are cast instead by the incircle iteration of Algorithm 1, its
+ * nearest-neighbour queries answered by a uniform grid over the cube (built
+ * per call; nodes must lie in [0,1]^d; d <= 6, FP32 only), starting from the
+ * ray's exit point of the cube; results are the same (the certificate and
+ * the FP64 recheck are shared), and vg_stats.nn_calls counts the queries.
  *   dirs [n_nodes][rays_per_cell][d] f32 unit vectors
- *   flags VG_PREC_BF16X3, VG_NO_RECHECK
+ *   flags VG_PREC_BF16X3, VG_NO_RECHECK, VG_INCIRCLE
  * Outputs [n_nodes * rays_per_cell], cell-major: t_out, idx_out, status_out
  * (may be NULL).  1 <= rays_per_cell <= 4096. */
 int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,

@@ -34,6 +34,7 @@ LIB_PATH = os.path.join(_HERE, "libvgraph.so")
 VG_CLIP = 1 << 0
 VG_PREC_BF16X3 = 1 << 1
 VG_NO_RECHECK = 1 << 2
+VG_INCIRCLE = 1 << 3
 
 ST_NEAR_TIE = 1
 ST_RECHECKED = 2
@@ -51,7 +52,8 @@ class VGError(RuntimeError):
 class _Stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_int64), ("flagged", ctypes.c_int64),
                 ("fp64_ties", ctypes.c_int64), ("tie_eps", ctypes.c_double),
-                ("scan_launches", ctypes.c_int64), ("scan_ms", ctypes.c_double)]
+                ("scan_launches", ctypes.c_int64), ("scan_ms", ctypes.c_double),
+                ("nn_calls", ctypes.c_int64)]
 
 
 class _CellsProblem(ctypes.Structure):
@@ -161,7 +163,7 @@ def stats(device=None) -> dict:
     s = _Stats()
     _check(_lib.vg_get_stats(c, ctypes.byref(s)), c, "vg_get_stats")
     return dict(rays=s.rays, flagged=s.flagged, fp64_ties=s.fp64_ties, tie_eps=s.tie_eps,
-                scan_launches=s.scan_launches, scan_ms=s.scan_ms)
+                scan_launches=s.scan_launches, scan_ms=s.scan_ms, nn_calls=s.nn_calls)
 
 
 def set_profiling(enable: bool, device=None) -> None:
@@ -199,13 +201,14 @@ def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True):
     return t, idx, st
 
 
-def _cells_flags(precision: str, recheck: bool) -> int:
+def _cells_flags(precision: str, recheck: bool, incircle: bool = False) -> int:
     if precision not in ("fp32", "bf16x3"):
         raise ValueError("precision must be 'fp32' or 'bf16x3'")
-    return (VG_PREC_BF16X3 if precision == "bf16x3" else 0) | (0 if recheck else VG_NO_RECHECK)
+    return ((VG_PREC_BF16X3 if precision == "bf16x3" else 0) | (0 if recheck else VG_NO_RECHECK) |
+            (VG_INCIRCLE if incircle else 0))
 
 
-def raycast_cells(nodes, dirs, precision="fp32", recheck=True):
+def raycast_cells(nodes, dirs, precision="fp32", recheck=True, incircle=False):
     """Monte-Carlo rays of every cell: ``dirs`` is ``[N, R, d]``; returns
     ``(t, idx, status)`` shaped ``[N, R]``."""
     _dev(nodes, torch.float32, "nodes")
@@ -219,7 +222,7 @@ def raycast_cells(nodes, dirs, precision="fp32", recheck=True):
     idx = torch.empty((n, R), dtype=torch.int32, device=dev)
     st = torch.empty((n, R), dtype=torch.uint8, device=dev)
     c = _ctx(dev)
-    _check(_lib.vg_raycast_cells(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck),
+    _check(_lib.vg_raycast_cells(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck, incircle),
                                  _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast_cells")
     return t, idx, st
 
@@ -245,12 +248,14 @@ class MCResult:
 
 
 def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out=None,
-                   neighbors=None) -> MCResult:
+                   neighbors=None, incircle=False) -> MCResult:
     """Monte-Carlo cell volumes, second moments and interface areas
     (Sec. 3.1, Algorithm 3 with f = 1).  ``out`` may pass a previous
     ``MCResult`` of the same shape to reuse its buffers.  ``neighbors`` =
     ``(offsets [N+1] int64, nbr [nnz] int32)`` (e.g. from
-    :func:`tuple_neighbors`) restricts each cell's scan to its neighbours."""
+    :func:`tuple_neighbors`) restricts each cell's scan to its neighbours;
+    ``incircle=True`` casts the rays by Algorithm 1 with a grid index
+    (d <= 6, FP32) instead of the dense scan."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
     n, d = nodes.shape
@@ -270,7 +275,8 @@ def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out
             status=torch.empty((n, R), dtype=torch.uint8, device=dev))
     c = _ctx(dev)
     if neighbors is None:
-        _check(_lib.vg_mc_volume_area(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck),
+        _check(_lib.vg_mc_volume_area(c, d, n, _ptr(nodes), R, _ptr(dirs),
+                                      _cells_flags(precision, recheck, incircle),
                                       _ptr(out.t), _ptr(out.idx), _ptr(out.status), _ptr(out.volume),
                                       _ptr(out.energy2), _ptr(out.facet_j), _ptr(out.facet_area),
                                       _ptr(out.facet_count)), c, "vg_mc_volume_area")
@@ -281,7 +287,7 @@ def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out
     if off.shape != (n + 1,) or nbr.dim() != 1:
         raise ValueError("neighbors must be (offsets [N+1], nbr [nnz])")
     _check(_lib.vg_mc_volume_area_nbr(c, d, n, _ptr(nodes), _ptr(off), _ptr(nbr), R, _ptr(dirs),
-                                      _cells_flags(precision, recheck), _ptr(out.t), _ptr(out.idx),
+                                      _cells_flags(precision, recheck, incircle), _ptr(out.t), _ptr(out.idx),
                                       _ptr(out.status), _ptr(out.volume), _ptr(out.energy2),
                                       _ptr(out.facet_j), _ptr(out.facet_area), _ptr(out.facet_count)),
            c, "vg_mc_volume_area_nbr")

@@ -112,12 +112,17 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   const int64_t m = n * (int64_t)R;
   const bool recheck = !(flags & VG_NO_RECHECK);
   const bool bf16 = (flags & VG_PREC_BF16X3) != 0;
-  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m});
+  const bool incircle = (flags & VG_INCIRCLE) != 0;
+  if (incircle && (bf16 || nbr || d > 6))
+    return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs d <= 6, FP32 and no neighbour lists");
+  const size_t grid_bytes = incircle ? incircle_scratch_bytes(n, d) : 0;
+  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
   uint8_t *st = st_out ? st_out : cv.take<uint8_t>(m);
+  void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
 
@@ -137,7 +142,12 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   a.nbr_off = nbr_off;
   a.nbr = nbr;
   ScanTimer timer(ctx);
-  hipError_t e = bf16 ? launch_cell_scan_bf16x3(a, ctx->stream) : launch_cell_scan_fp32(a, ctx->stream);
+  hipError_t e;
+  if (incircle)
+    e = launch_incircle_cells(a, grid_scratch,
+                              reinterpret_cast<unsigned long long *>(ctx->counters + CNT_NN_CALLS), ctx->stream);
+  else
+    e = bf16 ? launch_cell_scan_bf16x3(a, ctx->stream) : launch_cell_scan_fp32(a, ctx->stream);
   timer.stop();
   if (e != hipSuccess) return hip_fail(ctx, e, "cell scan launch");
   if (recheck) {
@@ -279,6 +289,7 @@ int vg_get_stats(vg_ctx *ctx, vg_stats *out) {
   VG_HIP(ctx, hipMemcpy(c, ctx->last_counters ? ctx->last_counters : ctx->counters, sizeof c,
                         hipMemcpyDeviceToHost));
   out->rays = ctx->last_rays;
+  out->nn_calls = (int64_t)((uint64_t)c[CNT_NN_CALLS] | ((uint64_t)c[CNT_NN_CALLS + 1] << 32));
   out->flagged = c[CNT_FLAGGED];
   out->fp64_ties = c[CNT_FP64_TIE];
   out->tie_eps = ctx->last_tau;

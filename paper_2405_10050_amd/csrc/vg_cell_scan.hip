@@ -124,25 +124,6 @@ __device__ __forceinline__ int64_t row_node(const CellScanArgs &a, int64_t nb0, 
   return (j >= 0 && j < a.n) ? j : a.n;
 }
 
-// Re-evaluate t for MC ray (origin x_i) hitting node x_j.
-template <int DK>
-__device__ float reeval_cell(const float (&xi)[DK], const float *__restrict__ xj,
-                             const float (&u)[DK], int d) {
-  dfacc num, den;
-#pragma unroll
-  for (int k = 0; k < DK; ++k) {
-    if (k < d) {
-      float h, l;
-      two_sum(xj[k], -xi[k], h, l);  // x_j - x_i exactly as h + l
-      num.add_prod(h, h);
-      num.add_small(2.f * h * l);
-      den.add_prod(u[k], h);
-      den.add_small(u[k] * l);
-    }
-  }
-  return df_half_ratio(num, den);
-}
-
 // Merge the two lanes of each ray, add the cube faces, certify the gap,
 // re-evaluate t* and write the ray results.
 template <int C, int DK, int NT>

@@ -57,4 +57,25 @@ __device__ __forceinline__ float df_half_ratio(const dfacc &num, const dfacc &de
   return 0.5f * (q + (r + nl - q * dl) / dh);
 }
 
+// t of eq. (t) for a Monte-Carlo ray (origin x_i, direction u) ending on
+// the bisector of x_i and node x_j, t = |x_j - x_i|^2 / (2 u.(x_j - x_i)),
+// in double-float: x_j - x_i is formed exactly as h + l (TwoSum).
+template <int DK>
+__device__ float reeval_cell(const float (&xi)[DK], const float *__restrict__ xj,
+                             const float (&u)[DK], int d) {
+  dfacc num, den;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    if (k < d) {
+      float h, l;
+      two_sum(xj[k], -xi[k], h, l);  // x_j - x_i exactly as h + l
+      num.add_prod(h, h);
+      num.add_small(2.f * h * l);
+      den.add_prod(u[k], h);
+      den.add_small(u[k] * l);
+    }
+  }
+  return df_half_ratio(num, den);
+}
+
 }  // namespace vg

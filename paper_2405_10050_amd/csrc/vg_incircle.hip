@@ -1,0 +1,362 @@
+// The incircle RayCast of Algorithm 1 for the Monte-Carlo rays of every cell
+// (eta = {i}, origin x_i, clipped to the unit cube), with a uniform-grid
+// nearest-neighbour index: a sublinear alternative to the dense scan when N
+// is large and d small.
+//
+// Index: G^d cells over [0,1]^d (about two nodes per cell), nodes sorted by
+// cell (counting sort), their coordinates stored in cell order.
+//
+// nn(q): the nearest node to q whose `skip` predicate of Algorithm 1 is false
+// (u.x_k > u.x_i: the half-space ahead of the ray), with the second nearest.
+// Cells are visited in Chebyshev rings around q's cell; a node in ring rho
+// differs from q by at least (rho - 1) h in one coordinate (h = 1/G), also
+// when q lies outside the grid, so the search stops once ((rho - 1) h)^2
+// exceeds the second-best squared distance.
+//
+// RayCast: Algorithm 1 needs a starting candidate, and its InitialHeuristic
+// is undefined for |eta| = 1.  The ray's exit point from the cube is used
+// instead: if no eligible node is nearer to it than x_i, the exit point lies
+// in cell i and the cube face is the result.  Otherwise nn returned a node k
+// with t_k below the exit, and the loop of Algorithm 1 runs from there:
+// t = |x_k - x_i|^2 / (2 u.(x_k - x_i)) (eq. (t) with r = x_i), candidate
+// r' = x_i + t u, j = nn(r'); j = k ends it.  Every candidate has t below the
+// exit, so it lies inside the cube, where the grid query is cheap.
+//
+// Certificate: at the final candidate, the gap between the squared distances
+// of the nearest and second-nearest eligible node (the face test: between
+// the nearest eligible node and x_i) equals 2 u.(x_k - x_i)(t_k - t*) for the
+// runner-up k, so a gap above the FP32 error of the distances certifies the
+// result.  Other rays (and iteration caps, nearly grazing winners) are
+// queued for the FP64 recheck over all nodes.
+#include <hipcub/hipcub.hpp>
+
+#include "vg_dfloat.h"
+#include "vg_internal.h"
+
+namespace vg {
+namespace {
+
+constexpr int NT = 256;
+constexpr int kMaxIter = 64;
+
+__global__ void grid_count_kernel(const float *__restrict__ X, int64_t n, int d, int G,
+                                  int32_t *__restrict__ cell_of, uint32_t *__restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  int64_t c = 0;
+  for (int k = 0; k < d; ++k) {
+    int q = (int)floorf(X[i * d + k] * (float)G);
+    q = q < 0 ? 0 : (q >= G ? G - 1 : q);
+    c = c * G + q;
+  }
+  cell_of[i] = (int32_t)c;
+  atomicAdd(&counts[c + 1], 1u);
+}
+
+// Scatter every node into its cell's range (order within a cell is
+// arbitrary; the nearest-neighbour query breaks distance ties by index).
+__global__ void grid_fill_kernel(const float *__restrict__ X, int64_t n, int d, const int32_t *__restrict__ cell_of,
+                                 const uint32_t *__restrict__ start, uint32_t *__restrict__ cursor,
+                                 float *__restrict__ Xs, int32_t *__restrict__ ids) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = cell_of[i];
+  const uint32_t p = start[c] + atomicAdd(&cursor[c], 1u);
+  ids[p] = (int32_t)i;
+  for (int k = 0; k < d; ++k) Xs[(int64_t)p * d + k] = X[i * d + k];
+}
+
+// Bound on the FP32 error of a difference da - db of squared distances from
+// a computed point q to two nodes, where q lies within delta of the exact
+// point (candidate t with FP32 relative error (2d+4) 2^-24, coordinates
+// rounded): the evaluation errors (d+2) 2^-24 (da + db), plus the shift of
+// q, which moves the difference by at most 2 delta (sqrt(da) + sqrt(db));
+// times 4 for safety.
+__device__ __forceinline__ float gap_tol(float da, float db, float t, int d) {
+  const float delta = ((float)(2 * d + 4) * t + sqrtf((float)d)) * 0x1p-24f;
+  return 4.f * (2.f * delta * (sqrtf(da) + sqrtf(db)) + (float)(d + 2) * 0x1p-24f * (da + db));
+}
+
+struct GridView {
+  const float *X;         // [n][d] nodes in cell order
+  const int32_t *id;      // [n] node index of each sorted slot
+  const uint32_t *start;  // [G^d + 1]
+  int G;
+  float h;
+};
+
+// Top-2 nearest eligible nodes of q (squared distances).  A node whose
+// squared distance exceeds ref + gap_tol(ref, .) with ref = min(d1, limit)
+// cannot change the caller's decision or its certificate, so the ring search
+// stops once every unvisited node is that far (or beyond d2).  t is the
+// candidate's ray parameter (for gap_tol).
+template <int DK>
+__device__ void nn2(const GridView &g, int d, const float (&q)[DK], const float (&u)[DK], float ui,
+                    int32_t self, float limit, float t, int32_t &i1, float &d1, float &d2) {
+  int c[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    int v = k < d ? (int)floorf(q[k] * (float)g.G) : 0;
+    c[k] = v < 0 ? 0 : (v >= g.G ? g.G - 1 : v);
+  }
+  i1 = -1;
+  d1 = d2 = __builtin_inff();
+  for (int rho = 0; rho < g.G; ++rho) {
+    if (rho >= 1) {
+      const float lb = (float)(rho - 1) * g.h;
+      const float lb2 = lb * lb;
+      const float ref = fminf(d1, limit);
+      if (lb2 > d2 || lb2 > ref + gap_tol(ref, lb2, t, d)) break;
+    }
+    // offsets o in [-rho, rho]^d with max |o_k| = rho, as a mixed-radix counter
+    const int span = 2 * rho + 1;
+    int o[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) o[k] = -rho;
+    for (;;) {
+      bool on_ring = false, inside = true;
+      int64_t cell = 0;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        if (k < d) {
+          const int ck = c[k] + o[k];
+          on_ring |= (o[k] == rho || o[k] == -rho);
+          inside &= (ck >= 0 && ck < g.G);
+          cell = cell * g.G + ck;
+        }
+      }
+      if (on_ring && inside) {
+        for (uint32_t p = g.start[cell]; p < g.start[cell + 1]; ++p) {
+          const int32_t node = g.id[p];
+          if (node == self) continue;
+          const float *xp = g.X + (int64_t)p * d;
+          float ux = 0.f, dist = 0.f;
+#pragma unroll
+          for (int k = 0; k < DK; ++k) {
+            if (k < d) {
+              ux = __builtin_fmaf(u[k], xp[k], ux);
+              const float e = q[k] - xp[k];
+              dist = __builtin_fmaf(e, e, dist);
+            }
+          }
+          if (!(ux > ui)) continue;  // skip: not ahead of the ray
+          if (dist < d1 || (dist == d1 && node < i1)) {
+            d2 = d1;
+            d1 = dist;
+            i1 = node;
+          } else if (dist < d2) {
+            d2 = dist;
+          }
+        }
+      }
+      // next offset
+      int k = d - 1;
+      while (k >= 0) {
+        if (++o[k] <= rho) break;
+        o[k] = -rho;
+        --k;
+      }
+      if (k < 0 || span == 1) break;
+    }
+  }
+}
+
+template <int DK>
+__global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, GridView g, unsigned long long *nn_calls) {
+  __shared__ unsigned int block_calls;
+  if (threadIdx.x == 0) block_calls = 0;
+  __syncthreads();
+  const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int d = a.d, R = a.R;
+  if (gid < a.n * R) {
+    const int64_t cell = gid / R;
+    float xi[DK], u[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      xi[k] = k < d ? a.nodes[cell * d + k] : 0.f;
+      u[k] = k < d ? a.dirs[gid * d + k] : 0.f;
+    }
+    float ui = 0.f;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) ui = __builtin_fmaf(u[k], xi[k], ui);
+    // exit through the cube
+    float tbox = __builtin_inff();
+    int face = -1;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d && u[k] != 0.f) {
+        const float hk = u[k] > 0.f ? 1.f - xi[k] : xi[k];
+        const float tk = hk / fabsf(u[k]);
+        if (tk < tbox) {
+          tbox = tk;
+          face = 2 * k + (u[k] > 0.f ? 1 : 0);
+        }
+      }
+    }
+    uint32_t calls = 0;
+    bool flag = false;
+    uint8_t st = 0;
+    int32_t j = -1;
+    float t = tbox;
+    float q[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) q[k] = __builtin_fmaf(tbox, u[k], xi[k]);
+    float di = 0.f;  // squared distance of x_i to the exit point
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      const float e = q[k] - xi[k];
+      di = __builtin_fmaf(e, e, di);
+    }
+    int32_t i1;
+    float d1, d2;
+    nn2<DK>(g, d, q, u, ui, (int32_t)cell, di, tbox, i1, d1, d2);
+    ++calls;
+    if (face < 0) {
+      flag = true;  // zero direction
+    } else if (i1 < 0 || d1 > di) {
+      j = -2 - face;  // the exit point lies in cell i
+      if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, tbox, d))) flag = true;
+    } else {
+      int32_t k = i1;
+      int it = 0;
+      for (; it < kMaxIter; ++it) {
+        const float *xk = a.nodes + (int64_t)k * d;
+        float num = 0.f, den = 0.f;
+#pragma unroll
+        for (int q2 = 0; q2 < DK; ++q2) {
+          if (q2 < d) {
+            const float e = xk[q2] - xi[q2];
+            num = __builtin_fmaf(e, e, num);
+            den = __builtin_fmaf(u[q2], e, den);
+          }
+        }
+        t = num / (2.f * den);
+#pragma unroll
+        for (int q2 = 0; q2 < DK; ++q2) q[q2] = __builtin_fmaf(t, u[q2], xi[q2]);
+        float dk = 0.f;  // the candidate's own node: nothing farther matters
+#pragma unroll
+        for (int q2 = 0; q2 < DK; ++q2) {
+          if (q2 < d) {
+            const float e = q[q2] - xk[q2];
+            dk = __builtin_fmaf(e, e, dk);
+          }
+        }
+        nn2<DK>(g, d, q, u, ui, (int32_t)cell, dk, t, i1, d1, d2);
+        ++calls;
+        if (i1 == k) break;
+        if (i1 < 0) break;  // cannot happen: k itself is eligible
+        k = i1;
+      }
+      j = k;
+      if (it == kMaxIter || i1 != k) {
+        flag = true;
+        st |= VG_ST_SUSPECT;
+      }
+      if (d2 < __builtin_inff() && !(d2 - d1 > gap_tol(d2, d1, t, d))) flag = true;  // runner-up within rounding
+      // a nearly grazing winner: its eligibility may hinge on rounding
+      float den = 0.f, nrm = 0.f;
+      const float *xj = a.nodes + (int64_t)j * d;
+#pragma unroll
+      for (int q2 = 0; q2 < DK; ++q2) {
+        if (q2 < d) {
+          const float e = xj[q2] - xi[q2];
+          den = __builtin_fmaf(u[q2], e, den);
+          nrm = __builtin_fmaf(e, e, nrm);
+        }
+      }
+      if (!(den > (1.f / 4096.f) * sqrtf(nrm))) {
+        flag = true;
+        st |= VG_ST_SUSPECT;
+      }
+      t = reeval_cell<DK>(xi, xj, u, d);
+      if (!(t <= tbox)) {  // the face is nearer after all: settle it in FP64
+        flag = true;
+      }
+    }
+    if (j <= -2) t = tbox;
+    if (flag && a.flag_list) {
+      st |= VG_ST_NEAR_TIE;
+      const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
+      a.flag_list[pos] = gid | a.flag_tag;
+    }
+    a.t_out[gid] = t;
+    a.idx_out[gid] = j;
+    a.st_out[gid] = st;
+    atomicAdd(&block_calls, calls);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && nn_calls) atomicAdd(nn_calls, (unsigned long long)block_calls);
+}
+
+unsigned blocks_of(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+}  // namespace
+
+static int incircle_grid_size(int64_t n, int d) {
+  // about two nodes per cell, at most 2^22 cells
+  int G = (int)std::floor(std::pow((double)n / 2.0, 1.0 / d));
+  G = std::max(G, 1);
+  while (G > 1 && std::pow((double)G, d) > 4194304.0) --G;
+  return G;
+}
+
+size_t incircle_scratch_bytes(int64_t n, int d) {
+  const int G = incircle_grid_size(n, d);
+  int64_t cells = 1;
+  for (int k = 0; k < d; ++k) cells *= G;
+  size_t tmp = 0;
+  (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                          (int)(cells + 1));
+  // cell_of, ids [n] i32; Xs [n][d] f32; counts, start, cursor [cells + 1]; scan temp
+  return (size_t)n * 8 + (size_t)n * d * 4 + 3 * (size_t)(cells + 1) * 4 + tmp + 6 * 256;
+}
+
+hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
+                                 hipStream_t s) {
+  const int64_t n = a.n;
+  const int d = a.d;
+  const int G = incircle_grid_size(n, d);
+  int64_t cells = 1;
+  for (int k = 0; k < d; ++k) cells *= G;
+  auto carve = [&](size_t bytes) {
+    char *p = static_cast<char *>(scratch);
+    scratch = p + ((bytes + 255) & ~size_t(255));
+    return p;
+  };
+  int32_t *cell_of = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
+  int32_t *ids = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
+  float *Xs = reinterpret_cast<float *>(carve((size_t)n * d * 4));
+  uint32_t *counts = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
+  uint32_t *start = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
+  uint32_t *cursor = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
+  size_t tmp = 0;
+  hipError_t e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp, counts, start, (int)(cells + 1), s);
+  if (e != hipSuccess) return e;
+  void *tmpp = carve(tmp);
+  e = fill_u32(counts, 0u, cells + 1, s);
+  if (e == hipSuccess) e = fill_u32(cursor, 0u, cells + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grid_count_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, a.nodes, n, d, G, cell_of, counts);
+  // counts[0] = 0 and counts[c + 1] = size of cell c, so the inclusive scan
+  // gives start[c] = nodes in cells before c (start[cells] = n)
+  e = hipcub::DeviceScan::InclusiveSum(tmpp, tmp, counts, start, (int)(cells + 1), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grid_fill_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, a.nodes, n, d, cell_of, start,
+                     cursor, Xs, ids);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const GridView g{Xs, ids, start, G, 1.f / (float)G};
+  const int64_t rays = n * a.R;
+  const dim3 grid(blocks_of(rays)), blk(NT);
+  if (d <= 2)
+    hipLaunchKernelGGL(incircle_cells_kernel<2>, grid, blk, 0, s, a, g, nn_calls);
+  else if (d <= 3)
+    hipLaunchKernelGGL(incircle_cells_kernel<3>, grid, blk, 0, s, a, g, nn_calls);
+  else if (d <= 4)
+    hipLaunchKernelGGL(incircle_cells_kernel<4>, grid, blk, 0, s, a, g, nn_calls);
+  else
+    hipLaunchKernelGGL(incircle_cells_kernel<6>, grid, blk, 0, s, a, g, nn_calls);
+  return hipGetLastError();
+}
+
+}  // namespace vg

@@ -16,7 +16,8 @@ namespace vg {
 enum : int {
   CNT_FLAGGED = 0,   // rays appended to the FP64 recheck list
   CNT_FP64_TIE = 1,  // rays whose FP64 gap is below 1e-9
-  CNT_WORDS = 4
+  CNT_NN_CALLS = 4,  // u64 (words 4, 5): nearest-neighbour queries of the incircle RayCast
+  CNT_WORDS = 6
 };
 
 // Where the recheck kernel finds a ray.
@@ -158,6 +159,13 @@ hipError_t launch_cell_scan_bf16x3(const CellScanArgs &a, hipStream_t s);
 int tuple_neighbors(int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sigma,
                     int64_t *offsets, int32_t *nbr, int64_t nbr_capacity, int64_t *nnz_out,
                     hipStream_t s, std::string &err);
+
+// Incircle RayCast (Algorithm 1) of the Monte-Carlo rays with a grid index
+// (vg_incircle.hip): scratch of incircle_scratch_bytes(n, d), nn-call count
+// added to *nn_calls.
+size_t incircle_scratch_bytes(int64_t n, int d);
+hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
+                                 hipStream_t s);
 
 hipError_t launch_ray_scan(const RayScanArgs &a, hipStream_t s);
 constexpr int kRayTile = 256;  // rays per workgroup (and per batched item) of the ray scan
