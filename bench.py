@@ -231,6 +231,49 @@ def bench_nbr(args):
     }
 
 
+def bench_incircle(args):
+    """Monte-Carlo estimators with the rays cast by the incircle RayCast of
+    Algorithm 1 over a uniform-grid index (low dimension, large N): uniform
+    d=3 N=1 000 000 with 64 rays per cell, or d=4 N=50 000 with 512.  A step
+    is the estimators' forward pass (volumes, second moments, facet areas).
+    The same step with the dense scan over all nodes is timed once beside it."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    d, n, R = (3, 1_000_000, 64) if args.workload == "incircle_d3_n1000000" else (4, 50_000, 512)
+    dev = torch.device("cuda", 0)
+    X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).to(dev)
+    D = W.mc_directions_device(n, R, d, seed=1, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    res = vg.mc_volume_area(X, D, incircle=True)
+    step = lambda: vg.mc_volume_area(X, D, incircle=True, out=res)  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    ms = _timed(stream, step, args.steps)
+    st = vg.stats()
+    print(f"[bench] incircle: {ms:.1f} ms/step, dense scan next", file=sys.stderr, flush=True)
+    full = vg.mc_volume_area(X, D)
+    ms_full = _timed(stream, lambda: vg.mc_volume_area(X, D, out=full), 1)
+    agree = float((res.idx == full.idx).float().mean().item())
+    vol_rel = float(((res.volume - full.volume).abs() / full.volume).max().item())
+    rays = n * R
+    return {
+        "metric": f"MC rays/s, incircle RayCast with a grid index (d={d}, N={n}, {R} rays/cell)",
+        "value": rays / (ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"uniform d={d} N={n}, {R} MC rays per cell, volumes + second "
+                               "moments + facet areas",
+                   "rays": rays, "nn_calls_per_ray": st["nn_calls"] / rays,
+                   "flagged_rays_per_step": st["flagged"],
+                   "dense_scan_ms_per_step": ms_full, "speedup_vs_dense_scan": ms_full / ms,
+                   "argmin_agreement_with_dense_scan": agree,
+                   "max_rel_volume_diff_vs_dense_scan": vol_rel},
+    }
+
+
 def bench_explore(args):
     """Exhaustive vertex search (Algorithm 2) of a uniform cloud."""
     import torch
@@ -266,7 +309,7 @@ def main():
     ap.add_argument("--workload", default="gmm8_d10_n100000",
                     choices=["gmm8_d10_n100000", "uneven64", "uniform_d4_n50000",
                              "uniform_d2_n1000", "uniform_d6_n10000", "nbr_d4_n50000",
-                             "nbr_d6_n10000"])
+                             "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -292,7 +335,8 @@ def main():
     if args.workload != "gmm8_d10_n100000":
         other = {"uneven64": bench_uneven, "uniform_d4_n50000": bench_grad,
                  "uniform_d2_n1000": bench_explore, "uniform_d6_n10000": bench_explore,
-                 "nbr_d4_n50000": bench_nbr, "nbr_d6_n10000": bench_nbr}
+                 "nbr_d4_n50000": bench_nbr, "nbr_d6_n10000": bench_nbr,
+                 "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 

@@ -13,14 +13,18 @@
 // when q lies outside the grid, so the search stops once ((rho - 1) h)^2
 // exceeds the second-best squared distance.
 //
-// RayCast: Algorithm 1 needs a starting candidate, and its InitialHeuristic
-// is undefined for |eta| = 1.  The ray's exit point from the cube is used
+// RayCast: Algorithm 1 needs a first generator candidate, and its
+// InitialHeuristic is undefined for |eta| = 1.  Any eligible node k gives an
+// upper bound t_k = |x_k - x_i|^2 / (2 u.(x_k - x_i)) on the result (eq. (t)
+// with r = x_i), so the first candidate is the best of the cell's K nearest
+// nodes (one search per cell, shared by its R rays): usually the winner
+// itself, so one nn call confirms it.  From there the loop of Algorithm 1
+// runs: candidate r' = x_i + t u, j = nn(r'); j = k ends it.  When no listed
+// node crosses the ray before the cube, the ray's exit point is tested
 // instead: if no eligible node is nearer to it than x_i, the exit point lies
-// in cell i and the cube face is the result.  Otherwise nn returned a node k
-// with t_k below the exit, and the loop of Algorithm 1 runs from there:
-// t = |x_k - x_i|^2 / (2 u.(x_k - x_i)) (eq. (t) with r = x_i), candidate
-// r' = x_i + t u, j = nn(r'); j = k ends it.  Every candidate has t below the
-// exit, so it lies inside the cube, where the grid query is cheap.
+// in cell i and the cube face is the result; otherwise the loop starts from
+// the node nn returned.  Every candidate has t below the exit, so it lies
+// inside the cube, where the grid query is cheap.
 //
 // Certificate: at the final candidate, the gap between the squared distances
 // of the nearest and second-nearest eligible node (the face test: between
@@ -38,6 +42,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int kMaxIter = 64;
+constexpr int kMaxKnn = 32;  // largest list of nearest nodes kept per cell
 
 __global__ void grid_count_kernel(const float *__restrict__ X, int64_t n, int d, int G,
                                   int32_t *__restrict__ cell_of, uint32_t *__restrict__ counts) {
@@ -161,8 +166,103 @@ __device__ void nn2(const GridView &g, int d, const float (&q)[DK], const float 
   }
 }
 
+// Nearest nodes kept per cell for the first candidate.
 template <int DK>
-__global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, GridView g, unsigned long long *nn_calls) {
+constexpr int knn_of() {
+  return DK <= 2 ? 8 : (DK <= 3 ? 16 : (DK <= 4 ? 24 : 32));
+}
+
+// The KN nearest nodes of every node (excluding itself), nearest first, -1
+// past the end when n <= KN: ring search stopping once ((rho - 1) h)^2
+// exceeds the KN-th squared distance; the list is kept sorted by a fully
+// unrolled insertion so it stays in registers.
+template <int DK>
+__global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes, int64_t n, int d, GridView g,
+                                                 int32_t *__restrict__ knn) {
+  constexpr int KN = knn_of<DK>();
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  float x[DK];
+  int c[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    x[k] = k < d ? nodes[i * d + k] : 0.f;
+    int v = k < d ? (int)floorf(x[k] * (float)g.G) : 0;
+    c[k] = v < 0 ? 0 : (v >= g.G ? g.G - 1 : v);
+  }
+  float dl[KN];
+  int32_t il[KN];
+#pragma unroll
+  for (int s = 0; s < KN; ++s) {
+    dl[s] = __builtin_inff();
+    il[s] = -1;
+  }
+  for (int rho = 0; rho < g.G; ++rho) {
+    if (rho >= 1) {
+      const float lb = (float)(rho - 1) * g.h;
+      if (lb * lb > dl[KN - 1]) break;
+    }
+    const int span = 2 * rho + 1;
+    int o[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) o[k] = -rho;
+    for (;;) {
+      bool on_ring = false, inside = true;
+      int64_t cell = 0;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        if (k < d) {
+          const int ck = c[k] + o[k];
+          on_ring |= (o[k] == rho || o[k] == -rho);
+          inside &= (ck >= 0 && ck < g.G);
+          cell = cell * g.G + ck;
+        }
+      }
+      if (on_ring && inside) {
+        for (uint32_t p = g.start[cell]; p < g.start[cell + 1]; ++p) {
+          int32_t node = g.id[p];
+          if (node == (int32_t)i) continue;
+          const float *xp = g.X + (int64_t)p * d;
+          float dist = 0.f;
+#pragma unroll
+          for (int k = 0; k < DK; ++k) {
+            if (k < d) {
+              const float e = x[k] - xp[k];
+              dist = __builtin_fmaf(e, e, dist);
+            }
+          }
+          if (dist < dl[KN - 1]) {
+#pragma unroll
+            for (int s = 0; s < KN; ++s) {
+              if (dist < dl[s]) {
+                const float td = dl[s];
+                const int32_t ti = il[s];
+                dl[s] = dist;
+                il[s] = node;
+                dist = td;
+                node = ti;
+              }
+            }
+          }
+        }
+      }
+      int k = d - 1;
+      while (k >= 0) {
+        if (++o[k] <= rho) break;
+        o[k] = -rho;
+        --k;
+      }
+      if (k < 0 || span == 1) break;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < KN; ++s) knn[i * KN + s] = il[s];
+}
+
+template <int DK>
+__global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, GridView g, const int32_t *__restrict__ knn,
+                                                            unsigned long long *nn_calls) {
+  constexpr int KN = knn_of<DK>();
   __shared__ unsigned int block_calls;
   if (threadIdx.x == 0) block_calls = 0;
   __syncthreads();
@@ -193,31 +293,67 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
         }
       }
     }
+    // first candidate: the eligible listed node with the smallest t_k
+    // (grazing nodes are left out; their t_k is large anyway)
+    int32_t kseed = -1;
+    {
+      float tbest = tbox;
+      const int32_t *lst = knn + cell * KN;
+#pragma unroll
+      for (int s = 0; s < KN; ++s) {
+        const int32_t k = lst[s];
+        if (k >= 0) {
+          const float *xk = a.nodes + (int64_t)k * d;
+          float num = 0.f, den = 0.f;
+#pragma unroll
+          for (int q2 = 0; q2 < DK; ++q2) {
+            if (q2 < d) {
+              const float e = xk[q2] - xi[q2];
+              num = __builtin_fmaf(e, e, num);
+              den = __builtin_fmaf(u[q2], e, den);
+            }
+          }
+          if (den > (1.f / 4096.f) * sqrtf(num)) {
+            const float tk = num / (2.f * den);
+            if (tk < tbest) {
+              tbest = tk;
+              kseed = k;
+            }
+          }
+        }
+      }
+    }
     uint32_t calls = 0;
     bool flag = false;
     uint8_t st = 0;
     int32_t j = -1;
     float t = tbox;
     float q[DK];
-#pragma unroll
-    for (int k = 0; k < DK; ++k) q[k] = __builtin_fmaf(tbox, u[k], xi[k]);
-    float di = 0.f;  // squared distance of x_i to the exit point
-#pragma unroll
-    for (int k = 0; k < DK; ++k) {
-      const float e = q[k] - xi[k];
-      di = __builtin_fmaf(e, e, di);
-    }
-    int32_t i1;
-    float d1, d2;
-    nn2<DK>(g, d, q, u, ui, (int32_t)cell, di, tbox, i1, d1, d2);
-    ++calls;
+    int32_t i1 = -1;
+    float d1 = __builtin_inff(), d2 = __builtin_inff();
+    int32_t k = kseed;
     if (face < 0) {
       flag = true;  // zero direction
-    } else if (i1 < 0 || d1 > di) {
-      j = -2 - face;  // the exit point lies in cell i
-      if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, tbox, d))) flag = true;
-    } else {
-      int32_t k = i1;
+      k = -1;
+    } else if (k < 0) {
+#pragma unroll
+      for (int q2 = 0; q2 < DK; ++q2) q[q2] = __builtin_fmaf(tbox, u[q2], xi[q2]);
+      float di = 0.f;  // squared distance of x_i to the exit point
+#pragma unroll
+      for (int q2 = 0; q2 < DK; ++q2) {
+        const float e = q[q2] - xi[q2];
+        di = __builtin_fmaf(e, e, di);
+      }
+      nn2<DK>(g, d, q, u, ui, (int32_t)cell, di, tbox, i1, d1, d2);
+      ++calls;
+      if (i1 < 0 || d1 > di) {
+        j = -2 - face;  // the exit point lies in cell i
+        if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, tbox, d))) flag = true;
+      } else {
+        k = i1;
+      }
+    }
+    if (k >= 0) {
       int it = 0;
       for (; it < kMaxIter; ++it) {
         const float *xk = a.nodes + (int64_t)k * d;
@@ -307,8 +443,10 @@ size_t incircle_scratch_bytes(int64_t n, int d) {
   size_t tmp = 0;
   (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                           (int)(cells + 1));
-  // cell_of, ids [n] i32; Xs [n][d] f32; counts, start, cursor [cells + 1]; scan temp
-  return (size_t)n * 8 + (size_t)n * d * 4 + 3 * (size_t)(cells + 1) * 4 + tmp + 6 * 256;
+  // cell_of, ids [n] i32; Xs [n][d] f32; knn [n][<= kMaxKnn] i32;
+  // counts, start, cursor [cells + 1]; scan temp
+  return (size_t)n * 8 + (size_t)n * d * 4 + (size_t)n * kMaxKnn * 4 + 3 * (size_t)(cells + 1) * 4 + tmp +
+         7 * 256;
 }
 
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
@@ -326,6 +464,7 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   int32_t *cell_of = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
   int32_t *ids = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
   float *Xs = reinterpret_cast<float *>(carve((size_t)n * d * 4));
+  int32_t *knn = reinterpret_cast<int32_t *>(carve((size_t)n * kMaxKnn * 4));
   uint32_t *counts = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
   uint32_t *start = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
   uint32_t *cursor = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
@@ -348,14 +487,19 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   const GridView g{Xs, ids, start, G, 1.f / (float)G};
   const int64_t rays = n * a.R;
   const dim3 grid(blocks_of(rays)), blk(NT);
-  if (d <= 2)
-    hipLaunchKernelGGL(incircle_cells_kernel<2>, grid, blk, 0, s, a, g, nn_calls);
-  else if (d <= 3)
-    hipLaunchKernelGGL(incircle_cells_kernel<3>, grid, blk, 0, s, a, g, nn_calls);
-  else if (d <= 4)
-    hipLaunchKernelGGL(incircle_cells_kernel<4>, grid, blk, 0, s, a, g, nn_calls);
-  else
-    hipLaunchKernelGGL(incircle_cells_kernel<6>, grid, blk, 0, s, a, g, nn_calls);
+#define VG_INCIRCLE_LAUNCH(DKV)                                                                          \
+  hipLaunchKernelGGL(knn_kernel<DKV>, dim3(blocks_of(n)), blk, 0, s, a.nodes, n, d, g, knn);            \
+  hipLaunchKernelGGL(incircle_cells_kernel<DKV>, grid, blk, 0, s, a, g, knn, nn_calls)
+  if (d <= 2) {
+    VG_INCIRCLE_LAUNCH(2);
+  } else if (d <= 3) {
+    VG_INCIRCLE_LAUNCH(3);
+  } else if (d <= 4) {
+    VG_INCIRCLE_LAUNCH(4);
+  } else {
+    VG_INCIRCLE_LAUNCH(6);
+  }
+#undef VG_INCIRCLE_LAUNCH
   return hipGetLastError();
 }
 

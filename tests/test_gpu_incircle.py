@@ -41,7 +41,9 @@ def test_incircle_matches_oracle_and_dense_scan(vg, d, n, R):
     assert rel.max(initial=0.0) <= 1e-6
     per_ray = s["nn_calls"] / (n * R)
     print(f"  nn calls per ray {per_ray:.2f}, flagged {s['flagged']}", flush=True)
-    assert 1.0 <= per_ray <= 20.0
+    # the first candidate (best of the cell's nearest nodes) is usually the
+    # winner, so about one query confirms it
+    assert 1.0 <= per_ray <= 1.5
 
 
 def test_incircle_estimators_match_oracle(vg):
