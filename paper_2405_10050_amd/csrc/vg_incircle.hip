@@ -7,7 +7,9 @@
 // cell (counting sort), their coordinates stored in cell order.
 //
 // nn(q): the nearest node to q whose `skip` predicate of Algorithm 1 is false
-// (u.x_k > u.x_i: the half-space ahead of the ray), with the second nearest.
+// (u.(x_k - x_i) > 0: the half-space ahead of the ray), with the second
+// nearest.  Distances are taken from coordinates relative to x_i, so their
+// rounding scales with the cell rather than with the cube.
 // Cells are visited in Chebyshev rings around q's cell; a node in ring rho
 // differs from q by at least (rho - 1) h in one coordinate (h = 1/G), also
 // when q lies outside the grid, so the search stops once ((rho - 1) h)^2
@@ -71,16 +73,25 @@ __global__ void grid_fill_kernel(const float *__restrict__ X, int64_t n, int d, 
   for (int k = 0; k < d; ++k) Xs[(int64_t)p * d + k] = X[i * d + k];
 }
 
-// Bound on the FP32 error of a difference da - db of squared distances from
-// a computed point q to two nodes, where q lies within delta of the exact
-// point (candidate t with FP32 relative error (2d+4) 2^-24, coordinates
-// rounded): the evaluation errors (d+2) 2^-24 (da + db), plus the shift of
-// q, which moves the difference by at most 2 delta (sqrt(da) + sqrt(db));
-// times 4 for safety.
-__device__ __forceinline__ float gap_tol(float da, float db, float t, int d) {
-  const float delta = ((float)(2 * d + 4) * t + sqrtf((float)d)) * 0x1p-24f;
-  return 4.f * (2.f * delta * (sqrtf(da) + sqrtf(db)) + (float)(d + 2) * 0x1p-24f * (da + db));
+// Error bound of a difference da - db of squared distances from a computed
+// candidate q = x_i + t u to two nodes a, b, each distance evaluated from
+// coordinates relative to x_i, e = t u - (x_a - x_i):
+//  - evaluation: coordinate k of e carries at most (|t u_k| + |x_ak - x_ik|
+//    + |e_k|) 2^-24, a vector of norm at most 2 (t + s_a) 2^-24 (s_a =
+//    sqrt(da), |x_a - x_i| <= t + s_a), which moves da by 2 s_a times that;
+//    the sum of squares adds (d + 1) 2^-24 da;
+//  - position: q lies within `shift` of the exact candidate, which moves
+//    da - db by at most 2 shift (s_a + s_b).
+// Times 4 for safety.  All terms scale with the cell, not with the cube.
+__device__ __forceinline__ float gap_tol(float da, float db, float shift, float t, int d) {
+  const float sa = sqrtf(da), sb = sqrtf(db);
+  const float eval = (4.f * (sa * (t + sa) + sb * (t + sb)) + (float)(d + 1) * (da + db)) * 0x1p-24f;
+  return 4.f * (eval + 2.f * shift * (sa + sb));
 }
+
+// Slack of the ring bound for the rounding of cell indices (of q and of the
+// nodes) and of q's absolute coordinates.
+constexpr float kRingSlack = 0x1p-20f;
 
 struct GridView {
   const float *X;         // [n][d] nodes in cell order
@@ -90,28 +101,32 @@ struct GridView {
   float h;
 };
 
-// Top-2 nearest eligible nodes of q (squared distances).  A node whose
+// Top-2 nearest eligible nodes (squared distances) of the candidate
+// q = x_i + t u, from coordinates relative to x_i; eligible means
+// u.(x_k - x_i) > 0 (the skip predicate of Algorithm 1).  A node whose
 // squared distance exceeds ref + gap_tol(ref, .) with ref = min(d1, limit)
 // cannot change the caller's decision or its certificate, so the ring search
-// stops once every unvisited node is that far (or beyond d2).  t is the
-// candidate's ray parameter (for gap_tol).
+// stops once every unvisited node is that far (or beyond d2).  `shift`
+// bounds the distance of q from the exact candidate (for gap_tol).
 template <int DK>
-__device__ void nn2(const GridView &g, int d, const float (&q)[DK], const float (&u)[DK], float ui,
-                    int32_t self, float limit, float t, int32_t &i1, float &d1, float &d2) {
+__device__ void nn2(const GridView &g, int d, const float (&xi)[DK], const float (&u)[DK], float t,
+                    int32_t self, float limit, float shift, int32_t &i1, float &d1, float &d2) {
+  float qr[DK];
   int c[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
-    int v = k < d ? (int)floorf(q[k] * (float)g.G) : 0;
+    qr[k] = t * u[k];
+    int v = k < d ? (int)floorf((xi[k] + qr[k]) * (float)g.G) : 0;
     c[k] = v < 0 ? 0 : (v >= g.G ? g.G - 1 : v);
   }
   i1 = -1;
   d1 = d2 = __builtin_inff();
   for (int rho = 0; rho < g.G; ++rho) {
     if (rho >= 1) {
-      const float lb = (float)(rho - 1) * g.h;
+      const float lb = fmaxf(0.f, (float)(rho - 1) * g.h - kRingSlack);
       const float lb2 = lb * lb;
       const float ref = fminf(d1, limit);
-      if (lb2 > d2 || lb2 > ref + gap_tol(ref, lb2, t, d)) break;
+      if (lb2 > d2 || lb2 > ref + gap_tol(ref, lb2, shift, t, d)) break;
     }
     // offsets o in [-rho, rho]^d with max |o_k| = rho, as a mixed-radix counter
     const int span = 2 * rho + 1;
@@ -135,16 +150,17 @@ __device__ void nn2(const GridView &g, int d, const float (&q)[DK], const float 
           const int32_t node = g.id[p];
           if (node == self) continue;
           const float *xp = g.X + (int64_t)p * d;
-          float ux = 0.f, dist = 0.f;
+          float den = 0.f, dist = 0.f;
 #pragma unroll
           for (int k = 0; k < DK; ++k) {
             if (k < d) {
-              ux = __builtin_fmaf(u[k], xp[k], ux);
-              const float e = q[k] - xp[k];
+              const float ek = xp[k] - xi[k];
+              den = __builtin_fmaf(u[k], ek, den);
+              const float e = qr[k] - ek;
               dist = __builtin_fmaf(e, e, dist);
             }
           }
-          if (!(ux > ui)) continue;  // skip: not ahead of the ray
+          if (!(den > 0.f)) continue;  // skip: not ahead of the ray
           if (dist < d1 || (dist == d1 && node < i1)) {
             d2 = d1;
             d1 = dist;
@@ -276,9 +292,6 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
       xi[k] = k < d ? a.nodes[cell * d + k] : 0.f;
       u[k] = k < d ? a.dirs[gid * d + k] : 0.f;
     }
-    float ui = 0.f;
-#pragma unroll
-    for (int k = 0; k < DK; ++k) ui = __builtin_fmaf(u[k], xi[k], ui);
     // exit through the cube
     float tbox = __builtin_inff();
     int face = -1;
@@ -328,7 +341,6 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
     uint8_t st = 0;
     int32_t j = -1;
     float t = tbox;
-    float q[DK];
     int32_t i1 = -1;
     float d1 = __builtin_inff(), d2 = __builtin_inff();
     int32_t k = kseed;
@@ -336,51 +348,50 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
       flag = true;  // zero direction
       k = -1;
     } else if (k < 0) {
-#pragma unroll
-      for (int q2 = 0; q2 < DK; ++q2) q[q2] = __builtin_fmaf(tbox, u[q2], xi[q2]);
       float di = 0.f;  // squared distance of x_i to the exit point
 #pragma unroll
       for (int q2 = 0; q2 < DK; ++q2) {
-        const float e = q[q2] - xi[q2];
+        const float e = tbox * u[q2];
         di = __builtin_fmaf(e, e, di);
       }
-      nn2<DK>(g, d, q, u, ui, (int32_t)cell, di, tbox, i1, d1, d2);
+      // tbox: one subtraction and one division
+      const float shift = tbox * 0x1p-22f;
+      nn2<DK>(g, d, xi, u, tbox, (int32_t)cell, di, shift, i1, d1, d2);
       ++calls;
       if (i1 < 0 || d1 > di) {
         j = -2 - face;  // the exit point lies in cell i
-        if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, tbox, d))) flag = true;
+        if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, shift, tbox, d))) flag = true;
       } else {
         k = i1;
       }
     }
     if (k >= 0) {
       int it = 0;
+      float shift = 0.f;
       for (; it < kMaxIter; ++it) {
         const float *xk = a.nodes + (int64_t)k * d;
+        float ek[DK];
         float num = 0.f, den = 0.f;
 #pragma unroll
         for (int q2 = 0; q2 < DK; ++q2) {
-          if (q2 < d) {
-            const float e = xk[q2] - xi[q2];
-            num = __builtin_fmaf(e, e, num);
-            den = __builtin_fmaf(u[q2], e, den);
-          }
+          ek[q2] = q2 < d ? xk[q2] - xi[q2] : 0.f;
+          num = __builtin_fmaf(ek[q2], ek[q2], num);
+          den = __builtin_fmaf(u[q2], ek[q2], den);
         }
         t = num / (2.f * den);
-#pragma unroll
-        for (int q2 = 0; q2 < DK; ++q2) q[q2] = __builtin_fmaf(t, u[q2], xi[q2]);
+        // relative error of t: (d + 2) ulps of num, (d + 1) |e| / den ulps of
+        // den (its cancellation), one of the division
+        shift = t * ((float)(d + 3) + (float)(d + 1) * sqrtf(num) / den) * 0x1p-24f;
         float dk = 0.f;  // the candidate's own node: nothing farther matters
 #pragma unroll
         for (int q2 = 0; q2 < DK; ++q2) {
-          if (q2 < d) {
-            const float e = q[q2] - xk[q2];
-            dk = __builtin_fmaf(e, e, dk);
-          }
+          const float e = t * u[q2] - ek[q2];
+          dk = __builtin_fmaf(e, e, dk);
         }
-        nn2<DK>(g, d, q, u, ui, (int32_t)cell, dk, t, i1, d1, d2);
+        nn2<DK>(g, d, xi, u, t, (int32_t)cell, dk, shift, i1, d1, d2);
         ++calls;
         if (i1 == k) break;
-        if (i1 < 0) break;  // cannot happen: k itself is eligible
+        if (i1 < 0) break;  // k itself is eligible, so only through NaN
         k = i1;
       }
       j = k;
@@ -388,7 +399,8 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
         flag = true;
         st |= VG_ST_SUSPECT;
       }
-      if (d2 < __builtin_inff() && !(d2 - d1 > gap_tol(d2, d1, t, d))) flag = true;  // runner-up within rounding
+      // runner-up within rounding
+      if (d2 < __builtin_inff() && !(d2 - d1 > gap_tol(d2, d1, shift, t, d))) flag = true;
       // a nearly grazing winner: its eligibility may hinge on rounding
       float den = 0.f, nrm = 0.f;
       const float *xj = a.nodes + (int64_t)j * d;

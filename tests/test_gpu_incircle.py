@@ -46,6 +46,30 @@ def test_incircle_matches_oracle_and_dense_scan(vg, d, n, R):
     assert 1.0 <= per_ray <= 1.5
 
 
+def test_incircle_small_cells_match_dense_scan_and_oracle(vg):
+    """N = 200 000 in 3-D: cells about 1/60 of the cube across, where the
+    certificate's error bound must scale with the cell.  Every ray against
+    the dense scan (FP64 ties excused), 64 sampled cells against the oracle."""
+    d, n, R = 3, 200_000, 32
+    X = W.uniform_cloud(n, d, seed=91)
+    dev = torch.device("cuda", 0)
+    nodes = torch.from_numpy(X).to(dev)
+    dirs = W.mc_directions_device(n, R, d, seed=92, device=dev)
+    t, idx, st = vg.raycast_cells(nodes, dirs, incircle=True)
+    s = vg.stats()
+    t_d, idx_d, st_d = vg.raycast_cells(nodes, dirs)
+    tie = ((st | st_d) & vg.ST_FP64_TIE) != 0
+    assert torch.equal(idx[~tie], idx_d[~tie])
+    per_ray = s["nn_calls"] / (n * R)
+    print(f"  nn calls per ray {per_ray:.3f}, flagged {s['flagged']} of {n * R}", flush=True)
+    assert s["flagged"] <= 1e-4 * n * R
+    cells = np.random.default_rng(93).choice(n, 64, replace=False)
+    D = dirs[torch.from_numpy(cells).to(dev)].cpu().numpy()
+    t_ref, idx_ref, t2_ref = oracle.raycast_cells(X, cells, D)
+    sel = torch.from_numpy(cells).to(dev)
+    compare_rays(t[sel].cpu().numpy(), idx[sel].cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+
+
 def test_incircle_estimators_match_oracle(vg):
     d, n, R = 3, 600, 256
     X = W.uniform_cloud(n, d, seed=5)
