@@ -267,6 +267,7 @@ def bench_incircle(args):
         "config": {"workload": f"uniform d={d} N={n}, {R} MC rays per cell, volumes + second "
                                "moments + facet areas",
                    "rays": rays, "nn_calls_per_ray": st["nn_calls"] / rays,
+                   "grid_nn_calls_per_ray": st["nn_grid_calls"] / rays,
                    "flagged_rays_per_step": st["flagged"],
                    "dense_scan_ms_per_step": ms_full, "speedup_vs_dense_scan": ms_full / ms,
                    "argmin_agreement_with_dense_scan": agree,

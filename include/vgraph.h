@@ -76,6 +76,8 @@ typedef struct vg_stats {
   int64_t scan_launches; /* candidate-scan launches timed since profiling began */
   double scan_ms;        /* their summed duration (HIP events on the stream)    */
   int64_t nn_calls;      /* nearest-neighbour queries of the last VG_INCIRCLE call */
+  int64_t nn_grid_calls; /* of those, queries answered by the grid (the others
+                            by the cell's list of nearest nodes)             */
 } vg_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -119,9 +121,11 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
  * directions with the nodes inverted about x_i, on MFMA.  With VG_INCIRCLE
  * the rays are cast instead by the incircle iteration of Algorithm 1, its
  * nearest-neighbour queries answered by a uniform grid over the cube (built
- * per call; nodes must lie in [0,1]^d; d <= 6, FP32 only), starting from the
- * ray's exit point of the cube; results are the same (the certificate and
- * the FP64 recheck are shared), and vg_stats.nn_calls counts the queries.
+ * per call; nodes must lie in [0,1]^d; d <= 6, FP32 only) or, when it
+ * provably holds every node that matters, by the cell's list of nearest
+ * nodes, which also gives the first candidate; results are the same (the
+ * certificate and the FP64 recheck are shared), and vg_stats.nn_calls and
+ * nn_grid_calls count the queries.
  *   dirs [n_nodes][rays_per_cell][d] f32 unit vectors
  *   flags VG_PREC_BF16X3, VG_NO_RECHECK, VG_INCIRCLE
  * Outputs [n_nodes * rays_per_cell], cell-major: t_out, idx_out, status_out

@@ -53,7 +53,7 @@ class _Stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_int64), ("flagged", ctypes.c_int64),
                 ("fp64_ties", ctypes.c_int64), ("tie_eps", ctypes.c_double),
                 ("scan_launches", ctypes.c_int64), ("scan_ms", ctypes.c_double),
-                ("nn_calls", ctypes.c_int64)]
+                ("nn_calls", ctypes.c_int64), ("nn_grid_calls", ctypes.c_int64)]
 
 
 class _CellsProblem(ctypes.Structure):
@@ -163,7 +163,8 @@ def stats(device=None) -> dict:
     s = _Stats()
     _check(_lib.vg_get_stats(c, ctypes.byref(s)), c, "vg_get_stats")
     return dict(rays=s.rays, flagged=s.flagged, fp64_ties=s.fp64_ties, tie_eps=s.tie_eps,
-                scan_launches=s.scan_launches, scan_ms=s.scan_ms, nn_calls=s.nn_calls)
+                scan_launches=s.scan_launches, scan_ms=s.scan_ms, nn_calls=s.nn_calls,
+                nn_grid_calls=s.nn_grid_calls)
 
 
 def set_profiling(enable: bool, device=None) -> None:

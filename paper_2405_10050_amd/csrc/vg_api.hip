@@ -290,6 +290,7 @@ int vg_get_stats(vg_ctx *ctx, vg_stats *out) {
                         hipMemcpyDeviceToHost));
   out->rays = ctx->last_rays;
   out->nn_calls = (int64_t)((uint64_t)c[CNT_NN_CALLS] | ((uint64_t)c[CNT_NN_CALLS + 1] << 32));
+  out->nn_grid_calls = (int64_t)((uint64_t)c[CNT_NN_GRID] | ((uint64_t)c[CNT_NN_GRID + 1] << 32));
   out->flagged = c[CNT_FLAGGED];
   out->fp64_ties = c[CNT_FP64_TIE];
   out->tie_eps = ctx->last_tau;

@@ -44,7 +44,6 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int kMaxIter = 64;
-constexpr int kMaxKnn = 32;  // largest list of nearest nodes kept per cell
 
 __global__ void grid_count_kernel(const float *__restrict__ X, int64_t n, int d, int G,
                                   int32_t *__restrict__ cell_of, uint32_t *__restrict__ counts) {
@@ -182,19 +181,31 @@ __device__ void nn2(const GridView &g, int d, const float (&xi)[DK], const float
   }
 }
 
-// Nearest nodes kept per cell for the first candidate.
+// Nearest nodes kept per cell (first candidates, and the list that answers
+// most queries by itself).
 template <int DK>
 constexpr int knn_of() {
-  return DK <= 2 ? 8 : (DK <= 3 ? 16 : (DK <= 4 ? 24 : 32));
+  return DK <= 2 ? 16 : (DK <= 3 ? 32 : (DK <= 4 ? 48 : 64));
 }
+static int knn_count(int d) { return d <= 2 ? 16 : (d <= 3 ? 32 : (d <= 4 ? 48 : 64)); }
 
-// The KN nearest nodes of every node (excluding itself), nearest first, -1
-// past the end when n <= KN: ring search stopping once ((rho - 1) h)^2
-// exceeds the KN-th squared distance; the list is kept sorted by a fully
-// unrolled insertion so it stays in registers.
+// Per-cell list: the KN nearest nodes of x_i (excluding itself), nearest
+// first, -1 past the end when n <= KN; their coordinates relative to x_i;
+// and r2, the KN-th squared distance (+inf when the list holds every other
+// node).  Every node outside the list is at least about sqrt(r2) from x_i:
+// it was either rejected against a list bound that only decreases, or lies
+// beyond the ring bound.  Ring search stopping once the ring bound exceeds
+// the KN-th distance; the list is kept sorted by a fully unrolled insertion
+// so it stays in registers.
+struct KnnList {
+  int32_t *ids;  // [n][KN]
+  float *rel;    // [n][KN][d]
+  float *r2;     // [n]
+};
+
 template <int DK>
 __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes, int64_t n, int d, GridView g,
-                                                 int32_t *__restrict__ knn) {
+                                                 KnnList out) {
   constexpr int KN = knn_of<DK>();
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
@@ -215,7 +226,7 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
   }
   for (int rho = 0; rho < g.G; ++rho) {
     if (rho >= 1) {
-      const float lb = (float)(rho - 1) * g.h;
+      const float lb = fmaxf(0.f, (float)(rho - 1) * g.h - kRingSlack);
       if (lb * lb > dl[KN - 1]) break;
     }
     const int span = 2 * rho + 1;
@@ -243,7 +254,7 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
 #pragma unroll
           for (int k = 0; k < DK; ++k) {
             if (k < d) {
-              const float e = x[k] - xp[k];
+              const float e = xp[k] - x[k];
               dist = __builtin_fmaf(e, e, dist);
             }
           }
@@ -272,15 +283,77 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
     }
   }
 #pragma unroll
-  for (int s = 0; s < KN; ++s) knn[i * KN + s] = il[s];
+  for (int s = 0; s < KN; ++s) {
+    out.ids[i * KN + s] = il[s];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d) out.rel[(i * KN + s) * d + k] = il[s] >= 0 ? nodes[(int64_t)il[s] * d + k] - x[k] : 0.f;
+    }
+  }
+  out.r2[i] = dl[KN - 1];
+}
+
+// Top-2 as nn2, over the cell's list only.
+template <int DK, int KN>
+__device__ void list_nn2(const int32_t *ids, const float *rel, int d, const float (&u)[DK], float t, int32_t &i1,
+                         float &d1, float &d2) {
+  float qr[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) qr[k] = t * u[k];
+  i1 = -1;
+  d1 = d2 = __builtin_inff();
+#pragma unroll 4
+  for (int s = 0; s < KN; ++s) {
+    const int32_t node = ids[s];
+    if (node < 0) break;
+    float den = 0.f, dist = 0.f;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d) {
+        const float ek = rel[s * d + k];
+        den = __builtin_fmaf(u[k], ek, den);
+        const float e = qr[k] - ek;
+        dist = __builtin_fmaf(e, e, dist);
+      }
+    }
+    if (!(den > 0.f)) continue;
+    if (dist < d1 || (dist == d1 && node < i1)) {
+      d2 = d1;
+      d1 = dist;
+      i1 = node;
+    } else if (dist < d2) {
+      d2 = dist;
+    }
+  }
+}
+
+// One query of Algorithm 1 at q = x_i + t u.  Only nodes with squared
+// distance up to dmax = limit + gap_tol(limit, 2 limit) can change nn2's
+// answer or its certificate (a farther node exceeds ref + gap_tol(ref, .)
+// for ref <= limit, given shift < sqrt(limit) / 32); they lie within
+// t + sqrt(dmax) of x_i, so when that is inside the cell's list radius the
+// list answers exactly as the grid would.  Returns true when the grid was
+// searched.
+template <int DK, int KN>
+__device__ bool query(const GridView &g, int d, const float (&xi)[DK], const float (&u)[DK], float t,
+                      int32_t self, float limit, float shift, const int32_t *ids, const float *rel, float r2,
+                      int32_t &i1, float &d1, float &d2) {
+  const float dmax = limit + gap_tol(limit, 2.f * limit, shift, t, d);
+  const float rr = t + sqrtf(dmax);
+  if (dmax <= 2.f * limit && 32.f * shift < sqrtf(limit) && rr * rr * (1.f + 0x1p-12f) < r2) {
+    list_nn2<DK, KN>(ids, rel, d, u, t, i1, d1, d2);
+    return false;
+  }
+  nn2<DK>(g, d, xi, u, t, self, limit, shift, i1, d1, d2);
+  return true;
 }
 
 template <int DK>
-__global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, GridView g, const int32_t *__restrict__ knn,
+__global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, GridView g, KnnList kl,
                                                             unsigned long long *nn_calls) {
   constexpr int KN = knn_of<DK>();
-  __shared__ unsigned int block_calls;
-  if (threadIdx.x == 0) block_calls = 0;
+  __shared__ unsigned int block_calls[2];
+  if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
   const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
   const int d = a.d, R = a.R;
@@ -308,35 +381,35 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
     }
     // first candidate: the eligible listed node with the smallest t_k
     // (grazing nodes are left out; their t_k is large anyway)
+    const int32_t *lids = kl.ids + cell * KN;
+    const float *lrel = kl.rel + cell * KN * d;
+    const float r2 = kl.r2[cell];
     int32_t kseed = -1;
     {
       float tbest = tbox;
-      const int32_t *lst = knn + cell * KN;
-#pragma unroll
+#pragma unroll 4
       for (int s = 0; s < KN; ++s) {
-        const int32_t k = lst[s];
-        if (k >= 0) {
-          const float *xk = a.nodes + (int64_t)k * d;
-          float num = 0.f, den = 0.f;
+        const int32_t k = lids[s];
+        if (k < 0) break;
+        float num = 0.f, den = 0.f;
 #pragma unroll
-          for (int q2 = 0; q2 < DK; ++q2) {
-            if (q2 < d) {
-              const float e = xk[q2] - xi[q2];
-              num = __builtin_fmaf(e, e, num);
-              den = __builtin_fmaf(u[q2], e, den);
-            }
+        for (int q2 = 0; q2 < DK; ++q2) {
+          if (q2 < d) {
+            const float e = lrel[s * d + q2];
+            num = __builtin_fmaf(e, e, num);
+            den = __builtin_fmaf(u[q2], e, den);
           }
-          if (den > (1.f / 4096.f) * sqrtf(num)) {
-            const float tk = num / (2.f * den);
-            if (tk < tbest) {
-              tbest = tk;
-              kseed = k;
-            }
+        }
+        if (den > (1.f / 4096.f) * sqrtf(num)) {
+          const float tk = num / (2.f * den);
+          if (tk < tbest) {
+            tbest = tk;
+            kseed = k;
           }
         }
       }
     }
-    uint32_t calls = 0;
+    uint32_t calls = 0, grid_calls = 0;
     bool flag = false;
     uint8_t st = 0;
     int32_t j = -1;
@@ -356,7 +429,7 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
       }
       // tbox: one subtraction and one division
       const float shift = tbox * 0x1p-22f;
-      nn2<DK>(g, d, xi, u, tbox, (int32_t)cell, di, shift, i1, d1, d2);
+      grid_calls += query<DK, KN>(g, d, xi, u, tbox, (int32_t)cell, di, shift, lids, lrel, r2, i1, d1, d2);
       ++calls;
       if (i1 < 0 || d1 > di) {
         j = -2 - face;  // the exit point lies in cell i
@@ -388,7 +461,7 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
           const float e = t * u[q2] - ek[q2];
           dk = __builtin_fmaf(e, e, dk);
         }
-        nn2<DK>(g, d, xi, u, t, (int32_t)cell, dk, shift, i1, d1, d2);
+        grid_calls += query<DK, KN>(g, d, xi, u, t, (int32_t)cell, dk, shift, lids, lrel, r2, i1, d1, d2);
         ++calls;
         if (i1 == k) break;
         if (i1 < 0) break;  // k itself is eligible, so only through NaN
@@ -430,10 +503,11 @@ __global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, Grid
     a.t_out[gid] = t;
     a.idx_out[gid] = j;
     a.st_out[gid] = st;
-    atomicAdd(&block_calls, calls);
+    atomicAdd(&block_calls[0], calls);
+    atomicAdd(&block_calls[1], grid_calls);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && nn_calls) atomicAdd(nn_calls, (unsigned long long)block_calls);
+  if (threadIdx.x < 2 && nn_calls) atomicAdd(nn_calls + threadIdx.x, (unsigned long long)block_calls[threadIdx.x]);
 }
 
 unsigned blocks_of(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
@@ -455,10 +529,11 @@ size_t incircle_scratch_bytes(int64_t n, int d) {
   size_t tmp = 0;
   (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                           (int)(cells + 1));
-  // cell_of, ids [n] i32; Xs [n][d] f32; knn [n][<= kMaxKnn] i32;
-  // counts, start, cursor [cells + 1]; scan temp
-  return (size_t)n * 8 + (size_t)n * d * 4 + (size_t)n * kMaxKnn * 4 + 3 * (size_t)(cells + 1) * 4 + tmp +
-         7 * 256;
+  // cell_of, ids [n] i32; Xs [n][d] f32; list ids [n][KN] i32, rel
+  // [n][KN][d] f32, r2 [n] f32; counts, start, cursor [cells + 1]; scan temp
+  const size_t kn = (size_t)knn_count(d);
+  return (size_t)n * 8 + (size_t)n * d * 4 + (size_t)n * kn * (d + 1) * 4 + (size_t)n * 4 +
+         3 * (size_t)(cells + 1) * 4 + tmp + 9 * 256;
 }
 
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
@@ -476,7 +551,11 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   int32_t *cell_of = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
   int32_t *ids = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
   float *Xs = reinterpret_cast<float *>(carve((size_t)n * d * 4));
-  int32_t *knn = reinterpret_cast<int32_t *>(carve((size_t)n * kMaxKnn * 4));
+  const size_t kn = (size_t)knn_count(d);
+  KnnList kl;
+  kl.ids = reinterpret_cast<int32_t *>(carve((size_t)n * kn * 4));
+  kl.rel = reinterpret_cast<float *>(carve((size_t)n * kn * d * 4));
+  kl.r2 = reinterpret_cast<float *>(carve((size_t)n * 4));
   uint32_t *counts = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
   uint32_t *start = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
   uint32_t *cursor = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
@@ -500,8 +579,8 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   const int64_t rays = n * a.R;
   const dim3 grid(blocks_of(rays)), blk(NT);
 #define VG_INCIRCLE_LAUNCH(DKV)                                                                          \
-  hipLaunchKernelGGL(knn_kernel<DKV>, dim3(blocks_of(n)), blk, 0, s, a.nodes, n, d, g, knn);            \
-  hipLaunchKernelGGL(incircle_cells_kernel<DKV>, grid, blk, 0, s, a, g, knn, nn_calls)
+  hipLaunchKernelGGL(knn_kernel<DKV>, dim3(blocks_of(n)), blk, 0, s, a.nodes, n, d, g, kl);             \
+  hipLaunchKernelGGL(incircle_cells_kernel<DKV>, grid, blk, 0, s, a, g, kl, nn_calls)
   if (d <= 2) {
     VG_INCIRCLE_LAUNCH(2);
   } else if (d <= 3) {

@@ -17,7 +17,8 @@ enum : int {
   CNT_FLAGGED = 0,   // rays appended to the FP64 recheck list
   CNT_FP64_TIE = 1,  // rays whose FP64 gap is below 1e-9
   CNT_NN_CALLS = 4,  // u64 (words 4, 5): nearest-neighbour queries of the incircle RayCast
-  CNT_WORDS = 6
+  CNT_NN_GRID = 6,   // u64 (words 6, 7): of those, queries answered by the grid
+  CNT_WORDS = 8
 };
 
 // Where the recheck kernel finds a ray.
@@ -161,8 +162,8 @@ int tuple_neighbors(int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sig
                     hipStream_t s, std::string &err);
 
 // Incircle RayCast (Algorithm 1) of the Monte-Carlo rays with a grid index
-// (vg_incircle.hip): scratch of incircle_scratch_bytes(n, d), nn-call count
-// added to *nn_calls.
+// (vg_incircle.hip): scratch of incircle_scratch_bytes(n, d); query counts
+// added to nn_calls[0] (all) and nn_calls[1] (answered by the grid).
 size_t incircle_scratch_bytes(int64_t n, int d);
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
                                  hipStream_t s);

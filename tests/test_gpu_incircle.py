@@ -40,7 +40,8 @@ def test_incircle_matches_oracle_and_dense_scan(vg, d, n, R):
     rel = np.abs(t.cpu().numpy().ravel() - t_d.cpu().numpy().ravel())[ok] / t_ref[ok]
     assert rel.max(initial=0.0) <= 1e-6
     per_ray = s["nn_calls"] / (n * R)
-    print(f"  nn calls per ray {per_ray:.2f}, flagged {s['flagged']}", flush=True)
+    print(f"  nn calls per ray {per_ray:.2f} (grid {s['nn_grid_calls'] / (n * R):.2f}), "
+          f"flagged {s['flagged']}", flush=True)
     # the first candidate (best of the cell's nearest nodes) is usually the
     # winner, so about one query confirms it
     assert 1.0 <= per_ray <= 1.5
@@ -61,7 +62,8 @@ def test_incircle_small_cells_match_dense_scan_and_oracle(vg):
     tie = ((st | st_d) & vg.ST_FP64_TIE) != 0
     assert torch.equal(idx[~tie], idx_d[~tie])
     per_ray = s["nn_calls"] / (n * R)
-    print(f"  nn calls per ray {per_ray:.3f}, flagged {s['flagged']} of {n * R}", flush=True)
+    print(f"  nn calls per ray {per_ray:.3f} (grid {s['nn_grid_calls'] / (n * R):.3f}), "
+          f"flagged {s['flagged']} of {n * R}", flush=True)
     assert s["flagged"] <= 1e-4 * n * R
     cells = np.random.default_rng(93).choice(n, 64, replace=False)
     D = dirs[torch.from_numpy(cells).to(dev)].cpu().numpy()
