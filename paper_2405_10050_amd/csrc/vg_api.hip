@@ -115,7 +115,7 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   const bool incircle = (flags & VG_INCIRCLE) != 0;
   if (incircle && (bf16 || nbr || d > 6))
     return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs d <= 6, FP32 and no neighbour lists");
-  const size_t grid_bytes = incircle ? incircle_scratch_bytes(n, d) : 0;
+  const size_t grid_bytes = incircle ? incircle_scratch_bytes(n, d, R) : 0;
   size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;

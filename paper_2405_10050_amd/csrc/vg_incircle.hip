@@ -28,6 +28,10 @@
 // the node nn returned.  Every candidate has t below the exit, so it lies
 // inside the cube, where the grid query is cheap.
 //
+// Two passes: one thread per ray casts it while the cell's list answers its
+// queries (almost always); the few rays that need the grid are queued and
+// resumed by a second pass, so that grid walks do not hold up whole waves.
+//
 // Certificate: at the final candidate, the gap between the squared distances
 // of the nearest and second-nearest eligible node (the face test: between
 // the nearest eligible node and x_i) equals 2 u.(x_k - x_i)(t_k - t*) for the
@@ -207,13 +211,15 @@ template <int DK>
 __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes, int64_t n, int d, GridView g,
                                                  KnnList out) {
   constexpr int KN = knn_of<DK>();
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i >= n) return;
+  // threads take the nodes in grid order, so a wave searches neighbouring cells
+  const int64_t slot = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (slot >= n) return;
+  const int64_t i = g.id[slot];
   float x[DK];
   int c[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
-    x[k] = k < d ? nodes[i * d + k] : 0.f;
+    x[k] = k < d ? g.X[slot * d + k] : 0.f;
     int v = k < d ? (int)floorf(x[k] * (float)g.G) : 0;
     c[k] = v < 0 ? 0 : (v >= g.G ? g.G - 1 : v);
   }
@@ -327,187 +333,254 @@ __device__ void list_nn2(const int32_t *ids, const float *rel, int d, const floa
   }
 }
 
-// One query of Algorithm 1 at q = x_i + t u.  Only nodes with squared
-// distance up to dmax = limit + gap_tol(limit, 2 limit) can change nn2's
-// answer or its certificate (a farther node exceeds ref + gap_tol(ref, .)
-// for ref <= limit, given shift < sqrt(limit) / 32); they lie within
-// t + sqrt(dmax) of x_i, so when that is inside the cell's list radius the
-// list answers exactly as the grid would.  Returns true when the grid was
-// searched.
-template <int DK, int KN>
-__device__ bool query(const GridView &g, int d, const float (&xi)[DK], const float (&u)[DK], float t,
-                      int32_t self, float limit, float shift, const int32_t *ids, const float *rel, float r2,
-                      int32_t &i1, float &d1, float &d2) {
+// Whether the cell's list answers a query at q = x_i + t u exactly as the
+// grid would.  Only nodes with squared distance up to dmax = limit +
+// gap_tol(limit, 2 limit) can change nn2's answer or its certificate (a
+// farther node exceeds ref + gap_tol(ref, .) for ref <= limit, given
+// shift < sqrt(limit) / 32); they lie within t + sqrt(dmax) of x_i, inside
+// the list radius when this holds.
+__device__ __forceinline__ bool list_covers(float t, float limit, float shift, float r2, int d) {
   const float dmax = limit + gap_tol(limit, 2.f * limit, shift, t, d);
   const float rr = t + sqrtf(dmax);
-  if (dmax <= 2.f * limit && 32.f * shift < sqrtf(limit) && rr * rr * (1.f + 0x1p-12f) < r2) {
-    list_nn2<DK, KN>(ids, rel, d, u, t, i1, d1, d2);
-    return false;
-  }
-  nn2<DK>(g, d, xi, u, t, self, limit, shift, i1, d1, d2);
-  return true;
+  return dmax <= 2.f * limit && 32.f * shift < sqrtf(limit) && rr * rr * (1.f + 0x1p-12f) < r2;
 }
 
-template <int DK>
-__global__ __launch_bounds__(NT) void incircle_cells_kernel(CellScanArgs a, GridView g, KnnList kl,
-                                                            unsigned long long *nn_calls) {
+// Rays whose next query needs the grid, with their current candidate (-1:
+// the exit-point test), handed from the list pass to the grid pass.
+struct DeferQueue {
+  int64_t *gid;     // [rays]
+  int32_t *k;       // [rays]
+  uint32_t *count;
+};
+
+// The RayCast of ray gid.  With GRID false the first candidate comes from
+// the list, and a query the list cannot answer stops the ray: returns true
+// with the current candidate in kdef, having written nothing.  With GRID
+// true the ray resumes from kstart and such queries search the grid.
+template <int DK, bool GRID>
+__device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList &kl, int64_t gid,
+                         int32_t kstart, int32_t &kdef, uint32_t &calls, uint32_t &grid_calls) {
   constexpr int KN = knn_of<DK>();
+  const int d = a.d;
+  const int64_t cell = gid / a.R;
+  float xi[DK], u[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    xi[k] = k < d ? a.nodes[cell * d + k] : 0.f;
+    u[k] = k < d ? a.dirs[gid * d + k] : 0.f;
+  }
+  // exit through the cube
+  float tbox = __builtin_inff();
+  int face = -1;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    if (k < d && u[k] != 0.f) {
+      const float hk = u[k] > 0.f ? 1.f - xi[k] : xi[k];
+      const float tk = hk / fabsf(u[k]);
+      if (tk < tbox) {
+        tbox = tk;
+        face = 2 * k + (u[k] > 0.f ? 1 : 0);
+      }
+    }
+  }
+  const int32_t *lids = kl.ids + cell * KN;
+  const float *lrel = kl.rel + cell * KN * d;
+  const float r2 = kl.r2[cell];
+  int32_t k = kstart;
+  if (!GRID) {
+    // first candidate: the eligible listed node with the smallest t_k
+    // (grazing nodes are left out; their t_k is large anyway)
+    k = -1;
+    float tbest = tbox;
+#pragma unroll 4
+    for (int s = 0; s < KN; ++s) {
+      const int32_t ks = lids[s];
+      if (ks < 0) break;
+      float num = 0.f, den = 0.f;
+#pragma unroll
+      for (int q2 = 0; q2 < DK; ++q2) {
+        if (q2 < d) {
+          const float e = lrel[s * d + q2];
+          num = __builtin_fmaf(e, e, num);
+          den = __builtin_fmaf(u[q2], e, den);
+        }
+      }
+      if (den > (1.f / 4096.f) * sqrtf(num)) {
+        const float tk = num / (2.f * den);
+        if (tk < tbest) {
+          tbest = tk;
+          k = ks;
+        }
+      }
+    }
+  }
+  bool flag = false;
+  uint8_t st = 0;
+  int32_t j = -1;
+  float t = tbox;
+  int32_t i1 = -1;
+  float d1 = __builtin_inff(), d2 = __builtin_inff();
+  if (face < 0) {
+    flag = true;  // zero direction
+    k = -1;
+  } else if (k < 0) {
+    float di = 0.f;  // squared distance of x_i to the exit point
+#pragma unroll
+    for (int q2 = 0; q2 < DK; ++q2) {
+      const float e = tbox * u[q2];
+      di = __builtin_fmaf(e, e, di);
+    }
+    // tbox: one subtraction and one division
+    const float shift = tbox * 0x1p-22f;
+    const bool in_list = list_covers(tbox, di, shift, r2, d);
+    if (!GRID && !in_list) {
+      kdef = -1;
+      return true;
+    }
+    if (in_list) {
+      list_nn2<DK, KN>(lids, lrel, d, u, tbox, i1, d1, d2);
+    } else {
+      nn2<DK>(g, d, xi, u, tbox, (int32_t)cell, di, shift, i1, d1, d2);
+      ++grid_calls;
+    }
+    ++calls;
+    if (i1 < 0 || d1 > di) {
+      j = -2 - face;  // the exit point lies in cell i
+      if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, shift, tbox, d))) flag = true;
+    } else {
+      k = i1;
+    }
+  }
+  if (k >= 0) {
+    int it = 0;
+    float shift = 0.f;
+    for (; it < kMaxIter; ++it) {
+      const float *xk = a.nodes + (int64_t)k * d;
+      float ek[DK];
+      float num = 0.f, den = 0.f;
+#pragma unroll
+      for (int q2 = 0; q2 < DK; ++q2) {
+        ek[q2] = q2 < d ? xk[q2] - xi[q2] : 0.f;
+        num = __builtin_fmaf(ek[q2], ek[q2], num);
+        den = __builtin_fmaf(u[q2], ek[q2], den);
+      }
+      t = num / (2.f * den);
+      // relative error of t: (d + 2) ulps of num, (d + 1) |e| / den ulps of
+      // den (its cancellation), one of the division
+      shift = t * ((float)(d + 3) + (float)(d + 1) * sqrtf(num) / den) * 0x1p-24f;
+      float dk = 0.f;  // the candidate's own node: nothing farther matters
+#pragma unroll
+      for (int q2 = 0; q2 < DK; ++q2) {
+        const float e = t * u[q2] - ek[q2];
+        dk = __builtin_fmaf(e, e, dk);
+      }
+      const bool in_list = list_covers(t, dk, shift, r2, d);
+      if (!GRID && !in_list) {
+        kdef = k;
+        return true;
+      }
+      if (in_list) {
+        list_nn2<DK, KN>(lids, lrel, d, u, t, i1, d1, d2);
+      } else {
+        nn2<DK>(g, d, xi, u, t, (int32_t)cell, dk, shift, i1, d1, d2);
+        ++grid_calls;
+      }
+      ++calls;
+      if (i1 == k) break;
+      if (i1 < 0) break;  // k itself is eligible, so only through NaN
+      k = i1;
+    }
+    j = k;
+    if (it == kMaxIter || i1 != k) {
+      flag = true;
+      st |= VG_ST_SUSPECT;
+    }
+    // runner-up within rounding
+    if (d2 < __builtin_inff() && !(d2 - d1 > gap_tol(d2, d1, shift, t, d))) flag = true;
+    // a nearly grazing winner: its eligibility may hinge on rounding
+    float den = 0.f, nrm = 0.f;
+    const float *xj = a.nodes + (int64_t)j * d;
+#pragma unroll
+    for (int q2 = 0; q2 < DK; ++q2) {
+      if (q2 < d) {
+        const float e = xj[q2] - xi[q2];
+        den = __builtin_fmaf(u[q2], e, den);
+        nrm = __builtin_fmaf(e, e, nrm);
+      }
+    }
+    if (!(den > (1.f / 4096.f) * sqrtf(nrm))) {
+      flag = true;
+      st |= VG_ST_SUSPECT;
+    }
+    t = reeval_cell<DK>(xi, xj, u, d);
+    if (!(t <= tbox)) {  // the face is nearer after all: settle it in FP64
+      flag = true;
+    }
+  }
+  if (j <= -2) t = tbox;
+  if (flag && a.flag_list) {
+    st |= VG_ST_NEAR_TIE;
+    const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
+    a.flag_list[pos] = gid | a.flag_tag;
+  }
+  a.t_out[gid] = t;
+  a.idx_out[gid] = j;
+  a.st_out[gid] = st;
+  return false;
+}
+
+// Sums the block's query counts into nn_calls[0] (all) and [1] (grid).
+__device__ __forceinline__ void add_calls(unsigned int *block_calls, uint32_t calls, uint32_t grid_calls,
+                                          unsigned long long *nn_calls) {
+  if (calls) atomicAdd(&block_calls[0], calls);
+  if (grid_calls) atomicAdd(&block_calls[1], grid_calls);
+  __syncthreads();
+  if (threadIdx.x < 2 && nn_calls) atomicAdd(nn_calls + threadIdx.x, (unsigned long long)block_calls[threadIdx.x]);
+}
+
+// List pass: one thread per ray; rays that need the grid are appended to the
+// queue (one atomic per wave).
+template <int DK>
+__global__ __launch_bounds__(NT) void incircle_list_kernel(CellScanArgs a, GridView g, KnnList kl, DeferQueue dq,
+                                                           unsigned long long *nn_calls) {
   __shared__ unsigned int block_calls[2];
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
   const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const int d = a.d, R = a.R;
-  if (gid < a.n * R) {
-    const int64_t cell = gid / R;
-    float xi[DK], u[DK];
-#pragma unroll
-    for (int k = 0; k < DK; ++k) {
-      xi[k] = k < d ? a.nodes[cell * d + k] : 0.f;
-      u[k] = k < d ? a.dirs[gid * d + k] : 0.f;
+  uint32_t calls = 0, grid_calls = 0;
+  bool defer = false;
+  int32_t kdef = -1;
+  if (gid < a.n * a.R) defer = cast_ray<DK, false>(a, g, kl, gid, -1, kdef, calls, grid_calls);
+  const unsigned long long mask = __ballot(defer);
+  if (mask) {
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(dq.count, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (defer) {
+      const uint32_t pos = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+      dq.gid[pos] = gid;
+      dq.k[pos] = kdef;
     }
-    // exit through the cube
-    float tbox = __builtin_inff();
-    int face = -1;
-#pragma unroll
-    for (int k = 0; k < DK; ++k) {
-      if (k < d && u[k] != 0.f) {
-        const float hk = u[k] > 0.f ? 1.f - xi[k] : xi[k];
-        const float tk = hk / fabsf(u[k]);
-        if (tk < tbox) {
-          tbox = tk;
-          face = 2 * k + (u[k] > 0.f ? 1 : 0);
-        }
-      }
-    }
-    // first candidate: the eligible listed node with the smallest t_k
-    // (grazing nodes are left out; their t_k is large anyway)
-    const int32_t *lids = kl.ids + cell * KN;
-    const float *lrel = kl.rel + cell * KN * d;
-    const float r2 = kl.r2[cell];
-    int32_t kseed = -1;
-    {
-      float tbest = tbox;
-#pragma unroll 4
-      for (int s = 0; s < KN; ++s) {
-        const int32_t k = lids[s];
-        if (k < 0) break;
-        float num = 0.f, den = 0.f;
-#pragma unroll
-        for (int q2 = 0; q2 < DK; ++q2) {
-          if (q2 < d) {
-            const float e = lrel[s * d + q2];
-            num = __builtin_fmaf(e, e, num);
-            den = __builtin_fmaf(u[q2], e, den);
-          }
-        }
-        if (den > (1.f / 4096.f) * sqrtf(num)) {
-          const float tk = num / (2.f * den);
-          if (tk < tbest) {
-            tbest = tk;
-            kseed = k;
-          }
-        }
-      }
-    }
-    uint32_t calls = 0, grid_calls = 0;
-    bool flag = false;
-    uint8_t st = 0;
-    int32_t j = -1;
-    float t = tbox;
-    int32_t i1 = -1;
-    float d1 = __builtin_inff(), d2 = __builtin_inff();
-    int32_t k = kseed;
-    if (face < 0) {
-      flag = true;  // zero direction
-      k = -1;
-    } else if (k < 0) {
-      float di = 0.f;  // squared distance of x_i to the exit point
-#pragma unroll
-      for (int q2 = 0; q2 < DK; ++q2) {
-        const float e = tbox * u[q2];
-        di = __builtin_fmaf(e, e, di);
-      }
-      // tbox: one subtraction and one division
-      const float shift = tbox * 0x1p-22f;
-      grid_calls += query<DK, KN>(g, d, xi, u, tbox, (int32_t)cell, di, shift, lids, lrel, r2, i1, d1, d2);
-      ++calls;
-      if (i1 < 0 || d1 > di) {
-        j = -2 - face;  // the exit point lies in cell i
-        if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, shift, tbox, d))) flag = true;
-      } else {
-        k = i1;
-      }
-    }
-    if (k >= 0) {
-      int it = 0;
-      float shift = 0.f;
-      for (; it < kMaxIter; ++it) {
-        const float *xk = a.nodes + (int64_t)k * d;
-        float ek[DK];
-        float num = 0.f, den = 0.f;
-#pragma unroll
-        for (int q2 = 0; q2 < DK; ++q2) {
-          ek[q2] = q2 < d ? xk[q2] - xi[q2] : 0.f;
-          num = __builtin_fmaf(ek[q2], ek[q2], num);
-          den = __builtin_fmaf(u[q2], ek[q2], den);
-        }
-        t = num / (2.f * den);
-        // relative error of t: (d + 2) ulps of num, (d + 1) |e| / den ulps of
-        // den (its cancellation), one of the division
-        shift = t * ((float)(d + 3) + (float)(d + 1) * sqrtf(num) / den) * 0x1p-24f;
-        float dk = 0.f;  // the candidate's own node: nothing farther matters
-#pragma unroll
-        for (int q2 = 0; q2 < DK; ++q2) {
-          const float e = t * u[q2] - ek[q2];
-          dk = __builtin_fmaf(e, e, dk);
-        }
-        grid_calls += query<DK, KN>(g, d, xi, u, t, (int32_t)cell, dk, shift, lids, lrel, r2, i1, d1, d2);
-        ++calls;
-        if (i1 == k) break;
-        if (i1 < 0) break;  // k itself is eligible, so only through NaN
-        k = i1;
-      }
-      j = k;
-      if (it == kMaxIter || i1 != k) {
-        flag = true;
-        st |= VG_ST_SUSPECT;
-      }
-      // runner-up within rounding
-      if (d2 < __builtin_inff() && !(d2 - d1 > gap_tol(d2, d1, shift, t, d))) flag = true;
-      // a nearly grazing winner: its eligibility may hinge on rounding
-      float den = 0.f, nrm = 0.f;
-      const float *xj = a.nodes + (int64_t)j * d;
-#pragma unroll
-      for (int q2 = 0; q2 < DK; ++q2) {
-        if (q2 < d) {
-          const float e = xj[q2] - xi[q2];
-          den = __builtin_fmaf(u[q2], e, den);
-          nrm = __builtin_fmaf(e, e, nrm);
-        }
-      }
-      if (!(den > (1.f / 4096.f) * sqrtf(nrm))) {
-        flag = true;
-        st |= VG_ST_SUSPECT;
-      }
-      t = reeval_cell<DK>(xi, xj, u, d);
-      if (!(t <= tbox)) {  // the face is nearer after all: settle it in FP64
-        flag = true;
-      }
-    }
-    if (j <= -2) t = tbox;
-    if (flag && a.flag_list) {
-      st |= VG_ST_NEAR_TIE;
-      const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
-      a.flag_list[pos] = gid | a.flag_tag;
-    }
-    a.t_out[gid] = t;
-    a.idx_out[gid] = j;
-    a.st_out[gid] = st;
-    atomicAdd(&block_calls[0], calls);
-    atomicAdd(&block_calls[1], grid_calls);
   }
+  add_calls(block_calls, calls, grid_calls, nn_calls);
+}
+
+// Grid pass over the queued rays (grid-stride over the queue's count).
+template <int DK>
+__global__ __launch_bounds__(NT) void incircle_grid_kernel(CellScanArgs a, GridView g, KnnList kl, DeferQueue dq,
+                                                           unsigned long long *nn_calls) {
+  __shared__ unsigned int block_calls[2];
+  if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
-  if (threadIdx.x < 2 && nn_calls) atomicAdd(nn_calls + threadIdx.x, (unsigned long long)block_calls[threadIdx.x]);
+  const uint32_t cnt = *dq.count;
+  uint32_t calls = 0, grid_calls = 0;
+  for (uint32_t q = blockIdx.x * NT + threadIdx.x; q < cnt; q += gridDim.x * NT) {
+    int32_t kd;
+    (void)cast_ray<DK, true>(a, g, kl, dq.gid[q], dq.k[q], kd, calls, grid_calls);
+  }
+  add_calls(block_calls, calls, grid_calls, nn_calls);
 }
 
 unsigned blocks_of(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
@@ -522,7 +595,7 @@ static int incircle_grid_size(int64_t n, int d) {
   return G;
 }
 
-size_t incircle_scratch_bytes(int64_t n, int d) {
+size_t incircle_scratch_bytes(int64_t n, int d, int R) {
   const int G = incircle_grid_size(n, d);
   int64_t cells = 1;
   for (int k = 0; k < d; ++k) cells *= G;
@@ -530,16 +603,20 @@ size_t incircle_scratch_bytes(int64_t n, int d) {
   (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                           (int)(cells + 1));
   // cell_of, ids [n] i32; Xs [n][d] f32; list ids [n][KN] i32, rel
-  // [n][KN][d] f32, r2 [n] f32; counts, start, cursor [cells + 1]; scan temp
+  // [n][KN][d] f32, r2 [n] f32; counts, start, cursor [cells + 1]; scan
+  // temp; queue gid [rays] i64, k [rays] i32, count
   const size_t kn = (size_t)knn_count(d);
+  const size_t rays = (size_t)n * (size_t)R;
   return (size_t)n * 8 + (size_t)n * d * 4 + (size_t)n * kn * (d + 1) * 4 + (size_t)n * 4 +
-         3 * (size_t)(cells + 1) * 4 + tmp + 9 * 256;
+         3 * (size_t)(cells + 1) * 4 + tmp + rays * 12 + 12 * 256;
 }
 
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
                                  hipStream_t s) {
   const int64_t n = a.n;
   const int d = a.d;
+  const int64_t rays = n * a.R;
+  if (rays >= (int64_t(1) << 32)) return hipErrorInvalidValue;  // 32-bit queue and flag counters
   const int G = incircle_grid_size(n, d);
   int64_t cells = 1;
   for (int k = 0; k < d; ++k) cells *= G;
@@ -559,12 +636,17 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   uint32_t *counts = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
   uint32_t *start = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
   uint32_t *cursor = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
+  DeferQueue dq;
+  dq.gid = reinterpret_cast<int64_t *>(carve((size_t)rays * 8));
+  dq.k = reinterpret_cast<int32_t *>(carve((size_t)rays * 4));
+  dq.count = reinterpret_cast<uint32_t *>(carve(4));
   size_t tmp = 0;
   hipError_t e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp, counts, start, (int)(cells + 1), s);
   if (e != hipSuccess) return e;
   void *tmpp = carve(tmp);
   e = fill_u32(counts, 0u, cells + 1, s);
   if (e == hipSuccess) e = fill_u32(cursor, 0u, cells + 1, s);
+  if (e == hipSuccess) e = fill_u32(dq.count, 0u, 1, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(grid_count_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, a.nodes, n, d, G, cell_of, counts);
   // counts[0] = 0 and counts[c + 1] = size of cell c, so the inclusive scan
@@ -576,11 +658,13 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const GridView g{Xs, ids, start, G, 1.f / (float)G};
-  const int64_t rays = n * a.R;
   const dim3 grid(blocks_of(rays)), blk(NT);
+  // the grid pass strides over the queue, whose length only the device knows
+  const dim3 grid2(std::min<unsigned>(blocks_of(rays), 2048u));
 #define VG_INCIRCLE_LAUNCH(DKV)                                                                          \
   hipLaunchKernelGGL(knn_kernel<DKV>, dim3(blocks_of(n)), blk, 0, s, a.nodes, n, d, g, kl);             \
-  hipLaunchKernelGGL(incircle_cells_kernel<DKV>, grid, blk, 0, s, a, g, kl, nn_calls)
+  hipLaunchKernelGGL(incircle_list_kernel<DKV>, grid, blk, 0, s, a, g, kl, dq, nn_calls);               \
+  hipLaunchKernelGGL(incircle_grid_kernel<DKV>, grid2, blk, 0, s, a, g, kl, dq, nn_calls)
   if (d <= 2) {
     VG_INCIRCLE_LAUNCH(2);
   } else if (d <= 3) {

@@ -164,7 +164,7 @@ int tuple_neighbors(int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sig
 // Incircle RayCast (Algorithm 1) of the Monte-Carlo rays with a grid index
 // (vg_incircle.hip): scratch of incircle_scratch_bytes(n, d); query counts
 // added to nn_calls[0] (all) and nn_calls[1] (answered by the grid).
-size_t incircle_scratch_bytes(int64_t n, int d);
+size_t incircle_scratch_bytes(int64_t n, int d, int R);
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
                                  hipStream_t s);
 
