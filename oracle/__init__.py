@@ -32,6 +32,14 @@ Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
                             gradient identity 2 V (x - c).
   star                      equals the vertices of ``explore`` that contain the
                             generator.
+  explore_clipped           brute-force enumeration of the constraint sets
+                            (generators and faces) on tiny inputs; 2-D closed
+                            form V = 2N + 2; every cell's 2-D polygon from
+                            half-plane clipping; 3-D cell volumes (convex
+                            hulls of the cells' vertices) sum to 1; its
+                            face-free vertices are the unbounded diagram's
+                            vertices inside the cube; every edge seen by
+                            exactly two vertices.
   mc_integrals              f = 1 gives the facet areas, and t = 1 (t = 1/2)
                             gives d (d 2^{1-d}) times the volume, exactly;
                             2-D: exact cell and edge integrals of a linear f
@@ -87,6 +95,9 @@ def _load():
         lib.vgo_mc_ray_weights.argtypes = [i32, i64, P, i64, P, i32, P, P, P, P, P, P]
         lib.vgo_mc_adjoint.argtypes = [i32, i64, P, i64, P, i32, P, P, P, dbl, P, P, P, P]
         lib.vgo_num_threads.restype = i32
+        lib.vgo_explore_clipped.argtypes = [i32, i64, P]
+        lib.vgo_explore_clipped.restype = P
+        lib.vgo_clipped_vertex.argtypes = [i32, i64, P, P, P]
         lib.vgo_star.argtypes = [i32, i64, P, i32, P, i32, P, i64]
         lib.vgo_star.restype = i64
         _lib = lib
@@ -223,6 +234,40 @@ def explore(nodes, draws, mode: int = 0):
                     duplicates=int(lib.vgo_mesh_duplicates(h)))
     finally:
         lib.vgo_mesh_free(h)
+
+
+def explore_clipped(nodes):
+    """Exhaustive search (Algorithm 2) of the diagram clipped to the unit
+    cube, from the corner 0.  A vertex key holds d+1 sorted constraints:
+    generator indices, and the code ``n + 2k + s`` for the face ``x_k = s``.
+    Returns a dict with ``sigma`` ``[V][d+1]`` (discovery order), ``coord``
+    ``[V][d]`` and the counters ``raycasts``, ``duplicates``."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    h = lib.vgo_explore_clipped(d, n, _p(X))
+    if not h:
+        raise RuntimeError("oracle clipped explore failed (singular vertex)")
+    try:
+        nv = lib.vgo_mesh_nv(h)
+        sig = np.empty((nv, d + 1), dtype=np.int32)
+        coord = np.empty((nv, d))
+        lib.vgo_mesh_copy(h, _p(sig), _p(coord), None, None)
+        return dict(sigma=sig, coord=coord, raycasts=int(lib.vgo_mesh_raycasts(h)),
+                    duplicates=int(lib.vgo_mesh_duplicates(h)))
+    finally:
+        lib.vgo_mesh_free(h)
+
+
+def clipped_vertex(nodes, key):
+    """The point fixed by the d+1 constraints ``key`` (clipped encoding)."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    v = np.empty(d)
+    if lib.vgo_clipped_vertex(d, n, _p(X), _p(_i32(np.sort(key))), _p(v)):
+        raise ValueError("singular constraints")
+    return v
 
 
 def star(nodes, i, draws, cap=200_000):

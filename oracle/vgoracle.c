@@ -22,6 +22,10 @@
  *   vgo_explore           Algorithm 2 (VoronoiGraph exhaustive search with the
  *                         edge visit counter), Descent, SearchDirection and
  *                         the vertex coordinates of Sec. 2.1.
+ *   vgo_explore_clipped   Algorithm 2 on the diagram clipped to the unit
+ *                         cube: the faces of the cube join the generators
+ *                         as constraints of a vertex (face x_k = s has the
+ *                         code n + 2k + s in a key).
  *   vgo_mc_ray_weights    per-ray terms of the Monte-Carlo estimators of
  *                         Sec. 3.1 / Algorithm 3 (volume, area, and the
  *                         second moment used for the centroidal energy).
@@ -670,6 +674,210 @@ fail:
   free(M->bomit);
   free(M);
   return NULL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2b: Algorithm 2 on the clipped diagram.                                  */
+/*                                                                           */
+/* The cells are C_i intersected with the unit cube.  A vertex of the        */
+/* clipped diagram is a point of the cube fixed by d+1 constraints: a >= 1   */
+/* generators at a common smallest distance, and d+1-a faces x_k = s it lies */
+/* on.  Its key is the sorted tuple of the generator indices and the face    */
+/* codes n + 2k + s (so generators come first).  An edge keeps d of the      */
+/* constraints (at least one generator): the points that satisfy them form a */
+/* line, and the edge leaves the vertex along that line, away from the       */
+/* dropped constraint: away from a dropped generator j (it gets farther than */
+/* the kept ones), or off a dropped face into the cube.  RayCast with        */
+/* clipping ends the edge at the next generator or face.  Every edge is      */
+/* bounded, so every edge is found from both ends.  The search starts at the */
+/* corner 0, which lies in the cell of its nearest generator and on the d    */
+/* faces x_k = 0.                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* The vertex fixed by the d+1 constraints `key` (generator key[0] first):
+ * with y = v - x_a, each further generator b gives 2 (x_b - x_a).y =
+ * |x_b - x_a|^2 and each face x_k = s gives y_k = s - x_a,k.  Face
+ * coordinates are then set exactly. */
+static int clipped_vertex(int d, int64_t n, const double *X, const int32_t *key,
+                          double *v) {
+  double A[64 * 64], b[64], y[64];
+  const double *xa = X + (int64_t)key[0] * d;
+  for (int r = 0; r < d; ++r) {
+    int32_t c = key[r + 1];
+    for (int k = 0; k < d; ++k) A[r * d + k] = 0.0;
+    if (c < n) {
+      const double *xb = X + (int64_t)c * d;
+      double s2 = 0.0;
+      for (int k = 0; k < d; ++k) {
+        double e = xb[k] - xa[k];
+        A[r * d + k] = 2.0 * e;
+        s2 += e * e;
+      }
+      b[r] = s2;
+    } else {
+      int f = (int)(c - n), k = f / 2;
+      A[r * d + k] = 1.0;
+      b[r] = (double)(f % 2) - xa[k];
+    }
+  }
+  if (solve_dense(d, A, b, y)) return -1;
+  for (int k = 0; k < d; ++k) v[k] = xa[k] + y[k];
+  for (int r = 1; r <= d; ++r)
+    if (key[r] >= n) {
+      int f = (int)(key[r] - n);
+      v[f / 2] = (double)(f % 2);
+    }
+  return 0;
+}
+
+/* Direction of the edge that keeps the constraints eta (d of them, sorted,
+ * eta[0] a generator) and drops `omit`: the unit vector orthogonal to the
+ * kept faces' normals e_k and to x_g - x_eta0 for the kept generators g,
+ * pointing away from x_omit (a generator) or into the cube (a face).  Built
+ * as the component of w orthogonal to those vectors, by Gram-Schmidt applied
+ * twice with the face normals first, where w = -(x_omit - x_eta0) for a
+ * generator and w = +-e_k (into the cube) for a face.  Returns -1 when the
+ * component vanishes. */
+static int clipped_direction(int d, int64_t n, const double *X, const int32_t *eta,
+                             int32_t omit, double *u) {
+  double Q[64 * 64];
+  int q = 0;
+  const double *x0 = X + (int64_t)eta[0] * d;
+  for (int pass_kind = 0; pass_kind < 2; ++pass_kind) {
+    for (int a = 0; a < d; ++a) {
+      int is_f = eta[a] >= n;
+      if (is_f != (pass_kind == 0) || (!is_f && a == 0)) continue;
+      double *e = Q + q * d;
+      if (is_f) {
+        int k = (int)(eta[a] - n) / 2;
+        for (int c = 0; c < d; ++c) e[c] = (c == k) ? 1.0 : 0.0;
+      } else {
+        const double *xg = X + (int64_t)eta[a] * d;
+        for (int c = 0; c < d; ++c) e[c] = xg[c] - x0[c];
+      }
+      for (int pass = 0; pass < 2; ++pass)
+        for (int b = 0; b < q; ++b) {
+          double c = dot(e, Q + b * d, d);
+          for (int k = 0; k < d; ++k) e[k] -= c * Q[b * d + k];
+        }
+      double nr = sqrt(dot(e, e, d));
+      if (nr == 0.0) continue;
+      for (int k = 0; k < d; ++k) e[k] /= nr;
+      ++q;
+    }
+  }
+  if (omit < n) {
+    const double *xo = X + (int64_t)omit * d;
+    for (int k = 0; k < d; ++k) u[k] = x0[k] - xo[k];
+  } else {
+    int f = (int)(omit - n), k = f / 2;
+    for (int c = 0; c < d; ++c) u[c] = 0.0;
+    u[k] = (f % 2) ? -1.0 : 1.0;
+  }
+  for (int pass = 0; pass < 2; ++pass)
+    for (int b = 0; b < q; ++b) {
+      double c = dot(u, Q + b * d, d);
+      for (int k = 0; k < d; ++k) u[k] -= c * Q[b * d + k];
+    }
+  double nr = sqrt(dot(u, u, d));
+  if (!(nr > 0.0)) return -1;
+  for (int k = 0; k < d; ++k) u[k] /= nr;
+  return 0;
+}
+
+void *vgo_explore_clipped(int d, int64_t n, const double *X) {
+  if (d < 1 || d > 62 || n < 1) return NULL;
+  vgo_mesh *M = (vgo_mesh *)calloc(1, sizeof(vgo_mesh));
+  if (!M) return NULL;
+  M->d = d;
+  tmap G, V;
+  int ok = !tmap_init(&G, d, 1 << 12) && !tmap_init(&V, d + 1, 1 << 12);
+  int32_t s0[64], eta[64], key[64], gens[64];
+  double v[64], u[64];
+  int cr;
+  if (!ok) goto fail;
+  {
+    /* start: the corner 0 and its nearest generator (lowest index on ties) */
+    int64_t g0 = 0;
+    double best = VGO_INF;
+    for (int64_t i = 0; i < n; ++i) {
+      double s2 = dot(X + i * d, X + i * d, d);
+      if (s2 < best) {
+        best = s2;
+        g0 = i;
+      }
+    }
+    s0[0] = (int32_t)g0;
+    for (int k = 0; k < d; ++k) s0[k + 1] = (int32_t)(n + 2 * k);
+    for (int k = 0; k < d; ++k) v[k] = 0.0;
+    if (mesh_push_vertex(M, s0, v)) goto fail;
+    *tmap_slot(&V, s0, 1, &cr) = 0;
+    for (int o = 0; o <= d; ++o) {
+      int a = 0;
+      for (int b = 0; b <= d; ++b)
+        if (b != o) eta[a++] = s0[b];
+      *tmap_slot(&G, eta, 1, &cr) += 1;
+    }
+  }
+  for (int64_t head = 0; head < M->nv; ++head) {
+    int32_t sig[64];
+    double r[64];
+    memcpy(sig, M->sig + head * (d + 1), sizeof(int32_t) * (d + 1));
+    memcpy(r, M->coord + head * d, sizeof(double) * d);
+    for (int o = 0; o <= d; ++o) {
+      int a = 0, ng = 0;
+      for (int b = 0; b <= d; ++b)
+        if (b != o) eta[a++] = sig[b];
+      for (int b = 0; b < d; ++b)
+        if (eta[b] < n) gens[ng++] = eta[b];
+      if (ng == 0) continue; /* d faces meet in a corner, not along an edge */
+      int64_t *gc = tmap_slot(&G, eta, 0, &cr);
+      if (gc && *gc >= 2) continue;
+      if (clipped_direction(d, n, X, eta, sig[o], u)) continue;
+      double t, t2;
+      int32_t j;
+      M->raycasts++;
+      raycast_one(d, n, X, r, u, eta[0], gens, ng, 1, &t, &j, &t2);
+      if (j == -1) goto fail; /* a clipped ray always ends */
+      int32_t code = j >= 0 ? j : (int32_t)(n + (-2 - j));
+      for (int b = 0; b < d; ++b) key[b] = eta[b];
+      key[d] = code;
+      sort_small(key, d + 1);
+      int64_t *vs = tmap_slot(&V, key, 1, &cr);
+      if (!vs) goto fail;
+      if (!cr) {
+        M->duplicates++;
+        continue;
+      }
+      *vs = M->nv;
+      if (clipped_vertex(d, n, X, key, v)) goto fail;
+      if (mesh_push_vertex(M, key, v)) goto fail;
+      for (int o2 = 0; o2 <= d; ++o2) {
+        int a2 = 0;
+        int32_t e2[64];
+        for (int b = 0; b <= d; ++b)
+          if (b != o2) e2[a2++] = key[b];
+        int64_t *g2 = tmap_slot(&G, e2, 1, &cr);
+        if (!g2) goto fail;
+        *g2 += 1;
+      }
+    }
+  }
+  tmap_free(&G);
+  tmap_free(&V);
+  return M;
+fail:
+  tmap_free(&G);
+  tmap_free(&V);
+  free(M->sig);
+  free(M->coord);
+  free(M);
+  return NULL;
+}
+
+/* Exposed for the tests. */
+int vgo_clipped_vertex(int d, int64_t n, const double *X, const int32_t *key, double *v) {
+  return clipped_vertex(d, n, X, key, v);
 }
 
 /* The star of generator i: every vertex of the unbounded diagram whose
