@@ -276,27 +276,30 @@ def bench_incircle(args):
 
 
 def bench_explore(args):
-    """Exhaustive vertex search (Algorithm 2) of a uniform cloud."""
+    """Exhaustive vertex search (Algorithm 2) of a uniform cloud: the
+    unbounded diagram, or (clipped_*) the diagram clipped to the unit cube."""
     import torch
 
     import paper_2405_10050_amd as vg
     import workloads as W
 
-    n, d = (1000, 2) if args.workload == "uniform_d2_n1000" else (10_000, 6)
+    n, d = (1000, 2) if args.workload.endswith("d2_n1000") else (10_000, 6)
+    clip = args.workload.startswith("clipped")
     X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).cuda()
-    draws = W.descent_draws(d)
+    draws = None if clip else W.descent_draws(d)
     if args.warmup:
-        vg.explore(X, draws)
+        vg.explore(X, draws, clip=clip)
     t0 = time.perf_counter()
-    m = vg.explore(X, draws)
+    m = vg.explore(X, draws, clip=clip)
     dt = time.perf_counter() - t0
     nv = m["sigma"].shape[0]
+    kind = "diagram clipped to the unit cube (faces as vertex constraints)" if clip else "unbounded diagram"
     return {
         "metric": "vertices/sec exhaustive Voronoi vertex search",
         "value": nv / dt, "unit": "vertices/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"uniform d={d} N={n}, unbounded diagram", "vertices": nv,
+        "config": {"workload": f"uniform d={d} N={n}, {kind}", "vertices": nv,
                    "unbounded_edges": int(m["b_sigma"].shape[0]), "raycasts": m["raycasts"]},
     }
 
@@ -310,7 +313,8 @@ def main():
     ap.add_argument("--workload", default="gmm8_d10_n100000",
                     choices=["gmm8_d10_n100000", "uneven64", "uniform_d4_n50000",
                              "uniform_d2_n1000", "uniform_d6_n10000", "nbr_d4_n50000",
-                             "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000"])
+                             "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000",
+                             "clipped_d2_n1000", "clipped_d6_n10000"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -337,7 +341,8 @@ def main():
         other = {"uneven64": bench_uneven, "uniform_d4_n50000": bench_grad,
                  "uniform_d2_n1000": bench_explore, "uniform_d6_n10000": bench_explore,
                  "nbr_d4_n50000": bench_nbr, "nbr_d6_n10000": bench_nbr,
-                 "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle}
+                 "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle,
+                 "clipped_d2_n1000": bench_explore, "clipped_d6_n10000": bench_explore}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 

@@ -297,10 +297,17 @@ int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems,
  * keyed by its sorted (d+1)-tuple of generators, with FP64 coordinates
  * solved from the tuple, and every unbounded edge as (vertex, omitted
  * generator).  Rays are cast without clipping, in batches of one
- * breadth-first level; the edge visit counts and vertex set live in host
- * hash tables.  `descent_draws` is a HOST array [n_draws][d] f64 of standard
- * normal draws consumed in order by Descent.  Synchronises the stream.
- * The result is library-owned: query it, copy it out, free it. */
+ * breadth-first level; the edge visit counts and the vertex set live in
+ * device hash tables.  `descent_draws` is a HOST array [n_draws][d] f64 of
+ * standard normal draws consumed in order by Descent.
+ * flags: 0, or VG_CLIP for the diagram clipped to the unit cube [0,1]^d (the
+ * cells C_i intersected with the cube).  Its vertices are fixed by d+1
+ * constraints, generators and cube faces: a key holds the generator indices,
+ * then n_nodes + 2k + s for each face x_k = s the vertex lies on.  The search
+ * starts at the corner 0 (no Descent: draws may be NULL), rays are clipped,
+ * and there are no unbounded edges.  n_nodes >= 1 then.
+ * Synchronises the stream.  The result is library-owned: query it, copy it
+ * out, free it. */
 int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
                const double *descent_draws, int n_draws, uint32_t flags,
                vg_mesh **out);

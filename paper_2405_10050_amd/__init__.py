@@ -505,17 +505,22 @@ def raycast_batched(problems, clip=True, out=None):
     return outs
 
 
-def explore(nodes, descent_draws) -> dict:
-    """Exhaustive search (Algorithm 2) of the unbounded diagram.  Returns host
+def explore(nodes, descent_draws=None, clip=False) -> dict:
+    """Exhaustive search (Algorithm 2) of the unbounded diagram, or with
+    ``clip=True`` of the diagram clipped to the unit cube (keys then hold
+    ``n + 2k + s`` for the face ``x_k = s``; no draws needed).  Returns host
     arrays ``sigma [V, d+1]``, ``coord [V, d]`` (float64), ``b_sigma``,
     ``b_omit`` and ``raycasts``."""
     _dev(nodes, torch.float32, "nodes")
     n, d = nodes.shape
-    draws = np.ascontiguousarray(np.asarray(descent_draws, dtype=np.float64).reshape(-1, d))
+    if descent_draws is None:
+        draws = np.zeros((0, d))
+    else:
+        draws = np.ascontiguousarray(np.asarray(descent_draws, dtype=np.float64).reshape(-1, d))
     c = _ctx(nodes.device)
     mesh = ctypes.c_void_p()
-    _check(_lib.vg_explore(c, d, n, _ptr(nodes), draws.ctypes.data_as(ctypes.c_void_p), draws.shape[0],
-                           0, ctypes.byref(mesh)), c, "vg_explore")
+    _check(_lib.vg_explore(c, d, n, _ptr(nodes), draws.ctypes.data_as(ctypes.c_void_p) if draws.size else None,
+                           draws.shape[0], VG_CLIP if clip else 0, ctypes.byref(mesh)), c, "vg_explore")
     try:
         nv = _lib.vg_mesh_num_vertices(mesh)
         nb = _lib.vg_mesh_num_unbounded(mesh)

@@ -15,12 +15,14 @@ struct ExploreRays {
   const int32_t *item_o;   // [m] position in the key of the omitted generator
   double *o64, *u64;       // [m][d] ray origin and direction (FP64)
   int32_t *gen;            // [m]
-  int32_t *excl;           // [m][d] sorted eta
+  int32_t *excl;           // [m][d] kept generators, sorted, padded with INT32_MAX
   int32_t *ok;             // [m] direction well defined
   const int32_t *idx;      // [m] raycast result
   int32_t *new_keys;       // [m][d+1] (key[0] < 0: no vertex)
   double *new_coords;      // [m][d]
   int64_t n_nodes;         // nodes (for the sphere check)
+  int32_t face_base;       // clipped diagram: face x_k = s is face_base + 2k + s
+                           // in a key; INT32_MAX for the unbounded diagram
 };
 
 hipError_t launch_sphere_check(const ExploreRays &a, double *viol, hipStream_t s);
@@ -53,9 +55,10 @@ hipError_t eset_clear(ESet E, hipStream_t s);
 hipError_t vset_rebuild(VSet V, ESet E, const int32_t *vkeys, int64_t nv, int d, bool vertices,
                         bool edges, uint32_t *err, hipStream_t s);
 // flags[(v - lb)(d+1) + o] = 1 when the edge of vertex v omitting position o
-// has been seen fewer than two times.
-hipError_t frontier_flags(const int32_t *vkeys, int64_t lb, int64_t le, int d, ESet E, uint8_t *flags,
-                          uint32_t *err, hipStream_t s);
+// has been seen fewer than two times (and keeps a generator: entries below
+// face_base).
+hipError_t frontier_flags(const int32_t *vkeys, int64_t lb, int64_t le, int d, int32_t face_base, ESet E,
+                          uint8_t *flags, uint32_t *err, hipStream_t s);
 hipError_t frontier_items(const int64_t *sel, int64_t m, int64_t lb, int d, int64_t *item_v,
                           int32_t *item_o, hipStream_t s);
 // Claim, settle and verify the new tuples of a level; is_new marks the items

@@ -14,6 +14,14 @@
 // sequential sweep over each level.  The vertex set equals the sequential
 // algorithm's: batching only changes the order of discovery (and may
 // discover a vertex twice in one level, which the set absorbs).
+//
+// With VG_CLIP the diagram is clipped to the unit cube: a vertex is fixed by
+// d+1 constraints, generators at a common smallest distance and faces x_k = s
+// it lies on (key entry n + 2k + s, after the generators).  An edge keeps d
+// of them with at least one generator and leaves the vertex away from the
+// dropped one; rays are clipped, so a face hit -2-(2k+s) adds that face.
+// Every edge is bounded.  The search starts at the corner 0, in the cell of
+// its nearest generator, instead of at a Descent.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -98,8 +106,8 @@ extern "C" {
 
 int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const double *draws,
                int n_draws, uint32_t flags, vg_mesh **out) {
-  (void)flags;
   if (!ctx) return VG_EINVAL;
+  const bool clipped = (flags & VG_CLIP) != 0;
   ctx->err.clear();
   if (!out) {
     ctx->err = "out is NULL";
@@ -110,8 +118,18 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     ctx->err = "d outside [2, VG_MAX_DIM]";
     return VG_EUNSUPPORTED;
   }
-  if (n_nodes < d + 1 || n_nodes >= (int64_t(1) << 31) || !nodes || !draws || n_draws < 1) {
-    ctx->err = "explore needs n_nodes >= d+1, nodes and descent draws";
+  if (flags & ~(uint32_t)VG_CLIP) {
+    ctx->err = "explore takes VG_CLIP only";
+    return VG_EINVAL;
+  }
+  if (clipped ? (n_nodes < 1 || !nodes)
+              : (n_nodes < d + 1 || !nodes || !draws || n_draws < 1)) {
+    ctx->err = clipped ? "clipped explore needs n_nodes >= 1 and nodes"
+                       : "explore needs n_nodes >= d+1, nodes and descent draws";
+    return VG_EINVAL;
+  }
+  if (n_nodes >= (int64_t(1) << 31) - 2 * VG_MAX_DIM) {
+    ctx->err = "n_nodes too large for int32 keys";
     return VG_EINVAL;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) {
@@ -135,7 +153,25 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     if (rc != VG_OK) goto fail; \
   } while (0)
 
-  {
+  if (clipped) {
+    // ------------------------------------------- start at the corner 0
+    std::vector<float> xh((size_t)n_nodes * d);
+    EX_HIP(hipMemcpyAsync(xh.data(), nodes, sizeof(float) * xh.size(), hipMemcpyDeviceToHost, X.s));
+    EX_HIP(hipStreamSynchronize(X.s));
+    int64_t g0 = 0;
+    double best = 0.0;
+    for (int64_t i = 0; i < n_nodes; ++i) {
+      double s2 = 0.0;
+      for (int k = 0; k < d; ++k) s2 += (double)xh[i * d + k] * (double)xh[i * d + k];
+      if (i == 0 || s2 < best) {
+        best = s2;
+        g0 = i;
+      }
+    }
+    M->sig.assign(1, (int32_t)g0);
+    for (int k = 0; k < d; ++k) M->sig.push_back((int32_t)(n_nodes + 2 * k));
+    M->coord.assign(d, 0.0);
+  } else {
     // ---------------------------------------------------------- Descent
     // sigma = {0}, r = x_0; each step: next draw, project out span(X_sigma),
     // cast with eta = sigma (FP64 result), r += t u, add the hit generator.
@@ -228,6 +264,7 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     // The vertex set, the edge counts, the frontier and the unbounded edges
     // all live on the device; per level the host reads three counts.
     int64_t nv = 1, nb_total = 0, item_base = 0, vcap = 0, ecap = 0;
+    const int32_t face_base = clipped ? (int32_t)n_nodes : INT32_MAX;
     uint32_t *errd = nullptr;
     int64_t *cntd = nullptr;
     EX_HIP(X.counters.reserve(64, false, X.s));
@@ -313,8 +350,8 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       const int64_t cand = (level_end - level_begin) * L;
       EX_HIP(X.flags.reserve(cand, false, X.s));
       EX_HIP(X.sel.reserve(sizeof(int64_t) * cand, false, X.s));
-      EX_HIP(frontier_flags(X.keys_d.as<int32_t>(), level_begin, level_end, d, eset(), X.flags.as<uint8_t>(),
-                            errd, X.s));
+      EX_HIP(frontier_flags(X.keys_d.as<int32_t>(), level_begin, level_end, d, face_base, eset(),
+                            X.flags.as<uint8_t>(), errd, X.s));
       int64_t m = 0;
       EX_HIP(compact(X.flags, cand, X.sel, m));
       EX_RC(check_err());
@@ -355,8 +392,9 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       er.new_keys = X.nkeys.as<int32_t>();
       er.new_coords = X.ncoords.as<double>();
       er.n_nodes = n_nodes;
+      er.face_base = face_base;
       EX_HIP(launch_edge_rays(er, X.s));
-      EX_RC(raycast_f64(ctx, d, n_nodes, nodes, m, er.o64, er.u64, er.gen, er.excl, d, 0, false,
+      EX_RC(raycast_f64(ctx, d, n_nodes, nodes, m, er.o64, er.u64, er.gen, er.excl, d, clipped ? 1 : 0, false,
                         X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr));
       M->raycasts += m;
       EX_HIP(launch_new_vertices(er, X.s));

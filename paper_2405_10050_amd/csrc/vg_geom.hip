@@ -7,6 +7,11 @@
 //   * the vertex of sigma: the point equidistant to its d+1 generators, from
 //     2 (x_b - x_a).y = |x_b - x_a|^2 (y = v - x_a), Gaussian elimination
 //     with partial pivoting;
+//   * on the diagram clipped to the unit cube, keys also hold faces x_k = s
+//     (code face_base + 2k + s, after the generators): a kept face adds e_k
+//     to the span the direction is orthogonal to, a dropped face makes the
+//     direction point into the cube (w = -+e_k in place of x_omit - x_eta0),
+//     and a face of the vertex adds the row y_k = s - x_a,k to the solve;
 //   * the Descent projection (Algorithm 2): a random direction with its
 //     component in the span of X_sigma removed.
 #include "vg_internal.h"
@@ -15,14 +20,26 @@
 namespace vg {
 namespace {
 
+// Removes from w its components along span{e_k : faces among s} U
+// {X[s_j] - X[s_0] : generators s_j, j > 0} (s_0 a generator; faces are
+// the entries >= face_base), by Gram-Schmidt applied twice, faces first.
 template <int DK>
 __device__ void orth_complement(const float *__restrict__ X, int d, const int32_t *s, int m,
-                                double *w) {
-  // Q holds up to m-1 orthonormal vectors of span{X[s_j] - X[s_0]}
+                                int32_t face_base, double *w) {
+  // Q holds up to m-1 orthonormal vectors of the span
   double Q[DK - 1 > 0 ? DK - 1 : 1][DK];
   int q = 0;
   const float *x0 = X + (int64_t)s[0] * d;
   for (int j = 1; j < m; ++j) {
+    if (s[j] < face_base) continue;
+    // a face normal is orthogonal to the other faces' (distinct axes)
+    const int k0 = (s[j] - face_base) / 2;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) Q[q][k] = (k == k0) ? 1.0 : 0.0;
+    ++q;
+  }
+  for (int j = 1; j < m; ++j) {
+    if (s[j] >= face_base) continue;
     const float *xj = X + (int64_t)s[j] * d;
     double e[DK];
 #pragma unroll
@@ -57,7 +74,8 @@ __device__ void orth_complement(const float *__restrict__ X, int d, const int32_
 }
 
 template <int DK>
-__device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *s, double *v) {
+__device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *s, int32_t face_base,
+                             double *v) {
   double A[DK][DK], b[DK], y[DK];
   const float *xa = X + (int64_t)s[0] * d;
   for (int r = 0; r < DK; ++r) {
@@ -65,6 +83,12 @@ __device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *
     for (int k = 0; k < DK; ++k) A[r][k] = 0.0;
   }
   for (int r = 0; r < d; ++r) {
+    if (s[r + 1] >= face_base) {  // face x_k = side: y_k = side - x_a,k
+      const int f = s[r + 1] - face_base;
+      A[r][f / 2] = 1.0;
+      b[r] = (double)(f % 2) - (double)xa[f / 2];
+      continue;
+    }
     const float *xb = X + (int64_t)s[r + 1] * d;
     double acc = 0.0;
     for (int k = 0; k < d; ++k) {
@@ -105,6 +129,8 @@ __device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *
     y[c] = acc / A[c][c];
   }
   for (int k = 0; k < d; ++k) v[k] = (double)xa[k] + y[k];
+  for (int r = 1; r <= d; ++r)  // a vertex on a face lies on it exactly
+    if (s[r] >= face_base) v[(s[r] - face_base) / 2] = (double)((s[r] - face_base) % 2);
   return true;
 }
 
@@ -122,23 +148,32 @@ __global__ __launch_bounds__(128) void edge_rays_kernel(ExploreRays a) {
   for (int b = 0; b <= d; ++b)
     if (b != o) eta[q++] = sig[b];
   const int32_t omit = sig[o];
+  const int32_t fb = a.face_base;
   double w[DK];
   const float *x0 = a.nodes + (int64_t)eta[0] * d;
-  const float *xo = a.nodes + (int64_t)omit * d;
+  if (omit < fb) {
+    const float *xo = a.nodes + (int64_t)omit * d;
 #pragma unroll
-  for (int k = 0; k < DK; ++k) w[k] = (k < d) ? (double)xo[k] - (double)x0[k] : 0.0;
-  orth_complement<DK>(a.nodes, d, eta, d, w);
+    for (int k = 0; k < DK; ++k) w[k] = (k < d) ? (double)xo[k] - (double)x0[k] : 0.0;
+  } else {  // off the face x_k = side, into the cube: u_k of sign 1 - 2 side
+    const int f = omit - fb;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) w[k] = (k == f / 2) ? ((f % 2) ? 1.0 : -1.0) : 0.0;
+  }
+  orth_complement<DK>(a.nodes, d, eta, d, fb, w);
   double nr = 0.0;
 #pragma unroll
   for (int k = 0; k < DK; ++k) nr += w[k] * w[k];
   nr = sqrt(nr);
+  const bool good = nr > 0.0 && eta[0] < fb;
   for (int k = 0; k < d; ++k) {
-    a.u64[it * d + k] = nr > 0.0 ? -w[k] / nr : 0.0;
+    a.u64[it * d + k] = good ? -w[k] / nr : 0.0;
     a.o64[it * d + k] = a.coords[v * d + k];
   }
   a.gen[it] = eta[0];
-  for (int b = 0; b < d; ++b) a.excl[it * d + b] = eta[b];
-  a.ok[it] = nr > 0.0 ? 1 : 0;
+  // the kept generators (sorted, first in the key), padded past the end
+  for (int b = 0; b < d; ++b) a.excl[it * d + b] = eta[b] < fb ? eta[b] : INT32_MAX;
+  a.ok[it] = good ? 1 : 0;
 }
 
 // New vertex of each hit: key sort(eta U {j}) and its FP64 coordinates.
@@ -147,27 +182,31 @@ __global__ __launch_bounds__(128) void new_vertex_kernel(ExploreRays a) {
   const int64_t it = (int64_t)blockIdx.x * 128 + threadIdx.x;
   if (it >= a.m) return;
   const int d = a.d;
-  const int32_t j = a.idx[it];
+  const int32_t hit = a.idx[it];
   int32_t *key = a.new_keys + it * (d + 1);
-  if (j < 0 || !a.ok[it]) {
+  if (hit == -1 || !a.ok[it]) {
     key[0] = -1;
     return;
   }
-  const int32_t *eta = a.excl + it * d;
+  // a face hit -2-f (clipped rays only) is the constraint face_base + f
+  const int32_t j = hit >= 0 ? hit : a.face_base + (-2 - hit);
+  const int32_t *sig = a.keys + a.item_v[it] * (d + 1);
+  const int o = a.item_o[it];
   int q = 0;
   bool placed = false;
-  for (int b = 0; b < d; ++b) {
-    if (!placed && j < eta[b]) {
+  for (int b = 0; b <= d; ++b) {
+    if (b == o) continue;
+    if (!placed && j < sig[b]) {
       key[q++] = j;
       placed = true;
     }
-    key[q++] = eta[b];
+    key[q++] = sig[b];
   }
   if (!placed) key[q++] = j;
   double v[DK];
   int32_t ks[DK + 1];
   for (int b = 0; b <= d; ++b) ks[b] = key[b];
-  if (!solve_vertex<DK>(a.nodes, d, ks, v)) {
+  if (!solve_vertex<DK>(a.nodes, d, ks, a.face_base, v)) {
     key[0] = -2;  // singular: degenerate input
     return;
   }
@@ -181,7 +220,7 @@ __global__ void descent_project_kernel(const float *X, int d, const int32_t *sig
   double w[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) w[k] = (k < d) ? u[k] : 0.0;
-  orth_complement<DK>(X, d, sig, m, w);
+  orth_complement<DK>(X, d, sig, m, INT32_MAX, w);
   double nr = 0.0;
 #pragma unroll
   for (int k = 0; k < DK; ++k) nr += w[k] * w[k];
@@ -201,7 +240,7 @@ __global__ void solve_one_kernel(const float *X, int d, const int32_t *sig, doub
   int32_t ks[DK + 1];
   for (int b = 0; b <= d; ++b) ks[b] = sig[b];
   double vv[DK];
-  const bool good = solve_vertex<DK>(X, d, ks, vv);
+  const bool good = solve_vertex<DK>(X, d, ks, INT32_MAX, vv);
   for (int k = 0; k < d; ++k) v[k] = good ? vv[k] : 0.0;
   *ok = good ? 1 : 0;
 }

@@ -70,14 +70,21 @@ __device__ __forceinline__ void edge_of(const int32_t *key, int d, int o, int32_
 }
 
 __global__ void frontier_flags_kernel(const int32_t *__restrict__ vkeys, int64_t lb, int64_t le,
-                                      int d, ESet E, uint8_t *__restrict__ flags, uint32_t *err) {
+                                      int d, int32_t face_base, ESet E, uint8_t *__restrict__ flags,
+                                      uint32_t *err) {
   const int64_t t = (int64_t)blockIdx.x * kBlk + threadIdx.x;
   const int L = d + 1;
   if (t >= (le - lb) * L) return;
   const int64_t v = lb + t / L;
   const int o = (int)(t - (t / L) * L);
+  const int32_t *key = vkeys + v * L;
+  // d faces meet in a corner of the cube, not along an edge
+  if (key[o] < face_base && (L < 2 || key[1] >= face_base)) {
+    flags[t] = 0;
+    return;
+  }
   int32_t eta[VG_MAX_DIM];
-  edge_of(vkeys + v * L, d, o, eta);
+  edge_of(key, d, o, eta);
   const int64_t h = lookup(E.fp, E.cap, tuple_fp(eta, d));
   uint32_t c = 0;
   if (h >= 0) {
@@ -104,7 +111,7 @@ __global__ void vset_claim_kernel(VSet V, const int32_t *__restrict__ nkeys, con
   if (it >= m) return;
   slot[it] = -1;
   const int32_t *key = nkeys + it * V.L;
-  if (idx[it] < 0) return;  // no hit: an unbounded edge
+  if (idx[it] == -1) return;  // no hit: an unbounded edge (-2-f is a face hit)
   if (key[0] == -2) {
     atomicOr(err, VSET_SINGULAR);
     return;
@@ -125,7 +132,7 @@ __global__ void vset_settle_kernel(VSet V, const int32_t *__restrict__ nkeys, co
                                    uint8_t *__restrict__ is_new, uint8_t *__restrict__ is_unb) {
   const int64_t it = (int64_t)blockIdx.x * kBlk + threadIdx.x;
   if (it >= m) return;
-  is_unb[it] = idx[it] < 0 ? 1 : 0;
+  is_unb[it] = idx[it] == -1 ? 1 : 0;
   const int64_t h = slot[it];
   const bool own = h >= 0 && V.owner[h] == item_base + it;
   is_new[it] = own ? 1 : 0;
@@ -295,12 +302,12 @@ hipError_t vset_rebuild(VSet V, ESet E, const int32_t *vkeys, int64_t nv, int d,
   return hipGetLastError();
 }
 
-hipError_t frontier_flags(const int32_t *vkeys, int64_t lb, int64_t le, int d, ESet E, uint8_t *flags,
-                          uint32_t *err, hipStream_t s) {
+hipError_t frontier_flags(const int32_t *vkeys, int64_t lb, int64_t le, int d, int32_t face_base, ESet E,
+                          uint8_t *flags, uint32_t *err, hipStream_t s) {
   const int64_t cnt = (le - lb) * (d + 1);
   if (cnt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(frontier_flags_kernel, dim3(grid_of(cnt)), dim3(kBlk), 0, s, vkeys, lb, le, d, E,
-                     flags, err);
+  hipLaunchKernelGGL(frontier_flags_kernel, dim3(grid_of(cnt)), dim3(kBlk), 0, s, vkeys, lb, le, d,
+                     face_base, E, flags, err);
   return hipGetLastError();
 }
 

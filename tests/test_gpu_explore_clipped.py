@@ -1,0 +1,101 @@
+"""GPU exhaustive search of the diagram clipped to the unit cube (Algorithm 2
+with the cube's faces as constraints, VG_CLIP) against the FP64 oracle:
+vertex keys bit-exact as sets, FP64 coordinates to 1e-9; at d=6, N=10 000
+against properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vg():
+    import paper_2405_10050_amd as vg
+    return vg
+
+
+def _by_key(m):
+    return {tuple(int(c) for c in row): v for row, v in zip(m["sigma"], m["coord"])}
+
+
+@pytest.mark.parametrize("d,n,seed", [(2, 1, 0), (2, 2, 1), (2, 7, 2), (2, 1000, 0), (3, 1, 0), (3, 300, 1),
+                                      (4, 100, 2), (5, 40, 3), (6, 30, 4)])
+def test_clipped_explore_matches_oracle(vg, d, n, seed):
+    print(f"clipped explore d={d} n={n} seed={seed}", flush=True)
+    X = W.uniform_cloud(n, d, seed=seed)
+    got = vg.explore(torch.from_numpy(X).cuda(), clip=True)
+    ref = oracle.explore_clipped(X)
+    assert got["b_sigma"].shape[0] == 0
+    g, r = _by_key(got), _by_key(ref)
+    assert set(g) == set(r)
+    worst = max(float(np.abs(g[k] - r[k]).max()) for k in r)
+    assert worst <= 1e-9, worst
+    if d == 2:
+        assert len(g) == 2 * n + 2  # planar clipped diagram
+
+
+def test_clipped_explore_unit_square_workload(vg):
+    """The d=2, N=1000 workload on the unit square: 2N + 2 vertices, and the
+    face-free ones are the unbounded diagram's vertices inside the square."""
+    d, n = 2, 1000
+    X = W.uniform_cloud(n, d, seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    clipped = vg.explore(Xd, clip=True)
+    full = vg.explore(Xd, W.descent_draws(d))
+    inner = {tuple(r) for r in clipped["sigma"][(clipped["sigma"] < n).all(axis=1)].tolist()}
+    inside = {tuple(r) for r in full["sigma"][((full["coord"] > 0) & (full["coord"] < 1)).all(axis=1)].tolist()}
+    assert inner == inside
+    assert clipped["sigma"].shape[0] == 2 * n + 2
+
+
+def _edge_counts(sigma, n):
+    """How many vertices see each edge (d-tuple keeping a generator), via a
+    64-bit hash of the sorted tuple."""
+    V, L = sigma.shape
+    rng = np.random.default_rng(0)
+    mult = rng.integers(1, 2**62, size=L - 1, dtype=np.int64) | 1
+    hs, keep = [], []
+    for o in range(L):
+        e = np.delete(sigma, o, axis=1).astype(np.int64)
+        hs.append((e * mult).sum(axis=1))  # wraps mod 2^64
+        keep.append(e[:, 0] < n)  # sorted: a generator first, if any
+    h = np.concatenate(hs)[np.concatenate(keep)]
+    _, cnt = np.unique(h, return_counts=True)
+    return cnt
+
+
+def test_clipped_explore_d6_n10000_properties(vg):
+    d, n = 6, 10_000
+    X = W.uniform_cloud(n, d, seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    clipped = vg.explore(Xd, clip=True)
+    sig, coord = clipped["sigma"], clipped["coord"]
+    print(f"  clipped d=6 N=10000: {sig.shape[0]} vertices, {clipped['raycasts']} raycasts", flush=True)
+    # every vertex inside the cube, on exactly the faces of its key
+    assert np.all(coord >= -1e-12) and np.all(coord <= 1 + 1e-12)
+    # face-free vertices = the unbounded diagram's vertices inside the cube
+    full = vg.explore(Xd, W.descent_draws(d))
+    inner = sig[(sig < n).all(axis=1)]
+    inside = full["sigma"][((full["coord"] > 0) & (full["coord"] < 1)).all(axis=1)]
+    a = np.unique(inner, axis=0)
+    b = np.unique(inside, axis=0)
+    assert a.shape == b.shape and np.array_equal(a, b)
+    # every edge is bounded, so it is seen from both ends
+    cnt = _edge_counts(sig, n)
+    assert cnt.min() == 2 and cnt.max() == 2
+    # sampled vertices: generators of the key equidistant, no generator closer
+    X64 = X.astype(np.float64)
+    for v in np.random.default_rng(1).choice(sig.shape[0], 300, replace=False):
+        key, p = sig[v], coord[v]
+        gens = key[key < n]
+        d2 = ((X64 - p) ** 2).sum(axis=1)
+        rho = d2[gens]
+        assert rho.max() - rho.min() <= 1e-9 * rho.max()
+        others = np.delete(d2, gens)
+        assert others.min() >= rho.min() * (1 - 1e-9)
+        for f in key[key >= n] - n:
+            assert p[f // 2] == float(f % 2)
