@@ -40,6 +40,11 @@ Pins (what each function is checked against, in ``tests/test_oracle_*.py``):
                             face-free vertices are the unbounded diagram's
                             vertices inside the cube; every edge seen by
                             exactly two vertices.
+  hmc_integrals             f = 1 turns F into the areas and the cell integral
+                            into the volume-from-areas identity; 2-D with
+                            exact edge lengths: exact cell and edge integrals
+                            of a linear f; 3-D with exact facet areas: f = 1
+                            gives the convex-hull cell volumes.
   mc_integrals              f = 1 gives the facet areas, and t = 1 (t = 1/2)
                             gives d (d 2^{1-d}) times the volume, exactly;
                             2-D: exact cell and edge integrals of a linear f
@@ -268,6 +273,60 @@ def clipped_vertex(nodes, key):
     if lib.vgo_clipped_vertex(d, n, _p(X), _p(_i32(np.sort(key))), _p(v)):
         raise ValueError("singular constraints")
     return v
+
+
+def hmc_integrals(nodes, sigma, coord, areas, f):
+    """Heuristic Monte-Carlo integrals (Sec. 3.3) over the clipped diagram.
+
+    ``sigma``/``coord`` are the clipped vertex set (``explore_clipped``),
+    ``areas`` a dict ``(i, j) -> A_ij`` of interface areas keyed like
+    ``mc_volume_area``'s facets (``j`` a generator, or ``-2-(2k+s)`` for the
+    face ``x_k = s``), ``f`` maps float64 points ``[P, d]`` to ``[P]``.  For
+    every facet with an area:
+
+      V_ij      = the vertices whose key holds both i and j (K_ij of them)
+      y_ij      = K_ij^{-1} sum_k nu_k                       (its centroid)
+      F_ij      = d/(d+1) K_ij^{-1} sum_k f(nu_k) A_ij + 1/(d+1) f(y_ij) A_ij
+      h_ij      = distance of x_i to the facet's hyperplane: |x_j - x_i|/2,
+                  or x_i,k (s = 0) / 1 - x_i,k (s = 1) for a face
+      volume_i  = 1/d sum_j h_ij A_ij
+      cell_i    = sum_j h_ij/d (d/(d+1) F_ij + 1/(d+1) A_ij f(x_i))
+
+    the last being the pyramid rule of eq. (leibniz-int) applied to the
+    pyramid over each facet with apex x_i.  Returns a dict with
+    ``centroid`` and ``F`` (dicts keyed like ``areas``), ``cell`` and
+    ``volume`` ``[n]``."""
+    X = _f64(nodes)
+    n, d = X.shape
+    sig = np.asarray(sigma)
+    P = _f64(coord)
+    members = {}
+    for v, row in enumerate(sig):
+        for a in row:
+            if a >= n:
+                continue
+            for b in row:
+                if b == a:
+                    continue
+                j = int(b) if b < n else -2 - int(b - n)
+                members.setdefault((int(a), j), []).append(v)
+    fv = np.asarray(f(P), dtype=np.float64)
+    fx = np.asarray(f(X), dtype=np.float64)
+    keys = [k for k in areas if k in members]
+    cent = {k: P[members[k]].mean(axis=0) for k in keys}
+    fy = dict(zip(keys, np.asarray(f(np.array([cent[k] for k in keys]).reshape(-1, d)), dtype=np.float64)))
+    F, cell, volume = {}, np.zeros(n), np.zeros(n)
+    for (i, j) in keys:
+        A = areas[(i, j)]
+        F[(i, j)] = d / (d + 1) * fv[members[(i, j)]].mean() * A + fy[(i, j)] * A / (d + 1)
+        if j >= 0:
+            h = 0.5 * np.sqrt(((X[j] - X[i]) ** 2).sum())
+        else:
+            k, side = divmod(-2 - j, 2)
+            h = X[i, k] if side == 0 else 1.0 - X[i, k]
+        volume[i] += h * A / d
+        cell[i] += h / d * (d / (d + 1) * F[(i, j)] + A * fx[i] / (d + 1))
+    return dict(centroid=cent, F=F, cell=cell, volume=volume)
 
 
 def star(nodes, i, draws, cap=200_000):
