@@ -275,6 +275,63 @@ def bench_incircle(args):
     }
 
 
+def bench_hmc(args):
+    """Integrals of f(x) = |x - 1/2|^2 over every cell, d=5, N=10 000, 1000
+    rays per cell (the sizes of the paper's comparison of the integrators in
+    Sec. 4): the clipped vertex search once, then per step the Monte-Carlo
+    forward pass (areas) and the heuristic integrals of Sec. 3.3 from the
+    vertices.  The Monte-Carlo integrals of Algorithm 3 with m = 2 draws are
+    timed beside them.  The integral over the cube is d/12 exactly."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    d, n, R, m = 5, 10_000, 1000, 2
+    dev = torch.device("cuda", 0)
+    X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).to(dev)
+    D = W.mc_directions_device(n, R, d, seed=1, device=dev)
+    T = torch.rand((n, R, m), generator=torch.Generator(device=dev).manual_seed(2), device=dev)
+    T.clamp_(min=1e-7, max=1 - 1e-7)
+    f = lambda p: ((p - 0.5) ** 2).sum(dim=1)  # noqa: E731
+    t0 = time.perf_counter()
+    mesh = vg.explore(X, clip=True)
+    t_explore = time.perf_counter() - t0
+    stream = torch.cuda.current_stream(dev)
+    res = vg.mc_volume_area(X, D)
+
+    def step():
+        vg.mc_volume_area(X, D, out=res)
+        return vg.hmc_integrals(X, mesh, res, f)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    t0 = time.perf_counter()
+    vg.mc_volume_area(X, D, out=res)
+    mci = vg.mc_integrals(X, D, res, f, T)
+    torch.cuda.synchronize()
+    ms_mc = (time.perf_counter() - t0) * 1e3
+    exact = d / 12.0
+    return {
+        "metric": "cells/s heuristic Monte-Carlo integrals (d=5, N=10000, 1000 rays/cell)",
+        "value": n / (ms / 1e3), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "uniform d=5 N=10000, 1000 MC rays per cell, f = |x - 1/2|^2, clipped diagram",
+                   "explore_s": t_explore, "vertices": int(mesh["sigma"].shape[0]),
+                   "mc_integrals_ms_per_step": ms_mc,
+                   "hmc_total_rel_err": float(out.cell.double().sum().item()) / exact - 1.0,
+                   "mc_total_rel_err": float(mci.volume.double().sum().item()) / exact - 1.0,
+                   "hmc_volume_sum": float(out.volume.double().sum().item())},
+    }
+
+
 def bench_explore(args):
     """Exhaustive vertex search (Algorithm 2) of a uniform cloud: the
     unbounded diagram, or (clipped_*) the diagram clipped to the unit cube."""
@@ -314,7 +371,7 @@ def main():
                     choices=["gmm8_d10_n100000", "uneven64", "uniform_d4_n50000",
                              "uniform_d2_n1000", "uniform_d6_n10000", "nbr_d4_n50000",
                              "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000",
-                             "clipped_d2_n1000", "clipped_d6_n10000"])
+                             "clipped_d2_n1000", "clipped_d6_n10000", "hmc_d5_n10000"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -342,7 +399,8 @@ def main():
                  "uniform_d2_n1000": bench_explore, "uniform_d6_n10000": bench_explore,
                  "nbr_d4_n50000": bench_nbr, "nbr_d6_n10000": bench_nbr,
                  "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle,
-                 "clipped_d2_n1000": bench_explore, "clipped_d6_n10000": bench_explore}
+                 "clipped_d2_n1000": bench_explore, "clipped_d6_n10000": bench_explore,
+                 "hmc_d5_n10000": bench_hmc}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 

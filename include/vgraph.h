@@ -292,6 +292,40 @@ typedef struct vg_cells_problem {
 int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems,
                              const vg_cells_problem *probs, uint32_t flags);
 
+/* Heuristic Monte-Carlo integrals (Sec. 3.3) over the diagram clipped to the
+ * unit cube, from its vertex set (vg_explore with VG_CLIP: sigma, coords)
+ * and the Monte-Carlo facet rows of every cell (vg_mc_volume_area: facet_j,
+ * facet_area, facet_count; a face is -2-(2k+s) there and n_nodes + 2k + s in
+ * sigma).  For facet (i, j): V_ij = the vertices whose key holds i and j
+ * (K_ij), y_ij = their mean, F_ij = A_ij (d/(d+1) mean f(V_ij) + 1/(d+1)
+ * f(y_ij)); the cell integral sums the pyramid rule of eq. (leibniz-int)
+ * over the facets with apex x_i: sum_j h_ij/d (d/(d+1) F_ij + 1/(d+1) A_ij
+ * f(x_i)), and the volume is sum_j h_ij A_ij / d, with h_ij = |x_j - x_i|/2
+ * or the distance of x_i to the face.  Two calls, the caller evaluating f in
+ * between:
+ *
+ * vg_hmc_centroids: centroid [n_nodes][rays_per_cell][d] f32 and kcount
+ *   [n_nodes][rays_per_cell] i32 (K_ij) of every facet row.
+ * vg_hmc_integrals: with f at the vertices f_vertex [V] f32, at the
+ *   centroids f_centroid [n_nodes][rays_per_cell] f32 and at the generators
+ *   f_node [n_nodes] f32: fint_facet [n_nodes][rays_per_cell] f32 (F_ij,
+ *   aligned with the facet rows), fint_cell [n_nodes] f32, volume
+ *   [n_nodes] f32.
+ * All arrays are DEVICE, sigma [V][d+1] i32, coords [V][d] f64.  Rows past
+ * facet_count are not touched.  A facet row whose pair no vertex holds, or
+ * out-of-range keys or codes, give VG_EINVAL.  Both calls allocate
+ * temporary device memory (the cells' vertex lists, one sort) and
+ * synchronise the stream; results are bitwise reproducible. */
+int vg_hmc_centroids(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t n_vertices,
+                     const int32_t *sigma, const double *coords, int rays_per_cell,
+                     const int32_t *facet_j, const int32_t *facet_count, float *centroid,
+                     int32_t *kcount);
+int vg_hmc_integrals(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t n_vertices,
+                     const int32_t *sigma, const float *f_vertex, int rays_per_cell,
+                     const int32_t *facet_j, const float *facet_area, const int32_t *facet_count,
+                     const float *f_centroid, const float *f_node, float *fint_facet,
+                     float *fint_cell, float *volume);
+
 /* ------------------------------------------------------ exhaustive search */
 /* Algorithm 2 (VoronoiGraph) on the unbounded diagram: every Voronoi vertex
  * keyed by its sorted (d+1)-tuple of generators, with FP64 coordinates

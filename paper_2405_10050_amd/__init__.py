@@ -75,7 +75,7 @@ EXPORTS = (
     "vg_set_profiling", "vg_raycast",
     "vg_raycast_cells", "vg_mc_volume_area", "vg_mc_backward", "vg_raycast_cells_batched",
     "vg_raycast_batched", "vg_mc_volume_area_nbr", "vg_tuple_neighbors", "vg_mc_sample_points",
-    "vg_mc_integrals",
+    "vg_mc_integrals", "vg_hmc_centroids", "vg_hmc_integrals",
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
     "vg_mesh_copy", "vg_mesh_free",
 )
@@ -105,6 +105,8 @@ def _load_lib():
     lib.vg_tuple_neighbors.argtypes = [P, I, I64, I64, P, P, P, I64, ctypes.POINTER(I64)]
     lib.vg_mc_sample_points.argtypes = [P, I, I64, P, I, P, P, I, P, P]
     lib.vg_mc_integrals.argtypes = [P, I, I64, P, I, P, P, I, P, P, P, P, P, P]
+    lib.vg_hmc_centroids.argtypes = [P, I, I64, P, I64, P, P, I, P, P, P, P]
+    lib.vg_hmc_integrals.argtypes = [P, I, I64, P, I64, P, P, I, P, P, P, P, P, P, P, P]
     lib.vg_explore.argtypes = [P, I, I64, P, P, I, U32, ctypes.POINTER(P)]
     for f in ("vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts"):
         getattr(lib, f).argtypes = [P]
@@ -361,6 +363,57 @@ def mc_integrals(nodes, dirs, res: MCResult, f, tsamp=None) -> MCIntegrals:
     _check(_lib.vg_mc_integrals(c, d, n, _ptr(nodes), R, _ptr(res.t), _ptr(res.idx), m, _ptr(tsamp),
                                 _ptr(fvals), _ptr(out.volume), _ptr(out.facet_j), _ptr(out.facet),
                                 _ptr(out.facet_count)), c, "vg_mc_integrals")
+    return out
+
+
+@dataclass
+class HMCResult:
+    cell: torch.Tensor       # [N] heuristic integral of f over each cell
+    volume: torch.Tensor     # [N] volume from the areas, sum_j h_ij A_ij / d
+    facet: torch.Tensor      # [N, R] integral of f over each facet row of the forward result
+    centroid: torch.Tensor   # [N, R, d] centroid of each facet's vertices
+    kcount: torch.Tensor     # [N, R] number of those vertices
+
+
+def hmc_integrals(nodes, mesh, res: MCResult, f) -> HMCResult:
+    """Heuristic Monte-Carlo integrals of ``f`` (Sec. 3.3): the facet
+    integrals from the vertices of each facet of the clipped diagram
+    (``mesh`` = :func:`explore` with ``clip=True``) and its Monte-Carlo area
+    in ``res`` (:func:`mc_volume_area`), and the cell integrals by the
+    pyramid rule over the facets.  ``f`` maps float32 GPU points ``[P, d]``
+    to ``[P]``; it is called on the vertices, the facet centroids and the
+    generators."""
+    _dev(nodes, torch.float32, "nodes")
+    dev = nodes.device
+    n, d = nodes.shape
+    R = res.facet_j.shape[1]
+    sig = torch.from_numpy(np.ascontiguousarray(mesh["sigma"], dtype=np.int32)).to(dev)
+    coord = torch.from_numpy(np.ascontiguousarray(mesh["coord"], dtype=np.float64)).to(dev)
+    V = sig.shape[0]
+    if sig.shape != (V, d + 1) or coord.shape != (V, d):
+        raise ValueError("mesh must hold sigma [V, d+1] and coord [V, d]")
+    centroid = torch.empty((n, R, d), dtype=torch.float32, device=dev)
+    kcount = torch.empty((n, R), dtype=torch.int32, device=dev)
+    c = _ctx(dev)
+    _check(_lib.vg_hmc_centroids(c, d, n, _ptr(nodes), V, _ptr(sig), _ptr(coord), R, _ptr(res.facet_j),
+                                 _ptr(res.facet_count), _ptr(centroid), _ptr(kcount)), c, "vg_hmc_centroids")
+
+    def values(p, count):
+        v = f(p)
+        if not isinstance(v, torch.Tensor) or v.numel() != count:
+            raise ValueError("f must return one value per point")
+        return v.to(device=dev, dtype=torch.float32).contiguous()
+
+    fv = values(coord.to(torch.float32), V)
+    fc = values(centroid.view(-1, d), n * R)
+    fx = values(nodes, n)
+    out = HMCResult(cell=torch.empty(n, dtype=torch.float32, device=dev),
+                    volume=torch.empty(n, dtype=torch.float32, device=dev),
+                    facet=torch.empty((n, R), dtype=torch.float32, device=dev),
+                    centroid=centroid, kcount=kcount)
+    _check(_lib.vg_hmc_integrals(c, d, n, _ptr(nodes), V, _ptr(sig), _ptr(fv), R, _ptr(res.facet_j),
+                                 _ptr(res.facet_area), _ptr(res.facet_count), _ptr(fc), _ptr(fx),
+                                 _ptr(out.facet), _ptr(out.cell), _ptr(out.volume)), c, "vg_hmc_integrals")
     return out
 
 

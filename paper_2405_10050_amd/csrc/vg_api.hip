@@ -507,6 +507,43 @@ int vg_mc_integrals(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int
   return VG_OK;
 }
 
+static int hmc_check(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t n_vertices,
+                     const int32_t *sigma, int rays_per_cell, const int32_t *facet_j,
+                     const int32_t *facet_count) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (n_vertices < 0 || (n_vertices > 0 && !sigma)) return fail(ctx, VG_EINVAL, "bad vertex array");
+  if (n_nodes + 2 * d >= (int64_t(1) << 31)) return fail(ctx, VG_EINVAL, "n_nodes too large for int32 keys");
+  if (!facet_j || !facet_count) return fail(ctx, VG_EINVAL, "null facet array");
+  return VG_OK;
+}
+
+int vg_hmc_centroids(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t n_vertices,
+                     const int32_t *sigma, const double *coords, int rays_per_cell, const int32_t *facet_j,
+                     const int32_t *facet_count, float *centroid, int32_t *kcount) {
+  int rc = hmc_check(ctx, d, n_nodes, nodes, n_vertices, sigma, rays_per_cell, facet_j, facet_count);
+  if (rc) return rc;
+  if (!coords || !centroid || !kcount) return fail(ctx, VG_EINVAL, "null array");
+  return hmc_run(false, d, n_nodes, nodes, n_vertices, sigma, coords, nullptr, rays_per_cell, facet_j, nullptr,
+                 facet_count, nullptr, nullptr, centroid, kcount, nullptr, nullptr, nullptr, ctx->stream,
+                 ctx->err);
+}
+
+int vg_hmc_integrals(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t n_vertices,
+                     const int32_t *sigma, const float *f_vertex, int rays_per_cell, const int32_t *facet_j,
+                     const float *facet_area, const int32_t *facet_count, const float *f_centroid,
+                     const float *f_node, float *fint_facet, float *fint_cell, float *volume) {
+  int rc = hmc_check(ctx, d, n_nodes, nodes, n_vertices, sigma, rays_per_cell, facet_j, facet_count);
+  if (rc) return rc;
+  if (!f_vertex || !facet_area || !f_centroid || !f_node || !fint_facet || !fint_cell || !volume)
+    return fail(ctx, VG_EINVAL, "null array");
+  return hmc_run(true, d, n_nodes, nodes, n_vertices, sigma, nullptr, f_vertex, rays_per_cell, facet_j,
+                 facet_area, facet_count, f_centroid, f_node, nullptr, nullptr, fint_facet, fint_cell, volume,
+                 ctx->stream, ctx->err);
+}
+
 int vg_tuple_neighbors(vg_ctx *ctx, int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sigma,
                        int64_t *offsets, int32_t *nbr, int64_t nbr_capacity, int64_t *nnz) {
   if (!ctx) return VG_EINVAL;

@@ -161,6 +161,13 @@ int tuple_neighbors(int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sig
                     int64_t *offsets, int32_t *nbr, int64_t nbr_capacity, int64_t *nnz_out,
                     hipStream_t s, std::string &err);
 
+// Heuristic Monte-Carlo integrals (Sec. 3.3) over a clipped vertex set
+// (vg_hmc.hip): the centroid pass (integrals false) or the integral pass.
+int hmc_run(bool integrals, int d, int64_t n, const float *nodes, int64_t V, const int32_t *sigma,
+            const double *coords, const float *fv, int R, const int32_t *facet_j, const float *facet_area,
+            const int32_t *facet_count, const float *fc, const float *fx, float *centroid, int32_t *kcount,
+            float *F, float *cell, float *volume, hipStream_t s, std::string &err);
+
 // Incircle RayCast (Algorithm 1) of the Monte-Carlo rays with a grid index
 // (vg_incircle.hip): scratch of incircle_scratch_bytes(n, d); query counts
 // added to nn_calls[0] (all) and nn_calls[1] (answered by the grid).

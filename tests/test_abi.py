@@ -20,7 +20,7 @@ def test_header_declares_the_boundary():
     for want in ("vg_create", "vg_raycast", "vg_raycast_cells", "vg_mc_volume_area",
                  "vg_mc_backward", "vg_raycast_cells_batched", "vg_raycast_batched",
                  "vg_mc_volume_area_nbr", "vg_tuple_neighbors", "vg_mc_sample_points",
-                 "vg_mc_integrals",
+                 "vg_mc_integrals", "vg_hmc_centroids", "vg_hmc_integrals",
                  "vg_explore"):
         assert want in names
 

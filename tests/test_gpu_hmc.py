@@ -1,0 +1,108 @@
+"""GPU heuristic Monte-Carlo integrals (Sec. 3.3) over the clipped diagram
+against the FP64 oracle.  Each side uses its own clipped vertex set and its
+own Monte-Carlo areas on the same seeded directions; the integrand is the
+same formula (numpy on the oracle's side, torch on the GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vg():
+    import paper_2405_10050_amd as vg
+    return vg
+
+
+def _coeffs(d):
+    rng = np.random.default_rng(200 + d)
+    return rng.standard_normal(d), rng.standard_normal(d)
+
+
+def _f_np(d):
+    a, b = _coeffs(d)
+    return lambda p: 1.0 + np.sin(3.0 * (p @ a)) + (p - 0.5) @ b + (p * p).sum(axis=1)
+
+
+def _f_torch(d, dev):
+    a, b = (torch.from_numpy(v).to(dev, torch.float32) for v in _coeffs(d))
+    return lambda p: 1.0 + torch.sin(3.0 * (p @ a)) + (p - 0.5) @ b + (p * p).sum(dim=1)
+
+
+@pytest.mark.parametrize("d,n,R", [(2, 300, 256), (3, 150, 256), (4, 60, 256), (5, 30, 128)])
+def test_hmc_matches_oracle(vg, d, n, R):
+    print(f"hmc d={d} n={n} R={R}", flush=True)
+    X = W.uniform_cloud(n, d, seed=70 + d)
+    D = W.mc_directions(range(n), R, d, seed=71)
+    dev = torch.device("cuda", 0)
+    nodes = torch.from_numpy(X).to(dev)
+    dirs = torch.from_numpy(D).to(dev)
+    mesh = vg.explore(nodes, clip=True)
+    res = vg.mc_volume_area(nodes, dirs)
+    out = vg.hmc_integrals(nodes, mesh, res, _f_torch(d, dev))
+    torch.cuda.synchronize()
+    mc = oracle.mc_volume_area(X, np.arange(n), D)
+    om = oracle.explore_clipped(X)
+    ref = oracle.hmc_integrals(X, om["sigma"], om["coord"], mc["facets"], _f_np(d))
+    tie = oracle.near_tie(mc["t"], mc["t2"]).reshape(n, R)
+    bad_cell = tie.any(axis=1)
+    idx = mc["idx"].reshape(n, R)
+    excused = {(i, int(idx[i, k])) for i, k in zip(*np.nonzero(tie))}
+    ok = ~bad_cell
+    assert np.allclose(out.volume.cpu().numpy()[ok], ref["volume"][ok], rtol=1e-5, atol=0)
+    assert np.allclose(out.cell.cpu().numpy()[ok], ref["cell"][ok], rtol=1e-5, atol=1e-6)
+    cnt = res.facet_count.cpu().numpy()
+    fj = res.facet_j.cpu().numpy()
+    F = out.facet.cpu().numpy()
+    K = out.kcount.cpu().numpy()
+    C = out.centroid.cpu().numpy()
+    members = {}
+    for row in om["sigma"]:
+        for a in row[row < n]:
+            for b in row:
+                if b != a:
+                    j = int(b) if b < n else -2 - int(b - n)
+                    members[(int(a), j)] = members.get((int(a), j), 0) + 1
+    scale = max(abs(v) for v in ref["F"].values())
+    for i in range(n):
+        for s in range(cnt[i]):
+            key = (i, int(fj[i, s]))
+            assert K[i, s] == members[key]  # same vertex sets on both sides
+            assert np.allclose(C[i, s], ref["centroid"][key], atol=1e-6)
+            if key in excused:
+                continue
+            assert F[i, s] == pytest.approx(ref["F"][key], rel=1e-5, abs=1e-6 * scale), key
+
+
+def test_hmc_constant_f_gives_areas_and_volumes(vg):
+    d, n, R = 3, 200, 256
+    X = W.uniform_cloud(n, d, seed=5)
+    dev = torch.device("cuda", 0)
+    nodes = torch.from_numpy(X).to(dev)
+    dirs = torch.from_numpy(W.mc_directions(range(n), R, d, seed=6)).to(dev)
+    mesh = vg.explore(nodes, clip=True)
+    res = vg.mc_volume_area(nodes, dirs)
+    out = vg.hmc_integrals(nodes, mesh, res, lambda p: torch.ones(p.shape[0], device=p.device))
+    valid = torch.arange(R, device=dev)[None, :] < res.facet_count[:, None]
+    assert torch.allclose(out.facet[valid], res.facet_area[valid], rtol=1e-6, atol=0)
+    assert torch.allclose(out.cell, out.volume, rtol=1e-6, atol=0)
+    # per ray h l^{d-1} / |n.u| = l^d: the volume from the areas is the estimator's volume
+    assert torch.allclose(out.volume, res.volume, rtol=2e-5, atol=0)
+
+
+def test_hmc_rejects_a_mesh_without_the_cube_faces(vg):
+    """The unbounded diagram has no vertex on the cube's faces, so the facet
+    rows toward the faces name pairs no vertex holds."""
+    d, n, R = 2, 100, 64
+    X = W.uniform_cloud(n, d, seed=8)
+    dev = torch.device("cuda", 0)
+    nodes = torch.from_numpy(X).to(dev)
+    dirs = torch.from_numpy(W.mc_directions(range(n), R, d, seed=9)).to(dev)
+    mesh = vg.explore(nodes, W.descent_draws(d))
+    res = vg.mc_volume_area(nodes, dirs)
+    with pytest.raises(vg.VGError):
+        vg.hmc_integrals(nodes, mesh, res, lambda p: torch.ones(p.shape[0], device=p.device))
