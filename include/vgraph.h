@@ -55,8 +55,10 @@ typedef enum vg_status {
 #define VG_CLIP (1u << 0)        /* clip rays to the unit cube                 */
 #define VG_PREC_BF16X3 (1u << 1) /* Monte-Carlo scan in split BF16x3 MFMA       */
 #define VG_NO_RECHECK (1u << 2)  /* skip the FP64 re-evaluation (diagnostics)  */
-#define VG_INCIRCLE (1u << 3)    /* Monte-Carlo rays by the incircle RayCast of
-                                    Algorithm 1 with a grid index (d <= 6)     */
+#define VG_INCIRCLE (1u << 3)    /* rays by the incircle RayCast of Algorithm 1
+                                    with a grid index (d <= 6)                  */
+#define VG_INIT_HEURISTIC (1u << 4) /* with VG_INCIRCLE on general rays: start
+                                    from InitialHeuristic (|eta| >= 2)         */
 
 /* per-ray status bits (uint8) */
 #define VG_ST_NEAR_TIE 1  /* FP32 gap of the two best candidates below VG_TIE_EPS */
@@ -106,7 +108,13 @@ int vg_set_profiling(vg_ctx *ctx, int enable);
  *   gen    [n_rays]     i32   g = eta[0], the generator in eq. (t)
  *   excl   [n_rays][n_excl] i32, each row sorted ascending: eta (nodes never
  *          returned); may be NULL when n_excl == 0.  0 <= n_excl <= d.
- *   flags  VG_CLIP, VG_NO_RECHECK
+ *   flags  VG_CLIP, VG_NO_RECHECK, VG_INCIRCLE, VG_INIT_HEURISTIC
+ * With VG_INCIRCLE (d <= 6) each ray runs Algorithm 1 with nearest-neighbour
+ * queries answered by a uniform grid over the cube (built per call), from
+ * the origin or, with VG_INIT_HEURISTIC and |eta| >= 2, from
+ * InitialHeuristic's point; the results are the same as the scan's (the
+ * FP32 certificate and the FP64 recheck of uncertain rays), and
+ * vg_stats.nn_calls counts the queries.
  * Outputs (all [n_rays]): t_out f32 (+inf when no hit), idx_out i32,
  * status_out u8 (may be NULL).  n_rays == 0 is a no-op. */
 int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
@@ -340,6 +348,9 @@ int vg_hmc_integrals(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, in
  * then n_nodes + 2k + s for each face x_k = s the vertex lies on.  The search
  * starts at the corner 0 (no Descent: draws may be NULL), rays are clipped,
  * and there are no unbounded edges.  n_nodes >= 1 then.
+ * VG_INCIRCLE (d <= 6), optionally with VG_INIT_HEURISTIC, casts the edge
+ * rays by Algorithm 1 (as vg_raycast); vg_mesh_num_nn_calls then counts its
+ * nearest-neighbour queries (the measure of Table nncalls).
  * Synchronises the stream.  The result is library-owned: query it, copy it
  * out, free it. */
 int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
@@ -348,6 +359,7 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
 int64_t vg_mesh_num_vertices(const vg_mesh *mesh);
 int64_t vg_mesh_num_unbounded(const vg_mesh *mesh);
 int64_t vg_mesh_num_raycasts(const vg_mesh *mesh);
+int64_t vg_mesh_num_nn_calls(const vg_mesh *mesh);
 /* HOST outputs: sigma [V][d+1] (tuples in discovery order), coords [V][d] f64
  * or NULL, b_sigma [B][d+1] or NULL, b_omit [B] or NULL. */
 int vg_mesh_copy(const vg_mesh *mesh, int32_t *sigma, double *coords,

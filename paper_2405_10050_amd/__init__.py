@@ -35,6 +35,7 @@ VG_CLIP = 1 << 0
 VG_PREC_BF16X3 = 1 << 1
 VG_NO_RECHECK = 1 << 2
 VG_INCIRCLE = 1 << 3
+VG_INIT_HEURISTIC = 1 << 4
 
 ST_NEAR_TIE = 1
 ST_RECHECKED = 2
@@ -77,7 +78,7 @@ EXPORTS = (
     "vg_raycast_batched", "vg_mc_volume_area_nbr", "vg_tuple_neighbors", "vg_mc_sample_points",
     "vg_mc_integrals", "vg_hmc_centroids", "vg_hmc_integrals",
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
-    "vg_mesh_copy", "vg_mesh_free",
+    "vg_mesh_copy", "vg_mesh_free", "vg_mesh_num_nn_calls",
 )
 
 
@@ -108,7 +109,7 @@ def _load_lib():
     lib.vg_hmc_centroids.argtypes = [P, I, I64, P, I64, P, P, I, P, P, P, P]
     lib.vg_hmc_integrals.argtypes = [P, I, I64, P, I64, P, P, I, P, P, P, P, P, P, P, P]
     lib.vg_explore.argtypes = [P, I, I64, P, P, I, U32, ctypes.POINTER(P)]
-    for f in ("vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts"):
+    for f in ("vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts", "vg_mesh_num_nn_calls"):
         getattr(lib, f).argtypes = [P]
         getattr(lib, f).restype = I64
     lib.vg_mesh_copy.argtypes = [P, P, P, P, P]
@@ -177,8 +178,11 @@ def set_profiling(enable: bool, device=None) -> None:
     _check(_lib.vg_set_profiling(c, int(bool(enable))), c, "vg_set_profiling")
 
 
-def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True):
-    """RayCast of arbitrary rays; returns ``(t, idx, status)`` of length M."""
+def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True, incircle=False,
+            heuristic=False):
+    """RayCast of arbitrary rays; returns ``(t, idx, status)`` of length M.
+    ``incircle=True`` casts them by Algorithm 1 with a grid index (d <= 6),
+    ``heuristic=True`` starting from InitialHeuristic's point."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
     n, d = nodes.shape
@@ -197,7 +201,8 @@ def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True):
     t = torch.empty(m, dtype=torch.float32, device=dev)
     idx = torch.empty(m, dtype=torch.int32, device=dev)
     st = torch.empty(m, dtype=torch.uint8, device=dev)
-    flags = (VG_CLIP if clip else 0) | (0 if recheck else VG_NO_RECHECK)
+    flags = ((VG_CLIP if clip else 0) | (0 if recheck else VG_NO_RECHECK) |
+             (VG_INCIRCLE if incircle else 0) | (VG_INIT_HEURISTIC if heuristic else 0))
     c = _ctx(dev)
     _check(_lib.vg_raycast(c, d, n, _ptr(nodes), m, _ptr(origin), _ptr(direction), _ptr(gen),
                            _ptr(excl), ne, flags, _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast")
@@ -558,12 +563,15 @@ def raycast_batched(problems, clip=True, out=None):
     return outs
 
 
-def explore(nodes, descent_draws=None, clip=False) -> dict:
+def explore(nodes, descent_draws=None, clip=False, incircle=False, heuristic=False) -> dict:
     """Exhaustive search (Algorithm 2) of the unbounded diagram, or with
     ``clip=True`` of the diagram clipped to the unit cube (keys then hold
-    ``n + 2k + s`` for the face ``x_k = s``; no draws needed).  Returns host
-    arrays ``sigma [V, d+1]``, ``coord [V, d]`` (float64), ``b_sigma``,
-    ``b_omit`` and ``raycasts``."""
+    ``n + 2k + s`` for the face ``x_k = s``; no draws needed).  With
+    ``incircle=True`` (d <= 6) the edge rays are cast by Algorithm 1 with a
+    grid index (``heuristic``: from InitialHeuristic's point) and
+    ``nn_calls`` counts its queries.  Returns host arrays ``sigma [V, d+1]``,
+    ``coord [V, d]`` (float64), ``b_sigma``, ``b_omit``, ``raycasts`` and
+    ``nn_calls``."""
     _dev(nodes, torch.float32, "nodes")
     n, d = nodes.shape
     if descent_draws is None:
@@ -573,7 +581,9 @@ def explore(nodes, descent_draws=None, clip=False) -> dict:
     c = _ctx(nodes.device)
     mesh = ctypes.c_void_p()
     _check(_lib.vg_explore(c, d, n, _ptr(nodes), draws.ctypes.data_as(ctypes.c_void_p) if draws.size else None,
-                           draws.shape[0], VG_CLIP if clip else 0, ctypes.byref(mesh)), c, "vg_explore")
+                           draws.shape[0],
+                           (VG_CLIP if clip else 0) | (VG_INCIRCLE if incircle else 0) |
+                           (VG_INIT_HEURISTIC if heuristic else 0), ctypes.byref(mesh)), c, "vg_explore")
     try:
         nv = _lib.vg_mesh_num_vertices(mesh)
         nb = _lib.vg_mesh_num_unbounded(mesh)
@@ -584,6 +594,7 @@ def explore(nodes, descent_draws=None, clip=False) -> dict:
         P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         _check(_lib.vg_mesh_copy(mesh, P(sig), P(coord), P(bsig), P(bomit)), c, "vg_mesh_copy")
         return dict(sigma=sig, coord=coord, b_sigma=bsig, b_omit=bomit,
-                    raycasts=int(_lib.vg_mesh_num_raycasts(mesh)))
+                    raycasts=int(_lib.vg_mesh_num_raycasts(mesh)),
+                    nn_calls=int(_lib.vg_mesh_num_nn_calls(mesh)))
     finally:
         _lib.vg_mesh_free(mesh)

@@ -179,13 +179,16 @@ namespace vg {
 
 int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, const double *o64,
                 const double *u64, const int32_t *gen, const int32_t *excl, int n_excl, int clip,
-                bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64) {
+                bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64,
+                int incircle) {
   if (m <= 0) return VG_OK;
-  size_t need = Carver::need({(size_t)m * 8});
+  const size_t grid_bytes = incircle ? incircle_rays_scratch_bytes(n, d) : 0;
+  size_t need = Carver::need({(size_t)m * 8, grid_bytes});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = cv.take<int64_t>(m);
+  void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
   RayScanArgs a{};
@@ -207,7 +210,11 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   a.tau = kTauRays;
   a.force_all = force_all ? 1 : 0;
   ScanTimer timer(ctx);
-  hipError_t e = launch_ray_scan(a, ctx->stream);
+  hipError_t e =
+      incircle ? launch_incircle_rays(a, grid_scratch, incircle == 2,
+                                      reinterpret_cast<unsigned long long *>(ctx->counters + CNT_NN_CALLS),
+                                      ctx->stream)
+               : launch_ray_scan(a, ctx->stream);
   timer.stop();
   if (e != hipSuccess) return hip_fail(ctx, e, "ray scan launch");
   RecheckArgs r{};
@@ -334,12 +341,18 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t 
   if (!origin || !dir || !gen || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null ray array");
   if (n_excl > 0 && !excl) return fail(ctx, VG_EINVAL, "excl is NULL with n_excl > 0");
   const bool recheck = !(flags & VG_NO_RECHECK);
-  size_t need = Carver::need({recheck ? (size_t)n_rays * 8 : 0, status_out ? 0 : (size_t)n_rays});
+  const bool incircle = (flags & VG_INCIRCLE) != 0;
+  if (incircle && d > 6) return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs d <= 6");
+  if ((flags & VG_INIT_HEURISTIC) && !incircle)
+    return fail(ctx, VG_EINVAL, "VG_INIT_HEURISTIC needs VG_INCIRCLE");
+  const size_t grid_bytes = incircle ? incircle_rays_scratch_bytes(n_nodes, d) : 0;
+  size_t need = Carver::need({recheck ? (size_t)n_rays * 8 : 0, status_out ? 0 : (size_t)n_rays, grid_bytes});
   rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = recheck ? cv.take<int64_t>(n_rays) : nullptr;
   uint8_t *st = status_out ? status_out : cv.take<uint8_t>(n_rays);
+  void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
   RayScanArgs a{};
@@ -360,7 +373,11 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t 
   a.flag_list = flag_list;
   a.tau = kTauRays;
   ScanTimer timer(ctx);
-  hipError_t e = launch_ray_scan(a, ctx->stream);
+  hipError_t e =
+      incircle ? launch_incircle_rays(a, grid_scratch, (flags & VG_INIT_HEURISTIC) ? 1 : 0,
+                                      reinterpret_cast<unsigned long long *>(ctx->counters + CNT_NN_CALLS),
+                                      ctx->stream)
+               : launch_ray_scan(a, ctx->stream);
   timer.stop();
   if (e != hipSuccess) return hip_fail(ctx, e, "ray scan launch");
   if (recheck) {

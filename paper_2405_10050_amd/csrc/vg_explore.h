@@ -85,9 +85,12 @@ hipError_t launch_solve_one(const float *X, int d, const int32_t *sig, double *v
 
 // RayCast of FP64-described rays (FP32 scan, FP64 recheck of flagged rays).
 // force_all queues every ray for the FP64 pass; t64 (optional) receives the
-// FP64 t of rechecked rays.  Defined in vg_api.hip.
+// FP64 t of rechecked rays; incircle 1 (2) casts by Algorithm 1 without
+// (with) InitialHeuristic, counting queries in the context's counters.
+// Defined in vg_api.hip.
 int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, const double *o64,
                 const double *u64, const int32_t *gen, const int32_t *excl, int n_excl, int clip,
-                bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64);
+                bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64,
+                int incircle);
 
 }  // namespace vg

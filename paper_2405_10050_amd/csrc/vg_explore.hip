@@ -39,6 +39,7 @@ struct vg_mesh {
   std::vector<double> coord;
   std::vector<int32_t> bsig, bomit;
   int64_t raycasts = 0;
+  int64_t nn_calls = 0;  // nearest-neighbour queries of Algorithm 1 (VG_INCIRCLE)
 };
 
 using namespace vg;
@@ -108,6 +109,7 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
                int n_draws, uint32_t flags, vg_mesh **out) {
   if (!ctx) return VG_EINVAL;
   const bool clipped = (flags & VG_CLIP) != 0;
+  const int incircle = (flags & VG_INCIRCLE) ? ((flags & VG_INIT_HEURISTIC) ? 2 : 1) : 0;
   ctx->err.clear();
   if (!out) {
     ctx->err = "out is NULL";
@@ -118,9 +120,17 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     ctx->err = "d outside [2, VG_MAX_DIM]";
     return VG_EUNSUPPORTED;
   }
-  if (flags & ~(uint32_t)VG_CLIP) {
-    ctx->err = "explore takes VG_CLIP only";
+  if (flags & ~(uint32_t)(VG_CLIP | VG_INCIRCLE | VG_INIT_HEURISTIC)) {
+    ctx->err = "explore takes VG_CLIP, VG_INCIRCLE and VG_INIT_HEURISTIC only";
     return VG_EINVAL;
+  }
+  if ((flags & VG_INIT_HEURISTIC) && !incircle) {
+    ctx->err = "VG_INIT_HEURISTIC needs VG_INCIRCLE";
+    return VG_EINVAL;
+  }
+  if (incircle && d > 6) {
+    ctx->err = "VG_INCIRCLE needs d <= 6";
+    return VG_EUNSUPPORTED;
   }
   if (clipped ? (n_nodes < 1 || !nodes)
               : (n_nodes < d + 1 || !nodes || !draws || n_draws < 1)) {
@@ -233,10 +243,13 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
         }
         EX_RC(raycast_f64(ctx, d, n_nodes, nodes, 1, r_d.as<double>(), u_d.as<double>(),
                           g_d.as<int32_t>(), ex_d.as<int32_t>(), m, 0, true, t32_d.as<float>(),
-                          i_d.as<int32_t>(), st_d.as<uint8_t>(), t64_d.as<double>()));
+                          i_d.as<int32_t>(), st_d.as<uint8_t>(), t64_d.as<double>(), incircle));
         M->raycasts++;
+        uint64_t calls = 0;
         EX_HIP(hipMemcpyAsync(&j, i_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, X.s));
+        EX_HIP(hipMemcpyAsync(&calls, ctx->counters + CNT_NN_CALLS, 8, hipMemcpyDeviceToHost, X.s));
         EX_HIP(hipStreamSynchronize(X.s));
+        M->nn_calls += (int64_t)calls;
       }
       if (j < 0) continue;
       EX_HIP(launch_advance(r_d.as<double>(), u_d.as<double>(), t64_d.as<double>(), d, sign, X.s));
@@ -395,8 +408,14 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       er.face_base = face_base;
       EX_HIP(launch_edge_rays(er, X.s));
       EX_RC(raycast_f64(ctx, d, n_nodes, nodes, m, er.o64, er.u64, er.gen, er.excl, d, clipped ? 1 : 0, false,
-                        X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr));
+                        X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr, incircle));
       M->raycasts += m;
+      if (incircle) {
+        uint64_t calls = 0;
+        EX_HIP(hipMemcpyAsync(&calls, ctx->counters + CNT_NN_CALLS, 8, hipMemcpyDeviceToHost, X.s));
+        EX_HIP(hipStreamSynchronize(X.s));
+        M->nn_calls += (int64_t)calls;
+      }
       EX_HIP(launch_new_vertices(er, X.s));
       if (validate) {
         // count the edge rays whose new vertex has a node inside its sphere
@@ -482,6 +501,7 @@ fail:
 int64_t vg_mesh_num_vertices(const vg_mesh *m) { return m ? (int64_t)m->sig.size() / (m->d + 1) : -1; }
 int64_t vg_mesh_num_unbounded(const vg_mesh *m) { return m ? (int64_t)m->bomit.size() : -1; }
 int64_t vg_mesh_num_raycasts(const vg_mesh *m) { return m ? m->raycasts : -1; }
+int64_t vg_mesh_num_nn_calls(const vg_mesh *m) { return m ? m->nn_calls : -1; }
 
 int vg_mesh_copy(const vg_mesh *m, int32_t *sigma, double *coords, int32_t *b_sigma,
                  int32_t *b_omit) {

@@ -104,32 +104,40 @@ struct GridView {
   float h;
 };
 
-// Top-2 nearest eligible nodes (squared distances) of the candidate
-// q = x_i + t u, from coordinates relative to x_i; eligible means
-// u.(x_k - x_i) > 0 (the skip predicate of Algorithm 1).  A node whose
-// squared distance exceeds ref + gap_tol(ref, .) with ref = min(d1, limit)
-// cannot change the caller's decision or its certificate, so the ring search
-// stops once every unvisited node is that far (or beyond d2).  `shift`
-// bounds the distance of q from the exact candidate (for gap_tol).
+// Top-2 nearest eligible nodes (squared distances) of the query point
+// q = x_g + qr, from coordinates relative to the ray's generator x_g (|qr| =
+// T); eligible means u.(x_k - x_g) > 0 (the skip predicate of Algorithm 1)
+// and k not in ex[0 .. n_ex) (eta).  A node whose squared distance exceeds
+// ref + gap_tol(ref, .) with ref = min(d1, limit) cannot change the caller's
+// decision or its certificate, so the ring search stops once every
+// unvisited node is that far (or beyond d2).  A node outside ring rho - 1 of
+// q's (clamped) cell is at least (rho - 1) h away in one coordinate and at
+// least q's distance to the cube in the others, so the bound adds that
+// distance when q lies outside.  `shift` bounds the distance of q from the
+// exact point (for gap_tol).
 template <int DK>
-__device__ void nn2(const GridView &g, int d, const float (&xi)[DK], const float (&u)[DK], float t,
-                    int32_t self, float limit, float shift, int32_t &i1, float &d1, float &d2) {
-  float qr[DK];
+__device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float (&qr)[DK], const float (&u)[DK],
+                    float T, const int32_t *ex, int n_ex, float limit, float shift, int32_t &i1, float &d1,
+                    float &d2) {
   int c[DK];
+  float out2 = 0.f;
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
-    qr[k] = t * u[k];
-    int v = k < d ? (int)floorf((xi[k] + qr[k]) * (float)g.G) : 0;
+    const float qa = xg[k] + qr[k];
+    int v = k < d ? (int)floorf(qa * (float)g.G) : 0;
     c[k] = v < 0 ? 0 : (v >= g.G ? g.G - 1 : v);
+    const float o = k < d ? fmaxf(0.f, fmaxf(-qa, qa - 1.f)) : 0.f;
+    out2 = __builtin_fmaf(o, o, out2);
   }
+  out2 *= 1.f - 0x1p-20f;
   i1 = -1;
   d1 = d2 = __builtin_inff();
   for (int rho = 0; rho < g.G; ++rho) {
     if (rho >= 1) {
       const float lb = fmaxf(0.f, (float)(rho - 1) * g.h - kRingSlack);
-      const float lb2 = lb * lb;
+      const float lb2 = lb * lb + out2;
       const float ref = fminf(d1, limit);
-      if (lb2 > d2 || lb2 > ref + gap_tol(ref, lb2, shift, t, d)) break;
+      if (lb2 > d2 || lb2 > ref + gap_tol(ref, lb2, shift, T, d)) break;
     }
     // offsets o in [-rho, rho]^d with max |o_k| = rho, as a mixed-radix counter
     const int span = 2 * rho + 1;
@@ -151,13 +159,15 @@ __device__ void nn2(const GridView &g, int d, const float (&xi)[DK], const float
       if (on_ring && inside) {
         for (uint32_t p = g.start[cell]; p < g.start[cell + 1]; ++p) {
           const int32_t node = g.id[p];
-          if (node == self) continue;
+          bool in_eta = false;
+          for (int e = 0; e < n_ex; ++e) in_eta |= ex[e] == node;
+          if (in_eta) continue;
           const float *xp = g.X + (int64_t)p * d;
           float den = 0.f, dist = 0.f;
 #pragma unroll
           for (int k = 0; k < DK; ++k) {
             if (k < d) {
-              const float ek = xp[k] - xi[k];
+              const float ek = xp[k] - xg[k];
               den = __builtin_fmaf(u[k], ek, den);
               const float e = qr[k] - ek;
               dist = __builtin_fmaf(e, e, dist);
@@ -440,7 +450,11 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
     if (in_list) {
       list_nn2<DK, KN>(lids, lrel, d, u, tbox, i1, d1, d2);
     } else {
-      nn2<DK>(g, d, xi, u, tbox, (int32_t)cell, di, shift, i1, d1, d2);
+      const int32_t self = (int32_t)cell;
+      float qr[DK];
+#pragma unroll
+      for (int q2 = 0; q2 < DK; ++q2) qr[q2] = tbox * u[q2];
+      nn2<DK>(g, d, xi, qr, u, tbox, &self, 1, di, shift, i1, d1, d2);
       ++grid_calls;
     }
     ++calls;
@@ -482,7 +496,11 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
       if (in_list) {
         list_nn2<DK, KN>(lids, lrel, d, u, t, i1, d1, d2);
       } else {
-        nn2<DK>(g, d, xi, u, t, (int32_t)cell, dk, shift, i1, d1, d2);
+        const int32_t self = (int32_t)cell;
+        float qr[DK];
+#pragma unroll
+        for (int q2 = 0; q2 < DK; ++q2) qr[q2] = t * u[q2];
+        nn2<DK>(g, d, xi, qr, u, t, &self, 1, dk, shift, i1, d1, d2);
         ++grid_calls;
       }
       ++calls;
@@ -583,6 +601,193 @@ __global__ __launch_bounds__(NT) void incircle_grid_kernel(CellScanArgs a, GridV
   add_calls(block_calls, calls, grid_calls, nn_calls);
 }
 
+// General rays (vg_raycast, the exhaustive search's edge rays): Algorithm 1
+// from the origin x, or from InitialHeuristic's point when asked for and
+// |eta| >= 2 (it projects x onto the hyperplane through x_g orthogonal to u,
+// then walks the height r / sqrt((|eta|-1)(|eta|+1)) of a regular simplex
+// over the face of radius r along u; the point stays on the ray's line).
+// Everything is relative to the ray's generator x_g (an FP64 origin is made
+// relative in FP64).  The first nn call gives the first candidate i; then
+// t = (|r - x_i|^2 - |r - x_g|^2) / (2 u.(x_i - x_g)), r' = r + t u,
+// j = nn(r'), until j = i.  The certificate is the one of the Monte-Carlo
+// rays (gap of the two nearest eligible nodes at r' against their FP32
+// error); uncertain, capped, grazing and no-hit rays go to the FP64 recheck.
+// t* from the origin is then re-evaluated in FP64 from eq. (t).
+template <int DK>
+__device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuristic, int64_t ray,
+                             uint32_t &calls) {
+  const int d = a.d;
+  const int32_t gidx = a.gen[ray];
+  if (gidx < 0 || gidx >= a.n) {  // invalid generator index: report, skip
+    a.t_out[ray] = __builtin_nanf("");
+    a.idx_out[ray] = -1;
+    a.st_out[ray] = VG_ST_SUSPECT;
+    return;
+  }
+  const int32_t *ex = a.n_excl > 0 ? a.excl + ray * a.n_excl : nullptr;
+  int n_eta = 0;  // members of eta (entries past the nodes are padding)
+  for (int e = 0; e < a.n_excl; ++e) n_eta += (ex[e] >= 0 && ex[e] < a.n);
+  float xg[DK], u[DK], r0[DK], r[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    if (k < d) {
+      xg[k] = a.nodes[(int64_t)gidx * d + k];
+      r0[k] = a.o64 ? (float)(a.o64[ray * d + k] - (double)xg[k]) : a.o32[ray * d + k] - xg[k];
+      u[k] = a.u64 ? (float)a.u64[ray * d + k] : a.u32[ray * d + k];
+    } else {
+      xg[k] = u[k] = r0[k] = 0.f;
+    }
+    r[k] = r0[k];
+  }
+  float r0n = 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) r0n = __builtin_fmaf(r0[k], r0[k], r0n);
+  r0n = sqrtf(r0n);
+  if (heuristic && n_eta >= 2) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) s = __builtin_fmaf(u[k], -r[k], s);
+#pragma unroll
+    for (int k = 0; k < DK; ++k) r[k] = __builtin_fmaf(s, u[k], r[k]);
+    float rad = 0.f;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) rad = __builtin_fmaf(r[k], r[k], rad);
+    const float hh = sqrtf(rad) / sqrtf((float)((n_eta - 1) * (n_eta + 1)));
+#pragma unroll
+    for (int k = 0; k < DK; ++k) r[k] = __builtin_fmaf(hh, u[k], r[k]);
+  }
+  float rn = 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) rn = __builtin_fmaf(r[k], r[k], rn);
+  rn = sqrtf(rn);
+  // the start point's own error (origin rounding, the heuristic's steps)
+  const float shift0 = (2.f * r0n + 4.f * rn) * 0x1p-24f;
+  int32_t i1;
+  float d1, d2;
+  nn2<DK>(g, d, xg, r, u, rn, ex, a.n_excl, __builtin_inff(), shift0, i1, d1, d2);
+  ++calls;
+  bool flag = a.force_all != 0;
+  uint8_t st = 0;
+  int32_t j = -1;
+  double t64 = __builtin_inf();
+  if (i1 >= 0) {
+    int32_t k = i1;
+    int it = 0;
+    float shift = shift0;
+    float rp[DK];
+    float rpn = 0.f;
+    for (; it < kMaxIter; ++it) {
+      const float *xk = a.nodes + (int64_t)k * d;
+      float ek[DK];
+      float num = 0.f, den = 0.f, en = 0.f;
+#pragma unroll
+      for (int q = 0; q < DK; ++q) {
+        ek[q] = q < d ? xk[q] - xg[q] : 0.f;
+        // |r - e|^2 - |r|^2 = e.(e - 2 r)
+        num = __builtin_fmaf(ek[q], ek[q] - 2.f * r[q], num);
+        den = __builtin_fmaf(u[q], ek[q], den);
+        en = __builtin_fmaf(ek[q], ek[q], en);
+      }
+      const float t = num / (2.f * den);
+      rpn = 0.f;
+#pragma unroll
+      for (int q = 0; q < DK; ++q) {
+        rp[q] = __builtin_fmaf(t, u[q], r[q]);
+        rpn = __builtin_fmaf(rp[q], rp[q], rpn);
+      }
+      rpn = sqrtf(rpn);
+      // error of r': the start point's, then t's (num = e.(e - 2r) carries
+      // (d+2) |e| (|e| + 2|r|) ulps, den (d+1) |e| ulps of t den, one
+      // division), then the rounding of r + t u
+      const float el = sqrtf(en);
+      shift = shift0 + ((float)(d + 2) * el * (el + 2.f * rn) / (2.f * den) +
+                        fabsf(t) * ((float)(d + 1) * el / den + 2.f) + rpn) * 0x1p-24f;
+      float dk = 0.f;
+#pragma unroll
+      for (int q = 0; q < DK; ++q) {
+        const float e = rp[q] - ek[q];
+        dk = __builtin_fmaf(e, e, dk);
+      }
+      nn2<DK>(g, d, xg, rp, u, rpn, ex, a.n_excl, dk, shift, i1, d1, d2);
+      ++calls;
+      if (i1 == k) break;
+      if (i1 < 0) break;  // k itself is eligible, so only through NaN
+      k = i1;
+    }
+    j = k;
+    if (it == kMaxIter || i1 != k) {
+      flag = true;
+      st |= VG_ST_SUSPECT;
+    }
+    if (d2 < __builtin_inff() && !(d2 - d1 > gap_tol(d2, d1, shift, rpn, d))) flag = true;
+    // the winner's t from the origin, eq. (t) relative to x_g, in FP64
+    const float *xj = a.nodes + (int64_t)j * d;
+    double num = 0.0, den = 0.0, nrm = 0.0;
+    for (int q = 0; q < d; ++q) {
+      const double e = (double)xj[q] - (double)xg[q];
+      // exact for an FP32 origin: the difference of two floats in FP64
+      const double o = (a.o64 ? a.o64[ray * d + q] : (double)a.o32[ray * d + q]) - (double)xg[q];
+      num += e * (e - 2.0 * o);
+      den += (double)u[q] * e;
+      nrm += e * e;
+    }
+    if (!(den > (1.0 / 4096.0) * sqrt(nrm))) {  // nearly grazing winner
+      flag = true;
+      st |= VG_ST_SUSPECT;
+    }
+    t64 = num / (2.0 * den);
+  }
+  float t = (float)t64;
+  if (a.clip) {
+    float tb = __builtin_inff();
+    int face = -1;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d && u[k] != 0.f) {
+        const float xa = a.o64 ? (float)a.o64[ray * d + k] : a.o32[ray * d + k];
+        const float h = u[k] > 0.f ? 1.f - xa : -xa;
+        const float tk = h / u[k];
+        if (tk < tb) {
+          tb = tk;
+          face = 2 * k + (u[k] > 0.f ? 1 : 0);
+        }
+      }
+    }
+    if (face >= 0) {
+      if (!(fabsf(tb - t) > 0x1p-16f * fmaxf(fabsf(tb), fabsf(t)))) flag = true;  // face against node
+      if (tb < t) {
+        t = tb;
+        j = -2 - face;
+      }
+    }
+  }
+  if (j == -1) {
+    st |= VG_ST_NO_HIT;
+    t = __builtin_inff();
+    flag = true;
+  }
+  if (flag && a.flag_list) {
+    st |= VG_ST_NEAR_TIE;
+    const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
+    a.flag_list[pos] = ray | a.flag_tag;
+  }
+  a.t_out[ray] = t;
+  a.idx_out[ray] = j;
+  a.st_out[ray] = st;
+}
+
+template <int DK>
+__global__ __launch_bounds__(NT) void incircle_rays_kernel(RayScanArgs a, GridView g, int heuristic,
+                                                           unsigned long long *nn_calls) {
+  __shared__ unsigned int block_calls[2];
+  if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t ray = (int64_t)blockIdx.x * NT + threadIdx.x;
+  uint32_t calls = 0;
+  if (ray < a.m) incircle_ray<DK>(a, g, heuristic, ray, calls);
+  add_calls(block_calls, calls, calls, nn_calls);
+}
+
 unsigned blocks_of(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
@@ -595,20 +800,90 @@ static int incircle_grid_size(int64_t n, int d) {
   return G;
 }
 
-size_t incircle_scratch_bytes(int64_t n, int d, int R) {
+
+namespace {
+
+// Bump allocator over a scratch block (256-byte aligned pieces).
+struct Carve {
+  char *p;
+  template <typename T>
+  T *take(size_t count) {
+    T *q = reinterpret_cast<T *>(p);
+    p += (count * sizeof(T) + 255) & ~size_t(255);
+    return q;
+  }
+};
+
+size_t grid_bytes(int64_t n, int d) {
   const int G = incircle_grid_size(n, d);
   int64_t cells = 1;
   for (int k = 0; k < d; ++k) cells *= G;
   size_t tmp = 0;
   (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                           (int)(cells + 1));
-  // cell_of, ids [n] i32; Xs [n][d] f32; list ids [n][KN] i32, rel
-  // [n][KN][d] f32, r2 [n] f32; counts, start, cursor [cells + 1]; scan
-  // temp; queue gid [rays] i64, k [rays] i32, count
+  // cell_of, ids [n] i32; Xs [n][d] f32; counts, start, cursor [cells + 1]; scan temp
+  return (size_t)n * 8 + (size_t)n * d * 4 + 3 * (size_t)(cells + 1) * 4 + tmp + 7 * 256;
+}
+
+// Counting sort of the nodes into the grid's cells (grid_bytes of scratch).
+hipError_t build_grid(const float *nodes, int64_t n, int d, Carve &cv, GridView &g, hipStream_t s) {
+  const int G = incircle_grid_size(n, d);
+  int64_t cells = 1;
+  for (int k = 0; k < d; ++k) cells *= G;
+  int32_t *cell_of = cv.take<int32_t>((size_t)n);
+  int32_t *ids = cv.take<int32_t>((size_t)n);
+  float *Xs = cv.take<float>((size_t)n * d);
+  uint32_t *counts = cv.take<uint32_t>((size_t)(cells + 1));
+  uint32_t *start = cv.take<uint32_t>((size_t)(cells + 1));
+  uint32_t *cursor = cv.take<uint32_t>((size_t)(cells + 1));
+  size_t tmp = 0;
+  hipError_t e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp, counts, start, (int)(cells + 1), s);
+  if (e != hipSuccess) return e;
+  void *tmpp = cv.take<char>(tmp);
+  e = fill_u32(counts, 0u, cells + 1, s);
+  if (e == hipSuccess) e = fill_u32(cursor, 0u, cells + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grid_count_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, nodes, n, d, G, cell_of, counts);
+  // counts[0] = 0 and counts[c + 1] = size of cell c, so the inclusive scan
+  // gives start[c] = nodes in cells before c (start[cells] = n)
+  e = hipcub::DeviceScan::InclusiveSum(tmpp, tmp, counts, start, (int)(cells + 1), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grid_fill_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, nodes, n, d, cell_of, start, cursor,
+                     Xs, ids);
+  e = hipGetLastError();
+  g = GridView{Xs, ids, start, G, 1.f / (float)G};
+  return e;
+}
+
+}  // namespace
+
+size_t incircle_rays_scratch_bytes(int64_t n, int d) { return grid_bytes(n, d); }
+
+size_t incircle_scratch_bytes(int64_t n, int d, int R) {
+  // the grid; list ids [n][KN] i32, rel [n][KN][d] f32, r2 [n] f32; queue
+  // gid [rays] i64, k [rays] i32, count
   const size_t kn = (size_t)knn_count(d);
   const size_t rays = (size_t)n * (size_t)R;
-  return (size_t)n * 8 + (size_t)n * d * 4 + (size_t)n * kn * (d + 1) * 4 + (size_t)n * 4 +
-         3 * (size_t)(cells + 1) * 4 + tmp + rays * 12 + 12 * 256;
+  return grid_bytes(n, d) + (size_t)n * kn * (d + 1) * 4 + (size_t)n * 4 + rays * 12 + 6 * 256;
+}
+
+hipError_t launch_incircle_rays(const RayScanArgs &a, void *scratch, int heuristic, unsigned long long *nn_calls,
+                                hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  Carve cv{static_cast<char *>(scratch)};
+  GridView g;
+  hipError_t e = build_grid(a.nodes, a.n, a.d, cv, g, s);
+  if (e != hipSuccess) return e;
+  const dim3 grid(blocks_of(a.m)), blk(NT);
+  if (a.d <= 2)
+    hipLaunchKernelGGL(incircle_rays_kernel<2>, grid, blk, 0, s, a, g, heuristic, nn_calls);
+  else if (a.d <= 3)
+    hipLaunchKernelGGL(incircle_rays_kernel<3>, grid, blk, 0, s, a, g, heuristic, nn_calls);
+  else if (a.d <= 4)
+    hipLaunchKernelGGL(incircle_rays_kernel<4>, grid, blk, 0, s, a, g, heuristic, nn_calls);
+  else
+    hipLaunchKernelGGL(incircle_rays_kernel<6>, grid, blk, 0, s, a, g, heuristic, nn_calls);
+  return hipGetLastError();
 }
 
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
@@ -617,47 +892,21 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   const int d = a.d;
   const int64_t rays = n * a.R;
   if (rays >= (int64_t(1) << 32)) return hipErrorInvalidValue;  // 32-bit queue and flag counters
-  const int G = incircle_grid_size(n, d);
-  int64_t cells = 1;
-  for (int k = 0; k < d; ++k) cells *= G;
-  auto carve = [&](size_t bytes) {
-    char *p = static_cast<char *>(scratch);
-    scratch = p + ((bytes + 255) & ~size_t(255));
-    return p;
-  };
-  int32_t *cell_of = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
-  int32_t *ids = reinterpret_cast<int32_t *>(carve((size_t)n * 4));
-  float *Xs = reinterpret_cast<float *>(carve((size_t)n * d * 4));
+  Carve cv{static_cast<char *>(scratch)};
+  GridView g;
+  hipError_t e = build_grid(a.nodes, n, d, cv, g, s);
+  if (e != hipSuccess) return e;
   const size_t kn = (size_t)knn_count(d);
   KnnList kl;
-  kl.ids = reinterpret_cast<int32_t *>(carve((size_t)n * kn * 4));
-  kl.rel = reinterpret_cast<float *>(carve((size_t)n * kn * d * 4));
-  kl.r2 = reinterpret_cast<float *>(carve((size_t)n * 4));
-  uint32_t *counts = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
-  uint32_t *start = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
-  uint32_t *cursor = reinterpret_cast<uint32_t *>(carve((size_t)(cells + 1) * 4));
+  kl.ids = cv.take<int32_t>((size_t)n * kn);
+  kl.rel = cv.take<float>((size_t)n * kn * d);
+  kl.r2 = cv.take<float>((size_t)n);
   DeferQueue dq;
-  dq.gid = reinterpret_cast<int64_t *>(carve((size_t)rays * 8));
-  dq.k = reinterpret_cast<int32_t *>(carve((size_t)rays * 4));
-  dq.count = reinterpret_cast<uint32_t *>(carve(4));
-  size_t tmp = 0;
-  hipError_t e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp, counts, start, (int)(cells + 1), s);
+  dq.gid = cv.take<int64_t>((size_t)rays);
+  dq.k = cv.take<int32_t>((size_t)rays);
+  dq.count = cv.take<uint32_t>(1);
+  e = fill_u32(dq.count, 0u, 1, s);
   if (e != hipSuccess) return e;
-  void *tmpp = carve(tmp);
-  e = fill_u32(counts, 0u, cells + 1, s);
-  if (e == hipSuccess) e = fill_u32(cursor, 0u, cells + 1, s);
-  if (e == hipSuccess) e = fill_u32(dq.count, 0u, 1, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(grid_count_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, a.nodes, n, d, G, cell_of, counts);
-  // counts[0] = 0 and counts[c + 1] = size of cell c, so the inclusive scan
-  // gives start[c] = nodes in cells before c (start[cells] = n)
-  e = hipcub::DeviceScan::InclusiveSum(tmpp, tmp, counts, start, (int)(cells + 1), s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(grid_fill_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, a.nodes, n, d, cell_of, start,
-                     cursor, Xs, ids);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const GridView g{Xs, ids, start, G, 1.f / (float)G};
   const dim3 grid(blocks_of(rays)), blk(NT);
   // the grid pass strides over the queue, whose length only the device knows
   const dim3 grid2(std::min<unsigned>(blocks_of(rays), 2048u));

@@ -174,6 +174,12 @@ int hmc_run(bool integrals, int d, int64_t n, const float *nodes, int64_t V, con
 size_t incircle_scratch_bytes(int64_t n, int d, int R);
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
                                  hipStream_t s);
+// The same for general rays (scratch of incircle_rays_scratch_bytes; query
+// counts added to nn_calls[0] and nn_calls[1]); heuristic applies
+// InitialHeuristic to rays with |eta| >= 2.
+size_t incircle_rays_scratch_bytes(int64_t n, int d);
+hipError_t launch_incircle_rays(const RayScanArgs &a, void *scratch, int heuristic, unsigned long long *nn_calls,
+                                hipStream_t s);
 
 hipError_t launch_ray_scan(const RayScanArgs &a, hipStream_t s);
 constexpr int kRayTile = 256;  // rays per workgroup (and per batched item) of the ray scan
