@@ -332,6 +332,45 @@ def bench_hmc(args):
     }
 
 
+def bench_explore_incircle(args):
+    """Exhaustive search of a uniform d=3 cloud of N = 100 000 with the edge
+    rays cast by Algorithm 1 (grid index, InitialHeuristic); the same search
+    with the dense scan is timed beside it and must return the same
+    vertices."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    d, n = 3, 100_000
+    print("[bench] explore d=3 N=100000 with Algorithm 1 (warm-up, then timed)", file=sys.stderr, flush=True)
+    X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).cuda()
+    draws = W.descent_draws(d)
+    if args.warmup:
+        vg.explore(X, draws, incircle=True, heuristic=True)
+    t0 = time.perf_counter()
+    m = vg.explore(X, draws, incircle=True, heuristic=True)
+    dt = time.perf_counter() - t0
+    print(f"[bench] explore with Algorithm 1: {dt:.2f} s; dense scan next", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ref = vg.explore(X, draws)
+    dt_scan = time.perf_counter() - t0
+    same = bool(np.array_equal(np.unique(m["sigma"], axis=0), np.unique(ref["sigma"], axis=0)))
+    nv = m["sigma"].shape[0]
+    return {
+        "metric": "vertices/sec exhaustive Voronoi vertex search",
+        "value": nv / dt, "unit": "vertices/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"uniform d={d} N={n}, unbounded diagram, edge rays by Algorithm 1 "
+                               "with a grid index and InitialHeuristic",
+                   "vertices": nv, "raycasts": m["raycasts"],
+                   "nn_calls_per_raycast": m["nn_calls"] / m["raycasts"],
+                   "dense_scan_s": dt_scan, "speedup_vs_dense_scan": dt_scan / dt,
+                   "same_vertex_set_as_dense_scan": same},
+    }
+
+
 def bench_explore(args):
     """Exhaustive vertex search (Algorithm 2) of a uniform cloud: the
     unbounded diagram, or (clipped_*) the diagram clipped to the unit cube."""
@@ -371,7 +410,8 @@ def main():
                     choices=["gmm8_d10_n100000", "uneven64", "uniform_d4_n50000",
                              "uniform_d2_n1000", "uniform_d6_n10000", "nbr_d4_n50000",
                              "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000",
-                             "clipped_d2_n1000", "clipped_d6_n10000", "hmc_d5_n10000"])
+                             "clipped_d2_n1000", "clipped_d6_n10000", "hmc_d5_n10000",
+                             "explore_incircle_d3_n100000"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -400,7 +440,7 @@ def main():
                  "nbr_d4_n50000": bench_nbr, "nbr_d6_n10000": bench_nbr,
                  "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle,
                  "clipped_d2_n1000": bench_explore, "clipped_d6_n10000": bench_explore,
-                 "hmc_d5_n10000": bench_hmc}
+                 "hmc_d5_n10000": bench_hmc, "explore_incircle_d3_n100000": bench_explore_incircle}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 

@@ -48,6 +48,13 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int kMaxIter = 64;
+// Ring offsets one query may visit.  A query point far outside the cube sees
+// a whole face nearly equidistant, and a ray with no eligible node sweeps
+// the grid: past this budget the query gives up (i1 = kGaveUp) and the ray
+// goes to the FP64 recheck over all nodes.  A full sweep of a grid of
+// N = 1000 nodes in d = 2..5 stays below it.
+constexpr int kRingBudget = 1 << 15;
+constexpr int32_t kGaveUp = -2;
 
 __global__ void grid_count_kernel(const float *__restrict__ X, int64_t n, int d, int G,
                                   int32_t *__restrict__ cell_of, uint32_t *__restrict__ counts) {
@@ -132,6 +139,7 @@ __device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float
   out2 *= 1.f - 0x1p-20f;
   i1 = -1;
   d1 = d2 = __builtin_inff();
+  int budget = kRingBudget;
   for (int rho = 0; rho < g.G; ++rho) {
     if (rho >= 1) {
       const float lb = fmaxf(0.f, (float)(rho - 1) * g.h - kRingSlack);
@@ -145,6 +153,10 @@ __device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float
 #pragma unroll
     for (int k = 0; k < DK; ++k) o[k] = -rho;
     for (;;) {
+      if (--budget < 0) {
+        i1 = kGaveUp;
+        return;
+      }
       bool on_ring = false, inside = true;
       int64_t cell = 0;
 #pragma unroll
@@ -458,7 +470,11 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
       ++grid_calls;
     }
     ++calls;
-    if (i1 < 0 || d1 > di) {
+    if (i1 == kGaveUp) {
+      flag = true;
+      st |= VG_ST_SUSPECT;
+      j = -2 - face;
+    } else if (i1 < 0 || d1 > di) {
       j = -2 - face;  // the exit point lies in cell i
       if (i1 >= 0 && !(d1 - di > gap_tol(d1, di, shift, tbox, d))) flag = true;
     } else {
@@ -670,6 +686,10 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
   uint8_t st = 0;
   int32_t j = -1;
   double t64 = __builtin_inf();
+  if (i1 == kGaveUp) {  // the FP64 recheck settles it
+    flag = true;
+    st |= VG_ST_SUSPECT;
+  }
   if (i1 >= 0) {
     int32_t k = i1;
     int it = 0;
