@@ -56,13 +56,18 @@ constexpr int kMaxIter = 64;
 constexpr int kRingBudget = 1 << 15;
 constexpr int32_t kGaveUp = -2;
 
+// Cell of every node; a node outside [0,1]^d (clamped into a boundary cell,
+// where the ring bound does not hold for it) sets *outside.
 __global__ void grid_count_kernel(const float *__restrict__ X, int64_t n, int d, int G,
-                                  int32_t *__restrict__ cell_of, uint32_t *__restrict__ counts) {
+                                  int32_t *__restrict__ cell_of, uint32_t *__restrict__ counts,
+                                  uint32_t *__restrict__ outside) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
   int64_t c = 0;
   for (int k = 0; k < d; ++k) {
-    int q = (int)floorf(X[i * d + k] * (float)G);
+    const float x = X[i * d + k];
+    if (!(x >= 0.f && x <= 1.f)) atomicOr(outside, 1u);
+    int q = (int)floorf(x * (float)G);
     q = q < 0 ? 0 : (q >= G ? G - 1 : q);
     c = c * G + q;
   }
@@ -109,6 +114,8 @@ struct GridView {
   const uint32_t *start;  // [G^d + 1]
   int G;
   float h;
+  const uint32_t *outside;  // nonzero: some node lies outside [0,1]^d, and
+                            // every query defers to the FP64 recheck
 };
 
 // Top-2 nearest eligible nodes (squared distances) of the query point
@@ -408,6 +415,16 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
   const int32_t *lids = kl.ids + cell * KN;
   const float *lrel = kl.rel + cell * KN * d;
   const float r2 = kl.r2[cell];
+  if (*g.outside) {  // the grid does not bound every node: settle in FP64
+    if (a.flag_list) {
+      const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
+      a.flag_list[pos] = gid | a.flag_tag;
+    }
+    a.t_out[gid] = tbox;
+    a.idx_out[gid] = -1;
+    a.st_out[gid] = VG_ST_NEAR_TIE | VG_ST_SUSPECT;
+    return false;
+  }
   int32_t k = kstart;
   if (!GRID) {
     // first candidate: the eligible listed node with the smallest t_k
@@ -640,6 +657,16 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
     a.st_out[ray] = VG_ST_SUSPECT;
     return;
   }
+  if (*g.outside) {  // the grid does not bound every node: settle in FP64
+    if (a.flag_list) {
+      const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
+      a.flag_list[pos] = ray | a.flag_tag;
+    }
+    a.t_out[ray] = __builtin_inff();
+    a.idx_out[ray] = -1;
+    a.st_out[ray] = VG_ST_NEAR_TIE | VG_ST_SUSPECT;
+    return;
+  }
   const int32_t *ex = a.n_excl > 0 ? a.excl + ray * a.n_excl : nullptr;
   int n_eta = 0;  // members of eta (entries past the nodes are padding)
   for (int e = 0; e < a.n_excl; ++e) n_eta += (ex[e] >= 0 && ex[e] < a.n);
@@ -841,8 +868,9 @@ size_t grid_bytes(int64_t n, int d) {
   size_t tmp = 0;
   (void)hipcub::DeviceScan::InclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr,
                                           (int)(cells + 1));
-  // cell_of, ids [n] i32; Xs [n][d] f32; counts, start, cursor [cells + 1]; scan temp
-  return (size_t)n * 8 + (size_t)n * d * 4 + 3 * (size_t)(cells + 1) * 4 + tmp + 7 * 256;
+  // cell_of, ids [n] i32; Xs [n][d] f32; counts, start, cursor [cells + 1];
+  // outside flag; scan temp
+  return (size_t)n * 8 + (size_t)n * d * 4 + 3 * (size_t)(cells + 1) * 4 + tmp + 8 * 256;
 }
 
 // Counting sort of the nodes into the grid's cells (grid_bytes of scratch).
@@ -856,14 +884,17 @@ hipError_t build_grid(const float *nodes, int64_t n, int d, Carve &cv, GridView 
   uint32_t *counts = cv.take<uint32_t>((size_t)(cells + 1));
   uint32_t *start = cv.take<uint32_t>((size_t)(cells + 1));
   uint32_t *cursor = cv.take<uint32_t>((size_t)(cells + 1));
+  uint32_t *outside = cv.take<uint32_t>(1);
   size_t tmp = 0;
   hipError_t e = hipcub::DeviceScan::InclusiveSum(nullptr, tmp, counts, start, (int)(cells + 1), s);
   if (e != hipSuccess) return e;
   void *tmpp = cv.take<char>(tmp);
   e = fill_u32(counts, 0u, cells + 1, s);
   if (e == hipSuccess) e = fill_u32(cursor, 0u, cells + 1, s);
+  if (e == hipSuccess) e = fill_u32(outside, 0u, 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(grid_count_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, nodes, n, d, G, cell_of, counts);
+  hipLaunchKernelGGL(grid_count_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, nodes, n, d, G, cell_of, counts,
+                     outside);
   // counts[0] = 0 and counts[c + 1] = size of cell c, so the inclusive scan
   // gives start[c] = nodes in cells before c (start[cells] = n)
   e = hipcub::DeviceScan::InclusiveSum(tmpp, tmp, counts, start, (int)(cells + 1), s);
@@ -871,7 +902,7 @@ hipError_t build_grid(const float *nodes, int64_t n, int d, Carve &cv, GridView 
   hipLaunchKernelGGL(grid_fill_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, nodes, n, d, cell_of, start, cursor,
                      Xs, ids);
   e = hipGetLastError();
-  g = GridView{Xs, ids, start, G, 1.f / (float)G};
+  g = GridView{Xs, ids, start, G, 1.f / (float)G, outside};
   return e;
 }
 
