@@ -1,21 +1,26 @@
-// The incircle RayCast of Algorithm 1 for the Monte-Carlo rays of every cell
-// (eta = {i}, origin x_i, clipped to the unit cube), with a uniform-grid
-// nearest-neighbour index: a sublinear alternative to the dense scan when N
-// is large and d small.
+// The incircle RayCast of Algorithm 1 on the GPU, with a uniform-grid
+// nearest-neighbour index: for the Monte-Carlo rays of every cell (eta =
+// {i}, origin x_i, clipped to the unit cube) and for general rays (an origin
+// equidistant to eta, e.g. the exhaustive search's edge rays).  A sublinear
+// alternative to the dense scan when N is large and d small.
 //
 // Index: G^d cells over [0,1]^d (about two nodes per cell), nodes sorted by
-// cell (counting sort), their coordinates stored in cell order.
+// cell (counting sort), their coordinates stored in cell order.  A node
+// outside [0,1]^d would escape the ring bound below, so its presence sends
+// every ray to the FP64 recheck.
 //
 // nn(q): the nearest node to q whose `skip` predicate of Algorithm 1 is false
-// (u.(x_k - x_i) > 0: the half-space ahead of the ray), with the second
-// nearest.  Distances are taken from coordinates relative to x_i, so their
-// rounding scales with the cell rather than with the cube.
-// Cells are visited in Chebyshev rings around q's cell; a node in ring rho
-// differs from q by at least (rho - 1) h in one coordinate (h = 1/G), also
-// when q lies outside the grid, so the search stops once ((rho - 1) h)^2
-// exceeds the second-best squared distance.
+// (u.(x_k - x_g) > 0: the half-space ahead of the ray; eta excluded), with
+// the second nearest.  Distances are taken from coordinates relative to the
+// ray's generator x_g, so their rounding scales with the cell rather than
+// with the cube.  Cells are visited in Chebyshev rings around q's (clamped)
+// cell; a node outside ring rho - 1 is at least (rho - 1) h away in one
+// coordinate and at least q's distance to the cube in the others, so the
+// search stops once that bound exceeds every distance that could still
+// change the answer or its certificate.  A query that would visit more than
+// a budget of ring offsets gives up, and its ray goes to the FP64 recheck.
 //
-// RayCast: Algorithm 1 needs a first generator candidate, and its
+// Monte-Carlo rays: Algorithm 1 needs a first generator candidate, and its
 // InitialHeuristic is undefined for |eta| = 1.  Any eligible node k gives an
 // upper bound t_k = |x_k - x_i|^2 / (2 u.(x_k - x_i)) on the result (eq. (t)
 // with r = x_i), so the first candidate is the best of the cell's K nearest
@@ -26,18 +31,23 @@
 // instead: if no eligible node is nearer to it than x_i, the exit point lies
 // in cell i and the cube face is the result; otherwise the loop starts from
 // the node nn returned.  Every candidate has t below the exit, so it lies
-// inside the cube, where the grid query is cheap.
+// inside the cube, where the grid query is cheap.  The cell's list answers a
+// query by itself when it provably holds every node that matters.
 //
-// Two passes: one thread per ray casts it while the cell's list answers its
-// queries (almost always); the few rays that need the grid are queued and
-// resumed by a second pass, so that grid walks do not hold up whole waves.
+// Two passes for the Monte-Carlo rays: one thread per ray casts it while the
+// cell's list answers its queries (almost always); the few rays that need
+// the grid are queued and resumed by a second pass, so that grid walks do
+// not hold up whole waves.
+//
+// General rays: Algorithm 1 as printed, from the origin or from
+// InitialHeuristic's point (incircle_ray below).
 //
 // Certificate: at the final candidate, the gap between the squared distances
 // of the nearest and second-nearest eligible node (the face test: between
-// the nearest eligible node and x_i) equals 2 u.(x_k - x_i)(t_k - t*) for the
+// the nearest eligible node and x_i) equals 2 u.(x_k - x_g)(t_k - t*) for the
 // runner-up k, so a gap above the FP32 error of the distances certifies the
-// result.  Other rays (and iteration caps, nearly grazing winners) are
-// queued for the FP64 recheck over all nodes.
+// result.  Other rays (and iteration caps, nearly grazing winners, queries
+// that gave up) are queued for the FP64 recheck over all nodes.
 #include <hipcub/hipcub.hpp>
 
 #include "vg_dfloat.h"

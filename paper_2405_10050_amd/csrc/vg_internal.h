@@ -169,7 +169,7 @@ int hmc_run(bool integrals, int d, int64_t n, const float *nodes, int64_t V, con
             float *F, float *cell, float *volume, hipStream_t s, std::string &err);
 
 // Incircle RayCast (Algorithm 1) of the Monte-Carlo rays with a grid index
-// (vg_incircle.hip): scratch of incircle_scratch_bytes(n, d); query counts
+// (vg_incircle.hip): scratch of incircle_scratch_bytes(n, d, R); query counts
 // added to nn_calls[0] (all) and nn_calls[1] (answered by the grid).
 size_t incircle_scratch_bytes(int64_t n, int d, int R);
 hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned long long *nn_calls,
