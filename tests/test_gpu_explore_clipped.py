@@ -99,3 +99,16 @@ def test_clipped_explore_d6_n10000_properties(vg):
         assert others.min() >= rho.min() * (1 - 1e-9)
         for f in key[key >= n] - n:
             assert p[f // 2] == float(f % 2)
+
+
+@pytest.mark.parametrize("d,n", [(2, 1000), (3, 300), (4, 100)])
+def test_clipped_explore_with_algorithm_1_rays(vg, d, n):
+    """The clipped search with its edge rays cast by Algorithm 1 (grid index,
+    InitialHeuristic over the kept generators) finds the same vertices."""
+    X = W.uniform_cloud(n, d, seed=50 + d)
+    Xd = torch.from_numpy(X).cuda()
+    ref = vg.explore(Xd, clip=True)
+    for heuristic in (False, True):
+        got = vg.explore(Xd, clip=True, incircle=True, heuristic=heuristic)
+        assert np.array_equal(np.unique(got["sigma"], axis=0), np.unique(ref["sigma"], axis=0))
+        assert got["nn_calls"] > 0
