@@ -161,13 +161,23 @@ __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
   int nh = 0;
   for (int p = p0; p < p1; ++p)
     if (p == 0 || (keys[p] >> 32) != (keys[p - 1] >> 32)) ++nh;
-  seg[tid + 1] = nh;
-  __syncthreads();
-  if (tid == 0) {
-    seg[0] = 0;
-    for (int q = 1; q <= NT; ++q) seg[q] += seg[q - 1];
+  // inclusive scan of the head counts: within each wave by shuffles, then
+  // the totals of the waves before it
+  {
+    __shared__ int wave_tot[NT / 64];
+    const int lane = tid & 63, wave = tid >> 6;
+    int v = nh;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(v, off);
+      if (lane >= off) v += o;
+    }
+    if (lane == 63) wave_tot[wave] = v;
+    __syncthreads();
+    for (int w2 = 0; w2 < wave; ++w2) v += wave_tot[w2];
+    seg[tid + 1] = v;
+    if (tid == 0) seg[0] = 0;
+    __syncthreads();
   }
-  __syncthreads();
   // run sums of the ray weights: the areas, then (weights times f at the
   // hit point) the facet integrals of f
   for (int pass = 0; pass < 2; ++pass) {
