@@ -239,7 +239,12 @@ static int knn_count(int d) { return d <= 2 ? 16 : (d <= 3 ? 32 : (d <= 4 ? 48 :
 // it was either rejected against a list bound that only decreases, or lies
 // beyond the ring bound.  Ring search stopping once the ring bound exceeds
 // the KN-th distance; the list is kept sorted by a fully unrolled insertion
-// so it stays in registers.
+// so it stays in registers.  Candidates below the list's current bound are
+// first appended to a short per-lane buffer, which the whole wave merges
+// into the lists at once when some lane's buffer is full (and before every
+// stopping test): a wave then runs the insertion a few times per node
+// instead of once for every candidate that any of its lanes accepts.  The
+// insertions happen in candidate order, so the lists are the same.
 struct KnnList {
   int32_t *ids;  // [n][KN]
   float *rel;    // [n][KN][d]
@@ -269,8 +274,37 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
     dl[s] = __builtin_inff();
     il[s] = -1;
   }
+  constexpr int BUF = 8;
+  float bd[BUF];
+  int32_t bi[BUF];
+  int bc = 0;
+  // merge the buffer into the sorted list, in append order
+  auto flush = [&]() {
+#pragma unroll
+    for (int b = 0; b < BUF; ++b) {
+      if (b < bc) {
+        float dist = bd[b];
+        int32_t node = bi[b];
+        if (dist < dl[KN - 1]) {
+#pragma unroll
+          for (int s = 0; s < KN; ++s) {
+            if (dist < dl[s]) {
+              const float td = dl[s];
+              const int32_t ti = il[s];
+              dl[s] = dist;
+              il[s] = node;
+              dist = td;
+              node = ti;
+            }
+          }
+        }
+      }
+    }
+    bc = 0;
+  };
   for (int rho = 0; rho < g.G; ++rho) {
     if (rho >= 1) {
+      flush();
       const float lb = fmaxf(0.f, (float)(rho - 1) * g.h - kRingSlack);
       if (lb * lb > dl[KN - 1]) break;
     }
@@ -305,17 +339,15 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
           }
           if (dist < dl[KN - 1]) {
 #pragma unroll
-            for (int s = 0; s < KN; ++s) {
-              if (dist < dl[s]) {
-                const float td = dl[s];
-                const int32_t ti = il[s];
-                dl[s] = dist;
-                il[s] = node;
-                dist = td;
-                node = ti;
+            for (int b = 0; b < BUF; ++b) {
+              if (b == bc) {
+                bd[b] = dist;
+                bi[b] = node;
               }
             }
+            ++bc;
           }
+          if (__any(bc == BUF)) flush();
         }
       }
       int k = d - 1;
@@ -327,6 +359,7 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
       if (k < 0 || span == 1) break;
     }
   }
+  flush();
 #pragma unroll
   for (int s = 0; s < KN; ++s) {
     out.ids[i * KN + s] = il[s];
