@@ -470,10 +470,13 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
   }
   int32_t k = kstart;
   if (!GRID) {
-    // first candidate: the eligible listed node with the smallest t_k
-    // (grazing nodes are left out; their t_k is large anyway)
+    // first candidate: the eligible listed node with the smallest t_k =
+    // num / (2 den) (grazing nodes, den <= |e| / 4096, are left out; their
+    // t_k is large anyway).  Division-free: with den > 0 the order of the
+    // t_k is that of the cross products; the best starts at the exit,
+    // num / den = 2 tbox.  Any eligible node is a valid start.
     k = -1;
-    float tbest = tbox;
+    float nb = 2.f * tbox, db = 1.f;
 #pragma unroll 4
     for (int s = 0; s < KN; ++s) {
       const int32_t ks = lids[s];
@@ -487,12 +490,10 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
           den = __builtin_fmaf(u[q2], e, den);
         }
       }
-      if (den > (1.f / 4096.f) * sqrtf(num)) {
-        const float tk = num / (2.f * den);
-        if (tk < tbest) {
-          tbest = tk;
-          k = ks;
-        }
+      if (den > 0.f && den * den > 0x1p-24f * num && num * db < nb * den) {
+        nb = num;
+        db = den;
+        k = ks;
       }
     }
   }
