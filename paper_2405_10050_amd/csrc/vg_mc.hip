@@ -83,6 +83,49 @@ __device__ void bitonic_sort(uint64_t *keys, int P) {
   __syncthreads();
 }
 
+// The terms of ray k of `cell`: l^d, l^{d+2}, the volume integrand of f
+// (sum_s f(x_i + t_s l u) t_s^{d-1} l^d) and the area weight, computed as
+// 2 l^d / |x_j - x_i| (= l^{d-1} / |n.u| at the bisector) or l^d / h for a
+// cube face at distance h; its facet key (j, k).
+template <int DK>
+__device__ __forceinline__ void ray_terms(const AccumArgs &a, int64_t cell, const float (&xi)[DK], int k,
+                                          float &ld, float &le, float &lf, float &wa, uint64_t &key) {
+  const int d = a.d, R = a.R, M1 = a.m + 1;
+  const int64_t gid = cell * R + k;
+  const float l = a.t[gid];
+  const int32_t j = a.idx[gid];
+  ld = powi(l, d);
+  le = ld * l * l;
+  lf = 0.f;
+  if (a.fvals && a.m > 0) {
+    float g = 0.f;
+    for (int q = 0; q < a.m; ++q) g += a.fvals[gid * M1 + 1 + q] * powi(a.tsamp[gid * a.m + q], d - 1);
+    lf = g * ld;
+  }
+  wa = 0.f;
+  if (j >= 0) {
+    const float *xj = a.nodes + (int64_t)j * d;
+    float n2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < DK; ++q) {
+      if (q < d) {
+        const float e = xj[q] - xi[q];
+        n2 = __builtin_fmaf(e, e, n2);
+      }
+    }
+    wa = 2.f * ld / sqrtf(n2);
+  } else if (j <= -2) {
+    const int face = -2 - j, kk = face >> 1;
+    float xk = 0.f;
+#pragma unroll
+    for (int q = 0; q < DK; ++q)
+      if (q == kk) xk = xi[q];
+    const float h = (face & 1) ? 1.f - xk : xk;
+    wa = ld / h;
+  }
+  key = facet_key(j, k);
+}
+
 template <int DK>
 __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
   // one 16-byte aligned dynamic block: keys [P] u64 | w [P] f32 | red [NT] f32 | seg [NT+1] i32
@@ -106,39 +149,13 @@ __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
   const int M1 = a.m + 1;
   for (int k = tid; k < P; k += NT) {
     if (k < R) {
-      const int64_t gid = cell * R + k;
-      const float l = a.t[gid];
-      const int32_t j = a.idx[gid];
-      const float ld = powi(l, d);
+      float ld, le, lf, wa;
+      uint64_t key;
+      ray_terms<DK>(a, cell, xi, k, ld, le, lf, wa, key);
       pv += ld;
-      pe += ld * l * l;
-      if (a.fvals && a.m > 0) {  // volume integral of f: sum_s f(x_i + t_s l u) t_s^{d-1} l^d
-        float g = 0.f;
-        for (int q = 0; q < a.m; ++q) g += a.fvals[gid * M1 + 1 + q] * powi(a.tsamp[gid * a.m + q], d - 1);
-        pf += g * ld;
-      }
-      float wa = 0.f;
-      if (j >= 0) {
-        const float *xj = a.nodes + (int64_t)j * d;
-        float n2 = 0.f;
-#pragma unroll
-        for (int q = 0; q < DK; ++q) {
-          if (q < d) {
-            const float e = xj[q] - xi[q];
-            n2 = __builtin_fmaf(e, e, n2);
-          }
-        }
-        wa = 2.f * ld / sqrtf(n2);
-      } else if (j <= -2) {
-        const int face = -2 - j, kk = face >> 1;
-        float xk = 0.f;
-#pragma unroll
-        for (int q = 0; q < DK; ++q)
-          if (q == kk) xk = xi[q];
-        const float h = (face & 1) ? 1.f - xk : xk;
-        wa = ld / h;
-      }
-      keys[k] = facet_key(j, k);
+      pe += le;
+      pf += lf;
+      keys[k] = key;
       w[k] = wa;
     } else {
       keys[k] = ~0ull;
@@ -204,6 +221,83 @@ __global__ __launch_bounds__(NT) void accum_kernel(AccumArgs a) {
     }
   }
   if (tid == 0) a.facet_count[cell] = seg[NT];
+}
+
+// The same for at most 64 rays per cell: one wave per cell (four cells per
+// workgroup), each lane one ray.  The facet keys are sorted across the wave
+// by a bitonic network of shuffles, runs of equal j are found against the
+// neighbouring lane, and their weights summed by a segmented scan, so no
+// LDS and no barrier is needed.  Sums run in a shuffle tree, so they agree
+// with the workgroup kernel's to rounding.
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Inclusive sums of v within runs that start at the lanes with head set.
+__device__ __forceinline__ float segmented_scan(float v, bool head, int lane) {
+  int f = head ? 1 : 0;
+  for (int off = 1; off < 64; off <<= 1) {
+    const float ov = __shfl_up(v, off);
+    const int of = __shfl_up(f, off);
+    if (lane >= off && !f) {
+      v += ov;
+      f = of;
+    }
+  }
+  return v;
+}
+
+template <int DK>
+__global__ __launch_bounds__(NT) void accum_wave_kernel(AccumArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cell = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (cell >= a.n) return;  // the whole wave
+  const int d = a.d, R = a.R, M1 = a.m + 1;
+  float xi[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+  float ld = 0.f, le = 0.f, lf = 0.f, wa = 0.f;
+  uint64_t key = ~0ull;
+  if (lane < R) ray_terms<DK>(a, cell, xi, lane, ld, le, lf, wa, key);
+  const float sum_v = wave_sum(ld), sum_e = wave_sum(le), sum_f = wave_sum(lf);
+  if (lane == 0) {
+    if (a.volume) a.volume[cell] = a.sv * sum_v;
+    if (a.energy2) a.energy2[cell] = a.se * sum_e;
+    if (a.fint_volume) a.fint_volume[cell] = a.sf * sum_f;
+  }
+  if (!a.facet_j) return;
+  // bitonic sort of the 64 keys, ascending
+  for (int size = 2; size <= 64; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint64_t other = __shfl_xor(key, stride);
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      const uint64_t lo = key < other ? key : other, hi = key < other ? other : key;
+      key = (lower == up) ? lo : hi;
+    }
+  }
+  const uint32_t hj = (uint32_t)(key >> 32);
+  const uint32_t prev = __shfl_up(hj, 1);
+  const uint32_t next = __shfl_down(hj, 1);
+  const bool valid = lane < R;
+  const bool head = valid && (lane == 0 || prev != hj);
+  const bool tail = valid && (lane == R - 1 || next != hj);
+  const unsigned long long heads = __ballot(head);
+  const int slot = __popcll(heads & ((2ull << lane) - 1ull)) - 1;  // run of this lane
+  const int ray = valid ? (int)(uint32_t)key : 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    float *out = pass == 0 ? a.facet_area : a.fint_facet;
+    if (pass == 1 && !a.fint_facet) break;
+    float w = __shfl(wa, ray);  // the weight of the ray now at this lane
+    if (pass == 1) w *= valid ? a.fvals[(cell * R + ray) * M1] : 0.f;
+    const float run = segmented_scan(valid ? w : 0.f, head, lane);
+    if (tail) {
+      if (pass == 0) a.facet_j[cell * R + slot] = key_j(key);
+      if (out) out[cell * R + slot] = a.sa * run;
+    }
+  }
+  if (lane == 0) a.facet_count[cell] = __popcll(heads);
 }
 
 // Algorithm 3's sample points of every ray: the hit point, then the interior
@@ -390,6 +484,18 @@ hipError_t launch_accum(const AccumArgs &a, hipStream_t s) {
   const size_t shm = (size_t)P * (sizeof(uint64_t) + sizeof(float)) + NT * sizeof(float) +
                      (NT + 1) * sizeof(int32_t);
   dim3 grid((unsigned)a.n), blk(NT);
+  if (a.R <= 64) {  // one wave per cell
+    const dim3 gw((unsigned)((a.n + NT / 64 - 1) / (NT / 64)));
+    if (a.d <= 4)
+      hipLaunchKernelGGL(accum_wave_kernel<4>, gw, blk, 0, s, a);
+    else if (a.d <= 8)
+      hipLaunchKernelGGL(accum_wave_kernel<8>, gw, blk, 0, s, a);
+    else if (a.d <= 12)
+      hipLaunchKernelGGL(accum_wave_kernel<12>, gw, blk, 0, s, a);
+    else
+      hipLaunchKernelGGL(accum_wave_kernel<16>, gw, blk, 0, s, a);
+    return hipGetLastError();
+  }
   if (a.d <= 4)
     hipLaunchKernelGGL(accum_kernel<4>, grid, blk, shm, s, a);
   else if (a.d <= 8)

@@ -30,7 +30,8 @@ def _gpu_facets(res, n):
 @pytest.mark.parametrize("d,n,R,prec", [(2, 1000, 128, "fp32"), (3, 400, 256, "fp32"),
                                         (4, 500, 512, "fp32"), (6, 300, 100, "fp32"),
                                         (10, 300, 1024, "fp32"), (10, 300, 1024, "bf16x3"),
-                                        (16, 120, 64, "fp32")])
+                                        (16, 120, 64, "fp32"), (2, 500, 1, "fp32"), (3, 300, 16, "fp32"),
+                                        (5, 200, 33, "fp32"), (3, 1000, 64, "bf16x3")])
 def test_mc_volume_area_match_oracle(vg, d, n, R, prec):
     print(f"mc d={d} n={n} R={R} {prec}", flush=True)
     X = W.uniform_cloud(n, d, seed=d)
