@@ -52,6 +52,95 @@ constexpr int NT1 = 512;
 constexpr int WAVES1 = NT1 / 64;
 
 #pragma clang fp contract(off)
+// The end of a ray's recheck (lane 0 of its wave or workgroup): the cube
+// clip, the status bits and the outputs.
+template <int DK>
+__device__ __forceinline__ void finish_ray(const RecheckArgs &a, int64_t ray, int d, int clip, const double (&x)[DK],
+                                           const double (&u)[DK], const Top2 &tp) {
+  double t1 = tp.t1, t2 = tp.t2;
+  int32_t i1 = tp.i1;
+  if (clip) {
+    double tb = __builtin_inf();
+    int face = -1;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k >= d) continue;
+      double tk;
+      int fc;
+      if (u[k] > 0.0) {
+        tk = (1.0 - x[k]) / u[k];
+        fc = 2 * k + 1;
+      } else if (u[k] < 0.0) {
+        tk = (0.0 - x[k]) / u[k];
+        fc = 2 * k;
+      } else {
+        continue;
+      }
+      if (tk < tb) {
+        tb = tk;
+        face = fc;
+      }
+    }
+    if (face >= 0) {
+      if (tb < t1) {
+        t2 = t1;
+        t1 = tb;
+        i1 = -2 - face;
+      } else if (tb < t2) {
+        t2 = tb;
+      }
+    }
+  }
+  uint8_t st = (uint8_t)((a.st_out[ray] & ~VG_ST_NO_HIT) | VG_ST_RECHECKED);
+  if (i1 == -1) st |= VG_ST_NO_HIT;
+  if (t2 - t1 <= 1e-9 * fabs(t1)) {
+    st |= VG_ST_FP64_TIE;
+    atomicAdd(a.tie_counter, 1u);
+  }
+  a.t_out[ray] = (float)t1;
+  if (a.t64_out) a.t64_out[ray] = t1;
+  a.idx_out[ray] = i1;
+  a.st_out[ray] = st;
+}
+
+// One node r (coordinates xr, as read from memory) against the ray: eq. (t)
+// in FP64 with the factored numerator, into the running top-2.  CELLS: the
+// Monte-Carlo form, x = g.
+template <int DK, bool CELLS>
+__device__ __forceinline__ void eval_node(const float *xr, int stride, int d, int32_t r, const double (&x)[DK],
+                                          const double (&u)[DK], const double (&g)[DK],
+                                          const double (&gx)[DK], Top2 &tp) {
+  double e[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) e[k] = k < d ? (double)xr[k * stride] - g[k] : 0.0;
+  double den = 0.0;
+#pragma unroll
+  for (int k = 0; k < DK; ++k)
+    if (k < d) den += u[k] * e[k];
+  if (!(den > 0.0)) return;
+  // |r - x|^2 - |g - x|^2 as (r - g).((r - x) + (g - x))
+  double num = 0.0;
+  if (CELLS) {
+#pragma unroll
+    for (int k = 0; k < DK; ++k)
+      if (k < d) num += e[k] * e[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < DK; ++k)
+      if (k < d) num += e[k] * (((double)xr[k * stride] - x[k]) + gx[k]);
+  }
+  // cheap filter (relaxed by 1e-12 so no candidate within rounding is lost)
+  if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) return;
+  const double t = num / (2.0 * den);
+  if (t < tp.t1) {
+    tp.t2 = tp.t1;
+    tp.t1 = t;
+    tp.i1 = r;
+  } else if (t < tp.t2) {
+    tp.t2 = t;
+  }
+}
+
 // DK: the dimension rounded up to 4, 8, 12 or 16 (loops guard k < d, so the
 // order of every FP64 sum is the plain k = 0 .. d-1 order).  CELLS: the
 // Monte-Carlo rays of a cell, x = g = x_i and eta = {i}; there the numerator
@@ -131,35 +220,7 @@ __global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
           for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
         }
         if (skip) continue;
-        double e[DK];
-#pragma unroll
-        for (int k = 0; k < DK; ++k) e[k] = k < d ? (double)tile[k * NT1 + q] - g[k] : 0.0;
-        double den = 0.0;
-#pragma unroll
-        for (int k = 0; k < DK; ++k)
-          if (k < d) den += u[k] * e[k];
-        if (!(den > 0.0)) continue;
-        // |r - x|^2 - |g - x|^2 as (r - g).((r - x) + (g - x))
-        double num = 0.0;
-        if (CELLS) {
-#pragma unroll
-          for (int k = 0; k < DK; ++k)
-            if (k < d) num += e[k] * e[k];
-        } else {
-#pragma unroll
-          for (int k = 0; k < DK; ++k)
-            if (k < d) num += e[k] * (((double)tile[k * NT1 + q] - x[k]) + gx[k]);
-        }
-        // cheap filter (relaxed by 1e-12 so no candidate within rounding is lost)
-        if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) continue;
-        const double t = num / (2.0 * den);
-        if (t < tp.t1) {
-          tp.t2 = tp.t1;
-          tp.t1 = t;
-          tp.i1 = r;
-        } else if (t < tp.t2) {
-          tp.t2 = t;
-        }
+        eval_node<DK, CELLS>(tile + q, NT1, d, r, x, u, g, gx, tp);
       }
     }
     if (live) {
@@ -170,52 +231,89 @@ __global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
         o.i1 = __shfl_xor(tp.i1, off);
         tp = merge(tp, o);
       }
-      if (lane == 0) {
-        double t1 = tp.t1, t2 = tp.t2;
-        int32_t i1 = tp.i1;
-        if (clip) {
-          double tb = __builtin_inf();
-          int face = -1;
+      if (lane == 0) finish_ray<DK>(a, ray, d, clip, x, u, tp);
+    }
+  }
+}
+
+// Large clouds: one queued ray per workgroup, its 512 threads striding over
+// the nodes read from memory (a few queued rays then still fill the GPU),
+// merged by shuffles and across waves in LDS.  The same node expression and
+// finish as recheck_kernel, and the top-2 does not depend on the order of
+// the merges, so the results are the same.
+template <int DK, bool CELLS>
+__global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a) {
+  __shared__ double st1[WAVES1], st2[WAVES1];
+  __shared__ int32_t si1[WAVES1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int d = a.d;
+  const int64_t n = a.n;
+  const uint32_t cnt = a.counters[CNT_FLAGGED];
+  for (uint32_t f = blockIdx.x; f < cnt; f += gridDim.x) {
+    const int64_t ray = a.flag_list[f];
+    int n_excl = 0, clip = 0;
+    int32_t gi;
+    double x[DK], u[DK], g[DK];
+    int32_t ex[VG_MAX_DIM];
 #pragma unroll
-          for (int k = 0; k < DK; ++k) {
-            if (k >= d) continue;
-            double tk;
-            int fc;
-            if (u[k] > 0.0) {
-              tk = (1.0 - x[k]) / u[k];
-              fc = 2 * k + 1;
-            } else if (u[k] < 0.0) {
-              tk = (0.0 - x[k]) / u[k];
-              fc = 2 * k;
-            } else {
-              continue;
-            }
-            if (tk < tb) {
-              tb = tk;
-              face = fc;
-            }
-          }
-          if (face >= 0) {
-            if (tb < t1) {
-              t2 = t1;
-              t1 = tb;
-              i1 = -2 - face;
-            } else if (tb < t2) {
-              t2 = tb;
-            }
-          }
-        }
-        uint8_t st = (uint8_t)((a.st_out[ray] & ~VG_ST_NO_HIT) | VG_ST_RECHECKED);
-        if (i1 == -1) st |= VG_ST_NO_HIT;
-        if (t2 - t1 <= 1e-9 * fabs(t1)) {
-          st |= VG_ST_FP64_TIE;
-          atomicAdd(a.tie_counter, 1u);
-        }
-        a.t_out[ray] = (float)t1;
-        if (a.t64_out) a.t64_out[ray] = t1;
-        a.idx_out[ray] = i1;
-        a.st_out[ray] = st;
+    for (int e = 0; e < VG_MAX_DIM; ++e) ex[e] = -1;
+    if (CELLS) {
+      gi = (int32_t)(ray / a.R);
+      clip = 1;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) u[k] = k < d ? (double)a.dirs[ray * d + k] : 0.0;
+    } else {
+      gi = a.gen[ray];
+      n_excl = a.n_excl;
+      clip = a.clip;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        x[k] = k < d ? (a.mode == RAYS_F64 ? a.o64[ray * d + k] : (double)a.o32[ray * d + k]) : 0.0;
+        u[k] = k < d ? (a.mode == RAYS_F64 ? a.u64[ray * d + k] : (double)a.u32[ray * d + k]) : 0.0;
       }
+#pragma unroll
+      for (int e = 0; e < VG_MAX_DIM; ++e)
+        if (e < n_excl) ex[e] = a.excl[ray * n_excl + e];
+    }
+#pragma unroll
+    for (int k = 0; k < DK; ++k) g[k] = k < d ? (double)a.nodes[(int64_t)gi * d + k] : 0.0;
+    if (CELLS) {
+#pragma unroll
+      for (int k = 0; k < DK; ++k) x[k] = g[k];
+    }
+    double gx[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) gx[k] = g[k] - x[k];
+    Top2 tp{__builtin_inf(), __builtin_inf(), -1};
+    for (int64_t r = tid; r < n; r += NT1) {
+      bool skip;
+      if (CELLS) {
+        skip = r == gi;
+      } else {
+        skip = false;
+#pragma unroll
+        for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
+      }
+      if (!skip) eval_node<DK, CELLS>(a.nodes + r * d, 1, d, (int32_t)r, x, u, g, gx, tp);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      Top2 o;
+      o.t1 = __shfl_xor(tp.t1, off);
+      o.t2 = __shfl_xor(tp.t2, off);
+      o.i1 = __shfl_xor(tp.i1, off);
+      tp = merge(tp, o);
+    }
+    __syncthreads();  // the previous ray's merge has read the LDS slots
+    if (lane == 0) {
+      st1[w] = tp.t1;
+      st2[w] = tp.t2;
+      si1[w] = tp.i1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Top2 all{st1[0], st2[0], si1[0]};
+      for (int q = 1; q < WAVES1; ++q) all = merge(all, Top2{st1[q], st2[q], si1[q]});
+      finish_ray<DK>(a, ray, d, clip, x, u, all);
     }
   }
 }
@@ -437,12 +535,19 @@ hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
   if (max_grid <= 0) return hipSuccess;
   const dim3 grid((max_grid + WAVES1 - 1) / WAVES1), blk(NT1);
   const bool cells = a.mode == RAYS_CELLS;
-#define VG_RECHECK(DKV)                                                      \
-  do {                                                                      \
-    if (cells)                                                              \
-      hipLaunchKernelGGL((recheck_kernel<DKV, true>), grid, blk, 0, s, a);  \
-    else                                                                    \
-      hipLaunchKernelGGL((recheck_kernel<DKV, false>), grid, blk, 0, s, a); \
+  // large clouds: a workgroup per queued ray (the queue is often short there)
+  const bool wide = a.n >= (int64_t(1) << 18);
+  const dim3 gridw(max_grid);
+#define VG_RECHECK(DKV)                                                            \
+  do {                                                                            \
+    if (wide && cells)                                                            \
+      hipLaunchKernelGGL((recheck_wide_kernel<DKV, true>), gridw, blk, 0, s, a);  \
+    else if (wide)                                                                \
+      hipLaunchKernelGGL((recheck_wide_kernel<DKV, false>), gridw, blk, 0, s, a); \
+    else if (cells)                                                               \
+      hipLaunchKernelGGL((recheck_kernel<DKV, true>), grid, blk, 0, s, a);        \
+    else                                                                          \
+      hipLaunchKernelGGL((recheck_kernel<DKV, false>), grid, blk, 0, s, a);       \
   } while (0)
   if (a.d <= 4)
     VG_RECHECK(4);

@@ -85,3 +85,39 @@ def test_incircle_with_nodes_outside_the_cube_defers_to_fp64(vg, heuristic):
     assert vg.stats()["flagged"] == m
     t_ref, idx_ref, t2_ref = oracle.raycast(X, O, U, g, excl=g[:, None], clip=False)
     compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+
+
+def test_wide_recheck_general_rays_match_oracle(vg):
+    """N = 300 000 (the FP64 recheck then takes one workgroup per queued ray):
+    nodes outside the cube send every incircle ray to it."""
+    d, n, m = 3, 300_000, 2000
+    rng = np.random.default_rng(36)
+    X = (rng.random((n, d)) * 1.2 - 0.1).astype(np.float32)
+    g = rng.integers(n, size=m).astype(np.int32)
+    U = rng.standard_normal((m, d))
+    U = (U / np.linalg.norm(U, axis=1, keepdims=True)).astype(np.float32)
+    O = X[g]
+    dev = torch.device("cuda", 0)
+    t, idx, st = vg.raycast(torch.from_numpy(X).to(dev), torch.from_numpy(O).to(dev), torch.from_numpy(U).to(dev),
+                            torch.from_numpy(g).to(dev), torch.from_numpy(g[:, None].copy()).to(dev), clip=True,
+                            incircle=True)
+    assert vg.stats()["flagged"] == m
+    t_ref, idx_ref, t2_ref = oracle.raycast(X, O, U, g, excl=g[:, None], clip=True)
+    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+
+
+def test_wide_recheck_cells_match_oracle(vg):
+    """The Monte-Carlo rays of N = 300 000 cells: the cells holding rays the
+    FP32 scan flagged (settled by the wide FP64 recheck) against the oracle."""
+    d, n, R = 3, 300_000, 8
+    X = W.uniform_cloud(n, d, seed=37)
+    dev = torch.device("cuda", 0)
+    dirs = W.mc_directions_device(n, R, d, seed=38, device=dev)
+    t, idx, st = vg.raycast_cells(torch.from_numpy(X).to(dev), dirs)
+    rechecked = ((st & vg.ST_RECHECKED) != 0).any(dim=1).nonzero().flatten().cpu().numpy()
+    assert rechecked.size > 0
+    cells = rechecked[:200]
+    D = dirs[torch.from_numpy(cells).to(dev)].cpu().numpy()
+    t_ref, idx_ref, t2_ref = oracle.raycast_cells(X, cells, D)
+    sel = torch.from_numpy(cells).to(dev)
+    compare_rays(t[sel].cpu().numpy(), idx[sel].cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
