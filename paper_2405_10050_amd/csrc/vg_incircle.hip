@@ -60,10 +60,14 @@ constexpr int NT = 256;
 constexpr int kMaxIter = 64;
 // Ring offsets one query may visit.  A query point far outside the cube sees
 // a whole face nearly equidistant, and a ray with no eligible node sweeps
-// the grid: past this budget the query gives up (i1 = kGaveUp) and the ray
-// goes to the FP64 recheck over all nodes.  A full sweep of a grid of
-// N = 1000 nodes in d = 2..5 stays below it.
-constexpr int kRingBudget = 1 << 15;
+// the grid: past the budget the query gives up (i1 = kGaveUp) and the ray
+// goes to the FP64 recheck over all nodes.  Where a full sweep costs at most
+// kFullSweep offsets (every grid of N = 1000 nodes in d = 2..5) the budget
+// is that sweep, so no query gives up; on larger grids it is kRingBudget,
+// about twelve times a local query in 3-D, so that no ray holds up its
+// breadth-first level for long.
+constexpr int kFullSweep = 1 << 15;
+constexpr int kRingBudget = 1 << 12;
 constexpr int32_t kGaveUp = -2;
 
 // Cell of every node; a node outside [0,1]^d (clamped into a boundary cell,
@@ -126,6 +130,7 @@ struct GridView {
   float h;
   const uint32_t *outside;  // nonzero: some node lies outside [0,1]^d, and
                             // every query defers to the FP64 recheck
+  int budget;               // ring offsets one query may visit
 };
 
 // Top-2 nearest eligible nodes (squared distances) of the query point
@@ -156,7 +161,7 @@ __device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float
   out2 *= 1.f - 0x1p-20f;
   i1 = -1;
   d1 = d2 = __builtin_inff();
-  int budget = kRingBudget;
+  int budget = g.budget;
   for (int rho = 0; rho < g.G; ++rho) {
     if (rho >= 1) {
       const float lb = fmaxf(0.f, (float)(rho - 1) * g.h - kRingSlack);
@@ -946,7 +951,12 @@ hipError_t build_grid(const float *nodes, int64_t n, int d, Carve &cv, GridView 
   hipLaunchKernelGGL(grid_fill_kernel, dim3(blocks_of(n)), dim3(NT), 0, s, nodes, n, d, cell_of, start, cursor,
                      Xs, ids);
   e = hipGetLastError();
-  g = GridView{Xs, ids, start, G, 1.f / (float)G, outside};
+  // offsets of a full sweep: sum over the rings of the (2 rho + 1)^d offsets
+  // the ring loop enumerates
+  double sweep = 0.0;
+  for (int rho = 0; rho < G && sweep <= (double)kFullSweep; ++rho) sweep += std::pow(2.0 * rho + 1.0, d);
+  const int budget = sweep <= (double)kFullSweep ? (int)sweep : kRingBudget;
+  g = GridView{Xs, ids, start, G, 1.f / (float)G, outside, budget};
   return e;
 }
 
