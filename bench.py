@@ -333,7 +333,8 @@ def bench_hmc(args):
 
 
 def bench_explore_incircle(args):
-    """Exhaustive search of a uniform d=3 cloud of N = 100 000 with the edge
+    """Exhaustive search of a uniform cloud (d=3, N = 100 000, or d=2,
+    N = 300 000, the largest 2-D size of the paper's timings) with the edge
     rays cast by Algorithm 1 (grid index, InitialHeuristic); the same search
     with the dense scan is timed beside it and must return the same
     vertices."""
@@ -342,8 +343,8 @@ def bench_explore_incircle(args):
     import paper_2405_10050_amd as vg
     import workloads as W
 
-    d, n = 3, 100_000
-    print("[bench] explore d=3 N=100000 with Algorithm 1 (warm-up, then timed)", file=sys.stderr, flush=True)
+    d, n = (3, 100_000) if args.workload == "explore_incircle_d3_n100000" else (2, 300_000)
+    print(f"[bench] explore d={d} N={n} with Algorithm 1 (warm-up, then timed)", file=sys.stderr, flush=True)
     X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).cuda()
     draws = W.descent_draws(d)
     if args.warmup:
@@ -411,7 +412,7 @@ def main():
                              "uniform_d2_n1000", "uniform_d6_n10000", "nbr_d4_n50000",
                              "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000",
                              "clipped_d2_n1000", "clipped_d6_n10000", "hmc_d5_n10000",
-                             "explore_incircle_d3_n100000"])
+                             "explore_incircle_d3_n100000", "explore_incircle_d2_n300000"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -440,7 +441,8 @@ def main():
                  "nbr_d4_n50000": bench_nbr, "nbr_d6_n10000": bench_nbr,
                  "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle,
                  "clipped_d2_n1000": bench_explore, "clipped_d6_n10000": bench_explore,
-                 "hmc_d5_n10000": bench_hmc, "explore_incircle_d3_n100000": bench_explore_incircle}
+                 "hmc_d5_n10000": bench_hmc, "explore_incircle_d3_n100000": bench_explore_incircle,
+                 "explore_incircle_d2_n300000": bench_explore_incircle}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 
