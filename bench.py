@@ -425,8 +425,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Monte-Carlo "
-              "path shards over cells with no exchange, and this build measures one GPU's share",
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): it measures one GPU's "
+              "share of the work; the Monte-Carlo path shards over cells with no exchange",
               file=sys.stderr)
         sys.exit(1)
 

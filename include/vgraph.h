@@ -48,7 +48,7 @@ typedef enum vg_status {
   VG_EINVAL = -1,       /* bad argument (null pointer, size, dimension)      */
   VG_ENOMEM = -2,       /* device or host allocation failed                  */
   VG_EDEVICE = -3,      /* a HIP call failed                                 */
-  VG_EUNSUPPORTED = -4  /* valid request outside what this build supports    */
+  VG_EUNSUPPORTED = -4  /* valid request outside what the library supports  */
 } vg_status;
 
 /* flags */
