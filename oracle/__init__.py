@@ -103,6 +103,8 @@ def _load():
         lib.vgo_explore_clipped.argtypes = [i32, i64, P]
         lib.vgo_explore_clipped.restype = P
         lib.vgo_clipped_vertex.argtypes = [i32, i64, P, P, P]
+        lib.vgo_explore_periodic.argtypes = [i32, i64, P, P, i32, P]
+        lib.vgo_explore_periodic.restype = P
         lib.vgo_star.argtypes = [i32, i64, P, i32, P, i32, P, i64]
         lib.vgo_star.restype = i64
         _lib = lib
@@ -259,6 +261,52 @@ def explore_clipped(nodes):
         coord = np.empty((nv, d))
         lib.vgo_mesh_copy(h, _p(sig), _p(coord), None, None)
         return dict(sigma=sig, coord=coord, raycasts=int(lib.vgo_mesh_raycasts(h)),
+                    duplicates=int(lib.vgo_mesh_duplicates(h)))
+    finally:
+        lib.vgo_mesh_free(h)
+
+
+_PERIODIC_FAIL = {-1: "nodes outside [0,1)^d, n * 3^d >= 2^31 or allocation",
+                  -2: "a vertex ball reaches past the images in [-1,2]^d",
+                  -3: "a vertex ball of radius >= 1/2 (key outside the shift range)",
+                  -4: "singular vertex or Descent out of draws"}
+
+
+def periodic_decode(keys, d):
+    """Split periodic key entries ``i * 3^d + c(k)`` into node indices and
+    lattice shifts ``k`` in ``{-1,0,1}^d`` (``c(k) = sum_a (k_a + 1) 3^a``)."""
+    keys = np.asarray(keys, dtype=np.int64)
+    S = 3 ** d
+    ids = keys // S
+    c = keys % S
+    shift = np.stack([(c // 3 ** a) % 3 - 1 for a in range(d)], axis=-1).astype(np.int8)
+    return ids.astype(np.int32), shift
+
+
+def explore_periodic(nodes, draws):
+    """Exhaustive search (Algorithm 2) of the periodic diagram of nodes in
+    ``[0,1)^d`` (the torus R^d / Z^d).  A key entry is a node image
+    ``x_i + k``, coded ``i * 3^d + c(k)``; a vertex key is translated so that
+    its smallest node has ``k = 0`` and its coordinates are in that frame.
+    Needs every vertex ball radius below 1/2.  Returns a dict with ``key``
+    ``[V][d+1]`` (codes, sorted), ``sigma`` (node indices) and ``shift``
+    (``[V][d+1][d]``) decoded from it, ``coord`` ``[V][d]``, and the counters
+    ``raycasts``, ``duplicates``."""
+    lib = _load()
+    X = _f64(nodes)
+    n, d = X.shape
+    W = _f64(draws).reshape(-1, d)
+    st = ctypes.c_int(0)
+    h = lib.vgo_explore_periodic(d, n, _p(X), _p(W), W.shape[0], ctypes.byref(st))
+    if not h:
+        raise RuntimeError("oracle periodic explore failed: " + _PERIODIC_FAIL.get(st.value, str(st.value)))
+    try:
+        nv = lib.vgo_mesh_nv(h)
+        key = np.empty((nv, d + 1), dtype=np.int32)
+        coord = np.empty((nv, d))
+        lib.vgo_mesh_copy(h, _p(key), _p(coord), None, None)
+        sigma, shift = periodic_decode(key, d)
+        return dict(key=key, sigma=sigma, shift=shift, coord=coord, raycasts=int(lib.vgo_mesh_raycasts(h)),
                     duplicates=int(lib.vgo_mesh_duplicates(h)))
     finally:
         lib.vgo_mesh_free(h)

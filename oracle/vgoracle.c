@@ -26,6 +26,10 @@
  *                         cube: the faces of the cube join the generators
  *                         as constraints of a vertex (face x_k = s has the
  *                         code n + 2k + s in a key).
+ *   vgo_explore_periodic  Algorithm 2 on the periodic diagram (the torus
+ *                         R^d / Z^d): key entries are node images coded by
+ *                         node and lattice shift, rays are cast over the
+ *                         images in [-1,2)^d.
  *   vgo_mc_ray_weights    per-ray terms of the Monte-Carlo estimators of
  *                         Sec. 3.1 / Algorithm 3 (volume, area, and the
  *                         second moment used for the centroidal energy).
@@ -556,19 +560,20 @@ static int32_t cast(int d, int64_t n, const double *X, const int32_t *eta,
   return j;
 }
 
-/* Descent of Algorithm 2: from sigma = {0}, r = x_0, cast rays onto faces of
+/* Descent of Algorithm 2: from sigma = {start}, r = X[start] (node 0 for
+ * the unbounded diagram), cast rays onto faces of
  * decreasing dimension until d+1 generators are known.  Each step takes the
  * next Gaussian draw as the search direction, removes its component in the
  * span of X_sigma, and casts with eta = sigma; a step whose ray escapes is
  * retried with -u and then with the next draw. */
-static int descent(int d, int64_t n, const double *X, const double *draws,
-                   int n_draws, int mode, int32_t *sigma, double *v,
-                   vgo_mesh *M) {
+static int descent(int d, int64_t n, const double *X, int32_t start,
+                   const double *draws, int n_draws, int mode, int32_t *sigma,
+                   double *v, vgo_mesh *M) {
   int m = 1;
   int used = 0;
   double r[64], u[64];
-  sigma[0] = 0;
-  for (int k = 0; k < d; ++k) r[k] = X[k];
+  sigma[0] = start;
+  for (int k = 0; k < d; ++k) r[k] = X[(int64_t)start * d + k];
   while (m < d + 1) {
     if (used >= n_draws) return -1;
     for (int k = 0; k < d; ++k) u[k] = draws[used * d + k];
@@ -612,7 +617,7 @@ void *vgo_explore(int d, int64_t n, const double *X, const double *draws,
   int32_t s0[64], eta[64], key[64];
   double v0[64], u[64], v[64];
   int cr;
-  if (!ok || descent(d, n, X, draws, n_draws, mode, s0, v0, M)) goto fail;
+  if (!ok || descent(d, n, X, 0, draws, n_draws, mode, s0, v0, M)) goto fail;
   if (mesh_push_vertex(M, s0, v0)) goto fail;
   *tmap_slot(&V, s0, 1, &cr) = 0;
   for (int o = 0; o <= d; ++o) { /* E(sigma): omit one generator */
@@ -878,6 +883,190 @@ fail:
 /* Exposed for the tests. */
 int vgo_clipped_vertex(int d, int64_t n, const double *X, const int32_t *key, double *v) {
   return clipped_vertex(d, n, X, key, v);
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2c: Algorithm 2 on the periodic diagram (the flat torus R^d / Z^d).      */
+/*                                                                           */
+/* Every node x_i in [0,1)^d stands for all its images x_i + k, k in Z^d; a  */
+/* vertex is a point equidistant to d+1 images with no image closer.  A key  */
+/* entry is an image, coded i S + c(k) with S = 3^d and                      */
+/* c(k) = sum_a (k_a + 1) 3^a for k in {-1,0,1}^d.  The keys of one vertex   */
+/* differ by a lattice translation; the canonical one is translated so that  */
+/* the entry of the smallest node index has k = 0, and the vertex            */
+/* coordinates are solved in that frame.  An edge (d entries) is             */
+/* canonicalised the same way.  Requirement: every vertex's empty ball has   */
+/* radius below 1/2.  Then the images of one key belong to distinct nodes    */
+/* and their shifts relative to each other lie in {-1,0,1}^d, so keys stay   */
+/* in the code range; anything else is reported as a failure.                */
+/*                                                                           */
+/* Rays are cast by definition over the 3^d images of every node with        */
+/* k in {-1,0,1}^d, i.e. every image in [-1,2)^d.  A ray whose true first    */
+/* hit w is outside that set ends at a point y' whose ball (radius |y'-g|)   */
+/* holds w in its interior, so it leaves [-1,2]^d: each new vertex's ball is */
+/* checked to lie inside, in the frame of its ray, and a failed check (or a  */
+/* ray with no hit) fails the search.                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Translate the sorted key (L entries i S + c) so that its first entry has
+ * k = 0; returns -1 when a shift leaves {-1,0,1}^d or a node repeats. */
+static int periodic_canon(int d, int L, int32_t *key) {
+  int32_t S = 1;
+  for (int a = 0; a < d; ++a) S *= 3;
+  int32_t c0 = key[0] % S;
+  for (int e = 0; e < L; ++e) {
+    int32_t id = key[e] / S, c = key[e] % S, cn = 0, p = 1, r0 = c0, r = c;
+    for (int a = 0; a < d; ++a) {
+      int dig = (r % 3) - (r0 % 3) + 1; /* k_a - k0_a + 1 */
+      if (dig < 0 || dig > 2) return -1;
+      cn += dig * p;
+      p *= 3;
+      r /= 3;
+      r0 /= 3;
+    }
+    if (e > 0 && id == key[e - 1] / S) return -1;
+    key[e] = id * S + cn;
+  }
+  return 0;
+}
+
+/* Radius of the empty ball of the vertex v of key (images in Xi) and whether
+ * it lies strictly inside [-1,2]^d. */
+static int ball_inside(int d, const double *Xi, const int32_t *key, const double *v) {
+  double R = sqrt(dist2(v, Xi + (int64_t)key[0] * d, d));
+  for (int a = 0; a < d; ++a)
+    if (!(v[a] - R > -1.0 && v[a] + R < 2.0)) return 0;
+  return 1;
+}
+
+/* Algorithm 2 on the torus; *status is 0, or -1 (input out of range or
+ * allocation), -2 (a ball reaching past the image layer, or a ray without a
+ * hit), -3 (a key outside the code range: a ball of radius >= 1/2),
+ * -4 (singular vertex or failed Descent). */
+void *vgo_explore_periodic(int d, int64_t n, const double *X, const double *draws,
+                           int n_draws, int *status) {
+  *status = -1;
+  if (d < 1 || d > 12 || n < 1) return NULL;
+  int64_t S = 1;
+  for (int a = 0; a < d; ++a) S *= 3;
+  if (n * S >= ((int64_t)1 << 31)) return NULL;
+  for (int64_t i = 0; i < n * d; ++i)
+    if (!(X[i] >= 0.0 && X[i] < 1.0)) return NULL;
+  /* every image with k in {-1,0,1}^d, row i S + c(k) */
+  double *Xi = (double *)malloc(sizeof(double) * (size_t)(n * S * d));
+  vgo_mesh *M = (vgo_mesh *)calloc(1, sizeof(vgo_mesh));
+  tmap G, V;
+  memset(&G, 0, sizeof G);
+  memset(&V, 0, sizeof V);
+  if (!Xi || !M) goto fail;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t c = 0; c < S; ++c) {
+      int64_t r = c;
+      for (int a = 0; a < d; ++a) {
+        Xi[(i * S + c) * d + a] = X[i * d + a] + (double)(r % 3 - 1);
+        r /= 3;
+      }
+    }
+  M->d = d;
+  if (tmap_init(&G, d, 1 << 12) || tmap_init(&V, d + 1, 1 << 12)) goto fail;
+  {
+    int32_t s0[64], key[64], eta[64];
+    double v[64], u[64];
+    int cr;
+    const int32_t centre = (int32_t)((S - 1) / 2); /* c(0) */
+    *status = -4;
+    if (descent(d, n * S, Xi, centre, draws, n_draws, 0, s0, v, M)) goto fail;
+    *status = -2;
+    if (!ball_inside(d, Xi, s0, v)) goto fail;
+    *status = -3;
+    if (periodic_canon(d, d + 1, s0)) goto fail;
+    *status = -4;
+    if (circumcentre(d, Xi, s0, v)) goto fail;
+    *status = -1;
+    if (mesh_push_vertex(M, s0, v)) goto fail;
+    *tmap_slot(&V, s0, 1, &cr) = 0;
+    for (int o = 0; o <= d; ++o) {
+      int a = 0;
+      for (int b = 0; b <= d; ++b)
+        if (b != o) eta[a++] = s0[b];
+      *status = -3;
+      if (periodic_canon(d, d, eta)) goto fail;
+      *tmap_slot(&G, eta, 1, &cr) += 1;
+    }
+    for (int64_t head = 0; head < M->nv; ++head) {
+      int32_t sig[64];
+      double r[64];
+      memcpy(sig, M->sig + head * (d + 1), sizeof(int32_t) * (d + 1));
+      memcpy(r, M->coord + head * d, sizeof(double) * d);
+      for (int o = 0; o <= d; ++o) {
+        int a = 0;
+        for (int b = 0; b <= d; ++b)
+          if (b != o) eta[a++] = sig[b];
+        int32_t ec[64];
+        memcpy(ec, eta, sizeof(int32_t) * d);
+        *status = -3;
+        if (periodic_canon(d, d, ec)) goto fail;
+        int64_t *gc = tmap_slot(&G, ec, 0, &cr);
+        if (gc && *gc >= 2) continue;
+        if (search_direction(d, Xi, eta, sig[o], u)) continue;
+        double t, t2;
+        int32_t j;
+        M->raycasts++;
+        raycast_one(d, n * S, Xi, r, u, eta[0], eta, d, 0, &t, &j, &t2);
+        *status = -2;
+        if (j < 0) goto fail;
+        for (int b = 0; b < d; ++b) key[b] = eta[b];
+        key[d] = j;
+        sort_small(key, d + 1);
+        /* the ball of the new vertex, in the frame of its ray */
+        *status = -4;
+        if (circumcentre(d, Xi, key, v)) goto fail;
+        *status = -2;
+        if (!ball_inside(d, Xi, key, v)) goto fail;
+        *status = -3;
+        if (periodic_canon(d, d + 1, key)) goto fail;
+        int64_t *vs = tmap_slot(&V, key, 1, &cr);
+        *status = -1;
+        if (!vs) goto fail;
+        if (!cr) {
+          M->duplicates++;
+          continue;
+        }
+        *vs = M->nv;
+        *status = -4;
+        if (circumcentre(d, Xi, key, v)) goto fail;
+        *status = -1;
+        if (mesh_push_vertex(M, key, v)) goto fail;
+        for (int o2 = 0; o2 <= d; ++o2) {
+          int a2 = 0;
+          int32_t e2[64];
+          for (int b = 0; b <= d; ++b)
+            if (b != o2) e2[a2++] = key[b];
+          *status = -3;
+          if (periodic_canon(d, d, e2)) goto fail;
+          int64_t *g2 = tmap_slot(&G, e2, 1, &cr);
+          *status = -1;
+          if (!g2) goto fail;
+          *g2 += 1;
+        }
+      }
+    }
+  }
+  *status = 0;
+  tmap_free(&G);
+  tmap_free(&V);
+  free(Xi);
+  return M;
+fail:
+  tmap_free(&G);
+  tmap_free(&V);
+  free(Xi);
+  if (M) {
+    free(M->sig);
+    free(M->coord);
+    free(M);
+  }
+  return NULL;
 }
 
 /* The star of generator i: every vertex of the unbounded diagram whose
