@@ -59,6 +59,7 @@ typedef enum vg_status {
                                     with a grid index (d <= 6)                  */
 #define VG_INIT_HEURISTIC (1u << 4) /* with VG_INCIRCLE on general rays: start
                                     from InitialHeuristic (|eta| >= 2)         */
+#define VG_PERIODIC (1u << 5)    /* vg_explore: the periodic diagram (torus)    */
 
 /* per-ray status bits (uint8) */
 #define VG_ST_NEAR_TIE 1  /* FP32 gap of the two best candidates below VG_TIE_EPS */
@@ -351,6 +352,18 @@ int vg_hmc_integrals(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, in
  * VG_INCIRCLE (d <= 6), optionally with VG_INIT_HEURISTIC, casts the edge
  * rays by Algorithm 1 (as vg_raycast); vg_mesh_num_nn_calls then counts its
  * nearest-neighbour queries (the measure of Table nncalls).
+ * VG_PERIODIC (d <= 8; excludes VG_CLIP and VG_INCIRCLE) searches the
+ * periodic diagram, the torus R^d / Z^d of the periodic boundary conditions
+ * behind Table empscaling, for nodes in [0,1)^d (VG_EINVAL otherwise).  A
+ * key entry is a node image x_i + k, coded i*3^d + sum_a (k_a + 1) 3^a with
+ * k in {-1,0,1}^d; each key is sorted and translated by a lattice vector so
+ * that its first node has k = 0, and coords are solved in that frame from
+ * the exact images.  Rays run over the images inside [-w, 1+w]^d (FP32
+ * rows; the FP64 recheck reads the exact images), and every new vertex's
+ * ball is checked to lie inside that layer; otherwise the search restarts
+ * with w doubled, up to w = 1.  Needs n_nodes * 3^d < 2^31 - 1 and every
+ * vertex ball radius below 1/2 (VG_EUNSUPPORTED otherwise, e.g. for a
+ * handful of nodes).  There are no unbounded edges.
  * Synchronises the stream.  The result is library-owned: query it, copy it
  * out, free it. */
 int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,

@@ -36,6 +36,7 @@ VG_PREC_BF16X3 = 1 << 1
 VG_NO_RECHECK = 1 << 2
 VG_INCIRCLE = 1 << 3
 VG_INIT_HEURISTIC = 1 << 4
+VG_PERIODIC = 1 << 5
 
 ST_NEAR_TIE = 1
 ST_RECHECKED = 2
@@ -563,7 +564,7 @@ def raycast_batched(problems, clip=True, out=None):
     return outs
 
 
-def explore(nodes, descent_draws=None, clip=False, incircle=False, heuristic=False) -> dict:
+def explore(nodes, descent_draws=None, clip=False, incircle=False, heuristic=False, periodic=False) -> dict:
     """Exhaustive search (Algorithm 2) of the unbounded diagram, or with
     ``clip=True`` of the diagram clipped to the unit cube (keys then hold
     ``n + 2k + s`` for the face ``x_k = s``; no draws needed).  With
@@ -571,7 +572,15 @@ def explore(nodes, descent_draws=None, clip=False, incircle=False, heuristic=Fal
     grid index (``heuristic``: from InitialHeuristic's point) and
     ``nn_calls`` counts its queries.  Returns host arrays ``sigma [V, d+1]``,
     ``coord [V, d]`` (float64), ``b_sigma``, ``b_omit``, ``raycasts`` and
-    ``nn_calls``."""
+    ``nn_calls``.
+
+    ``periodic=True`` (d <= 8, nodes in [0,1)^d) searches the periodic
+    diagram (the torus R^d / Z^d): key entries are node images
+    ``x_i + k`` coded ``i * 3^d + c(k)`` with ``c(k) = sum_a (k_a+1) 3^a``,
+    each key translated so that its first (smallest) node has ``k = 0`` and
+    ``coord`` in that frame.  The result then also holds ``key`` (the codes)
+    with ``sigma`` the node indices and ``shift [V, d+1, d]`` int8 the
+    ``k`` decoded from it."""
     _dev(nodes, torch.float32, "nodes")
     n, d = nodes.shape
     if descent_draws is None:
@@ -583,7 +592,8 @@ def explore(nodes, descent_draws=None, clip=False, incircle=False, heuristic=Fal
     _check(_lib.vg_explore(c, d, n, _ptr(nodes), draws.ctypes.data_as(ctypes.c_void_p) if draws.size else None,
                            draws.shape[0],
                            (VG_CLIP if clip else 0) | (VG_INCIRCLE if incircle else 0) |
-                           (VG_INIT_HEURISTIC if heuristic else 0), ctypes.byref(mesh)), c, "vg_explore")
+                           (VG_INIT_HEURISTIC if heuristic else 0) | (VG_PERIODIC if periodic else 0),
+                           ctypes.byref(mesh)), c, "vg_explore")
     try:
         nv = _lib.vg_mesh_num_vertices(mesh)
         nb = _lib.vg_mesh_num_unbounded(mesh)
@@ -593,8 +603,15 @@ def explore(nodes, descent_draws=None, clip=False, incircle=False, heuristic=Fal
         bomit = np.empty(nb, dtype=np.int32)
         P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         _check(_lib.vg_mesh_copy(mesh, P(sig), P(coord), P(bsig), P(bomit)), c, "vg_mesh_copy")
-        return dict(sigma=sig, coord=coord, b_sigma=bsig, b_omit=bomit,
-                    raycasts=int(_lib.vg_mesh_num_raycasts(mesh)),
-                    nn_calls=int(_lib.vg_mesh_num_nn_calls(mesh)))
+        out = dict(sigma=sig, coord=coord, b_sigma=bsig, b_omit=bomit,
+                   raycasts=int(_lib.vg_mesh_num_raycasts(mesh)),
+                   nn_calls=int(_lib.vg_mesh_num_nn_calls(mesh)))
+        if periodic:
+            S = 3 ** d
+            key = sig.astype(np.int64)
+            out["key"] = sig
+            out["sigma"] = (key // S).astype(np.int32)
+            out["shift"] = np.stack([(key % S) // 3 ** a % 3 - 1 for a in range(d)], axis=-1).astype(np.int8)
+        return out
     finally:
         _lib.vg_mesh_free(mesh)

@@ -180,8 +180,9 @@ namespace vg {
 int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, const double *o64,
                 const double *u64, const int32_t *gen, const int32_t *excl, int n_excl, int clip,
                 bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64,
-                int incircle) {
+                int incircle, const double *nodes64, float node_err) {
   if (m <= 0) return VG_OK;
+  if (nodes64 && incircle) return fail(ctx, VG_EUNSUPPORTED, "exact FP64 rows need the dense scan");
   const size_t grid_bytes = incircle ? incircle_rays_scratch_bytes(n, d) : 0;
   size_t need = Carver::need({(size_t)m * 8, grid_bytes});
   int rc = ensure_scratch(ctx, need);
@@ -209,6 +210,7 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   a.flag_list = flag_list;
   a.tau = kTauRays;
   a.force_all = force_all ? 1 : 0;
+  a.node_err = nodes64 ? node_err : 0.f;
   ScanTimer timer(ctx);
   hipError_t e =
       incircle ? launch_incircle_rays(a, grid_scratch, incircle == 2,
@@ -235,6 +237,7 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   r.st_out = st_out;
   r.tie_counter = ctx->counters + CNT_FP64_TIE;
   r.t64_out = t64;
+  r.nodes64 = nodes64;
   e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
   ctx->last_rays = m;

@@ -24,6 +24,7 @@
 // its nearest generator, instead of at a Descent.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -101,57 +102,40 @@ struct Explorer {
   }
 };
 
-}  // namespace
+// What one search runs over.  Rays are cast over `scan` (n_scan rows): the
+// nodes, or on the periodic diagram the images of the scanned layer.
+struct Setup {
+  int d = 0;
+  int64_t n_nodes = 0;
+  const float *nodes = nullptr;
+  int64_t n_scan = 0;
+  const float *scan = nullptr;
+  const double *scan64 = nullptr;  // periodic: the exact images the rows were rounded from
+  float node_err = 0.f;            // periodic: bound on |row - image|
+  const double *draws = nullptr;
+  int n_draws = 0;
+  bool clipped = false;
+  int incircle = 0;
+  Periodic per;
+  const std::vector<int32_t> *tkey_h = nullptr;  // periodic: code of each scanned image
+  const std::vector<float> *xh = nullptr;        // periodic: the nodes, host copy
+};
 
-extern "C" {
-
-int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const double *draws,
-               int n_draws, uint32_t flags, vg_mesh **out) {
-  if (!ctx) return VG_EINVAL;
-  const bool clipped = (flags & VG_CLIP) != 0;
-  const int incircle = (flags & VG_INCIRCLE) ? ((flags & VG_INIT_HEURISTIC) ? 2 : 1) : 0;
-  ctx->err.clear();
-  if (!out) {
-    ctx->err = "out is NULL";
-    return VG_EINVAL;
-  }
-  *out = nullptr;
-  if (d < 2 || d > VG_MAX_DIM) {
-    ctx->err = "d outside [2, VG_MAX_DIM]";
-    return VG_EUNSUPPORTED;
-  }
-  if (flags & ~(uint32_t)(VG_CLIP | VG_INCIRCLE | VG_INIT_HEURISTIC)) {
-    ctx->err = "explore takes VG_CLIP, VG_INCIRCLE and VG_INIT_HEURISTIC only";
-    return VG_EINVAL;
-  }
-  if ((flags & VG_INIT_HEURISTIC) && !incircle) {
-    ctx->err = "VG_INIT_HEURISTIC needs VG_INCIRCLE";
-    return VG_EINVAL;
-  }
-  if (incircle && d > 6) {
-    ctx->err = "VG_INCIRCLE needs d <= 6";
-    return VG_EUNSUPPORTED;
-  }
-  if (clipped ? (n_nodes < 1 || !nodes)
-              : (n_nodes < d + 1 || !nodes || !draws || n_draws < 1)) {
-    ctx->err = clipped ? "clipped explore needs n_nodes >= 1 and nodes"
-                       : "explore needs n_nodes >= d+1, nodes and descent draws";
-    return VG_EINVAL;
-  }
-  if (n_nodes >= (int64_t(1) << 31) - 2 * VG_MAX_DIM) {
-    ctx->err = "n_nodes too large for int32 keys";
-    return VG_EINVAL;
-  }
-  if (hipSetDevice(ctx->device) != hipSuccess) {
-    ctx->err = "hipSetDevice failed";
-    return VG_EDEVICE;
-  }
-  vg_mesh *M = new (std::nothrow) vg_mesh();
-  if (!M) return VG_ENOMEM;
-  M->d = d;
-  Explorer X{ctx, d, n_nodes, nodes, ctx->stream, {}};
+// One search into M.  thin is set when a periodic search met a vertex ball
+// past its image layer (or a key outside the shift range).
+int explore_run(vg_ctx *ctx, const Setup &su, vg_mesh *M, bool &thin) {
+  const int d = su.d;
+  const int64_t n_nodes = su.n_nodes;
+  const float *nodes = su.nodes;
+  const bool clipped = su.clipped;
+  const int incircle = su.incircle;
+  const bool periodic = su.per.S > 0;
+  const double *draws = su.draws;
+  const int n_draws = su.n_draws;
+  Explorer X{ctx, d, su.n_scan, su.scan, ctx->stream, {}};
   const int L = d + 1;
   int rc = VG_OK;
+  thin = false;
 
 #define EX_HIP(call)                        \
   do {                                      \
@@ -198,7 +182,7 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     EX_HIP(v_d.reserve(sizeof(double) * d, false, X.s));
     {
       std::vector<float> x0(d);
-      EX_HIP(hipMemcpyAsync(x0.data(), nodes, sizeof(float) * d, hipMemcpyDeviceToHost, X.s));
+      EX_HIP(hipMemcpyAsync(x0.data(), su.scan, sizeof(float) * d, hipMemcpyDeviceToHost, X.s));
       EX_HIP(hipStreamSynchronize(X.s));
       std::vector<double> r0(x0.begin(), x0.end());
       EX_HIP(hipMemcpyAsync(r_d.p, r0.data(), sizeof(double) * d, hipMemcpyHostToDevice, X.s));
@@ -217,7 +201,7 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       const int m = (int)sig.size();
       // the first generator stays first (it is g of eq. (t)); excl is sorted
       EX_HIP(hipMemcpyAsync(sig_d.p, sig.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, X.s));
-      EX_HIP(launch_descent_project(nodes, d, sig_d.as<int32_t>(), m, u_d.as<double>(),
+      EX_HIP(launch_descent_project(su.scan, d, sig_d.as<int32_t>(), m, u_d.as<double>(),
                                     ok_d.as<int>(), X.s));
       int okh = 0;
       EX_HIP(hipMemcpyAsync(&okh, ok_d.p, sizeof(int), hipMemcpyDeviceToHost, X.s));
@@ -241,9 +225,10 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
           EX_HIP(hipMemcpyAsync(u_d.p, uh.data(), sizeof(double) * d, hipMemcpyHostToDevice, X.s));
           EX_HIP(hipStreamSynchronize(X.s));
         }
-        EX_RC(raycast_f64(ctx, d, n_nodes, nodes, 1, r_d.as<double>(), u_d.as<double>(),
+        EX_RC(raycast_f64(ctx, d, su.n_scan, su.scan, 1, r_d.as<double>(), u_d.as<double>(),
                           g_d.as<int32_t>(), ex_d.as<int32_t>(), m, 0, true, t32_d.as<float>(),
-                          i_d.as<int32_t>(), st_d.as<uint8_t>(), t64_d.as<double>(), incircle));
+                          i_d.as<int32_t>(), st_d.as<uint8_t>(), t64_d.as<double>(), incircle, su.scan64,
+                          su.node_err));
         M->raycasts++;
         uint64_t calls = 0;
         EX_HIP(hipMemcpyAsync(&j, i_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, X.s));
@@ -255,11 +240,39 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       EX_HIP(launch_advance(r_d.as<double>(), u_d.as<double>(), t64_d.as<double>(), d, sign, X.s));
       sig.push_back(j);
     }
-    std::sort(sig.begin(), sig.end());
-    EX_HIP(hipMemcpyAsync(sig_d.p, sig.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, X.s));
-    EX_HIP(launch_solve_one(nodes, d, sig_d.as<int32_t>(), v_d.as<double>(), ok_d.as<int>(), X.s));
     std::vector<double> v0(d);
     int okh = 0;
+    // periodic: rows -> image codes; the ball in the frame of the Descent
+    // must lie inside the layer, then the key takes its normal form
+    if (periodic)
+      for (auto &e : sig) e = (*su.tkey_h)[(size_t)e];
+    std::sort(sig.begin(), sig.end());
+    if (periodic) {
+      EX_HIP(hipMemcpyAsync(sig_d.p, sig.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, X.s));
+      EX_HIP(launch_solve_one(su.scan, d, sig_d.as<int32_t>(), su.per, v_d.as<double>(), ok_d.as<int>(), X.s));
+      EX_HIP(hipMemcpyAsync(v0.data(), v_d.p, sizeof(double) * d, hipMemcpyDeviceToHost, X.s));
+      EX_HIP(hipMemcpyAsync(&okh, ok_d.p, sizeof(int), hipMemcpyDeviceToHost, X.s));
+      EX_HIP(hipStreamSynchronize(X.s));
+      if (okh) {
+        const int32_t i0 = sig[0] / su.per.S, c0 = sig[0] % su.per.S;
+        double r2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          const double e = v0[k] - ((double)(*su.xh)[(size_t)i0 * d + k] + (double)(code_digit(c0, k) - 1));
+          r2 += e * e;
+        }
+        const double R = std::sqrt(r2);
+        for (int k = 0; k < d; ++k)
+          if (!(v0[k] - R > -su.per.w && v0[k] + R < 1.0 + su.per.w)) thin = true;
+        if (!periodic_canon(sig.data(), L, d, su.per.S)) thin = true;
+        if (thin) {
+          ctx->err = "periodic start vertex outside the image layer";
+          rc = VG_EUNSUPPORTED;
+          goto fail;
+        }
+      }
+    }
+    EX_HIP(hipMemcpyAsync(sig_d.p, sig.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, X.s));
+    EX_HIP(launch_solve_one(su.scan, d, sig_d.as<int32_t>(), su.per, v_d.as<double>(), ok_d.as<int>(), X.s));
     EX_HIP(hipMemcpyAsync(v0.data(), v_d.p, sizeof(double) * d, hipMemcpyDeviceToHost, X.s));
     EX_HIP(hipMemcpyAsync(&okh, ok_d.p, sizeof(int), hipMemcpyDeviceToHost, X.s));
     EX_HIP(hipStreamSynchronize(X.s));
@@ -292,7 +305,9 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     auto vset = [&]() {
       return VSet{X.vfp.as<uint64_t>(), X.vowner.as<int64_t>(), X.vkey.as<int32_t>(), vcap, L};
     };
-    auto eset = [&]() { return ESet{X.efp.as<uint64_t>(), X.ecnt.as<uint32_t>(), X.ekey.as<int32_t>(), ecap}; };
+    auto eset = [&]() {
+      return ESet{X.efp.as<uint64_t>(), X.ecnt.as<uint32_t>(), X.ekey.as<int32_t>(), ecap, su.per.S};
+    };
     auto grow_v = [&](int64_t need) -> hipError_t {
       if (2 * need <= vcap) return hipSuccess;
       int64_t c = int64_t(1) << 16;
@@ -348,13 +363,19 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
         ctx->err = "explore: a device table ran full";
         return VG_EDEVICE;
       }
+      if (eh & (VSET_THIN | VSET_RANGE)) {
+        thin = true;
+        ctx->err = (eh & VSET_RANGE) ? "periodic key outside the shift range (a vertex ball of radius >= 1/2)"
+                                     : "periodic vertex ball past the image layer";
+        return VG_EUNSUPPORTED;
+      }
       return VG_OK;
     };
     EX_HIP(grow_v(1));
     EX_HIP(grow_e((int64_t)L));
     int64_t level_begin = 0, level_end = 1;
     const bool verbose = std::getenv("VG_VERBOSE") != nullptr;
-    const bool validate = std::getenv("VG_VALIDATE") != nullptr;
+    const bool validate = std::getenv("VG_VALIDATE") != nullptr && !periodic;
     const auto t_start = std::chrono::steady_clock::now();
     int level = 0;
     while (level_begin < level_end) {
@@ -389,7 +410,7 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       EX_HIP(frontier_items(X.sel.as<int64_t>(), m, lb, d, X.item_v.as<int64_t>(), X.item_o.as<int32_t>(),
                             X.s));
       ExploreRays er{};
-      er.nodes = nodes;
+      er.nodes = su.scan;
       er.d = d;
       er.m = m;
       er.keys = X.keys_d.as<int32_t>();
@@ -404,11 +425,14 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       er.idx = X.idx.as<int32_t>();
       er.new_keys = X.nkeys.as<int32_t>();
       er.new_coords = X.ncoords.as<double>();
-      er.n_nodes = n_nodes;
+      er.n_nodes = su.n_scan;
       er.face_base = face_base;
+      er.per = su.per;
+      er.err = errd;
       EX_HIP(launch_edge_rays(er, X.s));
-      EX_RC(raycast_f64(ctx, d, n_nodes, nodes, m, er.o64, er.u64, er.gen, er.excl, d, clipped ? 1 : 0, false,
-                        X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr, incircle));
+      EX_RC(raycast_f64(ctx, d, su.n_scan, su.scan, m, er.o64, er.u64, er.gen, er.excl, d, clipped ? 1 : 0, false,
+                        X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr, incircle, su.scan64,
+                        su.node_err));
       M->raycasts += m;
       if (incircle) {
         uint64_t calls = 0;
@@ -485,17 +509,203 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     }
     EX_HIP(hipStreamSynchronize(X.s));
   }
-  *out = M;
   return VG_OK;
 
 device:
   ctx->err = X.err;
   rc = VG_EDEVICE;
 fail:
-  delete M;
   return rc;
 #undef EX_HIP
 #undef EX_RC
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const double *draws,
+               int n_draws, uint32_t flags, vg_mesh **out) {
+  if (!ctx) return VG_EINVAL;
+  const bool clipped = (flags & VG_CLIP) != 0;
+  const bool periodic = (flags & VG_PERIODIC) != 0;
+  const int incircle = (flags & VG_INCIRCLE) ? ((flags & VG_INIT_HEURISTIC) ? 2 : 1) : 0;
+  ctx->err.clear();
+  if (!out) {
+    ctx->err = "out is NULL";
+    return VG_EINVAL;
+  }
+  *out = nullptr;
+  if (d < 2 || d > VG_MAX_DIM) {
+    ctx->err = "d outside [2, VG_MAX_DIM]";
+    return VG_EUNSUPPORTED;
+  }
+  if (flags & ~(uint32_t)(VG_CLIP | VG_INCIRCLE | VG_INIT_HEURISTIC | VG_PERIODIC)) {
+    ctx->err = "explore takes VG_CLIP, VG_PERIODIC, VG_INCIRCLE and VG_INIT_HEURISTIC only";
+    return VG_EINVAL;
+  }
+  if (periodic && (clipped || incircle)) {
+    ctx->err = "VG_PERIODIC excludes VG_CLIP and VG_INCIRCLE";
+    return VG_EUNSUPPORTED;
+  }
+  if ((flags & VG_INIT_HEURISTIC) && !incircle) {
+    ctx->err = "VG_INIT_HEURISTIC needs VG_INCIRCLE";
+    return VG_EINVAL;
+  }
+  if (incircle && d > 6) {
+    ctx->err = "VG_INCIRCLE needs d <= 6";
+    return VG_EUNSUPPORTED;
+  }
+  if (clipped ? (n_nodes < 1 || !nodes)
+              : ((periodic ? n_nodes < 1 : n_nodes < d + 1) || !nodes || !draws || n_draws < 1)) {
+    ctx->err = clipped    ? "clipped explore needs n_nodes >= 1 and nodes"
+               : periodic ? "periodic explore needs n_nodes >= 1, nodes and descent draws"
+                          : "explore needs n_nodes >= d+1, nodes and descent draws";
+    return VG_EINVAL;
+  }
+  if (n_nodes >= (int64_t(1) << 31) - 2 * VG_MAX_DIM) {
+    ctx->err = "n_nodes too large for int32 keys";
+    return VG_EINVAL;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    ctx->err = "hipSetDevice failed";
+    return VG_EDEVICE;
+  }
+  Setup su;
+  su.d = d;
+  su.n_nodes = n_nodes;
+  su.nodes = nodes;
+  su.n_scan = n_nodes;
+  su.scan = nodes;
+  su.draws = draws;
+  su.n_draws = n_draws;
+  su.clipped = clipped;
+  su.incircle = incircle;
+  if (!periodic) {
+    vg_mesh *M = new (std::nothrow) vg_mesh();
+    if (!M) return VG_ENOMEM;
+    M->d = d;
+    bool thin = false;
+    const int rc = explore_run(ctx, su, M, thin);
+    if (rc != VG_OK) {
+      delete M;
+      return rc;
+    }
+    *out = M;
+    return VG_OK;
+  }
+  // ---------------------------------------------------------- periodic
+  // The images x_i + k (k in {-1,0,1}^d) inside [-w, 1+w]^d are scanned;
+  // a vertex ball reaching past them (found by the ball check) restarts the
+  // search with w doubled, up to w = 1 (every image in [-1,2]^d).
+  if (d > 8) {
+    ctx->err = "VG_PERIODIC needs d <= 8";
+    return VG_EUNSUPPORTED;
+  }
+  int32_t S = 1;
+  for (int a = 0; a < d; ++a) S *= 3;
+  if (n_nodes * S >= (int64_t)INT32_MAX) {
+    ctx->err = "periodic explore needs n_nodes * 3^d < 2^31 - 1";
+    return VG_EUNSUPPORTED;
+  }
+  std::vector<float> xh((size_t)n_nodes * d);
+  if (hipMemcpyAsync(xh.data(), nodes, sizeof(float) * xh.size(), hipMemcpyDeviceToHost, ctx->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    ctx->err = "copying the nodes failed";
+    return VG_EDEVICE;
+  }
+  for (float x : xh)
+    if (!(x >= 0.f && x < 1.f)) {
+      ctx->err = "periodic explore needs nodes in [0,1)^d";
+      return VG_EINVAL;
+    }
+  const int32_t centre = (S - 1) / 2;
+  double w = std::min(1.0, 3.0 * std::pow((double)n_nodes, -1.0 / d));
+  for (;;) {
+    std::vector<float> rows;
+    std::vector<double> rows64;
+    std::vector<int32_t> tkey, tix((size_t)n_nodes * S, -1);
+    rows.reserve(xh.size());
+    rows64.reserve(xh.size());
+    auto add = [&](int64_t i, int32_t c) {
+      for (int k = 0; k < d; ++k) {
+        const double y = (double)xh[(size_t)i * d + k] + (double)(code_digit(c, k) - 1);
+        if (!(y >= -w && y <= 1.0 + w)) return;
+      }
+      tix[(size_t)i * S + c] = (int32_t)tkey.size();
+      tkey.push_back((int32_t)(i * S + c));
+      for (int k = 0; k < d; ++k) {
+        const double y = (double)xh[(size_t)i * d + k] + (double)(code_digit(c, k) - 1);
+        rows64.push_back(y);
+        rows.push_back((float)y);
+      }
+    };
+    for (int64_t i = 0; i < n_nodes; ++i) add(i, centre);  // image i is node i
+    for (int32_t c = 0; c < S; ++c)
+      if (c != centre)
+        for (int64_t i = 0; i < n_nodes; ++i) add(i, c);
+    void *scan_d = nullptr, *scan64_d = nullptr, *tkey_d = nullptr, *tix_d = nullptr;
+    auto release = [&]() {
+      for (void *p : {scan_d, scan64_d, tkey_d, tix_d})
+        if (p) (void)hipFree(p);
+    };
+    if (hipMalloc(&scan_d, sizeof(float) * rows.size()) != hipSuccess ||
+        hipMalloc(&scan64_d, sizeof(double) * rows64.size()) != hipSuccess ||
+        hipMalloc(&tkey_d, sizeof(int32_t) * tkey.size()) != hipSuccess ||
+        hipMalloc(&tix_d, sizeof(int32_t) * tix.size()) != hipSuccess) {
+      release();
+      ctx->err = "periodic image layer allocation failed";
+      return VG_ENOMEM;
+    }
+    if (hipMemcpyAsync(scan_d, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(scan64_d, rows64.data(), sizeof(double) * rows64.size(), hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(tkey_d, tkey.data(), sizeof(int32_t) * tkey.size(), hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(tix_d, tix.data(), sizeof(int32_t) * tix.size(), hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      release();
+      ctx->err = "periodic image layer upload failed";
+      return VG_EDEVICE;
+    }
+    su.n_scan = (int64_t)tkey.size();
+    su.scan = static_cast<const float *>(scan_d);
+    su.scan64 = static_cast<const double *>(scan64_d);
+    // |fl(y) - y| <= 2^-24 |y| per coordinate, |y| <= 1 + w
+    su.node_err = 0x1p-24f * std::sqrt((float)d) * (float)(1.0 + w) * 1.01f;
+    su.per.S = S;
+    su.per.X = nodes;
+    su.per.tkey = static_cast<const int32_t *>(tkey_d);
+    su.per.tix = static_cast<const int32_t *>(tix_d);
+    su.per.n_codes = n_nodes * S;
+    su.per.w = w;
+    su.tkey_h = &tkey;
+    su.xh = &xh;
+    vg_mesh *M = new (std::nothrow) vg_mesh();
+    if (!M) {
+      release();
+      return VG_ENOMEM;
+    }
+    M->d = d;
+    bool thin = false;
+    const int rc = explore_run(ctx, su, M, thin);
+    release();
+    if (rc == VG_OK) {
+      *out = M;
+      return VG_OK;
+    }
+    delete M;
+    if (!thin) return rc;
+    if (w >= 1.0) {
+      ctx->err = "periodic explore needs every vertex ball radius below 1/2";
+      return VG_EUNSUPPORTED;
+    }
+    w = std::min(1.0, 2.0 * w);
+  }
 }
 
 int64_t vg_mesh_num_vertices(const vg_mesh *m) { return m ? (int64_t)m->sig.size() / (m->d + 1) : -1; }

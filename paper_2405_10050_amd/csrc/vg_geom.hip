@@ -13,23 +13,38 @@
 //     direction point into the cube (w = -+e_k in place of x_omit - x_eta0),
 //     and a face of the vertex adds the row y_k = s - x_a,k to the solve;
 //   * the Descent projection (Algorithm 2): a random direction with its
-//     component in the span of X_sigma removed.
+//     component in the span of X_sigma removed;
+//   * on the periodic diagram, key entries are images x_i + k (codes
+//     i S + c(k)) taken exactly in FP64; rays run over the scanned images,
+//     each new vertex's ball is checked to lie inside the scanned layer, and
+//     its key is translated to the normal form (first entry k = 0) before
+//     its coordinates are solved, so they depend on the vertex alone.
 #include "vg_internal.h"
 #include "vg_explore.h"
 
 namespace vg {
 namespace {
 
+// The points of a key: node rows, or exact images of the periodic diagram.
+struct NodePts {
+  const float *X;
+  int d;
+  __device__ double operator()(int32_t e, int k) const { return (double)X[(int64_t)e * d + k]; }
+};
+struct ImagePts {
+  Periodic P;
+  int d;
+  __device__ double operator()(int32_t e, int k) const { return image_coord(P, d, e, k); }
+};
+
 // Removes from w its components along span{e_k : faces among s} U
 // {X[s_j] - X[s_0] : generators s_j, j > 0} (s_0 a generator; faces are
 // the entries >= face_base), by Gram-Schmidt applied twice, faces first.
-template <int DK>
-__device__ void orth_complement(const float *__restrict__ X, int d, const int32_t *s, int m,
-                                int32_t face_base, double *w) {
+template <int DK, typename PT>
+__device__ void orth_complement(const PT &pt, int d, const int32_t *s, int m, int32_t face_base, double *w) {
   // Q holds up to m-1 orthonormal vectors of the span
   double Q[DK - 1 > 0 ? DK - 1 : 1][DK];
   int q = 0;
-  const float *x0 = X + (int64_t)s[0] * d;
   for (int j = 1; j < m; ++j) {
     if (s[j] < face_base) continue;
     // a face normal is orthogonal to the other faces' (distinct axes)
@@ -40,10 +55,9 @@ __device__ void orth_complement(const float *__restrict__ X, int d, const int32_
   }
   for (int j = 1; j < m; ++j) {
     if (s[j] >= face_base) continue;
-    const float *xj = X + (int64_t)s[j] * d;
     double e[DK];
 #pragma unroll
-    for (int k = 0; k < DK; ++k) e[k] = (k < d) ? (double)xj[k] - (double)x0[k] : 0.0;
+    for (int k = 0; k < DK; ++k) e[k] = (k < d) ? pt(s[j], k) - pt(s[0], k) : 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       for (int a = 0; a < q; ++a) {
         double c = 0.0;
@@ -73,11 +87,9 @@ __device__ void orth_complement(const float *__restrict__ X, int d, const int32_
   }
 }
 
-template <int DK>
-__device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *s, int32_t face_base,
-                             double *v) {
+template <int DK, typename PT>
+__device__ bool solve_vertex(const PT &pt, int d, const int32_t *s, int32_t face_base, double *v) {
   double A[DK][DK], b[DK], y[DK];
-  const float *xa = X + (int64_t)s[0] * d;
   for (int r = 0; r < DK; ++r) {
     b[r] = 0.0;
     for (int k = 0; k < DK; ++k) A[r][k] = 0.0;
@@ -86,13 +98,12 @@ __device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *
     if (s[r + 1] >= face_base) {  // face x_k = side: y_k = side - x_a,k
       const int f = s[r + 1] - face_base;
       A[r][f / 2] = 1.0;
-      b[r] = (double)(f % 2) - (double)xa[f / 2];
+      b[r] = (double)(f % 2) - pt(s[0], f / 2);
       continue;
     }
-    const float *xb = X + (int64_t)s[r + 1] * d;
     double acc = 0.0;
     for (int k = 0; k < d; ++k) {
-      const double e = (double)xb[k] - (double)xa[k];
+      const double e = pt(s[r + 1], k) - pt(s[0], k);
       A[r][k] = 2.0 * e;
       acc += e * e;
     }
@@ -128,10 +139,124 @@ __device__ bool solve_vertex(const float *__restrict__ X, int d, const int32_t *
     for (int k = c + 1; k < d; ++k) acc -= A[c][k] * y[k];
     y[c] = acc / A[c][c];
   }
-  for (int k = 0; k < d; ++k) v[k] = (double)xa[k] + y[k];
+  for (int k = 0; k < d; ++k) v[k] = pt(s[0], k) + y[k];
   for (int r = 1; r <= d; ++r)  // a vertex on a face lies on it exactly
     if (s[r] >= face_base) v[(s[r] - face_base) / 2] = (double)((s[r] - face_base) % 2);
   return true;
+}
+
+// Edge ray of a periodic item: the direction from the exact images; g and
+// the exclusions are the kept images' rows in the scanned layer (sorted),
+// and a kept image outside it marks the layer too thin.
+template <int DK>
+__device__ void edge_ray_periodic(const ExploreRays &a, int64_t it) {
+  const int d = a.d;
+  const int64_t v = a.item_v[it];
+  const int o = a.item_o[it];
+  const int32_t *sig = a.keys + v * (d + 1);
+  int32_t eta[DK];
+  int q = 0;
+  for (int b = 0; b <= d; ++b)
+    if (b != o) eta[q++] = sig[b];
+  const ImagePts pt{a.per, d};
+  double w[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) w[k] = (k < d) ? pt(sig[o], k) - pt(eta[0], k) : 0.0;
+  orth_complement<DK>(pt, d, eta, d, INT32_MAX, w);
+  double nr = 0.0;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) nr += w[k] * w[k];
+  nr = sqrt(nr);
+  int32_t ex[DK];
+  bool inside = true;
+  for (int b = 0; b < d; ++b) {
+    const int32_t e = eta[b];
+    const int32_t r = (e >= 0 && (int64_t)e < a.per.n_codes) ? a.per.tix[e] : -1;
+    inside = inside && r >= 0;
+    ex[b] = r >= 0 ? r : INT32_MAX;
+  }
+  if (!inside) atomicOr(a.err, VSET_THIN);
+  const bool good = nr > 0.0 && inside;
+  a.gen[it] = inside ? ex[0] : 0;
+  for (int b = 1; b < d; ++b) {  // insertion sort of the exclusions
+    const int32_t x = ex[b];
+    int c = b - 1;
+    while (c >= 0 && ex[c] > x) {
+      ex[c + 1] = ex[c];
+      --c;
+    }
+    ex[c + 1] = x;
+  }
+  for (int b = 0; b < d; ++b) a.excl[it * d + b] = ex[b];
+  for (int k = 0; k < d; ++k) {
+    a.u64[it * d + k] = good ? -w[k] / nr : 0.0;
+    a.o64[it * d + k] = a.coords[v * d + k];
+  }
+  a.ok[it] = good ? 1 : 0;
+}
+
+// New vertex of a periodic hit: the hit image's code joins the kept ones,
+// the ball is checked against the layer in the frame of the ray, then the
+// key is translated to its normal form and the vertex solved from it.
+template <int DK>
+__device__ void new_vertex_periodic(const ExploreRays &a, int64_t it) {
+  const int d = a.d;
+  const int32_t hit = a.idx[it];
+  int32_t *key = a.new_keys + it * (d + 1);
+  if (!a.ok[it]) {
+    key[0] = -1;
+    return;
+  }
+  if (hit < 0 || (int64_t)hit >= a.n_nodes) {  // no hit: the ray left the layer
+    atomicOr(a.err, VSET_THIN);
+    key[0] = -1;
+    return;
+  }
+  const int32_t j = a.per.tkey[hit];
+  const int32_t *sig = a.keys + a.item_v[it] * (d + 1);
+  const int o = a.item_o[it];
+  int32_t ks[DK + 1];
+  int q = 0;
+  bool placed = false;
+  for (int b = 0; b <= d; ++b) {
+    if (b == o) continue;
+    if (!placed && j < sig[b]) {
+      ks[q++] = j;
+      placed = true;
+    }
+    ks[q++] = sig[b];
+  }
+  if (!placed) ks[q++] = j;
+  const ImagePts pt{a.per, d};
+  double v[DK];
+  if (!solve_vertex<DK>(pt, d, ks, INT32_MAX, v)) {
+    key[0] = -2;
+    return;
+  }
+  double r2 = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double e = v[k] - pt(ks[0], k);
+    r2 += e * e;
+  }
+  const double R = sqrt(r2);
+  bool inside = true;
+  for (int k = 0; k < d; ++k) inside = inside && v[k] - R > -a.per.w && v[k] + R < 1.0 + a.per.w;
+  if (!inside) {
+    atomicOr(a.err, VSET_THIN);
+    key[0] = -1;
+    return;
+  }
+  if (!periodic_canon(ks, d + 1, d, a.per.S)) {
+    atomicOr(a.err, VSET_RANGE);
+    key[0] = -1;
+    return;
+  }
+  if (!solve_vertex<DK>(pt, d, ks, INT32_MAX, v)) {
+    key[0] = -2;
+    return;
+  }
+  for (int b = 0; b <= d; ++b) key[b] = ks[b];
+  for (int k = 0; k < d; ++k) a.new_coords[it * d + k] = v[k];
 }
 
 // Edge rays of the frontier: item (vertex v, omitted position o).
@@ -139,6 +264,10 @@ template <int DK>
 __global__ __launch_bounds__(128) void edge_rays_kernel(ExploreRays a) {
   const int64_t it = (int64_t)blockIdx.x * 128 + threadIdx.x;
   if (it >= a.m) return;
+  if (a.per.S) {
+    edge_ray_periodic<DK>(a, it);
+    return;
+  }
   const int d = a.d;
   const int64_t v = a.item_v[it];
   const int o = a.item_o[it];
@@ -160,7 +289,7 @@ __global__ __launch_bounds__(128) void edge_rays_kernel(ExploreRays a) {
 #pragma unroll
     for (int k = 0; k < DK; ++k) w[k] = (k == f / 2) ? ((f % 2) ? 1.0 : -1.0) : 0.0;
   }
-  orth_complement<DK>(a.nodes, d, eta, d, fb, w);
+  orth_complement<DK>(NodePts{a.nodes, d}, d, eta, d, fb, w);
   double nr = 0.0;
 #pragma unroll
   for (int k = 0; k < DK; ++k) nr += w[k] * w[k];
@@ -181,6 +310,10 @@ template <int DK>
 __global__ __launch_bounds__(128) void new_vertex_kernel(ExploreRays a) {
   const int64_t it = (int64_t)blockIdx.x * 128 + threadIdx.x;
   if (it >= a.m) return;
+  if (a.per.S) {
+    new_vertex_periodic<DK>(a, it);
+    return;
+  }
   const int d = a.d;
   const int32_t hit = a.idx[it];
   int32_t *key = a.new_keys + it * (d + 1);
@@ -206,7 +339,7 @@ __global__ __launch_bounds__(128) void new_vertex_kernel(ExploreRays a) {
   double v[DK];
   int32_t ks[DK + 1];
   for (int b = 0; b <= d; ++b) ks[b] = key[b];
-  if (!solve_vertex<DK>(a.nodes, d, ks, a.face_base, v)) {
+  if (!solve_vertex<DK>(NodePts{a.nodes, d}, d, ks, a.face_base, v)) {
     key[0] = -2;  // singular: degenerate input
     return;
   }
@@ -220,7 +353,7 @@ __global__ void descent_project_kernel(const float *X, int d, const int32_t *sig
   double w[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) w[k] = (k < d) ? u[k] : 0.0;
-  orth_complement<DK>(X, d, sig, m, INT32_MAX, w);
+  orth_complement<DK>(NodePts{X, d}, d, sig, m, INT32_MAX, w);
   double nr = 0.0;
 #pragma unroll
   for (int k = 0; k < DK; ++k) nr += w[k] * w[k];
@@ -235,12 +368,13 @@ __global__ void advance_kernel(double *r, const double *u, const double *t, int 
 }
 
 template <int DK>
-__global__ void solve_one_kernel(const float *X, int d, const int32_t *sig, double *v, int *ok) {
+__global__ void solve_one_kernel(const float *X, int d, const int32_t *sig, Periodic per, double *v, int *ok) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int32_t ks[DK + 1];
   for (int b = 0; b <= d; ++b) ks[b] = sig[b];
   double vv[DK];
-  const bool good = solve_vertex<DK>(X, d, ks, INT32_MAX, vv);
+  const bool good = per.S ? solve_vertex<DK>(ImagePts{per, d}, d, ks, INT32_MAX, vv)
+                          : solve_vertex<DK>(NodePts{X, d}, d, ks, INT32_MAX, vv);
   for (int k = 0; k < d; ++k) v[k] = good ? vv[k] : 0.0;
   *ok = good ? 1 : 0;
 }
@@ -329,9 +463,9 @@ hipError_t launch_advance(double *r, const double *u, const double *t, int d, do
   return hipGetLastError();
 }
 
-hipError_t launch_solve_one(const float *X, int d, const int32_t *sig, double *v, int *ok,
-                            hipStream_t s) {
-  VG_DK_DISPATCH(d, solve_one_kernel, dim3(1), dim3(64), X, d, sig, v, ok);
+hipError_t launch_solve_one(const float *X, int d, const int32_t *sig, const Periodic &per, double *v,
+                            int *ok, hipStream_t s) {
+  VG_DK_DISPATCH(d, solve_one_kernel, dim3(1), dim3(64), X, d, sig, per, v, ok);
   return hipGetLastError();
 }
 

@@ -45,6 +45,8 @@ struct RayScanArgs {
   float tau;
   int force_all;     // queue every ray for the FP64 recheck
   int64_t flag_tag;  // ORed into queued ray ids (batched mode: problem << 40)
+  float node_err;    // bound on |row - exact point| of a node row (rows rounded
+                     // from FP64 points, e.g. periodic images); 0: rows exact
 };
 
 // One problem of a persistent batch of general rays: its scan arguments and
@@ -107,6 +109,8 @@ struct RecheckArgs {
   uint8_t *st_out;
   uint32_t *tie_counter;
   double *t64_out;  // optional FP64 t of each rechecked ray
+  const double *nodes64;  // RAYS_F64: exact FP64 node rows read in place of
+                          // `nodes` when set (rows rounded for the FP32 scan)
 };
 
 struct AccumArgs {

@@ -21,6 +21,8 @@
 //   * some nearly grazing node (|den| within its rounding bound, so its true
 //     eligibility is unknown) could still beat the winner,
 //   * the winner's bisector is nearly parallel to the ray, or it has no hit.
+// Node rows rounded from exact FP64 points (node_err > 0) widen the bounds by
+// their rounding; the recheck then reads the exact points.
 #include "vg_dfloat.h"
 #include "vg_internal.h"
 
@@ -71,6 +73,11 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
   // grazing test: den^2 <= kd^2 |r - g|^2 with |r - g|^2 <= 2 num + 4 rho^2
   const float kd = (4.f * (float)(d + 4)) * 0x1p-24f;
   const float kd2 = kd * kd;
+  // node rows rounded from exact points (error up to ne each) move den by up
+  // to 2 ne: |den| <= kd |r-g| + 2 ne, squared below 2 kd^2 |r-g|^2 + 8 ne^2
+  const float ne = a.node_err;
+  const float kd2g = ne > 0.f ? 2.f * kd2 : kd2;
+  const float ne8 = 8.f * ne * ne;
   const float rho4 = 4.f * rho2;
   float gmin = __builtin_inff();  // smallest num of a nearly grazing node
   const int32_t *ex = (active && a.n_excl > 0) ? a.excl + ray * a.n_excl : nullptr;
@@ -105,7 +112,7 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
         next_ex = ep < a.n_excl ? ex[ep] : -1;
         continue;
       }
-      if (den * den <= kd2 * __builtin_fmaf(2.f, num, rho4)) gmin = fminf(gmin, num);
+      if (den * den <= kd2g * __builtin_fmaf(2.f, num, rho4) + ne8) gmin = fminf(gmin, num);
       if (den > 0.f && num < t2 * den) {
         const float t = num / den;
         if (t < t1) {
@@ -142,6 +149,10 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
       en += 2.f * rg * 0x1p-24f * sqrtf(xn2);
       ed += rg * 0x1p-24f;
     }
+    if (ne > 0.f) {  // rounded rows of r and g
+      en += 2.f * rg * ne;
+      ed += 2.f * ne;
+    }
     return (en + tc * ed) / dc;
   };
   float eb = 0.f, eb1 = 0.f;
@@ -152,7 +163,7 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
   bool grazing = false;
   if (gmin < __builtin_inff()) {
     grazing = gmin < 0.f ||
-              gmin * gmin <= 4.f * kd2 * __builtin_fmaf(2.f, gmin, rho4) * t1 * t1 ||
+              gmin * gmin <= (4.f * kd2g * __builtin_fmaf(2.f, gmin, rho4) + 4.f * ne8) * t1 * t1 ||
               i1 < 0;
   }
 

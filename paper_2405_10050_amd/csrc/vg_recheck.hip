@@ -106,8 +106,8 @@ __device__ __forceinline__ void finish_ray(const RecheckArgs &a, int64_t ray, in
 // One node r (coordinates xr, as read from memory) against the ray: eq. (t)
 // in FP64 with the factored numerator, into the running top-2.  CELLS: the
 // Monte-Carlo form, x = g.
-template <int DK, bool CELLS>
-__device__ __forceinline__ void eval_node(const float *xr, int stride, int d, int32_t r, const double (&x)[DK],
+template <int DK, bool CELLS, typename NT>
+__device__ __forceinline__ void eval_node(const NT *xr, int stride, int d, int32_t r, const double (&x)[DK],
                                           const double (&u)[DK], const double (&g)[DK],
                                           const double (&gx)[DK], Top2 &tp) {
   double e[DK];
@@ -236,13 +236,27 @@ __global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
   }
 }
 
+// The node rows a recheck reads: FP32 rows, or the exact FP64 ones.
+template <typename NT>
+__device__ __forceinline__ const NT *node_rows(const RecheckArgs &a);
+template <>
+__device__ __forceinline__ const float *node_rows<float>(const RecheckArgs &a) {
+  return a.nodes;
+}
+template <>
+__device__ __forceinline__ const double *node_rows<double>(const RecheckArgs &a) {
+  return a.nodes64;
+}
+
 // Large clouds: one queued ray per workgroup, its 512 threads striding over
 // the nodes read from memory (a few queued rays then still fill the GPU),
 // merged by shuffles and across waves in LDS.  The same node expression and
 // finish as recheck_kernel, and the top-2 does not depend on the order of
-// the merges, so the results are the same.
-template <int DK, bool CELLS>
+// the merges, so the results are the same.  NT = double reads the exact
+// FP64 rows (general rays whose FP32 rows were rounded).
+template <int DK, bool CELLS, typename NT = float>
 __global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a) {
+  const NT *rows = node_rows<NT>(a);
   __shared__ double st1[WAVES1], st2[WAVES1];
   __shared__ int32_t si1[WAVES1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -276,7 +290,7 @@ __global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a) {
         if (e < n_excl) ex[e] = a.excl[ray * n_excl + e];
     }
 #pragma unroll
-    for (int k = 0; k < DK; ++k) g[k] = k < d ? (double)a.nodes[(int64_t)gi * d + k] : 0.0;
+    for (int k = 0; k < DK; ++k) g[k] = k < d ? (double)rows[(int64_t)gi * d + k] : 0.0;
     if (CELLS) {
 #pragma unroll
       for (int k = 0; k < DK; ++k) x[k] = g[k];
@@ -294,7 +308,7 @@ __global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a) {
 #pragma unroll
         for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
       }
-      if (!skip) eval_node<DK, CELLS>(a.nodes + r * d, 1, d, (int32_t)r, x, u, g, gx, tp);
+      if (!skip) eval_node<DK, CELLS>(rows + r * d, 1, d, (int32_t)r, x, u, g, gx, tp);
     }
     for (int off = 32; off > 0; off >>= 1) {
       Top2 o;
@@ -538,6 +552,14 @@ hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
   // large clouds: a workgroup per queued ray (the queue is often short there)
   const bool wide = a.n >= (int64_t(1) << 18);
   const dim3 gridw(max_grid);
+  if (a.nodes64) {  // exact FP64 rows: general rays, d <= 8
+    if (cells || a.d > 8) return hipErrorInvalidValue;
+    if (a.d <= 4)
+      hipLaunchKernelGGL((recheck_wide_kernel<4, false, double>), gridw, blk, 0, s, a);
+    else
+      hipLaunchKernelGGL((recheck_wide_kernel<8, false, double>), gridw, blk, 0, s, a);
+    return hipGetLastError();
+  }
 #define VG_RECHECK(DKV)                                                            \
   do {                                                                            \
     if (wide && cells)                                                            \

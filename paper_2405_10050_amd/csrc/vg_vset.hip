@@ -62,11 +62,15 @@ __device__ __forceinline__ int64_t lookup(const uint64_t *fps, int64_t cap, uint
   return -1;
 }
 
-// The edge of vertex key `key` that omits position o.
-__device__ __forceinline__ void edge_of(const int32_t *key, int d, int o, int32_t *eta) {
+// The edge of vertex key `key` that omits position o.  On the periodic
+// diagram (S > 0) a vertex key's first entry has k = 0; dropping it leaves
+// an edge that is translated to the same normal form.  False when that
+// fails (shifts outside {-1,0,1}^d).
+__device__ __forceinline__ bool edge_of(const int32_t *key, int d, int o, int32_t *eta, int32_t S) {
   int q = 0;
   for (int b = 0; b <= d; ++b)
     if (b != o) eta[q++] = key[b];
+  return S == 0 || o != 0 || periodic_canon(eta, d, d, S);
 }
 
 __global__ void frontier_flags_kernel(const int32_t *__restrict__ vkeys, int64_t lb, int64_t le,
@@ -84,7 +88,11 @@ __global__ void frontier_flags_kernel(const int32_t *__restrict__ vkeys, int64_t
     return;
   }
   int32_t eta[VG_MAX_DIM];
-  edge_of(key, d, o, eta);
+  if (!edge_of(key, d, o, eta, E.S)) {
+    atomicOr(err, VSET_RANGE);
+    flags[t] = 0;
+    return;
+  }
   const int64_t h = lookup(E.fp, E.cap, tuple_fp(eta, d));
   uint32_t c = 0;
   if (h >= 0) {
@@ -165,7 +173,11 @@ __global__ void append_vertices_kernel(const int64_t *__restrict__ sel, int64_t 
   for (int k = 0; k < d; ++k) vcoords[(nv + p) * d + k] = ncoords[it * d + k];
   int32_t eta[VG_MAX_DIM];
   for (int o = 0; o <= d; ++o) {
-    edge_of(key, d, o, eta);
+    if (!edge_of(key, d, o, eta, E.S)) {
+      eslot[p * L + o] = -1;
+      atomicOr(err, VSET_RANGE);
+      continue;
+    }
     const uint64_t fp = tuple_fp(eta, d);
     int64_t h = (int64_t)(fp & (uint64_t)(E.cap - 1));
     int64_t got = -1;
@@ -204,8 +216,8 @@ __global__ void eset_verify_kernel(const int64_t *__restrict__ sel, int64_t nn, 
   const int64_t h = eslot[t];
   if (h < 0) return;
   int32_t eta[VG_MAX_DIM];
-  edge_of(nkeys + sel[p] * L, d, o, eta);
-  if (!tuple_eq(E.key + h * d, eta, d)) atomicOr(err, VSET_COLLISION);
+  if (edge_of(nkeys + sel[p] * L, d, o, eta, E.S) && !tuple_eq(E.key + h * d, eta, d))
+    atomicOr(err, VSET_COLLISION);
 }
 
 __global__ void append_unbounded_kernel(const int64_t *__restrict__ sel, int64_t nb, int64_t b0, int d,
@@ -243,7 +255,10 @@ __global__ void rebuild_eset_kernel(ESet E, const int32_t *__restrict__ vkeys, i
   const int32_t *key = vkeys + v * (d + 1);
   int32_t eta[VG_MAX_DIM];
   for (int o = 0; o <= d; ++o) {
-    edge_of(key, d, o, eta);
+    if (!edge_of(key, d, o, eta, E.S)) {
+      atomicOr(err, VSET_RANGE);
+      continue;
+    }
     const uint64_t fp = tuple_fp(eta, d);
     int64_t h = (int64_t)(fp & (uint64_t)(E.cap - 1));
     int64_t got = -1;
