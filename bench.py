@@ -372,6 +372,59 @@ def bench_explore_incircle(args):
     }
 
 
+# Vertices and neighbours per cell with periodic boundary conditions as Table
+# empscaling prints them (d = 2..6), for the comparison in the JSON line.
+EMPSCALING_TABLE = {2: (6.6, 6.6), 3: (29.2, 16.6), 4: (191, 43), 5: (1250, 95), 6: (9720, 210)}
+
+
+def bench_periodic(args):
+    """Exhaustive search of the periodic diagram (the torus) of uniform
+    clouds for d = 2..6: vertices and neighbours per cell, the quantities of
+    Table empscaling, with the search's vertex rate over all five."""
+    import torch
+
+    import paper_2405_10050_amd as vg
+    import workloads as W
+
+    sizes = {2: 100_000, 3: 100_000, 4: 20_000, 5: 2000, 6: 1000}
+    rows, total_v, total_t = [], 0, 0.0
+    for d, n in sizes.items():
+        X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).cuda()
+        draws = W.descent_draws(d)
+        if args.warmup:
+            vg.explore(X, draws, periodic=True)
+        t0 = time.perf_counter()
+        m = vg.explore(X, draws, periodic=True)
+        dt = time.perf_counter() - t0
+        ids, sh = m["sigma"].astype(np.int64), m["shift"].astype(np.int64)
+        pairs = []
+        for a in range(d + 1):
+            for b in range(a + 1, d + 1):
+                rel = np.zeros(ids.shape[0], dtype=np.int64)
+                for q in range(d):
+                    rel += (sh[:, b, q] - sh[:, a, q] + 1) * 3 ** q
+                pairs.append((ids[:, a] * n + ids[:, b]) * 3 ** d + rel)
+        facets = np.unique(np.concatenate(pairs)).size
+        nv = ids.shape[0]
+        total_v += nv
+        total_t += dt
+        row = {"d": d, "N": n, "vertices": nv, "seconds": dt, "raycasts": m["raycasts"],
+               "vertices_per_cell": (d + 1) * nv / n, "neighbours_per_cell": 2 * facets / n,
+               "table_empscaling": EMPSCALING_TABLE[d]}
+        rows.append(row)
+        print(f"[bench] periodic d={d} N={n}: {nv} vertices in {dt:.2f} s, "
+              f"{row['vertices_per_cell']:.1f} vertices and {row['neighbours_per_cell']:.1f} neighbours per cell",
+              file=sys.stderr, flush=True)
+    return {
+        "metric": "vertices/sec exhaustive Voronoi vertex search",
+        "value": total_v / total_t, "unit": "vertices/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": total_t * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "periodic diagram (torus) of uniform clouds, d=2..6 "
+                               "(N = 1e5, 1e5, 2e4, 2000, 1000)", "per_dimension": rows},
+    }
+
+
 def bench_explore(args):
     """Exhaustive vertex search (Algorithm 2) of a uniform cloud: the
     unbounded diagram, or (clipped_*) the diagram clipped to the unit cube."""
@@ -412,7 +465,8 @@ def main():
                              "uniform_d2_n1000", "uniform_d6_n10000", "nbr_d4_n50000",
                              "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000",
                              "clipped_d2_n1000", "clipped_d6_n10000", "hmc_d5_n10000",
-                             "explore_incircle_d3_n100000", "explore_incircle_d2_n300000"])
+                             "explore_incircle_d3_n100000", "explore_incircle_d2_n300000",
+                             "periodic_d2to6"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -442,7 +496,7 @@ def main():
                  "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle,
                  "clipped_d2_n1000": bench_explore, "clipped_d6_n10000": bench_explore,
                  "hmc_d5_n10000": bench_hmc, "explore_incircle_d3_n100000": bench_explore_incircle,
-                 "explore_incircle_d2_n300000": bench_explore_incircle}
+                 "explore_incircle_d2_n300000": bench_explore_incircle, "periodic_d2to6": bench_periodic}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 

@@ -184,12 +184,14 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   if (m <= 0) return VG_OK;
   if (nodes64 && incircle) return fail(ctx, VG_EUNSUPPORTED, "exact FP64 rows need the dense scan");
   const size_t grid_bytes = incircle ? incircle_rays_scratch_bytes(n, d) : 0;
-  size_t need = Carver::need({(size_t)m * 8, grid_bytes});
+  const size_t split_bytes = incircle ? 0 : ray_scan_split_bytes(m, n);
+  size_t need = Carver::need({(size_t)m * 8, grid_bytes, split_bytes});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = cv.take<int64_t>(m);
   void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
+  void *split = split_bytes ? cv.take<char>(split_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
   RayScanArgs a{};
@@ -216,7 +218,7 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
       incircle ? launch_incircle_rays(a, grid_scratch, incircle == 2,
                                       reinterpret_cast<unsigned long long *>(ctx->counters + CNT_NN_CALLS),
                                       ctx->stream)
-               : launch_ray_scan(a, ctx->stream);
+               : launch_ray_scan(a, split, split_bytes, ctx->stream);
   timer.stop();
   if (e != hipSuccess) return hip_fail(ctx, e, "ray scan launch");
   RecheckArgs r{};
@@ -349,13 +351,16 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t 
   if ((flags & VG_INIT_HEURISTIC) && !incircle)
     return fail(ctx, VG_EINVAL, "VG_INIT_HEURISTIC needs VG_INCIRCLE");
   const size_t grid_bytes = incircle ? incircle_rays_scratch_bytes(n_nodes, d) : 0;
-  size_t need = Carver::need({recheck ? (size_t)n_rays * 8 : 0, status_out ? 0 : (size_t)n_rays, grid_bytes});
+  const size_t split_bytes = incircle ? 0 : ray_scan_split_bytes(n_rays, n_nodes);
+  size_t need = Carver::need(
+      {recheck ? (size_t)n_rays * 8 : 0, status_out ? 0 : (size_t)n_rays, grid_bytes, split_bytes});
   rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = recheck ? cv.take<int64_t>(n_rays) : nullptr;
   uint8_t *st = status_out ? status_out : cv.take<uint8_t>(n_rays);
   void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
+  void *split = split_bytes ? cv.take<char>(split_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
   RayScanArgs a{};
@@ -380,7 +385,7 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t 
       incircle ? launch_incircle_rays(a, grid_scratch, (flags & VG_INIT_HEURISTIC) ? 1 : 0,
                                       reinterpret_cast<unsigned long long *>(ctx->counters + CNT_NN_CALLS),
                                       ctx->stream)
-               : launch_ray_scan(a, ctx->stream);
+               : launch_ray_scan(a, split, split_bytes, ctx->stream);
   timer.stop();
   if (e != hipSuccess) return hip_fail(ctx, e, "ray scan launch");
   if (recheck) {

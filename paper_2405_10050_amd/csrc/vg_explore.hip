@@ -434,6 +434,11 @@ int explore_run(vg_ctx *ctx, const Setup &su, vg_mesh *M, bool &thin) {
                         X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr, incircle, su.scan64,
                         su.node_err));
       M->raycasts += m;
+      uint32_t flagged = 0;
+      if (verbose) {
+        EX_HIP(hipMemcpyAsync(&flagged, ctx->counters + CNT_FLAGGED, 4, hipMemcpyDeviceToHost, X.s));
+        EX_HIP(hipStreamSynchronize(X.s));
+      }
       if (incircle) {
         uint64_t calls = 0;
         EX_HIP(hipMemcpyAsync(&calls, ctx->counters + CNT_NN_CALLS, 8, hipMemcpyDeviceToHost, X.s));
@@ -489,8 +494,8 @@ int explore_run(vg_ctx *ctx, const Setup &su, vg_mesh *M, bool &thin) {
       ++level;
       if (verbose) {
         const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-        std::fprintf(stderr, "[explore] level %d: %lld rays, %lld new vertices, %lld total, %.2f s\n",
-                     level, (long long)m, (long long)nn, (long long)nv, el);
+        std::fprintf(stderr, "[explore] level %d: %lld rays (%u rechecked), %lld new vertices, %lld total, %.2f s\n",
+                     level, (long long)m, flagged, (long long)nn, (long long)nv, el);
         std::fflush(stderr);
       }
     }

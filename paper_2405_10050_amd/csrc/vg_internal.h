@@ -185,7 +185,10 @@ size_t incircle_rays_scratch_bytes(int64_t n, int d);
 hipError_t launch_incircle_rays(const RayScanArgs &a, void *scratch, int heuristic, unsigned long long *nn_calls,
                                 hipStream_t s);
 
-hipError_t launch_ray_scan(const RayScanArgs &a, hipStream_t s);
+// split: device scratch of ray_scan_split_bytes(m, n) bytes (or null): a call
+// with few rays then splits the node range over workgroups and merges.
+size_t ray_scan_split_bytes(int64_t m, int64_t n);
+hipError_t launch_ray_scan(const RayScanArgs &a, void *split, size_t split_bytes, hipStream_t s);
 constexpr int kRayTile = 256;  // rays per workgroup (and per batched item) of the ray scan
 hipError_t launch_ray_scan_batched(const RayBatchProblem *probs_dev, int np, int64_t total,
                                    unsigned long long *next, int grid, hipStream_t s);

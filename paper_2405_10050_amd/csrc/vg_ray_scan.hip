@@ -31,22 +31,53 @@ namespace {
 
 constexpr int TILE = kRayTile;
 
-// Rays [blk*TILE, blk*TILE + TILE) of one problem; sx holds TILE*DK floats.
-// Every thread of the workgroup must call it (it contains barriers).
-template <int DK>
-__device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk, float *sx) {
-  const int tid = threadIdx.x;
-  const int64_t ray = blk * TILE + tid;
-  const int d = a.d;
-  const int64_t n = a.n;
-  int32_t gidx = ray < a.m ? a.gen[ray] : 0;
-  if (ray < a.m && (gidx < 0 || gidx >= n)) {  // invalid generator index: report, skip
-    a.t_out[ray] = __builtin_nanf("");
-    a.idx_out[ray] = -1;
-    a.st_out[ray] = VG_ST_SUSPECT;
-  }
-  const bool active = ray < a.m && gidx >= 0 && gidx < n;
+// Scan state of one ray over a range of nodes (t in units of 2t): the
+// running top-2 (t, den, node of the best) and the smallest numerator of a
+// nearly grazing node.
+struct ScanState {
+  float t1, t2, den1, den2, gmin;
+  int32_t i1;
+};
 
+__device__ __forceinline__ ScanState scan_state_empty() {
+  return ScanState{__builtin_inff(), __builtin_inff(), 0.f, 0.f, __builtin_inff(), -1};
+}
+
+// Folds the state of a later node range into S: equal t keeps S's node, the
+// lower index, as the sequential scan does.
+__device__ __forceinline__ void scan_state_merge(ScanState &S, const ScanState &T) {
+  if (T.t1 < S.t1) {
+    S.t2 = S.t1;
+    S.den2 = S.den1;
+    S.t1 = T.t1;
+    S.den1 = T.den1;
+    S.i1 = T.i1;
+  } else if (T.t1 < S.t2) {
+    S.t2 = T.t1;
+    S.den2 = T.den1;
+  }
+  if (T.t2 < S.t2) {
+    S.t2 = T.t2;
+    S.den2 = T.den2;
+  }
+  S.gmin = fminf(S.gmin, T.gmin);
+}
+
+// One ray's inputs in FP32.
+template <int DK>
+struct RayIn {
+  bool active;
+  float x[DK], u[DK], g[DK], gx[DK];
+  float rho2;
+};
+
+template <int DK>
+__device__ __forceinline__ void ray_load(const RayScanArgs &a, int64_t ray, RayIn<DK> &R) {
+  const int d = a.d;
+  const int32_t gidx = ray < a.m ? a.gen[ray] : 0;
+  const bool active = ray < a.m && gidx >= 0 && gidx < a.n;
+  // plain local arrays first, then unconditional copies: keeps every array
+  // in registers
   float x[DK], u[DK], g[DK];
   if (active) {
     const float *xg = a.nodes + (int64_t)gidx * d;
@@ -64,39 +95,79 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
 #pragma unroll
     for (int k = 0; k < DK; ++k) x[k] = u[k] = g[k] = 0.f;
   }
-  float rho2 = 0.f, gx[DK];
+  float rho2 = 0.f;
+  R.active = active;
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
-    gx[k] = g[k] - x[k];
-    rho2 = __builtin_fmaf(gx[k], gx[k], rho2);
+    const float e = g[k] - x[k];
+    rho2 = __builtin_fmaf(e, e, rho2);
+    R.x[k] = x[k];
+    R.u[k] = u[k];
+    R.g[k] = g[k];
+    R.gx[k] = e;
   }
-  // grazing test: den^2 <= kd^2 |r - g|^2 with |r - g|^2 <= 2 num + 4 rho^2
-  const float kd = (4.f * (float)(d + 4)) * 0x1p-24f;
-  const float kd2 = kd * kd;
-  // node rows rounded from exact points (error up to ne each) move den by up
-  // to 2 ne: |den| <= kd |r-g| + 2 ne, squared below 2 kd^2 |r-g|^2 + 8 ne^2
-  const float ne = a.node_err;
-  const float kd2g = ne > 0.f ? 2.f * kd2 : kd2;
-  const float ne8 = 8.f * ne * ne;
-  const float rho4 = 4.f * rho2;
-  float gmin = __builtin_inff();  // smallest num of a nearly grazing node
-  const int32_t *ex = (active && a.n_excl > 0) ? a.excl + ray * a.n_excl : nullptr;
-  int ep = 0;
-  int32_t next_ex = ex ? ex[0] : -1;
+  R.rho2 = rho2;
+}
 
-  float t1 = __builtin_inff(), t2 = __builtin_inff();  // in units of 2t
-  float den1 = 0.f, den2 = 0.f;
-  int32_t i1 = -1;
-  for (int64_t base = 0; base < n; base += TILE) {
+// An invalid generator index is reported and the ray skipped.
+__device__ __forceinline__ void report_invalid_gen(const RayScanArgs &a, int64_t ray) {
+  if (ray >= a.m) return;
+  const int32_t gidx = a.gen[ray];
+  if (gidx < 0 || gidx >= a.n) {
+    a.t_out[ray] = __builtin_nanf("");
+    a.idx_out[ray] = -1;
+    a.st_out[ray] = VG_ST_SUSPECT;
+  }
+}
+
+// grazing test: den^2 <= kd^2 |r - g|^2 with |r - g|^2 <= 2 num + 4 rho^2.
+// Node rows rounded from exact points (error up to ne each) move den by up
+// to 2 ne: |den| <= kd |r-g| + 2 ne, squared below 2 kd^2 |r-g|^2 + 8 ne^2.
+struct GrazeBound {
+  float kd2g, ne8;
+};
+__device__ __forceinline__ GrazeBound graze_bound(const RayScanArgs &a) {
+  const float kd = (4.f * (float)(a.d + 4)) * 0x1p-24f;
+  const float kd2 = kd * kd;
+  const float ne = a.node_err;
+  return GrazeBound{ne > 0.f ? 2.f * kd2 : kd2, 8.f * ne * ne};
+}
+
+// Nodes [lo, hi) into S; every thread of the workgroup calls it with the
+// same range (it contains barriers); sx holds TILE*DK floats.
+template <int DK>
+__device__ __forceinline__ void ray_scan_nodes(const RayScanArgs &a, int64_t ray, const RayIn<DK> &R, int64_t lo,
+                                               int64_t hi, float *sx, ScanState &S) {
+  const int tid = threadIdx.x;
+  const int d = a.d;
+  const GrazeBound gb = graze_bound(a);
+  const float rho4 = 4.f * R.rho2;
+  float x[DK], u[DK], g[DK], gx[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    x[k] = R.x[k];
+    u[k] = R.u[k];
+    g[k] = R.g[k];
+    gx[k] = R.gx[k];
+  }
+  // exclusions (sorted) walked alongside the ascending node index from lo
+  const int32_t *ex = (R.active && a.n_excl > 0) ? a.excl + ray * a.n_excl : nullptr;
+  int ep = 0;
+  if (ex)
+    while (ep < a.n_excl && (int64_t)ex[ep] < lo) ++ep;
+  int32_t next_ex = (ex && ep < a.n_excl) ? ex[ep] : -1;
+  float t1 = S.t1, t2 = S.t2, den1 = S.den1, den2 = S.den2, gmin = S.gmin;
+  int32_t i1 = S.i1;
+  for (int64_t base = lo; base < hi; base += TILE) {
     __syncthreads();
     {
       const int64_t r = base + tid;
 #pragma unroll
-      for (int k = 0; k < DK; ++k) sx[tid * DK + k] = (r < n && k < d) ? a.nodes[r * d + k] : 0.f;
+      for (int k = 0; k < DK; ++k) sx[tid * DK + k] = (r < hi && k < d) ? a.nodes[r * d + k] : 0.f;
     }
     __syncthreads();
-    if (!active) continue;
-    const int cnt = (int)((n - base) < TILE ? (n - base) : TILE);
+    if (!R.active) continue;
+    const int cnt = (int)((hi - base) < TILE ? (hi - base) : TILE);
     for (int q = 0; q < cnt; ++q) {
       const int32_t r = (int32_t)(base + q);
       float num = 0.f, den = 0.f;
@@ -112,7 +183,7 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
         next_ex = ep < a.n_excl ? ex[ep] : -1;
         continue;
       }
-      if (den * den <= kd2g * __builtin_fmaf(2.f, num, rho4) + ne8) gmin = fminf(gmin, num);
+      if (den * den <= gb.kd2g * __builtin_fmaf(2.f, num, rho4) + gb.ne8) gmin = fminf(gmin, num);
       if (den > 0.f && num < t2 * den) {
         const float t = num / den;
         if (t < t1) {
@@ -128,7 +199,27 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
       }
     }
   }
-  if (!active) return;
+  S = ScanState{t1, t2, den1, den2, gmin, i1};
+}
+
+// Certificate and outputs of an active ray from its full scan state.
+template <int DK>
+__device__ __forceinline__ void ray_finish(const RayScanArgs &a, int64_t ray, const RayIn<DK> &R,
+                                           const ScanState &S) {
+  const int d = a.d;
+  float x[DK], u[DK], g[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    x[k] = R.x[k];
+    u[k] = R.u[k];
+    g[k] = R.g[k];
+  }
+  const float rho2 = R.rho2;
+  const float rho4 = 4.f * rho2;
+  const GrazeBound gb = graze_bound(a);
+  const float kd2g = gb.kd2g, ne8 = gb.ne8, ne = a.node_err;
+  const float t1 = S.t1, t2 = S.t2, den1 = S.den1, den2 = S.den2, gmin = S.gmin;
+  const int32_t i1 = S.i1;
 
   // FP32 error bound of t' = num/den for a candidate (units of 2t): num and
   // den are sums of d rounded products of differences, |r - x|^2 = t' den +
@@ -243,10 +334,66 @@ __device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk,
   a.st_out[ray] = st;
 }
 
+// Rays [blk*TILE, blk*TILE + TILE) of one problem over all nodes; sx holds
+// TILE*DK floats.  Every thread of the workgroup must call it (barriers).
+template <int DK>
+__device__ __forceinline__ void ray_scan_tile(const RayScanArgs &a, int64_t blk, float *sx) {
+  const int64_t ray = blk * TILE + threadIdx.x;
+  report_invalid_gen(a, ray);
+  RayIn<DK> R;
+  ray_load<DK>(a, ray, R);
+  ScanState S = scan_state_empty();
+  ray_scan_nodes<DK>(a, ray, R, 0, a.n, sx, S);
+  if (R.active) ray_finish<DK>(a, ray, R, S);
+}
+
 template <int DK>
 __global__ __launch_bounds__(TILE) void ray_scan_kernel(RayScanArgs a) {
   __shared__ float sx[TILE * DK];
   ray_scan_tile<DK>(a, blockIdx.x, sx);
+}
+
+// Few rays: workgroup (ray tile x, node part y) scans nodes
+// [y chunk, (y+1) chunk) and stores its state in parts[y][ray].
+template <int DK>
+__global__ __launch_bounds__(TILE) void ray_scan_part_kernel(RayScanArgs a, int64_t chunk,
+                                                             ScanState *__restrict__ parts) {
+  __shared__ float sx[TILE * DK];
+  const int64_t ray = (int64_t)blockIdx.x * TILE + threadIdx.x;
+  RayIn<DK> R;
+  ray_load<DK>(a, ray, R);
+  const int64_t lo = (int64_t)blockIdx.y * chunk;
+  const int64_t hi = lo + chunk < a.n ? lo + chunk : a.n;
+  ScanState S = scan_state_empty();
+  ray_scan_nodes<DK>(a, ray, R, lo, hi, sx, S);
+  if (ray < a.m) parts[(int64_t)blockIdx.y * a.m + ray] = S;
+}
+
+// Folds the parts of each ray in node order, then certifies it as the
+// whole-range scan does.
+template <int DK>
+__global__ __launch_bounds__(TILE) void ray_merge_kernel(RayScanArgs a, int P, const ScanState *__restrict__ parts) {
+  const int64_t ray = (int64_t)blockIdx.x * TILE + threadIdx.x;
+  if (ray >= a.m) return;
+  report_invalid_gen(a, ray);
+  RayIn<DK> R;
+  ray_load<DK>(a, ray, R);
+  if (!R.active) return;
+  ScanState S = parts[ray];
+  for (int p = 1; p < P; ++p) scan_state_merge(S, parts[(int64_t)p * a.m + ray]);
+  ray_finish<DK>(a, ray, R, S);
+}
+
+// Node parts of a call with few rays (1: no split): enough workgroups to
+// fill the GPU, each part at least two node tiles.
+int split_parts(int64_t m, int64_t n) {
+  const int64_t tiles = (m + TILE - 1) / TILE;
+  if (tiles >= 1024) return 1;
+  int64_t P = (2048 + tiles - 1) / tiles;
+  const int64_t by_nodes = n / (2 * TILE);
+  if (P > by_nodes) P = by_nodes;
+  if (P > 256) P = 256;
+  return P > 1 ? (int)P : 1;
 }
 
 // Uneven batches of problems: workgroups take (problem, ray tile) items from
@@ -285,11 +432,38 @@ __global__ __launch_bounds__(TILE) void ray_scan_batched_kernel(const RayBatchPr
 
 }  // namespace
 
-hipError_t launch_ray_scan(const RayScanArgs &a, hipStream_t s) {
+size_t ray_scan_split_bytes(int64_t m, int64_t n) {
+  const int P = split_parts(m, n);
+  return P > 1 ? (size_t)P * (size_t)m * sizeof(ScanState) : 0;
+}
+
+hipError_t launch_ray_scan(const RayScanArgs &a, void *split, size_t split_bytes, hipStream_t s) {
   if (a.m <= 0) return hipSuccess;
   const int64_t grid64 = (a.m + TILE - 1) / TILE;
   if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)grid64), blk(TILE);
+  const int P = split_parts(a.m, a.n);
+  if (P > 1 && split && split_bytes >= (size_t)P * (size_t)a.m * sizeof(ScanState)) {
+    const int64_t chunk = ((a.n + P - 1) / P + TILE - 1) / TILE * TILE;
+    const int parts = (int)((a.n + chunk - 1) / chunk);
+    ScanState *st = static_cast<ScanState *>(split);
+    dim3 gsplit((unsigned)grid64, (unsigned)parts);
+#define VG_SPLIT(DKV)                                                                       \
+  do {                                                                                      \
+    hipLaunchKernelGGL(ray_scan_part_kernel<DKV>, gsplit, blk, 0, s, a, chunk, st);         \
+    hipLaunchKernelGGL(ray_merge_kernel<DKV>, grid, blk, 0, s, a, parts, (const ScanState *)st); \
+  } while (0)
+    if (a.d <= 4)
+      VG_SPLIT(4);
+    else if (a.d <= 8)
+      VG_SPLIT(8);
+    else if (a.d <= 12)
+      VG_SPLIT(12);
+    else
+      VG_SPLIT(16);
+#undef VG_SPLIT
+    return hipGetLastError();
+  }
   if (a.d <= 4)
     hipLaunchKernelGGL(ray_scan_kernel<4>, grid, blk, 0, s, a);
   else if (a.d <= 8)

@@ -141,14 +141,27 @@ __device__ __forceinline__ void eval_node(const NT *xr, int stride, int d, int32
   }
 }
 
+// The node rows a recheck reads: FP32 rows, or the exact FP64 ones.
+template <typename NT>
+__device__ __forceinline__ const NT *node_rows(const RecheckArgs &a);
+template <>
+__device__ __forceinline__ const float *node_rows<float>(const RecheckArgs &a) {
+  return a.nodes;
+}
+template <>
+__device__ __forceinline__ const double *node_rows<double>(const RecheckArgs &a) {
+  return a.nodes64;
+}
+
 // DK: the dimension rounded up to 4, 8, 12 or 16 (loops guard k < d, so the
 // order of every FP64 sum is the plain k = 0 .. d-1 order).  CELLS: the
 // Monte-Carlo rays of a cell, x = g = x_i and eta = {i}; there the numerator
 // (r - g).((r - x) + (g - x)) is exactly sum_k (r_k - g_k)^2, since
 // (r_k - g_k) + 0 = r_k - g_k.
-template <int DK, bool CELLS>
+template <int DK, bool CELLS, typename NT = float>
 __global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
-  __shared__ float tile[DK * NT1];  // [k][node]: lane-contiguous reads
+  __shared__ NT tile[DK * NT1];  // [k][node]: lane-contiguous reads
+  const NT *rows = node_rows<NT>(a);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int d = a.d;
   const int64_t n = a.n;
@@ -188,7 +201,7 @@ __global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
           if (e < n_excl) ex[e] = a.excl[ray * n_excl + e];
       }
 #pragma unroll
-      for (int k = 0; k < DK; ++k) g[k] = k < d ? (double)a.nodes[(int64_t)gi * d + k] : 0.0;
+      for (int k = 0; k < DK; ++k) g[k] = k < d ? (double)rows[(int64_t)gi * d + k] : 0.0;
     }
     if (CELLS) {
 #pragma unroll
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
       const int cntn = (int)((n - base) < NT1 ? (n - base) : NT1);
       __syncthreads();
       if (tid < cntn) {
-        const float *src = a.nodes + (base + tid) * d;
+        const NT *src = rows + (base + tid) * d;
 #pragma unroll
         for (int k = 0; k < DK; ++k)
           if (k < d) tile[k * NT1 + tid] = src[k];
@@ -234,18 +247,6 @@ __global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
       if (lane == 0) finish_ray<DK>(a, ray, d, clip, x, u, tp);
     }
   }
-}
-
-// The node rows a recheck reads: FP32 rows, or the exact FP64 ones.
-template <typename NT>
-__device__ __forceinline__ const NT *node_rows(const RecheckArgs &a);
-template <>
-__device__ __forceinline__ const float *node_rows<float>(const RecheckArgs &a) {
-  return a.nodes;
-}
-template <>
-__device__ __forceinline__ const double *node_rows<double>(const RecheckArgs &a) {
-  return a.nodes64;
 }
 
 // Large clouds: one queued ray per workgroup, its 512 threads striding over
@@ -552,12 +553,12 @@ hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
   // large clouds: a workgroup per queued ray (the queue is often short there)
   const bool wide = a.n >= (int64_t(1) << 18);
   const dim3 gridw(max_grid);
-  if (a.nodes64) {  // exact FP64 rows: general rays, d <= 8
+  if (a.nodes64) {  // exact FP64 rows: general rays, d <= 8, 8 rays per LDS tile
     if (cells || a.d > 8) return hipErrorInvalidValue;
     if (a.d <= 4)
-      hipLaunchKernelGGL((recheck_wide_kernel<4, false, double>), gridw, blk, 0, s, a);
+      hipLaunchKernelGGL((recheck_kernel<4, false, double>), grid, blk, 0, s, a);
     else
-      hipLaunchKernelGGL((recheck_wide_kernel<8, false, double>), gridw, blk, 0, s, a);
+      hipLaunchKernelGGL((recheck_kernel<8, false, double>), grid, blk, 0, s, a);
     return hipGetLastError();
   }
 #define VG_RECHECK(DKV)                                                            \
