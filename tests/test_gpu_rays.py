@@ -91,3 +91,29 @@ def test_argument_errors(vg):
         vg.raycast_cells(torch.rand(10, 3), torch.rand(10, 4, 3))  # CPU tensors
     with pytest.raises(ValueError):
         vg.raycast_cells(torch.rand(10, 3, device=dev), torch.rand(9, 4, 3, device=dev))
+
+
+@pytest.mark.parametrize("d", [3, 7])
+def test_node_split_scan_matches_whole_range_scan(vg, d):
+    """A call with few rays splits the nodes over workgroups and merges the
+    partial top-2 states; the same rays inside one call large enough not to
+    split give the same argmin and t*.  (Which rays the certificate queues
+    may differ where the runner-up's t sits within an ulp of the division-free
+    filter, so t* is compared to FP32 rounding and the status bits on all but
+    a few rays.)"""
+    n, m = 6000, 300_000
+    rng = np.random.default_rng(60 + d)
+    X = torch.from_numpy(W.uniform_cloud(n, d, seed=61)).cuda()
+    g = torch.from_numpy(rng.integers(n, size=m).astype(np.int32)).cuda()
+    U = rng.standard_normal((m, d))
+    U = torch.from_numpy((U / np.linalg.norm(U, axis=1, keepdims=True)).astype(np.float32)).cuda()
+    O = X[g.long()] + 0.01 * torch.rand(m, d, device="cuda")
+    ex = g[:, None].contiguous()
+    t_all, i_all, s_all = vg.raycast(X, O, U, g, ex, clip=True)
+    for lo in (0, 1000, 150_000, m - 700):
+        hi = min(m, lo + 700)
+        t, i, s = vg.raycast(X, O[lo:hi].contiguous(), U[lo:hi].contiguous(), g[lo:hi].contiguous(),
+                             ex[lo:hi].contiguous(), clip=True)
+        assert torch.equal(i, i_all[lo:hi])
+        assert torch.allclose(t, t_all[lo:hi], rtol=3e-7, atol=0)
+        assert int((s != s_all[lo:hi]).sum()) <= 2
