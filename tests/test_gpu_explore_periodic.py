@@ -132,3 +132,12 @@ def test_periodic_explore_rejects_nodes_outside_the_unit_cube(vg):
     X[7, 1] = 1.0
     with pytest.raises(vg.VGError):
         _explore(vg, X)
+
+
+def test_periodic_explore_reports_balls_of_radius_half_or_more(vg):
+    """Three nodes in 3-D: vertex balls reach radius 1/2, which the key codes
+    cannot describe; the search widens its layer to w = 1 and then reports
+    it (the oracle fails the same way)."""
+    X = W.uniform_cloud(3, 3, seed=0)
+    with pytest.raises(vg.VGError, match="radius|draws"):
+        _explore(vg, X)
