@@ -185,13 +185,15 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   if (nodes64 && incircle) return fail(ctx, VG_EUNSUPPORTED, "exact FP64 rows need the dense scan");
   const size_t grid_bytes = incircle ? incircle_rays_scratch_bytes(n, d) : 0;
   const size_t split_bytes = incircle ? 0 : ray_scan_split_bytes(m, n);
-  size_t need = Carver::need({(size_t)m * 8, grid_bytes, split_bytes});
+  const size_t parts_bytes = recheck_split_reserve(m, n);
+  size_t need = Carver::need({(size_t)m * 8, grid_bytes, split_bytes, parts_bytes});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = cv.take<int64_t>(m);
   void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
   void *split = split_bytes ? cv.take<char>(split_bytes) : nullptr;
+  void *parts = parts_bytes ? cv.take<char>(parts_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
   RayScanArgs a{};
@@ -240,7 +242,13 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   r.tie_counter = ctx->counters + CNT_FP64_TIE;
   r.t64_out = t64;
   r.nodes64 = nodes64;
-  e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
+  // the queue length, read here (callers of this path synchronise anyway),
+  // sizes a split recheck over many nodes
+  uint32_t queued = 0;
+  VG_HIP(ctx, hipMemcpyAsync(&queued, ctx->counters + CNT_FLAGGED, 4, hipMemcpyDeviceToHost, ctx->stream));
+  VG_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (queued > 0 && !launch_recheck_split(r, queued, parts, parts_bytes, ctx->stream, e))
+    e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
   ctx->last_rays = m;
   ctx->last_tau = kTauRays;

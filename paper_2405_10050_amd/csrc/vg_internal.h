@@ -197,6 +197,13 @@ hipError_t launch_recheck_rays_batched(const RayBatchProblem *probs_dev, const u
                                        const int64_t *flag_list, uint32_t *tie_counter, int grid,
                                        hipStream_t s);
 hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s);
+// General rays with a known queue length cnt (host): where one workgroup
+// per queued ray would stream many nodes, split each ray's nodes over
+// workgroups and merge.  Returns false (nothing launched) when the split does
+// not apply; parts: device scratch of recheck_split_reserve(m, n) bytes.
+size_t recheck_split_reserve(int64_t m, int64_t n);
+bool launch_recheck_split(const RecheckArgs &a, uint32_t cnt, void *parts, size_t parts_bytes, hipStream_t s,
+                          hipError_t &err);
 hipError_t launch_accum(const AccumArgs &a, hipStream_t s);
 // Sample points of Algorithm 3 per ray: the hit point x_i + l u, then the m
 // interior points x_i + t_s l u.  points [n][R][m+1][d].

@@ -535,6 +535,99 @@ __global__ __launch_bounds__(NT) void recheck_rays_batched_kernel(const RayBatch
   }
 }
 
+// Few queued general rays over many nodes (the caller knows the queue length
+// cnt): workgroup (x, y) takes queued rays x, x + gridDim.x, ... over the
+// nodes [y chunk, (y+1) chunk), with the wide kernel's striding and merges,
+// and stores the part's top-2 in parts[y][f]; recheck_fold_kernel merges the
+// parts of each ray (the top-2 does not depend on the order of the merges,
+// so the results are the wide kernel's) and finishes it.
+template <int DK, typename NT = float>
+__global__ __launch_bounds__(NT1) void recheck_part_kernel(RecheckArgs a, int64_t chunk, uint32_t cnt,
+                                                           Top2 *__restrict__ parts) {
+  __shared__ double st1[WAVES1], st2[WAVES1];
+  __shared__ int32_t si1[WAVES1];
+  const NT *rows = node_rows<NT>(a);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int d = a.d;
+  const int64_t lo = (int64_t)blockIdx.y * chunk;
+  const int64_t hi = lo + chunk < a.n ? lo + chunk : a.n;
+  for (uint32_t f = blockIdx.x; f < cnt; f += gridDim.x) {
+    const int64_t ray = a.flag_list[f];
+    const int32_t gi = a.gen[ray];
+    const int n_excl = a.n_excl;
+    double x[DK], u[DK], g[DK];
+    int32_t ex[VG_MAX_DIM];
+#pragma unroll
+    for (int e = 0; e < VG_MAX_DIM; ++e) ex[e] = e < n_excl ? a.excl[ray * n_excl + e] : -1;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      x[k] = k < d ? (a.mode == RAYS_F64 ? a.o64[ray * d + k] : (double)a.o32[ray * d + k]) : 0.0;
+      u[k] = k < d ? (a.mode == RAYS_F64 ? a.u64[ray * d + k] : (double)a.u32[ray * d + k]) : 0.0;
+      g[k] = k < d ? (double)rows[(int64_t)gi * d + k] : 0.0;
+    }
+    double gx[DK];
+#pragma unroll
+    for (int k = 0; k < DK; ++k) gx[k] = g[k] - x[k];
+    Top2 tp{__builtin_inf(), __builtin_inf(), -1};
+    for (int64_t r = lo + tid; r < hi; r += NT1) {
+      bool skip = false;
+#pragma unroll
+      for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
+      if (!skip) eval_node<DK, false>(rows + r * d, 1, d, (int32_t)r, x, u, g, gx, tp);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      Top2 o;
+      o.t1 = __shfl_xor(tp.t1, off);
+      o.t2 = __shfl_xor(tp.t2, off);
+      o.i1 = __shfl_xor(tp.i1, off);
+      tp = merge(tp, o);
+    }
+    __syncthreads();  // the previous ray's merge has read the LDS slots
+    if (lane == 0) {
+      st1[w] = tp.t1;
+      st2[w] = tp.t2;
+      si1[w] = tp.i1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Top2 all{st1[0], st2[0], si1[0]};
+      for (int q = 1; q < WAVES1; ++q) all = merge(all, Top2{st1[q], st2[q], si1[q]});
+      parts[(int64_t)blockIdx.y * cnt + f] = all;
+    }
+  }
+}
+
+template <int DK>
+__global__ __launch_bounds__(256) void recheck_fold_kernel(RecheckArgs a, int P, uint32_t cnt,
+                                                           const Top2 *__restrict__ parts) {
+  const uint32_t f = blockIdx.x * 256u + threadIdx.x;
+  if (f >= cnt) return;
+  const int64_t ray = a.flag_list[f];
+  const int d = a.d;
+  double x[DK], u[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    x[k] = k < d ? (a.mode == RAYS_F64 ? a.o64[ray * d + k] : (double)a.o32[ray * d + k]) : 0.0;
+    u[k] = k < d ? (a.mode == RAYS_F64 ? a.u64[ray * d + k] : (double)a.u32[ray * d + k]) : 0.0;
+  }
+  Top2 tp = parts[f];
+  for (int p = 1; p < P; ++p) tp = merge(tp, parts[(int64_t)p * cnt + f]);
+  finish_ray<DK>(a, ray, d, a.clip, x, u, tp);
+}
+
+// Parts of the split recheck of cnt queued general rays over n nodes (1: no
+// split): only where one workgroup per ray would stream many nodes, and
+// P cnt <= kSplitRecheckEntries.
+constexpr int64_t kSplitRecheckEntries = int64_t(1) << 20;
+int split_recheck_parts(uint32_t cnt, int64_t n) {
+  if (cnt == 0 || n < (int64_t(1) << 18)) return 1;
+  int64_t P = 8192 / cnt;
+  if (P > 64) P = 64;
+  if (P > n / 4096) P = n / 4096;
+  if (P > kSplitRecheckEntries / cnt) P = kSplitRecheckEntries / cnt;
+  return P > 1 ? (int)P : 1;
+}
+
 }  // namespace
 
 hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t *counters,
@@ -544,6 +637,48 @@ hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t 
   hipLaunchKernelGGL(recheck_batched_kernel, dim3(grid), dim3(NT), 0, s, probs_dev, counters,
                      flag_list, tie_counter);
   return hipGetLastError();
+}
+
+size_t recheck_split_reserve(int64_t m, int64_t n) {
+  if (n < (int64_t(1) << 18)) return 0;
+  const int64_t e = m * 64 < kSplitRecheckEntries ? m * 64 : kSplitRecheckEntries;
+  return (size_t)e * sizeof(Top2);
+}
+
+bool launch_recheck_split(const RecheckArgs &a, uint32_t cnt, void *parts, size_t parts_bytes, hipStream_t s,
+                          hipError_t &err) {
+  err = hipSuccess;
+  const int P = split_recheck_parts(cnt, a.n);
+  if (P <= 1 || a.mode == RAYS_CELLS || (a.nodes64 && a.d > 8) || !parts ||
+      parts_bytes < (size_t)P * cnt * sizeof(Top2))
+    return false;
+  const int64_t chunk = ((a.n + P - 1) / P + NT1 - 1) / NT1 * NT1;
+  const int parts_n = (int)((a.n + chunk - 1) / chunk);
+  const unsigned gx = cnt < 8192u / (unsigned)parts_n ? cnt : 8192u / (unsigned)parts_n;
+  const dim3 grid(gx, (unsigned)parts_n), blk(NT1), gfold((cnt + 255) / 256), bfold(256);
+  Top2 *pt = static_cast<Top2 *>(parts);
+#define VG_SPLIT_RECHECK(DKV, NTV)                                                                  \
+  do {                                                                                              \
+    hipLaunchKernelGGL((recheck_part_kernel<DKV, NTV>), grid, blk, 0, s, a, chunk, cnt, pt);         \
+    hipLaunchKernelGGL(recheck_fold_kernel<DKV>, gfold, bfold, 0, s, a, parts_n, cnt, (const Top2 *)pt); \
+  } while (0)
+  if (a.nodes64) {
+    if (a.d <= 4)
+      VG_SPLIT_RECHECK(4, double);
+    else
+      VG_SPLIT_RECHECK(8, double);
+  } else if (a.d <= 4) {
+    VG_SPLIT_RECHECK(4, float);
+  } else if (a.d <= 8) {
+    VG_SPLIT_RECHECK(8, float);
+  } else if (a.d <= 12) {
+    VG_SPLIT_RECHECK(12, float);
+  } else {
+    VG_SPLIT_RECHECK(16, float);
+  }
+#undef VG_SPLIT_RECHECK
+  err = hipGetLastError();
+  return true;
 }
 
 hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {

@@ -81,3 +81,20 @@ def test_explore_d6_n10000_full_size_properties(vg):
         r2 = d2[sig[v]]
         assert np.allclose(r2, r2[0], rtol=1e-7)
         assert d2.min() >= r2[0] * (1 - 1e-9)
+
+
+@pytest.mark.parametrize("incircle", [False, True])
+def test_explore_d2_n300000_is_qhulls_delaunay(vg, incircle):
+    """At N = 3e5 (the FP64 recheck then splits each queued ray's nodes over
+    workgroups): the vertex keys are exactly qhull's Delaunay triangles, and
+    the unbounded edges its hull edges."""
+    from scipy.spatial import Delaunay
+
+    n, d = 300_000, 2
+    X = W.uniform_cloud(n, d, seed=0)
+    got = vg.explore(torch.from_numpy(X).cuda(), W.descent_draws(d), incircle=incircle, heuristic=incircle)
+    tri = Delaunay(X.astype(np.float64))
+    a = oracle.sorted_rows(got["sigma"])
+    b = oracle.sorted_rows(np.sort(tri.simplices.astype(np.int32), axis=1))
+    assert a.shape == b.shape and np.array_equal(a, b)
+    assert got["b_sigma"].shape[0] == tri.convex_hull.shape[0]
