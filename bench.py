@@ -343,7 +343,8 @@ def bench_explore_incircle(args):
     import paper_2405_10050_amd as vg
     import workloads as W
 
-    d, n = (3, 100_000) if args.workload == "explore_incircle_d3_n100000" else (2, 300_000)
+    d, n = {"explore_incircle_d3_n100000": (3, 100_000), "explore_incircle_d3_n1000000": (3, 1_000_000),
+            "explore_incircle_d2_n300000": (2, 300_000)}[args.workload]
     print(f"[bench] explore d={d} N={n} with Algorithm 1 (warm-up, then timed)", file=sys.stderr, flush=True)
     X = torch.from_numpy(W.uniform_cloud(n, d, seed=0)).cuda()
     draws = W.descent_draws(d)
@@ -466,7 +467,7 @@ def main():
                              "nbr_d6_n10000", "incircle_d3_n1000000", "incircle_d4_n50000",
                              "clipped_d2_n1000", "clipped_d6_n10000", "hmc_d5_n10000",
                              "explore_incircle_d3_n100000", "explore_incircle_d2_n300000",
-                             "periodic_d2to6"])
+                             "explore_incircle_d3_n1000000", "periodic_d2to6"])
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--rays", type=int, default=1024)
     ap.add_argument("--cpu-cells", type=int, default=256, help="oracle sample size (0: skip)")
@@ -496,7 +497,8 @@ def main():
                  "incircle_d3_n1000000": bench_incircle, "incircle_d4_n50000": bench_incircle,
                  "clipped_d2_n1000": bench_explore, "clipped_d6_n10000": bench_explore,
                  "hmc_d5_n10000": bench_hmc, "explore_incircle_d3_n100000": bench_explore_incircle,
-                 "explore_incircle_d2_n300000": bench_explore_incircle, "periodic_d2to6": bench_periodic}
+                 "explore_incircle_d2_n300000": bench_explore_incircle,
+                 "explore_incircle_d3_n1000000": bench_explore_incircle, "periodic_d2to6": bench_periodic}
         print(json.dumps(other[args.workload](args)), flush=True)
         return
 

@@ -64,10 +64,14 @@ constexpr int kMaxIter = 64;
 // goes to the FP64 recheck over all nodes.  Where a full sweep costs at most
 // kFullSweep offsets (every grid of N = 1000 nodes in d = 2..5) the budget
 // is that sweep, so no query gives up; on larger grids it is kRingBudget,
-// about twelve times a local query in 3-D, so that no ray holds up its
-// breadth-first level for long.
+// about twelve times a local query in 3-D, for the Monte-Carlo rays, and
+// kRayRingBudget for general rays: a breadth-first level of the search waits
+// for its slowest ray, and the rays near the hull of the unbounded diagram,
+// which find no eligible node, would each walk the whole budget; the FP64
+// recheck settles them faster.
 constexpr int kFullSweep = 1 << 15;
 constexpr int kRingBudget = 1 << 12;
+constexpr int kRayRingBudget = 1 << 9;
 constexpr int32_t kGaveUp = -2;
 
 // Cell of every node; a node outside [0,1]^d (clamped into a boundary cell,
@@ -923,7 +927,8 @@ size_t grid_bytes(int64_t n, int d) {
 }
 
 // Counting sort of the nodes into the grid's cells (grid_bytes of scratch).
-hipError_t build_grid(const float *nodes, int64_t n, int d, Carve &cv, GridView &g, hipStream_t s) {
+hipError_t build_grid(const float *nodes, int64_t n, int d, int large_budget, Carve &cv, GridView &g,
+                      hipStream_t s) {
   const int G = incircle_grid_size(n, d);
   int64_t cells = 1;
   for (int k = 0; k < d; ++k) cells *= G;
@@ -955,7 +960,7 @@ hipError_t build_grid(const float *nodes, int64_t n, int d, Carve &cv, GridView 
   // the ring loop enumerates
   double sweep = 0.0;
   for (int rho = 0; rho < G && sweep <= (double)kFullSweep; ++rho) sweep += std::pow(2.0 * rho + 1.0, d);
-  const int budget = sweep <= (double)kFullSweep ? (int)sweep : kRingBudget;
+  const int budget = sweep <= (double)kFullSweep ? (int)sweep : large_budget;
   g = GridView{Xs, ids, start, G, 1.f / (float)G, outside, budget};
   return e;
 }
@@ -977,7 +982,7 @@ hipError_t launch_incircle_rays(const RayScanArgs &a, void *scratch, int heurist
   if (a.m <= 0) return hipSuccess;
   Carve cv{static_cast<char *>(scratch)};
   GridView g;
-  hipError_t e = build_grid(a.nodes, a.n, a.d, cv, g, s);
+  hipError_t e = build_grid(a.nodes, a.n, a.d, kRayRingBudget, cv, g, s);
   if (e != hipSuccess) return e;
   const dim3 grid(blocks_of(a.m)), blk(NT);
   if (a.d <= 2)
@@ -999,7 +1004,7 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   if (rays >= (int64_t(1) << 32)) return hipErrorInvalidValue;  // 32-bit queue and flag counters
   Carve cv{static_cast<char *>(scratch)};
   GridView g;
-  hipError_t e = build_grid(a.nodes, n, d, cv, g, s);
+  hipError_t e = build_grid(a.nodes, n, d, kRingBudget, cv, g, s);
   if (e != hipSuccess) return e;
   const size_t kn = (size_t)knn_count(d);
   KnnList kl;
