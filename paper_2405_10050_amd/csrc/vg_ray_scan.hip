@@ -221,11 +221,18 @@ __device__ __forceinline__ void ray_finish(const RayScanArgs &a, int64_t ray, co
   const float t1 = S.t1, t2 = S.t2, den1 = S.den1, den2 = S.den2, gmin = S.gmin;
   const int32_t i1 = S.i1;
 
-  // FP32 error bound of t' = num/den for a candidate (units of 2t): num and
-  // den are sums of d rounded products of differences, |r - x|^2 = t' den +
-  // rho^2 and |r - g| <= |r - x| + rho; an origin rounded from FP64 moves num
-  // by up to 2 |r - g| |dx| and a rounded direction moves den by |r - g| |du|.
-  const float kap = (8.f * (float)(d + 2)) * 0x1p-24f;
+  // FP32 error bound of t' = num/den for a candidate (units of 2t), u = 2^-24:
+  // num = sum_k a_k b_k with a_k = fl(r_k - g_k) (relative error u) and
+  // b_k = fl(fl(r_k - x_k) + fl(g_k - x_k)) (off by at most 3u c_k, where
+  // c_k = |r_k - x_k| + |g_k - x_k| and |c| <= |r - x| + rho), summed by a
+  // chain of d FMAs (gamma_d sum |a_k b_k|): |dnum| <= (d + 4) u |r - g|
+  // (|r - x| + rho); den = sum_k u_k a_k likewise: |dden| <= (d + 1) u |r - g|.
+  // With rg = |r - x| + rho >= |r - g| (|r - x|^2 = t' den + rho^2), both fit
+  // under kap rg^2 and kap rg for kap = 2 (d + 4) u, twice the first-order
+  // bound (which also covers the rounding of the division).  An origin
+  // rounded from FP64 moves num by up to 2 |r - g| |dx| and a rounded
+  // direction moves den by |r - g| |du|.
+  const float kap = (2.f * (float)(d + 4)) * 0x1p-24f;
   float xn2 = 0.f;
 #pragma unroll
   for (int k = 0; k < DK; ++k) xn2 = __builtin_fmaf(x[k], x[k], xn2);
