@@ -158,8 +158,10 @@ __device__ __forceinline__ const double *node_rows<double>(const RecheckArgs &a)
 // Monte-Carlo rays of a cell, x = g = x_i and eta = {i}; there the numerator
 // (r - g).((r - x) + (g - x)) is exactly sum_k (r_k - g_k)^2, since
 // (r_k - g_k) + 0 = r_k - g_k.
+// Up to d = 8 the registers fit four waves per SIMD (two workgroups per CU),
+// which hides the latency of the dependent FP64 sums; wider rays would spill.
 template <int DK, bool CELLS, typename NT = float>
-__global__ __launch_bounds__(NT1) void recheck_kernel(RecheckArgs a) {
+__global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckArgs a) {
   __shared__ NT tile[DK * NT1];  // [k][node]: lane-contiguous reads
   const NT *rows = node_rows<NT>(a);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
