@@ -102,6 +102,66 @@ struct Explorer {
   }
 };
 
+// The scanned images of the periodic search: the images x_i + k,
+// k in {-1,0,1}^d, inside [-w, 1+w]^d, as FP32 rows with the k = 0 images
+// first (row i is node i), their exact FP64 points, the code of each row and
+// the row of each code (-1 outside the layer).
+struct ImageLayer {
+  int d = 0;
+  int32_t S = 0;
+  int64_t n = 0;
+  const float *nodes = nullptr;          // device
+  const std::vector<float> *xh = nullptr;  // host copy of the nodes
+  hipStream_t s{};
+  double w = 0.0;
+  std::vector<int32_t> tkey;
+  DevBuf scan, scan64, tkey_d, tix_d;
+
+  // (Re)builds the layer for w_new; a HIP error code or hipSuccess.
+  hipError_t build(double w_new) {
+    w = w_new;
+    const int32_t centre = (S - 1) / 2;
+    std::vector<float> rows;
+    std::vector<double> rows64;
+    std::vector<int32_t> tix((size_t)n * S, -1);
+    tkey.clear();
+    auto add = [&](int64_t i, int32_t c) {
+      double y[VG_MAX_DIM];
+      for (int k = 0; k < d; ++k) {
+        y[k] = (double)(*xh)[(size_t)i * d + k] + (double)(code_digit(c, k) - 1);
+        if (!(y[k] >= -w && y[k] <= 1.0 + w)) return;
+      }
+      tix[(size_t)i * S + c] = (int32_t)tkey.size();
+      tkey.push_back((int32_t)(i * S + c));
+      for (int k = 0; k < d; ++k) {
+        rows64.push_back(y[k]);
+        rows.push_back((float)y[k]);
+      }
+    };
+    for (int64_t i = 0; i < n; ++i) add(i, centre);
+    for (int32_t c = 0; c < S; ++c)
+      if (c != centre)
+        for (int64_t i = 0; i < n; ++i) add(i, c);
+    hipError_t e = scan.reserve(sizeof(float) * rows.size(), false, s);
+    if (e == hipSuccess) e = scan64.reserve(sizeof(double) * rows64.size(), false, s);
+    if (e == hipSuccess) e = tkey_d.reserve(sizeof(int32_t) * tkey.size(), false, s);
+    if (e == hipSuccess) e = tix_d.reserve(sizeof(int32_t) * tix.size(), false, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(scan.p, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(scan64.p, rows64.data(), sizeof(double) * rows64.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tkey_d.p, tkey.data(), sizeof(int32_t) * tkey.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tix_d.p, tix.data(), sizeof(int32_t) * tix.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && std::getenv("VG_VERBOSE")) {
+      std::fprintf(stderr, "[explore] periodic image layer w = %.4g: %zu rows (%.2f per node)\n", w, tkey.size(),
+                   (double)tkey.size() / (double)n);
+      std::fflush(stderr);
+    }
+    return e;
+  }
+};
+
 // What one search runs over.  Rays are cast over `scan` (n_scan rows): the
 // nodes, or on the periodic diagram the images of the scanned layer.
 struct Setup {
@@ -119,11 +179,30 @@ struct Setup {
   Periodic per;
   const std::vector<int32_t> *tkey_h = nullptr;  // periodic: code of each scanned image
   const std::vector<float> *xh = nullptr;        // periodic: the nodes, host copy
+  ImageLayer *layer = nullptr;                   // periodic: the layer, widened in place
+
+  // Points the scan fields at the layer's current rows.
+  void use(const ImageLayer &L) {
+    n_scan = (int64_t)L.tkey.size();
+    scan = L.scan.as<const float>();
+    scan64 = L.scan64.as<const double>();
+    // |fl(y) - y| <= 2^-24 |y| per coordinate, |y| <= 1 + w
+    node_err = 0x1p-24f * std::sqrt((float)d) * (float)(1.0 + L.w) * 1.01f;
+    per.S = L.S;
+    per.X = L.nodes;
+    per.tkey = L.tkey_d.as<const int32_t>();
+    per.tix = L.tix_d.as<const int32_t>();
+    per.n_codes = L.n * L.S;
+    per.w = L.w;
+    tkey_h = &L.tkey;
+    xh = L.xh;
+  }
 };
 
-// One search into M.  thin is set when a periodic search met a vertex ball
-// past its image layer (or a key outside the shift range).
-int explore_run(vg_ctx *ctx, const Setup &su, vg_mesh *M, bool &thin) {
+// One search into M.  On the periodic diagram a level whose new vertex balls
+// reach past the image layer is cast again on a layer twice as wide; thin is
+// set when that cannot help (w = 1) or the start vertex or an edge key fails.
+int explore_run(vg_ctx *ctx, Setup &su, vg_mesh *M, bool &thin) {
   const int d = su.d;
   const int64_t n_nodes = su.n_nodes;
   const float *nodes = su.nodes;
@@ -410,7 +489,6 @@ int explore_run(vg_ctx *ctx, const Setup &su, vg_mesh *M, bool &thin) {
       EX_HIP(frontier_items(X.sel.as<int64_t>(), m, lb, d, X.item_v.as<int64_t>(), X.item_o.as<int32_t>(),
                             X.s));
       ExploreRays er{};
-      er.nodes = su.scan;
       er.d = d;
       er.m = m;
       er.keys = X.keys_d.as<int32_t>();
@@ -425,27 +503,42 @@ int explore_run(vg_ctx *ctx, const Setup &su, vg_mesh *M, bool &thin) {
       er.idx = X.idx.as<int32_t>();
       er.new_keys = X.nkeys.as<int32_t>();
       er.new_coords = X.ncoords.as<double>();
-      er.n_nodes = su.n_scan;
       er.face_base = face_base;
-      er.per = su.per;
       er.err = errd;
-      EX_HIP(launch_edge_rays(er, X.s));
-      EX_RC(raycast_f64(ctx, d, su.n_scan, su.scan, m, er.o64, er.u64, er.gen, er.excl, d, clipped ? 1 : 0, false,
-                        X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr, incircle, su.scan64,
-                        su.node_err));
-      M->raycasts += m;
       uint32_t flagged = 0;
-      if (verbose) {
-        EX_HIP(hipMemcpyAsync(&flagged, ctx->counters + CNT_FLAGGED, 4, hipMemcpyDeviceToHost, X.s));
+      for (;;) {
+        er.nodes = su.scan;
+        er.n_nodes = su.n_scan;
+        er.per = su.per;
+        EX_HIP(launch_edge_rays(er, X.s));
+        EX_RC(raycast_f64(ctx, d, su.n_scan, su.scan, m, er.o64, er.u64, er.gen, er.excl, d, clipped ? 1 : 0, false,
+                          X.tb.as<float>(), X.idx.as<int32_t>(), X.st.as<uint8_t>(), nullptr, incircle, su.scan64,
+                          su.node_err));
+        M->raycasts += m;
+        if (verbose) {
+          EX_HIP(hipMemcpyAsync(&flagged, ctx->counters + CNT_FLAGGED, 4, hipMemcpyDeviceToHost, X.s));
+          EX_HIP(hipStreamSynchronize(X.s));
+        }
+        if (incircle) {
+          uint64_t calls = 0;
+          EX_HIP(hipMemcpyAsync(&calls, ctx->counters + CNT_NN_CALLS, 8, hipMemcpyDeviceToHost, X.s));
+          EX_HIP(hipStreamSynchronize(X.s));
+          M->nn_calls += (int64_t)calls;
+        }
+        EX_HIP(launch_new_vertices(er, X.s));
+        if (!periodic) break;
+        // nothing of this level is in the tables yet: if a ball reached past
+        // the layer, widen it and cast the level again
+        uint32_t eh = 0;
+        EX_HIP(hipMemcpyAsync(&eh, errd, sizeof eh, hipMemcpyDeviceToHost, X.s));
         EX_HIP(hipStreamSynchronize(X.s));
+        if (!(eh & (VSET_THIN | VSET_RANGE)) || su.layer->w >= 1.0) break;
+        const uint32_t keep = eh & ~(uint32_t)(VSET_THIN | VSET_RANGE);
+        EX_HIP(hipMemcpyAsync(errd, &keep, sizeof keep, hipMemcpyHostToDevice, X.s));
+        EX_HIP(su.layer->build(std::min(1.0, 2.0 * su.layer->w)));
+        su.use(*su.layer);
+        M->raycasts -= m;
       }
-      if (incircle) {
-        uint64_t calls = 0;
-        EX_HIP(hipMemcpyAsync(&calls, ctx->counters + CNT_NN_CALLS, 8, hipMemcpyDeviceToHost, X.s));
-        EX_HIP(hipStreamSynchronize(X.s));
-        M->nn_calls += (int64_t)calls;
-      }
-      EX_HIP(launch_new_vertices(er, X.s));
       if (validate) {
         // count the edge rays whose new vertex has a node inside its sphere
         EX_HIP(X.viol.reserve(sizeof(double) * m, false, X.s));
@@ -626,90 +719,38 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
       ctx->err = "periodic explore needs nodes in [0,1)^d";
       return VG_EINVAL;
     }
-  const int32_t centre = (S - 1) / 2;
+  ImageLayer layer;
+  layer.d = d;
+  layer.S = S;
+  layer.n = n_nodes;
+  layer.nodes = nodes;
+  layer.xh = &xh;
+  layer.s = ctx->stream;
   double w = std::min(1.0, 3.0 * std::pow((double)n_nodes, -1.0 / d));
   for (;;) {
-    std::vector<float> rows;
-    std::vector<double> rows64;
-    std::vector<int32_t> tkey, tix((size_t)n_nodes * S, -1);
-    rows.reserve(xh.size());
-    rows64.reserve(xh.size());
-    auto add = [&](int64_t i, int32_t c) {
-      for (int k = 0; k < d; ++k) {
-        const double y = (double)xh[(size_t)i * d + k] + (double)(code_digit(c, k) - 1);
-        if (!(y >= -w && y <= 1.0 + w)) return;
-      }
-      tix[(size_t)i * S + c] = (int32_t)tkey.size();
-      tkey.push_back((int32_t)(i * S + c));
-      for (int k = 0; k < d; ++k) {
-        const double y = (double)xh[(size_t)i * d + k] + (double)(code_digit(c, k) - 1);
-        rows64.push_back(y);
-        rows.push_back((float)y);
-      }
-    };
-    for (int64_t i = 0; i < n_nodes; ++i) add(i, centre);  // image i is node i
-    for (int32_t c = 0; c < S; ++c)
-      if (c != centre)
-        for (int64_t i = 0; i < n_nodes; ++i) add(i, c);
-    void *scan_d = nullptr, *scan64_d = nullptr, *tkey_d = nullptr, *tix_d = nullptr;
-    auto release = [&]() {
-      for (void *p : {scan_d, scan64_d, tkey_d, tix_d})
-        if (p) (void)hipFree(p);
-    };
-    if (hipMalloc(&scan_d, sizeof(float) * rows.size()) != hipSuccess ||
-        hipMalloc(&scan64_d, sizeof(double) * rows64.size()) != hipSuccess ||
-        hipMalloc(&tkey_d, sizeof(int32_t) * tkey.size()) != hipSuccess ||
-        hipMalloc(&tix_d, sizeof(int32_t) * tix.size()) != hipSuccess) {
-      release();
-      ctx->err = "periodic image layer allocation failed";
-      return VG_ENOMEM;
+    const hipError_t e = layer.build(w);
+    if (e != hipSuccess) {
+      ctx->err = std::string("periodic image layer: ") + hipGetErrorString(e);
+      return e == hipErrorOutOfMemory ? VG_ENOMEM : VG_EDEVICE;
     }
-    if (hipMemcpyAsync(scan_d, rows.data(), sizeof(float) * rows.size(), hipMemcpyHostToDevice, ctx->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(scan64_d, rows64.data(), sizeof(double) * rows64.size(), hipMemcpyHostToDevice,
-                       ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(tkey_d, tkey.data(), sizeof(int32_t) * tkey.size(), hipMemcpyHostToDevice, ctx->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(tix_d, tix.data(), sizeof(int32_t) * tix.size(), hipMemcpyHostToDevice, ctx->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
-      release();
-      ctx->err = "periodic image layer upload failed";
-      return VG_EDEVICE;
-    }
-    su.n_scan = (int64_t)tkey.size();
-    su.scan = static_cast<const float *>(scan_d);
-    su.scan64 = static_cast<const double *>(scan64_d);
-    // |fl(y) - y| <= 2^-24 |y| per coordinate, |y| <= 1 + w
-    su.node_err = 0x1p-24f * std::sqrt((float)d) * (float)(1.0 + w) * 1.01f;
-    su.per.S = S;
-    su.per.X = nodes;
-    su.per.tkey = static_cast<const int32_t *>(tkey_d);
-    su.per.tix = static_cast<const int32_t *>(tix_d);
-    su.per.n_codes = n_nodes * S;
-    su.per.w = w;
-    su.tkey_h = &tkey;
-    su.xh = &xh;
+    su.use(layer);
+    su.layer = &layer;
     vg_mesh *M = new (std::nothrow) vg_mesh();
-    if (!M) {
-      release();
-      return VG_ENOMEM;
-    }
+    if (!M) return VG_ENOMEM;
     M->d = d;
     bool thin = false;
     const int rc = explore_run(ctx, su, M, thin);
-    release();
     if (rc == VG_OK) {
       *out = M;
       return VG_OK;
     }
     delete M;
     if (!thin) return rc;
-    if (w >= 1.0) {
+    if (layer.w >= 1.0) {
       ctx->err = "periodic explore needs every vertex ball radius below 1/2";
       return VG_EUNSUPPORTED;
     }
-    w = std::min(1.0, 2.0 * w);
+    w = std::min(1.0, 2.0 * layer.w);
   }
 }
 
