@@ -148,11 +148,43 @@ struct GridView {
 // least q's distance to the cube in the others, so the bound adds that
 // distance when q lies outside.  `shift` bounds the distance of q from the
 // exact point (for gap_tol).
+// The eligible nodes of one grid cell into the running nearest two (d1 with
+// node i1, d2); equal distances go to the lower node index.
 template <int DK>
-__device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float (&qr)[DK], const float (&u)[DK],
-                    float T, const int32_t *ex, int n_ex, float limit, float shift, int32_t &i1, float &d1,
-                    float &d2) {
-  int c[DK];
+__device__ __forceinline__ void scan_cell(const GridView &g, int64_t cell, int d, const float (&xg)[DK],
+                                          const float (&qr)[DK], const float (&u)[DK], const int32_t *ex, int n_ex,
+                                          int32_t &i1, float &d1, float &d2) {
+  for (uint32_t p = g.start[cell]; p < g.start[cell + 1]; ++p) {
+    const int32_t node = g.id[p];
+    bool in_eta = false;
+    for (int e = 0; e < n_ex; ++e) in_eta |= ex[e] == node;
+    if (in_eta) continue;
+    const float *xp = g.X + (int64_t)p * d;
+    float den = 0.f, dist = 0.f;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d) {
+        const float ek = xp[k] - xg[k];
+        den = __builtin_fmaf(u[k], ek, den);
+        const float e = qr[k] - ek;
+        dist = __builtin_fmaf(e, e, dist);
+      }
+    }
+    if (!(den > 0.f)) continue;  // skip: not ahead of the ray
+    if (dist < d1 || (dist == d1 && node < i1)) {
+      d2 = d1;
+      d1 = dist;
+      i1 = node;
+    } else if (dist < d2) {
+      d2 = dist;
+    }
+  }
+}
+
+// Query cell of q and its squared distance to the cube (0 inside).
+template <int DK>
+__device__ __forceinline__ float query_cell(const GridView &g, int d, const float (&xg)[DK], const float (&qr)[DK],
+                                            int (&c)[DK]) {
   float out2 = 0.f;
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
@@ -162,7 +194,15 @@ __device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float
     const float o = k < d ? fmaxf(0.f, fmaxf(-qa, qa - 1.f)) : 0.f;
     out2 = __builtin_fmaf(o, o, out2);
   }
-  out2 *= 1.f - 0x1p-20f;
+  return out2 * (1.f - 0x1p-20f);
+}
+
+template <int DK>
+__device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float (&qr)[DK], const float (&u)[DK],
+                    float T, const int32_t *ex, int n_ex, float limit, float shift, int32_t &i1, float &d1,
+                    float &d2) {
+  int c[DK];
+  const float out2 = query_cell<DK>(g, d, xg, qr, c);
   i1 = -1;
   d1 = d2 = __builtin_inff();
   int budget = g.budget;
@@ -194,33 +234,7 @@ __device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float
           cell = cell * g.G + ck;
         }
       }
-      if (on_ring && inside) {
-        for (uint32_t p = g.start[cell]; p < g.start[cell + 1]; ++p) {
-          const int32_t node = g.id[p];
-          bool in_eta = false;
-          for (int e = 0; e < n_ex; ++e) in_eta |= ex[e] == node;
-          if (in_eta) continue;
-          const float *xp = g.X + (int64_t)p * d;
-          float den = 0.f, dist = 0.f;
-#pragma unroll
-          for (int k = 0; k < DK; ++k) {
-            if (k < d) {
-              const float ek = xp[k] - xg[k];
-              den = __builtin_fmaf(u[k], ek, den);
-              const float e = qr[k] - ek;
-              dist = __builtin_fmaf(e, e, dist);
-            }
-          }
-          if (!(den > 0.f)) continue;  // skip: not ahead of the ray
-          if (dist < d1 || (dist == d1 && node < i1)) {
-            d2 = d1;
-            d1 = dist;
-            i1 = node;
-          } else if (dist < d2) {
-            d2 = dist;
-          }
-        }
-      }
+      if (on_ring && inside) scan_cell<DK>(g, cell, d, xg, qr, u, ex, n_ex, i1, d1, d2);
       // next offset
       int k = d - 1;
       while (k >= 0) {
@@ -229,6 +243,86 @@ __device__ void nn2(const GridView &g, int d, const float (&xg)[DK], const float
         --k;
       }
       if (k < 0 || span == 1) break;
+    }
+  }
+}
+
+// nn2 by a group of GL lanes of one wave (aligned, GL dividing 64), all in
+// the same call with the same arguments: the lanes stride over the offsets
+// of each ring, each keeping the nearest two of its own cells, and after
+// every ring their states are merged by shuffles within the group, so every
+// lane holds the same (i1, d1, d2).  The nearest node (lowest
+// index on equal distances) and the second distance do not depend on the
+// order in which cells are visited, and a ring is skipped as a whole when it
+// would overrun the budget (the serial walk gives up inside that ring), so
+// the result is nn2's.
+template <int DK, int GL>
+__device__ void nn2_group(const GridView &g, int d, const float (&xg)[DK], const float (&qr)[DK],
+                          const float (&u)[DK], float T, const int32_t *ex, int n_ex, float limit, float shift,
+                          int lane, int32_t &i1, float &d1, float &d2) {
+  int c[DK];
+  const float out2 = query_cell<DK>(g, d, xg, qr, c);
+  // each lane's own nearest two over the cells it visited (disjoint across
+  // the group); (i1, d1, d2) is their merge after every ring
+  int32_t li1 = -1;
+  float ld1 = __builtin_inff(), ld2 = __builtin_inff();
+  i1 = -1;
+  d1 = d2 = __builtin_inff();
+  int budget = g.budget;
+  for (int rho = 0; rho < g.G; ++rho) {
+    if (rho >= 1) {
+      const float lb = fmaxf(0.f, (float)(rho - 1) * g.h - kRingSlack);
+      const float lb2 = lb * lb + out2;
+      const float ref = fminf(d1, limit);
+      if (lb2 > d2 || lb2 > ref + gap_tol(ref, lb2, shift, T, d)) break;
+    }
+    const int span = 2 * rho + 1;
+    int count = 1;
+    for (int k = 0; k < d; ++k) count *= span;
+    budget -= count;
+    if (budget < 0) {
+      i1 = kGaveUp;
+      return;
+    }
+    for (int idx = lane; idx < count; idx += GL) {
+      bool on_ring = false, inside = true;
+      int64_t cell = 0;
+      int rem = idx;
+      int o[DK];
+#pragma unroll
+      for (int k = DK - 1; k >= 0; --k) {
+        if (k < d) {
+          o[k] = rem % span - rho;
+          rem /= span;
+        } else {
+          o[k] = 0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        if (k < d) {
+          const int ck = c[k] + o[k];
+          on_ring |= (o[k] == rho || o[k] == -rho);
+          inside &= (ck >= 0 && ck < g.G);
+          cell = cell * g.G + ck;
+        }
+      }
+      if (on_ring && inside) scan_cell<DK>(g, cell, d, xg, qr, u, ex, n_ex, li1, ld1, ld2);
+    }
+    i1 = li1;
+    d1 = ld1;
+    d2 = ld2;
+#pragma unroll
+    for (int off = 1; off < GL; off <<= 1) {
+      const float od1 = __shfl_xor(d1, off);
+      const int32_t oi1 = __shfl_xor(i1, off);
+      const float od2 = __shfl_xor(d2, off);
+      const float nd2 = fminf(fminf(d2, od2), fmaxf(d1, od1));
+      if (od1 < d1 || (od1 == d1 && oi1 >= 0 && (i1 < 0 || oi1 < i1))) {
+        d1 = od1;
+        i1 = oi1;
+      }
+      d2 = nd2;
     }
   }
 }
@@ -699,18 +793,23 @@ __global__ __launch_bounds__(NT) void incircle_grid_kernel(CellScanArgs a, GridV
 // rays (gap of the two nearest eligible nodes at r' against their FP32
 // error); uncertain, capped, grazing and no-hit rays go to the FP64 recheck.
 // t* from the origin is then re-evaluated in FP64 from eq. (t).
-template <int DK>
-__device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuristic, int64_t ray,
+// A group of GL lanes runs each ray: they share its queries (nn2_group) and
+// compute everything else alike; lane 0 writes the results.
+template <int DK, int GL>
+__device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuristic, int64_t ray, int lane,
                              uint32_t &calls) {
   const int d = a.d;
   const int32_t gidx = a.gen[ray];
   if (gidx < 0 || gidx >= a.n) {  // invalid generator index: report, skip
-    a.t_out[ray] = __builtin_nanf("");
-    a.idx_out[ray] = -1;
-    a.st_out[ray] = VG_ST_SUSPECT;
+    if (lane == 0) {
+      a.t_out[ray] = __builtin_nanf("");
+      a.idx_out[ray] = -1;
+      a.st_out[ray] = VG_ST_SUSPECT;
+    }
     return;
   }
   if (*g.outside) {  // the grid does not bound every node: settle in FP64
+    if (lane != 0) return;
     if (a.flag_list) {
       const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
       a.flag_list[pos] = ray | a.flag_tag;
@@ -760,7 +859,7 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
   const float shift0 = (2.f * r0n + 4.f * rn) * 0x1p-24f;
   int32_t i1;
   float d1, d2;
-  nn2<DK>(g, d, xg, r, u, rn, ex, a.n_excl, __builtin_inff(), shift0, i1, d1, d2);
+  nn2_group<DK, GL>(g, d, xg, r, u, rn, ex, a.n_excl, __builtin_inff(), shift0, lane, i1, d1, d2);
   ++calls;
   bool flag = a.force_all != 0;
   uint8_t st = 0;
@@ -808,7 +907,7 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
         const float e = rp[q] - ek[q];
         dk = __builtin_fmaf(e, e, dk);
       }
-      nn2<DK>(g, d, xg, rp, u, rpn, ex, a.n_excl, dk, shift, i1, d1, d2);
+      nn2_group<DK, GL>(g, d, xg, rp, u, rpn, ex, a.n_excl, dk, shift, lane, i1, d1, d2);
       ++calls;
       if (i1 == k) break;
       if (i1 < 0) break;  // k itself is eligible, so only through NaN
@@ -866,6 +965,7 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
     t = __builtin_inff();
     flag = true;
   }
+  if (lane != 0) return;
   if (flag && a.flag_list) {
     st |= VG_ST_NEAR_TIE;
     const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
@@ -876,15 +976,23 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
   a.st_out[ray] = st;
 }
 
+// Lanes per general ray: a breadth-first level of the search holds few rays
+// for the GPU, and each query walks grid cells with dependent loads, so
+// eight lanes share every query's rings.
+constexpr int kRayLanes = 8;
+
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_rays_kernel(RayScanArgs a, GridView g, int heuristic,
                                                            unsigned long long *nn_calls) {
   __shared__ unsigned int block_calls[2];
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t ray = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t gt = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t ray = gt / kRayLanes;
+  const int lane = (int)(gt % kRayLanes);
   uint32_t calls = 0;
-  if (ray < a.m) incircle_ray<DK>(a, g, heuristic, ray, calls);
+  if (ray < a.m) incircle_ray<DK, kRayLanes>(a, g, heuristic, ray, lane, calls);
+  if (lane != 0) calls = 0;
   add_calls(block_calls, calls, calls, nn_calls);
 }
 
@@ -984,7 +1092,7 @@ hipError_t launch_incircle_rays(const RayScanArgs &a, void *scratch, int heurist
   GridView g;
   hipError_t e = build_grid(a.nodes, a.n, a.d, kRayRingBudget, cv, g, s);
   if (e != hipSuccess) return e;
-  const dim3 grid(blocks_of(a.m)), blk(NT);
+  const dim3 grid(blocks_of(a.m * kRayLanes)), blk(NT);
   if (a.d <= 2)
     hipLaunchKernelGGL(incircle_rays_kernel<2>, grid, blk, 0, s, a, g, heuristic, nn_calls);
   else if (a.d <= 3)

@@ -95,3 +95,29 @@ def test_incircle_explore_reproduces_table_nncalls(vg, d):
         print(f"  explore d={d} {key}: {per_ray:.3f} queries per ray (Table nncalls {gold[key][a]})",
               flush=True)
         assert per_ray == pytest.approx(gold[key][a], rel=0.10)
+
+
+def test_incircle_rays_on_a_large_grid_match_the_dense_scan_with_few_rechecks(vg):
+    """d=3, N=1e5 (queries walk at most the ring budget, eight lanes per ray):
+    edge rays of the search give the dense scan's argmin, and the certificate
+    from the nearest two eligible nodes queues only a few of them for FP64."""
+    d, n, m = 3, 100_000, 4000
+    X = W.uniform_cloud(n, d, seed=0)
+    mesh = vg.explore(torch.from_numpy(X).cuda(), W.descent_draws(d))
+    rng = np.random.default_rng(7)
+    O, U, E = [], [], []
+    for v in rng.choice(mesh["sigma"].shape[0], m, replace=False):
+        sig = mesh["sigma"][v]
+        o = rng.integers(d + 1)
+        eta = np.delete(sig, o)
+        O.append(mesh["coord"][v])
+        U.append(oracle.search_direction(X, eta, sig[o]))
+        E.append(eta)
+    O, U, E = np.array(O, np.float32), np.array(U, np.float32), np.array(E, np.int32)
+    t, idx, _ = _cast(vg, X, O, U, E, clip=False, incircle=True, heuristic=True)
+    queued = vg.stats()["flagged"]
+    t_d, idx_d, _ = _cast(vg, X, O, U, E, clip=False)
+    print(f"  incircle rays d=3 N=1e5: {queued} of {m} rechecked", flush=True)
+    assert torch.equal(idx, idx_d)
+    assert torch.allclose(t, t_d, rtol=1e-6, atol=0)
+    assert queued <= 0.05 * m
