@@ -141,3 +141,16 @@ def test_periodic_explore_reports_balls_of_radius_half_or_more(vg):
     X = W.uniform_cloud(3, 3, seed=0)
     with pytest.raises(vg.VGError, match="radius|draws"):
         _explore(vg, X)
+
+
+def test_periodic_explore_argument_errors(vg):
+    X = torch.from_numpy(W.uniform_cloud(200, 3, seed=4)).cuda()
+    with pytest.raises(vg.VGError, match="excludes"):
+        vg.explore(X, W.descent_draws(3), clip=True, periodic=True)
+    with pytest.raises(vg.VGError, match="excludes"):
+        vg.explore(X, W.descent_draws(3), incircle=True, periodic=True)
+    with pytest.raises(vg.VGError, match="draws"):
+        vg.explore(X, None, periodic=True)
+    X9 = torch.from_numpy(W.uniform_cloud(50, 9, seed=4)).cuda()
+    with pytest.raises(vg.VGError, match="d <= 8"):
+        vg.explore(X9, W.descent_draws(9), periodic=True)
