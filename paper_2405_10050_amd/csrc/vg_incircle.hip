@@ -72,6 +72,11 @@ constexpr int kMaxIter = 64;
 constexpr int kFullSweep = 1 << 15;
 constexpr int kRingBudget = 1 << 12;
 constexpr int kRayRingBudget = 1 << 9;
+// Lanes sharing one ray's grid queries where rays are few for the GPU (a
+// breadth-first level of the search, the rays the lists could not answer):
+// each query walks grid cells with dependent loads, and eight lanes split
+// its rings.
+constexpr int kRayLanes = 8;
 constexpr int32_t kGaveUp = -2;
 
 // Cell of every node; a node outside [0,1]^d (clamped into a boundary cell,
@@ -327,6 +332,17 @@ __device__ void nn2_group(const GridView &g, int d, const float (&xg)[DK], const
   }
 }
 
+// nn2 by one lane (GL = 1) or by a group of GL lanes.
+template <int DK, int GL>
+__device__ __forceinline__ void nn2_lanes(const GridView &g, int d, const float (&xg)[DK], const float (&qr)[DK],
+                                          const float (&u)[DK], float T, const int32_t *ex, int n_ex, float limit,
+                                          float shift, int lane, int32_t &i1, float &d1, float &d2) {
+  if constexpr (GL == 1)
+    nn2<DK>(g, d, xg, qr, u, T, ex, n_ex, limit, shift, i1, d1, d2);
+  else
+    nn2_group<DK, GL>(g, d, xg, qr, u, T, ex, n_ex, limit, shift, lane, i1, d1, d2);
+}
+
 // Nearest nodes kept per cell (first candidates, and the list that answers
 // most queries by itself).
 template <int DK>
@@ -531,10 +547,11 @@ struct DeferQueue {
 // The RayCast of ray gid.  With GRID false the first candidate comes from
 // the list, and a query the list cannot answer stops the ray: returns true
 // with the current candidate in kdef, having written nothing.  With GRID
-// true the ray resumes from kstart and such queries search the grid.
-template <int DK, bool GRID>
+// true the ray resumes from kstart and such queries search the grid, by a
+// group of GL lanes (all alike; lane 0 writes).
+template <int DK, bool GRID, int GL = 1>
 __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList &kl, int64_t gid,
-                         int32_t kstart, int32_t &kdef, uint32_t &calls, uint32_t &grid_calls) {
+                         int32_t kstart, int32_t &kdef, uint32_t &calls, uint32_t &grid_calls, int lane = 0) {
   constexpr int KN = knn_of<DK>();
   const int d = a.d;
   const int64_t cell = gid / a.R;
@@ -562,6 +579,7 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
   const float *lrel = kl.rel + cell * KN * d;
   const float r2 = kl.r2[cell];
   if (*g.outside) {  // the grid does not bound every node: settle in FP64
+    if (lane != 0) return false;
     if (a.flag_list) {
       const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
       a.flag_list[pos] = gid | a.flag_tag;
@@ -630,7 +648,7 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
       float qr[DK];
 #pragma unroll
       for (int q2 = 0; q2 < DK; ++q2) qr[q2] = tbox * u[q2];
-      nn2<DK>(g, d, xi, qr, u, tbox, &self, 1, di, shift, i1, d1, d2);
+      nn2_lanes<DK, GL>(g, d, xi, qr, u, tbox, &self, 1, di, shift, lane, i1, d1, d2);
       ++grid_calls;
     }
     ++calls;
@@ -680,7 +698,7 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
         float qr[DK];
 #pragma unroll
         for (int q2 = 0; q2 < DK; ++q2) qr[q2] = t * u[q2];
-        nn2<DK>(g, d, xi, qr, u, t, &self, 1, dk, shift, i1, d1, d2);
+        nn2_lanes<DK, GL>(g, d, xi, qr, u, t, &self, 1, dk, shift, lane, i1, d1, d2);
         ++grid_calls;
       }
       ++calls;
@@ -716,6 +734,7 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
     }
   }
   if (j <= -2) t = tbox;
+  if (lane != 0) return false;
   if (flag && a.flag_list) {
     st |= VG_ST_NEAR_TIE;
     const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
@@ -765,7 +784,8 @@ __global__ __launch_bounds__(NT) void incircle_list_kernel(CellScanArgs a, GridV
   add_calls(block_calls, calls, grid_calls, nn_calls);
 }
 
-// Grid pass over the queued rays (grid-stride over the queue's count).
+// Grid pass over the queued rays, kRayLanes lanes per ray (grid-stride over
+// the queue's count).
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_grid_kernel(CellScanArgs a, GridView g, KnnList kl, DeferQueue dq,
                                                            unsigned long long *nn_calls) {
@@ -773,11 +793,15 @@ __global__ __launch_bounds__(NT) void incircle_grid_kernel(CellScanArgs a, GridV
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t cnt = *dq.count;
+  const uint32_t gt = blockIdx.x * NT + threadIdx.x;
+  const int lane = (int)(gt % kRayLanes);
+  const uint32_t stride = gridDim.x * (NT / kRayLanes);
   uint32_t calls = 0, grid_calls = 0;
-  for (uint32_t q = blockIdx.x * NT + threadIdx.x; q < cnt; q += gridDim.x * NT) {
+  for (uint32_t q = gt / kRayLanes; q < cnt; q += stride) {
     int32_t kd;
-    (void)cast_ray<DK, true>(a, g, kl, dq.gid[q], dq.k[q], kd, calls, grid_calls);
+    (void)cast_ray<DK, true, kRayLanes>(a, g, kl, dq.gid[q], dq.k[q], kd, calls, grid_calls, lane);
   }
+  if (lane != 0) calls = grid_calls = 0;
   add_calls(block_calls, calls, grid_calls, nn_calls);
 }
 
@@ -976,11 +1000,6 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
   a.st_out[ray] = st;
 }
 
-// Lanes per general ray: a breadth-first level of the search holds few rays
-// for the GPU, and each query walks grid cells with dependent loads, so
-// eight lanes share every query's rings.
-constexpr int kRayLanes = 8;
-
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_rays_kernel(RayScanArgs a, GridView g, int heuristic,
                                                            unsigned long long *nn_calls) {
@@ -1127,7 +1146,7 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   if (e != hipSuccess) return e;
   const dim3 grid(blocks_of(rays)), blk(NT);
   // the grid pass strides over the queue, whose length only the device knows
-  const dim3 grid2(std::min<unsigned>(blocks_of(rays), 2048u));
+  const dim3 grid2(std::min<unsigned>(blocks_of(rays * kRayLanes), 16384u));
 #define VG_INCIRCLE_LAUNCH(DKV)                                                                          \
   hipLaunchKernelGGL(knn_kernel<DKV>, dim3(blocks_of(n)), blk, 0, s, a.nodes, n, d, g, kl);             \
   hipLaunchKernelGGL(incircle_list_kernel<DKV>, grid, blk, 0, s, a, g, kl, dq, nn_calls);               \
