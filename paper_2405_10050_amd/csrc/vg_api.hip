@@ -116,13 +116,15 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   if (incircle && (bf16 || nbr || d > 6))
     return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs d <= 6, FP32 and no neighbour lists");
   const size_t grid_bytes = incircle ? incircle_scratch_bytes(n, d, R) : 0;
-  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes});
+  const size_t parts_bytes = recheck ? recheck_cells_reserve(m, n) : 0;
+  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes, parts_bytes});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   int64_t *flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
   uint8_t *st = st_out ? st_out : cv.take<uint8_t>(m);
   void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
+  void *parts = parts_bytes ? cv.take<char>(parts_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
 
@@ -165,7 +167,8 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
     r.idx_out = idx_out;
     r.st_out = st;
     r.tie_counter = ctx->counters + CNT_FP64_TIE;
-    e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
+    if (!launch_recheck_cells_split(r, m, parts, parts_bytes, ctx->stream, e))
+      e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
   }
   ctx->last_rays = m;

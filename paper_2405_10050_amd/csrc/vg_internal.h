@@ -197,6 +197,12 @@ hipError_t launch_recheck_rays_batched(const RayBatchProblem *probs_dev, const u
                                        const int64_t *flag_list, uint32_t *tie_counter, int grid,
                                        hipStream_t s);
 hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s);
+// Monte-Carlo rays over n >= 2^18 nodes: the recheck split over node chunks,
+// driven by the queue length on the device (m rays at most); parts scratch
+// of recheck_cells_reserve(m, n) bytes (0: no split, use launch_recheck).
+size_t recheck_cells_reserve(int64_t m, int64_t n);
+bool launch_recheck_cells_split(const RecheckArgs &a, int64_t m, void *parts, size_t parts_bytes, hipStream_t s,
+                                hipError_t &err);
 // General rays with a known queue length cnt (host): where one workgroup
 // per queued ray would stream many nodes, split each ray's nodes over
 // workgroups and merge.  Returns false (nothing launched) when the split does

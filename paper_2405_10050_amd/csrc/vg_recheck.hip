@@ -103,16 +103,16 @@ __device__ __forceinline__ void finish_ray(const RecheckArgs &a, int64_t ray, in
   a.st_out[ray] = st;
 }
 
-// One node r (coordinates xr, as read from memory) against the ray: eq. (t)
-// in FP64 with the factored numerator, into the running top-2.  CELLS: the
-// Monte-Carlo form, x = g.
+// One node r (coordinates v, as read from memory; entries k >= d unused)
+// against the ray: eq. (t) in FP64 with the factored numerator, into the
+// running top-2.  CELLS: the Monte-Carlo form, x = g.
 template <int DK, bool CELLS, typename NT>
-__device__ __forceinline__ void eval_node(const NT *xr, int stride, int d, int32_t r, const double (&x)[DK],
+__device__ __forceinline__ void eval_vals(const NT (&v)[DK], int d, int32_t r, const double (&x)[DK],
                                           const double (&u)[DK], const double (&g)[DK],
                                           const double (&gx)[DK], Top2 &tp) {
   double e[DK];
 #pragma unroll
-  for (int k = 0; k < DK; ++k) e[k] = k < d ? (double)xr[k * stride] - g[k] : 0.0;
+  for (int k = 0; k < DK; ++k) e[k] = k < d ? (double)v[k] - g[k] : 0.0;
   double den = 0.0;
 #pragma unroll
   for (int k = 0; k < DK; ++k)
@@ -127,7 +127,7 @@ __device__ __forceinline__ void eval_node(const NT *xr, int stride, int d, int32
   } else {
 #pragma unroll
     for (int k = 0; k < DK; ++k)
-      if (k < d) num += e[k] * (((double)xr[k * stride] - x[k]) + gx[k]);
+      if (k < d) num += e[k] * (((double)v[k] - x[k]) + gx[k]);
   }
   // cheap filter (relaxed by 1e-12 so no candidate within rounding is lost)
   if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) return;
@@ -139,6 +139,18 @@ __device__ __forceinline__ void eval_node(const NT *xr, int stride, int d, int32
   } else if (t < tp.t2) {
     tp.t2 = t;
   }
+}
+
+// The same for a node row read in place (stride between coordinates); only
+// the d coordinates of the row are read.
+template <int DK, bool CELLS, typename NT>
+__device__ __forceinline__ void eval_node(const NT *xr, int stride, int d, int32_t r, const double (&x)[DK],
+                                          const double (&u)[DK], const double (&g)[DK],
+                                          const double (&gx)[DK], Top2 &tp) {
+  NT v[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) v[k] = k < d ? xr[k * stride] : NT(0);
+  eval_vals<DK, CELLS>(v, d, r, x, u, g, gx, tp);
 }
 
 // The node rows a recheck reads: FP32 rows, or the exact FP64 ones.
@@ -160,14 +172,25 @@ __device__ __forceinline__ const double *node_rows<double>(const RecheckArgs &a)
 // (r_k - g_k) + 0 = r_k - g_k.
 // Up to d = 8 the registers fit four waves per SIMD (two workgroups per CU),
 // which hides the latency of the dependent FP64 sums; wider rays would spill.
-template <int DK, bool CELLS, typename NT = float>
-__global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckArgs a) {
+// PART: the workgroup covers only the nodes [blockIdx.y chunk, (blockIdx.y+1)
+// chunk) of the first `cap` queued rays and stores each ray's top-2 in
+// parts[blockIdx.y][f] for recheck_fold_kernel (the top-2 does not depend on
+// the order of the merges, so the folded result is the whole-range one).
+// EXACT: d == DK, known at compile time.  The tile rows k >= d hold zeros, so
+// a Monte-Carlo node's DK values are read from LDS without a branch.
+template <int DK, bool CELLS, typename NT = float, bool PART = false, bool EXACT = false>
+__global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckArgs a, int64_t chunk = 0,
+                                                                      uint32_t cap = 0,
+                                                                      Top2 *__restrict__ parts = nullptr) {
   __shared__ NT tile[DK * NT1];  // [k][node]: lane-contiguous reads
   const NT *rows = node_rows<NT>(a);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int d = a.d;
-  const int64_t n = a.n;
-  const uint32_t cnt = a.counters[CNT_FLAGGED];
+  const int d = EXACT ? DK : a.d;
+  for (int i = d * NT1 + tid; i < DK * NT1; i += NT1) tile[i] = NT(0);
+  const int64_t lo = PART ? (int64_t)blockIdx.y * chunk : 0;
+  const int64_t n = PART ? (lo + chunk < a.n ? lo + chunk : a.n) : a.n;
+  uint32_t cnt = a.counters[CNT_FLAGGED];
+  if (PART && cnt > cap) cnt = cap;
   for (uint32_t f0 = blockIdx.x * WAVES1; f0 < cnt; f0 += gridDim.x * WAVES1) {
     const uint32_t f = f0 + w;
     const bool live = f < cnt;
@@ -213,7 +236,7 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
 #pragma unroll
     for (int k = 0; k < DK; ++k) gx[k] = g[k] - x[k];
     Top2 tp{__builtin_inf(), __builtin_inf(), -1};
-    for (int64_t base = 0; base < n; base += NT1) {
+    for (int64_t base = lo; base < n; base += NT1) {
       const int cntn = (int)((n - base) < NT1 ? (n - base) : NT1);
       __syncthreads();
       if (tid < cntn) {
@@ -235,7 +258,14 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
           for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
         }
         if (skip) continue;
-        eval_node<DK, CELLS>(tile + q, NT1, d, r, x, u, g, gx, tp);
+        if (CELLS) {  // all DK rows, no branch (general rays: the register budget of d <= 8 is spent)
+          NT v[DK];
+#pragma unroll
+          for (int k = 0; k < DK; ++k) v[k] = tile[k * NT1 + q];
+          eval_vals<DK, CELLS>(v, d, r, x, u, g, gx, tp);
+        } else {
+          eval_node<DK, CELLS>(tile + q, NT1, d, r, x, u, g, gx, tp);
+        }
       }
     }
     if (live) {
@@ -246,7 +276,12 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
         o.i1 = __shfl_xor(tp.i1, off);
         tp = merge(tp, o);
       }
-      if (lane == 0) finish_ray<DK>(a, ray, d, clip, x, u, tp);
+      if (lane == 0) {
+        if (PART)
+          parts[(int64_t)blockIdx.y * cap + f] = tp;
+        else
+          finish_ray<DK>(a, ray, d, clip, x, u, tp);
+      }
     }
   }
 }
@@ -258,7 +293,7 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
 // the merges, so the results are the same.  NT = double reads the exact
 // FP64 rows (general rays whose FP32 rows were rounded).
 template <int DK, bool CELLS, typename NT = float>
-__global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a) {
+__global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a, uint32_t f_begin = 0) {
   const NT *rows = node_rows<NT>(a);
   __shared__ double st1[WAVES1], st2[WAVES1];
   __shared__ int32_t si1[WAVES1];
@@ -266,7 +301,7 @@ __global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a) {
   const int d = a.d;
   const int64_t n = a.n;
   const uint32_t cnt = a.counters[CNT_FLAGGED];
-  for (uint32_t f = blockIdx.x; f < cnt; f += gridDim.x) {
+  for (uint32_t f = f_begin + blockIdx.x; f < cnt; f += gridDim.x) {
     const int64_t ray = a.flag_list[f];
     int n_excl = 0, clip = 0;
     int32_t gi;
@@ -599,22 +634,47 @@ __global__ __launch_bounds__(NT1) void recheck_part_kernel(RecheckArgs a, int64_
   }
 }
 
-template <int DK>
-__global__ __launch_bounds__(256) void recheck_fold_kernel(RecheckArgs a, int P, uint32_t cnt,
+// The parts are stored as parts[p][f], f < stride.  CELLS: the Monte-Carlo
+// rays, whose queue length is read on the device (the first `stride` of it).
+template <int DK, bool CELLS = false>
+__global__ __launch_bounds__(256) void recheck_fold_kernel(RecheckArgs a, int P, uint32_t stride,
                                                            const Top2 *__restrict__ parts) {
   const uint32_t f = blockIdx.x * 256u + threadIdx.x;
+  uint32_t cnt = stride;
+  if (CELLS && a.counters[CNT_FLAGGED] < cnt) cnt = a.counters[CNT_FLAGGED];
   if (f >= cnt) return;
   const int64_t ray = a.flag_list[f];
   const int d = a.d;
   double x[DK], u[DK];
+  if (CELLS) {
+    const int64_t gi = ray / a.R;
 #pragma unroll
-  for (int k = 0; k < DK; ++k) {
-    x[k] = k < d ? (a.mode == RAYS_F64 ? a.o64[ray * d + k] : (double)a.o32[ray * d + k]) : 0.0;
-    u[k] = k < d ? (a.mode == RAYS_F64 ? a.u64[ray * d + k] : (double)a.u32[ray * d + k]) : 0.0;
+    for (int k = 0; k < DK; ++k) {
+      x[k] = k < d ? (double)a.nodes[gi * d + k] : 0.0;
+      u[k] = k < d ? (double)a.dirs[ray * d + k] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      x[k] = k < d ? (a.mode == RAYS_F64 ? a.o64[ray * d + k] : (double)a.o32[ray * d + k]) : 0.0;
+      u[k] = k < d ? (a.mode == RAYS_F64 ? a.u64[ray * d + k] : (double)a.u32[ray * d + k]) : 0.0;
+    }
   }
   Top2 tp = parts[f];
-  for (int p = 1; p < P; ++p) tp = merge(tp, parts[(int64_t)p * cnt + f]);
-  finish_ray<DK>(a, ray, d, a.clip, x, u, tp);
+  for (int p = 1; p < P; ++p) tp = merge(tp, parts[(int64_t)p * stride + f]);
+  finish_ray<DK>(a, ray, d, CELLS ? 1 : a.clip, x, u, tp);
+}
+
+// Monte-Carlo rays over many nodes, split with no host sync: the first
+// kCellsSplitCap queued rays go to the PART form of recheck_kernel (8 rays
+// per workgroup sharing each LDS node tile, over P node chunks) and the fold;
+// the rest of a longer queue to the wide kernel.
+constexpr uint32_t kCellsSplitCap = 8192;
+constexpr int64_t kCellsSplitChunk = 16384;
+int cells_split_parts(int64_t n) {
+  if (n < (int64_t(1) << 18)) return 1;
+  int64_t P = n / kCellsSplitChunk;
+  return P > 64 ? 64 : (int)P;
 }
 
 // Parts of the split recheck of cnt queued general rays over n nodes (1: no
@@ -679,6 +739,51 @@ bool launch_recheck_split(const RecheckArgs &a, uint32_t cnt, void *parts, size_
     VG_SPLIT_RECHECK(16, float);
   }
 #undef VG_SPLIT_RECHECK
+  err = hipGetLastError();
+  return true;
+}
+
+size_t recheck_cells_reserve(int64_t m, int64_t n) {
+  const int P = cells_split_parts(n);
+  if (P <= 1) return 0;
+  const int64_t cap = m < kCellsSplitCap ? m : kCellsSplitCap;
+  return (size_t)P * cap * sizeof(Top2);
+}
+
+bool launch_recheck_cells_split(const RecheckArgs &a, int64_t m, void *parts, size_t parts_bytes, hipStream_t s,
+                                hipError_t &err) {
+  err = hipSuccess;
+  const int P = cells_split_parts(a.n);
+  const uint32_t cap = (uint32_t)(m < kCellsSplitCap ? m : kCellsSplitCap);
+  if (a.mode != RAYS_CELLS || P <= 1 || !parts || parts_bytes < (size_t)P * cap * sizeof(Top2)) return false;
+  const int64_t chunk = ((a.n + P - 1) / P + NT1 - 1) / NT1 * NT1;
+  const int parts_n = (int)((a.n + chunk - 1) / chunk);
+  const unsigned groups = (cap + WAVES1 - 1) / WAVES1;
+  const dim3 grid(groups < 256u ? groups : 256u, (unsigned)parts_n), blk(NT1), gfold((cap + 255) / 256), bfold(256);
+  const int64_t rest = m - (int64_t)cap;
+  const dim3 gridw((unsigned)(rest < 4096 ? rest : 4096));
+  Top2 *pt = static_cast<Top2 *>(parts);
+#define VG_CELLS_SPLIT(DKV, EX, DW)                                                                         \
+  do {                                                                                                      \
+    hipLaunchKernelGGL((recheck_kernel<DKV, true, float, true, EX>), grid, blk, 0, s, a, chunk, cap, pt);    \
+    hipLaunchKernelGGL((recheck_fold_kernel<DW, true>), gfold, bfold, 0, s, a, parts_n, cap, (const Top2 *)pt); \
+    if (rest > 0) hipLaunchKernelGGL((recheck_wide_kernel<DW, true>), gridw, blk, 0, s, a, cap);              \
+  } while (0)
+  switch (a.d) {
+    case 2: VG_CELLS_SPLIT(2, true, 4); break;
+    case 3: VG_CELLS_SPLIT(3, true, 4); break;
+    case 4: VG_CELLS_SPLIT(4, true, 4); break;
+    case 5: VG_CELLS_SPLIT(5, true, 8); break;
+    case 6: VG_CELLS_SPLIT(6, true, 8); break;
+    case 7: VG_CELLS_SPLIT(7, true, 8); break;
+    case 8: VG_CELLS_SPLIT(8, true, 8); break;
+    default:
+      if (a.d <= 12)
+        VG_CELLS_SPLIT(12, false, 12);
+      else
+        VG_CELLS_SPLIT(16, false, 16);
+  }
+#undef VG_CELLS_SPLIT
   err = hipGetLastError();
   return true;
 }

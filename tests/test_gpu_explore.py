@@ -98,3 +98,30 @@ def test_explore_d2_n300000_is_qhulls_delaunay(vg, incircle):
     b = oracle.sorted_rows(np.sort(tri.simplices.astype(np.int32), axis=1))
     assert a.shape == b.shape and np.array_equal(a, b)
     assert got["b_sigma"].shape[0] == tri.convex_hull.shape[0]
+
+
+def test_explore_d6_n10000_equals_the_oracles_full_search(vg):
+    """The d=6, N=10 000 workload at full size against the oracle's own
+    sequential Algorithm 2 (run once by tests/golden/make_explore_d6_n10000.py):
+    the same vertex keys and unbounded edges, compared by SHA-256 of the
+    sorted int32 rows."""
+    import hashlib
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "explore_d6_n10000.json")
+    if not os.path.exists(path):
+        pytest.skip("run tests/golden/make_explore_d6_n10000.py first (about an hour on one core)")
+    gold = json.load(open(path))
+    d, n = 6, 10_000
+    X = W.uniform_cloud(n, d, seed=0)
+    got = vg.explore(torch.from_numpy(X).cuda(), W.descent_draws(d))
+
+    def digest(a):
+        rows = np.ascontiguousarray(oracle.sorted_rows(np.asarray(a, dtype=np.int32)), dtype="<i4")
+        return hashlib.sha256(rows.tobytes()).hexdigest()
+
+    assert got["sigma"].shape[0] == gold["vertices"]
+    assert got["b_sigma"].shape[0] == gold["unbounded_edges"]
+    assert digest(got["sigma"]) == gold["sigma_sha256"]
+    assert digest(np.column_stack([got["b_sigma"], got["b_omit"]])) == gold["unbounded_sha256"]
