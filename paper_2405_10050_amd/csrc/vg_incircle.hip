@@ -491,8 +491,8 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
 }
 
 // Top-2 as nn2, over the cell's list only.
-template <int DK, int KN>
-__device__ void list_nn2(const int32_t *ids, const float *rel, int d, const float (&u)[DK], float t, int32_t &i1,
+template <int DK, int KN, typename IP, typename FP>
+__device__ void list_nn2(IP ids, FP rel, int d, const float (&u)[DK], float t, int32_t &i1,
                          float &d1, float &d2) {
   float qr[DK];
 #pragma unroll
@@ -548,13 +548,16 @@ struct DeferQueue {
 // the list, and a query the list cannot answer stops the ray: returns true
 // with the current candidate in kdef, having written nothing.  With GRID
 // true the ray resumes from kstart and such queries search the grid, by a
-// group of GL lanes (all alike; lane 0 writes).
-template <int DK, bool GRID, int GL = 1>
+// group of GL lanes (all alike; lane 0 writes).  UNI: every active lane of
+// the wave casts a ray of the same cell, whose list is then read through the
+// constant address space with a wave-uniform address (scalar loads, shared
+// by the wave) instead of one vector load per list entry and coordinate.
+template <int DK, bool GRID, int GL = 1, bool UNI = false>
 __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList &kl, int64_t gid,
                          int32_t kstart, int32_t &kdef, uint32_t &calls, uint32_t &grid_calls, int lane = 0) {
   constexpr int KN = knn_of<DK>();
-  const int d = a.d;
-  const int64_t cell = gid / a.R;
+  const int d = DK <= 4 ? DK : a.d;  // instances 2, 3 and 4 serve only their own d
+  const int64_t cell = UNI ? (int64_t)__builtin_amdgcn_readfirstlane((int)(gid / a.R)) : gid / a.R;
   float xi[DK], u[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
@@ -575,9 +578,11 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
       }
     }
   }
-  const int32_t *lids = kl.ids + cell * KN;
-  const float *lrel = kl.rel + cell * KN * d;
-  const float r2 = kl.r2[cell];
+  using IP = typename std::conditional<UNI, const __attribute__((address_space(4))) int32_t *, const int32_t *>::type;
+  using FP = typename std::conditional<UNI, const __attribute__((address_space(4))) float *, const float *>::type;
+  const IP lids = (IP)(kl.ids + cell * KN);
+  const FP lrel = (FP)(kl.rel + cell * KN * d);
+  const float r2 = *(FP)(kl.r2 + cell);
   if (*g.outside) {  // the grid does not bound every node: settle in FP64
     if (lane != 0) return false;
     if (a.flag_list) {
@@ -767,7 +772,16 @@ __global__ __launch_bounds__(NT) void incircle_list_kernel(CellScanArgs a, GridV
   uint32_t calls = 0, grid_calls = 0;
   bool defer = false;
   int32_t kdef = -1;
-  if (gid < a.n * a.R) defer = cast_ray<DK, false>(a, g, kl, gid, -1, kdef, calls, grid_calls);
+  const bool live = gid < a.n * a.R;
+  // whether the wave's rays all belong to one cell (64 | R, or a cell boundary outside the wave)
+  const int cell0 = __builtin_amdgcn_readfirstlane((int)(gid / a.R));
+  const bool one_cell = __all(!live || gid / a.R == cell0);
+  if (live) {
+    if (one_cell)
+      defer = cast_ray<DK, false, 1, true>(a, g, kl, gid, -1, kdef, calls, grid_calls);
+    else
+      defer = cast_ray<DK, false>(a, g, kl, gid, -1, kdef, calls, grid_calls);
+  }
   const unsigned long long mask = __ballot(defer);
   if (mask) {
     const int lane = (int)__lane_id();
