@@ -501,8 +501,9 @@ __device__ void list_nn2(IP ids, FP rel, int d, const float (&u)[DK], float t, i
   d1 = d2 = __builtin_inff();
 #pragma unroll 4
   for (int s = 0; s < KN; ++s) {
+    // -1 marks the slots past the end (their coordinates are zero); the test
+    // joins the value tests, with no branch around the next entry's loads
     const int32_t node = ids[s];
-    if (node < 0) break;
     float den = 0.f, dist = 0.f;
 #pragma unroll
     for (int k = 0; k < DK; ++k) {
@@ -513,7 +514,7 @@ __device__ void list_nn2(IP ids, FP rel, int d, const float (&u)[DK], float t, i
         dist = __builtin_fmaf(e, e, dist);
       }
     }
-    if (!(den > 0.f)) continue;
+    if (!((node >= 0) & (den > 0.f))) continue;
     if (dist < d1 || (dist == d1 && node < i1)) {
       d2 = d1;
       d1 = dist;
@@ -605,8 +606,7 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
     float nb = 2.f * tbox, db = 1.f;
 #pragma unroll 4
     for (int s = 0; s < KN; ++s) {
-      const int32_t ks = lids[s];
-      if (ks < 0) break;
+      const int32_t ks = lids[s];  // -1 past the end (see list_nn2)
       float num = 0.f, den = 0.f;
 #pragma unroll
       for (int q2 = 0; q2 < DK; ++q2) {
@@ -616,7 +616,7 @@ __device__ bool cast_ray(const CellScanArgs &a, const GridView &g, const KnnList
           den = __builtin_fmaf(u[q2], e, den);
         }
       }
-      if (den > 0.f && den * den > 0x1p-24f * num && num * db < nb * den) {
+      if ((ks >= 0) & (den > 0.f) & (den * den > 0x1p-24f * num) & (num * db < nb * den)) {
         nb = num;
         db = den;
         k = ks;
