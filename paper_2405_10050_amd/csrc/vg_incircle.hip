@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes
     dl[s] = __builtin_inff();
     il[s] = -1;
   }
-  constexpr int BUF = 8;
+  constexpr int BUF = 4;  // 8 costs 8 more registers: 3 waves per SIMD at d = 3 instead of 4, 6% slower
   float bd[BUF];
   int32_t bi[BUF];
   int bc = 0;
