@@ -795,14 +795,29 @@ hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
   // large clouds: a workgroup per queued ray (the queue is often short there)
   const bool wide = a.n >= (int64_t(1) << 18);
   const dim3 gridw(max_grid);
-  if (a.nodes64) {  // exact FP64 rows: general rays, d <= 8, 8 rays per LDS tile
+  // general rays, d <= 8, 8 rays per LDS tile: d a compile-time constant
+#define VG_RECHECK_EXACT(NTV)                                                                  \
+  do {                                                                                        \
+    switch (a.d) {                                                                            \
+      case 2: hipLaunchKernelGGL((recheck_kernel<2, false, NTV, false, true>), grid, blk, 0, s, a); break; \
+      case 3: hipLaunchKernelGGL((recheck_kernel<3, false, NTV, false, true>), grid, blk, 0, s, a); break; \
+      case 4: hipLaunchKernelGGL((recheck_kernel<4, false, NTV, false, true>), grid, blk, 0, s, a); break; \
+      case 5: hipLaunchKernelGGL((recheck_kernel<5, false, NTV, false, true>), grid, blk, 0, s, a); break; \
+      case 6: hipLaunchKernelGGL((recheck_kernel<6, false, NTV, false, true>), grid, blk, 0, s, a); break; \
+      case 7: hipLaunchKernelGGL((recheck_kernel<7, false, NTV, false, true>), grid, blk, 0, s, a); break; \
+      default: hipLaunchKernelGGL((recheck_kernel<8, false, NTV, false, true>), grid, blk, 0, s, a); break; \
+    }                                                                                         \
+  } while (0)
+  if (a.nodes64) {  // exact FP64 rows: general rays, d <= 8
     if (cells || a.d > 8) return hipErrorInvalidValue;
-    if (a.d <= 4)
-      hipLaunchKernelGGL((recheck_kernel<4, false, double>), grid, blk, 0, s, a);
-    else
-      hipLaunchKernelGGL((recheck_kernel<8, false, double>), grid, blk, 0, s, a);
+    VG_RECHECK_EXACT(double);
     return hipGetLastError();
   }
+  if (!cells && !wide && a.d <= 8) {
+    VG_RECHECK_EXACT(float);
+    return hipGetLastError();
+  }
+#undef VG_RECHECK_EXACT
 #define VG_RECHECK(DKV)                                                            \
   do {                                                                            \
     if (wide && cells)                                                            \
