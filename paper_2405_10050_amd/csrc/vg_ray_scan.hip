@@ -460,8 +460,14 @@ hipError_t launch_ray_scan(const RayScanArgs &a, void *split, size_t split_bytes
     hipLaunchKernelGGL(ray_scan_part_kernel<DKV>, gsplit, blk, 0, s, a, chunk, st);         \
     hipLaunchKernelGGL(ray_merge_kernel<DKV>, grid, blk, 0, s, a, parts, (const ScanState *)st); \
   } while (0)
-    if (a.d <= 4)
+    if (a.d <= 2)
+      VG_SPLIT(2);
+    else if (a.d <= 3)
+      VG_SPLIT(3);
+    else if (a.d <= 4)
       VG_SPLIT(4);
+    else if (a.d <= 6)
+      VG_SPLIT(6);
     else if (a.d <= 8)
       VG_SPLIT(8);
     else if (a.d <= 12)
@@ -471,8 +477,16 @@ hipError_t launch_ray_scan(const RayScanArgs &a, void *split, size_t split_bytes
 #undef VG_SPLIT
     return hipGetLastError();
   }
-  if (a.d <= 4)
+  // DK: d rounded up to 2, 3, 4, 6, 8, 12 or 16 (padded coordinates are zeros
+  // and add exact zeros to every sum, so the width does not change a result)
+  if (a.d <= 2)
+    hipLaunchKernelGGL(ray_scan_kernel<2>, grid, blk, 0, s, a);
+  else if (a.d <= 3)
+    hipLaunchKernelGGL(ray_scan_kernel<3>, grid, blk, 0, s, a);
+  else if (a.d <= 4)
     hipLaunchKernelGGL(ray_scan_kernel<4>, grid, blk, 0, s, a);
+  else if (a.d <= 6)
+    hipLaunchKernelGGL(ray_scan_kernel<6>, grid, blk, 0, s, a);
   else if (a.d <= 8)
     hipLaunchKernelGGL(ray_scan_kernel<8>, grid, blk, 0, s, a);
   else if (a.d <= 12)
