@@ -251,7 +251,7 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   VG_HIP(ctx, hipMemcpyAsync(&queued, ctx->counters + CNT_FLAGGED, 4, hipMemcpyDeviceToHost, ctx->stream));
   VG_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (queued > 0 && !launch_recheck_split(r, queued, parts, parts_bytes, ctx->stream, e))
-    e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
+    e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream, queued);
   if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
   ctx->last_rays = m;
   ctx->last_tau = kTauRays;

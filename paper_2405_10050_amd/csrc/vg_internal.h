@@ -196,7 +196,8 @@ int ray_scan_batched_blocks_per_cu();
 hipError_t launch_recheck_rays_batched(const RayBatchProblem *probs_dev, const uint32_t *counters,
                                        const int64_t *flag_list, uint32_t *tie_counter, int grid,
                                        hipStream_t s);
-hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s);
+// queued: the queue length when the caller knows it (-1: read on the device only)
+hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s, int64_t queued = -1);
 // Monte-Carlo rays over n >= 2^18 nodes: the recheck split over node chunks,
 // driven by the queue length on the device (m rays at most); parts scratch
 // of recheck_cells_reserve(m, n) bytes (0: no split, use launch_recheck).

@@ -788,12 +788,14 @@ bool launch_recheck_cells_split(const RecheckArgs &a, int64_t m, void *parts, si
   return true;
 }
 
-hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s) {
+hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s, int64_t queued) {
   if (max_grid <= 0) return hipSuccess;
   const dim3 grid((max_grid + WAVES1 - 1) / WAVES1), blk(NT1);
   const bool cells = a.mode == RAYS_CELLS;
-  // large clouds: a workgroup per queued ray (the queue is often short there)
-  const bool wide = a.n >= (int64_t(1) << 18);
+  // large clouds: a workgroup per queued ray when the queue is short (or of
+  // unknown length); a queue of 2048 rays or more fills the GPU with 8 rays
+  // per workgroup, each node tile then read once for 8 rays
+  const bool wide = a.n >= (int64_t(1) << 18) && (queued < 0 || queued < 2048);
   const dim3 gridw(max_grid);
   // general rays, d <= 8, 8 rays per LDS tile: d a compile-time constant
 #define VG_RECHECK_EXACT(NTV)                                                                  \
