@@ -578,14 +578,15 @@ __global__ __launch_bounds__(NT) void recheck_rays_batched_kernel(const RayBatch
 // and stores the part's top-2 in parts[y][f]; recheck_fold_kernel merges the
 // parts of each ray (the top-2 does not depend on the order of the merges,
 // so the results are the wide kernel's) and finishes it.
-template <int DK, typename NT = float>
+// EXACT: d == DK, known at compile time (no guarded coordinate reads).
+template <int DK, typename NT = float, bool EXACT = false>
 __global__ __launch_bounds__(NT1) void recheck_part_kernel(RecheckArgs a, int64_t chunk, uint32_t cnt,
                                                            Top2 *__restrict__ parts) {
   __shared__ double st1[WAVES1], st2[WAVES1];
   __shared__ int32_t si1[WAVES1];
   const NT *rows = node_rows<NT>(a);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int d = a.d;
+  const int d = EXACT ? DK : a.d;
   const int64_t lo = (int64_t)blockIdx.y * chunk;
   const int64_t hi = lo + chunk < a.n ? lo + chunk : a.n;
   for (uint32_t f = blockIdx.x; f < cnt; f += gridDim.x) {
@@ -719,25 +720,33 @@ bool launch_recheck_split(const RecheckArgs &a, uint32_t cnt, void *parts, size_
   const unsigned gx = cnt < 8192u / (unsigned)parts_n ? cnt : 8192u / (unsigned)parts_n;
   const dim3 grid(gx, (unsigned)parts_n), blk(NT1), gfold((cnt + 255) / 256), bfold(256);
   Top2 *pt = static_cast<Top2 *>(parts);
-#define VG_SPLIT_RECHECK(DKV, NTV)                                                                  \
+#define VG_SPLIT_RECHECK(DKV, NTV, EX, DW)                                                           \
   do {                                                                                              \
-    hipLaunchKernelGGL((recheck_part_kernel<DKV, NTV>), grid, blk, 0, s, a, chunk, cnt, pt);         \
-    hipLaunchKernelGGL(recheck_fold_kernel<DKV>, gfold, bfold, 0, s, a, parts_n, cnt, (const Top2 *)pt); \
+    hipLaunchKernelGGL((recheck_part_kernel<DKV, NTV, EX>), grid, blk, 0, s, a, chunk, cnt, pt);     \
+    hipLaunchKernelGGL(recheck_fold_kernel<DW>, gfold, bfold, 0, s, a, parts_n, cnt, (const Top2 *)pt); \
+  } while (0)
+#define VG_SPLIT_RECHECK_EXACT(NTV)                                                                 \
+  do {                                                                                              \
+    switch (a.d) {                                                                                  \
+      case 2: VG_SPLIT_RECHECK(2, NTV, true, 4); break;                                             \
+      case 3: VG_SPLIT_RECHECK(3, NTV, true, 4); break;                                             \
+      case 4: VG_SPLIT_RECHECK(4, NTV, true, 4); break;                                             \
+      case 5: VG_SPLIT_RECHECK(5, NTV, true, 8); break;                                             \
+      case 6: VG_SPLIT_RECHECK(6, NTV, true, 8); break;                                             \
+      case 7: VG_SPLIT_RECHECK(7, NTV, true, 8); break;                                             \
+      default: VG_SPLIT_RECHECK(8, NTV, true, 8); break;                                            \
+    }                                                                                               \
   } while (0)
   if (a.nodes64) {
-    if (a.d <= 4)
-      VG_SPLIT_RECHECK(4, double);
-    else
-      VG_SPLIT_RECHECK(8, double);
-  } else if (a.d <= 4) {
-    VG_SPLIT_RECHECK(4, float);
+    VG_SPLIT_RECHECK_EXACT(double);  // d <= 8 here
   } else if (a.d <= 8) {
-    VG_SPLIT_RECHECK(8, float);
+    VG_SPLIT_RECHECK_EXACT(float);
   } else if (a.d <= 12) {
-    VG_SPLIT_RECHECK(12, float);
+    VG_SPLIT_RECHECK(12, float, false, 12);
   } else {
-    VG_SPLIT_RECHECK(16, float);
+    VG_SPLIT_RECHECK(16, float, false, 16);
   }
+#undef VG_SPLIT_RECHECK_EXACT
 #undef VG_SPLIT_RECHECK
   err = hipGetLastError();
   return true;
