@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.parity import compare_rays
+from tests.parity import compare_rays, runner_up_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +50,8 @@ def test_batched_matches_oracle_and_single_path(vg, batch, prec, tmp_path, monke
         n = X.shape[0]
         cells = np.sort(rng.choice(n, min(n, 40), replace=False))
         tr, ir, t2r = oracle.raycast_cells(X, cells, D[cells])
-        compare_rays(t[cells].ravel(), idx[cells].ravel(), tr, ir, t2r, rtol=1e-5)
+        compare_rays(t[cells].ravel(), idx[cells].ravel(), tr, ir, t2r, rtol=1e-5,
+                     runner_up=runner_up_cells(X, cells, D[cells], ir))
         t1, i1, s1 = vg.raycast_cells(Xd, Dd, precision=prec)
         assert np.array_equal(i1.cpu().numpy(), idx)
         assert np.array_equal(t1.cpu().numpy().view(np.uint32), t.view(np.uint32))

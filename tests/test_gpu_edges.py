@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.parity import compare_rays
+from tests.parity import compare_rays, runner_up_cells, runner_up_rays
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +26,8 @@ def test_largest_ray_count_per_cell(vg, precision):
     dev = torch.device("cuda", 0)
     t, idx, _ = vg.raycast_cells(torch.from_numpy(X).to(dev), torch.from_numpy(D).to(dev), precision=precision)
     t_ref, idx_ref, t2_ref = oracle.raycast_cells(X, np.arange(n), D)
-    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5,
+                 runner_up=runner_up_cells(X, np.arange(n), D, idx_ref))
 
 
 def test_ray_count_past_the_limit_is_rejected(vg):
@@ -63,7 +64,8 @@ def test_duplicate_generators_match_oracle(vg, mode):
     else:
         t, idx, _ = vg.raycast_cells(nodes, dirs, precision=mode)
     t_ref, idx_ref, t2_ref = oracle.raycast_cells(X, np.arange(n), D)
-    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5,
+                 runner_up=runner_up_cells(X, np.arange(n), D, idx_ref))
 
 
 @pytest.mark.parametrize("heuristic", [False, True])
@@ -84,7 +86,8 @@ def test_incircle_with_nodes_outside_the_cube_defers_to_fp64(vg, heuristic):
                             incircle=True, heuristic=heuristic)
     assert vg.stats()["flagged"] == m
     t_ref, idx_ref, t2_ref = oracle.raycast(X, O, U, g, excl=g[:, None], clip=False)
-    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5,
+                 runner_up=runner_up_rays(X, O, U, g, g[:, None], False, idx_ref))
 
 
 def test_wide_recheck_general_rays_match_oracle(vg):
@@ -103,7 +106,8 @@ def test_wide_recheck_general_rays_match_oracle(vg):
                             incircle=True)
     assert vg.stats()["flagged"] == m
     t_ref, idx_ref, t2_ref = oracle.raycast(X, O, U, g, excl=g[:, None], clip=True)
-    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+    compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5,
+                 runner_up=runner_up_rays(X, O, U, g, g[:, None], True, idx_ref))
 
 
 def test_wide_recheck_cells_match_oracle(vg):
@@ -120,4 +124,5 @@ def test_wide_recheck_cells_match_oracle(vg):
     D = dirs[torch.from_numpy(cells).to(dev)].cpu().numpy()
     t_ref, idx_ref, t2_ref = oracle.raycast_cells(X, cells, D)
     sel = torch.from_numpy(cells).to(dev)
-    compare_rays(t[sel].cpu().numpy(), idx[sel].cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+    compare_rays(t[sel].cpu().numpy(), idx[sel].cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5,
+                 runner_up=runner_up_cells(X, cells, D, idx_ref))

@@ -6,6 +6,7 @@ import torch
 
 import oracle
 import workloads as W
+from tests.parity import compare_rays, runner_up_cells, tie_adjusted
 
 pytestmark = pytest.mark.gpu
 
@@ -40,26 +41,21 @@ def test_mc_volume_area_match_oracle(vg, d, n, R, prec):
     res = vg.mc_volume_area(torch.from_numpy(X).to(dev), torch.from_numpy(D).to(dev), precision=prec)
     torch.cuda.synchronize()
     ref = oracle.mc_volume_area(X, np.arange(n), D)
-    tie = oracle.near_tie(ref["t"], ref["t2"]).reshape(n, R)
     idx = res.idx.cpu().numpy()
-    assert np.all((idx.ravel() == ref["idx"]) | tie.ravel())
+    compare_rays(res.t.cpu().numpy(), idx, ref["t"], ref["idx"], ref["t2"], rtol=1e-5,
+                 runner_up=runner_up_cells(X, np.arange(n), D, ref["idx"]))
     vol = res.volume.cpu().numpy()
     en = res.energy2.cpu().numpy()
     assert np.allclose(vol, ref["volume"], rtol=1e-5, atol=0)
     assert np.allclose(en, ref["energy2"], rtol=1e-5, atol=0)
     got, cnt, fj = _gpu_facets(res, n)
-    # facets that received a near-tie ray may legitimately differ
-    excused = set()
-    for i, k in zip(*np.nonzero(tie)):
-        excused.add((int(i), int(ref["idx"].reshape(n, R)[i, k])))
-        excused.add((int(i), int(idx[i, k])))
-    for key, A in ref["facets"].items():
-        if key in excused:
-            continue
+    # every facet, with the oracle's sums taken on the GPU's choice among
+    # tied candidates (compare_rays checked it is a correct one)
+    adj = oracle.mc_volume_area(X, np.arange(n), D, rays=tie_adjusted(ref["t"], ref["idx"], ref["t2"], idx))
+    for key, A in adj["facets"].items():
         assert key in got, f"facet {key} missing"
         assert got[key] == pytest.approx(A, rel=1e-5), key
-    for key in got:
-        assert key in ref["facets"] or key in excused, f"extra facet {key}"
+    assert set(got) == set(adj["facets"]), "extra facets"
     # rows are sorted by j and counts match
     for i in range(0, n, 17):
         row = fj[i, :cnt[i]]

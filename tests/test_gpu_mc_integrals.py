@@ -10,6 +10,7 @@ import torch
 
 import oracle
 import workloads as W
+from tests.parity import compare_rays, runner_up_cells, tie_adjusted
 
 pytestmark = pytest.mark.gpu
 
@@ -48,8 +49,13 @@ def test_function_integrals_match_oracle(vg, d, n, R, m):
     res = vg.mc_volume_area(nodes, dirs)
     out = vg.mc_integrals(nodes, dirs, res, _f_torch(d, dev), torch.from_numpy(T).to(dev) if m else None)
     torch.cuda.synchronize()
-    ref = oracle.mc_integrals(X, np.arange(n), D, T, _f_np(d))
-    tie = oracle.near_tie(ref["t"], ref["t2"]).reshape(n, R)
+    ref0 = oracle.mc_volume_area(X, np.arange(n), D)
+    idx = res.idx.cpu().numpy()
+    compare_rays(res.t.cpu().numpy(), idx, ref0["t"], ref0["idx"], ref0["t2"], rtol=1e-5,
+                 runner_up=runner_up_cells(X, np.arange(n), D, ref0["idx"]))
+    # the oracle's integrals on the GPU's choice among tied candidates
+    ref = oracle.mc_integrals(X, np.arange(n), D, T, _f_np(d),
+                              rays=tie_adjusted(ref0["t"], ref0["idx"], ref0["t2"], idx))
     if m:
         assert np.allclose(out.volume.cpu().numpy(), ref["F_V"], rtol=1e-5, atol=1e-6 * np.abs(ref["F_V"]).max())
     else:
@@ -61,16 +67,10 @@ def test_function_integrals_match_oracle(vg, d, n, R, m):
     cnt = out.facet_count.cpu().numpy()
     fj = out.facet_j.cpu().numpy()
     ff = out.facet.cpu().numpy()
-    idx = res.idx.cpu().numpy()
-    excused = set()
-    for i, k in zip(*np.nonzero(tie)):
-        excused.add((int(i), int(ref["idx"].reshape(n, R)[i, k])))
-        excused.add((int(i), int(idx[i, k])))
     scale = max(abs(v) for v in ref["F"].values())
     got = {(i, int(fj[i, s])): float(ff[i, s]) for i in range(n) for s in range(cnt[i])}
+    assert set(got) == set(ref["F"])
     for key, v in ref["F"].items():
-        if key in excused:
-            continue
         assert got[key] == pytest.approx(v, rel=1e-5, abs=1e-6 * scale), key
 
 

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.parity import compare_rays
+from tests.parity import compare_rays, runner_up_cells, tie_adjusted
 
 pytestmark = pytest.mark.gpu
 
@@ -59,24 +59,22 @@ def test_tuple_neighbors_equal_the_pairs_of_the_oracle_tuples(vg, d, n):
     assert np.all(np.diff(off_ref) >= 1)
 
 
-def _check_against_oracle(res, ref, n, R, rtol):
-    tie = oracle.near_tie(ref["t"], ref["t2"])
-    compare_rays(res.t.cpu().numpy(), res.idx.cpu().numpy(), ref["t"], ref["idx"], ref["t2"], rtol=rtol)
+def _check_against_oracle(res, ref, X, D, rtol):
+    n = X.shape[0]
+    idx = res.idx.cpu().numpy()
+    compare_rays(res.t.cpu().numpy(), idx, ref["t"], ref["idx"], ref["t2"], rtol=rtol,
+                 runner_up=runner_up_cells(X, np.arange(n), D, ref["idx"]))
     assert np.allclose(res.volume.cpu().numpy(), ref["volume"], rtol=rtol, atol=0)
     assert np.allclose(res.energy2.cpu().numpy(), ref["energy2"], rtol=rtol, atol=0)
     cnt = res.facet_count.cpu().numpy()
     fj = res.facet_j.cpu().numpy()
     fa = res.facet_area.cpu().numpy()
-    idx = res.idx.cpu().numpy().reshape(n, R)
-    excused = set()
-    for i, k in zip(*np.nonzero(tie.reshape(n, R))):
-        excused.add((int(i), int(ref["idx"].reshape(n, R)[i, k])))
-        excused.add((int(i), int(idx[i, k])))
+    # every facet, with the oracle's sums on the GPU's choice among tied candidates
+    adj = oracle.mc_volume_area(X, np.arange(n), D, rays=tie_adjusted(ref["t"], ref["idx"], ref["t2"], idx))
     got = {(i, int(fj[i, s])): float(fa[i, s]) for i in range(n) for s in range(cnt[i])}
-    for key, A in ref["facets"].items():
-        if key not in excused:
-            assert got[key] == pytest.approx(A, rel=rtol), key
-    assert set(got) <= set(ref["facets"]) | excused
+    assert set(got) == set(adj["facets"])
+    for key, A in adj["facets"].items():
+        assert got[key] == pytest.approx(A, rel=rtol), key
 
 
 @pytest.mark.parametrize("d,n,R,prec", [(2, 1000, 128, "fp32"), (3, 500, 256, "fp32"),
@@ -93,12 +91,11 @@ def test_mc_over_neighbours_matches_oracle_over_all_nodes(vg, d, n, R, prec):
     res = vg.mc_volume_area(nodes, dirs, precision=prec, neighbors=nb)
     torch.cuda.synchronize()
     ref = oracle.mc_volume_area(X, np.arange(n), D)
-    _check_against_oracle(res, ref, n, R, 1e-5)
+    _check_against_oracle(res, ref, X, D, 1e-5)
     # the same rays through the full scan
     full = vg.mc_volume_area(nodes, dirs, precision=prec)
-    tie = oracle.near_tie(ref["t"], ref["t2"])
-    same = (res.idx.cpu().numpy().ravel() == full.idx.cpu().numpy().ravel()) | tie
-    assert same.all()
+    compare_rays(full.t.cpu().numpy(), full.idx.cpu().numpy(), ref["t"], ref["idx"], ref["t2"], rtol=1e-5,
+                 runner_up=runner_up_cells(X, np.arange(n), D, ref["idx"]))
     # and the adjoint through the neighbour result equals the full one's
     g_full = vg.mc_backward(nodes, dirs, full, torch.ones(n, device=dev), torch.ones(n, device=dev), None)
     g_nb = vg.mc_backward(nodes, dirs, res, torch.ones(n, device=dev), torch.ones(n, device=dev), None)
@@ -127,7 +124,7 @@ def test_superset_lists_and_invalid_entries_change_nothing(vg):
                                                     torch.from_numpy(nbr2).to(dev)))
     torch.cuda.synchronize()
     ref = oracle.mc_volume_area(X, np.arange(n), D)
-    _check_against_oracle(res, ref, n, R, 1e-5)
+    _check_against_oracle(res, ref, X, D, 1e-5)
 
 
 def test_neighbor_argument_errors(vg):

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.parity import compare_rays
+from tests.parity import compare_rays, runner_up_rays
 
 pytestmark = pytest.mark.gpu
 
@@ -82,7 +82,8 @@ def test_batch_matches_oracle_and_single_calls(vg, clip):
         if O.shape[0] == 0:
             continue
         t_ref, idx_ref, t2_ref = oracle.raycast(X, O, U, g, excl=E, clip=clip)
-        compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5)
+        compare_rays(t.cpu().numpy(), idx.cpu().numpy(), t_ref, idx_ref, t2_ref, rtol=1e-5,
+                     runner_up=runner_up_rays(X, O, U, g, E, clip, idx_ref))
         t1, i1, s1 = vg.raycast(*problems[q][:4], problems[q][4], clip=clip)
         assert torch.equal(t, t1) and torch.equal(idx, i1) and torch.equal(st, s1), f"problem {q}"
 

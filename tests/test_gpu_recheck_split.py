@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads as W
-from tests.parity import compare_rays
+from tests.parity import compare_rays, runner_up_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -27,8 +27,10 @@ def check_rechecked_cells(vg, X, D, t, idx, st, n_cells, seed):
     assert cells.size > 0
     pick = np.sort(np.random.default_rng(seed).choice(cells, min(n_cells, cells.size), replace=False))
     sel = torch.from_numpy(pick).to(t.device)
-    tr, ir, t2r = oracle.raycast_cells(X, pick, D[sel].cpu().numpy())
-    compare_rays(t[sel].cpu().numpy().ravel(), idx[sel].cpu().numpy().ravel(), tr, ir, t2r, rtol=1e-5)
+    Ds = D[sel].cpu().numpy()
+    tr, ir, t2r = oracle.raycast_cells(X, pick, Ds)
+    compare_rays(t[sel].cpu().numpy().ravel(), idx[sel].cpu().numpy().ravel(), tr, ir, t2r, rtol=1e-5,
+                 runner_up=runner_up_cells(X, pick, Ds, ir))
     # the rechecked rays themselves: FP64 argmin, t* rounded once to FP32
     rr = rechecked[pick].ravel()
     tie = oracle.near_tie(tr, t2r)
