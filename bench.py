@@ -59,30 +59,45 @@ def measured_traffic(name, n, R):
     path = os.path.join(ROOT, "profiles", name)
     try:
         doc = json.load(open(path))
-        src = open(os.path.join(ROOT, doc["kernel_source"]), "rb").read()
+        h = hashlib.sha256()
+        for f in doc["kernel_sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != doc["kernel_source_sha256"]:
+    if h.hexdigest() != doc["kernel_sources_sha256"]:
         return None
     if n != 100_000 or R != 1024:
         return None
     return float(doc["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(X, cells, Ds):
+def cpu_baseline(X, cells, Ds, single=None, dirs_single=None):
     """The FP64 oracle on a bounded sample of the same workload (all host
     threads): RayCast of the sampled cells' rays over all nodes plus their
-    Monte-Carlo sums.  ``Ds`` holds the sampled cells' directions."""
+    Monte-Carlo sums.  ``Ds`` holds the sampled cells' directions.  With
+    ``single`` (a smaller sample of cells and their directions) the same is
+    timed on one thread."""
     import oracle
 
     oracle.build()
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     oracle.mc_volume_area(X, cells, Ds)
     dt = time.perf_counter() - t0
     rays = cells.size * Ds.shape[1]
-    return dict(value=rays / dt, unit="rays/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{cells.size} random cells x {Ds.shape[1]} rays of the same workload "
-                       f"({rays} rays, each over all {X.shape[0]} nodes; {dt:.1f} s)")
+    out = dict(value=rays / dt, unit="rays/s", cores=cores, kind="oracle",
+               sample=f"{cells.size} random cells x {Ds.shape[1]} rays of the same workload "
+                      f"({rays} rays, each over all {X.shape[0]} nodes; {dt:.1f} s)")
+    if single is not None:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.mc_volume_area(X, single, dirs_single)
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(cores)
+        r1 = single.size * dirs_single.shape[1]
+        out["single_thread"] = dict(value=r1 / dt1, unit="rays/s", cores=1,
+                                    sample=f"{single.size} of those cells ({r1} rays; {dt1:.1f} s)")
+    return out
 
 
 def _timed(stream, fn, steps):
@@ -477,6 +492,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters of a profiler run)")
     ap.add_argument("--compare-bf16", type=int, default=1,
                     help="also time the split-BF16x3 form of the step (extra field)")
+    ap.add_argument("--dirs", default="device", choices=["device", "input"],
+                    help="directions drawn on the device from the seed (default) or read from HBM")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -503,15 +520,15 @@ def main():
         return
 
     d, n, R = 10, args.n, args.rays
+    seed = 1  # direction seed of the workload
     t_setup = time.perf_counter()
     X = W.gaussian_mixture_cloud(n=n, d=d, seed=0)
-    D = directions_threaded(np.arange(n), R, d, seed=1)
-    print(f"[bench] inputs ready in {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
-
     dev = torch.device("cuda", 0)
     nodes = torch.from_numpy(X).to(dev)
-    dirs = torch.from_numpy(D).to(dev)
-    del D  # the CPU baseline regenerates the directions of its sample
+    dirs = None
+    if args.dirs == "input":
+        dirs = torch.from_numpy(directions_threaded(np.arange(n), R, d, seed=seed)).to(dev)
+    print(f"[bench] inputs ready in {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
     if args.copy_probe_mib > 0:
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -519,52 +536,79 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    res = vg.mc_volume_area(nodes, dirs, precision=args.precision)
+    # every launch of a step goes to one (default-priority) stream, which is
+    # also the stream the step is captured on
+    stream = torch.cuda.Stream(dev)
     g_vol = torch.ones(n, device=dev)
     g_en = torch.ones(n, device=dev)
     g_fa = torch.ones((n, R), device=dev)
-    stream = torch.cuda.current_stream(dev)
+    grad = torch.empty((n, d), device=dev)
 
-    def step():
-        vg.mc_volume_area(nodes, dirs, precision=args.precision, out=res)
-        if not args.no_backward:
-            vg.mc_backward(nodes, dirs, res, g_vol, g_en, g_fa)
+    def make_step(precision):
+        res = vg.mc_volume_area(nodes, dirs, precision=precision, seed=seed, rays_per_cell=R)
 
-    for w in range(args.warmup):
-        step()
-        torch.cuda.synchronize()
-        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        def step():
+            vg.mc_volume_area(nodes, dirs, precision=precision, seed=seed, rays_per_cell=R, out=res)
+            if not args.no_backward:
+                vg.mc_backward(nodes, dirs, res, g_vol, g_en, g_fa, out=grad)
 
-    st = vg.stats()
-    vg.set_profiling(True)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for k in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    st = vg.stats()
-    vg.set_profiling(False)
-    flagged = st["flagged"]
-    print(f"[bench] {args.steps} steps in {total_ms:.1f} ms", file=sys.stderr, flush=True)
+        return res, step
 
-    ms_step = total_ms / args.steps
+    def run(precision, steps, warmup):
+        """Warm-up steps (eager), then the step captured into a hipGraph and
+        replayed `steps` times, each replay bracketed by HIP events on the
+        capture stream; then 3 eager steps with the library's HIP events
+        around each candidate-scan launch.  Returns the result buffers, the
+        replay durations, the scan duration and the counters of a step."""
+        with torch.cuda.stream(stream):
+            res, step = make_step(precision)
+            warmup = max(1, warmup)  # the capture needs the scratch already grown
+            for w in range(warmup):
+                step()
+                torch.cuda.synchronize()
+                print(f"[bench] {precision} warmup {w + 1}/{warmup} done", file=sys.stderr, flush=True)
+            st = vg.stats()
+            eager = [res.t.clone(), res.idx.clone(), res.volume.clone(), grad.clone()]
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                step()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for k in range(steps):
+                graph.replay()
+                ev[k + 1].record(stream)
+            torch.cuda.synchronize()
+            replay_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+            # the replays reproduce the eager step bit for bit
+            same = all(torch.equal(a.view(torch.int32) if a.is_floating_point() else a,
+                                   b.view(torch.int32) if b.is_floating_point() else b)
+                       for a, b in zip(eager, [res.t, res.idx, res.volume, grad]))
+            vg.set_profiling(True)
+            for _ in range(3):
+                step()
+            st_p = vg.stats()
+            vg.set_profiling(False)
+            del graph
+        print(f"[bench] {precision}: {steps} replays, median {np.median(replay_ms):.1f} ms",
+              file=sys.stderr, flush=True)
+        return res, replay_ms, st_p["scan_ms"] / max(1, st_p["scan_launches"]), st, same
+
+    res, replay_ms, scan_ms, st, same = run(args.precision, args.steps, args.warmup)
+    ms_step = float(np.median(replay_ms))
     rays = n * R
     value = rays / (ms_step / 1e3)
-    scan_ms = st["scan_ms"] / max(1, st["scan_launches"])
     flops = 2.0 * d * n * rays + 2.0 * d * n * n  # U.R~^T per ray + X.R^T per cell
+    peaks = vg.peak_rates()
     if args.precision == "bf16x3":
         achieved = 3.0 * flops / (scan_ms / 1e3)
-        peak, unit = BF16_MFMA_PEAK, "TFLOP/s"
+        peak, peak_meas = BF16_MFMA_PEAK, peaks["bf16_mfma"]
     else:
         achieved = flops / (scan_ms / 1e3)
-        peak, unit = FP32_MFMA_PEAK, "TFLOP/s"
+        peak, peak_meas = FP32_MFMA_PEAK, peaks["fp32_mfma"]
 
     traffic = None
-    if args.precision == "fp32":
+    if args.precision == "fp32" and args.dirs == "device":
         traffic = measured_traffic("cell_scan_fp32_gmm8_d10_n100000_traffic.json", n, R)
     out = {
         "metric": "rays/sec batched RayCast (d=10,N=100k) at 1e-5 rel err; MC volume+grad cells/s",
@@ -580,61 +624,60 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "bf16x3",
         "data": "synthetic",
         "config": {
-            "workload": f"gaussian-mixture d={d} N={n}, {R} MC rays per cell "
+            "workload": f"gaussian-mixture d={d} N={n}, {R} MC rays per cell, directions drawn on the device "
+                        "(RayCast + FP64 recheck + volume/area/second moment + adjoint)"
+                        if args.dirs == "device" else
+                        f"gaussian-mixture d={d} N={n}, {R} MC rays per cell, directions read from HBM "
                         "(RayCast + FP64 recheck + volume/area/second moment + adjoint)",
             "d": d, "n_nodes": n, "rays_per_cell": R, "rays": rays,
+            "directions": "Philox4x32-10 + Box-Muller on the device, seed 1" if args.dirs == "device"
+                          else "host PCG64 draw, resident in HBM",
             "cells_per_s": n / (ms_step / 1e3),
-            "flagged_rays_per_step": flagged,
+            "flagged_rays_per_step": st["flagged"],
             "backward": not args.no_backward,
+            "timing": f"median of {args.steps} hipGraph replays of the captured step (HIP events per replay)",
+            "replay_ms_min_median_max": [float(np.min(replay_ms)), ms_step, float(np.max(replay_ms))],
+            "mean_ms_per_step": float(np.mean(replay_ms)),
+            "replays_equal_eager_step": same,
         },
         "roofline": {
             "bound": "mfma",
             "kernel": f"cell_scan_{args.precision}",
             "achieved": achieved / 1e12,
             "peak": peak / 1e12,
-            "unit": unit,
+            "unit": "TFLOP/s",
             "frac": achieved / peak,
+            "peak_measured": peak_meas / 1e12,
+            "frac_of_measured_peak": achieved / peak_meas,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes": float(rays * d * 4 + n * d * 4 + rays * 9),
+            "algorithmic_bytes": float(n * d * 4 + rays * 9 + (rays * d * 4 if args.dirs == "input" else 0)),
             "scan_ms": scan_ms,
+            "scan_timing": "HIP events around each scan launch on its stream, 3 eager steps after the replays",
         },
+        "measured_peaks_tflops": {k: v / 1e12 for k, v in peaks.items()},
     }
     if args.compare_bf16 and args.precision == "fp32":
-        # the split-precision form of the same step, timed on the same inputs
-        res_b = vg.mc_volume_area(nodes, dirs, precision="bf16x3")
-
-        def step_b():
-            vg.mc_volume_area(nodes, dirs, precision="bf16x3", out=res_b)
-            if not args.no_backward:
-                vg.mc_backward(nodes, dirs, res_b, g_vol, g_en, g_fa)
-
-        step_b()
-        torch.cuda.synchronize()
-        vg.set_profiling(True)
-        ev0.record(stream)
-        for k in range(args.steps):
-            step_b()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        sb = vg.stats()
-        vg.set_profiling(False)
-        ms_b = ev0.elapsed_time(ev1) / args.steps
-        scan_b = sb["scan_ms"] / max(1, sb["scan_launches"])
-        same = float((res_b.idx == res.idx).float().mean().item())
+        # the split-precision form of the same step, timed the same way
+        res_b, rep_b, scan_b, sb, same_b = run("bf16x3", args.steps, 1)
+        ms_b = float(np.median(rep_b))
+        agree = float((res_b.idx == res.idx).float().mean().item())
         rel_t = float(((res_b.t - res.t).abs() / res.t).max().item())
         out["bf16x3"] = {
             "ms_per_step": ms_b, "rays_per_s": rays / (ms_b / 1e3), "speedup_vs_fp32": ms_step / ms_b,
             "scan_ms": scan_b, "flagged_rays_per_step": sb["flagged"],
             "roofline_frac_bf16_peak": 3.0 * flops / (scan_b / 1e3) / BF16_MFMA_PEAK,
+            "roofline_frac_measured_bf16_peak": 3.0 * flops / (scan_b / 1e3) / peaks["bf16_mfma"],
             "fp32_equivalent_tflops": flops / (scan_b / 1e3) / 1e12,
-            "argmin_agreement_with_fp32": same, "max_rel_t_diff_vs_fp32": rel_t,
+            "argmin_agreement_with_fp32": agree, "max_rel_t_diff_vs_fp32": rel_t,
+            "replays_equal_eager_step": same_b,
         }
-        print(f"[bench] bf16x3: {ms_b:.1f} ms/step", file=sys.stderr, flush=True)
     if args.cpu_cells > 0:
         rng = np.random.default_rng(123)
         sample = np.sort(rng.choice(n, args.cpu_cells, replace=False))
-        out["cpu_baseline"] = cpu_baseline(X, sample, directions_threaded(sample, R, d, seed=1))
+        dir_fn = (lambda c: W.philox_directions(c, R, d, seed=seed)) if args.dirs == "device" else \
+                 (lambda c: directions_threaded(c, R, d, seed=seed))
+        out["cpu_baseline"] = cpu_baseline(X, sample, dir_fn(sample), single=sample[:8], dirs_single=dir_fn(sample[:8]))
     print(json.dumps(out), flush=True)
 
 

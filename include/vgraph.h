@@ -89,7 +89,10 @@ typedef struct vg_stats {
  * vg_destroy.  Returns VG_EDEVICE if the device is absent or not gfx950. */
 int vg_create(int device, vg_ctx **out);
 void vg_destroy(vg_ctx *ctx);
-/* Bind a hipStream_t (passed as void*); NULL selects the null stream. */
+/* Bind a hipStream_t (passed as void*); NULL selects the null stream.  When
+ * the stream changes, work later enqueued on the new stream waits for this
+ * context's work already enqueued on the old one (an event), since calls
+ * share the context's scratch and counters. */
 int vg_set_stream(vg_ctx *ctx, void *hip_stream);
 /* Text of the last error on this context ("" if none).  Owned by ctx. */
 const char *vg_last_error(const vg_ctx *ctx);
@@ -99,6 +102,14 @@ int vg_get_stats(vg_ctx *ctx, vg_stats *out);
  * (cell or ray scan) on the context's stream and accumulate their durations
  * into vg_stats.scan_ms / scan_launches; enable == 0 stops and clears. */
 int vg_set_profiling(vg_ctx *ctx, int enable);
+
+/* Measured peak rate of one arithmetic pipe, for reporting beside the
+ * datasheet peaks: kind 0 = FP32 MFMA (v_mfma_f32_32x32x2f32), 1 = BF16 MFMA
+ * (v_mfma_f32_32x32x16_bf16), 2 = FP64 vector FMA.  Runs a short
+ * issue-bound kernel on every SIMD three times and returns the best rate in
+ * FLOP/s (a multiply-add counts 2).  Allocates a small buffer and
+ * synchronises the stream. */
+int vg_peak_rate(vg_ctx *ctx, int kind, double *flops_per_s);
 
 /* ---------------------------------------------------------------- RayCast */
 /* RayCast of n_rays arbitrary rays (Sec. 2.2, eq. (t); the half-space
@@ -143,6 +154,29 @@ int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
                      int rays_per_cell, const float *dirs, uint32_t flags,
                      float *t_out, int32_t *idx_out, uint8_t *status_out);
 
+/* vg_raycast_cells with the directions drawn on the device instead of read
+ * from memory (Sec. 3.1: u uniform on the unit sphere, the normalised
+ * standard normal vector drawn in Algorithm 3).  Direction of ray k of cell
+ * i, component c: Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (c / 4, k, i mod 2^32, i / 2^32) and key (seed mod 2^32, seed / 2^32)
+ * gives words w0..w3; pair p = (c mod 4) / 2 takes a = w[2p], b = w[2p+1];
+ * u1 = (a + 1/2) 2^-32, u2 = b 2^-32, rho = sqrt(-2 ln u1), theta = 2 pi u2
+ * (Box-Muller, FP64); z_c = rho cos theta (c even) or rho sin theta (c odd);
+ * u_c = fp32(z_c / sqrt(z_0^2 + z_1^2 + ...)), the squares summed in order
+ * without fused multiply-add.  The directions are never stored: every
+ * kernel that needs one recomputes it, and vg_dump_dirs writes them out.
+ * Same flags and outputs as vg_raycast_cells (VG_INCIRCLE is
+ * VG_EUNSUPPORTED). */
+int vg_raycast_cells_seeded(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                            int rays_per_cell, uint64_t seed, uint32_t flags,
+                            float *t_out, int32_t *idx_out, uint8_t *status_out);
+
+/* The directions that the seeded calls draw for cells first_cell ..
+ * first_cell + n_cells - 1: out [n_cells][rays_per_cell][d] f32 (DEVICE).
+ * The same function of (seed, cell, ray) as in the kernels, bit for bit. */
+int vg_dump_dirs(vg_ctx *ctx, int d, int64_t first_cell, int64_t n_cells, int rays_per_cell,
+                 uint64_t seed, float *out);
+
 /* ------------------------------------------------ Monte-Carlo estimators */
 /* Sec. 3.1 / Algorithm 3 with f = 1: for every cell i, with l = t* of its
  * rays and S = S_{d-1} = 2 pi^{d/2} / Gamma(d/2),
@@ -164,6 +198,14 @@ int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
                       float *t_out, int32_t *idx_out, uint8_t *status_out,
                       float *volume, float *energy2, int32_t *facet_j,
                       float *facet_area, int32_t *facet_count);
+
+/* vg_mc_volume_area with the directions drawn on the device from `seed`, as
+ * in vg_raycast_cells_seeded (no dirs array anywhere). */
+int vg_mc_volume_area_seeded(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                             int rays_per_cell, uint64_t seed, uint32_t flags,
+                             float *t_out, int32_t *idx_out, uint8_t *status_out,
+                             float *volume, float *energy2, int32_t *facet_j,
+                             float *facet_area, int32_t *facet_count);
 
 /* vg_mc_volume_area with each cell's candidate scan restricted to a list of
  * its neighbours: once the Voronoi diagram is known, a ray of cell i can only
@@ -242,6 +284,14 @@ int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
                    const int32_t *facet_count, const float *g_volume,
                    const float *g_energy2, const float *g_facet_area,
                    float *grad_nodes);
+
+/* vg_mc_backward of a seeded forward call (directions drawn from `seed`). */
+int vg_mc_backward_seeded(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                          int rays_per_cell, uint64_t seed, const float *t,
+                          const int32_t *idx, const int32_t *facet_j,
+                          const int32_t *facet_count, const float *g_volume,
+                          const float *g_energy2, const float *g_facet_area,
+                          float *grad_nodes);
 
 /* ------------------------------------------------------ uneven batches */
 /* One independent RayCast problem of vg_raycast_batched: the arguments of

@@ -100,6 +100,8 @@ def _load():
         lib.vgo_mc_ray_weights.argtypes = [i32, i64, P, i64, P, i32, P, P, P, P, P, P]
         lib.vgo_mc_adjoint.argtypes = [i32, i64, P, i64, P, i32, P, P, P, dbl, P, P, P, P]
         lib.vgo_num_threads.restype = i32
+        lib.vgo_set_threads.argtypes = [i32]
+        lib.vgo_set_threads.restype = None
         lib.vgo_explore_clipped.argtypes = [i32, i64, P]
         lib.vgo_explore_clipped.restype = P
         lib.vgo_clipped_vertex.argtypes = [i32, i64, P, P, P]
@@ -125,6 +127,12 @@ def _i32(a):
 
 def num_threads() -> int:
     return int(_load().vgo_num_threads())
+
+
+def set_threads(k: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (the results do not
+    depend on it)."""
+    _load().vgo_set_threads(int(k))
 
 
 def sphere_area(d: int) -> float:

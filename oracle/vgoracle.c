@@ -1315,6 +1315,16 @@ int vgo_mc_adjoint(int d, int64_t n, const double *X, int64_t n_cells,
   return 0;
 }
 
+/* Threads of the OpenMP loops that follow (timing aid; results do not
+ * depend on it). */
+void vgo_set_threads(int k) {
+#ifdef _OPENMP
+  if (k > 0) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
+}
+
 int vgo_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -11,6 +11,8 @@ raises ``VGError``.
 Calls (names follow the paper's statement of the problem):
   raycast(nodes, origin, direction, gen, excl, clip)   RayCast of Sec. 2.2
   raycast_cells(nodes, dirs)                           Monte-Carlo rays of every cell
+  raycast_cells(nodes, seed=s, rays_per_cell=R)        the same, directions drawn on the device
+  dump_dirs(d, n_cells, R, seed)                       those directions, written out
   mc_volume_area(nodes, dirs, neighbors=None)          Sec. 3.1 / Algorithm 3 estimators
   tuple_neighbors(sigma, n)                            cell adjacency from vertex tuples
   mc_integrals(nodes, dirs, res, f, tsamp)             integrals of f over cells and facets
@@ -80,6 +82,8 @@ EXPORTS = (
     "vg_mc_integrals", "vg_hmc_centroids", "vg_hmc_integrals",
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
     "vg_mesh_copy", "vg_mesh_free", "vg_mesh_num_nn_calls",
+    "vg_raycast_cells_seeded", "vg_mc_volume_area_seeded", "vg_mc_backward_seeded", "vg_dump_dirs",
+    "vg_peak_rate",
 )
 
 
@@ -88,7 +92,7 @@ def _load_lib():
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                           "python paper_2405_10050_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
-    P, I, I64, U32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32
+    P, I, I64, U32, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
     lib.vg_create.argtypes = [I, ctypes.POINTER(P)]
     lib.vg_destroy.argtypes = [P]
     lib.vg_destroy.restype = None
@@ -99,6 +103,11 @@ def _load_lib():
     lib.vg_set_profiling.argtypes = [P, I]
     lib.vg_raycast.argtypes = [P, I, I64, P, I64, P, P, P, P, I, U32, P, P, P]
     lib.vg_raycast_cells.argtypes = [P, I, I64, P, I, P, U32, P, P, P]
+    lib.vg_raycast_cells_seeded.argtypes = [P, I, I64, P, I, U64, U32, P, P, P]
+    lib.vg_mc_volume_area_seeded.argtypes = [P, I, I64, P, I, U64, U32, P, P, P, P, P, P, P, P]
+    lib.vg_mc_backward_seeded.argtypes = [P, I, I64, P, I, U64, P, P, P, P, P, P, P, P]
+    lib.vg_dump_dirs.argtypes = [P, I, I64, I64, I, U64, P]
+    lib.vg_peak_rate.argtypes = [P, I, ctypes.POINTER(ctypes.c_double)]
     lib.vg_mc_volume_area.argtypes = [P, I, I64, P, I, P, U32, P, P, P, P, P, P, P, P]
     lib.vg_mc_backward.argtypes = [P, I, I64, P, I, P, P, P, P, P, P, P, P, P]
     lib.vg_raycast_cells_batched.argtypes = [P, I, ctypes.POINTER(_CellsProblem), U32]
@@ -171,6 +180,19 @@ def stats(device=None) -> dict:
                 nn_grid_calls=s.nn_grid_calls)
 
 
+def peak_rates(device=None) -> dict:
+    """Measured FLOP/s of the FP32 MFMA, BF16 MFMA and FP64 vector-FMA pipes
+    (short issue-bound kernels; synchronises)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    c = _ctx(dev)
+    out = {}
+    for kind, name in enumerate(("fp32_mfma", "bf16_mfma", "fp64_fma")):
+        v = ctypes.c_double(0.0)
+        _check(_lib.vg_peak_rate(c, kind, ctypes.byref(v)), c, "vg_peak_rate")
+        out[name] = v.value
+    return out
+
+
 def set_profiling(enable: bool, device=None) -> None:
     """Time every candidate-scan kernel with HIP events on the current stream
     (read back through ``stats()``); ``False`` stops and clears."""
@@ -217,23 +239,53 @@ def _cells_flags(precision: str, recheck: bool, incircle: bool = False) -> int:
             (VG_INCIRCLE if incircle else 0))
 
 
-def raycast_cells(nodes, dirs, precision="fp32", recheck=True, incircle=False):
-    """Monte-Carlo rays of every cell: ``dirs`` is ``[N, R, d]``; returns
+def _rays_per_cell(dirs, n, d, dev, seed, rays_per_cell):
+    """R of a call: from ``dirs`` [N, R, d], or ``rays_per_cell`` when the
+    directions are drawn on the device from ``seed`` (``dirs`` None)."""
+    if dirs is None:
+        if seed is None or rays_per_cell is None:
+            raise ValueError("without dirs, give seed and rays_per_cell (directions drawn on the device)")
+        return int(rays_per_cell)
+    _dev(dirs, torch.float32, "dirs", dev)
+    if dirs.dim() != 3 or dirs.shape[0] != n or dirs.shape[2] != d:
+        raise ValueError("dirs must be [N, R, d]")
+    return dirs.shape[1]
+
+
+def raycast_cells(nodes, dirs=None, precision="fp32", recheck=True, incircle=False, seed=None,
+                  rays_per_cell=None):
+    """Monte-Carlo rays of every cell: ``dirs`` is ``[N, R, d]``, or None with
+    ``seed`` and ``rays_per_cell``: the directions are then drawn on the
+    device (Philox4x32-10, see :func:`dump_dirs`) and never stored.  Returns
     ``(t, idx, status)`` shaped ``[N, R]``."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
     n, d = nodes.shape
-    _dev(dirs, torch.float32, "dirs", dev)
-    if dirs.dim() != 3 or dirs.shape[0] != n or dirs.shape[2] != d:
-        raise ValueError("dirs must be [N, R, d]")
-    R = dirs.shape[1]
+    R = _rays_per_cell(dirs, n, d, dev, seed, rays_per_cell)
     t = torch.empty((n, R), dtype=torch.float32, device=dev)
     idx = torch.empty((n, R), dtype=torch.int32, device=dev)
     st = torch.empty((n, R), dtype=torch.uint8, device=dev)
     c = _ctx(dev)
-    _check(_lib.vg_raycast_cells(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck, incircle),
-                                 _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast_cells")
+    flags = _cells_flags(precision, recheck, incircle)
+    if dirs is None:
+        _check(_lib.vg_raycast_cells_seeded(c, d, n, _ptr(nodes), R, int(seed) & (2 ** 64 - 1), flags,
+                                            _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast_cells_seeded")
+    else:
+        _check(_lib.vg_raycast_cells(c, d, n, _ptr(nodes), R, _ptr(dirs), flags, _ptr(t), _ptr(idx), _ptr(st)),
+               c, "vg_raycast_cells")
     return t, idx, st
+
+
+def dump_dirs(d, n_cells, rays_per_cell, seed, first_cell=0, device=None):
+    """The directions the seeded calls draw for cells ``first_cell ..
+    first_cell + n_cells - 1``, as a ``[n_cells, rays_per_cell, d]`` float32
+    GPU tensor (bit for bit those of the kernels)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    out = torch.empty((n_cells, rays_per_cell, d), dtype=torch.float32, device=dev)
+    c = _ctx(dev)
+    _check(_lib.vg_dump_dirs(c, d, first_cell, n_cells, rays_per_cell, int(seed) & (2 ** 64 - 1), _ptr(out)),
+           c, "vg_dump_dirs")
+    return out
 
 
 @dataclass
@@ -246,6 +298,7 @@ class MCResult:
     t: torch.Tensor            # [N, R]
     idx: torch.Tensor          # [N, R]
     status: torch.Tensor       # [N, R]
+    seed: int | None = None    # directions drawn on the device from this seed (dirs None)
 
     def facets_coo(self):
         """Facets as host COO arrays ``(i, j, area)`` sorted by (i, j)."""
@@ -256,22 +309,21 @@ class MCResult:
         return i, self.facet_j.cpu().numpy()[mask], self.facet_area.cpu().numpy()[mask]
 
 
-def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out=None,
-                   neighbors=None, incircle=False) -> MCResult:
+def mc_volume_area(nodes, dirs=None, precision="fp32", facets=True, recheck=True, out=None,
+                   neighbors=None, incircle=False, seed=None, rays_per_cell=None) -> MCResult:
     """Monte-Carlo cell volumes, second moments and interface areas
     (Sec. 3.1, Algorithm 3 with f = 1).  ``out`` may pass a previous
     ``MCResult`` of the same shape to reuse its buffers.  ``neighbors`` =
     ``(offsets [N+1] int64, nbr [nnz] int32)`` (e.g. from
     :func:`tuple_neighbors`) restricts each cell's scan to its neighbours;
     ``incircle=True`` casts the rays by Algorithm 1 with a grid index
-    (d <= 6, FP32) instead of the dense scan."""
+    (d <= 6, FP32) instead of the dense scan.  ``dirs=None`` with ``seed``
+    and ``rays_per_cell`` draws the directions on the device (no
+    neighbours or incircle then)."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
     n, d = nodes.shape
-    _dev(dirs, torch.float32, "dirs", dev)
-    if dirs.dim() != 3 or dirs.shape[0] != n or dirs.shape[2] != d:
-        raise ValueError("dirs must be [N, R, d]")
-    R = dirs.shape[1]
+    R = _rays_per_cell(dirs, n, d, dev, seed, rays_per_cell)
     if out is None:
         out = MCResult(
             volume=torch.empty(n, dtype=torch.float32, device=dev),
@@ -282,7 +334,17 @@ def mc_volume_area(nodes, dirs, precision="fp32", facets=True, recheck=True, out
             t=torch.empty((n, R), dtype=torch.float32, device=dev),
             idx=torch.empty((n, R), dtype=torch.int32, device=dev),
             status=torch.empty((n, R), dtype=torch.uint8, device=dev))
+    out.seed = int(seed) if dirs is None else None
     c = _ctx(dev)
+    if dirs is None:
+        if neighbors is not None:
+            raise ValueError("neighbour lists need dirs")
+        _check(_lib.vg_mc_volume_area_seeded(c, d, n, _ptr(nodes), R, int(seed) & (2 ** 64 - 1),
+                                             _cells_flags(precision, recheck, incircle),
+                                             _ptr(out.t), _ptr(out.idx), _ptr(out.status), _ptr(out.volume),
+                                             _ptr(out.energy2), _ptr(out.facet_j), _ptr(out.facet_area),
+                                             _ptr(out.facet_count)), c, "vg_mc_volume_area_seeded")
+        return out
     if neighbors is None:
         _check(_lib.vg_mc_volume_area(c, d, n, _ptr(nodes), R, _ptr(dirs),
                                       _cells_flags(precision, recheck, incircle),
@@ -423,14 +485,20 @@ def hmc_integrals(nodes, mesh, res: MCResult, f) -> HMCResult:
     return out
 
 
-def mc_backward(nodes, dirs, res: MCResult, g_volume=None, g_energy2=None, g_facet_area=None):
+def mc_backward(nodes, dirs, res: MCResult, g_volume=None, g_energy2=None, g_facet_area=None, out=None):
     """Gradient with respect to the generator positions of
     ``<g_volume, volume> + <g_energy2, energy2> + <g_facet_area, facet_area>``
-    with the directions frozen.  Returns ``[N, d]`` float32."""
+    with the directions frozen.  ``dirs=None``: the forward drew them on the
+    device (``res.seed``).  Returns ``[N, d]`` float32 (written into ``out``
+    when given)."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
     n, d = nodes.shape
-    R = dirs.shape[1]
+    R = res.t.shape[1]
+    if dirs is None and res.seed is None:
+        raise ValueError("dirs is None but the forward result has no seed")
+    if dirs is not None and dirs.shape != (n, R, d):
+        raise ValueError("dirs must be [N, R, d]")
     for name, g in (("g_volume", g_volume), ("g_energy2", g_energy2)):
         if g is not None:
             _dev(g, torch.float32, name, dev)
@@ -440,8 +508,18 @@ def mc_backward(nodes, dirs, res: MCResult, g_volume=None, g_energy2=None, g_fac
         _dev(g_facet_area, torch.float32, "g_facet_area", dev)
         if g_facet_area.shape != (n, R) or res.facet_j is None:
             raise ValueError("g_facet_area must be [N, R] and the forward must have facets")
-    grad = torch.empty((n, d), dtype=torch.float32, device=dev)
+    if out is not None:
+        _dev(out, torch.float32, "out", dev)
+        if out.shape != (n, d):
+            raise ValueError("out must be [N, d]")
+    grad = out if out is not None else torch.empty((n, d), dtype=torch.float32, device=dev)
     c = _ctx(dev)
+    if dirs is None:
+        _check(_lib.vg_mc_backward_seeded(c, d, n, _ptr(nodes), R, res.seed & (2 ** 64 - 1), _ptr(res.t),
+                                          _ptr(res.idx), _ptr(res.facet_j), _ptr(res.facet_count),
+                                          _ptr(g_volume), _ptr(g_energy2), _ptr(g_facet_area), _ptr(grad)),
+               c, "vg_mc_backward_seeded")
+        return grad
     _check(_lib.vg_mc_backward(c, d, n, _ptr(nodes), R, _ptr(dirs), _ptr(res.t), _ptr(res.idx),
                                _ptr(res.facet_j), _ptr(res.facet_count), _ptr(g_volume),
                                _ptr(g_energy2), _ptr(g_facet_area), _ptr(grad)), c, "vg_mc_backward")
@@ -449,7 +527,9 @@ def mc_backward(nodes, dirs, res: MCResult, g_volume=None, g_energy2=None, g_fac
 
 
 class VoronoiMC(torch.autograd.Function):
-    """``(volume, energy2, facet_area) = VoronoiMC.apply(nodes, dirs)``.
+    """``(volume, energy2, facet_area) = VoronoiMC.apply(nodes, dirs)``, or
+    ``VoronoiMC.apply(nodes, None, precision, seed, rays_per_cell)`` with the
+    directions drawn on the device.
 
     The forward is ``mc_volume_area``; the backward is the closed-form adjoint
     through the winning bisectors (``mc_backward``), directions frozen.
@@ -459,9 +539,11 @@ class VoronoiMC(torch.autograd.Function):
     last_result: MCResult | None = None
 
     @staticmethod
-    def forward(ctx, nodes, dirs, precision="fp32"):
-        res = mc_volume_area(nodes.detach().contiguous(), dirs, precision=precision, facets=True)
-        ctx.save_for_backward(nodes, dirs)
+    def forward(ctx, nodes, dirs, precision="fp32", seed=None, rays_per_cell=None):
+        res = mc_volume_area(nodes.detach().contiguous(), dirs, precision=precision, facets=True, seed=seed,
+                             rays_per_cell=rays_per_cell)
+        ctx.save_for_backward(nodes, dirs if dirs is not None else nodes.new_empty(0))
+        ctx.seeded = dirs is None
         ctx.res = res
         VoronoiMC.last_result = res
         return res.volume, res.energy2, res.facet_area
@@ -470,9 +552,9 @@ class VoronoiMC(torch.autograd.Function):
     def backward(ctx, g_volume, g_energy2, g_facet_area):
         nodes, dirs = ctx.saved_tensors
         f = lambda g: None if g is None else g.contiguous().float()
-        grad = mc_backward(nodes.detach().contiguous(), dirs, ctx.res, f(g_volume), f(g_energy2),
-                           f(g_facet_area))
-        return grad, None, None
+        grad = mc_backward(nodes.detach().contiguous(), None if ctx.seeded else dirs, ctx.res, f(g_volume),
+                           f(g_energy2), f(g_facet_area))
+        return grad, None, None, None, None
 
 
 def raycast_cells_batched(problems, precision="fp32", out=None):

@@ -56,19 +56,19 @@ struct Carver {
   }
 };
 
+// Grow the context scratch.  The old block is not freed but kept until
+// vg_destroy: a call captured into a graph earlier still reads it.  Growing
+// at least twofold bounds the kept blocks by the live one.
 int ensure_scratch(vg_ctx *ctx, size_t bytes) {
   if (bytes <= ctx->scratch_bytes) return VG_OK;
-  if (ctx->scratch) {
-    VG_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    VG_HIP(ctx, hipFree(ctx->scratch));
-    ctx->scratch = nullptr;
-    ctx->scratch_bytes = 0;
-  }
-  size_t want = bytes + bytes / 4;
-  if (hipMalloc(&ctx->scratch, want) != hipSuccess) {
-    ctx->scratch = nullptr;
+  const size_t want = std::max(bytes + bytes / 4, 2 * ctx->scratch_bytes);
+  void *p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
     return fail(ctx, VG_ENOMEM, "scratch allocation of %zu bytes failed", want);
   }
+  if (ctx->scratch) ctx->retired.push_back(ctx->scratch);
+  ctx->scratch = p;
   ctx->scratch_bytes = want;
   return VG_OK;
 }
@@ -88,8 +88,8 @@ int check_common(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes) {
 struct ScanTimer {
   vg_ctx *ctx;
   hipEvent_t a = nullptr, b = nullptr;
-  explicit ScanTimer(vg_ctx *c) : ctx(c) {
-    if (!ctx->profiling) return;
+  explicit ScanTimer(vg_ctx *c, bool enable = true) : ctx(c) {
+    if (!enable || !ctx->profiling) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       ctx->profiling = false;
       return;
@@ -106,48 +106,46 @@ struct ScanTimer {
 
 double sphere_area(int d) { return 2.0 * std::pow(M_PI, 0.5 * d) / std::tgamma(0.5 * d); }
 
-int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const float *dirs,
-              uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *st_out,
-              const int64_t *nbr_off = nullptr, const int32_t *nbr = nullptr) {
+}  // namespace
+
+namespace vg {
+
+int run_cells_in(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const float *dirs,
+                 uint64_t seed, uint32_t flags, float *t_out, int32_t *idx_out, const CellsScratch &sc,
+                 const int64_t *nbr_off, const int32_t *nbr) {
   const int64_t m = n * (int64_t)R;
   const bool recheck = !(flags & VG_NO_RECHECK);
   const bool bf16 = (flags & VG_PREC_BF16X3) != 0;
   const bool incircle = (flags & VG_INCIRCLE) != 0;
-  if (incircle && (bf16 || nbr || d > 6))
-    return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs d <= 6, FP32 and no neighbour lists");
-  const size_t grid_bytes = incircle ? incircle_scratch_bytes(n, d, R) : 0;
-  const size_t parts_bytes = recheck ? recheck_cells_reserve(m, n) : 0;
-  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes, parts_bytes});
-  int rc = ensure_scratch(ctx, need);
-  if (rc) return rc;
-  Carver cv(ctx->scratch);
-  int64_t *flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
-  uint8_t *st = st_out ? st_out : cv.take<uint8_t>(m);
-  void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
-  void *parts = parts_bytes ? cv.take<char>(parts_bytes) : nullptr;
-  ctx->last_counters = ctx->counters;
-  VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
+  int64_t *flag_list = recheck ? sc.flag_list : nullptr;
+  uint8_t *st = sc.status;
+  void *grid_scratch = sc.grid;
+  void *parts = sc.parts;
+  const size_t parts_bytes = sc.parts_bytes;
+  ctx->last_counters = sc.counters;
+  VG_HIP(ctx, fill_u32(sc.counters, 0u, CNT_WORDS, ctx->stream));
 
   CellScanArgs a{};
   a.nodes = nodes;
   a.n = n;
   a.d = d;
   a.dirs = dirs;
+  a.seed = seed;
   a.R = R;
   a.t_out = t_out;
   a.idx_out = idx_out;
   a.st_out = st;
-  a.counters = ctx->counters;
+  a.counters = sc.counters;
   a.flag_list = flag_list;
   a.tau_rel = bf16 ? kTauCellsBf16 : kTauCellsFp32;
   a.kappa = cell_kappa(d, bf16);
   a.nbr_off = nbr_off;
   a.nbr = nbr;
-  ScanTimer timer(ctx);
+  ScanTimer timer(ctx, sc.timed);
   hipError_t e;
   if (incircle)
     e = launch_incircle_cells(a, grid_scratch,
-                              reinterpret_cast<unsigned long long *>(ctx->counters + CNT_NN_CALLS), ctx->stream);
+                              reinterpret_cast<unsigned long long *>(sc.counters + CNT_NN_CALLS), ctx->stream);
   else
     e = bf16 ? launch_cell_scan_bf16x3(a, ctx->stream) : launch_cell_scan_fp32(a, ctx->stream);
   timer.stop();
@@ -159,14 +157,15 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
     r.n = n;
     r.d = d;
     r.dirs = dirs;
+    r.seed = seed;
     r.R = R;
     r.clip = 1;
-    r.counters = ctx->counters;
+    r.counters = sc.counters;
     r.flag_list = flag_list;
     r.t_out = t_out;
     r.idx_out = idx_out;
     r.st_out = st;
-    r.tie_counter = ctx->counters + CNT_FP64_TIE;
+    r.tie_counter = sc.counters + CNT_FP64_TIE;
     if (!launch_recheck_cells_split(r, m, parts, parts_bytes, ctx->stream, e))
       e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
@@ -174,6 +173,38 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   ctx->last_rays = m;
   ctx->last_tau = a.tau_rel;
   return VG_OK;
+}
+
+}  // namespace vg
+
+namespace {
+
+// run_cells_in with the scratch carved out of the context's (grown on demand).
+int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const float *dirs, uint64_t seed,
+              uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *st_out,
+              const int64_t *nbr_off = nullptr, const int32_t *nbr = nullptr) {
+  const int64_t m = n * (int64_t)R;
+  const bool recheck = !(flags & VG_NO_RECHECK);
+  const bool bf16 = (flags & VG_PREC_BF16X3) != 0;
+  const bool incircle = (flags & VG_INCIRCLE) != 0;
+  if (incircle && (bf16 || nbr || d > 6 || !dirs))
+    return fail(ctx, VG_EUNSUPPORTED,
+                "VG_INCIRCLE needs d <= 6, FP32, no neighbour lists and directions as input");
+  const size_t grid_bytes = incircle ? incircle_scratch_bytes(n, d, R) : 0;
+  const size_t parts_bytes = recheck ? recheck_cells_reserve(m, n) : 0;
+  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes, parts_bytes});
+  int rc = ensure_scratch(ctx, need);
+  if (rc) return rc;
+  Carver cv(ctx->scratch);
+  CellsScratch sc{};
+  sc.flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
+  sc.status = st_out ? st_out : cv.take<uint8_t>(m);
+  sc.grid = incircle ? cv.take<char>(grid_bytes) : nullptr;
+  sc.parts = parts_bytes ? cv.take<char>(parts_bytes) : nullptr;
+  sc.parts_bytes = parts_bytes;
+  sc.counters = ctx->counters;
+  sc.timed = true;
+  return run_cells_in(ctx, d, n, nodes, R, dirs, seed, flags, t_out, idx_out, sc, nbr_off, nbr);
 }
 
 }  // namespace
@@ -291,14 +322,32 @@ void vg_destroy(vg_ctx *ctx) {
     (void)hipEventDestroy(ev.second);
   }
   batch_state_free(ctx);
+  if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
+  for (void *p : ctx->retired) (void)hipFree(p);
   if (ctx->counters) (void)hipFree(ctx->counters);
   delete ctx;
 }
 
 int vg_set_stream(vg_ctx *ctx, void *stream) {
   if (!ctx) return VG_EINVAL;
-  ctx->stream = static_cast<hipStream_t>(stream);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (s == ctx->stream) return VG_OK;
+  // Every call of a context shares its counters, its scratch (recheck queue,
+  // split partials) and the batch buffers, so work enqueued on the new stream
+  // must not start before the old stream has finished this context's earlier
+  // calls: the new stream waits for an event recorded on the old one.
+  VG_HIP(ctx, hipSetDevice(ctx->device));
+  if (!ctx->handoff) VG_HIP(ctx, hipEventCreateWithFlags(&ctx->handoff, hipEventDisableTiming));
+  if (hipEventRecord(ctx->handoff, ctx->stream) == hipSuccess) {
+    VG_HIP(ctx, hipStreamWaitEvent(s, ctx->handoff, 0));
+  } else {
+    // the old stream cannot take an event (e.g. it was destroyed): wait for
+    // all work on the device instead
+    (void)hipGetLastError();
+    VG_HIP(ctx, hipDeviceSynchronize());
+  }
+  ctx->stream = s;
   return VG_OK;
 }
 
@@ -433,7 +482,7 @@ int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, in
   if (rays_per_cell < 1 || rays_per_cell > 4096)
     return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
   if (!dirs || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null array");
-  return run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, flags, t_out, idx_out, status_out);
+  return run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, 0, flags, t_out, idx_out, status_out);
 }
 
 }  // extern "C"
@@ -441,18 +490,19 @@ int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, in
 namespace {
 
 int mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const int64_t *nbr_off,
-                   const int32_t *nbr, int rays_per_cell, const float *dirs, uint32_t flags,
+                   const int32_t *nbr, int rays_per_cell, const float *dirs, uint64_t seed, bool seeded,
+                   uint32_t flags,
                    float *t_out, int32_t *idx_out, uint8_t *status_out, float *volume,
                    float *energy2, int32_t *facet_j, float *facet_area, int32_t *facet_count) {
   int rc = check_common(ctx, d, n_nodes, nodes);
   if (rc) return rc;
   if (rays_per_cell < 1 || rays_per_cell > 4096)
     return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
-  if (!dirs || !t_out || !idx_out || !volume) return fail(ctx, VG_EINVAL, "null array");
+  if ((!dirs && !seeded) || !t_out || !idx_out || !volume) return fail(ctx, VG_EINVAL, "null array");
   const int nf = (facet_j != nullptr) + (facet_area != nullptr) + (facet_count != nullptr);
   if (nf != 0 && nf != 3) return fail(ctx, VG_EINVAL, "facet outputs must be all set or all NULL");
-  rc = run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, flags, t_out, idx_out, status_out,
-                 nbr_off, nbr);
+  rc = run_cells(ctx, d, n_nodes, nodes, rays_per_cell, seeded ? nullptr : dirs, seed, flags, t_out, idx_out,
+                 status_out, nbr_off, nbr);
   if (rc) return rc;
   const double S = sphere_area(d);
   AccumArgs a{};
@@ -483,7 +533,7 @@ int vg_mc_volume_area(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, i
                       const float *dirs, uint32_t flags, float *t_out, int32_t *idx_out,
                       uint8_t *status_out, float *volume, float *energy2, int32_t *facet_j,
                       float *facet_area, int32_t *facet_count) {
-  return mc_volume_area(ctx, d, n_nodes, nodes, nullptr, nullptr, rays_per_cell, dirs, flags, t_out,
+  return mc_volume_area(ctx, d, n_nodes, nodes, nullptr, nullptr, rays_per_cell, dirs, 0, false, flags, t_out,
                         idx_out, status_out, volume, energy2, facet_j, facet_area, facet_count);
 }
 
@@ -494,8 +544,43 @@ int vg_mc_volume_area_nbr(vg_ctx *ctx, int d, int64_t n_nodes, const float *node
                           float *facet_area, int32_t *facet_count) {
   if (!ctx) return VG_EINVAL;
   if (!nbr_offsets || !nbr) return fail(ctx, VG_EINVAL, "nbr_offsets and nbr are required");
-  return mc_volume_area(ctx, d, n_nodes, nodes, nbr_offsets, nbr, rays_per_cell, dirs, flags, t_out,
+  return mc_volume_area(ctx, d, n_nodes, nodes, nbr_offsets, nbr, rays_per_cell, dirs, 0, false, flags, t_out,
                         idx_out, status_out, volume, energy2, facet_j, facet_area, facet_count);
+}
+
+int vg_raycast_cells_seeded(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                            uint64_t seed, uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *status_out) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (!t_out || !idx_out) return fail(ctx, VG_EINVAL, "null array");
+  return run_cells(ctx, d, n_nodes, nodes, rays_per_cell, nullptr, seed, flags, t_out, idx_out, status_out);
+}
+
+int vg_mc_volume_area_seeded(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                             uint64_t seed, uint32_t flags, float *t_out, int32_t *idx_out,
+                             uint8_t *status_out, float *volume, float *energy2, int32_t *facet_j,
+                             float *facet_area, int32_t *facet_count) {
+  return mc_volume_area(ctx, d, n_nodes, nodes, nullptr, nullptr, rays_per_cell, nullptr, seed, true, flags,
+                        t_out, idx_out, status_out, volume, energy2, facet_j, facet_area, facet_count);
+}
+
+int vg_dump_dirs(vg_ctx *ctx, int d, int64_t first_cell, int64_t n_cells, int rays_per_cell, uint64_t seed,
+                 float *out) {
+  if (!ctx) return VG_EINVAL;
+  ctx->err.clear();
+  if (d < 2 || d > VG_MAX_DIM) return fail(ctx, VG_EUNSUPPORTED, "d=%d outside [2, %d]", d, VG_MAX_DIM);
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (first_cell < 0 || n_cells < 0 || first_cell + n_cells > (int64_t(1) << 31))
+    return fail(ctx, VG_EINVAL, "cells [%lld, %lld) outside [0, 2^31)", (long long)first_cell,
+                (long long)(first_cell + n_cells));
+  if (n_cells == 0) return VG_OK;
+  if (!out) return fail(ctx, VG_EINVAL, "out is NULL");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, VG_EDEVICE, "hipSetDevice failed");
+  VG_HIP(ctx, launch_dump_dirs(d, first_cell, n_cells, rays_per_cell, seed, out, ctx->stream));
+  return VG_OK;
 }
 
 int vg_mc_sample_points(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
@@ -594,15 +679,20 @@ int vg_tuple_neighbors(vg_ctx *ctx, int d, int64_t n_nodes, int64_t n_tuples, co
                          ctx->err);
 }
 
-int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
-                   const float *dirs, const float *t, const int32_t *idx, const int32_t *facet_j,
-                   const int32_t *facet_count, const float *g_volume, const float *g_energy2,
-                   const float *g_facet_area, float *grad_nodes) {
+}  // extern "C"
+
+namespace {
+
+int mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                const float *dirs, uint64_t seed, bool seeded, const float *t, const int32_t *idx,
+                const int32_t *facet_j, const int32_t *facet_count, const float *g_volume,
+                const float *g_energy2, const float *g_facet_area, float *grad_nodes) {
   int rc = check_common(ctx, d, n_nodes, nodes);
   if (rc) return rc;
   if (rays_per_cell < 1 || rays_per_cell > 4096)
     return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
-  if (!dirs || !t || !idx || !grad_nodes) return fail(ctx, VG_EINVAL, "null array");
+  if ((!dirs && !seeded) || !t || !idx || !grad_nodes) return fail(ctx, VG_EINVAL, "null array");
+  if (seeded) dirs = nullptr;
   if (g_facet_area && (!facet_j || !facet_count))
     return fail(ctx, VG_EINVAL, "g_facet_area needs facet_j and facet_count");
   const int64_t n = n_nodes, m = n * (int64_t)rays_per_cell;
@@ -627,6 +717,7 @@ int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int 
   a.d = d;
   a.R = rays_per_cell;
   a.dirs = dirs;
+  a.seed = seed;
   a.t = t;
   a.idx = idx;
   a.facet_j = facet_j;
@@ -641,6 +732,26 @@ int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int 
   hipError_t e = launch_backward(a, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "backward launch");
   return VG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vg_mc_backward(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                   const float *dirs, const float *t, const int32_t *idx, const int32_t *facet_j,
+                   const int32_t *facet_count, const float *g_volume, const float *g_energy2,
+                   const float *g_facet_area, float *grad_nodes) {
+  return mc_backward(ctx, d, n_nodes, nodes, rays_per_cell, dirs, 0, false, t, idx, facet_j, facet_count,
+                     g_volume, g_energy2, g_facet_area, grad_nodes);
+}
+
+int vg_mc_backward_seeded(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                          uint64_t seed, const float *t, const int32_t *idx, const int32_t *facet_j,
+                          const int32_t *facet_count, const float *g_volume, const float *g_energy2,
+                          const float *g_facet_area, float *grad_nodes) {
+  return mc_backward(ctx, d, n_nodes, nodes, rays_per_cell, nullptr, seed, true, t, idx, facet_j, facet_count,
+                     g_volume, g_energy2, g_facet_area, grad_nodes);
 }
 
 }  // extern "C"

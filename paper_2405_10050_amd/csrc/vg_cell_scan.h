@@ -1,0 +1,523 @@
+// Monte-Carlo RayCast of every cell on MFMA (gfx950): FP32 and split BF16x3.
+//
+// A ray of cell i starts at the generator x_i with eta = {i} (Algorithm 3),
+// so eq. (t) reads t_r = |r - x_i|^2 / (2 u.(r - x_i)).  Inverting the nodes
+// about x_i,  r~ = (r - x_i) / |r - x_i|^2,  gives  1 / (2 t_r) = u . r~,
+// and the half-space restriction u.(r - x_i) > 0 becomes u . r~ > 0.  So
+//     t* = 1 / (2 max_r u . r~)
+// and the whole candidate scan of a cell is one dense contraction
+// S = R~ . U^T (nodes x directions, K = d) with a max/argmax epilogue: no
+// division, no mask, no cancellation between |r|^2 and x.r.  The faces of
+// the cube are the mirror images of x_i and enter the same max in closed
+// form: face x_k = 1 gives u_k / (2 (1 - x_k)), face x_k = 0 gives
+// -u_k / (2 x_k).
+//
+// Work decomposition: one workgroup per (cell, chunk of RW rays).  Each wave
+// owns C column blocks of 32 rays and keeps their directions as the MFMA B
+// operand for the whole scan.  Nodes stream through LDS in chunks of one node
+// per thread; every thread builds the inverted coordinates of its node
+// (the X.R^T part of the scan, once per cell and node) and the waves then run
+// v_mfma_f32_32x32x2_f32 over 32-node blocks.  Output layout of that MFMA:
+// lane l holds column l%32 (one ray) and rows 8*(i/4) + 4*(l/32) + i%4 of
+// register i, so the max over a lane's 16 values is register-local.
+//
+// Epilogue: per lane a running (best, second, argmax).  A 16-value block
+// whose max does not exceed the lane's second best cannot change anything
+// (fast path: an integer v_max3 tree over the bit patterns and one compare;
+// best and second are never negative, and non-negative floats order like
+// their bit patterns); otherwise every value updates the top-2 with v_med3
+// and the argmax with a compare/select.
+//
+// Near-tie certificate: with |u| = 1 the FP32 value of u.r~ is within
+// (2d+4) 2^-24 |r~| of the exact one, and |r~| <= 1/nn_i (nn_i = distance to
+// the nearest other node), so a gap above 2 (2d+4) 2^-24 / nn_i certifies the
+// argmax.  Rays below max(kappa / nn_i, tau_rel * best) are queued for the
+// FP64 recheck.  The winner's t* is re-evaluated from its two points in
+// double-float arithmetic (error-free transformations), about FP32 rounding.
+#pragma once
+
+#include "vg_dfloat.h"
+#include "vg_internal.h"
+#include "vg_philox.h"
+
+namespace vg {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int imax3(int a, int b, int c) { return max(max(a, b), c); }
+// Maximum of the 16 values' bit patterns as signed integers: for a maximum
+// >= +0 it is the bit pattern of the float maximum; otherwise it is negative.
+__device__ __forceinline__ int max16_bits(const f32x16 &v) {
+  int b[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) b[i] = __float_as_int(v[i]);
+  const int m1 = imax3(b[0], b[1], b[2]), m2 = imax3(b[3], b[4], b[5]);
+  const int m3 = imax3(b[6], b[7], b[8]), m4 = imax3(b[9], b[10], b[11]);
+  const int m5 = imax3(b[12], b[13], b[14]);
+  return max(imax3(m1, m2, m3), imax3(m4, m5, b[15]));
+}
+
+// Top-2 update of one lane with the 16 accumulator values of a 32x32 block.
+// The argmax is kept encoded as (32-row block << 4) | register (decoded by
+// decode_row), so the update needs no per-row index arithmetic.
+__device__ __forceinline__ void epilogue16(const f32x16 &acc, float &best, float &second,
+                                           int &bidx, int blk16) {
+  if (max16_bits(acc) > __float_as_int(second)) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float s = acc[i];
+      second = __builtin_amdgcn_fmed3f(s, best, second);
+      if (s > best) {
+        best = s;
+        bidx = blk16 | i;
+      }
+    }
+  }
+}
+
+// Node row of an encoded argmax held by `lane` (MFMA output layout above).
+__device__ __forceinline__ int decode_row(int e, int lane) {
+  if (e < 0) return e;
+  return (e >> 4) * 32 + 8 * ((e & 15) >> 2) + (e & 3) + 4 * (lane >> 5);
+}
+
+// Coordinates of node r (zero beyond n or d).
+template <int DK>
+__device__ __forceinline__ void load_node(const float *__restrict__ nodes, int64_t n, int d,
+                                          int64_t r, float (&x)[DK]) {
+  const bool ok = r < n;
+  const float *xr = nodes + (ok ? r : 0) * d;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) x[k] = (ok && k < d) ? xr[k] : 0.f;
+}
+
+// Inverted coordinates r~ = (x_r - x_i)/|x_r - x_i|^2 of node r about x_i (zero
+// for r = i, beyond n, and for a duplicate of x_i, which eq. (t) never makes
+// eligible).  Returns |x_r - x_i|^2 (or +inf when not a node).
+template <int DK>
+__device__ __forceinline__ float invert_node(const float (&xr)[DK], const float (&xi)[DK],
+                                             int64_t r, int64_t n, int64_t cell, float (&rt)[DK]) {
+  if (r >= n || r == cell) {
+#pragma unroll
+    for (int k = 0; k < DK; ++k) rt[k] = 0.f;
+    return __builtin_inff();
+  }
+  float n2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    rt[k] = xr[k] - xi[k];
+    n2 = __builtin_fmaf(rt[k], rt[k], n2);
+  }
+  const float inv = n2 > 0.f ? __builtin_amdgcn_rcpf(n2) : 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) rt[k] *= inv;
+  return n2;
+}
+
+// Node scanned as row r of `cell`: the row itself, or the r-th entry of the
+// cell's candidate list.  Rows past the end and entries outside [0, n) give
+// n, which load_node and invert_node treat as padding (a zero row never wins:
+// the eligibility threshold is u.r~ > 0).
+__device__ __forceinline__ int64_t row_node(const CellScanArgs &a, int64_t nb0, int64_t n_scan,
+                                            int64_t r) {
+  if (!a.nbr) return r;
+  if (r >= n_scan) return a.n;
+  const int32_t j = a.nbr[nb0 + r];
+  return (j >= 0 && j < a.n) ? j : a.n;
+}
+
+// Merge the two lanes of each ray, add the cube faces, certify the gap,
+// re-evaluate t* and write the ray results.
+template <int C, int DK, int NT, bool GEN>
+__device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (&xi)[DK],
+                                            float (&best)[C], float (&second)[C], int (&bidx)[C],
+                                            float nn2, float *red, int lane, int rayw,
+                                            int64_t cell, int64_t nb0, int64_t n_scan) {
+  const int d = a.d;
+  const int R = a.R;
+  // nearest-neighbour distance of x_i (for the error certificate)
+  const int tid = threadIdx.x;
+  red[tid] = nn2;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fminf(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const float nn = sqrtf(red[0]);
+
+  // merge the two lanes that hold each ray (rows split by l/32)
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    bidx[cb] = decode_row(bidx[cb], lane);
+    const float ob = __shfl_xor(best[cb], 32);
+    const float os = __shfl_xor(second[cb], 32);
+    const int oi = __shfl_xor(bidx[cb], 32);
+    const bool take = (ob > best[cb]) || (ob == best[cb] && oi >= 0 && (bidx[cb] < 0 || oi < bidx[cb]));
+    const float other = take ? best[cb] : ob;
+    if (take) {
+      best[cb] = ob;
+      bidx[cb] = oi;
+    }
+    second[cb] = fmaxf(fmaxf(second[cb], os), other);
+  }
+  if (lane >= 32) return;
+
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    const int ray = rayw + cb * 32 + lane;
+    if (ray >= R) continue;
+    const int64_t gid = (int64_t)cell * R + ray;
+    float u[DK];
+    cell_dir<DK>(GEN ? nullptr : a.dirs, a.seed, cell, R, ray, d, u);
+    // cube faces as mirror images of x_i
+    float sbox = 0.f, tbox = __builtin_inff();
+    int face = -1;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d && u[k] != 0.f) {
+        const float h = u[k] > 0.f ? 1.f - xi[k] : xi[k];
+        const float sk = fabsf(u[k]) / (2.f * h);
+        if (sk > sbox) {
+          sbox = sk;
+          tbox = h / fabsf(u[k]);
+          face = 2 * k + (u[k] > 0.f ? 1 : 0);
+        }
+      }
+    }
+    float s1 = best[cb], s2 = second[cb];
+    int j = bidx[cb];
+    if (face >= 0) {
+      if (sbox > s1) {
+        s2 = fmaxf(s2, s1);
+        s1 = sbox;
+        j = -2 - face;
+      } else {
+        s2 = fmaxf(s2, sbox);
+      }
+    }
+    uint8_t st = 0;
+    const float thr = fmaxf(a.tau_rel * s1, a.kappa / nn);
+    bool tie = !(s1 - s2 > thr);
+    float t;
+    const int64_t node = (j >= 0 && j < n_scan) ? row_node(a, nb0, n_scan, j) : a.n;
+    if (j >= 0 && node >= a.n) {  // cannot happen with the documented MFMA layout; never dereference
+      j = -1;
+      t = __builtin_nanf("");
+      st |= VG_ST_SUSPECT;
+      tie = true;
+    } else if (j >= 0) {
+      j = (int)node;
+      t = reeval_cell<DK>(xi, a.nodes + node * d, u, d);
+    } else if (j <= -2) {
+      t = tbox;
+    } else {
+      t = __builtin_inff();
+      st |= VG_ST_NO_HIT;
+      tie = true;
+    }
+    if (tie && a.flag_list) {
+      st |= VG_ST_NEAR_TIE;
+      const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
+      a.flag_list[pos] = gid | a.flag_tag;
+    }
+    a.t_out[gid] = t;
+    a.idx_out[gid] = j;
+    a.st_out[gid] = st;
+  }
+}
+
+// LDS tile of the FP32 scan: row k holds coordinate k of the chunk's NB
+// inverted nodes; rows are NB + 32 floats apart so that the two K halves of
+// an MFMA operand (lanes 0-31 and 32-63) fall in different bank halves.
+template <int KP, int WAVES>
+struct Fp32Tile {
+  static constexpr int NB = WAVES * 64;
+  static constexpr int LS = NB + 32;
+  static constexpr int FLOATS = 2 * KP * LS;
+};
+
+// Accumulators of one column block of a 32-node block.
+template <int KP>
+__device__ __forceinline__ f32x16 scan_block(const float (&A)[KP], const float (&ub)[KP]) {
+  f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kp = 0; kp < KP; ++kp) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[kp], ub[kp], acc, 0, 0, 0);
+  return acc;
+}
+
+// One work item of the FP32 scan: rays [chunk*RW, chunk*RW + RW) of `cell`.
+// lds holds Fp32Tile<KP, WAVES>::FLOATS floats, red WAVES*64 floats.  One
+// accumulator set per wave is reused by the column blocks in turn: separate
+// sets would cost the occupancy that hides each block's epilogue.
+template <int KP, int C, int WAVES, bool GEN>
+__device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t cell, int chunk,
+                                               float *__restrict__ lds, float *red) {
+  constexpr int NT = WAVES * 64;
+  constexpr int NB = Fp32Tile<KP, WAVES>::NB;  // nodes per LDS chunk (one per thread)
+  constexpr int LS = Fp32Tile<KP, WAVES>::LS;
+  constexpr int RW = WAVES * C * 32;           // rays per workgroup
+  constexpr int DK = 2 * KP;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int d = a.d;
+  const int64_t n = a.n;
+  const int R = a.R;
+
+  float xi[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+
+  // B operand: lane l holds u[ray l%32][2kp + l/32] of each column block.
+  const int rayw = chunk * RW + wave * (C * 32);
+  float ub[C][KP];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    const int ray = rayw + cb * 32 + (lane & 31);
+    if constexpr (!GEN) {
+      const float *up = a.dirs + ((int64_t)cell * R + ray) * d;
+#pragma unroll
+      for (int kp = 0; kp < KP; ++kp) {
+        const int k = 2 * kp + (lane >> 5);
+        ub[cb][kp] = (ray < R && k < d) ? up[k] : 0.f;
+      }
+    } else {
+      float u[DK];
+      cell_dir<DK>(nullptr, a.seed, cell, R, ray, d, u);
+#pragma unroll
+      for (int kp = 0; kp < KP; ++kp) ub[cb][kp] = (lane & 32) ? u[2 * kp + 1] : u[2 * kp];
+    }
+  }
+
+  float best[C], second[C];
+  int bidx[C];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    best[cb] = 0.f;  // eligibility: u.r~ > 0
+    second[cb] = 0.f;
+    bidx[cb] = -1;
+  }
+  float nn2 = __builtin_inff();
+
+  // A operand: lane l reads row 2kp + l/32, column l%32 of each node block
+  const float *lrow = lds + (lane >> 5) * LS + (lane & 31);
+
+  // the coordinates of the next chunk's node are loaded one chunk ahead, so
+  // their latency hides behind the MFMA loop of the current chunk
+  const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
+  const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
+  float pre[DK];
+  load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, tid), pre);
+  for (int64_t base = 0; base < n_scan; base += NB) {
+    float rt[DK];
+    nn2 = fminf(nn2, invert_node<DK>(pre, xi, row_node(a, nb0, n_scan, base + tid), n, cell, rt));
+    load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, base + NB + tid), pre);
+    __syncthreads();  // the previous chunk is consumed
+#pragma unroll
+    for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
+    __syncthreads();
+    const int64_t rem = n_scan - base;
+    const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
+    const int blk0 = (int)(base >> 5);
+    for (int nb = 0; nb < nblocks; ++nb) {
+      float A[KP];
+#pragma unroll
+      for (int kp = 0; kp < KP; ++kp) A[kp] = lrow[2 * kp * LS + nb * 32];
+      const int blk16 = (blk0 + nb) << 4;
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) {
+        const f32x16 acc = scan_block<KP>(A, ub[cb]);
+        epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
+      }
+    }
+  }
+
+  cell_finish<C, DK, NT, GEN>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
+}
+
+// GEN: the directions are drawn from a.seed (a.dirs is null), else read.
+template <int KP, int C, int WAVES, bool GEN>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs a) {
+  __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS];
+  __shared__ float red[WAVES * 64];
+  const int64_t cell = blockIdx.x / a.wg_per_cell;
+  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  scan_fp32_item<KP, C, WAVES, GEN>(a, cell, chunk, lds, red);
+}
+
+// ---------------------------------------------------------------- BF16x3
+// Split-precision variant: a = a_hi + a_lo with a_hi = bf16(a) and
+// a_lo = bf16(a - a_hi); u.r~ ~ sum hi*hi + hi*lo + lo*hi with FP32
+// accumulation.  The three products are packed along K: the node operand is
+// [hi | hi | lo] and the direction operand [hi | lo | hi], each block DKP long
+// (DKP = 5, 10 or 16 so that 3 DKP fits KQ MFMA K-blocks of 16), padded with
+// zeros.  Both operands use the same K slot for the same product, so the
+// v_mfma_f32_32x32x16_bf16 K ordering inside a lane does not matter.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int KQ>
+struct Bf16Pack {
+  static constexpr int DKP = KQ == 1 ? 5 : (KQ == 2 ? 10 : 16);
+  static constexpr int KT = 16 * KQ;
+};
+
+__device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// One work item of the BF16x3 scan; lds holds WAVES*64 * KT/8 bf16x8.
+template <int KQ, int C, int WAVES, bool GEN>
+__device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t cell, int chunk,
+                                                 bf16x8 *__restrict__ lds, float *red) {
+  constexpr int NT = WAVES * 64;
+  constexpr int NB = NT;
+  constexpr int RW = WAVES * C * 32;
+  constexpr int DKP = Bf16Pack<KQ>::DKP;
+  constexpr int KT = Bf16Pack<KQ>::KT;
+  constexpr int DK = DKP;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int d = a.d;
+  const int64_t n = a.n;
+  const int R = a.R;
+
+  float xi[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+
+  const int rayw = chunk * RW + wave * (C * 32);
+  bf16x8 ub[C][KQ];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    const int ray = rayw + cb * 32 + (lane & 31);
+    float u[DKP];
+    cell_dir<DKP>(GEN ? nullptr : a.dirs, a.seed, cell, R, ray, d, u);
+    __bf16 uh[DKP], ul[DKP];
+#pragma unroll
+    for (int k = 0; k < DKP; ++k) split_bf16(u[k], uh[k], ul[k]);
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kk = 16 * q + 8 * h + e;
+          v[h] = kk < DKP ? uh[kk % DKP]
+                          : (kk < 2 * DKP ? ul[kk % DKP] : (kk < 3 * DKP ? uh[kk % DKP] : (__bf16)0.f));
+        }
+        ub[cb][q][e] = (lane & 32) ? v[1] : v[0];
+      }
+    }
+  }
+
+  float best[C], second[C];
+  int bidx[C];
+#pragma unroll
+  for (int cb = 0; cb < C; ++cb) {
+    best[cb] = 0.f;
+    second[cb] = 0.f;
+    bidx[cb] = -1;
+  }
+  float nn2 = __builtin_inff();
+
+  const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
+  const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
+  float pre[DK];
+  load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, tid), pre);
+  for (int64_t base = 0; base < n_scan; base += NB) {
+    {
+      float rt[DK];
+      nn2 = fminf(nn2, invert_node<DK>(pre, xi, row_node(a, nb0, n_scan, base + tid), n, cell, rt));
+      load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, base + NB + tid), pre);
+      __syncthreads();  // the previous chunk is consumed
+      __bf16 rh[DKP], rl[DKP];
+#pragma unroll
+      for (int k = 0; k < DKP; ++k) split_bf16(rt[k], rh[k], rl[k]);
+#pragma unroll
+      for (int g = 0; g < KT / 8; ++g) {
+        bf16x8 v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int kk = 8 * g + e;
+          v[e] = kk < DKP ? rh[kk % DKP]
+                          : (kk < 2 * DKP ? rh[kk % DKP] : (kk < 3 * DKP ? rl[kk % DKP] : (__bf16)0.f));
+        }
+        lds[tid * (KT / 8) + g] = v;
+      }
+    }
+    __syncthreads();
+    const int64_t rem = n_scan - base;
+    const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
+    for (int nb = 0; nb < nblocks; ++nb) {
+      bf16x8 A[KQ];
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) A[q] = lds[(nb * 32 + (lane & 31)) * (KT / 8) + 2 * q + (lane >> 5)];
+      const int blk16 = (int)((base >> 5) + nb) << 4;
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) {
+        f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                      0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[q], ub[cb][q], acc, 0, 0, 0);
+        epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
+      }
+    }
+  }
+  cell_finish<C, DK, NT, GEN>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
+}
+
+template <int KQ, int C, int WAVES, bool GEN>
+__global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanArgs a) {
+  __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
+  __shared__ float red[WAVES * 64];
+  const int64_t cell = blockIdx.x / a.wg_per_cell;
+  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  scan_bf16x3_item<KQ, C, WAVES, GEN>(a, cell, chunk, lds, red);
+}
+
+template <int C, int WAVES, bool GEN>
+hipError_t launch_kq_g(const CellScanArgs &a, hipStream_t s, int grid) {
+  dim3 blk(WAVES * 64);
+  if (a.d <= 5)
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<1, C, WAVES, GEN>), dim3(grid), blk, 0, s, a);
+  else if (a.d <= 10)
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<2, C, WAVES, GEN>), dim3(grid), blk, 0, s, a);
+  else
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<3, C, WAVES, GEN>), dim3(grid), blk, 0, s, a);
+  return hipGetLastError();
+}
+
+
+template <int C, int WAVES, bool GEN>
+hipError_t launch_kp_g(const CellScanArgs &a, hipStream_t s, int grid) {
+  const int kp = (a.d + 1) / 2;
+  dim3 blk(WAVES * 64);
+  switch (kp) {
+#define VG_CASE(K)                                                              \
+  case K:                                                                       \
+    hipLaunchKernelGGL((cell_scan_fp32_kernel<K, C, WAVES, GEN>), dim3(grid), blk, 0, s, a); \
+    break;
+    VG_CASE(1)
+    VG_CASE(2)
+    VG_CASE(3)
+    VG_CASE(4)
+    VG_CASE(5)
+    VG_CASE(6)
+    VG_CASE(7)
+    VG_CASE(8)
+#undef VG_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace vg

@@ -60,7 +60,8 @@ struct CellScanArgs {
   const float *nodes;
   int64_t n;
   int d;
-  const float *dirs;  // [n][R][d]
+  const float *dirs;  // [n][R][d], or null: drawn from `seed` (vg_philox.h)
+  uint64_t seed;
   int R;
   int wg_per_cell;
   float *t_out;
@@ -95,7 +96,8 @@ struct RecheckArgs {
   const float *nodes;
   int64_t n;
   int d;
-  const float *dirs;  // cells mode
+  const float *dirs;  // cells mode ([n][R][d], or null: drawn from `seed`)
+  uint64_t seed;
   int R;
   const float *o32, *u32;
   const double *o64, *u64;
@@ -140,7 +142,8 @@ struct BackwardArgs {
   int64_t n;
   int d;
   int R;
-  const float *dirs;
+  const float *dirs;  // [n][R][d], or null: drawn from `seed`
+  uint64_t seed;
   const float *t;
   const int32_t *idx;
   const int32_t *facet_j;
@@ -244,8 +247,32 @@ inline float cell_kappa(int d, bool bf16) {
 
 void batch_state_free(vg_ctx *ctx);
 
+// Device scratch of one Monte-Carlo RayCast call (run_cells_in): the FP64
+// recheck queue [m], the status bytes [m], the incircle grid, the node-split
+// recheck parts, and the CNT_WORDS counters.
+struct CellsScratch {
+  int64_t *flag_list = nullptr;
+  uint8_t *status = nullptr;
+  void *grid = nullptr;
+  void *parts = nullptr;
+  size_t parts_bytes = 0;
+  uint32_t *counters = nullptr;
+  bool timed = false;  // time the scan launch when profiling is on
+};
+// vg_raycast_cells on caller-provided scratch (defined in vg_api.hip).
+// dirs null: the directions are drawn on the device from `seed` (vg_philox.h).
+int run_cells_in(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const float *dirs,
+                 uint64_t seed, uint32_t flags, float *t_out, int32_t *idx_out, const CellsScratch &sc,
+                 const int64_t *nbr_off, const int32_t *nbr);
+// Directions [n_cells][R][d] of cells first .. first + n_cells - 1 drawn from seed.
+hipError_t launch_dump_dirs(int d, int64_t first, int64_t n_cells, int R, uint64_t seed, float *out,
+                            hipStream_t s);
+
 // Cell-scan tile choice: rays per workgroup for a given rays-per-cell.
 int cell_scan_rays_per_wg(int R);
+// The cell scan with the directions drawn from a.seed (a.dirs null), rw rays
+// per workgroup, a.wg_per_cell set (vg_cell_scan_gen.hip).
+hipError_t launch_cells_gen(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s);
 
 // Relative gap floors of the near-tie test.  The cell scan certifies its
 // argmax with an absolute FP32/BF16x3 error bound (kappa / nn-distance); the
@@ -263,6 +290,7 @@ struct vg_ctx {
   std::string err;
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
+  std::vector<void *> retired;  // earlier scratch blocks (a captured graph may read them)
   uint32_t *counters = nullptr;  // device [CNT_WORDS]
   int64_t last_rays = 0;
   double last_tau = 0.0;
@@ -272,4 +300,5 @@ struct vg_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> scan_events;  // pending timings
   int64_t scan_launches = 0;
   double scan_ms = 0.0;
+  hipEvent_t handoff = nullptr;  // orders a new stream after the old one (vg_set_stream)
 };

@@ -28,7 +28,10 @@
 // per-node fixed-point scale chosen from that node's largest incoming
 // magnitude and count (integer addition is associative, so the result does
 // not depend on the order of the atomics).
+#include <algorithm>
+
 #include "vg_internal.h"
+#include "vg_philox.h"
 
 namespace vg {
 namespace {
@@ -386,9 +389,7 @@ __global__ __launch_bounds__(NT) void backward_rays_kernel(BackwardArgs a) {
       const float c = dl * 2.f * l / n2;             // dl * dt/dD scale
       const float cw = -ga * a.sa * 2.f * ld / (n2 * nD);  // direct area term
       float uk[DK];
-      const float *up = a.dirs + gid * d;
-#pragma unroll
-      for (int k = 0; k < DK; ++k) uk[k] = (k < d) ? up[k] : 0.f;
+      cell_dir<DK>(a.dirs, a.seed, cell, R, kr, d, uk);
 #pragma unroll
       for (int k = 0; k < DK; ++k) {
         win[k] = c * (D[k] - l * uk[k]) + cw * D[k];
@@ -400,7 +401,12 @@ __global__ __launch_bounds__(NT) void backward_rays_kernel(BackwardArgs a) {
 #pragma unroll
       for (int q = 0; q < DK; ++q)
         if (q == kk) xk = xi[q];
-      const float uk = a.dirs[gid * d + kk];
+      float ud[DK];
+      cell_dir<DK>(a.dirs, a.seed, cell, R, kr, d, ud);
+      float uk = 0.f;
+#pragma unroll
+      for (int q = 0; q < DK; ++q)
+        if (q == kk) uk = ud[q];
       const float h = (face & 1) ? 1.f - xk : xk;
       dl += ga * a.sa * (float)d * ld1 / h;
       const float gk = dl * (-1.f / uk) + ga * a.sa * ld / (h * h) * ((face & 1) ? 1.f : -1.f);
@@ -476,6 +482,41 @@ __global__ __launch_bounds__(NT) void backward_finish_kernel(BackwardArgs a) {
 }
 
 }  // namespace
+
+namespace {
+
+template <int DK>
+__global__ __launch_bounds__(NT) void dump_dirs_kernel(int d, int64_t first, int64_t n_cells, int R,
+                                                       uint64_t seed, float *__restrict__ out) {
+  for (int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x; gid < n_cells * R;
+       gid += (int64_t)gridDim.x * NT) {
+    const int64_t c = gid / R;
+    const int ray = (int)(gid - c * R);
+    float u[DK];
+    mc_direction<DK>(seed, first + c, ray, d, u);
+#pragma unroll
+    for (int k = 0; k < DK; ++k)
+      if (k < d) out[gid * d + k] = u[k];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_dump_dirs(int d, int64_t first, int64_t n_cells, int R, uint64_t seed, float *out,
+                            hipStream_t s) {
+  const int64_t m = n_cells * R;
+  if (m <= 0) return hipSuccess;
+  const dim3 grid((unsigned)std::min<int64_t>((m + NT - 1) / NT, 1 << 20)), blk(NT);
+  if (d <= 4)
+    hipLaunchKernelGGL(dump_dirs_kernel<4>, grid, blk, 0, s, d, first, n_cells, R, seed, out);
+  else if (d <= 8)
+    hipLaunchKernelGGL(dump_dirs_kernel<8>, grid, blk, 0, s, d, first, n_cells, R, seed, out);
+  else if (d <= 12)
+    hipLaunchKernelGGL(dump_dirs_kernel<12>, grid, blk, 0, s, d, first, n_cells, R, seed, out);
+  else
+    hipLaunchKernelGGL(dump_dirs_kernel<16>, grid, blk, 0, s, d, first, n_cells, R, seed, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_accum(const AccumArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;

@@ -18,6 +18,7 @@
 // The list length is read on the device, so the launch needs no host sync: a
 // fixed grid strides over the list.
 #include "vg_internal.h"
+#include "vg_philox.h"
 
 namespace vg {
 namespace {
@@ -208,8 +209,10 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
       if (CELLS) {
         gi = (int32_t)(ray / a.R);
         clip = 1;
+        float uf[DK];
+        cell_dir<DK>(a.dirs, a.seed, gi, a.R, (int)(ray - (int64_t)gi * a.R), d, uf);
 #pragma unroll
-        for (int k = 0; k < DK; ++k) u[k] = k < d ? (double)a.dirs[ray * d + k] : 0.0;
+        for (int k = 0; k < DK; ++k) u[k] = (double)uf[k];
       } else {
         gi = a.gen[ray];
         n_excl = a.n_excl;
@@ -312,8 +315,10 @@ __global__ __launch_bounds__(NT1) void recheck_wide_kernel(RecheckArgs a, uint32
     if (CELLS) {
       gi = (int32_t)(ray / a.R);
       clip = 1;
+      float uf[DK];
+      cell_dir<DK>(a.dirs, a.seed, gi, a.R, (int)(ray - (int64_t)gi * a.R), d, uf);
 #pragma unroll
-      for (int k = 0; k < DK; ++k) u[k] = k < d ? (double)a.dirs[ray * d + k] : 0.0;
+      for (int k = 0; k < DK; ++k) u[k] = (double)uf[k];
     } else {
       gi = a.gen[ray];
       n_excl = a.n_excl;
@@ -389,9 +394,11 @@ __global__ __launch_bounds__(NT) void recheck_batched_kernel(const BatchProblem 
     const int d = a.d;
     const int64_t cell = ray / a.R;
     double x[VG_MAX_DIM], u[VG_MAX_DIM];
+    float uf[VG_MAX_DIM];
+    cell_dir<VG_MAX_DIM>(a.dirs, a.seed, cell, a.R, (int)(ray - cell * a.R), d, uf);
     for (int k = 0; k < d; ++k) {
       x[k] = (double)a.nodes[cell * d + k];
-      u[k] = (double)a.dirs[ray * d + k];
+      u[k] = (double)uf[k];
     }
     Top2 tp{__builtin_inf(), __builtin_inf(), -1};
     for (int64_t r = lane; r < a.n; r += 64) {
@@ -649,10 +656,12 @@ __global__ __launch_bounds__(256) void recheck_fold_kernel(RecheckArgs a, int P,
   double x[DK], u[DK];
   if (CELLS) {
     const int64_t gi = ray / a.R;
+    float uf[DK];
+    cell_dir<DK>(a.dirs, a.seed, gi, a.R, (int)(ray - gi * a.R), d, uf);
 #pragma unroll
     for (int k = 0; k < DK; ++k) {
       x[k] = k < d ? (double)a.nodes[gi * d + k] : 0.0;
-      u[k] = k < d ? (double)a.dirs[ray * d + k] : 0.0;
+      u[k] = (double)uf[k];
     }
   } else {
 #pragma unroll

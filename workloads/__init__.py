@@ -21,6 +21,10 @@ Conventions
   vector divided by its norm (the uniform-on-the-sphere draw of Sec. 3.1),
   computed in float64 and rounded to float32.  Both sides use the rounded
   vector as given; it is not renormalised.
+* ``philox_directions`` is the host side of the library's on-device draw
+  (counter-based Philox4x32-10 and Box-Muller, keyed by (seed, cell, ray)):
+  each side implements the same published generator, so the oracle can be
+  given the directions of any seeded device run without reading them back.
 """
 from __future__ import annotations
 
@@ -34,6 +38,8 @@ __all__ = [
     "jittered_lattice",
     "mc_directions",
     "mc_directions_device",
+    "philox4x32_10",
+    "philox_directions",
     "descent_draws",
     "uneven_batch_spec",
     "fd_generators",
@@ -143,6 +149,62 @@ def mc_directions_device(n_cells: int, n_rays: int, d: int, seed: int, device):
         z /= torch.sqrt((z * z).sum(dim=-1, keepdim=True))
         out[c0:c1] = z.float()
     return out
+
+
+_PHILOX_M0, _PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+_PHILOX_W0, _PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11), vectorised:
+    ``ctr`` uint32 ``[..., 4]``, ``key`` uint32 ``[..., 2]`` (broadcast);
+    returns the four output words ``[..., 4]``.  Ten rounds; each round takes
+    the high and low halves of M0 c0 and M1 c2 and bumps the key by the two
+    Weyl constants."""
+    c = np.array(ctr, dtype=np.uint64) & 0xFFFFFFFF
+    k = np.array(key, dtype=np.uint64) & 0xFFFFFFFF
+    c0, c1, c2, c3 = (c[..., i] for i in range(4))
+    k0, k1 = k[..., 0], k[..., 1]
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(_PHILOX_M0) * c0
+        p1 = np.uint64(_PHILOX_M1) * c2
+        c0, c1, c2, c3 = ((p1 >> np.uint64(32)) ^ c1 ^ k0, p1 & mask, (p0 >> np.uint64(32)) ^ c3 ^ k1, p0 & mask)
+        k0 = (k0 + np.uint64(_PHILOX_W0)) & mask
+        k1 = (k1 + np.uint64(_PHILOX_W1)) & mask
+    return np.stack([c0, c1, c2, c3], axis=-1).astype(np.uint32)
+
+
+def philox_directions(cells, n_rays: int, d: int, seed: int) -> np.ndarray:
+    """Unit directions of the listed cells' Monte-Carlo rays as the library
+    draws them on the device from ``seed`` (float32 ``[len(cells)][n_rays][d]``).
+
+    Component k of ray r of cell c: Philox4x32-10 with counter
+    ``(k // 4, r, c mod 2^32, c >> 32)`` and key ``(seed mod 2^32, seed >> 32)``
+    gives words w0..w3; pair ``p = (k mod 4) // 2`` takes ``a = w[2p]``,
+    ``b = w[2p+1]``; ``u1 = (a + 1/2) 2^-32``, ``u2 = b 2^-32``,
+    ``rho = sqrt(-2 ln u1)``, ``theta = 2 pi u2`` (Box-Muller in float64);
+    ``z_k = rho cos theta`` (k even) or ``rho sin theta`` (k odd).  Then
+    ``s = z_0^2 + z_1^2 + ...`` summed in that order and ``u_k =
+    float32(z_k / sqrt(s))``."""
+    cells = np.asarray(cells, dtype=np.int64).ravel()
+    nc = cells.size
+    nj = (d + 3) // 4
+    cell = np.broadcast_to(cells[:, None, None].astype(np.uint64), (nc, n_rays, nj))
+    ray = np.broadcast_to(np.arange(n_rays, dtype=np.uint64)[None, :, None], (nc, n_rays, nj))
+    j = np.broadcast_to(np.arange(nj, dtype=np.uint64)[None, None, :], (nc, n_rays, nj))
+    ctr = np.stack([j, ray, cell & np.uint64(0xFFFFFFFF), cell >> np.uint64(32)], axis=-1)
+    seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    w = philox4x32_10(ctr, [seed & 0xFFFFFFFF, seed >> 32]).astype(np.float64)  # [nc, R, nj, 4]
+    u1 = (w[..., 0::2] + 0.5) * 2.0 ** -32
+    u2 = w[..., 1::2] * 2.0 ** -32
+    rho = np.sqrt(-2.0 * np.log(u1))
+    th = 6.283185307179586 * u2
+    z = np.stack([rho * np.cos(th), rho * np.sin(th)], axis=-1).reshape(nc, n_rays, 4 * nj)[..., :d]
+    s = np.zeros((nc, n_rays))
+    for k in range(d):
+        s = s + z[..., k] * z[..., k]
+    return (z / np.sqrt(s)[..., None]).astype(np.float32)
 
 
 def mc_radial_draws(cells, n_rays: int, m: int, seed: int = 3) -> np.ndarray:
