@@ -177,6 +177,24 @@ int vg_raycast_cells_seeded(vg_ctx *ctx, int d, int64_t n_nodes, const float *no
 int vg_dump_dirs(vg_ctx *ctx, int d, int64_t first_cell, int64_t n_cells, int rays_per_cell,
                  uint64_t seed, float *out);
 
+/* vg_raycast_cells for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the recheck queue, the
+ * status bytes (when status_out is NULL) and the counters in a fixed scratch
+ * array of the library (about 36 MiB per device, held from library load
+ * until the process ends).  No call allocates or frees device memory.
+ * n_nodes * rays_per_cell <= VG_NOALLOC_MAX_RAYS, else VG_EINVAL; VG_INCIRCLE
+ * is VG_EUNSUPPORTED; other arguments, flags and outputs as
+ * vg_raycast_cells.  Every call on one device shares that array and the
+ * array keeps the last call's contents (each call clears its counters
+ * first): calls that overlap on one device (other streams, other contexts
+ * or threads) race and give wrong results.  vg_get_stats reads the array's
+ * counters of the last call. */
+#define VG_NOALLOC_MAX_RAYS (1ll << 22)
+int vg_raycast_cells_noalloc(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                             int rays_per_cell, const float *dirs, uint32_t flags,
+                             float *t_out, int32_t *idx_out, uint8_t *status_out);
+
 /* ------------------------------------------------ Monte-Carlo estimators */
 /* Sec. 3.1 / Algorithm 3 with f = 1: for every cell i, with l = t* of its
  * rays and S = S_{d-1} = 2 pi^{d/2} / Gamma(d/2),

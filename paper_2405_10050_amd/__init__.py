@@ -13,6 +13,7 @@ Calls (names follow the paper's statement of the problem):
   raycast_cells(nodes, dirs)                           Monte-Carlo rays of every cell
   raycast_cells(nodes, seed=s, rays_per_cell=R)        the same, directions drawn on the device
   dump_dirs(d, n_cells, R, seed)                       those directions, written out
+  raycast_cells_noalloc(nodes, dirs, out=...)          raycast_cells with no device allocation
   mc_volume_area(nodes, dirs, neighbors=None)          Sec. 3.1 / Algorithm 3 estimators
   tuple_neighbors(sigma, n)                            cell adjacency from vertex tuples
   mc_integrals(nodes, dirs, res, f, tsamp)             integrals of f over cells and facets
@@ -47,6 +48,7 @@ ST_SUSPECT = 8
 ST_FP64_TIE = 16
 
 MAX_DIM = 16
+NOALLOC_MAX_RAYS = 1 << 22
 
 
 class VGError(RuntimeError):
@@ -81,7 +83,7 @@ EXPORTS = (
     "vg_raycast_batched", "vg_mc_volume_area_nbr", "vg_tuple_neighbors", "vg_mc_sample_points",
     "vg_mc_integrals", "vg_hmc_centroids", "vg_hmc_integrals",
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
-    "vg_mesh_copy", "vg_mesh_free", "vg_mesh_num_nn_calls",
+    "vg_mesh_copy", "vg_mesh_free", "vg_mesh_num_nn_calls", "vg_raycast_cells_noalloc",
     "vg_raycast_cells_seeded", "vg_mc_volume_area_seeded", "vg_mc_backward_seeded", "vg_dump_dirs",
     "vg_peak_rate",
 )
@@ -103,6 +105,7 @@ def _load_lib():
     lib.vg_set_profiling.argtypes = [P, I]
     lib.vg_raycast.argtypes = [P, I, I64, P, I64, P, P, P, P, I, U32, P, P, P]
     lib.vg_raycast_cells.argtypes = [P, I, I64, P, I, P, U32, P, P, P]
+    lib.vg_raycast_cells_noalloc.argtypes = [P, I, I64, P, I, P, U32, P, P, P]
     lib.vg_raycast_cells_seeded.argtypes = [P, I, I64, P, I, U64, U32, P, P, P]
     lib.vg_mc_volume_area_seeded.argtypes = [P, I, I64, P, I, U64, U32, P, P, P, P, P, P, P, P]
     lib.vg_mc_backward_seeded.argtypes = [P, I, I64, P, I, U64, P, P, P, P, P, P, P, P]
@@ -286,6 +289,36 @@ def dump_dirs(d, n_cells, rays_per_cell, seed, first_cell=0, device=None):
     _check(_lib.vg_dump_dirs(c, d, first_cell, n_cells, rays_per_cell, int(seed) & (2 ** 64 - 1), _ptr(out)),
            c, "vg_dump_dirs")
     return out
+
+
+def raycast_cells_noalloc(nodes, dirs, precision="fp32", recheck=True, out=None):
+    """:func:`raycast_cells` through the library's allocation-free entry
+    point (its recheck queue and counters live in a fixed device array of
+    the library; ``N * R <= NOALLOC_MAX_RAYS``).  ``out`` may pass
+    preallocated ``(t, idx, status)`` ``[N, R]`` tensors (status may be
+    None), so that the call itself allocates nothing."""
+    _dev(nodes, torch.float32, "nodes")
+    dev = nodes.device
+    n, d = nodes.shape
+    _dev(dirs, torch.float32, "dirs", dev)
+    if dirs.dim() != 3 or dirs.shape[0] != n or dirs.shape[2] != d:
+        raise ValueError("dirs must be [N, R, d]")
+    R = dirs.shape[1]
+    if out is None:
+        out = (torch.empty((n, R), dtype=torch.float32, device=dev),
+               torch.empty((n, R), dtype=torch.int32, device=dev),
+               torch.empty((n, R), dtype=torch.uint8, device=dev))
+    t, idx, st = out
+    _dev(t, torch.float32, "t", dev)
+    _dev(idx, torch.int32, "idx", dev)
+    if st is not None:
+        _dev(st, torch.uint8, "status", dev)
+    if t.shape != (n, R) or idx.shape != (n, R) or (st is not None and st.shape != (n, R)):
+        raise ValueError("out must hold [N, R] tensors")
+    c = _ctx(dev)
+    _check(_lib.vg_raycast_cells_noalloc(c, d, n, _ptr(nodes), R, _ptr(dirs), _cells_flags(precision, recheck),
+                                         _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast_cells_noalloc")
+    return t, idx, st
 
 
 @dataclass

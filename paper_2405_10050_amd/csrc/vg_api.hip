@@ -309,6 +309,13 @@ int vg_create(int device, vg_ctx **out) {
     delete ctx;
     return VG_EDEVICE;
   }
+  // the fixed scratch of vg_raycast_cells_noalloc on this device (looked up
+  // once per device, with the device current)
+  if (noalloc_attach(device) != hipSuccess) {
+    (void)hipFree(ctx->counters);
+    delete ctx;
+    return VG_EDEVICE;
+  }
   *out = ctx;
   return VG_OK;
 }
@@ -483,6 +490,33 @@ int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, in
     return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
   if (!dirs || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null array");
   return run_cells(ctx, d, n_nodes, nodes, rays_per_cell, dirs, 0, flags, t_out, idx_out, status_out);
+}
+
+int vg_raycast_cells_noalloc(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,
+                             const float *dirs, uint32_t flags, float *t_out, int32_t *idx_out,
+                             uint8_t *status_out) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (rays_per_cell < 1 || rays_per_cell > 4096)
+    return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
+  if (!dirs || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null array");
+  if (flags & VG_INCIRCLE) return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs scratch of its own");
+  const int64_t m = n_nodes * (int64_t)rays_per_cell;
+  if (m > VG_NOALLOC_MAX_RAYS)
+    return fail(ctx, VG_EINVAL, "n_nodes * rays_per_cell = %lld exceeds VG_NOALLOC_MAX_RAYS = %lld",
+                (long long)m, (long long)VG_NOALLOC_MAX_RAYS);
+  static_assert(VG_NOALLOC_MAX_RAYS == kNoAllocMaxRays, "header and library disagree");
+  char *base = static_cast<char *>(noalloc_scratch(ctx->device));
+  if (!base) return fail(ctx, VG_EDEVICE, "fixed scratch not attached on device %d", ctx->device);
+  // layout: counters | recheck queue [m] i64 | status [m] u8
+  CellsScratch sc{};
+  sc.counters = reinterpret_cast<uint32_t *>(base);
+  sc.flag_list = reinterpret_cast<int64_t *>(base + kNoAllocCounterBytes);
+  sc.status = status_out ? status_out
+                         : reinterpret_cast<uint8_t *>(base + kNoAllocCounterBytes + (size_t)kNoAllocMaxRays * 8);
+  sc.timed = false;
+  return run_cells_in(ctx, d, n_nodes, nodes, rays_per_cell, dirs, 0, flags, t_out, idx_out, sc, nullptr,
+                      nullptr);
 }
 
 }  // extern "C"

@@ -268,6 +268,15 @@ int run_cells_in(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const
 hipError_t launch_dump_dirs(int d, int64_t first, int64_t n_cells, int R, uint64_t seed, float *out,
                             hipStream_t s);
 
+// Fixed device scratch of the allocation-free entry point (vg_noalloc.hip):
+// noalloc_attach looks up its address on the current device once (called by
+// vg_create); noalloc_scratch returns it (null before attach or on failure).
+constexpr int64_t kNoAllocMaxRays = int64_t(1) << 22;
+constexpr size_t kNoAllocCounterBytes = 256;
+constexpr size_t kNoAllocBytes = kNoAllocCounterBytes + (size_t)kNoAllocMaxRays * 9 + 256;
+hipError_t noalloc_attach(int device);
+void *noalloc_scratch(int device);
+
 // Cell-scan tile choice: rays per workgroup for a given rays-per-cell.
 int cell_scan_rays_per_wg(int R);
 // The cell scan with the directions drawn from a.seed (a.dirs null), rw rays
