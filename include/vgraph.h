@@ -30,6 +30,13 @@
  *    the cube.  The scan runs in FP32; a ray whose two best candidates are
  *    within a relative gap VG_TIE_EPS (or whose result could hinge on FP32
  *    rounding) is re-evaluated over all nodes in FP64 and flagged.
+ *  - Non-finite input (NaN or Inf) is checked on the device without a
+ *    synchronisation: a non-finite node coordinate makes every ray of the
+ *    call, and a non-finite origin or direction makes that ray, return
+ *    t = NaN, idx = -1, status VG_ST_BAD_INPUT (counted in vg_stats);
+ *    Monte-Carlo sums over such rays are NaN.  vg_explore, which
+ *    synchronises anyway, returns VG_EINVAL instead.  The batched calls do
+ *    not check their inputs.
  *  - A context is not thread-safe; use one per host thread.
  */
 #ifndef VGRAPH_H
@@ -67,6 +74,9 @@ typedef enum vg_status {
 #define VG_ST_NO_HIT 4    /* no node ahead of the ray (t = +inf, idx = -1)       */
 #define VG_ST_SUSPECT 8   /* winner nearly parallel to its bisector in FP32      */
 #define VG_ST_FP64_TIE 16 /* FP64 gap below 1e-9: several answers are correct    */
+#define VG_ST_BAD_INPUT 32 /* non-finite input: a node coordinate (then every ray
+                              of the call), or this ray's origin or direction;
+                              t = NaN, idx = -1                                 */
 
 typedef struct vg_ctx vg_ctx;
 typedef struct vg_mesh vg_mesh;
@@ -81,6 +91,9 @@ typedef struct vg_stats {
   int64_t nn_calls;      /* nearest-neighbour queries of the last VG_INCIRCLE call */
   int64_t nn_grid_calls; /* of those, queries answered by the grid (the others
                             by the cell's list of nearest nodes)             */
+  int64_t bad_input_rays; /* rays of the last call answered NaN / -1 because of
+                             non-finite input (VG_ST_BAD_INPUT)              */
+  int64_t bad_node_values; /* non-finite node coordinates the last call saw   */
 } vg_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -134,6 +147,19 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
                const int32_t *gen, const int32_t *excl, int n_excl,
                uint32_t flags, float *t_out, int32_t *idx_out,
                uint8_t *status_out);
+
+/* vg_raycast with FP64 origins and directions (a vertex and a
+ * SearchDirection of Algorithm 2 are FP64): origin, dir [n_rays][d] f64.
+ * The scan runs on their FP32 rounding with the error of that rounding in
+ * its certificate, and the recheck and the winner's t* use the FP64 values
+ * (the exhaustive search casts its edge rays this way).  flags VG_CLIP,
+ * VG_INCIRCLE, VG_INIT_HEURISTIC; status_out may be NULL.  Reads the
+ * recheck queue's length back: synchronises the stream. */
+int vg_raycast_f64(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
+                   int64_t n_rays, const double *origin, const double *dir,
+                   const int32_t *gen, const int32_t *excl, int n_excl,
+                   uint32_t flags, float *t_out, int32_t *idx_out,
+                   uint8_t *status_out);
 
 /* Monte-Carlo rays of every cell (Algorithm 3): ray k of cell i starts at
  * x_i with eta = {i} and direction dirs[i][k], clipped to the unit cube

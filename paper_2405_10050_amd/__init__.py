@@ -46,6 +46,7 @@ ST_RECHECKED = 2
 ST_NO_HIT = 4
 ST_SUSPECT = 8
 ST_FP64_TIE = 16
+ST_BAD_INPUT = 32
 
 MAX_DIM = 16
 NOALLOC_MAX_RAYS = 1 << 22
@@ -59,7 +60,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("rays", ctypes.c_int64), ("flagged", ctypes.c_int64),
                 ("fp64_ties", ctypes.c_int64), ("tie_eps", ctypes.c_double),
                 ("scan_launches", ctypes.c_int64), ("scan_ms", ctypes.c_double),
-                ("nn_calls", ctypes.c_int64), ("nn_grid_calls", ctypes.c_int64)]
+                ("nn_calls", ctypes.c_int64), ("nn_grid_calls", ctypes.c_int64),
+                ("bad_input_rays", ctypes.c_int64), ("bad_node_values", ctypes.c_int64)]
 
 
 class _CellsProblem(ctypes.Structure):
@@ -85,7 +87,7 @@ EXPORTS = (
     "vg_explore", "vg_mesh_num_vertices", "vg_mesh_num_unbounded", "vg_mesh_num_raycasts",
     "vg_mesh_copy", "vg_mesh_free", "vg_mesh_num_nn_calls", "vg_raycast_cells_noalloc",
     "vg_raycast_cells_seeded", "vg_mc_volume_area_seeded", "vg_mc_backward_seeded", "vg_dump_dirs",
-    "vg_peak_rate",
+    "vg_peak_rate", "vg_raycast_f64",
 )
 
 
@@ -104,6 +106,7 @@ def _load_lib():
     lib.vg_get_stats.argtypes = [P, ctypes.POINTER(_Stats)]
     lib.vg_set_profiling.argtypes = [P, I]
     lib.vg_raycast.argtypes = [P, I, I64, P, I64, P, P, P, P, I, U32, P, P, P]
+    lib.vg_raycast_f64.argtypes = [P, I, I64, P, I64, P, P, P, P, I, U32, P, P, P]
     lib.vg_raycast_cells.argtypes = [P, I, I64, P, I, P, U32, P, P, P]
     lib.vg_raycast_cells_noalloc.argtypes = [P, I, I64, P, I, P, U32, P, P, P]
     lib.vg_raycast_cells_seeded.argtypes = [P, I, I64, P, I, U64, U32, P, P, P]
@@ -180,7 +183,8 @@ def stats(device=None) -> dict:
     _check(_lib.vg_get_stats(c, ctypes.byref(s)), c, "vg_get_stats")
     return dict(rays=s.rays, flagged=s.flagged, fp64_ties=s.fp64_ties, tie_eps=s.tie_eps,
                 scan_launches=s.scan_launches, scan_ms=s.scan_ms, nn_calls=s.nn_calls,
-                nn_grid_calls=s.nn_grid_calls)
+                nn_grid_calls=s.nn_grid_calls, bad_input_rays=s.bad_input_rays,
+                bad_node_values=s.bad_node_values)
 
 
 def peak_rates(device=None) -> dict:
@@ -208,12 +212,15 @@ def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True, i
             heuristic=False):
     """RayCast of arbitrary rays; returns ``(t, idx, status)`` of length M.
     ``incircle=True`` casts them by Algorithm 1 with a grid index (d <= 6),
-    ``heuristic=True`` starting from InitialHeuristic's point."""
+    ``heuristic=True`` starting from InitialHeuristic's point.  Float64
+    ``origin`` and ``direction`` take the FP64-origin path (vg_raycast_f64,
+    which synchronises)."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
     n, d = nodes.shape
-    _dev(origin, torch.float32, "origin", dev)
-    _dev(direction, torch.float32, "direction", dev)
+    f64 = isinstance(origin, torch.Tensor) and origin.dtype == torch.float64
+    _dev(origin, torch.float64 if f64 else torch.float32, "origin", dev)
+    _dev(direction, torch.float64 if f64 else torch.float32, "direction", dev)
     _dev(gen, torch.int32, "gen", dev)
     m = origin.shape[0]
     if origin.shape != (m, d) or direction.shape != (m, d) or gen.shape != (m,):
@@ -230,6 +237,12 @@ def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True, i
     flags = ((VG_CLIP if clip else 0) | (0 if recheck else VG_NO_RECHECK) |
              (VG_INCIRCLE if incircle else 0) | (VG_INIT_HEURISTIC if heuristic else 0))
     c = _ctx(dev)
+    if f64:
+        if not recheck:
+            raise ValueError("the FP64-origin path always rechecks")
+        _check(_lib.vg_raycast_f64(c, d, n, _ptr(nodes), m, _ptr(origin), _ptr(direction), _ptr(gen),
+                                   _ptr(excl), ne, flags, _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast_f64")
+        return t, idx, st
     _check(_lib.vg_raycast(c, d, n, _ptr(nodes), m, _ptr(origin), _ptr(direction), _ptr(gen),
                            _ptr(excl), ne, flags, _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast")
     return t, idx, st

@@ -124,6 +124,7 @@ int run_cells_in(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const
   const size_t parts_bytes = sc.parts_bytes;
   ctx->last_counters = sc.counters;
   VG_HIP(ctx, fill_u32(sc.counters, 0u, CNT_WORDS, ctx->stream));
+  VG_HIP(ctx, launch_check_finite(nodes, n * d, sc.counters + CNT_BAD_NODES, ctx->stream));
 
   CellScanArgs a{};
   a.nodes = nodes;
@@ -170,6 +171,20 @@ int run_cells_in(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const
       e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
   }
+  if (incircle) {
+    // the dense scans answer rays with non-finite input themselves; the
+    // incircle kernels stop at a non-finite node and leave it to this pass
+    FinalizeArgs f{};
+    f.m = m;
+    f.d = d;
+    f.u32 = dirs;
+    f.flags = sc.counters;
+    f.bad_rays = sc.counters + CNT_BAD_RAYS;
+    f.t_out = t_out;
+    f.idx_out = idx_out;
+    f.st_out = st;
+    VG_HIP(ctx, launch_finalize_bad(f, ctx->stream));
+  }
   ctx->last_rays = m;
   ctx->last_tau = a.tau_rel;
   return VG_OK;
@@ -214,13 +229,13 @@ namespace vg {
 int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, const double *o64,
                 const double *u64, const int32_t *gen, const int32_t *excl, int n_excl, int clip,
                 bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64,
-                int incircle, const double *nodes64, float node_err) {
+                int incircle, const double *nodes64, float node_err, bool check_input) {
   if (m <= 0) return VG_OK;
   if (nodes64 && incircle) return fail(ctx, VG_EUNSUPPORTED, "exact FP64 rows need the dense scan");
   const size_t grid_bytes = incircle ? incircle_rays_scratch_bytes(n, d) : 0;
   const size_t split_bytes = incircle ? 0 : ray_scan_split_bytes(m, n);
   const size_t parts_bytes = recheck_split_reserve(m, n);
-  size_t need = Carver::need({(size_t)m * 8, grid_bytes, split_bytes, parts_bytes});
+  size_t need = Carver::need({(size_t)m * 8, grid_bytes, split_bytes, parts_bytes, st_out ? 0 : (size_t)m});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
@@ -228,8 +243,10 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   void *grid_scratch = incircle ? cv.take<char>(grid_bytes) : nullptr;
   void *split = split_bytes ? cv.take<char>(split_bytes) : nullptr;
   void *parts = parts_bytes ? cv.take<char>(parts_bytes) : nullptr;
+  if (!st_out) st_out = cv.take<uint8_t>(m);
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
+  if (check_input) VG_HIP(ctx, launch_check_finite(nodes, n * d, ctx->counters + CNT_BAD_NODES, ctx->stream));
   RayScanArgs a{};
   a.nodes = nodes;
   a.n = n;
@@ -284,6 +301,19 @@ int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, co
   if (queued > 0 && !launch_recheck_split(r, queued, parts, parts_bytes, ctx->stream, e))
     e = launch_recheck(r, (int)std::min<int64_t>(m, 4096), ctx->stream, queued);
   if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
+  if (check_input) {
+    FinalizeArgs f{};
+    f.m = m;
+    f.d = d;
+    f.o64 = o64;
+    f.u64 = u64;
+    f.flags = ctx->counters;
+    f.bad_rays = ctx->counters + CNT_BAD_RAYS;
+    f.t_out = t_out;
+    f.idx_out = idx_out;
+    f.st_out = st_out;
+    VG_HIP(ctx, launch_finalize_bad(f, ctx->stream));
+  }
   ctx->last_rays = m;
   ctx->last_tau = kTauRays;
   return VG_OK;
@@ -372,6 +402,8 @@ int vg_get_stats(vg_ctx *ctx, vg_stats *out) {
   out->nn_grid_calls = (int64_t)((uint64_t)c[CNT_NN_GRID] | ((uint64_t)c[CNT_NN_GRID + 1] << 32));
   out->flagged = c[CNT_FLAGGED];
   out->fp64_ties = c[CNT_FP64_TIE];
+  out->bad_input_rays = c[CNT_BAD_RAYS];
+  out->bad_node_values = c[CNT_BAD_NODES];
   out->tie_eps = ctx->last_tau;
   for (auto &ev : ctx->scan_events) {
     float ms = 0.f;
@@ -430,6 +462,7 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t 
   void *split = split_bytes ? cv.take<char>(split_bytes) : nullptr;
   ctx->last_counters = ctx->counters;
   VG_HIP(ctx, fill_u32(ctx->counters, 0u, CNT_WORDS, ctx->stream));
+  VG_HIP(ctx, launch_check_finite(nodes, n_nodes * d, ctx->counters + CNT_BAD_NODES, ctx->stream));
   RayScanArgs a{};
   a.nodes = nodes;
   a.n = n_nodes;
@@ -476,9 +509,41 @@ int vg_raycast(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t 
     e = launch_recheck(r, (int)std::min<int64_t>(n_rays, 4096), ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "recheck launch");
   }
+  FinalizeArgs f{};
+  f.m = n_rays;
+  f.d = d;
+  f.o32 = origin;
+  f.u32 = dir;
+  f.flags = ctx->counters;
+  f.bad_rays = ctx->counters + CNT_BAD_RAYS;
+  f.t_out = t_out;
+  f.idx_out = idx_out;
+  f.st_out = st;
+  VG_HIP(ctx, launch_finalize_bad(f, ctx->stream));
   ctx->last_rays = n_rays;
   ctx->last_tau = kTauRays;
   return VG_OK;
+}
+
+int vg_raycast_f64(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int64_t n_rays,
+                   const double *origin, const double *dir, const int32_t *gen, const int32_t *excl, int n_excl,
+                   uint32_t flags, float *t_out, int32_t *idx_out, uint8_t *status_out) {
+  int rc = check_common(ctx, d, n_nodes, nodes);
+  if (rc) return rc;
+  if (n_rays < 0) return fail(ctx, VG_EINVAL, "n_rays < 0");
+  if (n_excl < 0 || n_excl > d) return fail(ctx, VG_EINVAL, "n_excl=%d outside [0, d]", n_excl);
+  if (n_rays == 0) return VG_OK;
+  if (!origin || !dir || !gen || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null ray array");
+  if (n_excl > 0 && !excl) return fail(ctx, VG_EINVAL, "excl is NULL with n_excl > 0");
+  if (flags & ~(uint32_t)(VG_CLIP | VG_INCIRCLE | VG_INIT_HEURISTIC))
+    return fail(ctx, VG_EINVAL, "vg_raycast_f64 takes VG_CLIP, VG_INCIRCLE and VG_INIT_HEURISTIC only");
+  const bool incircle = (flags & VG_INCIRCLE) != 0;
+  if (incircle && d > 6) return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs d <= 6");
+  if ((flags & VG_INIT_HEURISTIC) && !incircle)
+    return fail(ctx, VG_EINVAL, "VG_INIT_HEURISTIC needs VG_INCIRCLE");
+  return raycast_f64(ctx, d, n_nodes, nodes, n_rays, origin, dir, gen, excl, n_excl, (flags & VG_CLIP) ? 1 : 0,
+                     false, t_out, idx_out, status_out, nullptr,
+                     incircle ? ((flags & VG_INIT_HEURISTIC) ? 2 : 1) : 0, nullptr, 0.f, true);
 }
 
 int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, int rays_per_cell,

@@ -127,6 +127,23 @@ __device__ __forceinline__ int64_t row_node(const CellScanArgs &a, int64_t nb0, 
   return (j >= 0 && j < a.n) ? j : a.n;
 }
 
+// Rays [r0, r0 + RW) of `cell` when a node coordinate of the call is not
+// finite (the input check counted it): no answer, t = NaN, idx = -1.  The
+// whole workgroup takes this path or none (the count is read by all).
+template <int NT>
+__device__ __forceinline__ bool item_bad_nodes(const CellScanArgs &a, int64_t cell, int r0, int RW) {
+  if (!a.counters || a.counters[CNT_BAD_NODES] == 0) return false;
+  const int nr = min(RW, a.R - r0);
+  for (int r = threadIdx.x; r < nr; r += NT) {
+    const int64_t gid = cell * a.R + r0 + r;
+    a.t_out[gid] = __builtin_nanf("");
+    a.idx_out[gid] = -1;
+    a.st_out[gid] = VG_ST_BAD_INPUT;
+  }
+  if (threadIdx.x == 0 && nr > 0) atomicAdd(&a.counters[CNT_BAD_RAYS], (uint32_t)nr);
+  return true;
+}
+
 // Merge the two lanes of each ray, add the cube faces, certify the gap,
 // re-evaluate t* and write the ray results.
 template <int C, int DK, int NT, bool GEN>
@@ -216,6 +233,19 @@ __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (
       st |= VG_ST_NO_HIT;
       tie = true;
     }
+    if constexpr (!GEN) {
+      // a non-finite direction read from memory: no answer (drawn ones are finite)
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) bad |= k < d && !__builtin_isfinite(u[k]);
+      if (bad) {
+        t = __builtin_nanf("");
+        j = -1;
+        st = VG_ST_BAD_INPUT;
+        tie = false;
+        atomicAdd(&a.counters[CNT_BAD_RAYS], 1u);
+      }
+    }
     if (tie && a.flag_list) {
       st |= VG_ST_NEAR_TIE;
       const uint32_t pos = atomicAdd(&a.counters[CNT_FLAGGED], 1u);
@@ -265,6 +295,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   const int d = a.d;
   const int64_t n = a.n;
   const int R = a.R;
+  if (item_bad_nodes<NT>(a, cell, chunk * RW, RW)) return;
 
   float xi[DK];
 #pragma unroll
@@ -385,6 +416,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
   const int d = a.d;
   const int64_t n = a.n;
   const int R = a.R;
+  if (item_bad_nodes<NT>(a, cell, chunk * RW, RW)) return;
 
   float xi[DK];
 #pragma unroll

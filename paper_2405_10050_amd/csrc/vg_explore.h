@@ -153,6 +153,7 @@ hipError_t launch_solve_one(const float *X, int d, const int32_t *sig, const Per
 int raycast_f64(vg_ctx *ctx, int d, int64_t n, const float *nodes, int64_t m, const double *o64,
                 const double *u64, const int32_t *gen, const int32_t *excl, int n_excl, int clip,
                 bool force_all, float *t_out, int32_t *idx_out, uint8_t *st_out, double *t64,
-                int incircle, const double *nodes64 = nullptr, float node_err = 0.f);
+                int incircle, const double *nodes64 = nullptr, float node_err = 0.f,
+                bool check_input = false);
 
 }  // namespace vg

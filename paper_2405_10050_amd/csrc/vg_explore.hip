@@ -670,6 +670,25 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
     ctx->err = "hipSetDevice failed";
     return VG_EDEVICE;
   }
+  // non-finite input: the search synchronises anyway, so it is refused here
+  std::vector<float> xh((size_t)n_nodes * d);
+  if (hipMemcpyAsync(xh.data(), nodes, sizeof(float) * xh.size(), hipMemcpyDeviceToHost, ctx->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    ctx->err = "copying the nodes failed";
+    return VG_EDEVICE;
+  }
+  for (float x : xh)
+    if (!std::isfinite(x)) {
+      ctx->err = "non-finite node coordinate";
+      return VG_EINVAL;
+    }
+  if (draws)
+    for (int64_t q = 0; q < (int64_t)n_draws * d; ++q)
+      if (!std::isfinite(draws[q])) {
+        ctx->err = "non-finite descent draw";
+        return VG_EINVAL;
+      }
   Setup su;
   su.d = d;
   su.n_nodes = n_nodes;
@@ -706,13 +725,6 @@ int vg_explore(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes, const do
   if (n_nodes * S >= (int64_t)INT32_MAX) {
     ctx->err = "periodic explore needs n_nodes * 3^d < 2^31 - 1";
     return VG_EUNSUPPORTED;
-  }
-  std::vector<float> xh((size_t)n_nodes * d);
-  if (hipMemcpyAsync(xh.data(), nodes, sizeof(float) * xh.size(), hipMemcpyDeviceToHost, ctx->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(ctx->stream) != hipSuccess) {
-    ctx->err = "copying the nodes failed";
-    return VG_EDEVICE;
   }
   for (float x : xh)
     if (!(x >= 0.f && x < 1.f)) {

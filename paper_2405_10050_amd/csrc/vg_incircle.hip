@@ -372,8 +372,11 @@ struct KnnList {
 
 template <int DK>
 __global__ __launch_bounds__(NT) void knn_kernel(const float *__restrict__ nodes, int64_t n, int d, GridView g,
-                                                 KnnList out) {
+                                                 KnnList out, const uint32_t *__restrict__ counters) {
   constexpr int KN = knn_of<DK>();
+  // a non-finite node coordinate: no search at all (every ray is answered
+  // NaN / -1 by the pass after the recheck)
+  if (counters[CNT_BAD_NODES] != 0) return;
   // threads take the nodes in grid order, so a wave searches neighbouring cells
   const int64_t slot = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (slot >= n) return;
@@ -765,6 +768,7 @@ __device__ __forceinline__ void add_calls(unsigned int *block_calls, uint32_t ca
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_list_kernel(CellScanArgs a, GridView g, KnnList kl, DeferQueue dq,
                                                            unsigned long long *nn_calls) {
+  if (a.counters[CNT_BAD_NODES] != 0) return;  // see knn_kernel
   __shared__ unsigned int block_calls[2];
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
@@ -803,6 +807,7 @@ __global__ __launch_bounds__(NT) void incircle_list_kernel(CellScanArgs a, GridV
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_grid_kernel(CellScanArgs a, GridView g, KnnList kl, DeferQueue dq,
                                                            unsigned long long *nn_calls) {
+  if (a.counters[CNT_BAD_NODES] != 0) return;  // see knn_kernel
   __shared__ unsigned int block_calls[2];
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
@@ -1017,6 +1022,7 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_rays_kernel(RayScanArgs a, GridView g, int heuristic,
                                                            unsigned long long *nn_calls) {
+  if (a.counters[CNT_BAD_NODES] != 0) return;  // see knn_kernel
   __shared__ unsigned int block_calls[2];
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
@@ -1162,7 +1168,7 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   // the grid pass strides over the queue, whose length only the device knows
   const dim3 grid2(std::min<unsigned>(blocks_of(rays * kRayLanes), 16384u));
 #define VG_INCIRCLE_LAUNCH(DKV)                                                                          \
-  hipLaunchKernelGGL(knn_kernel<DKV>, dim3(blocks_of(n)), blk, 0, s, a.nodes, n, d, g, kl);             \
+  hipLaunchKernelGGL(knn_kernel<DKV>, dim3(blocks_of(n)), blk, 0, s, a.nodes, n, d, g, kl, a.counters); \
   hipLaunchKernelGGL(incircle_list_kernel<DKV>, grid, blk, 0, s, a, g, kl, dq, nn_calls);               \
   hipLaunchKernelGGL(incircle_grid_kernel<DKV>, grid2, blk, 0, s, a, g, kl, dq, nn_calls)
   if (d <= 2) {

@@ -16,6 +16,8 @@ namespace vg {
 enum : int {
   CNT_FLAGGED = 0,   // rays appended to the FP64 recheck list
   CNT_FP64_TIE = 1,  // rays whose FP64 gap is below 1e-9
+  CNT_BAD_NODES = 2, // non-finite node coordinates seen by the call's input check
+  CNT_BAD_RAYS = 3,  // rays answered NaN / -1 because of non-finite input
   CNT_NN_CALLS = 4,  // u64 (words 4, 5): nearest-neighbour queries of the incircle RayCast
   CNT_NN_GRID = 6,   // u64 (words 6, 7): of those, queries answered by the grid
   CNT_WORDS = 8
@@ -221,6 +223,26 @@ hipError_t launch_sample_points(const float *nodes, int64_t n, int d, int R, con
                                 int m, const float *tsamp, float *points, hipStream_t s);
 hipError_t launch_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Count the non-finite values of x[0 .. count) into *bad (vg_util.hip).
+hipError_t launch_check_finite(const float *x, int64_t count, uint32_t *bad, hipStream_t s);
+// After a raycast-type call: every ray gets t = NaN, idx = -1 and
+// VG_ST_BAD_INPUT when counters[CNT_BAD_NODES] is set or when its own input
+// (its rows of u32, o32, u64, o64, those given) is not finite; counted in
+// counters[CNT_BAD_RAYS].
+struct FinalizeArgs {
+  int64_t m;
+  int d;
+  const float *o32;  // [m][d] or null
+  const float *u32;  // [m][d] or null
+  const double *o64;  // [m][d] or null
+  const double *u64;  // [m][d] or null
+  const uint32_t *flags;  // counters of the call
+  uint32_t *bad_rays;
+  float *t_out;
+  int32_t *idx_out;
+  uint8_t *st_out;
+};
+hipError_t launch_finalize_bad(const FinalizeArgs &f, hipStream_t s);
 
 // Persistent batched scan over items [first, last) of the table, all of one
 // register class (batched_class); `next` is that launch's item counter.
@@ -236,12 +258,20 @@ hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t 
 
 // Error-bound coefficient of the cell scan's near-tie certificate: the
 // computed u.r~ of any node is within c |r~| <= c / nn of the exact value, so
-// a gap above 2 c / nn certifies the argmax; kappa = 4 (safety) * 2 c.
-//   FP32:    c = (2d + 4) 2^-24   (inverted node (d+4) ulps, K = d products)
-//   BF16x3:  c = 3 * 2^-18 + (4d + 4) 2^-24   (dropped lo*lo and split
-//            remainders of both operands, plus FP32 accumulation of 3d terms)
+// a gap above 2 c / nn certifies the argmax.
+//   FP32:    c = (2d + 4) 2^-24   (inverted node (d+4) ulps, K = d products);
+//            kappa = 4 (margin) * 2 c.
+//   BF16x3:  bf16 keeps 8 significant bits (unit roundoff 2^-8), so
+//            a = hi + lo + e with |e| <= 2^-16 |a| and |lo| <= 2^-8 |a|: the
+//            dropped lo*lo and the two remainders e_a b, a e_b are at most
+//            3 * 2^-16 |a b| (to first order), plus (4d + 4) 2^-24 for the
+//            inverted node and the FP32 accumulation of 3d terms;
+//            kappa = 2 (3 * 2^-16 + 4 (margin) (4d + 4) 2^-24).  The split
+//            term has no margin of its own: the factor 4 on the FP32 term
+//            (at least 3 (4d + 4) 2^-24 = 2^-17.4 spare) covers the
+//            second-order parts (about 2^-7 * 2^-16) many times over.
 inline float cell_kappa(int d, bool bf16) {
-  if (bf16) return 4.f * 2.f * (3.f * 0x1p-18f + (4.f * d + 4.f) * 0x1p-24f);
+  if (bf16) return 2.f * (3.f * 0x1p-16f + 4.f * (4.f * d + 4.f) * 0x1p-24f);
   return 4.f * 2.f * (2.f * d + 4.f) * 0x1p-24f;
 }
 

@@ -103,8 +103,8 @@ extern "C" int vg_peak_rate(vg_ctx *ctx, int kind, double *flops_per_s) {
   const double per_iter = kind == 0 ? kChains * 32.0 * 32 * 2 * 2
                         : kind == 1 ? kChains * 32.0 * 32 * 16 * 2
                                     : kFmaChains * 64.0 * 2;
-  // about 0.2 s per launch at the datasheet rates
-  const int iters = kind == 0 ? 256 : kind == 1 ? 512 : 2048;
+  // about 50 ms per launch at the datasheet rates
+  const int iters = kind == 0 ? 51200 : kind == 1 ? 102400 : 409600;
   double best = 0.0;
   for (int rep = 0; rep < 3 && rc == VG_OK; ++rep) {
     (void)hipEventRecord(e0, ctx->stream);

@@ -100,6 +100,23 @@ def test_explore_d2_n300000_is_qhulls_delaunay(vg, incircle):
     assert got["b_sigma"].shape[0] == tri.convex_hull.shape[0]
 
 
+def test_explore_d3_n300000_is_qhulls_delaunay(vg):
+    """d = 3, N = 3e5: the queued edge rays of far hull vertices take the
+    exact-width split of the FP64 recheck over 2^18 nodes or more; the
+    vertex keys are exactly qhull's Delaunay tetrahedra."""
+    from scipy.spatial import Delaunay
+
+    n, d = 300_000, 3
+    X = W.uniform_cloud(n, d, seed=0)
+    got = vg.explore(torch.from_numpy(X).cuda(), W.descent_draws(d))
+    print(f"explore d=3 n=3e5: {got['sigma'].shape[0]} vertices", flush=True)
+    tri = Delaunay(X.astype(np.float64))
+    a = oracle.sorted_rows(got["sigma"])
+    b = oracle.sorted_rows(np.sort(tri.simplices.astype(np.int32), axis=1))
+    assert a.shape == b.shape and np.array_equal(a, b)
+    assert got["b_sigma"].shape[0] == tri.convex_hull.shape[0]
+
+
 def test_explore_d6_n10000_equals_the_oracles_full_search(vg):
     """The d=6, N=10 000 workload at full size against the oracle's own
     sequential Algorithm 2 (run once by tests/golden/make_explore_d6_n10000.py):

@@ -70,3 +70,48 @@ def test_split_recheck_queue_beyond_the_split(vg):
     q = check_rechecked_cells(vg, X, D, t, idx, st, 48, seed=8)
     print(f"  {q} rays rechecked", flush=True)
     assert q > 8192
+
+
+def _far_rays(X, m, seed):
+    """FP64 rays from origins 3 away from the cube's centre, aimed back into
+    the cloud, each with its nearest node as generator (so the origin lies in
+    that node's cell): FP32 cancellation in |r - x|^2 - |g - x|^2 sends most
+    of them to the FP64 recheck."""
+    rng = np.random.default_rng(seed)
+    n, d = X.shape
+    v = rng.standard_normal((m, d))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    O = 0.5 + 3.0 * v
+    U = -v + 0.2 * rng.standard_normal((m, d))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    X64 = X.astype(np.float64)
+    x2 = (X64 * X64).sum(axis=1)
+    g = np.empty(m, dtype=np.int32)
+    for a in range(0, m, 64):
+        dd = x2[None, :] - 2.0 * (O[a:a + 64] @ X64.T)
+        g[a:a + 64] = np.argmin(dd, axis=1)
+    return O, U, g
+
+
+@pytest.mark.parametrize("d,m", [(3, 500), (3, 6000), (8, 500), (8, 6000)])
+def test_split_recheck_of_fp64_origin_rays(vg, d, m):
+    """General rays with FP64 origins over N = 2^18 + 1000 nodes: queues
+    below and above 2048 rays take the per-ray and the tiled split recheck;
+    a sample is compared with the oracle's RayCast on the same FP64 rays."""
+    n = (1 << 18) + 1000
+    X = W.uniform_cloud(n, d, seed=70 + d)
+    O, U, g = _far_rays(X, m, seed=d)
+    dev = torch.device("cuda", 0)
+    print(f"fp64-origin rays d={d} n={n} m={m}", flush=True)
+    t, idx, st = vg.raycast(torch.from_numpy(X).to(dev), torch.from_numpy(O).to(dev), torch.from_numpy(U).to(dev),
+                            torch.from_numpy(g).to(dev), torch.from_numpy(g[:, None].copy()).to(dev), clip=False)
+    s = vg.stats()
+    print(f"  {s['flagged']} of {m} rays rechecked", flush=True)
+    assert s["flagged"] > m // 4
+    if m > 4096:
+        assert s["flagged"] > 2048  # the tiled split, not the per-ray kernel
+    pick = np.sort(np.random.default_rng(1).choice(m, min(m, 400), replace=False))
+    tr, ir, t2r = oracle.raycast(X, O[pick], U[pick], g[pick], excl=g[pick, None], clip=False)
+    from tests.parity import runner_up_rays
+    compare_rays(t.cpu().numpy()[pick], idx.cpu().numpy()[pick], tr, ir, t2r, rtol=1e-5,
+                 runner_up=runner_up_rays(X, O[pick], U[pick], g[pick], g[pick, None], False, ir))
