@@ -17,6 +17,8 @@
 // variants below take one ray per wave and read their clouds directly.
 // The list length is read on the device, so the launch needs no host sync: a
 // fixed grid strides over the list.
+#include <cstdlib>
+
 #include "vg_internal.h"
 #include "vg_philox.h"
 
@@ -104,23 +106,22 @@ __device__ __forceinline__ void finish_ray(const RecheckArgs &a, int64_t ray, in
   a.st_out[ray] = st;
 }
 
-// One node r (coordinates v, as read from memory; entries k >= d unused)
-// against the ray: eq. (t) in FP64 with the factored numerator, into the
-// running top-2.  CELLS: the Monte-Carlo form, x = g.
+// Numerator and denominator of eq. (t) in FP64 for node r (coordinates v,
+// as read from memory; entries k >= d unused): den = u.(r - g) and, with the
+// factored numerator, num = |r - x|^2 - |g - x|^2 = (r - g).((r - x) + (g - x)).
+// CELLS: the Monte-Carlo form, x = g, num = |r - g|^2.
 template <int DK, bool CELLS, typename NT>
-__device__ __forceinline__ void eval_vals(const NT (&v)[DK], int d, int32_t r, const double (&x)[DK],
-                                          const double (&u)[DK], const double (&g)[DK],
-                                          const double (&gx)[DK], Top2 &tp) {
+__device__ __forceinline__ void node_num_den(const NT (&v)[DK], int d, const double (&x)[DK],
+                                             const double (&u)[DK], const double (&g)[DK],
+                                             const double (&gx)[DK], double &num, double &den) {
   double e[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) e[k] = k < d ? (double)v[k] - g[k] : 0.0;
-  double den = 0.0;
+  den = 0.0;
 #pragma unroll
   for (int k = 0; k < DK; ++k)
     if (k < d) den += u[k] * e[k];
-  if (!(den > 0.0)) return;
-  // |r - x|^2 - |g - x|^2 as (r - g).((r - x) + (g - x))
-  double num = 0.0;
+  num = 0.0;
   if (CELLS) {
 #pragma unroll
     for (int k = 0; k < DK; ++k)
@@ -130,6 +131,11 @@ __device__ __forceinline__ void eval_vals(const NT (&v)[DK], int d, int32_t r, c
     for (int k = 0; k < DK; ++k)
       if (k < d) num += e[k] * (((double)v[k] - x[k]) + gx[k]);
   }
+}
+
+// Node r with (num, den) into the running top-2 (eligible: den > 0).
+__device__ __forceinline__ void top2_update(double num, double den, int32_t r, Top2 &tp) {
+  if (!(den > 0.0)) return;
   // cheap filter (relaxed by 1e-12 so no candidate within rounding is lost)
   if (num > tp.t2 * (2.0 * den) * (1.0 + 1e-12) && num > 0.0) return;
   const double t = num / (2.0 * den);
@@ -140,6 +146,16 @@ __device__ __forceinline__ void eval_vals(const NT (&v)[DK], int d, int32_t r, c
   } else if (t < tp.t2) {
     tp.t2 = t;
   }
+}
+
+// One node against the ray, into the running top-2.
+template <int DK, bool CELLS, typename NT>
+__device__ __forceinline__ void eval_vals(const NT (&v)[DK], int d, int32_t r, const double (&x)[DK],
+                                          const double (&u)[DK], const double (&g)[DK],
+                                          const double (&gx)[DK], Top2 &tp) {
+  double num, den;
+  node_num_den<DK, CELLS>(v, d, x, u, g, gx, num, den);
+  top2_update(num, den, r, tp);
 }
 
 // The same for a node row read in place (stride between coordinates); only
@@ -184,6 +200,9 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
                                                                       uint32_t cap = 0,
                                                                       Top2 *__restrict__ parts = nullptr) {
   __shared__ NT tile[DK * NT1];  // [k][node]: lane-contiguous reads
+  // general rays: the excluded nodes of each wave's ray within the tile, one
+  // bit per node (word j covers tile nodes 64 j .. 64 j + 63)
+  __shared__ unsigned long long exmask[CELLS ? 1 : WAVES1][NT1 / 64];
   const NT *rows = node_rows<NT>(a);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int d = EXACT ? DK : a.d;
@@ -200,11 +219,9 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
     int32_t gi = 0;
     // the wave's ray: origin x, direction u, generator g (x = g for CELLS)
     double x[DK], u[DK], g[DK];
-    int32_t ex[VG_MAX_DIM];
+    int32_t my_ex = -1;  // lane e < n_excl holds eta[e]
 #pragma unroll
     for (int k = 0; k < DK; ++k) x[k] = u[k] = g[k] = 0.0;
-#pragma unroll
-    for (int e = 0; e < VG_MAX_DIM; ++e) ex[e] = -1;
     if (live) {
       if (CELLS) {
         gi = (int32_t)(ray / a.R);
@@ -224,9 +241,7 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
             u[k] = a.mode == RAYS_F64 ? a.u64[ray * d + k] : (double)a.u32[ray * d + k];
           }
         }
-#pragma unroll
-        for (int e = 0; e < VG_MAX_DIM; ++e)
-          if (e < n_excl) ex[e] = a.excl[ray * n_excl + e];
+        if (lane < n_excl) my_ex = a.excl[ray * n_excl + lane];
       }
 #pragma unroll
       for (int k = 0; k < DK; ++k) g[k] = k < d ? (double)rows[(int64_t)gi * d + k] : 0.0;
@@ -250,25 +265,45 @@ __global__ __launch_bounds__(NT1, DK <= 8 ? 4 : 1) void recheck_kernel(RecheckAr
       }
       __syncthreads();
       if (!live) continue;
-      for (int q = lane; q < cntn; q += 64) {
-        const int32_t r = (int32_t)(base + q);
-        bool skip;
+      if (!CELLS) {
+        // this wave's exclusion bits for the tile (LDS operations of one
+        // wave complete in order)
+        if (lane < NT1 / 64) exmask[w][lane] = 0ull;
+        __builtin_amdgcn_wave_barrier();
+        const int64_t off = (int64_t)my_ex - base;
+        if (my_ex >= 0 && off >= 0 && off < cntn)
+          atomicOr(&exmask[w][off >> 6], 1ull << (off & 63));
+        __builtin_amdgcn_wave_barrier();
+      }
+      // two nodes per step, q and q + 64: their FP64 sums are independent
+      // chains that overlap; the top-2 still takes the nodes in index order
+      for (int q = lane; q < cntn; q += 128) {
+        const bool has2 = q + 64 < cntn;
+        const int q2 = has2 ? q + 64 : q;
+        const int32_t r = (int32_t)(base + q), r2 = (int32_t)(base + q2);
+        bool skip, skip2;
         if (CELLS) {
           skip = r == gi;
+          skip2 = r2 == gi;
         } else {
-          skip = false;
-#pragma unroll
-          for (int e = 0; e < VG_MAX_DIM; ++e) skip |= (e < n_excl && ex[e] == r);
+          const int j = (q - lane) >> 6;  // wave-uniform word index
+          skip = (exmask[w][j] >> lane) & 1ull;
+          skip2 = j + 1 < NT1 / 64 ? ((exmask[w][j + 1] >> lane) & 1ull) : false;
         }
-        if (skip) continue;
-        if (CELLS) {  // all DK rows, no branch (general rays: the register budget of d <= 8 is spent)
-          NT v[DK];
+        skip2 |= !has2;
+        // CELLS: all DK rows, no branch (the rows k >= d of the tile are zero);
+        // general rays read only the d rows (their register budget is spent)
+        NT v[DK], w[DK];
 #pragma unroll
-          for (int k = 0; k < DK; ++k) v[k] = tile[k * NT1 + q];
-          eval_vals<DK, CELLS>(v, d, r, x, u, g, gx, tp);
-        } else {
-          eval_node<DK, CELLS>(tile + q, NT1, d, r, x, u, g, gx, tp);
+        for (int k = 0; k < DK; ++k) {
+          v[k] = (CELLS || EXACT || k < d) ? tile[k * NT1 + q] : NT(0);
+          w[k] = (CELLS || EXACT || k < d) ? tile[k * NT1 + q2] : NT(0);
         }
+        double num, den, num2, den2;
+        node_num_den<DK, CELLS>(v, d, x, u, g, gx, num, den);
+        node_num_den<DK, CELLS>(w, d, x, u, g, gx, num2, den2);
+        if (!skip) top2_update(num, den, r, tp);
+        if (!skip2) top2_update(num2, den2, r2, tp);
       }
     }
     if (live) {
@@ -579,6 +614,159 @@ __global__ __launch_bounds__(NT) void recheck_rays_batched_kernel(const RayBatch
   }
 }
 
+// Monte-Carlo rays over fewer than 2^18 nodes, targeted: a queued ray first
+// runs an FP32 pass over all nodes that keeps only the candidates that can
+// still be its winner, and only those are evaluated in FP64 (normally one to
+// three instead of every node).
+//
+// FP32 pass: with e = r - x_i the value s = (u.e)/|e|^2 = 1/(2 t) is
+// computed with FMAs, and |s~ - s| <= delta = c / |e|, c = (2d + 8) 2^-24
+// (to first order: u.e within (d + 1) 2^-24 |e|, |e|^2 within (d + 2)
+// 2^-24 relative, the reciprocal square root, its square and the product a
+// few ulps; |u| = 1).  L is the largest lower bound s~ - 2 delta seen
+// (initially the cube's exit, lowered by 2^-18 for its rounding), and a
+// node is kept while s~ + 4 delta >= L: the winner is always kept (its s
+// is at least every lower bound), and a dropped node has
+// s <= s~ + delta < L - 3 delta <= s(winner) - 3 delta, so it is worse than
+// the winner by far more than FP64 rounding and cannot be the FP64 argmin,
+// tie with it, or sit within the FP64 tie gap 1e-9 of it.  The kept nodes
+// are evaluated with the same FP64 expression as the full recheck, merged
+// with the same lowest-index rule and finished by the same finish_ray, so
+// the result is the full recheck's.  A lane that would keep more than KC
+// nodes at once marks its ray, which then gets the full FP64 pass.
+constexpr int KC = 4;
+
+template <int D>
+__global__ __launch_bounds__(NT1) void band_cells_kernel(RecheckArgs a) {
+  __shared__ float tile[D * NT1];  // [k][node]
+  __shared__ int any_over;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t n = a.n;
+  const uint32_t cnt = a.counters[CNT_FLAGGED];
+  constexpr float c_b = (2.f * D + 8.f) * 0x1p-24f;
+  for (uint32_t f0 = blockIdx.x * WAVES1; f0 < cnt; f0 += gridDim.x * WAVES1) {
+    const uint32_t f = f0 + w;
+    const bool live = f < cnt;
+    const int64_t ray = live ? a.flag_list[f] : 0;
+    const int32_t gi = (int32_t)(ray / a.R);
+    float uf[D], xf[D];
+    if (live) {
+      cell_dir<D>(a.dirs, a.seed, gi, a.R, (int)(ray - (int64_t)gi * a.R), D, uf);
+#pragma unroll
+      for (int k = 0; k < D; ++k) xf[k] = a.nodes[(int64_t)gi * D + k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < D; ++k) uf[k] = xf[k] = 0.f;
+    }
+    // the cube's exit in the s domain, lowered by a margin for its rounding
+    float L = 0.f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if (uf[k] != 0.f) {
+        const float h = uf[k] > 0.f ? 1.f - xf[k] : xf[k];
+        L = fmaxf(L, fabsf(uf[k]) / (2.f * h));
+      }
+    }
+    L *= 1.f - 0x1p-18f;
+    float cs[KC];
+    int32_t ci[KC];
+    int nc = 0;
+    bool over = false;
+    if (tid == 0) any_over = 0;
+    for (int64_t base = 0; base < n; base += NT1) {
+      const int cntn = (int)((n - base) < NT1 ? (n - base) : NT1);
+      __syncthreads();
+      if (tid < cntn) {
+        const float *src = a.nodes + (base + tid) * D;
+#pragma unroll
+        for (int k = 0; k < D; ++k) tile[k * NT1 + tid] = src[k];
+      }
+      __syncthreads();
+      if (!live) continue;
+      for (int q = lane; q < cntn; q += 64) {
+        const int32_t r = (int32_t)(base + q);
+        float n2 = 0.f, den = 0.f;
+        bool same = true;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const float e = tile[k * NT1 + q] - xf[k];
+          same &= e == 0.f;
+          n2 = __builtin_fmaf(e, e, n2);
+          den = __builtin_fmaf(uf[k], e, den);
+        }
+        // x_i itself and its exact duplicates are never eligible (u.e = 0);
+        // a node so close that |e|^2 underflows gets the full FP64 pass
+        if (r == gi || same) continue;
+        if (!(n2 >= 0x1p-100f)) {
+          over = true;
+          continue;
+        }
+        const float rs = __builtin_amdgcn_rsqf(n2);
+        const float sv = den * (rs * rs);
+        const float delta = c_b * rs;
+        const float lo = sv - 2.f * delta;  // below s by at least delta
+        if (lo > L) {
+          L = lo;
+          int m = 0;
+#pragma unroll
+          for (int e = 0; e < KC; ++e) {
+            const bool keep = e < nc && cs[e] >= L;
+            if (keep) {
+              cs[m] = cs[e];
+              ci[m] = ci[e];
+            }
+            m += keep ? 1 : 0;
+          }
+          nc = m;
+        }
+        const float hi = sv + 4.f * delta;
+        if (hi >= L) {
+          if (nc < KC) {
+#pragma unroll
+            for (int e = 0; e < KC; ++e)
+              if (e == nc) {
+                cs[e] = hi;
+                ci[e] = r;
+              }
+            ++nc;
+          } else {
+            over = true;
+          }
+        }
+      }
+    }
+    if (!live) continue;
+    // the wave's bound, then the kept nodes in FP64
+    float Lw = L;
+    for (int off = 32; off > 0; off >>= 1) Lw = fmaxf(Lw, __shfl_xor(Lw, off));
+    const bool wave_over = __ballot(over) != 0ull;
+    double x[D], u[D], g[D], gx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      u[k] = (double)uf[k];
+      g[k] = x[k] = (double)xf[k];
+      gx[k] = 0.0;
+    }
+    Top2 tp{__builtin_inf(), __builtin_inf(), -1};
+    if (!wave_over) {
+#pragma unroll
+      for (int e = 0; e < KC; ++e)
+        if (e < nc && cs[e] >= Lw) eval_node<D, true>(a.nodes + (int64_t)ci[e] * D, 1, D, ci[e], x, u, g, gx, tp);
+    } else {
+      for (int64_t r = lane; r < n; r += 64)
+        if (r != gi) eval_node<D, true>(a.nodes + r * D, 1, D, (int32_t)r, x, u, g, gx, tp);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      Top2 o;
+      o.t1 = __shfl_xor(tp.t1, off);
+      o.t2 = __shfl_xor(tp.t2, off);
+      o.i1 = __shfl_xor(tp.i1, off);
+      tp = merge(tp, o);
+    }
+    if (lane == 0) finish_ray<D>(a, ray, D, 1, x, u, tp);
+  }
+}
+
 // Few queued general rays over many nodes (the caller knows the queue length
 // cnt): workgroup (x, y) takes queued rays x, x + gridDim.x, ... over the
 // nodes [y chunk, (y+1) chunk), with the wide kernel's striding and merges,
@@ -838,6 +1026,19 @@ hipError_t launch_recheck(const RecheckArgs &a, int max_grid, hipStream_t s, int
     return hipGetLastError();
   }
 #undef VG_RECHECK_EXACT
+  // Monte-Carlo rays over fewer than 2^18 nodes: the targeted band recheck
+  // (VG_FULL_RECHECK set: every node in FP64, for comparison)
+  if (cells && !wide && std::getenv("VG_FULL_RECHECK") == nullptr) {
+    switch (a.d) {
+#define VG_BAND(DV) \
+  case DV: hipLaunchKernelGGL(band_cells_kernel<DV>, grid, blk, 0, s, a); break;
+      VG_BAND(2) VG_BAND(3) VG_BAND(4) VG_BAND(5) VG_BAND(6) VG_BAND(7) VG_BAND(8) VG_BAND(9)
+      VG_BAND(10) VG_BAND(11) VG_BAND(12) VG_BAND(13) VG_BAND(14) VG_BAND(15) VG_BAND(16)
+#undef VG_BAND
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
 #define VG_RECHECK(DKV)                                                            \
   do {                                                                            \
     if (wide && cells)                                                            \
