@@ -381,17 +381,22 @@ typedef struct vg_cells_problem {
 } vg_cells_problem;
 
 /* vg_raycast_cells (the Monte-Carlo rays of Algorithm 3) over many clouds of
- * different d, N and rays_per_cell: one persistent launch per register class
- * of d (d <= 4, <= 8, <= 12, <= 16; BF16x3: <= 5, <= 10, <= 16) in which
- * workgroups take (cloud, cell, ray chunk) items from a device counter,
- * largest clouds first; then one FP64 recheck of the flagged rays of every
- * cloud.  Each ray's result equals what vg_raycast_cells returns for it.
+ * different d, N and rays_per_cell in one graph launch: one launch of the
+ * single-cloud scan per cloud (the exact-K kernel of its d, in the tile shape
+ * tuned for its bucket), largest clouds first, spread over four parallel
+ * graph branches so the clouds' launch tails overlap; then one FP64 recheck
+ * of the flagged rays of every cloud.  Each ray's result equals what
+ * vg_raycast_cells returns for it.
  * flags: VG_PREC_BF16X3; VG_NO_RECHECK is VG_EUNSUPPORTED.  The problem table
  * is a HOST array read during the call only; the launches are captured into
- * a hipGraph per distinct table and replayed when the same table recurs.
- * With every status_out set, a tuner picks the tile shape per (d, N) bucket
- * on first sight (timings cached in $VG_TUNE_CACHE, default
- * $HOME/.cache/vgraph_tune.txt). */
+ * a hipGraph per distinct table and replayed when the same table recurs (at
+ * most 8 graphs are kept per context).  With every status_out set, a tuner
+ * times half, the default and twice the default rays per workgroup on a probe
+ * of each (ceil(d/2), log2 N, rays_per_cell, precision) bucket on first sight
+ * (timings cached in $VG_TUNE_CACHE, default $HOME/.cache/vgraph_tune.txt)
+ * and each cloud uses its bucket's fastest.  Errors: VG_EINVAL for a bad
+ * table entry (d outside [2, 16] is VG_EUNSUPPORTED), VG_ENOMEM when the
+ * queue or table cannot be allocated. */
 int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems,
                              const vg_cells_problem *probs, uint32_t flags);
 

@@ -1,22 +1,23 @@
-// Uneven batches of RayCast problems in persistent launches.
+// Uneven batches of RayCast problems in one graph launch.
 //
-// vg_raycast_cells_batched groups the clouds by register class of their K
-// extent (one persistent kernel per class keeps the occupancy of the small
-// extents), orders them by decreasing cost within a class (N^2 R ceil(d/2):
-// pairs times MFMA K-steps), lays their (cell, ray-chunk) items out in that
-// order, and runs per class one persistent scan kernel that takes items from
-// a device counter; then one batched FP64 recheck.  vg_raycast_batched does
-// the same for general rays (one persistent kernel over 256-ray tiles of all
-// problems).  The launches (counter fill, scans, recheck) are captured once
-// into a hipGraph per distinct problem table and replayed on later calls with
-// the same table.
+// vg_raycast_cells_batched orders the clouds by decreasing cost (N^2 R
+// ceil(d/2): pairs times MFMA K-steps) and captures, once per distinct
+// problem table, a hipGraph of: one launch of the single-cloud cell scan per
+// cloud -- the exact-K kernel of its dimension, in the tile shape tuned for
+// its bucket -- spread over kBranches parallel branches (each cloud goes to
+// the branch with the least work so far, largest clouds first), so that the
+// clouds' launch tails overlap; then one batched FP64 recheck of the flagged
+// rays of every cloud.  Later calls with the same table replay the graph.
+// vg_raycast_batched does the same for general rays with one persistent
+// kernel over 256-ray tiles of all problems.
 //
-// Tile shape: the persistent cell kernels exist in a few shapes (rays per
-// item, waves per workgroup).  A tuner times every shape on a probe of each
-// (K-steps, log2 N, rays-per-cell, precision) bucket present in a batch --
-// the first items of that bucket's clouds -- records nanoseconds per
-// ray-node pair, and picks the shape with the smallest predicted batch time.
-// Timings are cached in memory and in a text file (VG_TUNE_CACHE, default
+// Tile shape: the single-cloud scan exists for 64 .. 1024 rays per
+// workgroup.  A tuner times, on a probe of each (K-steps, log2 N,
+// rays-per-cell, precision) bucket present in a batch -- the first cells of
+// that bucket's largest cloud --, half, the default and twice the default
+// rays per workgroup for that rays-per-cell, records nanoseconds per
+// ray-node pair, and the bucket's clouds use the fastest.  Timings are
+// cached in memory and in a text file (VG_TUNE_CACHE, default
 // $HOME/.cache/vgraph_tune.txt) so later processes skip the probes.
 #include <algorithm>
 #include <cmath>
@@ -35,6 +36,9 @@
 using namespace vg;
 
 namespace {
+
+constexpr int kBranches = 4;   // parallel branches of a batch graph
+constexpr int kNumShapes = 3;  // half, default, twice the default rays per workgroup
 
 struct GraphEntry {
   uint64_t key = 0;
@@ -57,10 +61,13 @@ struct TuneKey {
 
 struct BatchState {
   hipStream_t capture = nullptr;
+  hipStream_t branch[kBranches] = {};
+  hipEvent_t fork = nullptr, join[kBranches] = {};
   std::vector<GraphEntry> graphs;
   uint64_t clock = 0;
   std::map<TuneKey, std::vector<double>> tune;  // ns per ray-node pair per shape
   bool tune_loaded = false;
+  std::string tune_file;  // the cache file the timings were loaded from
   int cus = 0;
 };
 
@@ -89,6 +96,7 @@ std::string tune_path() {
 void load_tune(BatchState &S) {
   S.tune_loaded = true;
   const std::string path = tune_path();
+  S.tune_file = path;
   if (path.empty()) return;
   FILE *f = std::fopen(path.c_str(), "r");
   if (!f) return;
@@ -96,9 +104,9 @@ void load_tune(BatchState &S) {
   int shape;
   double ns;
   while (std::fscanf(f, "%d %d %d %d %d %lf", &k.kp, &k.log2n, &k.R, &k.bf16, &shape, &ns) == 6) {
-    if (shape < 0 || shape >= kNumBatchShapes) continue;
+    if (shape < 0 || shape >= kNumShapes) continue;
     auto &v = S.tune[k];
-    v.resize(kNumBatchShapes, -1.0);
+    v.resize(kNumShapes, -1.0);
     v[shape] = ns;
   }
   std::fclose(f);
@@ -119,50 +127,59 @@ void save_tune(const BatchState &S) {
   std::rename(tmp.c_str(), path.c_str());
 }
 
-int rays_per_item(int shape) { return 32 * kBatchShapes[shape].C * kBatchShapes[shape].waves; }
-
 int ilog2(int64_t n) {
   int l = 0;
   while ((int64_t(1) << (l + 1)) <= n) ++l;
   return l;
 }
 
-// Device table of a batch for a given shape (host side).
-std::vector<BatchProblem> make_table(const std::vector<vg_cells_problem> &pr,
-                                     const std::vector<int> &order, int shape, bool bf16,
-                                     uint32_t *counters, int64_t *flags, uint8_t *status,
-                                     int64_t &total_items, int64_t &total_rays) {
+// Rays per workgroup of shape sh (0: half, 1: the default, 2: twice the
+// default for R rays per cell), or 0 when it is outside 64 .. 1024.
+int shape_rw(int R, int sh) {
+  const int r0 = cell_scan_rays_per_wg(R);
+  const int rw = sh == 0 ? r0 / 2 : (sh == 1 ? r0 : 2 * r0);
+  return (rw >= 64 && rw <= 1024) ? rw : 0;
+}
+
+TuneKey tune_key(const vg_cells_problem &p, bool bf16) {
+  return TuneKey{(p.d + 1) / 2, ilog2(p.n_nodes), p.rays_per_cell, bf16 ? 1 : 0};
+}
+
+// The scan arguments of one cloud of a batch (q: its position in the table).
+CellScanArgs cloud_args(const vg_cells_problem &p, int q, bool bf16, int rw, uint32_t *counters, int64_t *flags,
+                        uint8_t *status) {
+  CellScanArgs a{};
+  a.nodes = p.nodes;
+  a.n = p.n_nodes;
+  a.d = p.d;
+  a.dirs = p.dirs;
+  a.R = p.rays_per_cell;
+  a.wg_per_cell = (p.rays_per_cell + rw - 1) / rw;
+  a.t_out = p.t_out;
+  a.idx_out = p.idx_out;
+  a.st_out = p.status_out ? p.status_out : status;
+  a.counters = counters;
+  a.flag_list = flags;
+  a.tau_rel = bf16 ? kTauCellsBf16 : kTauCellsFp32;
+  a.kappa = cell_kappa(p.d, bf16);
+  a.flag_tag = (int64_t)q << 40;
+  return a;
+}
+
+// Device table of a batch (the recheck reads it).
+std::vector<BatchProblem> make_table(const std::vector<vg_cells_problem> &pr, const std::vector<int> &order,
+                                     const std::vector<int> &rw, bool bf16, uint32_t *counters, int64_t *flags,
+                                     uint8_t *status, int64_t &total_rays) {
   std::vector<BatchProblem> T(order.size());
-  const int rw = rays_per_item(shape);
-  total_items = 0;
   total_rays = 0;
   int64_t status_off = 0;
   for (size_t q = 0; q < order.size(); ++q) {
     const vg_cells_problem &p = pr[order[q]];
-    CellScanArgs &a = T[q].a;
-    a = CellScanArgs{};
-    a.nodes = p.nodes;
-    a.n = p.n_nodes;
-    a.d = p.d;
-    a.dirs = p.dirs;
-    a.R = p.rays_per_cell;
-    a.wg_per_cell = (p.rays_per_cell + rw - 1) / rw;
-    a.t_out = p.t_out;
-    a.idx_out = p.idx_out;
     const int64_t m = p.n_nodes * (int64_t)p.rays_per_cell;
-    if (p.status_out) {
-      a.st_out = p.status_out;
-    } else {
-      a.st_out = status ? status + status_off : nullptr;
-      status_off += m;
-    }
-    a.counters = counters;
-    a.flag_list = flags;
-    a.tau_rel = bf16 ? kTauCellsBf16 : kTauCellsFp32;
-    a.kappa = cell_kappa(p.d, bf16);
-    a.flag_tag = (int64_t)q << 40;
-    T[q].item_begin = total_items;
-    total_items += p.n_nodes * a.wg_per_cell;
+    T[q].a = cloud_args(p, (int)q, bf16, rw[order[q]], counters, flags,
+                        (!p.status_out && status) ? status + status_off : nullptr);
+    if (!p.status_out) status_off += m;
+    T[q].item_begin = 0;
     total_rays += m;
   }
   return T;
@@ -182,6 +199,11 @@ void batch_state_free(vg_ctx *ctx) {
   if (!S) return;
   for (auto &g : S->graphs) free_entry(g);
   if (S->capture) (void)hipStreamDestroy(S->capture);
+  for (int b = 0; b < kBranches; ++b) {
+    if (S->branch[b]) (void)hipStreamDestroy(S->branch[b]);
+    if (S->join[b]) (void)hipEventDestroy(S->join[b]);
+  }
+  if (S->fork) (void)hipEventDestroy(S->fork);
   delete S;
   ctx->batch_state = nullptr;
 }
@@ -195,25 +217,36 @@ BatchState &state(vg_ctx *ctx) {
   return *static_cast<BatchState *>(ctx->batch_state);
 }
 
-int persistent_grid(vg_ctx *ctx, int shape, bool bf16, int cls) {
+int cus(vg_ctx *ctx) {
   BatchState &S = state(ctx);
   if (!S.cus) {
     hipDeviceProp_t prop;
     S.cus = (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ? prop.multiProcessorCount : 256;
   }
-  return S.cus * batched_blocks_per_cu(shape, bf16, cls);
+  return S.cus;
+}
+
+// Branch streams and fork/join events of the batch graphs (default priority).
+int ensure_branches(vg_ctx *ctx) {
+  BatchState &S = state(ctx);
+  if (S.fork) return VG_OK;
+  for (int b = 0; b < kBranches; ++b)
+    if (hipStreamCreateWithFlags(&S.branch[b], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S.join[b], hipEventDisableTiming) != hipSuccess)
+      return err(ctx, VG_EDEVICE, "branch stream creation failed");
+  if (hipEventCreateWithFlags(&S.fork, hipEventDisableTiming) != hipSuccess)
+    return err(ctx, VG_EDEVICE, "branch event creation failed");
+  return VG_OK;
 }
 
 // Device buffers of one batch: problem table, FP64 recheck queue, counters
-// (CNT_WORDS u32, then from byte 32 one u64 item counter per launch, at most
-// four), status scratch.
+// (CNT_WORDS u32, then from byte 32 a u64 item counter), status scratch.
 struct BatchBuffers {
   void *table;
   int64_t *flags;
   uint32_t *counters;
   uint8_t *status;
 };
-
 // Runs the launches of one batch.  The first call with a given key allocates
 // the buffers, fills and uploads the table, and captures the launches into a
 // hipGraph on a private capture stream; later calls with the same key replay
@@ -299,22 +332,29 @@ int run_batch(vg_ctx *ctx, uint64_t key, int64_t rays, bool need_status, size_t 
   return VG_OK;
 }
 
-// Time every shape on a probe of each bucket missing from the cache.
-int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16) {
+// Time every shape on a probe of each bucket missing from the cache, then
+// set rw[i], the rays per workgroup of cloud i, to its bucket's fastest.
+int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16, std::vector<int> &rw) {
   BatchState &S = state(ctx);
-  if (!S.tune_loaded) load_tune(S);
+  if (!S.tune_loaded || S.tune_file != tune_path()) {
+    S.tune.clear();
+    load_tune(S);
+  }
   std::map<TuneKey, std::vector<int>> buckets;
-  for (int i = 0; i < (int)pr.size(); ++i)
-    buckets[{(pr[i].d + 1) / 2, ilog2(pr[i].n_nodes), pr[i].rays_per_cell, bf16 ? 1 : 0}].push_back(i);
+  for (int i = 0; i < (int)pr.size(); ++i) buckets[tune_key(pr[i], bf16)].push_back(i);
   bool changed = false;
-  void *counters = nullptr, *flags = nullptr, *tab = nullptr;
+  void *counters = nullptr, *flags = nullptr;
+  size_t flags_bytes = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = VG_OK;
   for (auto &b : buckets) {
     auto it = S.tune.find(b.first);
-    if (it != S.tune.end() && std::all_of(it->second.begin(), it->second.end(),
-                                          [](double v) { return v > 0; }))
-      continue;
+    if (it != S.tune.end() && it->second.size() == (size_t)kNumShapes) {
+      bool done = true;
+      for (int sh = 0; sh < kNumShapes; ++sh)
+        done &= it->second[sh] > 0 || !shape_rw(b.first.R, sh);
+      if (done) continue;
+    }
     if (!counters) {
       if (hipMalloc(&counters, 64) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
           hipEventCreate(&e1) != hipSuccess) {
@@ -325,56 +365,41 @@ int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16) {
     // probe: the first cells of the bucket's largest cloud
     int big = b.second[0];
     for (int i : b.second)
-      if (pr[i].n_nodes > pr[big].n_nodes) big = i;
-    std::vector<double> ns(kNumBatchShapes, -1.0);
-    for (int sh = 0; sh < kNumBatchShapes; ++sh) {
-      const int64_t cells = std::min<int64_t>(pr[big].n_nodes, 4 * 1024);
-      std::vector<int> one = {big};
-      int64_t items, rays;
-      const int64_t m = pr[big].n_nodes * (int64_t)pr[big].rays_per_cell;
+      if (pr[big].n_nodes < pr[i].n_nodes) big = i;
+    const vg_cells_problem &p = pr[big];
+    const int64_t cells = std::min<int64_t>(p.n_nodes, 4 * 1024);
+    const size_t need = (size_t)(cells * p.rays_per_cell) * 8;
+    if (need > flags_bytes) {
       if (flags) (void)hipFree(flags);
       flags = nullptr;
-      if (hipMalloc(&flags, (size_t)m * 8) != hipSuccess) {
+      if (hipMalloc(&flags, need) != hipSuccess) {
         rc = err(ctx, VG_ENOMEM, "tuner queue allocation failed");
         break;
       }
-      std::vector<BatchProblem> T =
-          make_table(pr, one, sh, bf16, (uint32_t *)counters, (int64_t *)flags,
-                     nullptr, items, rays);
-      if (!pr[big].status_out) {
-        rc = err(ctx, VG_EINVAL, "tuning needs status outputs");
-        break;
-      }
-      if (!tab && hipMalloc(&tab, sizeof(BatchProblem)) != hipSuccess) {
-        rc = err(ctx, VG_ENOMEM, "tuner table allocation failed");
-        break;
-      }
-      const int64_t probe_items = std::min<int64_t>(items, cells * T[0].a.wg_per_cell);
-      if (hipMemcpyAsync(tab, T.data(), sizeof(BatchProblem), hipMemcpyHostToDevice, ctx->stream) !=
-              hipSuccess ||
-          fill_u32((uint32_t *)counters, 0u, 16, ctx->stream) != hipSuccess) {
-        rc = err(ctx, VG_EDEVICE, "tuner upload failed");
-        break;
-      }
-      const int cls = batched_class(pr[big].d, bf16);
-      const int grid = persistent_grid(ctx, sh, bf16, cls);
-      unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)counters + 32);
-      // warm-up, then timed run of the probe
-      if (launch_cell_scan_batched((const BatchProblem *)tab, 1, 0, std::min<int64_t>(probe_items, grid),
-                                   next, sh, bf16, cls, grid, ctx->stream) != hipSuccess ||
+      flags_bytes = need;
+    }
+    if (!p.status_out) {
+      rc = err(ctx, VG_EINVAL, "tuning needs status outputs");
+      break;
+    }
+    std::vector<double> ns(kNumShapes, -2.0);  // -2: shape not available for this R
+    for (int sh = 0; sh < kNumShapes && rc == VG_OK; ++sh) {
+      const int r = shape_rw(p.rays_per_cell, sh);
+      if (!r) continue;
+      const CellScanArgs a = cloud_args(p, 0, bf16, r, (uint32_t *)counters, (int64_t *)flags, nullptr);
+      // warm-up, then the timed probe
+      if (fill_u32((uint32_t *)counters, 0u, 16, ctx->stream) != hipSuccess ||
+          launch_cell_scan_rw(a, bf16, r, std::min<int64_t>(cells, 256), ctx->stream) != hipSuccess ||
           fill_u32((uint32_t *)counters, 0u, 16, ctx->stream) != hipSuccess ||
           hipEventRecord(e0, ctx->stream) != hipSuccess ||
-          launch_cell_scan_batched((const BatchProblem *)tab, 1, 0, probe_items, next, sh, bf16, cls, grid,
-                                   ctx->stream) != hipSuccess ||
+          launch_cell_scan_rw(a, bf16, r, cells, ctx->stream) != hipSuccess ||
           hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
         rc = err(ctx, VG_EDEVICE, "tuner probe launch failed");
         break;
       }
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      const double pairs = (double)probe_items / T[0].a.wg_per_cell * pr[big].rays_per_cell *
-                           (double)pr[big].n_nodes;
-      ns[sh] = ms * 1e6 / pairs;
+      ns[sh] = ms * 1e6 / ((double)cells * p.rays_per_cell * (double)p.n_nodes);
     }
     if (rc) break;
     S.tune[b.first] = ns;
@@ -384,24 +409,16 @@ int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16) {
   if (e1) (void)hipEventDestroy(e1);
   if (counters) (void)hipFree(counters);
   if (flags) (void)hipFree(flags);
-  if (tab) (void)hipFree(tab);
-  if (rc) return -1;
+  if (rc) return rc;
   if (changed) save_tune(S);
-  // predicted batch time per shape
-  int best = 0;
-  double best_t = 1e300;
-  for (int sh = 0; sh < kNumBatchShapes; ++sh) {
-    double t = 0;
-    for (auto &p : pr) {
-      const auto &v = S.tune[{(p.d + 1) / 2, ilog2(p.n_nodes), p.rays_per_cell, bf16 ? 1 : 0}];
-      t += v[sh] * (double)p.n_nodes * p.rays_per_cell * (double)p.n_nodes;
-    }
-    if (t < best_t) {
-      best_t = t;
-      best = sh;
-    }
+  for (int i = 0; i < (int)pr.size(); ++i) {
+    const auto &v = S.tune[tune_key(pr[i], bf16)];
+    int best = 1;
+    for (int sh = 0; sh < kNumShapes; ++sh)
+      if (v[sh] > 0 && shape_rw(pr[i].rays_per_cell, sh) && v[sh] < v[best]) best = sh;
+    rw[i] = shape_rw(pr[i].rays_per_cell, best);
   }
-  return best;
+  return VG_OK;
 }
 
 }  // namespace
@@ -427,68 +444,73 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
     if (!p.nodes || !p.dirs || !p.t_out || !p.idx_out) return err(ctx, VG_EINVAL, "null problem array");
     if (p.n_nodes * (int64_t)p.rays_per_cell >= (int64_t(1) << 40))
       return err(ctx, VG_EINVAL, "problem too large");
+    if (p.n_nodes * ((p.rays_per_cell + 63) / 64) > 0x7fffffff)
+      return err(ctx, VG_EINVAL, "problem needs more than 2^31 workgroups");
   }
-  // grouped by register class, largest clouds first within a class
+  int rc = ensure_branches(ctx);
+  if (rc) return rc;
+  // largest clouds first
   std::vector<int> order(n_problems);
   std::iota(order.begin(), order.end(), 0);
   auto cost = [&](int i) {
     return (double)pr[i].n_nodes * pr[i].n_nodes * pr[i].rays_per_cell * ((pr[i].d + 1) / 2);
   };
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const int ca = batched_class(pr[a].d, bf16), cb = batched_class(pr[b].d, bf16);
-    return ca != cb ? ca < cb : cost(a) > cost(b);
-  });
-
-  int shape = 0;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<int> rw(n_problems);
+  for (int i = 0; i < n_problems; ++i) rw[i] = cell_scan_rays_per_wg(pr[i].rays_per_cell);
   if (const char *e = std::getenv("VG_BATCH_SHAPE")) {
-    shape = std::max(0, std::min(kNumBatchShapes - 1, std::atoi(e)));
+    const int sh = std::max(0, std::min(kNumShapes - 1, std::atoi(e)));
+    for (int i = 0; i < n_problems; ++i)
+      if (const int r = shape_rw(pr[i].rays_per_cell, sh)) rw[i] = r;
   } else {
     bool have_status = true;
     for (auto &p : pr) have_status &= p.status_out != nullptr;
     if (have_status) {
-      shape = tune(ctx, pr, bf16);
-      if (shape < 0) return VG_EDEVICE;
+      rc = tune(ctx, pr, bf16, rw);
+      if (rc) return rc;
+    }
+  }
+  // branches: each cloud, largest first, to the branch with the least work
+  std::vector<int> branch_of(order.size());
+  {
+    double load[kBranches] = {};
+    for (size_t q = 0; q < order.size(); ++q) {
+      const int b = (int)(std::min_element(load, load + kBranches) - load);
+      branch_of[q] = b;
+      load[b] += cost(order[q]);
     }
   }
   // key: everything the launches depend on
-  int64_t items0, rays0;
-  std::vector<BatchProblem> probe =
-      make_table(pr, order, shape, bf16, nullptr, nullptr, nullptr, items0, rays0);
+  int64_t rays0;
+  std::vector<BatchProblem> probe = make_table(pr, order, rw, bf16, nullptr, nullptr, nullptr, rays0);
   uint64_t key = fnv(probe.data(), probe.size() * sizeof(BatchProblem));
-  key = fnv(&shape, sizeof shape, key);
   key = fnv(&flags, sizeof flags, key);
   bool need_status = false;
   for (auto &p : pr) need_status |= p.status_out == nullptr;
-  // item range of each register class (the table is grouped by class)
-  int64_t cls_first[kNumBatchClasses], cls_last[kNumBatchClasses];
-  for (int c = 0; c < kNumBatchClasses; ++c) cls_first[c] = cls_last[c] = 0;
-  for (size_t q = 0; q < probe.size(); ++q) {
-    const int c = batched_class(probe[q].a.d, bf16);
-    const int64_t b0 = probe[q].item_begin;
-    const int64_t b1 = q + 1 < probe.size() ? probe[q + 1].item_begin : items0;
-    if (cls_last[c] == cls_first[c]) cls_first[c] = b0;
-    cls_last[c] = b1;
-  }
+  BatchState &S = state(ctx);
   auto fill = [&](const BatchBuffers &b, std::vector<char> &bytes) {
-    int64_t items, rays;
-    std::vector<BatchProblem> T =
-        make_table(pr, order, shape, bf16, b.counters, b.flags, b.status, items, rays);
-    bytes.assign(reinterpret_cast<const char *>(T.data()),
-                 reinterpret_cast<const char *>(T.data() + T.size()));
+    int64_t rays;
+    std::vector<BatchProblem> T = make_table(pr, order, rw, bf16, b.counters, b.flags, b.status, rays);
+    bytes.assign(reinterpret_cast<const char *>(T.data()), reinterpret_cast<const char *>(T.data() + T.size()));
   };
   auto enqueue = [&](const BatchBuffers &b, hipStream_t s) -> hipError_t {
+    int64_t rays;
+    const std::vector<BatchProblem> T = make_table(pr, order, rw, bf16, b.counters, b.flags, b.status, rays);
     const int rgrid = (int)std::min<int64_t>((rays0 + 3) / 4, 2048);
-    unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)b.counters + 32);
     hipError_t e = fill_u32(b.counters, 0u, 16, s);
-    for (int c = 0; c < kNumBatchClasses && e == hipSuccess; ++c) {
-      if (cls_last[c] <= cls_first[c]) continue;
-      const int grid = (int)std::min<int64_t>(cls_last[c] - cls_first[c], persistent_grid(ctx, shape, bf16, c));
-      e = launch_cell_scan_batched((const BatchProblem *)b.table, n_problems, cls_first[c], cls_last[c],
-                                   next + c, shape, bf16, c, grid, s);
+    // fork
+    if (e == hipSuccess) e = hipEventRecord(S.fork, s);
+    for (int k = 0; k < kBranches && e == hipSuccess; ++k) e = hipStreamWaitEvent(S.branch[k], S.fork, 0);
+    for (size_t q = 0; q < T.size() && e == hipSuccess; ++q)
+      e = launch_cell_scan_rw(T[q].a, bf16, rw[order[q]], T[q].a.n, S.branch[branch_of[q]]);
+    // join
+    for (int k = 0; k < kBranches && e == hipSuccess; ++k) {
+      e = hipEventRecord(S.join[k], S.branch[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, S.join[k], 0);
     }
     if (e == hipSuccess)
-      e = launch_recheck_batched((const BatchProblem *)b.table, b.counters, b.flags,
-                                 b.counters + CNT_FP64_TIE, std::max(rgrid, 1), s);
+      e = launch_recheck_batched((const BatchProblem *)b.table, b.counters, b.flags, b.counters + CNT_FP64_TIE,
+                                 std::max(rgrid, 1), s);
     return e;
   };
   return run_batch(ctx, key, rays0, need_status, probe.size() * sizeof(BatchProblem), fill, enqueue,

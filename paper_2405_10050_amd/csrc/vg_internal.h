@@ -87,12 +87,6 @@ struct BatchProblem {
   int64_t item_begin;
 };
 
-struct BatchShape {
-  int C, waves;
-};
-constexpr int kNumBatchShapes = 3;
-extern const BatchShape kBatchShapes[kNumBatchShapes];
-
 struct RecheckArgs {
   int mode;
   const float *nodes;
@@ -164,6 +158,9 @@ struct BackwardArgs {
 // Launchers (return a hipError_t of the launch).
 hipError_t launch_cell_scan_fp32(const CellScanArgs &a, hipStream_t s);
 hipError_t launch_cell_scan_bf16x3(const CellScanArgs &a, hipStream_t s);
+// The same over cells [0, n_cells) with rw rays per workgroup (64, 128, 256,
+// 512 or 1024; a.wg_per_cell is set from it).
+hipError_t launch_cell_scan_rw(const CellScanArgs &a, bool bf16, int rw, int64_t n_cells, hipStream_t s);
 // Directed generator adjacency (CSR) of a set of vertex tuples; synchronises
 // the stream.  Defined in vg_nbr.hip.
 int tuple_neighbors(int d, int64_t n_nodes, int64_t n_tuples, const int32_t *sigma,
@@ -244,14 +241,6 @@ struct FinalizeArgs {
 };
 hipError_t launch_finalize_bad(const FinalizeArgs &f, hipStream_t s);
 
-// Persistent batched scan over items [first, last) of the table, all of one
-// register class (batched_class); `next` is that launch's item counter.
-hipError_t launch_cell_scan_batched(const BatchProblem *probs_dev, int np, int64_t first, int64_t last,
-                                    unsigned long long *next, int shape, bool bf16, int cls, int grid,
-                                    hipStream_t s);
-int batched_blocks_per_cu(int shape, bool bf16, int cls);
-int batched_class(int d, bool bf16);
-constexpr int kNumBatchClasses = 4;
 hipError_t launch_recheck_batched(const BatchProblem *probs_dev, const uint32_t *counters,
                                   const int64_t *flag_list, uint32_t *tie_counter, int grid,
                                   hipStream_t s);

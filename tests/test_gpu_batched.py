@@ -1,6 +1,7 @@
-"""Uneven batches in one persistent launch: parity with the oracle and with
-the single-cloud path, hipGraph replays against eager launches, and the
-tuner's cache file."""
+"""Uneven batches in one graph launch (one exact single-cloud scan per cloud
+on parallel branches, then one batched FP64 recheck): parity with the oracle
+and with the single-cloud path in every tile shape, hipGraph replays against
+eager launches, and the tuner's cache file."""
 import os
 
 import numpy as np
@@ -75,3 +76,37 @@ def test_graph_replays_match_eager(vg, batch, monkeypatch):
             assert np.array_equal(i.cpu().numpy(), ie), rep
             assert np.array_equal(t.cpu().numpy().view(np.uint32), te.view(np.uint32)), rep
             assert np.array_equal(s.cpu().numpy(), se), rep
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_every_tile_shape_equals_the_single_path(vg, batch, shape, monkeypatch):
+    """Half, the default and twice the default rays per workgroup: the rays'
+    results do not depend on the tile shape."""
+    monkeypatch.setenv("VG_BATCH_SHAPE", str(shape))
+    for prec in ("fp32", "bf16x3"):
+        got = _run(vg, batch, prec)
+        for (X, D, Xd, Dd), (t, idx, st) in zip(batch, got):
+            t1, i1, s1 = vg.raycast_cells(Xd, Dd, precision=prec)
+            assert np.array_equal(i1.cpu().numpy(), idx)
+            assert np.array_equal(t1.cpu().numpy().view(np.uint32), t.view(np.uint32))
+            assert np.array_equal(s1.cpu().numpy(), st)
+
+
+def test_tuner_cache_file_format(vg, batch, tmp_path, monkeypatch):
+    """One line per (K-steps, log2 N, rays per cell, precision, shape) with a
+    positive time per ray-node pair; a second call with the same file probes
+    nothing new, so the file is left as it was."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("VG_TUNE_CACHE", str(path))
+    _run(vg, batch[:3])
+    text = path.read_text()
+    rows = [ln.split() for ln in text.splitlines()]
+    assert len(rows) >= 3
+    for r in rows:
+        assert len(r) == 6
+        kp, log2n, R, bf16, shape = map(int, r[:5])
+        assert 1 <= kp <= 8 and log2n >= 0 and 1 <= R <= 4096 and bf16 == 0 and 0 <= shape <= 2
+        assert float(r[5]) > 0
+    mtime = path.stat().st_mtime_ns
+    _run(vg, batch[:3])
+    assert path.stat().st_mtime_ns == mtime and path.read_text() == text
