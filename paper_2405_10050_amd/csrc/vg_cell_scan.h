@@ -25,8 +25,12 @@
 // whose max does not exceed the lane's second best cannot change anything
 // (fast path: an integer v_max3 tree over the bit patterns and one compare;
 // best and second are never negative, and non-negative floats order like
-// their bit patterns); otherwise every value updates the top-2 with v_med3
-// and the argmax with a compare/select.
+// their bit patterns); a block max between second and best only becomes the
+// new second; only a block holding a new best runs the exact top-2 update of
+// its 16 values (v_max/v_med3 on the bit patterns) and the argmax search.
+// A non-finite accumulator value (possible only next to a near-duplicate
+// node, whose cell the certificate flags wholesale) makes best or second NaN,
+// which the certificate's comparison also sends to the FP64 recheck.
 //
 // Near-tie certificate: with |u| = 1 the FP32 value of u.r~ is within
 // (2d+4) 2^-24 |r~| of the exact one, and |r~| <= 1/nn_i (nn_i = distance to
@@ -61,17 +65,41 @@ __device__ __forceinline__ int max16_bits(const f32x16 &v) {
 // Top-2 update of one lane with the 16 accumulator values of a 32x32 block.
 // The argmax is kept encoded as (32-row block << 4) | register (decoded by
 // decode_row), so the update needs no per-row index arithmetic.
+//
+// With m the block's maximum: a block with m <= second changes nothing; one
+// with second < m <= best only raises second to m (every value of the block
+// is <= best); only a block with m > best needs the exact running top-2 over
+// its 16 values (prefix maximum and median-of-three) and the argmax, the
+// lowest register that holds the new best.  The wave takes a branch when any
+// of its lanes needs it, so the common middle case costs one instruction.
+// All of it runs on the bit patterns: with best >= second >= +0, signed
+// integer max and median order them as the floats (a negative value is
+// below both and never enters).
+__device__ __forceinline__ int imed3(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+
 __device__ __forceinline__ void epilogue16(const f32x16 &acc, float &best, float &second,
                                            int &bidx, int blk16) {
-  if (max16_bits(acc) > __float_as_int(second)) {
+  const int m = max16_bits(acc);
+  const int bb = __float_as_int(best), sb = __float_as_int(second);
+  if (m > sb) {
+    if (m > bb) {
+      int v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const float s = acc[i];
-      second = __builtin_amdgcn_fmed3f(s, best, second);
-      if (s > best) {
-        best = s;
-        bidx = blk16 | i;
+      for (int i = 0; i < 16; ++i) v[i] = __float_as_int(acc[i]);
+      int b = bb, s = sb;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        s = imed3(v[i], b, s);
+        b = max(b, v[i]);
       }
+      int idx = 15;
+#pragma unroll
+      for (int i = 14; i >= 0; --i) idx = (v[i] == m) ? i : idx;
+      bidx = blk16 | idx;
+      best = __int_as_float(m);
+      second = __int_as_float(s);
+    } else {
+      second = __int_as_float(m);
     }
   }
 }
