@@ -397,8 +397,13 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 }
 
 // GEN: the directions are drawn from a.seed (a.dirs is null), else read.
+// At least two waves per SIMD: with a budget of 256 registers the compiler
+// keeps the MFMA accumulators in ordinary VGPRs (with the four-wave shapes it
+// would otherwise place them in AGPRs and copy all 16 back per block before
+// the epilogue).
 template <int KP, int C, int WAVES, bool GEN>
-__global__ __launch_bounds__(WAVES * 64) void cell_scan_fp32_kernel(CellScanArgs a) {
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void cell_scan_fp32_kernel(
+    CellScanArgs a) {
   __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS];
   __shared__ float red[WAVES * 64];
   const int64_t cell = blockIdx.x / a.wg_per_cell;
@@ -425,6 +430,15 @@ struct Bf16Pack {
 __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
+}
+
+// Accumulators of one column block of a 32-node block (BF16x3 operands).
+template <int KQ>
+__device__ __forceinline__ f32x16 scan_block_bf16(const bf16x8 (&A)[KQ], const bf16x8 (&ub)[KQ]) {
+  f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[q], ub[q], acc, 0, 0, 0);
+  return acc;
 }
 
 // One work item of the BF16x3 scan; lds holds WAVES*64 * KT/8 bf16x8.
@@ -521,11 +535,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
       const int blk16 = (int)((base >> 5) + nb) << 4;
 #pragma unroll
       for (int cb = 0; cb < C; ++cb) {
-        f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                      0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int q = 0; q < KQ; ++q)
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[q], ub[cb][q], acc, 0, 0, 0);
+        const f32x16 acc = scan_block_bf16<KQ>(A, ub[cb]);
         epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
       }
     }
@@ -534,7 +544,8 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
 }
 
 template <int KQ, int C, int WAVES, bool GEN>
-__global__ __launch_bounds__(WAVES * 64) void cell_scan_bf16x3_kernel(CellScanArgs a) {
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void cell_scan_bf16x3_kernel(
+    CellScanArgs a) {
   __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
   __shared__ float red[WAVES * 64];
   const int64_t cell = blockIdx.x / a.wg_per_cell;
