@@ -655,6 +655,15 @@ def main():
             "algorithmic_bytes": float(n * d * 4 + rays * 9 + (rays * d * 4 if args.dirs == "input" else 0)),
             "scan_ms": scan_ms,
             "scan_timing": "HIP events around each scan launch on its stream, 3 eager steps after the replays",
+            "node_order": "scan (Morton order, exact block skipping)" if d <= 10 else "index",
+            "evaluated_pair_fraction": st["scan_pairs"] / (float(n) * rays),
+            "executed": (3.0 if args.precision == "bf16x3" else 1.0) * 2.0 * d * st["scan_pairs"] / (scan_ms / 1e3)
+                        / 1e12,
+            "executed_frac": (3.0 if args.precision == "bf16x3" else 1.0) * 2.0 * d * st["scan_pairs"]
+                             / (scan_ms / 1e3) / peak,
+            "note": "achieved/frac count the dense scan's 2 d N (N R + N) flops; the scan in scan order "
+                    "evaluates only the ray-node pairs it cannot rule out (evaluated_pair_fraction), so "
+                    "frac can exceed 1; executed/executed_frac are the MFMA flops actually run",
         },
         "measured_peaks_tflops": {k: v / 1e12 for k, v in peaks.items()},
     }
@@ -667,6 +676,8 @@ def main():
         out["bf16x3"] = {
             "ms_per_step": ms_b, "rays_per_s": rays / (ms_b / 1e3), "speedup_vs_fp32": ms_step / ms_b,
             "scan_ms": scan_b, "flagged_rays_per_step": sb["flagged"],
+            "evaluated_pair_fraction": sb["scan_pairs"] / (float(n) * rays),
+            "executed_frac_bf16_peak": 3.0 * 2.0 * d * sb["scan_pairs"] / (scan_b / 1e3) / BF16_MFMA_PEAK,
             "roofline_frac_bf16_peak": 3.0 * flops / (scan_b / 1e3) / BF16_MFMA_PEAK,
             "roofline_frac_measured_bf16_peak": 3.0 * flops / (scan_b / 1e3) / peaks["bf16_mfma"],
             "fp32_equivalent_tflops": flops / (scan_b / 1e3) / 1e12,

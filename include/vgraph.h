@@ -67,6 +67,12 @@ typedef enum vg_status {
 #define VG_INIT_HEURISTIC (1u << 4) /* with VG_INCIRCLE on general rays: start
                                     from InitialHeuristic (|eta| >= 2)         */
 #define VG_PERIODIC (1u << 5)    /* vg_explore: the periodic diagram (torus)    */
+#define VG_SCAN_ORDER (1u << 6)  /* Monte-Carlo scan over the nodes sorted along
+                                    a Morton curve, skipping node blocks that
+                                    cannot change a ray's two best candidates
+                                    (default for d <= 10)                      */
+#define VG_INDEX_ORDER (1u << 7) /* Monte-Carlo scan over every node in index
+                                    order (default for d > 10)                 */
 
 /* per-ray status bits (uint8) */
 #define VG_ST_NEAR_TIE 1  /* FP32 gap of the two best candidates below VG_TIE_EPS */
@@ -94,6 +100,10 @@ typedef struct vg_stats {
   int64_t bad_input_rays; /* rays of the last call answered NaN / -1 because of
                              non-finite input (VG_ST_BAD_INPUT)              */
   int64_t bad_node_values; /* non-finite node coordinates the last call saw   */
+  int64_t scan_pairs;    /* ray-node pairs the last Monte-Carlo cell scan
+                            evaluated on MFMA (1024 per 32x32 block; blocks
+                            that provably cannot change a ray's two best
+                            candidates are skipped; 0 for other calls)       */
 } vg_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -172,8 +182,19 @@ int vg_raycast_f64(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
  * nodes, which also gives the first candidate; results are the same (the
  * certificate and the FP64 recheck are shared), and vg_stats.nn_calls and
  * nn_grid_calls count the queries.
+ * Node order of the dense scan: with VG_SCAN_ORDER (the default for
+ * d <= 10) the call first sorts a copy of the nodes along a Morton curve of
+ * their first min(3, d) coordinates (a pass of plain kernels, O(n log^2 n));
+ * each cell then scans from its own place in that order outwards and skips a
+ * 32-node block, or a whole chunk of nodes, when a rigorous bound on |u.r~|
+ * over it is below every ray's current second-best value.  The skip is
+ * exact: every output equals the one of the scan over all nodes in index
+ * order (VG_INDEX_ORDER, the default for d > 10, where uniform clouds leave
+ * little to skip); vg_stats.scan_pairs counts the ray-node pairs evaluated.
+ * Neighbour-restricted scans (vg_mc_volume_area_nbr) keep their list order.
  *   dirs [n_nodes][rays_per_cell][d] f32 unit vectors
- *   flags VG_PREC_BF16X3, VG_NO_RECHECK, VG_INCIRCLE
+ *   flags VG_PREC_BF16X3, VG_NO_RECHECK, VG_INCIRCLE, VG_SCAN_ORDER,
+ *         VG_INDEX_ORDER (not both)
  * Outputs [n_nodes * rays_per_cell], cell-major: t_out, idx_out, status_out
  * (may be NULL).  1 <= rays_per_cell <= 4096. */
 int vg_raycast_cells(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
@@ -210,7 +231,8 @@ int vg_dump_dirs(vg_ctx *ctx, int d, int64_t first_cell, int64_t n_cells, int ra
  * array of the library (about 36 MiB per device, held from library load
  * until the process ends).  No call allocates or frees device memory.
  * n_nodes * rays_per_cell <= VG_NOALLOC_MAX_RAYS, else VG_EINVAL; VG_INCIRCLE
- * is VG_EUNSUPPORTED; other arguments, flags and outputs as
+ * and VG_SCAN_ORDER are VG_EUNSUPPORTED (the scan runs in index order, with
+ * the same outputs); other arguments, flags and outputs as
  * vg_raycast_cells.  Every call on one device shares that array and the
  * array keeps the last call's contents (each call clears its counters
  * first): calls that overlap on one device (other streams, other contexts

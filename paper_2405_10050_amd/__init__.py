@@ -40,6 +40,8 @@ VG_NO_RECHECK = 1 << 2
 VG_INCIRCLE = 1 << 3
 VG_INIT_HEURISTIC = 1 << 4
 VG_PERIODIC = 1 << 5
+VG_SCAN_ORDER = 1 << 6
+VG_INDEX_ORDER = 1 << 7
 
 ST_NEAR_TIE = 1
 ST_RECHECKED = 2
@@ -61,7 +63,8 @@ class _Stats(ctypes.Structure):
                 ("fp64_ties", ctypes.c_int64), ("tie_eps", ctypes.c_double),
                 ("scan_launches", ctypes.c_int64), ("scan_ms", ctypes.c_double),
                 ("nn_calls", ctypes.c_int64), ("nn_grid_calls", ctypes.c_int64),
-                ("bad_input_rays", ctypes.c_int64), ("bad_node_values", ctypes.c_int64)]
+                ("bad_input_rays", ctypes.c_int64), ("bad_node_values", ctypes.c_int64),
+                ("scan_pairs", ctypes.c_int64)]
 
 
 class _CellsProblem(ctypes.Structure):
@@ -184,7 +187,7 @@ def stats(device=None) -> dict:
     return dict(rays=s.rays, flagged=s.flagged, fp64_ties=s.fp64_ties, tie_eps=s.tie_eps,
                 scan_launches=s.scan_launches, scan_ms=s.scan_ms, nn_calls=s.nn_calls,
                 nn_grid_calls=s.nn_grid_calls, bad_input_rays=s.bad_input_rays,
-                bad_node_values=s.bad_node_values)
+                bad_node_values=s.bad_node_values, scan_pairs=s.scan_pairs)
 
 
 def peak_rates(device=None) -> dict:
@@ -248,11 +251,14 @@ def raycast(nodes, origin, direction, gen, excl=None, clip=True, recheck=True, i
     return t, idx, st
 
 
-def _cells_flags(precision: str, recheck: bool, incircle: bool = False) -> int:
+def _cells_flags(precision: str, recheck: bool, incircle: bool = False, order=None) -> int:
     if precision not in ("fp32", "bf16x3"):
         raise ValueError("precision must be 'fp32' or 'bf16x3'")
+    if order not in (None, "scan", "index"):
+        raise ValueError("order must be None, 'scan' or 'index'")
     return ((VG_PREC_BF16X3 if precision == "bf16x3" else 0) | (0 if recheck else VG_NO_RECHECK) |
-            (VG_INCIRCLE if incircle else 0))
+            (VG_INCIRCLE if incircle else 0) | (VG_SCAN_ORDER if order == "scan" else 0) |
+            (VG_INDEX_ORDER if order == "index" else 0))
 
 
 def _rays_per_cell(dirs, n, d, dev, seed, rays_per_cell):
@@ -269,10 +275,12 @@ def _rays_per_cell(dirs, n, d, dev, seed, rays_per_cell):
 
 
 def raycast_cells(nodes, dirs=None, precision="fp32", recheck=True, incircle=False, seed=None,
-                  rays_per_cell=None):
+                  rays_per_cell=None, order=None):
     """Monte-Carlo rays of every cell: ``dirs`` is ``[N, R, d]``, or None with
     ``seed`` and ``rays_per_cell``: the directions are then drawn on the
-    device (Philox4x32-10, see :func:`dump_dirs`) and never stored.  Returns
+    device (Philox4x32-10, see :func:`dump_dirs`) and never stored.
+    ``order`` = "scan" / "index" forces the node order of the dense scan
+    (default: scan order, with exact block skipping, for d <= 10).  Returns
     ``(t, idx, status)`` shaped ``[N, R]``."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device
@@ -282,7 +290,7 @@ def raycast_cells(nodes, dirs=None, precision="fp32", recheck=True, incircle=Fal
     idx = torch.empty((n, R), dtype=torch.int32, device=dev)
     st = torch.empty((n, R), dtype=torch.uint8, device=dev)
     c = _ctx(dev)
-    flags = _cells_flags(precision, recheck, incircle)
+    flags = _cells_flags(precision, recheck, incircle, order)
     if dirs is None:
         _check(_lib.vg_raycast_cells_seeded(c, d, n, _ptr(nodes), R, int(seed) & (2 ** 64 - 1), flags,
                                             _ptr(t), _ptr(idx), _ptr(st)), c, "vg_raycast_cells_seeded")
@@ -356,7 +364,7 @@ class MCResult:
 
 
 def mc_volume_area(nodes, dirs=None, precision="fp32", facets=True, recheck=True, out=None,
-                   neighbors=None, incircle=False, seed=None, rays_per_cell=None) -> MCResult:
+                   neighbors=None, incircle=False, seed=None, rays_per_cell=None, order=None) -> MCResult:
     """Monte-Carlo cell volumes, second moments and interface areas
     (Sec. 3.1, Algorithm 3 with f = 1).  ``out`` may pass a previous
     ``MCResult`` of the same shape to reuse its buffers.  ``neighbors`` =
@@ -386,14 +394,14 @@ def mc_volume_area(nodes, dirs=None, precision="fp32", facets=True, recheck=True
         if neighbors is not None:
             raise ValueError("neighbour lists need dirs")
         _check(_lib.vg_mc_volume_area_seeded(c, d, n, _ptr(nodes), R, int(seed) & (2 ** 64 - 1),
-                                             _cells_flags(precision, recheck, incircle),
+                                             _cells_flags(precision, recheck, incircle, order),
                                              _ptr(out.t), _ptr(out.idx), _ptr(out.status), _ptr(out.volume),
                                              _ptr(out.energy2), _ptr(out.facet_j), _ptr(out.facet_area),
                                              _ptr(out.facet_count)), c, "vg_mc_volume_area_seeded")
         return out
     if neighbors is None:
         _check(_lib.vg_mc_volume_area(c, d, n, _ptr(nodes), R, _ptr(dirs),
-                                      _cells_flags(precision, recheck, incircle),
+                                      _cells_flags(precision, recheck, incircle, order),
                                       _ptr(out.t), _ptr(out.idx), _ptr(out.status), _ptr(out.volume),
                                       _ptr(out.energy2), _ptr(out.facet_j), _ptr(out.facet_area),
                                       _ptr(out.facet_count)), c, "vg_mc_volume_area")
@@ -404,7 +412,7 @@ def mc_volume_area(nodes, dirs=None, precision="fp32", facets=True, recheck=True
     if off.shape != (n + 1,) or nbr.dim() != 1:
         raise ValueError("neighbors must be (offsets [N+1], nbr [nnz])")
     _check(_lib.vg_mc_volume_area_nbr(c, d, n, _ptr(nodes), _ptr(off), _ptr(nbr), R, _ptr(dirs),
-                                      _cells_flags(precision, recheck, incircle), _ptr(out.t), _ptr(out.idx),
+                                      _cells_flags(precision, recheck, incircle, order), _ptr(out.t), _ptr(out.idx),
                                       _ptr(out.status), _ptr(out.volume), _ptr(out.energy2),
                                       _ptr(out.facet_j), _ptr(out.facet_area), _ptr(out.facet_count)),
            c, "vg_mc_volume_area_nbr")
@@ -603,7 +611,7 @@ class VoronoiMC(torch.autograd.Function):
         return grad, None, None, None, None
 
 
-def raycast_cells_batched(problems, precision="fp32", out=None):
+def raycast_cells_batched(problems, precision="fp32", out=None, order=None):
     """Uneven batch in persistent launches (one per register class of d,
     captured into one graph): ``problems`` is
     a list of ``(nodes [N_c, d_c], dirs [N_c, R_c, d_c])``.  Returns a list of
@@ -635,7 +643,7 @@ def raycast_cells_batched(problems, precision="fp32", out=None):
     if not problems:
         return outs
     c = _ctx(dev)
-    _check(_lib.vg_raycast_cells_batched(c, len(problems), probs, _cells_flags(precision, True)),
+    _check(_lib.vg_raycast_cells_batched(c, len(problems), probs, _cells_flags(precision, True, order=order)),
            c, "vg_raycast_cells_batched")
     return outs
 

@@ -133,6 +133,13 @@ int run_cells_in(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const
   a.dirs = dirs;
   a.seed = seed;
   a.R = R;
+  if (sc.xs && !nbr && !incircle) {
+    VG_HIP(ctx, launch_node_order(nodes, n, d, sc.order_keys, sc.perm, sc.rank, sc.xs, sc.aabb, ctx->stream));
+    a.xs = sc.xs;
+    a.perm = sc.perm;
+    a.rank = sc.rank;
+    a.aabb = sc.aabb;
+  }
   a.t_out = t_out;
   a.idx_out = idx_out;
   a.st_out = st;
@@ -207,11 +214,25 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
                 "VG_INCIRCLE needs d <= 6, FP32, no neighbour lists and directions as input");
   const size_t grid_bytes = incircle ? incircle_scratch_bytes(n, d, R) : 0;
   const size_t parts_bytes = recheck ? recheck_cells_reserve(m, n) : 0;
-  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes, parts_bytes});
+  if ((flags & VG_SCAN_ORDER) && (flags & VG_INDEX_ORDER))
+    return fail(ctx, VG_EINVAL, "VG_SCAN_ORDER and VG_INDEX_ORDER exclude each other");
+  const bool ordered = !incircle && !nbr && scan_order(d, flags);
+  const int64_t n_keys = ordered ? node_order_keys(n) : 0;
+  size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes, parts_bytes,
+                              (size_t)n_keys * 8, ordered ? (size_t)n * 4 : 0, ordered ? (size_t)n * 4 : 0,
+                              ordered ? (size_t)(n * d) * 4 : 0,
+                              ordered ? (size_t)((n + kOrderGroup - 1) / kOrderGroup) * 2 * d * 4 : 0});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
   CellsScratch sc{};
+  if (ordered) {
+    sc.order_keys = cv.take<uint64_t>(n_keys);
+    sc.perm = cv.take<int32_t>(n);
+    sc.rank = cv.take<int32_t>(n);
+    sc.xs = cv.take<float>(n * d);
+    sc.aabb = cv.take<float>((n + kOrderGroup - 1) / kOrderGroup * 2 * d);
+  }
   sc.flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
   sc.status = st_out ? st_out : cv.take<uint8_t>(m);
   sc.grid = incircle ? cv.take<char>(grid_bytes) : nullptr;
@@ -404,6 +425,7 @@ int vg_get_stats(vg_ctx *ctx, vg_stats *out) {
   out->fp64_ties = c[CNT_FP64_TIE];
   out->bad_input_rays = c[CNT_BAD_RAYS];
   out->bad_node_values = c[CNT_BAD_NODES];
+  out->scan_pairs = (int64_t)(((uint64_t)c[CNT_SCAN_BLOCKS] | ((uint64_t)c[CNT_SCAN_BLOCKS + 1] << 32)) * 1024u);
   out->tie_eps = ctx->last_tau;
   for (auto &ev : ctx->scan_events) {
     float ms = 0.f;
@@ -566,6 +588,7 @@ int vg_raycast_cells_noalloc(vg_ctx *ctx, int d, int64_t n_nodes, const float *n
     return fail(ctx, VG_EINVAL, "rays_per_cell=%d outside [1, 4096]", rays_per_cell);
   if (!dirs || !t_out || !idx_out) return fail(ctx, VG_EINVAL, "null array");
   if (flags & VG_INCIRCLE) return fail(ctx, VG_EUNSUPPORTED, "VG_INCIRCLE needs scratch of its own");
+  if (flags & VG_SCAN_ORDER) return fail(ctx, VG_EUNSUPPORTED, "VG_SCAN_ORDER needs scratch of its own");
   const int64_t m = n_nodes * (int64_t)rays_per_cell;
   if (m > VG_NOALLOC_MAX_RAYS)
     return fail(ctx, VG_EINVAL, "n_nodes * rays_per_cell = %lld exceeds VG_NOALLOC_MAX_RAYS = %lld",

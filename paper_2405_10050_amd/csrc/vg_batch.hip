@@ -46,16 +46,17 @@ struct GraphEntry {
   hipGraph_t graph = nullptr;
   void *table = nullptr;       // BatchProblem[np] on the device
   void *flags = nullptr;       // int64 queue
-  void *counters = nullptr;    // CNT_WORDS u32 + u64 item counter
+  void *counters = nullptr;    // CNT_WORDS u32, a u64 item counter at byte 48
   void *status = nullptr;      // status scratch for clouds without status_out
+  void *order = nullptr;       // scan-order buffers of the clouds
   int64_t rays = 0;
   uint64_t last_use = 0;
 };
 
 struct TuneKey {
-  int kp, log2n, R, bf16;
+  int kp, log2n, R, bf16, ord;  // ord: nodes in scan order
   bool operator<(const TuneKey &o) const {
-    return std::tie(kp, log2n, R, bf16) < std::tie(o.kp, o.log2n, o.R, o.bf16);
+    return std::tie(kp, log2n, R, bf16, ord) < std::tie(o.kp, o.log2n, o.R, o.bf16, o.ord);
   }
 };
 
@@ -78,6 +79,7 @@ void free_entry(GraphEntry &g) {
   if (g.flags) (void)hipFree(g.flags);
   if (g.counters) (void)hipFree(g.counters);
   if (g.status) (void)hipFree(g.status);
+  if (g.order) (void)hipFree(g.order);
   g = GraphEntry{};
 }
 
@@ -103,7 +105,7 @@ void load_tune(BatchState &S) {
   TuneKey k;
   int shape;
   double ns;
-  while (std::fscanf(f, "%d %d %d %d %d %lf", &k.kp, &k.log2n, &k.R, &k.bf16, &shape, &ns) == 6) {
+  while (std::fscanf(f, "%d %d %d %d %d %d %lf", &k.kp, &k.log2n, &k.R, &k.bf16, &k.ord, &shape, &ns) == 7) {
     if (shape < 0 || shape >= kNumShapes) continue;
     auto &v = S.tune[k];
     v.resize(kNumShapes, -1.0);
@@ -121,8 +123,8 @@ void save_tune(const BatchState &S) {
   for (auto &kv : S.tune)
     for (int s = 0; s < (int)kv.second.size(); ++s)
       if (kv.second[s] > 0)
-        std::fprintf(f, "%d %d %d %d %d %.6g\n", kv.first.kp, kv.first.log2n, kv.first.R,
-                     kv.first.bf16, s, kv.second[s]);
+        std::fprintf(f, "%d %d %d %d %d %d %.6g\n", kv.first.kp, kv.first.log2n, kv.first.R,
+                     kv.first.bf16, kv.first.ord, s, kv.second[s]);
   std::fclose(f);
   std::rename(tmp.c_str(), path.c_str());
 }
@@ -141,8 +143,8 @@ int shape_rw(int R, int sh) {
   return (rw >= 64 && rw <= 1024) ? rw : 0;
 }
 
-TuneKey tune_key(const vg_cells_problem &p, bool bf16) {
-  return TuneKey{(p.d + 1) / 2, ilog2(p.n_nodes), p.rays_per_cell, bf16 ? 1 : 0};
+TuneKey tune_key(const vg_cells_problem &p, bool bf16, uint32_t flags) {
+  return TuneKey{(p.d + 1) / 2, ilog2(p.n_nodes), p.rays_per_cell, bf16 ? 1 : 0, scan_order(p.d, flags) ? 1 : 0};
 }
 
 // The scan arguments of one cloud of a batch (q: its position in the table).
@@ -166,19 +168,54 @@ CellScanArgs cloud_args(const vg_cells_problem &p, int q, bool bf16, int rw, uin
   return a;
 }
 
-// Device table of a batch (the recheck reads it).
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of the scan-order buffers of one cloud (sort keys, perm, rank, the
+// sorted copy and its boxes), each 256-byte aligned.
+size_t order_bytes(const vg_cells_problem &p) {
+  const int64_t n = p.n_nodes;
+  return align256((size_t)node_order_keys(n) * 8) + 2 * align256((size_t)n * 4) + align256((size_t)(n * p.d) * 4) +
+         align256((size_t)((n + kOrderGroup - 1) / kOrderGroup) * 2 * p.d * 4);
+}
+
+// Points a's scan-order fields into the buffers at base (order_bytes(p) long).
+void carve_order(CellScanArgs &a, const vg_cells_problem &p, char *base, uint64_t *&keys) {
+  const int64_t n = p.n_nodes;
+  keys = reinterpret_cast<uint64_t *>(base);
+  base += align256((size_t)node_order_keys(n) * 8);
+  a.perm = reinterpret_cast<int32_t *>(base);
+  base += align256((size_t)n * 4);
+  a.rank = reinterpret_cast<int32_t *>(base);
+  base += align256((size_t)n * 4);
+  a.xs = reinterpret_cast<float *>(base);
+  base += align256((size_t)(n * p.d) * 4);
+  a.aabb = reinterpret_cast<float *>(base);
+}
+
+// Device table of a batch (the recheck reads it).  Clouds scanned in scan
+// order (scan_order) get their slice of `order` (null: no slices, as for the
+// table that only keys the graph cache).
 std::vector<BatchProblem> make_table(const std::vector<vg_cells_problem> &pr, const std::vector<int> &order,
-                                     const std::vector<int> &rw, bool bf16, uint32_t *counters, int64_t *flags,
-                                     uint8_t *status, int64_t &total_rays) {
+                                     const std::vector<int> &rw, bool bf16, uint32_t flags_in, uint32_t *counters,
+                                     int64_t *flags, uint8_t *status, char *order_base, int64_t &total_rays,
+                                     std::vector<uint64_t *> *keys = nullptr) {
   std::vector<BatchProblem> T(order.size());
   total_rays = 0;
   int64_t status_off = 0;
+  size_t order_off = 0;
+  if (keys) keys->assign(order.size(), nullptr);
   for (size_t q = 0; q < order.size(); ++q) {
     const vg_cells_problem &p = pr[order[q]];
     const int64_t m = p.n_nodes * (int64_t)p.rays_per_cell;
     T[q].a = cloud_args(p, (int)q, bf16, rw[order[q]], counters, flags,
                         (!p.status_out && status) ? status + status_off : nullptr);
     if (!p.status_out) status_off += m;
+    if (order_base && scan_order(p.d, flags_in)) {
+      uint64_t *k = nullptr;
+      carve_order(T[q].a, p, order_base + order_off, k);
+      if (keys) (*keys)[q] = k;
+      order_off += order_bytes(p);
+    }
     T[q].item_begin = 0;
     total_rays += m;
   }
@@ -240,12 +277,13 @@ int ensure_branches(vg_ctx *ctx) {
 }
 
 // Device buffers of one batch: problem table, FP64 recheck queue, counters
-// (CNT_WORDS u32, then from byte 32 a u64 item counter), status scratch.
+// (CNT_WORDS u32, then at byte 48 a u64 item counter), status scratch.
 struct BatchBuffers {
   void *table;
   int64_t *flags;
   uint32_t *counters;
   uint8_t *status;
+  char *order;  // scan-order buffers of the clouds that use them, or null
 };
 // Runs the launches of one batch.  The first call with a given key allocates
 // the buffers, fills and uploads the table, and captures the launches into a
@@ -253,7 +291,7 @@ struct BatchBuffers {
 // that graph on the context's stream (at most 8 graphs are kept, least
 // recently used first out).  With VG_NO_GRAPH set, the launches run directly
 // and the buffers are freed after a stream synchronisation.
-int run_batch(vg_ctx *ctx, uint64_t key, int64_t rays, bool need_status, size_t table_bytes,
+int run_batch(vg_ctx *ctx, uint64_t key, int64_t rays, bool need_status, size_t table_bytes, size_t order_total,
               const std::function<void(const BatchBuffers &, std::vector<char> &)> &fill,
               const std::function<hipError_t(const BatchBuffers &, hipStream_t)> &enqueue,
               float tau) {
@@ -269,12 +307,13 @@ int run_batch(vg_ctx *ctx, uint64_t key, int64_t rays, bool need_status, size_t 
     if (hipMalloc(&ne.flags, (size_t)std::max<int64_t>(rays, 1) * 8) != hipSuccess ||
         hipMalloc(&ne.counters, 64) != hipSuccess ||
         (need_status && hipMalloc(&ne.status, (size_t)std::max<int64_t>(rays, 1)) != hipSuccess) ||
+        (order_total && hipMalloc(&ne.order, order_total) != hipSuccess) ||
         hipMalloc(&ne.table, table_bytes) != hipSuccess) {
       free_entry(ne);
       return err(ctx, VG_ENOMEM, "batch buffers allocation failed");
     }
     const BatchBuffers b{ne.table, static_cast<int64_t *>(ne.flags), static_cast<uint32_t *>(ne.counters),
-                         static_cast<uint8_t *>(ne.status)};
+                         static_cast<uint8_t *>(ne.status), static_cast<char *>(ne.order)};
     std::vector<char> bytes;
     fill(b, bytes);
     if (bytes.size() != table_bytes ||
@@ -334,17 +373,17 @@ int run_batch(vg_ctx *ctx, uint64_t key, int64_t rays, bool need_status, size_t 
 
 // Time every shape on a probe of each bucket missing from the cache, then
 // set rw[i], the rays per workgroup of cloud i, to its bucket's fastest.
-int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16, std::vector<int> &rw) {
+int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16, uint32_t call_flags, std::vector<int> &rw) {
   BatchState &S = state(ctx);
   if (!S.tune_loaded || S.tune_file != tune_path()) {
     S.tune.clear();
     load_tune(S);
   }
   std::map<TuneKey, std::vector<int>> buckets;
-  for (int i = 0; i < (int)pr.size(); ++i) buckets[tune_key(pr[i], bf16)].push_back(i);
+  for (int i = 0; i < (int)pr.size(); ++i) buckets[tune_key(pr[i], bf16, call_flags)].push_back(i);
   bool changed = false;
-  void *counters = nullptr, *flags = nullptr;
-  size_t flags_bytes = 0;
+  void *counters = nullptr, *flags = nullptr, *ordbuf = nullptr;
+  size_t flags_bytes = 0, ord_bytes = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = VG_OK;
   for (auto &b : buckets) {
@@ -382,11 +421,37 @@ int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16, std::v
       rc = err(ctx, VG_EINVAL, "tuning needs status outputs");
       break;
     }
+    // the probe cloud in scan order when its bucket runs that way
+    uint64_t *okeys = nullptr;
+    CellScanArgs oa{};
+    if (b.first.ord) {
+      const size_t need_o = order_bytes(p);
+      if (need_o > ord_bytes) {
+        if (ordbuf) (void)hipFree(ordbuf);
+        ordbuf = nullptr;
+        if (hipMalloc(&ordbuf, need_o) != hipSuccess) {
+          rc = err(ctx, VG_ENOMEM, "tuner order allocation failed");
+          break;
+        }
+        ord_bytes = need_o;
+      }
+      carve_order(oa, p, static_cast<char *>(ordbuf), okeys);
+      if (launch_node_order(p.nodes, p.n_nodes, p.d, okeys, const_cast<int32_t *>(oa.perm),
+                            const_cast<int32_t *>(oa.rank), const_cast<float *>(oa.xs), const_cast<float *>(oa.aabb),
+                            ctx->stream) != hipSuccess) {
+        rc = err(ctx, VG_EDEVICE, "tuner order launch failed");
+        break;
+      }
+    }
     std::vector<double> ns(kNumShapes, -2.0);  // -2: shape not available for this R
     for (int sh = 0; sh < kNumShapes && rc == VG_OK; ++sh) {
       const int r = shape_rw(p.rays_per_cell, sh);
       if (!r) continue;
-      const CellScanArgs a = cloud_args(p, 0, bf16, r, (uint32_t *)counters, (int64_t *)flags, nullptr);
+      CellScanArgs a = cloud_args(p, 0, bf16, r, (uint32_t *)counters, (int64_t *)flags, nullptr);
+      a.xs = oa.xs;
+      a.perm = oa.perm;
+      a.rank = oa.rank;
+      a.aabb = oa.aabb;
       // warm-up, then the timed probe
       if (fill_u32((uint32_t *)counters, 0u, 16, ctx->stream) != hipSuccess ||
           launch_cell_scan_rw(a, bf16, r, std::min<int64_t>(cells, 256), ctx->stream) != hipSuccess ||
@@ -409,10 +474,11 @@ int tune(vg_ctx *ctx, const std::vector<vg_cells_problem> &pr, bool bf16, std::v
   if (e1) (void)hipEventDestroy(e1);
   if (counters) (void)hipFree(counters);
   if (flags) (void)hipFree(flags);
+  if (ordbuf) (void)hipFree(ordbuf);
   if (rc) return rc;
   if (changed) save_tune(S);
   for (int i = 0; i < (int)pr.size(); ++i) {
-    const auto &v = S.tune[tune_key(pr[i], bf16)];
+    const auto &v = S.tune[tune_key(pr[i], bf16, call_flags)];
     int best = 1;
     for (int sh = 0; sh < kNumShapes; ++sh)
       if (v[sh] > 0 && shape_rw(pr[i].rays_per_cell, sh) && v[sh] < v[best]) best = sh;
@@ -433,6 +499,8 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
   if (hipSetDevice(ctx->device) != hipSuccess) return err(ctx, VG_EDEVICE, "hipSetDevice failed");
   const bool bf16 = (flags & VG_PREC_BF16X3) != 0;
   if (flags & VG_NO_RECHECK) return err(ctx, VG_EUNSUPPORTED, "batched calls always recheck");
+  if ((flags & VG_SCAN_ORDER) && (flags & VG_INDEX_ORDER))
+    return err(ctx, VG_EINVAL, "VG_SCAN_ORDER and VG_INDEX_ORDER exclude each other");
   std::vector<vg_cells_problem> pr(probs, probs + n_problems);
   for (int i = 0; i < n_problems; ++i) {
     const vg_cells_problem &p = pr[i];
@@ -466,7 +534,7 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
     bool have_status = true;
     for (auto &p : pr) have_status &= p.status_out != nullptr;
     if (have_status) {
-      rc = tune(ctx, pr, bf16, rw);
+      rc = tune(ctx, pr, bf16, flags, rw);
       if (rc) return rc;
     }
   }
@@ -482,27 +550,41 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
   }
   // key: everything the launches depend on
   int64_t rays0;
-  std::vector<BatchProblem> probe = make_table(pr, order, rw, bf16, nullptr, nullptr, nullptr, rays0);
+  std::vector<BatchProblem> probe =
+      make_table(pr, order, rw, bf16, flags, nullptr, nullptr, nullptr, nullptr, rays0);
   uint64_t key = fnv(probe.data(), probe.size() * sizeof(BatchProblem));
   key = fnv(&flags, sizeof flags, key);
   bool need_status = false;
   for (auto &p : pr) need_status |= p.status_out == nullptr;
+  size_t order_total = 0;
+  for (auto &p : pr)
+    if (scan_order(p.d, flags)) order_total += order_bytes(p);
   BatchState &S = state(ctx);
   auto fill = [&](const BatchBuffers &b, std::vector<char> &bytes) {
     int64_t rays;
-    std::vector<BatchProblem> T = make_table(pr, order, rw, bf16, b.counters, b.flags, b.status, rays);
+    std::vector<BatchProblem> T =
+        make_table(pr, order, rw, bf16, flags, b.counters, b.flags, b.status, b.order, rays);
     bytes.assign(reinterpret_cast<const char *>(T.data()), reinterpret_cast<const char *>(T.data() + T.size()));
   };
   auto enqueue = [&](const BatchBuffers &b, hipStream_t s) -> hipError_t {
     int64_t rays;
-    const std::vector<BatchProblem> T = make_table(pr, order, rw, bf16, b.counters, b.flags, b.status, rays);
+    std::vector<uint64_t *> keys;
+    const std::vector<BatchProblem> T =
+        make_table(pr, order, rw, bf16, flags, b.counters, b.flags, b.status, b.order, rays, &keys);
     const int rgrid = (int)std::min<int64_t>((rays0 + 3) / 4, 2048);
     hipError_t e = fill_u32(b.counters, 0u, 16, s);
     // fork
     if (e == hipSuccess) e = hipEventRecord(S.fork, s);
     for (int k = 0; k < kBranches && e == hipSuccess; ++k) e = hipStreamWaitEvent(S.branch[k], S.fork, 0);
-    for (size_t q = 0; q < T.size() && e == hipSuccess; ++q)
-      e = launch_cell_scan_rw(T[q].a, bf16, rw[order[q]], T[q].a.n, S.branch[branch_of[q]]);
+    for (size_t q = 0; q < T.size() && e == hipSuccess; ++q) {
+      const CellScanArgs &a = T[q].a;
+      hipStream_t bs = S.branch[branch_of[q]];
+      if (a.xs)
+        e = launch_node_order(a.nodes, a.n, a.d, keys[q], const_cast<int32_t *>(a.perm),
+                              const_cast<int32_t *>(a.rank), const_cast<float *>(a.xs), const_cast<float *>(a.aabb),
+                              bs);
+      if (e == hipSuccess) e = launch_cell_scan_rw(a, bf16, rw[order[q]], a.n, bs);
+    }
     // join
     for (int k = 0; k < kBranches && e == hipSuccess; ++k) {
       e = hipEventRecord(S.join[k], S.branch[k]);
@@ -513,7 +595,7 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
                                  std::max(rgrid, 1), s);
     return e;
   };
-  return run_batch(ctx, key, rays0, need_status, probe.size() * sizeof(BatchProblem), fill, enqueue,
+  return run_batch(ctx, key, rays0, need_status, probe.size() * sizeof(BatchProblem), order_total, fill, enqueue,
                    bf16 ? kTauCellsBf16 : kTauCellsFp32);
 }
 
@@ -621,7 +703,7 @@ extern "C" int vg_raycast_batched(vg_ctx *ctx, int n_problems, const vg_rays_pro
   };
   auto enqueue = [&](const BatchBuffers &b, hipStream_t s) -> hipError_t {
     const int rgrid = (int)std::min<int64_t>((rays0 + 3) / 4, 2048);
-    unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)b.counters + 32);
+    unsigned long long *next = reinterpret_cast<unsigned long long *>((char *)b.counters + 48);
     hipError_t e = fill_u32(b.counters, 0u, 16, s);
     if (e == hipSuccess)
       e = launch_ray_scan_batched((const RayBatchProblem *)b.table, np, items0, next, grid, s);
@@ -630,6 +712,6 @@ extern "C" int vg_raycast_batched(vg_ctx *ctx, int n_problems, const vg_rays_pro
                                       b.counters + CNT_FP64_TIE, std::max(rgrid, 1), s);
     return e;
   };
-  return run_batch(ctx, key, rays0, need_status, probe.size() * sizeof(RayBatchProblem), fill,
+  return run_batch(ctx, key, rays0, need_status, probe.size() * sizeof(RayBatchProblem), 0, fill,
                    enqueue, kTauRays);
 }

@@ -155,6 +155,181 @@ __device__ __forceinline__ int64_t row_node(const CellScanArgs &a, int64_t nb0, 
   return (j >= 0 && j < a.n) ? j : a.n;
 }
 
+// Chunks of the scan in visiting order: with the nodes in scan order
+// (a.xs), the chunk that holds the cell's own node first, then alternately
+// the next chunk above and below it; else 0, 1, 2, ...
+struct ChunkWalk {
+  int lo, hi, nch;
+  bool up;
+  __device__ ChunkWalk(int first, int count) : lo(first - 1), hi(first + 1), nch(count), up(true) {}
+  // the chunk after the current one, or -1
+  __device__ int next() {
+    if (lo < 0 && hi >= nch) return -1;
+    const bool take_hi = (up && hi < nch) || lo < 0;
+    up = !up;
+    return take_hi ? hi++ : lo--;
+  }
+};
+
+// Upper bound on |u . r~| as any of the scans computes it, over the 32
+// nodes of the caller's 32-lane block (|u| = 1 up to rounding, so
+// |u . r~| <= |r~|; the factor 1 + 2^-12 covers the rounding of |r~|, of |u|
+// and of the FP32 or split-BF16 dot product).  Stored by the block's first
+// lane into bnd[block].
+template <int DK>
+__device__ __forceinline__ void block_bound(const float (&rt)[DK], float *bnd, int tid) {
+  float m2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) m2 = __builtin_fmaf(rt[k], rt[k], m2);
+  float b = __builtin_sqrtf(m2) * (1.f + 0x1p-12f);
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) b = fmaxf(b, __shfl_xor(b, off));
+  if ((tid & 31) == 0) bnd[tid >> 5] = b;
+}
+
+// Largest value over the wave's 64 lanes (uniform).
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Adds the wave's count of evaluated 32x32 blocks to the call's counter.
+__device__ __forceinline__ void count_blocks(const CellScanArgs &a, int blocks, int lane) {
+  if (a.counters && lane == 0 && blocks)
+    atomicAdd(reinterpret_cast<unsigned long long *>(a.counters + CNT_SCAN_BLOCKS), (unsigned long long)blocks);
+}
+
+// Smallest second-best value over the wave's 64 lanes (uniform).
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Largest second-best value a ray holds: each lane keeps the top two of its
+// half of the 32 node rows, the lane l ^ 32 those of the other half.
+__device__ __forceinline__ float merged_second(float b, float s) {
+  const float ob = __shfl_xor(b, 32), os = __shfl_xor(s, 32);
+  return fmaxf(fmaxf(s, os), fminf(b, ob));
+}
+
+// Upper bound on |u . r~| over the nodes of scan-order chunk c (NB nodes, the
+// 128-node boxes of the order pass): 1 / (distance from x_i to the boxes),
+// with a factor 1 + 2^-10 above the block bounds' 1 + 2^-12, so the chunk
+// that holds x_i's nearest node never falls below a bound taken from values
+// of that chunk.  Uniform over the wave.
+template <int NB, int DK>
+__device__ __forceinline__ float chunk_bound(const CellScanArgs &a, const float (&xi)[DK], int c, int lane) {
+  constexpr int GPC = NB / kOrderGroup;
+  const int d = a.d;
+  const int64_t g = (int64_t)c * GPC + lane;
+  float b = 0.f;
+  if (lane < GPC && g * kOrderGroup < a.n) {
+    const float *box = a.aabb + g * 2 * d;
+    float s2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < DK; ++k) {
+      if (k < d) {
+        const float gap = fmaxf(fmaxf(box[k] - xi[k], xi[k] - box[d + k]), 0.f);
+        s2 = __builtin_fmaf(gap, gap, s2);
+      }
+    }
+    b = s2 > 0.f ? __builtin_amdgcn_rsqf(s2) * (1.f + 0x1p-10f) : __builtin_inff();
+  }
+  return wave_max(b);
+}
+
+// The loop over the chunks of NB nodes shared by the FP32 and BF16x3 scans.
+// stage(rt) stores the calling thread's inverted node into the LDS tile;
+// block(nb, blk16, skip) runs the column blocks cb of node block nb for
+// which skip(cb) is false and returns how many it ran.  Returns the number of
+// 32x32 blocks the wave evaluated.
+//
+// Index order (!SORTED, also the candidate lists): every chunk, every block.
+// Scan order (SORTED): the cell's own chunk first, then outwards (ChunkWalk);
+// a node block is skipped for column block cb when its bound is below the
+// smallest merged second best of cb's 32 rays (none of its values can enter
+// a ray's top two: they are at most that second best, and an equal value
+// would only make a tie the certificate flags anyway); a whole chunk is not
+// even loaded when its box bound is below the smallest such value over the
+// workgroup, taken two chunks earlier from wsm (the slot of the same parity,
+// written after that chunk's second barrier, read before this chunk's first).
+template <int DK, int C, int NB, int WAVES, bool SORTED, class Stage, class Block>
+__device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, const float (&xi)[DK],
+                                           const float (&best)[C], const float (&second)[C], float &nn2,
+                                           float *bnd, float *wsm, int64_t nb0, int64_t n_scan, int rayw,
+                                           Stage &&stage, Block &&block) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int d = a.d;
+  const int64_t n = a.n;
+  int blocks = 0;
+  float pre[DK];
+  if constexpr (!SORTED) {
+    // the coordinates of the next chunk's node are loaded one chunk ahead, so
+    // their latency hides behind the MFMA loop of the current chunk
+    load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, tid), pre);
+    for (int64_t base = 0; base < n_scan; base += NB) {
+      float rt[DK];
+      nn2 = fminf(nn2, invert_node<DK>(pre, xi, row_node(a, nb0, n_scan, base + tid), n, cell, rt));
+      load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, base + NB + tid), pre);
+      __syncthreads();  // the previous chunk is consumed
+      stage(rt);
+      __syncthreads();
+      const int64_t rem = n_scan - base;
+      const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
+      for (int nb = 0; nb < nblocks; ++nb)
+        blocks += block(nb, (int)((base >> 5) + nb) << 4, [](int) { return false; });
+    }
+  } else {
+    const int64_t self = a.rank[cell];
+    const int c0 = (int)(self / NB);
+    ChunkWalk walk(c0, (int)((n + NB - 1) / NB));
+    int64_t base = (int64_t)c0 * NB;
+    float thr = 0.f;
+    load_node<DK>(a.xs, n, d, base + tid, pre);
+    for (int it = 0; base >= 0; ++it) {
+      float rt[DK];
+      nn2 = fminf(nn2, invert_node<DK>(pre, xi, base + tid, n, self, rt));
+      if (it >= 2) {
+        float t = wsm[(it & 1) * WAVES];
+#pragma unroll
+        for (int w = 1; w < WAVES; ++w) t = fminf(t, wsm[(it & 1) * WAVES + w]);
+        thr = t;
+      }
+      int next = walk.next();
+      while (next >= 0 && chunk_bound<NB, DK>(a, xi, next, lane) < thr) next = walk.next();
+      const int64_t nbase = next >= 0 ? (int64_t)next * NB : -1;
+      if (nbase >= 0) load_node<DK>(a.xs, n, d, nbase + tid, pre);
+      __syncthreads();  // the previous chunk is consumed
+      stage(rt);
+      block_bound<DK>(rt, bnd, tid);
+      __syncthreads();
+      float smin[C];
+      float sall = __builtin_inff();
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) {
+        // lanes of padding rays (ray >= R, zero direction) constrain nothing
+        const float ms = merged_second(best[cb], second[cb]);
+        smin[cb] = wave_min(rayw + cb * 32 + (lane & 31) < a.R ? ms : __builtin_inff());
+        sall = fminf(sall, smin[cb]);
+      }
+      if (lane == 0) wsm[(it & 1) * WAVES + wave] = sall;
+      const int64_t rem = n - base;
+      const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
+      if (!(wave_max(lane < nblocks ? bnd[lane] : 0.f) < sall)) {
+        for (int nb = 0; nb < nblocks; ++nb) {
+          const float bb = bnd[nb];
+          if (bb < sall) continue;
+          blocks += block(nb, (int)((base >> 5) + nb) << 4, [&](int cb) { return bb < smin[cb]; });
+        }
+      }
+      base = nbase;
+    }
+  }
+  return blocks;
+}
+
 // Rays [r0, r0 + RW) of `cell` when a node coordinate of the call is not
 // finite (the input check counted it): no answer, t = NaN, idx = -1.  The
 // whole workgroup takes this path or none (the count is read by all).
@@ -245,7 +420,8 @@ __device__ __forceinline__ void cell_finish(const CellScanArgs &a, const float (
     const float thr = fmaxf(a.tau_rel * s1, a.kappa / nn);
     bool tie = !(s1 - s2 > thr);
     float t;
-    const int64_t node = (j >= 0 && j < n_scan) ? row_node(a, nb0, n_scan, j) : a.n;
+    const int64_t node =
+        (j >= 0 && j < n_scan) ? (a.perm ? (int64_t)a.perm[j] : row_node(a, nb0, n_scan, j)) : a.n;
     if (j >= 0 && node >= a.n) {  // cannot happen with the documented MFMA layout; never dereference
       j = -1;
       t = __builtin_nanf("");
@@ -305,15 +481,17 @@ __device__ __forceinline__ f32x16 scan_block(const float (&A)[KP], const float (
 }
 
 // One work item of the FP32 scan: rays [chunk*RW, chunk*RW + RW) of `cell`.
-// lds holds Fp32Tile<KP, WAVES>::FLOATS floats, red WAVES*64 floats.  One
+// lds holds Fp32Tile<KP, WAVES>::FLOATS floats, NB/32 block bounds and
+// 2 x WAVES chunk thresholds, red WAVES*64 floats.  One
 // accumulator set per wave is reused by the column blocks in turn: separate
 // sets would cost the occupancy that hides each block's epilogue.
-template <int KP, int C, int WAVES, bool GEN>
+template <int KP, int C, int WAVES, bool GEN, bool SORTED>
 __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t cell, int chunk,
                                                float *__restrict__ lds, float *red) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = Fp32Tile<KP, WAVES>::NB;  // nodes per LDS chunk (one per thread)
   constexpr int LS = Fp32Tile<KP, WAVES>::LS;
+  constexpr int FLOATS = Fp32Tile<KP, WAVES>::FLOATS;
   constexpr int RW = WAVES * C * 32;           // rays per workgroup
   constexpr int DK = 2 * KP;
 
@@ -345,8 +523,12 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
     } else {
       float u[DK];
       cell_dir<DK>(nullptr, a.seed, cell, R, ray, d, u);
+      // component 2kp or 2kp + 1 by a bit mask (a select between the two
+      // array elements would become a dynamic index and move u to memory)
+      const int hi = (lane & 32) ? -1 : 0;
 #pragma unroll
-      for (int kp = 0; kp < KP; ++kp) ub[cb][kp] = (lane & 32) ? u[2 * kp + 1] : u[2 * kp];
+      for (int kp = 0; kp < KP; ++kp)
+        ub[cb][kp] = __int_as_float((__float_as_int(u[2 * kp]) & ~hi) | (__float_as_int(u[2 * kp + 1]) & hi));
     }
   }
 
@@ -362,37 +544,32 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 
   // A operand: lane l reads row 2kp + l/32, column l%32 of each node block
   const float *lrow = lds + (lane >> 5) * LS + (lane & 31);
-
-  // the coordinates of the next chunk's node are loaded one chunk ahead, so
-  // their latency hides behind the MFMA loop of the current chunk
+  float *bnd = lds + FLOATS;             // NB / 32 block bounds
+  float *wsm = lds + FLOATS + NB / 32;   // 2 x WAVES chunk thresholds
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
-  float pre[DK];
-  load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, tid), pre);
-  for (int64_t base = 0; base < n_scan; base += NB) {
-    float rt[DK];
-    nn2 = fminf(nn2, invert_node<DK>(pre, xi, row_node(a, nb0, n_scan, base + tid), n, cell, rt));
-    load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, base + NB + tid), pre);
-    __syncthreads();  // the previous chunk is consumed
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED>(
+      a, cell, xi, best, second, nn2, bnd, wsm, nb0, n_scan, rayw,
+      [&](const float (&rt)[DK]) {
 #pragma unroll
-    for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
-    __syncthreads();
-    const int64_t rem = n_scan - base;
-    const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
-    const int blk0 = (int)(base >> 5);
-    for (int nb = 0; nb < nblocks; ++nb) {
-      float A[KP];
+        for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
+      },
+      [&](int nb, int blk16, auto skip) {
+        float A[KP];
 #pragma unroll
-      for (int kp = 0; kp < KP; ++kp) A[kp] = lrow[2 * kp * LS + nb * 32];
-      const int blk16 = (blk0 + nb) << 4;
+        for (int kp = 0; kp < KP; ++kp) A[kp] = lrow[2 * kp * LS + nb * 32];
+        int ran = 0;
 #pragma unroll
-      for (int cb = 0; cb < C; ++cb) {
-        const f32x16 acc = scan_block<KP>(A, ub[cb]);
-        epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
-      }
-    }
-  }
+        for (int cb = 0; cb < C; ++cb) {
+          if (skip(cb)) continue;
+          const f32x16 acc = scan_block<KP>(A, ub[cb]);
+          epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
+          ++ran;
+        }
+        return ran;
+      });
 
+  count_blocks(a, blocks, lane);
   cell_finish<C, DK, NT, GEN>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
 }
 
@@ -401,14 +578,16 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 // keeps the MFMA accumulators in ordinary VGPRs (with the four-wave shapes it
 // would otherwise place them in AGPRs and copy all 16 back per block before
 // the epilogue).
-template <int KP, int C, int WAVES, bool GEN>
+// SORTED: the nodes are in scan order (a.xs, a.perm, a.rank, a.aabb).
+template <int KP, int C, int WAVES, bool GEN, bool SORTED>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void cell_scan_fp32_kernel(
     CellScanArgs a) {
-  __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS];
+  // tile, NB / 32 block bounds, 2 x WAVES chunk thresholds
+  __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2];
   __shared__ float red[WAVES * 64];
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
-  scan_fp32_item<KP, C, WAVES, GEN>(a, cell, chunk, lds, red);
+  scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red);
 }
 
 // ---------------------------------------------------------------- BF16x3
@@ -441,10 +620,11 @@ __device__ __forceinline__ f32x16 scan_block_bf16(const bf16x8 (&A)[KQ], const b
   return acc;
 }
 
-// One work item of the BF16x3 scan; lds holds WAVES*64 * KT/8 bf16x8.
-template <int KQ, int C, int WAVES, bool GEN>
+// One work item of the BF16x3 scan; lds holds WAVES*64 * KT/8 bf16x8, bnd
+// the NB/32 block bounds and 2 x WAVES chunk thresholds.
+template <int KQ, int C, int WAVES, bool GEN, bool SORTED>
 __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t cell, int chunk,
-                                                 bf16x8 *__restrict__ lds, float *red) {
+                                                 bf16x8 *__restrict__ lds, float *red, float *bnd) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = NT;
   constexpr int RW = WAVES * C * 32;
@@ -502,78 +682,74 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
 
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
-  float pre[DK];
-  load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, tid), pre);
-  for (int64_t base = 0; base < n_scan; base += NB) {
-    {
-      float rt[DK];
-      nn2 = fminf(nn2, invert_node<DK>(pre, xi, row_node(a, nb0, n_scan, base + tid), n, cell, rt));
-      load_node<DK>(a.nodes, n, d, row_node(a, nb0, n_scan, base + NB + tid), pre);
-      __syncthreads();  // the previous chunk is consumed
-      __bf16 rh[DKP], rl[DKP];
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED>(
+      a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, nb0, n_scan, rayw,
+      [&](const float (&rt)[DK]) {
+        __bf16 rh[DKP], rl[DKP];
 #pragma unroll
-      for (int k = 0; k < DKP; ++k) split_bf16(rt[k], rh[k], rl[k]);
+        for (int k = 0; k < DKP; ++k) split_bf16(rt[k], rh[k], rl[k]);
 #pragma unroll
-      for (int g = 0; g < KT / 8; ++g) {
-        bf16x8 v;
+        for (int g = 0; g < KT / 8; ++g) {
+          bf16x8 v;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int kk = 8 * g + e;
-          v[e] = kk < DKP ? rh[kk % DKP]
-                          : (kk < 2 * DKP ? rh[kk % DKP] : (kk < 3 * DKP ? rl[kk % DKP] : (__bf16)0.f));
+          for (int e = 0; e < 8; ++e) {
+            const int kk = 8 * g + e;
+            v[e] = kk < DKP ? rh[kk % DKP]
+                            : (kk < 2 * DKP ? rh[kk % DKP] : (kk < 3 * DKP ? rl[kk % DKP] : (__bf16)0.f));
+          }
+          lds[tid * (KT / 8) + g] = v;
         }
-        lds[tid * (KT / 8) + g] = v;
-      }
-    }
-    __syncthreads();
-    const int64_t rem = n_scan - base;
-    const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
-    for (int nb = 0; nb < nblocks; ++nb) {
-      bf16x8 A[KQ];
+      },
+      [&](int nb, int blk16, auto skip) {
+        bf16x8 A[KQ];
 #pragma unroll
-      for (int q = 0; q < KQ; ++q) A[q] = lds[(nb * 32 + (lane & 31)) * (KT / 8) + 2 * q + (lane >> 5)];
-      const int blk16 = (int)((base >> 5) + nb) << 4;
+        for (int q = 0; q < KQ; ++q) A[q] = lds[(nb * 32 + (lane & 31)) * (KT / 8) + 2 * q + (lane >> 5)];
+        int ran = 0;
 #pragma unroll
-      for (int cb = 0; cb < C; ++cb) {
-        const f32x16 acc = scan_block_bf16<KQ>(A, ub[cb]);
-        epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
-      }
-    }
-  }
+        for (int cb = 0; cb < C; ++cb) {
+          if (skip(cb)) continue;
+          const f32x16 acc = scan_block_bf16<KQ>(A, ub[cb]);
+          epilogue16(acc, best[cb], second[cb], bidx[cb], blk16);
+          ++ran;
+        }
+        return ran;
+      });
+  count_blocks(a, blocks, lane);
   cell_finish<C, DK, NT, GEN>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
 }
 
-template <int KQ, int C, int WAVES, bool GEN>
+template <int KQ, int C, int WAVES, bool GEN, bool SORTED>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void cell_scan_bf16x3_kernel(
     CellScanArgs a) {
   __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
   __shared__ float red[WAVES * 64];
+  __shared__ float bnd[WAVES * 2 + WAVES * 2];  // block bounds, chunk thresholds
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
-  scan_bf16x3_item<KQ, C, WAVES, GEN>(a, cell, chunk, lds, red);
+  scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd);
 }
 
-template <int C, int WAVES, bool GEN>
+template <int C, int WAVES, bool GEN, bool SORTED>
 hipError_t launch_kq_g(const CellScanArgs &a, hipStream_t s, int grid) {
   dim3 blk(WAVES * 64);
   if (a.d <= 5)
-    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<1, C, WAVES, GEN>), dim3(grid), blk, 0, s, a);
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<1, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a);
   else if (a.d <= 10)
-    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<2, C, WAVES, GEN>), dim3(grid), blk, 0, s, a);
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<2, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a);
   else
-    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<3, C, WAVES, GEN>), dim3(grid), blk, 0, s, a);
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<3, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a);
   return hipGetLastError();
 }
 
 
-template <int C, int WAVES, bool GEN>
+template <int C, int WAVES, bool GEN, bool SORTED>
 hipError_t launch_kp_g(const CellScanArgs &a, hipStream_t s, int grid) {
   const int kp = (a.d + 1) / 2;
   dim3 blk(WAVES * 64);
   switch (kp) {
 #define VG_CASE(K)                                                              \
   case K:                                                                       \
-    hipLaunchKernelGGL((cell_scan_fp32_kernel<K, C, WAVES, GEN>), dim3(grid), blk, 0, s, a); \
+    hipLaunchKernelGGL((cell_scan_fp32_kernel<K, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a); \
     break;
     VG_CASE(1)
     VG_CASE(2)
@@ -588,6 +764,28 @@ hipError_t launch_kp_g(const CellScanArgs &a, hipStream_t s, int grid) {
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Every tile shape of one (GEN, SORTED) instance set; each set is compiled in
+// a translation unit of its own (vg_cell_scan*.hip).
+template <bool GEN, bool SORTED>
+hipError_t launch_cells_set(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s) {
+  if (bf16) {
+    switch (rw) {
+      case 1024: return launch_kq_g<4, 8, GEN, SORTED>(a, s, grid);
+      case 512: return launch_kq_g<2, 8, GEN, SORTED>(a, s, grid);
+      case 256: return launch_kq_g<2, 4, GEN, SORTED>(a, s, grid);
+      case 128: return launch_kq_g<1, 4, GEN, SORTED>(a, s, grid);
+      default: return launch_kq_g<1, 2, GEN, SORTED>(a, s, grid);
+    }
+  }
+  switch (rw) {
+    case 1024: return launch_kp_g<4, 8, GEN, SORTED>(a, s, grid);
+    case 512: return launch_kp_g<2, 8, GEN, SORTED>(a, s, grid);
+    case 256: return launch_kp_g<2, 4, GEN, SORTED>(a, s, grid);
+    case 128: return launch_kp_g<1, 4, GEN, SORTED>(a, s, grid);
+    default: return launch_kp_g<1, 2, GEN, SORTED>(a, s, grid);
+  }
 }
 
 }  // namespace

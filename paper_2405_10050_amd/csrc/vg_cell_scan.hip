@@ -1,21 +1,17 @@
-// Launchers of the Monte-Carlo cell scan (kernels in vg_cell_scan.h), the
-// directions-as-input instances; the instances that draw the directions on
-// the device are compiled separately (vg_cell_scan_gen.hip).
+// Launchers of the Monte-Carlo cell scan (kernels in vg_cell_scan.h): the
+// dispatch over tile shapes and instance sets, and the instances that read
+// the directions from memory with the nodes in index order (also the
+// candidate-list scans).  The other instance sets -- directions drawn on the
+// device, nodes in scan order -- are compiled in translation units of their
+// own (vg_cell_scan_sorted.hip, vg_cell_scan_gen.hip,
+// vg_cell_scan_gen_sorted.hip) so that they build in parallel.
 #include "vg_cell_scan.h"
 
 namespace vg {
-namespace {
-template <int C, int WAVES>
-hipError_t launch_kq(const CellScanArgs &a, hipStream_t s, int grid) {
-  return a.dirs ? launch_kq_g<C, WAVES, false>(a, s, grid) : launch_cells_gen(a, true, C * WAVES * 32, grid, s);
-}
 
-template <int C, int WAVES>
-hipError_t launch_kp(const CellScanArgs &a, hipStream_t s, int grid) {
-  return a.dirs ? launch_kp_g<C, WAVES, false>(a, s, grid) : launch_cells_gen(a, false, C * WAVES * 32, grid, s);
+hipError_t launch_cells_read_index(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s) {
+  return launch_cells_set<false, false>(a, bf16, rw, grid, s);
 }
-
-}  // namespace
 
 int cell_scan_rays_per_wg(int R) {
   if (R >= 1024) return 1024;
@@ -33,22 +29,9 @@ hipError_t launch_cell_scan_rw(const CellScanArgs &a0, bool bf16, int rw, int64_
   if (grid64 <= 0) return hipSuccess;
   if (grid64 > 0x7fffffff) return hipErrorInvalidValue;
   const int grid = (int)grid64;
-  if (bf16) {
-    switch (rw) {
-      case 1024: return launch_kq<4, 8>(a, s, grid);
-      case 512: return launch_kq<2, 8>(a, s, grid);
-      case 256: return launch_kq<2, 4>(a, s, grid);
-      case 128: return launch_kq<1, 4>(a, s, grid);
-      default: return launch_kq<1, 2>(a, s, grid);
-    }
-  }
-  switch (rw) {
-    case 1024: return launch_kp<4, 8>(a, s, grid);
-    case 512: return launch_kp<2, 8>(a, s, grid);
-    case 256: return launch_kp<2, 4>(a, s, grid);
-    case 128: return launch_kp<1, 4>(a, s, grid);
-    default: return launch_kp<1, 2>(a, s, grid);
-  }
+  const bool sorted = a.xs != nullptr;
+  if (a.dirs) return sorted ? launch_cells_read_sorted(a, bf16, rw, grid, s) : launch_cells_read_index(a, bf16, rw, grid, s);
+  return sorted ? launch_cells_gen_sorted(a, bf16, rw, grid, s) : launch_cells_gen_index(a, bf16, rw, grid, s);
 }
 
 hipError_t launch_cell_scan_fp32(const CellScanArgs &a, hipStream_t s) {

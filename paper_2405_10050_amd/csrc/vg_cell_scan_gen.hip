@@ -1,28 +1,13 @@
-// The Monte-Carlo cell scan with the directions drawn on the device from the
-// seed (vg_philox.h): the GEN instances of the kernels in vg_cell_scan.h, in
-// a translation unit of their own so that they compile in parallel with the
-// directions-as-input ones.
+// The Monte-Carlo cell scan instances with the directions drawn on the device from the seed (vg_philox.h) and the
+// nodes in index order: one instance set of the
+// kernels in vg_cell_scan.h, in a translation unit of its own so that the
+// sets compile in parallel.
 #include "vg_cell_scan.h"
 
 namespace vg {
 
-hipError_t launch_cells_gen(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s) {
-  if (bf16) {
-    switch (rw) {
-      case 1024: return launch_kq_g<4, 8, true>(a, s, grid);
-      case 512: return launch_kq_g<2, 8, true>(a, s, grid);
-      case 256: return launch_kq_g<2, 4, true>(a, s, grid);
-      case 128: return launch_kq_g<1, 4, true>(a, s, grid);
-      default: return launch_kq_g<1, 2, true>(a, s, grid);
-    }
-  }
-  switch (rw) {
-    case 1024: return launch_kp_g<4, 8, true>(a, s, grid);
-    case 512: return launch_kp_g<2, 8, true>(a, s, grid);
-    case 256: return launch_kp_g<2, 4, true>(a, s, grid);
-    case 128: return launch_kp_g<1, 4, true>(a, s, grid);
-    default: return launch_kp_g<1, 2, true>(a, s, grid);
-  }
+hipError_t launch_cells_gen_index(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s) {
+  return launch_cells_set<true, false>(a, bf16, rw, grid, s);
 }
 
 }  // namespace vg

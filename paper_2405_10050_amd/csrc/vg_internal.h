@@ -20,7 +20,8 @@ enum : int {
   CNT_BAD_RAYS = 3,  // rays answered NaN / -1 because of non-finite input
   CNT_NN_CALLS = 4,  // u64 (words 4, 5): nearest-neighbour queries of the incircle RayCast
   CNT_NN_GRID = 6,   // u64 (words 6, 7): of those, queries answered by the grid
-  CNT_WORDS = 8
+  CNT_SCAN_BLOCKS = 8,  // u64 (words 8, 9): 32x32 MFMA blocks the Monte-Carlo scan evaluated
+  CNT_WORDS = 10
 };
 
 // Where the recheck kernel finds a ray.
@@ -78,6 +79,13 @@ struct CellScanArgs {
   // nbr_off[i+1]); null scans every node
   const int64_t *nbr_off;
   const int32_t *nbr;
+  // optional scan order (no candidate lists): xs[p] = node perm[p], and
+  // rank[i] is the position of node i; the scan then starts at the cell's
+  // own position and skips blocks that cannot reach a lane's second best
+  const float *xs;
+  const int32_t *perm;
+  const int32_t *rank;
+  const float *aabb;  // per kOrderGroup nodes of xs: d minima, then d maxima
 };
 
 // One cloud of a persistent batch: its scan arguments and the first global
@@ -154,6 +162,28 @@ struct BackwardArgs {
   unsigned long long *acc;  // [n][d] fixed-point sums
   float *grad;           // [n][d]
 };
+
+// Scan order of the nodes (vg_order.hip): sort keys needed for n nodes (a
+// power of two >= n), and the pass that fills perm, rank, xs and the
+// bounding boxes of each kOrderGroup consecutive nodes of xs (aabb,
+// ceil(n / kOrderGroup) x 2d floats).
+constexpr int kOrderGroup = 128;
+// Whether a Monte-Carlo scan of dimension d runs in scan order: the flags
+// decide, else d <= 10 (measured on uniform clouds at 256 rays per cell: from
+// d = 12 on nearly every block is evaluated and the bookkeeping only costs).
+inline bool scan_order(int d, uint32_t flags) {
+  if (flags & VG_INDEX_ORDER) return false;
+  return (flags & VG_SCAN_ORDER) || d <= 10;
+}
+int64_t node_order_keys(int64_t n);
+hipError_t launch_node_order(const float *nodes, int64_t n, int d, uint64_t *keys, int32_t *perm, int32_t *rank,
+                             float *xs, float *aabb, hipStream_t s);
+// The Monte-Carlo cell scan over cells [0, grid / a.wg_per_cell): one
+// translation unit per (directions drawn, nodes in scan order) instance set.
+hipError_t launch_cells_read_index(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s);
+hipError_t launch_cells_read_sorted(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s);
+hipError_t launch_cells_gen_index(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s);
+hipError_t launch_cells_gen_sorted(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s);
 
 // Launchers (return a hipError_t of the launch).
 hipError_t launch_cell_scan_fp32(const CellScanArgs &a, hipStream_t s);
@@ -270,6 +300,10 @@ void batch_state_free(vg_ctx *ctx);
 // recheck queue [m], the status bytes [m], the incircle grid, the node-split
 // recheck parts, and the CNT_WORDS counters.
 struct CellsScratch {
+  // scan order of the nodes (vg_order.hip), or all null: index order
+  uint64_t *order_keys = nullptr;  // node_order_keys(n) entries
+  int32_t *perm = nullptr, *rank = nullptr;
+  float *xs = nullptr, *aabb = nullptr;
   int64_t *flag_list = nullptr;
   uint8_t *status = nullptr;
   void *grid = nullptr;
@@ -298,9 +332,6 @@ void *noalloc_scratch(int device);
 
 // Cell-scan tile choice: rays per workgroup for a given rays-per-cell.
 int cell_scan_rays_per_wg(int R);
-// The cell scan with the directions drawn from a.seed (a.dirs null), rw rays
-// per workgroup, a.wg_per_cell set (vg_cell_scan_gen.hip).
-hipError_t launch_cells_gen(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s);
 
 // Relative gap floors of the near-tie test.  The cell scan certifies its
 // argmax with an absolute FP32/BF16x3 error bound (kappa / nn-distance); the

@@ -93,7 +93,7 @@ def test_every_tile_shape_equals_the_single_path(vg, batch, shape, monkeypatch):
 
 
 def test_tuner_cache_file_format(vg, batch, tmp_path, monkeypatch):
-    """One line per (K-steps, log2 N, rays per cell, precision, shape) with a
+    """One line per (K-steps, log2 N, rays per cell, precision, node order, shape) with a
     positive time per ray-node pair; a second call with the same file probes
     nothing new, so the file is left as it was."""
     path = tmp_path / "tune.txt"
@@ -103,10 +103,11 @@ def test_tuner_cache_file_format(vg, batch, tmp_path, monkeypatch):
     rows = [ln.split() for ln in text.splitlines()]
     assert len(rows) >= 3
     for r in rows:
-        assert len(r) == 6
-        kp, log2n, R, bf16, shape = map(int, r[:5])
+        assert len(r) == 7
+        kp, log2n, R, bf16, order, shape = map(int, r[:6])
         assert 1 <= kp <= 8 and log2n >= 0 and 1 <= R <= 4096 and bf16 == 0 and 0 <= shape <= 2
-        assert float(r[5]) > 0
+        assert order == (1 if kp <= 5 else 0)  # scan order for d <= 10 by default
+        assert float(r[6]) > 0
     mtime = path.stat().st_mtime_ns
     _run(vg, batch[:3])
     assert path.stat().st_mtime_ns == mtime and path.read_text() == text
