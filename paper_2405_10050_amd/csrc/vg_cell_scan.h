@@ -240,6 +240,35 @@ __device__ __forceinline__ float chunk_bound(const CellScanArgs &a, const float 
   return wave_max(b);
 }
 
+// The same bound for chunk c computed by one thread (no reduction).
+template <int NB, int DK>
+__device__ __forceinline__ float chunk_bound_thread(const CellScanArgs &a, const float (&xi)[DK], int c) {
+  constexpr int GPC = NB / kOrderGroup;
+  const int d = a.d;
+  float b = 0.f;
+#pragma unroll
+  for (int j = 0; j < GPC; ++j) {
+    const int64_t g = (int64_t)c * GPC + j;
+    if (g * kOrderGroup < a.n) {
+      const float *box = a.aabb + g * 2 * d;
+      float s2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < DK; ++k) {
+        if (k < d) {
+          const float gap = fmaxf(fmaxf(box[k] - xi[k], xi[k] - box[d + k]), 0.f);
+          s2 = __builtin_fmaf(gap, gap, s2);
+        }
+      }
+      b = fmaxf(b, s2 > 0.f ? __builtin_amdgcn_rsqf(s2) * (1.f + 0x1p-10f) : __builtin_inff());
+    }
+  }
+  return b;
+}
+
+// Chunk bounds kept in LDS for the whole walk when the cloud has at most
+// this many chunks (else evaluated one by one as the walk reaches them).
+constexpr int kChunkTable = 2048;
+
 // The loop over the chunks of NB nodes shared by the FP32 and BF16x3 scans.
 // stage(rt) stores the calling thread's inverted node into the LDS tile;
 // block(nb, blk16, skip) runs the column blocks cb of node block nb for
@@ -258,8 +287,8 @@ __device__ __forceinline__ float chunk_bound(const CellScanArgs &a, const float 
 template <int DK, int C, int NB, int WAVES, bool SORTED, class Stage, class Block>
 __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, const float (&xi)[DK],
                                            const float (&best)[C], const float (&second)[C], float &nn2,
-                                           float *bnd, float *wsm, int64_t nb0, int64_t n_scan, int rayw,
-                                           Stage &&stage, Block &&block) {
+                                           float *bnd, float *wsm, float *ctab, int64_t nb0, int64_t n_scan,
+                                           int rayw, Stage &&stage, Block &&block) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = a.d;
   const int64_t n = a.n;
@@ -284,7 +313,15 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
   } else {
     const int64_t self = a.rank[cell];
     const int c0 = (int)(self / NB);
-    ChunkWalk walk(c0, (int)((n + NB - 1) / NB));
+    const int nch = (int)((n + NB - 1) / NB);
+    ChunkWalk walk(c0, nch);
+    // every chunk's bound up front (they depend on x_i only): the walk then
+    // skips chunks on LDS reads instead of a chain of dependent box loads
+    const bool table = nch <= kChunkTable;
+    if (table) {
+      for (int c = tid; c < nch; c += WAVES * 64) ctab[c] = chunk_bound_thread<NB, DK>(a, xi, c);
+      __syncthreads();  // uniform: table depends on n only
+    }
     int64_t base = (int64_t)c0 * NB;
     float thr = 0.f;
     load_node<DK>(a.xs, n, d, base + tid, pre);
@@ -298,7 +335,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
         thr = t;
       }
       int next = walk.next();
-      while (next >= 0 && chunk_bound<NB, DK>(a, xi, next, lane) < thr) next = walk.next();
+      while (next >= 0 && (table ? ctab[next] : chunk_bound<NB, DK>(a, xi, next, lane)) < thr) next = walk.next();
       const int64_t nbase = next >= 0 ? (int64_t)next * NB : -1;
       if (nbase >= 0) load_node<DK>(a.xs, n, d, nbase + tid, pre);
       __syncthreads();  // the previous chunk is consumed
@@ -487,7 +524,7 @@ __device__ __forceinline__ f32x16 scan_block(const float (&A)[KP], const float (
 // sets would cost the occupancy that hides each block's epilogue.
 template <int KP, int C, int WAVES, bool GEN, bool SORTED>
 __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t cell, int chunk,
-                                               float *__restrict__ lds, float *red) {
+                                               float *__restrict__ lds, float *red, float *ctab) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = Fp32Tile<KP, WAVES>::NB;  // nodes per LDS chunk (one per thread)
   constexpr int LS = Fp32Tile<KP, WAVES>::LS;
@@ -549,7 +586,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
   const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED>(
-      a, cell, xi, best, second, nn2, bnd, wsm, nb0, n_scan, rayw,
+      a, cell, xi, best, second, nn2, bnd, wsm, ctab, nb0, n_scan, rayw,
       [&](const float (&rt)[DK]) {
 #pragma unroll
         for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
@@ -585,9 +622,10 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
   // tile, NB / 32 block bounds, 2 x WAVES chunk thresholds
   __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2];
   __shared__ float red[WAVES * 64];
+  __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
-  scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red);
+  scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, ctab);
 }
 
 // ---------------------------------------------------------------- BF16x3
@@ -624,7 +662,7 @@ __device__ __forceinline__ f32x16 scan_block_bf16(const bf16x8 (&A)[KQ], const b
 // the NB/32 block bounds and 2 x WAVES chunk thresholds.
 template <int KQ, int C, int WAVES, bool GEN, bool SORTED>
 __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t cell, int chunk,
-                                                 bf16x8 *__restrict__ lds, float *red, float *bnd) {
+                                                 bf16x8 *__restrict__ lds, float *red, float *bnd, float *ctab) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = NT;
   constexpr int RW = WAVES * C * 32;
@@ -683,7 +721,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
   const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED>(
-      a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, nb0, n_scan, rayw,
+      a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, ctab, nb0, n_scan, rayw,
       [&](const float (&rt)[DK]) {
         __bf16 rh[DKP], rl[DKP];
 #pragma unroll
@@ -724,9 +762,10 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
   __shared__ float red[WAVES * 64];
   __shared__ float bnd[WAVES * 2 + WAVES * 2];  // block bounds, chunk thresholds
+  __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
-  scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd);
+  scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd, ctab);
 }
 
 template <int C, int WAVES, bool GEN, bool SORTED>
