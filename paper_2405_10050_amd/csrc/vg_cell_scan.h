@@ -171,27 +171,62 @@ struct ChunkWalk {
   }
 };
 
+// Cross-lane reductions of non-negative floats (+inf allowed), on their bit
+// patterns, which order like the values: DPP within each row of 16 lanes
+// (quad permutes, half-row and row mirrors), then the four rows by readlane
+// and scalar min/max.  A NaN pattern sorts above +inf.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t row_umin(uint32_t v) {
+  v = min(v, dpp<0xb1>(v));      // quad_perm [1,0,3,2]
+  v = min(v, dpp<0x4e>(v));      // quad_perm [2,3,0,1]
+  v = min(v, dpp<0x141>(v));     // row_half_mirror
+  return min(v, dpp<0x140>(v));  // row_mirror
+}
+__device__ __forceinline__ uint32_t row_umax(uint32_t v) {
+  v = max(v, dpp<0xb1>(v));
+  v = max(v, dpp<0x4e>(v));
+  v = max(v, dpp<0x141>(v));
+  return max(v, dpp<0x140>(v));
+}
+__device__ __forceinline__ uint32_t lane_u(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+
+// Smallest value over the wave's 64 lanes (uniform).
+__device__ __forceinline__ float wave_min(float v) {
+  const uint32_t r = row_umin(__float_as_uint(v));
+  return __uint_as_float(min(min(lane_u(r, 0), lane_u(r, 16)), min(lane_u(r, 32), lane_u(r, 48))));
+}
+
+// Largest value over the wave's 64 lanes (uniform).
+__device__ __forceinline__ float wave_max(float v) {
+  const uint32_t r = row_umax(__float_as_uint(v));
+  return __uint_as_float(max(max(lane_u(r, 0), lane_u(r, 16)), max(lane_u(r, 32), lane_u(r, 48))));
+}
+
+// Value of lane l ^ 32.  v_permlane32_swap trades lanes 32-63 of its first
+// operand with lanes 0-31 of its second: with both operands v, the first
+// result holds lanes 0-31 of v in both halves and the second lanes 32-63.
+__device__ __forceinline__ float partner32(float v, int lane) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(lane < 32 ? r[1] : r[0]);
+}
+
 // Upper bound on |u . r~| as any of the scans computes it, over the 32
 // nodes of the caller's 32-lane block (|u| = 1 up to rounding, so
 // |u . r~| <= |r~|; the factor 1 + 2^-12 covers the rounding of |r~|, of |u|
-// and of the FP32 or split-BF16 dot product).  Stored by the block's first
+// and of the FP32 or split-BF16 dot product).  Stored by the block's last
 // lane into bnd[block].
 template <int DK>
 __device__ __forceinline__ void block_bound(const float (&rt)[DK], float *bnd, int tid) {
   float m2 = 0.f;
 #pragma unroll
   for (int k = 0; k < DK; ++k) m2 = __builtin_fmaf(rt[k], rt[k], m2);
-  float b = __builtin_sqrtf(m2) * (1.f + 0x1p-12f);
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) b = fmaxf(b, __shfl_xor(b, off));
-  if ((tid & 31) == 0) bnd[tid >> 5] = b;
-}
-
-// Largest value over the wave's 64 lanes (uniform).
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+  uint32_t b = row_umax(__float_as_uint(__builtin_sqrtf(m2) * (1.f + 0x1p-12f)));
+  // rows 1 and 3 take the maximum with rows 0 and 2 (row_bcast15)
+  b = max(b, (uint32_t)__builtin_amdgcn_update_dpp((int)b, (int)b, 0x142, 0xa, 0xf, false));
+  if ((tid & 31) == 31) bnd[tid >> 5] = __uint_as_float(b);
 }
 
 // Adds the wave's count of evaluated 32x32 blocks to the call's counter.
@@ -200,17 +235,10 @@ __device__ __forceinline__ void count_blocks(const CellScanArgs &a, int blocks, 
     atomicAdd(reinterpret_cast<unsigned long long *>(a.counters + CNT_SCAN_BLOCKS), (unsigned long long)blocks);
 }
 
-// Smallest second-best value over the wave's 64 lanes (uniform).
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
 // Largest second-best value a ray holds: each lane keeps the top two of its
 // half of the 32 node rows, the lane l ^ 32 those of the other half.
-__device__ __forceinline__ float merged_second(float b, float s) {
-  const float ob = __shfl_xor(b, 32), os = __shfl_xor(s, 32);
+__device__ __forceinline__ float merged_second(float b, float s, int lane) {
+  const float ob = partner32(b, lane), os = partner32(s, lane);
   return fmaxf(fmaxf(s, os), fminf(b, ob));
 }
 
@@ -347,7 +375,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
 #pragma unroll
       for (int cb = 0; cb < C; ++cb) {
         // lanes of padding rays (ray >= R, zero direction) constrain nothing
-        const float ms = merged_second(best[cb], second[cb]);
+        const float ms = merged_second(best[cb], second[cb], lane);
         smin[cb] = wave_min(rayw + cb * 32 + (lane & 31) < a.R ? ms : __builtin_inff());
         sall = fminf(sall, smin[cb]);
       }
