@@ -218,8 +218,9 @@ __device__ __forceinline__ float partner32(float v, int lane) {
 // |u . r~| <= |r~|; the factor 1 + 2^-12 covers the rounding of |r~|, of |u|
 // and of the FP32 or split-BF16 dot product).  Stored by the block's last
 // lane into bnd[block].
+// Returns the bound (valid in the block's last lane).
 template <int DK>
-__device__ __forceinline__ void block_bound(const float (&rt)[DK], float *bnd, int tid) {
+__device__ __forceinline__ float block_bound(const float (&rt)[DK], float *bnd, int tid) {
   float m2 = 0.f;
 #pragma unroll
   for (int k = 0; k < DK; ++k) m2 = __builtin_fmaf(rt[k], rt[k], m2);
@@ -227,12 +228,60 @@ __device__ __forceinline__ void block_bound(const float (&rt)[DK], float *bnd, i
   // rows 1 and 3 take the maximum with rows 0 and 2 (row_bcast15)
   b = max(b, (uint32_t)__builtin_amdgcn_update_dpp((int)b, (int)b, 0x142, 0xa, 0xf, false));
   if ((tid & 31) == 31) bnd[tid >> 5] = __uint_as_float(b);
+  return __uint_as_float(b);
 }
 
 // Adds the wave's count of evaluated 32x32 blocks to the call's counter.
 __device__ __forceinline__ void count_blocks(const CellScanArgs &a, int blocks, int lane) {
   if (a.counters && lane == 0 && blocks)
     atomicAdd(reinterpret_cast<unsigned long long *>(a.counters + CNT_SCAN_BLOCKS), (unsigned long long)blocks);
+}
+
+// Sum over each row of 16 lanes (every lane of the row gets it).
+__device__ __forceinline__ float row_fsum(float v) {
+  v += __uint_as_float(dpp<0xb1>(__float_as_uint(v)));
+  v += __uint_as_float(dpp<0x4e>(__float_as_uint(v)));
+  v += __uint_as_float(dpp<0x141>(__float_as_uint(v)));
+  return v + __uint_as_float(dpp<0x140>(__float_as_uint(v)));
+}
+
+// Centre and radius of the caller's 32-node block in inverted coordinates:
+// c = the mean of the 32 rows (any point would do; the mean keeps the radius
+// small), rho = max |r~ - c| over the block, times 1 + 2^-12 for its
+// rounding.  The block's first lane hands c to put(c, block) (which stores
+// it as the scan's operand) and its last lane stores rho + 2^-11 B into
+// rho[block] (B the block's
+// magnitude bound, which covers the rounding of the dot products with c and
+// with the nodes): then, for any ray, no computed u.r~ of the block exceeds
+// the computed u.c plus rho[block].
+template <int DK, class Put>
+__device__ __forceinline__ void block_centre(const float (&rt)[DK], float bb, float *rho, int d, int tid,
+                                             Put &&put) {
+  const int lane = tid & 63, blk = tid >> 5;
+  float c[DK];
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    float v = 0.f;
+    if (k < d) {
+      v = row_fsum(rt[k]);
+      // rows 1 and 3 add rows 0 and 2 (row_bcast15; rows 0 and 2 add 0)
+      v += __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, (int)__float_as_uint(v), 0x142, 0xa, 0xf, false));
+      const float s0 = __uint_as_float(lane_u(__float_as_uint(v), 31));
+      const float s1 = __uint_as_float(lane_u(__float_as_uint(v), 63));
+      v = (lane < 32 ? s0 : s1) * (1.f / 32.f);
+    }
+    c[k] = v;
+  }
+  float r2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < DK; ++k) {
+    const float e = rt[k] - c[k];
+    r2 = __builtin_fmaf(e, e, r2);
+  }
+  uint32_t r = row_umax(__float_as_uint(__builtin_sqrtf(r2) * (1.f + 0x1p-12f)));
+  r = max(r, (uint32_t)__builtin_amdgcn_update_dpp((int)r, (int)r, 0x142, 0xa, 0xf, false));
+  if ((tid & 31) == 0) put(c, blk);
+  if ((tid & 31) == 31) rho[blk] = __uint_as_float(r) + bb * 0x1p-11f;
 }
 
 // Largest second-best value a ray holds: each lane keeps the top two of its
@@ -312,11 +361,13 @@ constexpr int kChunkTable = 2048;
 // even loaded when its box bound is below the smallest such value over the
 // workgroup, taken two chunks earlier from wsm (the slot of the same parity,
 // written after that chunk's second barrier, read before this chunk's first).
-template <int DK, int C, int NB, int WAVES, bool SORTED, class Stage, class Block>
+template <int DK, int C, int NB, int WAVES, bool SORTED, bool CENTRES, class Stage, class Block, class Put,
+          class Centres>
 __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, const float (&xi)[DK],
                                            const float (&best)[C], const float (&second)[C], float &nn2,
-                                           float *bnd, float *wsm, float *ctab, int64_t nb0, int64_t n_scan,
-                                           int rayw, Stage &&stage, Block &&block) {
+                                           float *bnd, float *wsm, float *ctab, float *rho, int64_t nb0,
+                                           int64_t n_scan, int rayw, Stage &&stage, Block &&block, Put &&put,
+                                           Centres &&centres) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = a.d;
   const int64_t n = a.n;
@@ -368,25 +419,53 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       if (nbase >= 0) load_node<DK>(a.xs, n, d, nbase + tid, pre);
       __syncthreads();  // the previous chunk is consumed
       stage(rt);
-      block_bound<DK>(rt, bnd, tid);
+      const float bb_own = block_bound<DK>(rt, bnd, tid);
+      if constexpr (CENTRES) block_centre<DK>(rt, bb_own, rho, d, tid, put);
       __syncthreads();
-      float smin[C];
+      float smin[C], ms[C];
       float sall = __builtin_inff();
 #pragma unroll
       for (int cb = 0; cb < C; ++cb) {
         // lanes of padding rays (ray >= R, zero direction) constrain nothing
-        const float ms = merged_second(best[cb], second[cb], lane);
-        smin[cb] = wave_min(rayw + cb * 32 + (lane & 31) < a.R ? ms : __builtin_inff());
+        ms[cb] = rayw + cb * 32 + (lane & 31) < a.R ? merged_second(best[cb], second[cb], lane) : __builtin_inff();
+        smin[cb] = wave_min(ms[cb]);
         sall = fminf(sall, smin[cb]);
       }
       if (lane == 0) wsm[(it & 1) * WAVES + wave] = sall;
       const int64_t rem = n - base;
       const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
       if (!(wave_max(lane < nblocks ? bnd[lane] : 0.f) < sall)) {
+        // per column block, the node blocks some ray of it still needs by the
+        // centre bound u.c + rho (bit b: block b of the chunk)
+        uint32_t need[C];
+#pragma unroll
+        for (int cb = 0; cb < C; ++cb) need[cb] = ~0u;
+        if constexpr (CENTRES) {
+          // rows 0..15 of the centre product: register i of lane half h holds
+          // row 8 (i / 4) + 4 h + i % 4
+          float eb[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) eb[i] = rho[8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)];
+#pragma unroll
+          for (int cb = 0; cb < C; ++cb) {
+            if (smin[cb] == __builtin_inff()) continue;  // padding rays only: skipped anyway
+            const f32x16 uc = centres(cb);
+            uint32_t nd = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const uint64_t m = __ballot(!(uc[i] + eb[i] < ms[cb]));
+              const int row = 8 * (i >> 2) + (i & 3);
+              nd |= ((uint32_t)(m & 0xffffffffull) != 0u ? 1u : 0u) << row;
+              nd |= ((uint32_t)(m >> 32) != 0u ? 1u : 0u) << (row + 4);
+            }
+            need[cb] = nd;
+          }
+        }
         for (int nb = 0; nb < nblocks; ++nb) {
           const float bb = bnd[nb];
           if (bb < sall) continue;
-          blocks += block(nb, (int)((base >> 5) + nb) << 4, [&](int cb) { return bb < smin[cb]; });
+          blocks += block(nb, (int)((base >> 5) + nb) << 4,
+                          [&](int cb) { return bb < smin[cb] || !((need[cb] >> nb) & 1u); });
         }
       }
       base = nbase;
@@ -552,7 +631,7 @@ __device__ __forceinline__ f32x16 scan_block(const float (&A)[KP], const float (
 // sets would cost the occupancy that hides each block's epilogue.
 template <int KP, int C, int WAVES, bool GEN, bool SORTED>
 __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t cell, int chunk,
-                                               float *__restrict__ lds, float *red, float *ctab) {
+                                               float *__restrict__ lds, float *red, float *ctab, float *cen) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = Fp32Tile<KP, WAVES>::NB;  // nodes per LDS chunk (one per thread)
   constexpr int LS = Fp32Tile<KP, WAVES>::LS;
@@ -613,8 +692,10 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   float *wsm = lds + FLOATS + NB / 32;   // 2 x WAVES chunk thresholds
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
-  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED>(
-      a, cell, xi, best, second, nn2, bnd, wsm, ctab, nb0, n_scan, rayw,
+  // block centres (scan order, d >= 7; below, they cost more than they save)
+  constexpr bool CEN = SORTED && KP >= 4;
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN>(
+      a, cell, xi, best, second, nn2, bnd, wsm, ctab, cen + 16 * 16, nb0, n_scan, rayw,
       [&](const float (&rt)[DK]) {
 #pragma unroll
         for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
@@ -632,6 +713,18 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
           ++ran;
         }
         return ran;
+      },
+      [&](const float (&c)[DK], int blk) {
+#pragma unroll
+        for (int k = 0; k < DK; ++k) cen[k * 16 + blk] = c[k];
+      },
+      [&](int cb) {
+        // u.c for the chunk's block centres (rows 0..15; the rest zero)
+        float A[KP];
+#pragma unroll
+        for (int kp = 0; kp < KP; ++kp)
+          A[kp] = (lane & 31) < 16 ? cen[(2 * kp + (lane >> 5)) * 16 + (lane & 31)] : 0.f;
+        return scan_block<KP>(A, ub[cb]);
       });
 
   count_blocks(a, blocks, lane);
@@ -651,9 +744,10 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2];
   __shared__ float red[WAVES * 64];
   __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
+  __shared__ float cen[SORTED ? 16 * 16 + 16 : 1];  // block centres [k][block], radii
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
-  scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, ctab);
+  scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, ctab, cen);
 }
 
 // ---------------------------------------------------------------- BF16x3
@@ -748,8 +842,13 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
 
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
-  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED>(
-      a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, ctab, nb0, n_scan, rayw,
+  // No block centres here: this scan is VALU-bound by its epilogue, and the
+  // centres' per-chunk work and registers (3 instead of 4 waves per SIMD at
+  // d <= 10) cost more than the skipped blocks save (d=10 mixture: 260 ->
+  // 546 ms with them).
+  constexpr bool CEN = false;
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN>(
+      a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, ctab, nullptr, nb0, n_scan, rayw,
       [&](const float (&rt)[DK]) {
         __bf16 rh[DKP], rl[DKP];
 #pragma unroll
@@ -779,7 +878,8 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
           ++ran;
         }
         return ran;
-      });
+      },
+      [](const float (&)[DK], int) {}, [](int) { return f32x16{}; });
   count_blocks(a, blocks, lane);
   cell_finish<C, DK, NT, GEN>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
 }
