@@ -655,7 +655,8 @@ def main():
             "algorithmic_bytes": float(n * d * 4 + rays * 9 + (rays * d * 4 if args.dirs == "input" else 0)),
             "scan_ms": scan_ms,
             "scan_timing": "HIP events around each scan launch on its stream, 3 eager steps after the replays",
-            "node_order": "scan (Morton order, exact block skipping)" if d <= 10 else "index",
+            "node_order": "scan (Morton order, exact block and chunk skipping)"
+                          if d <= (10 if args.precision == "bf16x3" else 12) else "index",
             "evaluated_pair_fraction": st["scan_pairs"] / (float(n) * rays),
             "executed": (3.0 if args.precision == "bf16x3" else 1.0) * 2.0 * d * st["scan_pairs"] / (scan_ms / 1e3)
                         / 1e12,

@@ -68,11 +68,12 @@ typedef enum vg_status {
                                     from InitialHeuristic (|eta| >= 2)         */
 #define VG_PERIODIC (1u << 5)    /* vg_explore: the periodic diagram (torus)    */
 #define VG_SCAN_ORDER (1u << 6)  /* Monte-Carlo scan over the nodes sorted along
-                                    a Morton curve, skipping node blocks that
-                                    cannot change a ray's two best candidates
-                                    (default for d <= 10)                      */
+                                    a Morton curve, skipping node blocks and
+                                    chunks that cannot change a ray's two best
+                                    candidates (default for d <= 12 in FP32,
+                                    d <= 10 in BF16x3)                         */
 #define VG_INDEX_ORDER (1u << 7) /* Monte-Carlo scan over every node in index
-                                    order (default for d > 10)                 */
+                                    order (default above)                      */
 
 /* per-ray status bits (uint8) */
 #define VG_ST_NEAR_TIE 1  /* FP32 gap of the two best candidates below VG_TIE_EPS */
@@ -183,14 +184,17 @@ int vg_raycast_f64(vg_ctx *ctx, int d, int64_t n_nodes, const float *nodes,
  * certificate and the FP64 recheck are shared), and vg_stats.nn_calls and
  * nn_grid_calls count the queries.
  * Node order of the dense scan: with VG_SCAN_ORDER (the default for
- * d <= 10) the call first sorts a copy of the nodes along a Morton curve of
- * their first min(3, d) coordinates (a pass of plain kernels, O(n log^2 n));
- * each cell then scans from its own place in that order outwards and skips a
- * 32-node block, or a whole chunk of nodes, when a rigorous bound on |u.r~|
- * over it is below every ray's current second-best value.  The skip is
- * exact: every output equals the one of the scan over all nodes in index
- * order (VG_INDEX_ORDER, the default for d > 10, where uniform clouds leave
- * little to skip); vg_stats.scan_pairs counts the ray-node pairs evaluated.
+ * d <= 12 in FP32 and d <= 10 in BF16x3) the call first sorts a copy of the
+ * nodes along a Morton curve of all their coordinates, scaled to the cloud's
+ * bounding box (a pass of plain kernels, O(n log^2 n)); each cell then scans
+ * from its own place in that order outwards and skips a 32-node block, or a
+ * whole chunk of nodes, when a rigorous bound on u.r~ over it is below
+ * every ray's current second-best value.  The bounds need unit directions
+ * (up to rounding): a workgroup that holds a longer one skips nothing.  The
+ * skip is exact: every output equals the one of the scan over all nodes in
+ * index order (VG_INDEX_ORDER, the default above those dimensions, where
+ * uniform clouds leave little to skip); vg_stats.scan_pairs counts the
+ * ray-node pairs evaluated.
  * Neighbour-restricted scans (vg_mc_volume_area_nbr) keep their list order.
  *   dirs [n_nodes][rays_per_cell][d] f32 unit vectors
  *   flags VG_PREC_BF16X3, VG_NO_RECHECK, VG_INCIRCLE, VG_SCAN_ORDER,

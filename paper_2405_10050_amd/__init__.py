@@ -280,7 +280,8 @@ def raycast_cells(nodes, dirs=None, precision="fp32", recheck=True, incircle=Fal
     ``seed`` and ``rays_per_cell``: the directions are then drawn on the
     device (Philox4x32-10, see :func:`dump_dirs`) and never stored.
     ``order`` = "scan" / "index" forces the node order of the dense scan
-    (default: scan order, with exact block skipping, for d <= 10).  Returns
+    (default: scan order, with exact block skipping, for d <= 12 in FP32 and
+    d <= 10 in BF16x3).  Returns
     ``(t, idx, status)`` shaped ``[N, R]``."""
     _dev(nodes, torch.float32, "nodes")
     dev = nodes.device

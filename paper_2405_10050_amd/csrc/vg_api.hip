@@ -216,12 +216,12 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
   const size_t parts_bytes = recheck ? recheck_cells_reserve(m, n) : 0;
   if ((flags & VG_SCAN_ORDER) && (flags & VG_INDEX_ORDER))
     return fail(ctx, VG_EINVAL, "VG_SCAN_ORDER and VG_INDEX_ORDER exclude each other");
-  const bool ordered = !incircle && !nbr && scan_order(d, flags);
+  const bool ordered = !incircle && !nbr && scan_order(d, flags, bf16);
   const int64_t n_keys = ordered ? node_order_keys(n) : 0;
   size_t need = Carver::need({recheck ? (size_t)m * 8 : 0, st_out ? 0 : (size_t)m, grid_bytes, parts_bytes,
                               (size_t)n_keys * 8, ordered ? (size_t)n * 4 : 0, ordered ? (size_t)n * 4 : 0,
                               ordered ? (size_t)(n * d) * 4 : 0,
-                              ordered ? (size_t)((n + kOrderGroup - 1) / kOrderGroup) * 2 * d * 4 : 0});
+                              ordered ? (size_t)order_box_floats(n, d) * 4 : 0});
   int rc = ensure_scratch(ctx, need);
   if (rc) return rc;
   Carver cv(ctx->scratch);
@@ -231,7 +231,7 @@ int run_cells(vg_ctx *ctx, int d, int64_t n, const float *nodes, int R, const fl
     sc.perm = cv.take<int32_t>(n);
     sc.rank = cv.take<int32_t>(n);
     sc.xs = cv.take<float>(n * d);
-    sc.aabb = cv.take<float>((n + kOrderGroup - 1) / kOrderGroup * 2 * d);
+    sc.aabb = cv.take<float>(order_box_floats(n, d));
   }
   sc.flag_list = recheck ? cv.take<int64_t>(m) : nullptr;
   sc.status = st_out ? st_out : cv.take<uint8_t>(m);

@@ -144,7 +144,7 @@ int shape_rw(int R, int sh) {
 }
 
 TuneKey tune_key(const vg_cells_problem &p, bool bf16, uint32_t flags) {
-  return TuneKey{(p.d + 1) / 2, ilog2(p.n_nodes), p.rays_per_cell, bf16 ? 1 : 0, scan_order(p.d, flags) ? 1 : 0};
+  return TuneKey{(p.d + 1) / 2, ilog2(p.n_nodes), p.rays_per_cell, bf16 ? 1 : 0, scan_order(p.d, flags, bf16) ? 1 : 0};
 }
 
 // The scan arguments of one cloud of a batch (q: its position in the table).
@@ -171,11 +171,11 @@ CellScanArgs cloud_args(const vg_cells_problem &p, int q, bool bf16, int rw, uin
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Bytes of the scan-order buffers of one cloud (sort keys, perm, rank, the
-// sorted copy and its boxes), each 256-byte aligned.
+// sorted copy and its group boxes and balls), each 256-byte aligned.
 size_t order_bytes(const vg_cells_problem &p) {
   const int64_t n = p.n_nodes;
   return align256((size_t)node_order_keys(n) * 8) + 2 * align256((size_t)n * 4) + align256((size_t)(n * p.d) * 4) +
-         align256((size_t)((n + kOrderGroup - 1) / kOrderGroup) * 2 * p.d * 4);
+         align256((size_t)order_box_floats(n, p.d) * 4);
 }
 
 // Points a's scan-order fields into the buffers at base (order_bytes(p) long).
@@ -210,7 +210,7 @@ std::vector<BatchProblem> make_table(const std::vector<vg_cells_problem> &pr, co
     T[q].a = cloud_args(p, (int)q, bf16, rw[order[q]], counters, flags,
                         (!p.status_out && status) ? status + status_off : nullptr);
     if (!p.status_out) status_off += m;
-    if (order_base && scan_order(p.d, flags_in)) {
+    if (order_base && scan_order(p.d, flags_in, bf16)) {
       uint64_t *k = nullptr;
       carve_order(T[q].a, p, order_base + order_off, k);
       if (keys) (*keys)[q] = k;
@@ -558,7 +558,7 @@ extern "C" int vg_raycast_cells_batched(vg_ctx *ctx, int n_problems, const vg_ce
   for (auto &p : pr) need_status |= p.status_out == nullptr;
   size_t order_total = 0;
   for (auto &p : pr)
-    if (scan_order(p.d, flags)) order_total += order_bytes(p);
+    if (scan_order(p.d, flags, bf16)) order_total += order_bytes(p);
   BatchState &S = state(ctx);
   auto fill = [&](const BatchBuffers &b, std::vector<char> &bytes) {
     int64_t rays;

@@ -158,10 +158,17 @@ __device__ __forceinline__ int64_t row_node(const CellScanArgs &a, int64_t nb0, 
 // Chunks of the scan in visiting order: with the nodes in scan order
 // (a.xs), the chunk that holds the cell's own node first, then alternately
 // the next chunk above and below it; else 0, 1, 2, ...
+// A value the whole workgroup holds alike (x_i, the cell's generator), moved
+// to a scalar register: the scans keep their vector registers for the rays.
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 struct ChunkWalk {
   int lo, hi, nch;
   bool up;
   __device__ ChunkWalk(int first, int count) : lo(first - 1), hi(first + 1), nch(count), up(true) {}
+  __device__ bool done() const { return lo < 0 && hi >= nch; }
   // the chunk after the current one, or -1
   __device__ int next() {
     if (lo < 0 && hi >= nch) return -1;
@@ -353,21 +360,44 @@ constexpr int kChunkTable = 2048;
 // 32x32 blocks the wave evaluated.
 //
 // Index order (!SORTED, also the candidate lists): every chunk, every block.
-// Scan order (SORTED): the cell's own chunk first, then outwards (ChunkWalk);
-// a node block is skipped for column block cb when its bound is below the
-// smallest merged second best of cb's 32 rays (none of its values can enter
-// a ray's top two: they are at most that second best, and an equal value
-// would only make a tie the certificate flags anyway); a whole chunk is not
-// even loaded when its box bound is below the smallest such value over the
-// workgroup, taken two chunks earlier from wsm (the slot of the same parity,
-// written after that chunk's second barrier, read before this chunk's first).
-template <int DK, int C, int NB, int WAVES, bool SORTED, bool CENTRES, class Stage, class Block, class Put,
-          class Centres>
+// Scan order (SORTED): the cell's own chunk first, then outwards (ChunkWalk).
+// Every bound below holds for |u| = 1 up to rounding; `prune` (uniform) says
+// that every ray of the workgroup has such a direction, and without it
+// nothing is skipped.  A node block is skipped for column block cb when its
+// bound is below the smallest merged second best of cb's 32 rays (none of
+// its values can enter a ray's top two: they are at most that second best,
+// and an equal value would only make a tie the certificate flags anyway).
+// A whole chunk is not even loaded
+//  - when its box bound is below the smallest such value over the workgroup,
+//    taken two chunks earlier from wsm (the slot of the same parity, written
+//    after that chunk's second barrier, read before this chunk's first);
+//  - (WIN) when no ray of the workgroup reaches the bound of its groups'
+//    balls inverted about x_i: the walk is cut into windows of 32 groups
+//    (32 / GPC chunks that pass the box bound); at a window's start every
+//    wave computes u.c' for the 32 inverted centres c' with one product
+//    chain per column block (window(cb, c'): lane l holds row l % 32's
+//    centre), compares u.c' + e' with each
+//    ray's merged second, and the workgroup ORs the waves' group masks
+//    through wmask (two slots, alternating: a slot is rewritten only after
+//    a later barrier all waves have passed).  A column block's own mask also
+//    removes the node blocks of groups none of its rays reach.
+// The ball of a group (centre c, radius r, holding every node of the group)
+// inverted about x_i is the ball of centre c' = (c - x_i) / D and radius
+// r / D, D = |c - x_i|^2 - r^2 > 0 (x_i outside), so u.r~ <= u.c' + r / D
+// for |u| = 1.  With D >= 2^-8 |c - x_i|^2 its FP32 evaluation is within
+// (d + 3) 2^-24 |c - x_i|^2 / D <= 2^-11.7 of D relative, c' and r / D within
+// about 2^-10.9 of |c'| = |c - x_i| / D; e' = (r + 2^-8 |c - x_i|) / D covers
+// these, the rounding of the inverted nodes and of the FP32 or split-BF16
+// products with room to spare.  Closer groups (x_i inside or near the ball)
+// are always needed.
+template <int DK, int C, int NB, int WAVES, bool SORTED, bool CENTRES, bool WIN, class Stage, class Block,
+          class Put, class Centres, class Window>
 __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, const float (&xi)[DK],
                                            const float (&best)[C], const float (&second)[C], float &nn2,
-                                           float *bnd, float *wsm, float *ctab, float *rho, int64_t nb0,
-                                           int64_t n_scan, int rayw, Stage &&stage, Block &&block, Put &&put,
-                                           Centres &&centres) {
+                                           float *bnd, float *wsm, uint32_t *wmask, float *ctab, float *rho,
+                                           int64_t nb0, int64_t n_scan, int rayw, bool prune, Stage &&stage,
+                                           Block &&block, Put &&put, Centres &&centres, Window &&window) {
+  static_assert(NB / 32 <= 32, "block masks are 32 bits");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = a.d;
   const int64_t n = a.n;
@@ -390,6 +420,10 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
         blocks += block(nb, (int)((base >> 5) + nb) << 4, [](int) { return false; });
     }
   } else {
+    static_assert(NB % kOrderGroup == 0, "chunks hold whole groups");
+    constexpr int GPC = NB / kOrderGroup;  // groups per chunk
+    constexpr int WS = 32 / GPC;           // chunks per window
+    constexpr uint32_t GMASK = (1u << GPC) - 1u;
     const int64_t self = a.rank[cell];
     const int c0 = (int)(self / NB);
     const int nch = (int)((n + NB - 1) / NB);
@@ -401,8 +435,123 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       for (int c = tid; c < nch; c += WAVES * 64) ctab[c] = chunk_bound_thread<NB, DK>(a, xi, c);
       __syncthreads();  // uniform: table depends on n only
     }
+    auto cbound = [&](int c) { return table ? ctab[c] : chunk_bound<NB, DK>(a, xi, c, lane); };
+    // per column block, the value a ray's bound must reach: its merged second
+    // best; +inf on lanes of padding rays (ray >= R, zero direction), which
+    // constrain nothing; 0 without prune (no bound is below it)
+    auto floors = [&](float (&ms)[C]) {
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) {
+        const float m = merged_second(best[cb], second[cb], lane);
+        ms[cb] = !prune ? 0.f : (rayw + cb * 32 + (lane & 31) < a.R ? m : __builtin_inff());
+      }
+    };
+    const float *ball = a.aabb + order_groups(n) * 2 * d;
+    uint32_t wq = 0u;       // window slots not yet visited
+    int slot_chunk = -1;    // lane s < WS: the chunk of window slot s
+    uint32_t gneed[C];      // bit j: window group j reaches some ray of cb
+    int wpar = 0;
+    // backoff of the window test: after a test that rejects fewer than an
+    // eighth of its chunks the next `idle` windows are taken untested (the
+    // test costs about as much as staging a chunk per column block; where
+    // the balls rarely separate, as in uniform clouds of d >= 10, it would
+    // only cost)
+    int idle = 0, untested = 0;
+    // A new window: its chunks (in walk order, past the box bound) and the
+    // mask of the slots the workgroup needs.  Uniform; one barrier.
+    auto refill = [&](float thr_now) -> uint32_t {
+      int cnt = 0, my_chunk = -1;  // row j = lane % 32 is group j % GPC of slot j / GPC
+      slot_chunk = -1;
+      while (cnt < WS) {
+        const int c = walk.next();
+        if (c < 0) break;
+        if (cbound(c) < thr_now) continue;
+        if ((lane & 31) / GPC == cnt) my_chunk = c;
+        if (lane == cnt) slot_chunk = c;
+        ++cnt;
+      }
+      if (cnt == 0) return 0u;
+      const uint32_t all_slots = cnt >= 32 ? ~0u : (1u << cnt) - 1u;
+      if (!prune || untested > 0) {
+        untested = untested > 0 ? untested - 1 : 0;
+#pragma unroll
+        for (int cb = 0; cb < C; ++cb) gneed[cb] = ~0u;
+        return all_slots;
+      }
+      // lane row's group ball inverted about x_i: centre cp = (c - x_i) / D
+      // and e' = (r + 2^-8 |c - x_i|) / D; cp = 0 without a group (e' = -inf:
+      // never needed) or with x_i inside or near it (e' = +inf)
+      float cp[DK], e = -__builtin_inff();
+#pragma unroll
+      for (int k = 0; k < DK; ++k) cp[k] = 0.f;
+      const int64_t g = (int64_t)my_chunk * GPC + ((lane & 31) % GPC);
+      if (my_chunk >= 0 && g < order_groups(n)) {
+        const float *bp = ball + g * (d + 1);
+        float s2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+          cp[k] = k < d ? bp[k] - xi[k] : 0.f;
+          s2 = __builtin_fmaf(cp[k], cp[k], s2);
+        }
+        const float r = bp[d];
+        const float D = __builtin_fmaf(-r, r, s2);
+        if (D > s2 * 0x1p-8f && D < __builtin_inff()) {
+          const float inv = 1.f / D;
+#pragma unroll
+          for (int k = 0; k < DK; ++k) cp[k] *= inv;
+          e = __builtin_fmaf(0x1p-8f, __builtin_sqrtf(s2), r) * inv;
+        } else {
+#pragma unroll
+          for (int k = 0; k < DK; ++k) cp[k] = 0.f;
+          e = __builtin_inff();
+        }
+      }
+      float ms[C];
+      floors(ms);
+      uint32_t wm = 0u;
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) {
+        gneed[cb] = 0u;
+        if (__ballot(ms[cb] < __builtin_inff()) == 0ull) continue;  // padding rays only
+        // u.c' + e' (one more K step adds e' of each row: A = e' and B = 1 in
+        // lane half 0, zero in half 1); register i of lane half h holds row
+        // 8 (i / 4) + 4 h + i % 4
+        const f32x16 uc = __builtin_amdgcn_mfma_f32_32x32x2f32(lane < 32 ? e : 0.f, lane < 32 ? 1.f : 0.f,
+                                                               window(cb, cp), 0, 0, 0);
+        uint32_t nd = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const uint64_t m = __ballot(!(uc[i] < ms[cb]));
+          const int row = 8 * (i >> 2) + (i & 3);
+          nd |= ((uint32_t)(m & 0xffffffffull) != 0u ? 1u : 0u) << row;
+          nd |= ((uint32_t)(m >> 32) != 0u ? 1u : 0u) << (row + 4);
+        }
+        gneed[cb] = nd;
+        wm |= nd;
+      }
+      if (lane == 0) wmask[wpar * WAVES + wave] = wm;
+      __syncthreads();
+      uint32_t all = 0u;
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) all |= wmask[wpar * WAVES + w];
+      wpar ^= 1;
+      uint32_t q = 0u;
+#pragma unroll
+      for (int sl = 0; sl < WS; ++sl)
+        if (sl < cnt && ((all >> (sl * GPC)) & GMASK)) q |= 1u << sl;
+      if (8 * (cnt - __builtin_popcount(q)) < cnt) {
+        idle = idle < 8 ? idle + 1 : 8;
+        untested = idle;
+      } else {
+        idle = 0;
+      }
+      return q;
+    };
     int64_t base = (int64_t)c0 * NB;
     float thr = 0.f;
+    uint32_t cur_g[C];  // groups of the current chunk that reach a ray of cb
+#pragma unroll
+    for (int cb = 0; cb < C; ++cb) cur_g[cb] = GMASK;
     load_node<DK>(a.xs, n, d, base + tid, pre);
     for (int it = 0; base >= 0; ++it) {
       float rt[DK];
@@ -413,62 +562,112 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
         for (int w = 1; w < WAVES; ++w) t = fminf(t, wsm[(it & 1) * WAVES + w]);
         thr = t;
       }
-      int next = walk.next();
-      while (next >= 0 && (table ? ctab[next] : chunk_bound<NB, DK>(a, xi, next, lane)) < thr) next = walk.next();
-      const int64_t nbase = next >= 0 ? (int64_t)next * NB : -1;
-      if (nbase >= 0) load_node<DK>(a.xs, n, d, nbase + tid, pre);
+      // the next chunk: the next slot of the window the workgroup needs (or
+      // the walk's next chunk) whose box bound still reaches thr; its nodes
+      // load while this chunk is staged and scanned
+      int next = -1;
+      uint32_t nxt_g[C];
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) nxt_g[cb] = GMASK;
+      auto pop = [&]() {
+        while (wq != 0u) {
+          const int sl = __builtin_ctz(wq);
+          wq &= wq - 1u;
+          const int c = __builtin_amdgcn_readlane(slot_chunk, sl);
+          if (cbound(c) < thr) continue;
+          next = c;
+#pragma unroll
+          for (int cb = 0; cb < C; ++cb) nxt_g[cb] = (gneed[cb] >> (sl * GPC)) & GMASK;
+          return;
+        }
+      };
+      if constexpr (WIN) {
+        pop();
+      } else {
+        next = walk.next();
+        while (next >= 0 && cbound(next) < thr) next = walk.next();
+      }
+      if (next >= 0) load_node<DK>(a.xs, n, d, (int64_t)next * NB + tid, pre);
       __syncthreads();  // the previous chunk is consumed
       stage(rt);
       const float bb_own = block_bound<DK>(rt, bnd, tid);
       if constexpr (CENTRES) block_centre<DK>(rt, bb_own, rho, d, tid, put);
+      if constexpr (WIN) {
+        // window spent: the next windows are tested here, where rt is dead
+        // (the test's registers do not add to it)
+        if (next < 0) {
+          while (next < 0 && !walk.done()) {
+            wq = refill(thr);
+            pop();
+          }
+          if (next >= 0) load_node<DK>(a.xs, n, d, (int64_t)next * NB + tid, pre);
+        }
+      }
+      const int64_t nbase = next >= 0 ? (int64_t)next * NB : -1;
       __syncthreads();
       float smin[C], ms[C];
       float sall = __builtin_inff();
+      floors(ms);
 #pragma unroll
       for (int cb = 0; cb < C; ++cb) {
-        // lanes of padding rays (ray >= R, zero direction) constrain nothing
-        ms[cb] = rayw + cb * 32 + (lane & 31) < a.R ? merged_second(best[cb], second[cb], lane) : __builtin_inff();
         smin[cb] = wave_min(ms[cb]);
         sall = fminf(sall, smin[cb]);
       }
       if (lane == 0) wsm[(it & 1) * WAVES + wave] = sall;
       const int64_t rem = n - base;
       const int nblocks = rem >= NB ? NB / 32 : (int)((rem + 31) / 32);
-      if (!(wave_max(lane < nblocks ? bnd[lane] : 0.f) < sall)) {
-        // per column block, the node blocks some ray of it still needs by the
-        // centre bound u.c + rho (bit b: block b of the chunk)
-        uint32_t need[C];
+      // lane b < nblocks holds the bound of node block b
+      const float lb = lane < nblocks ? bnd[lane] : 0.f;
+      if (!(wave_max(lb) < sall)) {
+        // run[cb] bit b: node block b for column block cb, by the magnitude
+        // bound, the groups' balls (WIN) and the centre bound u.c + rho
+        // (CENTRES) of some ray of cb
+        uint32_t run[C], any = 0u;
 #pragma unroll
-        for (int cb = 0; cb < C; ++cb) need[cb] = ~0u;
+        for (int cb = 0; cb < C; ++cb) {
+          run[cb] = (uint32_t)__ballot(!(lb < smin[cb]) && lane < nblocks);
+          if constexpr (WIN) {
+            uint32_t gb = 0u;  // each group is kOrderGroup / 32 = 4 node blocks
+#pragma unroll
+            for (int gi = 0; gi < GPC; ++gi) gb |= ((cur_g[cb] >> gi) & 1u) ? 0xfu << (4 * gi) : 0u;
+            run[cb] &= gb;
+          }
+          any |= run[cb];
+        }
         if constexpr (CENTRES) {
-          // rows 0..15 of the centre product: register i of lane half h holds
-          // row 8 (i / 4) + 4 h + i % 4
-          float eb[8];
+          if (prune) {
+            // rows 0..15 of the centre product: register i of lane half h
+            // holds row 8 (i / 4) + 4 h + i % 4
+            float eb[8];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) eb[i] = rho[8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)];
+            for (int i = 0; i < 8; ++i) eb[i] = rho[8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)];
+            any = 0u;
 #pragma unroll
-          for (int cb = 0; cb < C; ++cb) {
-            if (smin[cb] == __builtin_inff()) continue;  // padding rays only: skipped anyway
-            const f32x16 uc = centres(cb);
-            uint32_t nd = 0;
+            for (int cb = 0; cb < C; ++cb) {
+              if (run[cb] == 0u) continue;  // no block in reach (also padding rays only)
+              const f32x16 uc = centres(cb);
+              uint32_t nd = 0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-              const uint64_t m = __ballot(!(uc[i] + eb[i] < ms[cb]));
-              const int row = 8 * (i >> 2) + (i & 3);
-              nd |= ((uint32_t)(m & 0xffffffffull) != 0u ? 1u : 0u) << row;
-              nd |= ((uint32_t)(m >> 32) != 0u ? 1u : 0u) << (row + 4);
+              for (int i = 0; i < 8; ++i) {
+                const uint64_t m = __ballot(!(uc[i] + eb[i] < ms[cb]));
+                const int row = 8 * (i >> 2) + (i & 3);
+                nd |= ((uint32_t)(m & 0xffffffffull) != 0u ? 1u : 0u) << row;
+                nd |= ((uint32_t)(m >> 32) != 0u ? 1u : 0u) << (row + 4);
+              }
+              run[cb] &= nd;
+              any |= run[cb];
             }
-            need[cb] = nd;
           }
         }
-        for (int nb = 0; nb < nblocks; ++nb) {
-          const float bb = bnd[nb];
-          if (bb < sall) continue;
-          blocks += block(nb, (int)((base >> 5) + nb) << 4,
-                          [&](int cb) { return bb < smin[cb] || !((need[cb] >> nb) & 1u); });
+        while (any) {
+          const int nb = __builtin_ctz(any);
+          any &= any - 1u;
+          blocks += block(nb, (int)((base >> 5) + nb) << 4, [&](int cb) { return !((run[cb] >> nb) & 1u); });
         }
       }
       base = nbase;
+#pragma unroll
+      for (int cb = 0; cb < C; ++cb) cur_g[cb] = nxt_g[cb];
     }
   }
   return blocks;
@@ -649,7 +848,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 
   float xi[DK];
 #pragma unroll
-  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+  for (int k = 0; k < DK; ++k) xi[k] = uniform_f((k < d) ? a.nodes[cell * d + k] : 0.f);
 
   // B operand: lane l holds u[ray l%32][2kp + l/32] of each column block.
   const int rayw = chunk * RW + wave * (C * 32);
@@ -676,6 +875,22 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
     }
   }
 
+  // scan order: the skip bounds need |u| = 1 up to rounding for every ray of
+  // the workgroup (the two lane halves hold complementary components)
+  bool prune = true;
+  if constexpr (SORTED) {
+    bool unit = true;
+#pragma unroll
+    for (int cb = 0; cb < C; ++cb) {
+      float uu = 0.f;
+#pragma unroll
+      for (int kp = 0; kp < KP; ++kp) uu = __builtin_fmaf(ub[cb][kp], ub[cb][kp], uu);
+      uu += partner32(uu, lane);
+      unit = unit && uu <= 1.f + 0x1p-14f;
+    }
+    prune = __syncthreads_and(unit) != 0;
+  }
+
   float best[C], second[C];
   int bidx[C];
 #pragma unroll
@@ -690,12 +905,13 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   const float *lrow = lds + (lane >> 5) * LS + (lane & 31);
   float *bnd = lds + FLOATS;             // NB / 32 block bounds
   float *wsm = lds + FLOATS + NB / 32;   // 2 x WAVES chunk thresholds
+  uint32_t *wmask = reinterpret_cast<uint32_t *>(wsm + 2 * WAVES);  // 2 x WAVES window masks
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
-  // block centres (scan order, d >= 7; below, they cost more than they save)
-  constexpr bool CEN = SORTED && KP >= 4;
-  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN>(
-      a, cell, xi, best, second, nn2, bnd, wsm, ctab, cen + 16 * 16, nb0, n_scan, rayw,
+  // block centres (scan order, d >= 3)
+  constexpr bool CEN = SORTED && KP >= 2;
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, SORTED>(
+      a, cell, xi, best, second, nn2, bnd, wsm, wmask, ctab, cen + 16 * 16, nb0, n_scan, rayw, prune,
       [&](const float (&rt)[DK]) {
 #pragma unroll
         for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
@@ -725,6 +941,15 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
         for (int kp = 0; kp < KP; ++kp)
           A[kp] = (lane & 31) < 16 ? cen[(2 * kp + (lane >> 5)) * 16 + (lane & 31)] : 0.f;
         return scan_block<KP>(A, ub[cb]);
+      },
+      [&](int cb, const float (&cp)[DK]) {
+        // u.c' for the window's 32 inverted ball centres (row l % 32: lane l's)
+        const int hi = (lane & 32) ? -1 : 0;
+        float A[KP];
+#pragma unroll
+        for (int kp = 0; kp < KP; ++kp)
+          A[kp] = __int_as_float((__float_as_int(cp[2 * kp]) & ~hi) | (__float_as_int(cp[2 * kp + 1]) & hi));
+        return scan_block<KP>(A, ub[cb]);
       });
 
   count_blocks(a, blocks, lane);
@@ -740,8 +965,8 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 template <int KP, int C, int WAVES, bool GEN, bool SORTED>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void cell_scan_fp32_kernel(
     CellScanArgs a) {
-  // tile, NB / 32 block bounds, 2 x WAVES chunk thresholds
-  __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2];
+  // tile, NB / 32 block bounds, 2 x WAVES chunk thresholds, 2 x WAVES window masks
+  __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2 + WAVES * 2];
   __shared__ float red[WAVES * 64];
   __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
   __shared__ float cen[SORTED ? 16 * 16 + 16 : 1];  // block centres [k][block], radii
@@ -802,15 +1027,20 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
 
   float xi[DK];
 #pragma unroll
-  for (int k = 0; k < DK; ++k) xi[k] = (k < d) ? a.nodes[cell * d + k] : 0.f;
+  for (int k = 0; k < DK; ++k) xi[k] = uniform_f((k < d) ? a.nodes[cell * d + k] : 0.f);
 
   const int rayw = chunk * RW + wave * (C * 32);
   bf16x8 ub[C][KQ];
+  bool unit = true;  // |u| = 1 up to rounding (the scan-order bounds need it)
 #pragma unroll
   for (int cb = 0; cb < C; ++cb) {
     const int ray = rayw + cb * 32 + (lane & 31);
     float u[DKP];
     cell_dir<DKP>(GEN ? nullptr : a.dirs, a.seed, cell, R, ray, d, u);
+    float uu = 0.f;
+#pragma unroll
+    for (int k = 0; k < DKP; ++k) uu = __builtin_fmaf(u[k], u[k], uu);
+    unit = unit && uu <= 1.f + 0x1p-14f;
     __bf16 uh[DKP], ul[DKP];
 #pragma unroll
     for (int k = 0; k < DKP; ++k) split_bf16(u[k], uh[k], ul[k]);
@@ -830,6 +1060,8 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
     }
   }
 
+  const bool prune = SORTED ? __syncthreads_and(unit) != 0 : true;
+
   float best[C], second[C];
   int bidx[C];
 #pragma unroll
@@ -847,8 +1079,12 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
   // d <= 10) cost more than the skipped blocks save (d=10 mixture: 260 ->
   // 546 ms with them).
   constexpr bool CEN = false;
-  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN>(
-      a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, ctab, nullptr, nb0, n_scan, rayw,
+  // The window test of the walk: with four column blocks its registers cost
+  // a wave per SIMD (3 instead of 4) and the d=10 mixture scan 25 %.
+  constexpr bool WIN = SORTED && C <= 2;
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, WIN>(
+      a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, reinterpret_cast<uint32_t *>(bnd + NB / 32 + 2 * WAVES),
+      ctab, nullptr, nb0, n_scan, rayw, prune,
       [&](const float (&rt)[DK]) {
         __bf16 rh[DKP], rl[DKP];
 #pragma unroll
@@ -879,7 +1115,29 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
         }
         return ran;
       },
-      [](const float (&)[DK], int) {}, [](int) { return f32x16{}; });
+      [](const float (&)[DK], int) {}, [](int) { return f32x16{}; },
+      [&](int cb, const float (&cp)[DK]) {
+        // u.c' for the window's 32 inverted ball centres, split as the nodes
+        __bf16 ch[DKP], cl[DKP];
+#pragma unroll
+        for (int k = 0; k < DKP; ++k) split_bf16(cp[k], ch[k], cl[k]);
+        bf16x8 A[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int kk = 16 * q + 8 * h + e;
+              v[h] = kk < DKP ? ch[kk % DKP]
+                              : (kk < 2 * DKP ? ch[kk % DKP] : (kk < 3 * DKP ? cl[kk % DKP] : (__bf16)0.f));
+            }
+            A[q][e] = (lane & 32) ? v[1] : v[0];
+          }
+        }
+        return scan_block_bf16<KQ>(A, ub[cb]);
+      });
   count_blocks(a, blocks, lane);
   cell_finish<C, DK, NT, GEN>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
 }
@@ -889,7 +1147,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
     CellScanArgs a) {
   __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
   __shared__ float red[WAVES * 64];
-  __shared__ float bnd[WAVES * 2 + WAVES * 2];  // block bounds, chunk thresholds
+  __shared__ float bnd[WAVES * 2 + WAVES * 2 + WAVES * 2];  // block bounds, chunk thresholds, window masks
   __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);

@@ -85,7 +85,7 @@ struct CellScanArgs {
   const float *xs;
   const int32_t *perm;
   const int32_t *rank;
-  const float *aabb;  // per kOrderGroup nodes of xs: d minima, then d maxima
+  const float *aabb;  // per kOrderGroup nodes of xs: boxes, then balls (order_box_floats)
 };
 
 // One cloud of a persistent batch: its scan arguments and the first global
@@ -164,16 +164,22 @@ struct BackwardArgs {
 };
 
 // Scan order of the nodes (vg_order.hip): sort keys needed for n nodes (a
-// power of two >= n), and the pass that fills perm, rank, xs and the
-// bounding boxes of each kOrderGroup consecutive nodes of xs (aabb,
-// ceil(n / kOrderGroup) x 2d floats).
+// power of two >= n), and the pass that fills perm, rank, xs and, per group
+// of kOrderGroup consecutive nodes of xs, the bounding box and a bounding
+// ball (aabb: G = ceil(n / kOrderGroup) boxes of 2d floats, d minima then d
+// maxima, followed by G balls of d + 1 floats, the centre then a radius that
+// holds every node of the group; order_box_floats floats in all).
 constexpr int kOrderGroup = 128;
+__host__ __device__ inline int64_t order_groups(int64_t n) { return (n + kOrderGroup - 1) / kOrderGroup; }
+__host__ __device__ inline int64_t order_box_floats(int64_t n, int d) { return order_groups(n) * (3 * (int64_t)d + 1); }
 // Whether a Monte-Carlo scan of dimension d runs in scan order: the flags
-// decide, else d <= 10 (measured on uniform clouds at 256 rays per cell: from
-// d = 12 on nearly every block is evaluated and the bookkeeping only costs).
-inline bool scan_order(int d, uint32_t flags) {
+// decide, else d <= 12 for FP32 and d <= 10 for BF16x3 (measured on uniform
+// clouds at 256 rays per cell: beyond, nearly every block is evaluated and
+// the order's bookkeeping costs more than it saves; FP32 d=12: 272 ms in scan
+// order against 331 ms, d=16: 496 against 439; BF16x3 d=12: 158 against 139).
+inline bool scan_order(int d, uint32_t flags, bool bf16) {
   if (flags & VG_INDEX_ORDER) return false;
-  return (flags & VG_SCAN_ORDER) || d <= 10;
+  return (flags & VG_SCAN_ORDER) || d <= (bf16 ? 10 : 12);
 }
 int64_t node_order_keys(int64_t n);
 hipError_t launch_node_order(const float *nodes, int64_t n, int d, uint64_t *keys, int32_t *perm, int32_t *rank,

@@ -106,7 +106,7 @@ def test_tuner_cache_file_format(vg, batch, tmp_path, monkeypatch):
         assert len(r) == 7
         kp, log2n, R, bf16, order, shape = map(int, r[:6])
         assert 1 <= kp <= 8 and log2n >= 0 and 1 <= R <= 4096 and bf16 == 0 and 0 <= shape <= 2
-        assert order == (1 if kp <= 5 else 0)  # scan order for d <= 10 by default
+        assert order == (1 if kp <= 6 else 0)  # FP32: scan order for d <= 12 by default
         assert float(r[6]) > 0
     mtime = path.stat().st_mtime_ns
     _run(vg, batch[:3])

@@ -129,7 +129,7 @@ def test_scan_order_estimators_equal(vg, precision):
 
 
 def test_scan_order_batched(vg, tmp_path, monkeypatch):
-    """The batched call sorts each cloud of d <= 10 in its graph; forced
+    """The batched call sorts each cloud of d <= 12 (FP32) in its graph; forced
     index order gives the same bits."""
     monkeypatch.setenv("VG_TUNE_CACHE", str(tmp_path / "tune.txt"))
     dev = torch.device("cuda", 0)
@@ -159,3 +159,23 @@ def test_order_flags_exclude_each_other(vg):
     assert rc == -1  # VG_EINVAL
     with pytest.raises(ValueError):
         vg.raycast_cells(X, seed=1, rays_per_cell=8, order="morton")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_scan_order_non_unit_directions(vg, precision):
+    """The skip bounds hold for unit directions only: a workgroup holding a
+    longer direction skips nothing, so scan order still gives the
+    index-order bits, both when every ray is scaled and when one is."""
+    dev = torch.device("cuda", 0)
+    d, n, R = 5, 3000, 64
+    X = W.uniform_cloud(n, d, seed=77)
+    D = W.mc_directions(range(n), R, d, seed=78)
+    nodes = torch.from_numpy(X).to(dev)
+    for scale in ("all", "one"):
+        Dm = D.copy()
+        if scale == "all":
+            Dm *= np.float32(3.0)
+        else:
+            Dm[17, 5] *= np.float32(1.5)
+        a, b = _both(vg, nodes, torch.from_numpy(Dm).to(dev), precision=precision)
+        _assert_same(a, b)
