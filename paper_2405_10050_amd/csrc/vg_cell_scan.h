@@ -181,10 +181,13 @@ struct ChunkWalk {
 // Cross-lane reductions of non-negative floats (+inf allowed), on their bit
 // patterns, which order like the values: DPP within each row of 16 lanes
 // (quad permutes, half-row and row mirrors), then the four rows by readlane
-// and scalar min/max.  A NaN pattern sorts above +inf.
+// and scalar min/max.  A NaN pattern sorts above +inf.  Every source lane of
+// these patterns lies in the row, so the move needs no old value: with
+// bound_ctrl the compiler folds it into the min / max / add that uses it
+// (v_max_u32_dpp and the like, one instruction per step instead of two).
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
 }
 __device__ __forceinline__ uint32_t row_umin(uint32_t v) {
   v = min(v, dpp<0xb1>(v));      // quad_perm [1,0,3,2]

@@ -46,10 +46,14 @@ __global__ void cloud_box_init_kernel(int d, uint32_t *__restrict__ box) {
 }
 
 // Bounding box of the cloud: per coordinate, a grid-stride min / max over the
-// nodes (NaN ignored), a wave reduction, and one atomic per wave.
+// nodes (NaN ignored), reduced over the wave, then over the block's four
+// waves in LDS, and one atomic per block (a few dozen blocks: the atomics on
+// the 2d words would otherwise queue behind each other).
+constexpr int kBoxBlocks = 64;
 __global__ __launch_bounds__(256) void cloud_box_kernel(const float *__restrict__ nodes, int64_t n, int d,
                                                         uint32_t *__restrict__ box) {
-  const int lane = threadIdx.x & 63;
+  __shared__ float red[2][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = 0; k < d; ++k) {
     float lo = __builtin_inff(), hi = -__builtin_inff();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -62,9 +66,17 @@ __global__ __launch_bounds__(256) void cloud_box_kernel(const float *__restrict_
       hi = fmaxf(hi, __shfl_xor(hi, off));
     }
     if (lane == 0) {
+      red[0][wave] = lo;
+      red[1][wave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      lo = fminf(fminf(red[0][0], red[0][1]), fminf(red[0][2], red[0][3]));
+      hi = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
       atomicMin(box + k, float_key(lo));
       atomicMax(box + d + k, float_key(hi));
     }
+    __syncthreads();
   }
 }
 
@@ -224,7 +236,8 @@ hipError_t launch_node_order(const float *nodes, int64_t n, int d, uint64_t *key
   // for n >= 1) until order_boxes_kernel overwrites them.
   uint32_t *box = reinterpret_cast<uint32_t *>(aabb);
   hipLaunchKernelGGL(cloud_box_init_kernel, dim3(1), dim3(64), 0, s, d, box);
-  hipLaunchKernelGGL(cloud_box_kernel, dim3(std::min(grid_for(n, 256), 1024)), dim3(256), 0, s, nodes, n, d, box);
+  hipLaunchKernelGGL(cloud_box_kernel, dim3(std::min(grid_for(n, 256), kBoxBlocks)), dim3(256), 0, s, nodes, n, d,
+                     box);
   hipLaunchKernelGGL(order_keys_kernel, dim3(grid_for(p2, 256)), dim3(256), 0, s, nodes, n, d, p2,
                      static_cast<const uint32_t *>(box), keys);
   const int spans = (int)(p2 / kSortSpan);
