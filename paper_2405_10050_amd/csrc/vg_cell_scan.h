@@ -356,6 +356,17 @@ __device__ __forceinline__ float chunk_bound_thread(const CellScanArgs &a, const
 // this many chunks (else evaluated one by one as the walk reaches them).
 constexpr int kChunkTable = 2048;
 
+// A chunk's table entry: its bound's bit pattern with the low 11 bits
+// replaced by the chunk index (< kChunkTable), so that the entries sort like
+// the bounds; key_bound rounds the bound back up to the end of its bucket
+// (at most 2^-12 relative above the bound: still a bound).
+__device__ __forceinline__ uint32_t chunk_key(float b, int c) {
+  return (__float_as_uint(b) & ~(uint32_t)(kChunkTable - 1)) | (uint32_t)c;
+}
+__device__ __forceinline__ float key_bound(uint32_t key) {
+  return __uint_as_float(min((key | (uint32_t)(kChunkTable - 1)) + 1u, 0x7f800000u));
+}
+
 // The loop over the chunks of NB nodes shared by the FP32 and BF16x3 scans.
 // stage(rt) stores the calling thread's inverted node into the LDS tile;
 // block(nb, blk16, skip) runs the column blocks cb of node block nb for
@@ -431,14 +442,59 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
     const int c0 = (int)(self / NB);
     const int nch = (int)((n + NB - 1) / NB);
     ChunkWalk walk(c0, nch);
-    // every chunk's bound up front (they depend on x_i only): the walk then
-    // skips chunks on LDS reads instead of a chain of dependent box loads
+    // Every chunk's bound up front (they depend on x_i only), sorted from the
+    // largest down: the walk then takes the chunks most likely to hold the
+    // rays' winners first, so the thresholds rise sooner, and it ends at the
+    // first chunk whose bound is below the workgroup's threshold (all later
+    // ones are below it too).  Clouds of more chunks than the table holds
+    // walk outwards from x_i's chunk in scan order instead, with each bound
+    // computed as the walk reaches it.  The order decides only the speed.
     const bool table = nch <= kChunkTable;
+    uint32_t *ckey = reinterpret_cast<uint32_t *>(ctab);
     if (table) {
-      for (int c = tid; c < nch; c += WAVES * 64) ctab[c] = chunk_bound_thread<NB, DK>(a, xi, c);
+      int p2 = 2;
+      while (p2 < nch) p2 <<= 1;
+      for (int c = tid; c < p2; c += WAVES * 64)
+        ckey[c] = c < nch ? chunk_key(chunk_bound_thread<NB, DK>(a, xi, c), c) : 0u;  // 0: after every chunk
       __syncthreads();  // uniform: table depends on n only
+      // bitonic sort, descending
+      for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int t = tid; t < p2 / 2; t += WAVES * 64) {
+            const int i = 2 * t - (t & (j - 1));
+            const uint32_t x = ckey[i], y = ckey[i + j];
+            if ((x < y) == ((i & k) == 0)) {
+              ckey[i] = y;
+              ckey[i + j] = x;
+            }
+          }
+          __syncthreads();
+        }
+      }
     }
-    auto cbound = [&](int c) { return table ? ctab[c] : chunk_bound<NB, DK>(a, xi, c, lane); };
+    int spos = 0;  // table: next position in the sorted keys
+    // the walk's next chunk other than x_i's own (-1: none left) and its bound
+    auto next_chunk = [&](float &bnd) -> int {
+      if (table) {
+        while (spos < nch) {
+          const uint32_t key = ckey[spos++];
+          const int c = (int)(key & (uint32_t)(kChunkTable - 1));
+          if (c == c0) continue;
+          bnd = key_bound(key);
+          return c;
+        }
+        return -1;
+      }
+      const int c = walk.next();
+      if (c >= 0) bnd = chunk_bound<NB, DK>(a, xi, c, lane);
+      return c;
+    };
+    auto walk_done = [&]() { return table ? spos >= nch : walk.done(); };
+    // a chunk's bound fell below the threshold: in the sorted walk so does
+    // every later one
+    auto below = [&]() {
+      if (table) spos = nch;
+    };
     // per column block, the value a ray's bound must reach: its merged second
     // best; +inf on lanes of padding rays (ray >= R, zero direction), which
     // constrain nothing; 0 without prune (no bound is below it)
@@ -452,6 +508,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
     const float *ball = a.aabb + order_groups(n) * 2 * d;
     uint32_t wq = 0u;       // window slots not yet visited
     int slot_chunk = -1;    // lane s < WS: the chunk of window slot s
+    float slot_bnd = 0.f;   // and its bound
     uint32_t gneed[C];      // bit j: window group j reaches some ray of cb
     int wpar = 0;
     // backoff of the window test: after a test that rejects fewer than an
@@ -466,11 +523,21 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       int cnt = 0, my_chunk = -1;  // row j = lane % 32 is group j % GPC of slot j / GPC
       slot_chunk = -1;
       while (cnt < WS) {
-        const int c = walk.next();
+        float b;
+        const int c = next_chunk(b);
         if (c < 0) break;
-        if (cbound(c) < thr_now) continue;
+        if (b < thr_now) {
+          if (table) {
+            below();
+            break;
+          }
+          continue;
+        }
         if ((lane & 31) / GPC == cnt) my_chunk = c;
-        if (lane == cnt) slot_chunk = c;
+        if (lane == cnt) {
+          slot_chunk = c;
+          slot_bnd = b;
+        }
         ++cnt;
       }
       if (cnt == 0) return 0u;
@@ -577,7 +644,13 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
           const int sl = __builtin_ctz(wq);
           wq &= wq - 1u;
           const int c = __builtin_amdgcn_readlane(slot_chunk, sl);
-          if (cbound(c) < thr) continue;
+          if (__int_as_float(__builtin_amdgcn_readlane(__float_as_int(slot_bnd), sl)) < thr) {
+            if (table) {  // the later slots and chunks are below thr too
+              wq = 0u;
+              below();
+            }
+            continue;
+          }
           next = c;
 #pragma unroll
           for (int cb = 0; cb < C; ++cb) nxt_g[cb] = (gneed[cb] >> (sl * GPC)) & GMASK;
@@ -587,8 +660,16 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       if constexpr (WIN) {
         pop();
       } else {
-        next = walk.next();
-        while (next >= 0 && cbound(next) < thr) next = walk.next();
+        float b;
+        next = next_chunk(b);
+        while (next >= 0 && b < thr) {
+          if (table) {
+            below();
+            next = -1;
+            break;
+          }
+          next = next_chunk(b);
+        }
       }
       if (next >= 0) load_node<DK>(a.xs, n, d, (int64_t)next * NB + tid, pre);
       __syncthreads();  // the previous chunk is consumed
@@ -599,7 +680,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
         // window spent: the next windows are tested here, where rt is dead
         // (the test's registers do not add to it)
         if (next < 0) {
-          while (next < 0 && !walk.done()) {
+          while (next < 0 && !walk_done()) {
             wq = refill(thr);
             pop();
           }
@@ -966,7 +1047,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 // the epilogue).
 // SORTED: the nodes are in scan order (a.xs, a.perm, a.rank, a.aabb).
 template <int KP, int C, int WAVES, bool GEN, bool SORTED>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void cell_scan_fp32_kernel(
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVES == 4 && KP <= 6 ? 5 : 2))) void cell_scan_fp32_kernel(
     CellScanArgs a) {
   // tile, NB / 32 block bounds, 2 x WAVES chunk thresholds, 2 x WAVES window masks
   __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2 + WAVES * 2];
