@@ -255,30 +255,40 @@ __device__ __forceinline__ float row_fsum(float v) {
   return v + __uint_as_float(dpp<0x140>(__float_as_uint(v)));
 }
 
-// Centre and radius of the caller's 32-node block in inverted coordinates:
-// c = the mean of the 32 rows (any point would do; the mean keeps the radius
-// small), rho = max |r~ - c| over the block, times 1 + 2^-12 for its
-// rounding.  The block's first lane hands c to put(c, block) (which stores
-// it as the scan's operand) and its last lane stores rho + 2^-11 B into
-// rho[block] (B the block's
-// magnitude bound, which covers the rounding of the dot products with c and
-// with the nodes): then, for any ray, no computed u.r~ of the block exceeds
-// the computed u.c plus rho[block].
-template <int DK, class Put>
+// Centre and radius of the caller's part of a 32-node block in inverted
+// coordinates: the 16-node half-block of its DPP row (HALF) or the whole
+// block.  c = the mean of the part's rows (any point would do; the mean
+// keeps the radius small), rho = max |r~ - c| over the part, times
+// 1 + 2^-12 for its rounding.  The part's first lane hands c to
+// put(c, part) (which stores it as the scan's operand) and its last lane
+// stores rho + 2^-11 B into rho[part], where B is the magnitude bound that
+// lane holds from block_bound (its row's or its block's, both bounds on the
+// part's |r~| and so on |c|), which covers the rounding of the dot products
+// with c and with the nodes: then, for any ray, no computed u.r~ of the part
+// exceeds the computed u.c plus rho[part].  Halves bound a block more
+// tightly but need twice the rows in the centre product: used where they
+// fit in the 16 rows one result register pair per lane covers (chunks of at
+// most 256 nodes).
+template <int DK, bool HALF, class Put>
 __device__ __forceinline__ void block_centre(const float (&rt)[DK], float bb, float *rho, int d, int tid,
                                              Put &&put) {
-  const int lane = tid & 63, blk = tid >> 5;
+  const int lane = tid & 63;
+  constexpr int PART = HALF ? 16 : 32;
+  const int part = tid / PART;
   float c[DK];
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
     float v = 0.f;
     if (k < d) {
       v = row_fsum(rt[k]);
-      // rows 1 and 3 add rows 0 and 2 (row_bcast15; rows 0 and 2 add 0)
-      v += __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, (int)__float_as_uint(v), 0x142, 0xa, 0xf, false));
-      const float s0 = __uint_as_float(lane_u(__float_as_uint(v), 31));
-      const float s1 = __uint_as_float(lane_u(__float_as_uint(v), 63));
-      v = (lane < 32 ? s0 : s1) * (1.f / 32.f);
+      if constexpr (!HALF) {
+        // rows 1 and 3 add rows 0 and 2 (row_bcast15; rows 0 and 2 add 0)
+        v += __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, (int)__float_as_uint(v), 0x142, 0xa, 0xf, false));
+        const float s0 = __uint_as_float(lane_u(__float_as_uint(v), 31));
+        const float s1 = __uint_as_float(lane_u(__float_as_uint(v), 63));
+        v = lane < 32 ? s0 : s1;
+      }
+      v *= 1.f / PART;
     }
     c[k] = v;
   }
@@ -289,9 +299,18 @@ __device__ __forceinline__ void block_centre(const float (&rt)[DK], float bb, fl
     r2 = __builtin_fmaf(e, e, r2);
   }
   uint32_t r = row_umax(__float_as_uint(__builtin_sqrtf(r2) * (1.f + 0x1p-12f)));
-  r = max(r, (uint32_t)__builtin_amdgcn_update_dpp((int)r, (int)r, 0x142, 0xa, 0xf, false));
-  if ((tid & 31) == 0) put(c, blk);
-  if ((tid & 31) == 31) rho[blk] = __uint_as_float(r) + bb * 0x1p-11f;
+  if constexpr (!HALF) r = max(r, (uint32_t)__builtin_amdgcn_update_dpp((int)r, (int)r, 0x142, 0xa, 0xf, false));
+  if ((tid & (PART - 1)) == 0) put(c, part);
+  if ((tid & (PART - 1)) == PART - 1) rho[part] = __uint_as_float(r) + bb * 0x1p-11f;
+}
+
+// Bit b set when bit 2b or 2b + 1 of x is (half-blocks to blocks).
+__device__ __forceinline__ uint32_t pair_or(uint32_t x) {
+  x = (x | (x >> 1)) & 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  return (x | (x >> 8)) & 0x0000ffffu;
 }
 
 // Largest second-best value a ray holds: each lane keeps the top two of its
@@ -412,6 +431,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
                                            int64_t nb0, int64_t n_scan, int rayw, bool prune, Stage &&stage,
                                            Block &&block, Put &&put, Centres &&centres, Window &&window) {
   static_assert(NB / 32 <= 32, "block masks are 32 bits");
+  constexpr bool HALF = NB <= 256;  // centres per half-block (else per block)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = a.d;
   const int64_t n = a.n;
@@ -675,7 +695,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       __syncthreads();  // the previous chunk is consumed
       stage(rt);
       const float bb_own = block_bound<DK>(rt, bnd, tid);
-      if constexpr (CENTRES) block_centre<DK>(rt, bb_own, rho, d, tid, put);
+      if constexpr (CENTRES) block_centre<DK, HALF>(rt, bb_own, rho, d, tid, put);
       if constexpr (WIN) {
         // window spent: the next windows are tested here, where rt is dead
         // (the test's registers do not add to it)
@@ -720,11 +740,13 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
         }
         if constexpr (CENTRES) {
           if (prune) {
-            // rows 0..15 of the centre product: register i of lane half h
-            // holds row 8 (i / 4) + 4 h + i % 4
-            float eb[8];
+            // rows 0 .. NB/16 - 1 (half-blocks) or NB/32 - 1 (blocks) of the
+            // centre product: register i of lane half h holds row
+            // 8 (i / 4) + 4 h + i % 4
+            constexpr int NI = HALF ? NB / 32 : NB / 64;
+            float eb[NI];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) eb[i] = rho[8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)];
+            for (int i = 0; i < NI; ++i) eb[i] = rho[8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)];
             any = 0u;
 #pragma unroll
             for (int cb = 0; cb < C; ++cb) {
@@ -732,13 +754,13 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
               const f32x16 uc = centres(cb);
               uint32_t nd = 0;
 #pragma unroll
-              for (int i = 0; i < 8; ++i) {
+              for (int i = 0; i < NI; ++i) {
                 const uint64_t m = __ballot(!(uc[i] + eb[i] < ms[cb]));
                 const int row = 8 * (i >> 2) + (i & 3);
                 nd |= ((uint32_t)(m & 0xffffffffull) != 0u ? 1u : 0u) << row;
                 nd |= ((uint32_t)(m >> 32) != 0u ? 1u : 0u) << (row + 4);
               }
-              run[cb] &= nd;
+              run[cb] &= HALF ? pair_or(nd) : nd;
               any |= run[cb];
             }
           }
@@ -995,7 +1017,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   // block centres (scan order, d >= 3)
   constexpr bool CEN = SORTED && KP >= 2;
   const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, SORTED>(
-      a, cell, xi, best, second, nn2, bnd, wsm, wmask, ctab, cen + 16 * 16, nb0, n_scan, rayw, prune,
+      a, cell, xi, best, second, nn2, bnd, wsm, wmask, ctab, cen + 16 * 32, nb0, n_scan, rayw, prune,
       [&](const float (&rt)[DK]) {
 #pragma unroll
         for (int k = 0; k < DK; ++k) lds[k * LS + tid] = rt[k];
@@ -1014,16 +1036,18 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
         }
         return ran;
       },
-      [&](const float (&c)[DK], int blk) {
+      [&](const float (&c)[DK], int part) {
 #pragma unroll
-        for (int k = 0; k < DK; ++k) cen[k * 16 + blk] = c[k];
+        for (int k = 0; k < DK; ++k) cen[k * 32 + part] = c[k];
       },
       [&](int cb) {
-        // u.c for the chunk's block centres (rows 0..15; the rest zero)
+        // u.c for the chunk's half-block (chunks of at most 256 nodes) or
+        // block centres; the rows past them zero
+        constexpr int ROWS = NB <= 256 ? NB / 16 : NB / 32;
         float A[KP];
 #pragma unroll
         for (int kp = 0; kp < KP; ++kp)
-          A[kp] = (lane & 31) < 16 ? cen[(2 * kp + (lane >> 5)) * 16 + (lane & 31)] : 0.f;
+          A[kp] = (lane & 31) < ROWS ? cen[(2 * kp + (lane >> 5)) * 32 + (lane & 31)] : 0.f;
         return scan_block<KP>(A, ub[cb]);
       },
       [&](int cb, const float (&cp)[DK]) {
@@ -1053,7 +1077,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
   __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2 + WAVES * 2];
   __shared__ float red[WAVES * 64];
   __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
-  __shared__ float cen[SORTED ? 16 * 16 + 16 : 1];  // block centres [k][block], radii
+  __shared__ float cen[SORTED ? 16 * 32 + 32 : 1];  // centres [k][part] of (half-)blocks, radii
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
   scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, ctab, cen);
