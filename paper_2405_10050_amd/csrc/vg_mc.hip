@@ -331,10 +331,47 @@ __global__ __launch_bounds__(NT) void sample_points_kernel(const float *__restri
 }
 
 // ----------------------------------------------------------------- adjoint
+// Per-cell tables of the winners of a round of rays, shared by the adjoint
+// kernels: a cell's rays meet far fewer winners than there are rays (about
+// 180 per 1024 rays of the d=10 mixture), so their global atomics are first
+// combined per winner in LDS.  Rays go in rounds of kScatterRays; a round's
+// winners fill at most half of the open-addressing table, so a probe always
+// ends.
+constexpr int kScatterRays = 1024;
+constexpr int kScatterSlots = 2 * kScatterRays;
+constexpr int kScatterLog2 = 11;
+static_assert((1 << kScatterLog2) == kScatterSlots, "table size");
+
+// Slot of winner j (inserted if new; a new slot is appended to used).
+__device__ __forceinline__ int winner_slot(int32_t *key, int32_t *used, int *n_used, int32_t j) {
+  uint32_t h = ((uint32_t)j * 2654435761u) >> (32 - kScatterLog2);
+  for (;;) {
+    const int32_t old = atomicCAS(&key[h], -1, j);
+    if (old == -1) {
+      used[atomicAdd(n_used, 1)] = (int32_t)h;
+      return (int)h;
+    }
+    if (old == j) return (int)h;
+    h = (h + 1) & (kScatterSlots - 1);
+  }
+}
+
 template <int DK>
 __global__ __launch_bounds__(NT) void backward_rays_kernel(BackwardArgs a) {
   __shared__ float red[NT];
+  __shared__ int32_t key[kScatterSlots];  // winner of a slot, -1: free
+  __shared__ uint32_t wmax[kScatterSlots];  // largest |record| (float bits) per winner
+  __shared__ uint32_t wcnt[kScatterSlots];  // records per winner
+  __shared__ int32_t used[kScatterRays];
+  __shared__ int n_used;
   const int tid = threadIdx.x;
+  for (int sl = tid; sl < kScatterSlots; sl += NT) {
+    key[sl] = -1;
+    wmax[sl] = 0u;
+    wcnt[sl] = 0u;
+  }
+  if (tid == 0) n_used = 0;
+  __syncthreads();
   const int64_t cell = blockIdx.x;
   const int d = a.d, R = a.R;
   float xi[DK];
@@ -349,85 +386,104 @@ __global__ __launch_bounds__(NT) void backward_rays_kernel(BackwardArgs a) {
 #pragma unroll
   for (int k = 0; k < DK; ++k) own[k] = 0.f;
 
-  for (int kr = tid; kr < R; kr += NT) {
-    const int64_t gid = cell * R + kr;
-    const float l = a.t[gid];
-    const int32_t j = a.idx[gid];
-    const float ld1 = powi(l, d - 1);
-    const float ld = ld1 * l;
-    // upstream weight of the facet this ray contributes to
-    float ga = 0.f;
-    if (a.ga && fj) {
-      int lo = 0, hi = nf - 1;
-      while (lo <= hi) {  // facets sorted by j as signed int
-        const int mid = (lo + hi) >> 1;
-        const int32_t v = fj[mid];
-        if (v == j) {
-          ga = a.ga[cell * R + mid];
-          break;
-        }
-        if (v < j)
-          lo = mid + 1;
-        else
-          hi = mid - 1;
-      }
-    }
-    float dl = gv * a.sv * (float)d * ld1 + ge * a.se * (float)(d + 2) * ld * l;
-    float win[DK];
-#pragma unroll
-    for (int k = 0; k < DK; ++k) win[k] = 0.f;
-    if (j >= 0) {
-      const float *xj = a.nodes + (int64_t)j * d;
-      float D[DK], n2 = 0.f;
-#pragma unroll
-      for (int k = 0; k < DK; ++k) {
-        D[k] = (k < d) ? xj[k] - xi[k] : 0.f;
-        n2 = __builtin_fmaf(D[k], D[k], n2);
-      }
-      const float nD = sqrtf(n2);
-      dl += ga * a.sa * 2.f * (float)d * ld1 / nD;
-      const float c = dl * 2.f * l / n2;             // dl * dt/dD scale
-      const float cw = -ga * a.sa * 2.f * ld / (n2 * nD);  // direct area term
-      float uk[DK];
-      cell_dir<DK>(a.dirs, a.seed, cell, R, kr, d, uk);
-#pragma unroll
-      for (int k = 0; k < DK; ++k) {
-        win[k] = c * (D[k] - l * uk[k]) + cw * D[k];
-        own[k] -= win[k];
-      }
-    } else if (j <= -2) {
-      const int face = -2 - j, kk = face >> 1;
-      float xk = 0.f;
-#pragma unroll
-      for (int q = 0; q < DK; ++q)
-        if (q == kk) xk = xi[q];
-      float ud[DK];
-      cell_dir<DK>(a.dirs, a.seed, cell, R, kr, d, ud);
-      float uk = 0.f;
-#pragma unroll
-      for (int q = 0; q < DK; ++q)
-        if (q == kk) uk = ud[q];
-      const float h = (face & 1) ? 1.f - xk : xk;
-      dl += ga * a.sa * (float)d * ld1 / h;
-      const float gk = dl * (-1.f / uk) + ga * a.sa * ld / (h * h) * ((face & 1) ? 1.f : -1.f);
-#pragma unroll
-      for (int q = 0; q < DK; ++q)
-        if (q == kk) own[q] += gk;
-    }
-    // record the contribution aimed at the winner
-    a.rec_j[gid] = j >= 0 ? j : -1;
-    if (j >= 0) {
-      float m = 0.f;
-#pragma unroll
-      for (int k = 0; k < DK; ++k) {
-        if (k < d) {
-          a.rec[gid * d + k] = win[k];
-          m = fmaxf(m, fabsf(win[k]));
+  for (int r0 = 0; r0 < R; r0 += kScatterRays) {
+    const int r1 = min(R, r0 + kScatterRays);
+    for (int kr = r0 + tid; kr < r1; kr += NT) {
+      const int64_t gid = cell * R + kr;
+      const float l = a.t[gid];
+      const int32_t j = a.idx[gid];
+      const float ld1 = powi(l, d - 1);
+      const float ld = ld1 * l;
+      // upstream weight of the facet this ray contributes to
+      float ga = 0.f;
+      if (a.ga && fj) {
+        int lo = 0, hi = nf - 1;
+        while (lo <= hi) {  // facets sorted by j as signed int
+          const int mid = (lo + hi) >> 1;
+          const int32_t v = fj[mid];
+          if (v == j) {
+            ga = a.ga[cell * R + mid];
+            break;
+          }
+          if (v < j)
+            lo = mid + 1;
+          else
+            hi = mid - 1;
         }
       }
-      atomicMax(&a.maxabs[j], __float_as_uint(m));
-      atomicAdd(&a.count[j], 1u);
+      float dl = gv * a.sv * (float)d * ld1 + ge * a.se * (float)(d + 2) * ld * l;
+      float win[DK];
+#pragma unroll
+      for (int k = 0; k < DK; ++k) win[k] = 0.f;
+      if (j >= 0) {
+        const float *xj = a.nodes + (int64_t)j * d;
+        float D[DK], n2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+          D[k] = (k < d) ? xj[k] - xi[k] : 0.f;
+          n2 = __builtin_fmaf(D[k], D[k], n2);
+        }
+        const float nD = sqrtf(n2);
+        dl += ga * a.sa * 2.f * (float)d * ld1 / nD;
+        const float c = dl * 2.f * l / n2;             // dl * dt/dD scale
+        const float cw = -ga * a.sa * 2.f * ld / (n2 * nD);  // direct area term
+        float uk[DK];
+        cell_dir<DK>(a.dirs, a.seed, cell, R, kr, d, uk);
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+          win[k] = c * (D[k] - l * uk[k]) + cw * D[k];
+          own[k] -= win[k];
+        }
+      } else if (j <= -2) {
+        const int face = -2 - j, kk = face >> 1;
+        float xk = 0.f;
+#pragma unroll
+        for (int q = 0; q < DK; ++q)
+          if (q == kk) xk = xi[q];
+        float ud[DK];
+        cell_dir<DK>(a.dirs, a.seed, cell, R, kr, d, ud);
+        float uk = 0.f;
+#pragma unroll
+        for (int q = 0; q < DK; ++q)
+          if (q == kk) uk = ud[q];
+        const float h = (face & 1) ? 1.f - xk : xk;
+        dl += ga * a.sa * (float)d * ld1 / h;
+        const float gk = dl * (-1.f / uk) + ga * a.sa * ld / (h * h) * ((face & 1) ? 1.f : -1.f);
+#pragma unroll
+        for (int q = 0; q < DK; ++q)
+          if (q == kk) own[q] += gk;
+      }
+      // record the contribution aimed at the winner
+      a.rec_j[gid] = j >= 0 ? j : -1;
+      if (j >= 0) {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+          if (k < d) {
+            a.rec[gid * d + k] = win[k];
+            m = fmaxf(m, fabsf(win[k]));
+          }
+        }
+        // |record| >= 0, so its bits order like the value
+        const int sl = winner_slot(key, used, &n_used, j);
+        atomicMax(&wmax[sl], __float_as_uint(m));
+        atomicAdd(&wcnt[sl], 1u);
+      }
     }
+    __syncthreads();
+    // one global max and count per winner of the round (both exact in any order)
+    const int nu = n_used;
+    for (int e = tid; e < nu; e += NT) {
+      const int sl = used[e];
+      atomicMax(&a.maxabs[key[sl]], wmax[sl]);
+      atomicAdd(&a.count[key[sl]], wcnt[sl]);
+      key[sl] = -1;
+      wmax[sl] = 0u;
+      wcnt[sl] = 0u;
+    }
+    __syncthreads();
+    if (tid == 0) n_used = 0;
+    __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
@@ -450,16 +506,9 @@ __device__ __forceinline__ int fixed_scale(uint32_t maxbits, uint32_t count) {
 // Winner-side part of the adjoint, one workgroup per cell: the records of
 // the cell's rays are summed per winner j in LDS, as fixed-point int64 at
 // j's scale, then added to acc with one global atomic per (winner,
-// coordinate) instead of one per (ray, coordinate); a cell's rays meet far
-// fewer winners than there are rays (about 180 per 1024 rays of the d=10
-// mixture).  Integer addition is associative, so neither the LDS nor the
-// global order of the additions changes a bit of the result.  Rays go in
-// rounds of kScatterRays; the winners of a round fill at most half of the
-// open-addressing table, so a probe always ends.
-constexpr int kScatterRays = 1024;
-constexpr int kScatterSlots = 2 * kScatterRays;
-constexpr int kScatterLog2 = 11;
-static_assert((1 << kScatterLog2) == kScatterSlots, "table size");
+// coordinate) instead of one per (ray, coordinate).  Integer addition is
+// associative, so neither the LDS nor the global order of the additions
+// changes a bit of the result.
 
 template <int DK>
 __global__ __launch_bounds__(NT) void backward_scatter_kernel(BackwardArgs a) {
@@ -493,17 +542,7 @@ __global__ __launch_bounds__(NT) void backward_scatter_kernel(BackwardArgs a) {
       F[p] = fixed_scale(mb, a.count[j]);
 #pragma unroll
       for (int k = 0; k < DK; ++k) v[p][k] = k < d ? a.rec[gid * d + k] : 0.f;
-      uint32_t h = ((uint32_t)j * 2654435761u) >> (32 - kScatterLog2);
-      for (;;) {
-        const int32_t old = atomicCAS(&key[h], -1, j);
-        if (old == -1) {
-          used[atomicAdd(&n_used, 1)] = (int32_t)h;
-          break;
-        }
-        if (old == j) break;
-        h = (h + 1) & (kScatterSlots - 1);
-      }
-      slot[p] = (int)h;
+      slot[p] = winner_slot(key, used, &n_used, j);
     }
     __syncthreads();
     const int nu = n_used;
