@@ -255,62 +255,34 @@ __device__ __forceinline__ float row_fsum(float v) {
   return v + __uint_as_float(dpp<0x140>(__float_as_uint(v)));
 }
 
-// Centre and radius of the caller's part of a 32-node block in inverted
-// coordinates: the 16-node half-block of its DPP row (HALF) or the whole
-// block.  c = the mean of the part's rows (any point would do; the mean
-// keeps the radius small), rho = max |r~ - c| over the part, times
-// 1 + 2^-12 for its rounding.  The part's first lane hands c to
-// put(c, part) (which stores it as the scan's operand) and its last lane
-// stores rho + 2^-11 B into rho[part], where B is the magnitude bound that
-// lane holds from block_bound (its row's or its block's, both bounds on the
-// part's |r~| and so on |c|), which covers the rounding of the dot products
-// with c and with the nodes: then, for any ray, no computed u.r~ of the part
-// exceeds the computed u.c plus rho[part].  Halves bound a block more
-// tightly but need twice the rows in the centre product: used where they
-// fit in the 16 rows one result register pair per lane covers (chunks of at
-// most 256 nodes).
-template <int DK, bool HALF, class Put>
+// Centre and radius of the caller's 16-node half-block (its DPP row of 16
+// lanes) in inverted coordinates: c = the mean of the 16 rows (any point
+// would do; the mean keeps the radius small), rho = max |r~ - c| over the
+// half-block, times 1 + 2^-12 for its rounding.  The row's first lane hands
+// c to put(c, half) (which stores it as the scan's operand) and its last
+// lane stores rho + 2^-11 B into rho[half], where B is the magnitude bound
+// that lane holds from block_bound (its row's or its block's, both bounds
+// on the half-block's |r~| and so on |c|), which covers the rounding of the
+// dot products with c and with the nodes: then, for any ray, no computed
+// u.r~ of the half-block exceeds the computed u.c plus rho[half].  Two
+// halves bound a block more tightly than one centre, and their sums are the
+// row sums the reduction forms first.
+template <int DK, class Put>
 __device__ __forceinline__ void block_centre(const float (&rt)[DK], float bb, float *rho, int d, int tid,
                                              Put &&put) {
-  const int lane = tid & 63;
-  constexpr int PART = HALF ? 16 : 32;
-  const int part = tid / PART;
+  const int half = tid >> 4;
   float c[DK];
 #pragma unroll
-  for (int k = 0; k < DK; ++k) {
-    float v = 0.f;
-    if (k < d) {
-      v = row_fsum(rt[k]);
-      if constexpr (!HALF) {
-        // rows 1 and 3 add rows 0 and 2 (row_bcast15; rows 0 and 2 add 0)
-        v += __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, (int)__float_as_uint(v), 0x142, 0xa, 0xf, false));
-        const float s0 = __uint_as_float(lane_u(__float_as_uint(v), 31));
-        const float s1 = __uint_as_float(lane_u(__float_as_uint(v), 63));
-        v = lane < 32 ? s0 : s1;
-      }
-      v *= 1.f / PART;
-    }
-    c[k] = v;
-  }
+  for (int k = 0; k < DK; ++k) c[k] = k < d ? row_fsum(rt[k]) * (1.f / 16.f) : 0.f;
   float r2 = 0.f;
 #pragma unroll
   for (int k = 0; k < DK; ++k) {
     const float e = rt[k] - c[k];
     r2 = __builtin_fmaf(e, e, r2);
   }
-  uint32_t r = row_umax(__float_as_uint(__builtin_sqrtf(r2) * (1.f + 0x1p-12f)));
-  if constexpr (!HALF) r = max(r, (uint32_t)__builtin_amdgcn_update_dpp((int)r, (int)r, 0x142, 0xa, 0xf, false));
-  if ((tid & (PART - 1)) == 0) put(c, part);
-  if ((tid & (PART - 1)) == PART - 1) rho[part] = __uint_as_float(r) + bb * 0x1p-11f;
-}
-
-// Bit b set when bit 2b or 2b + 1 of x is (half-blocks to blocks).
-__device__ __forceinline__ uint32_t pair_or(uint32_t x) {
-  x = (x | (x >> 1)) & 0x55555555u;
-  x = (x | (x >> 1)) & 0x33333333u;
-  x = (x | (x >> 2)) & 0x0f0f0f0fu;
-  x = (x | (x >> 4)) & 0x00ff00ffu;
-  return (x | (x >> 8)) & 0x0000ffffu;
+  const uint32_t r = row_umax(__float_as_uint(__builtin_sqrtf(r2) * (1.f + 0x1p-12f)));
+  if ((tid & 15) == 0) put(c, half);
+  if ((tid & 15) == 15) rho[half] = __uint_as_float(r) + bb * 0x1p-11f;
 }
 
 // Largest second-best value a ray holds: each lane keeps the top two of its
@@ -431,7 +403,6 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
                                            int64_t nb0, int64_t n_scan, int rayw, bool prune, Stage &&stage,
                                            Block &&block, Put &&put, Centres &&centres, Window &&window) {
   static_assert(NB / 32 <= 32, "block masks are 32 bits");
-  constexpr bool HALF = NB <= 256;  // centres per half-block (else per block)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = a.d;
   const int64_t n = a.n;
@@ -695,7 +666,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       __syncthreads();  // the previous chunk is consumed
       stage(rt);
       const float bb_own = block_bound<DK>(rt, bnd, tid);
-      if constexpr (CENTRES) block_centre<DK, HALF>(rt, bb_own, rho, d, tid, put);
+      if constexpr (CENTRES) block_centre<DK>(rt, bb_own, rho, d, tid, put);
       if constexpr (WIN) {
         // window spent: the next windows are tested here, where rt is dead
         // (the test's registers do not add to it)
@@ -740,10 +711,12 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
         }
         if constexpr (CENTRES) {
           if (prune) {
-            // rows 0 .. NB/16 - 1 (half-blocks) or NB/32 - 1 (blocks) of the
-            // centre product: register i of lane half h holds row
-            // 8 (i / 4) + 4 h + i % 4
-            constexpr int NI = HALF ? NB / 32 : NB / 64;
+            // rows 0 .. NB/16 - 1 of the centre product, the chunk's
+            // half-blocks: register i of lane half h holds row
+            // 8 (i / 4) + 4 h + i % 4, so registers 2q and 2q + 1 hold the
+            // two halves of block 4 (q / 2) + 2 h + q % 2, whose bound is the
+            // larger of theirs
+            constexpr int NI = NB / 32;
             float eb[NI];
 #pragma unroll
             for (int i = 0; i < NI; ++i) eb[i] = rho[8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)];
@@ -754,13 +727,14 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
               const f32x16 uc = centres(cb);
               uint32_t nd = 0;
 #pragma unroll
-              for (int i = 0; i < NI; ++i) {
-                const uint64_t m = __ballot(!(uc[i] + eb[i] < ms[cb]));
-                const int row = 8 * (i >> 2) + (i & 3);
-                nd |= ((uint32_t)(m & 0xffffffffull) != 0u ? 1u : 0u) << row;
-                nd |= ((uint32_t)(m >> 32) != 0u ? 1u : 0u) << (row + 4);
+              for (int q = 0; q < NI / 2; ++q) {
+                const float bm = fmaxf(uc[2 * q] + eb[2 * q], uc[2 * q + 1] + eb[2 * q + 1]);
+                const uint64_t m = __ballot(!(bm < ms[cb]));
+                const int blk = 4 * (q >> 1) + (q & 1);
+                nd |= ((uint32_t)(m & 0xffffffffull) != 0u ? 1u : 0u) << blk;
+                nd |= ((uint32_t)(m >> 32) != 0u ? 1u : 0u) << (blk + 2);
               }
-              run[cb] &= HALF ? pair_or(nd) : nd;
+              run[cb] &= nd;
               any |= run[cb];
             }
           }
@@ -1041,9 +1015,8 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
         for (int k = 0; k < DK; ++k) cen[k * 32 + part] = c[k];
       },
       [&](int cb) {
-        // u.c for the chunk's half-block (chunks of at most 256 nodes) or
-        // block centres; the rows past them zero
-        constexpr int ROWS = NB <= 256 ? NB / 16 : NB / 32;
+        // u.c for the chunk's half-block centres; the rows past them zero
+        constexpr int ROWS = NB / 16;
         float A[KP];
 #pragma unroll
         for (int kp = 0; kp < KP; ++kp)
@@ -1071,7 +1044,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
 // the epilogue).
 // SORTED: the nodes are in scan order (a.xs, a.perm, a.rank, a.aabb).
 template <int KP, int C, int WAVES, bool GEN, bool SORTED>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVES == 4 && KP <= 6 ? 5 : 2))) void cell_scan_fp32_kernel(
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVES == 4 && KP <= 6 ? 5 : (WAVES == 8 && KP <= 5 ? 4 : 2)))) void cell_scan_fp32_kernel(
     CellScanArgs a) {
   // tile, NB / 32 block bounds, 2 x WAVES chunk thresholds, 2 x WAVES window masks
   __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2 + WAVES * 2];
