@@ -904,8 +904,9 @@ __device__ __forceinline__ f32x16 scan_block(const float (&A)[KP], const float (
 }
 
 // One work item of the FP32 scan: rays [chunk*RW, chunk*RW + RW) of `cell`.
-// lds holds Fp32Tile<KP, WAVES>::FLOATS floats, NB/32 block bounds and
-// 2 x WAVES chunk thresholds, red WAVES*64 floats.  One
+// lds holds Fp32Tile<KP, WAVES>::FLOATS floats, NB/32 block bounds,
+// 2 x WAVES chunk thresholds and 2 x WAVES window masks, red WAVES*64
+// floats, ctab the sorted chunk keys, cen the half-block centres.  One
 // accumulator set per wave is reused by the column blocks in turn: separate
 // sets would cost the occupancy that hides each block's epilogue.
 template <int KP, int C, int WAVES, bool GEN, bool SORTED>
@@ -1049,7 +1050,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
   // tile, NB / 32 block bounds, 2 x WAVES chunk thresholds, 2 x WAVES window masks
   __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2 + WAVES * 2];
   __shared__ float red[WAVES * 64];
-  __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
+  __shared__ float ctab[SORTED ? kChunkTable : 1];  // the walk's chunk keys (chunk_key), sorted
   __shared__ float cen[SORTED ? 16 * 32 + 32 : 1];  // centres [k][part] of (half-)blocks, radii
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
@@ -1087,7 +1088,8 @@ __device__ __forceinline__ f32x16 scan_block_bf16(const bf16x8 (&A)[KQ], const b
 }
 
 // One work item of the BF16x3 scan; lds holds WAVES*64 * KT/8 bf16x8, bnd
-// the NB/32 block bounds and 2 x WAVES chunk thresholds.
+// the NB/32 block bounds, 2 x WAVES chunk thresholds and 2 x WAVES window
+// masks, ctab the walk's sorted chunk keys.
 template <int KQ, int C, int WAVES, bool GEN, bool SORTED>
 __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t cell, int chunk,
                                                  bf16x8 *__restrict__ lds, float *red, float *bnd, float *ctab) {
@@ -1229,7 +1231,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
   __shared__ float red[WAVES * 64];
   __shared__ float bnd[WAVES * 2 + WAVES * 2 + WAVES * 2];  // block bounds, chunk thresholds, window masks
-  __shared__ float ctab[SORTED ? kChunkTable : 1];  // chunk bounds of the walk
+  __shared__ float ctab[SORTED ? kChunkTable : 1];  // the walk's chunk keys (chunk_key), sorted
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
   scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd, ctab);
