@@ -195,3 +195,29 @@ def test_scan_order_beyond_the_chunk_table(vg, d, precision):
     a, b = _both(vg, X, precision=precision, seed=91, R=R)
     _assert_same(a, b)
     assert a[3]["scan_pairs"] < 0.2 * b[3]["scan_pairs"]
+
+
+def _random_configs(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        d = int(rng.integers(2, 17))
+        n = int(np.exp(rng.uniform(np.log(2), np.log(30000))))
+        R = int(rng.choice([1, 7, 33, 64, 100, 256, 512, 1024]))
+        R = max(1, min(R, int(1e7 // n)))
+        out.append((d, n, R, str(rng.choice(["uni", "gmm"])), str(rng.choice(["fp32", "bf16x3"])),
+                    int(rng.integers(1, 1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("d,n,R,kind,precision,seed", _random_configs(24, 2025))
+def test_scan_order_random_configurations(vg, d, n, R, kind, precision, seed):
+    """Seeded random shapes (d 2..16, N log-uniform up to 3e4, odd and even
+    ray counts, uniform and clustered clouds, both precisions): every skip is
+    exact, so scan order gives the index-order bits."""
+    print(f"random d={d} n={n} R={R} {kind} {precision}", flush=True)
+    dev = torch.device("cuda", 0)
+    X = W.gaussian_mixture_cloud(n=n, d=d, seed=seed % 1000) if (kind == "gmm" and n >= 16) \
+        else W.uniform_cloud(n, d, seed=seed % 1000)
+    a, b = _both(vg, torch.from_numpy(X).to(dev), precision=precision, seed=seed, R=R)
+    _assert_same(a, b)
