@@ -768,35 +768,40 @@ __device__ __forceinline__ void add_calls(unsigned int *block_calls, uint32_t ca
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_list_kernel(CellScanArgs a, GridView g, KnnList kl, DeferQueue dq,
                                                            unsigned long long *nn_calls) {
+  // once per workgroup: the grid strides over the rays (a check at the start
+  // of each of 2.5e5 short workgroups cost 1.7 ms of a 14.6 ms d=3 step)
   if (a.counters[CNT_BAD_NODES] != 0) return;  // see knn_kernel
   __shared__ unsigned int block_calls[2];
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
   uint32_t calls = 0, grid_calls = 0;
-  bool defer = false;
-  int32_t kdef = -1;
-  const bool live = gid < a.n * a.R;
-  // whether the wave's rays all belong to one cell (64 | R, or a cell boundary outside the wave)
-  const int cell0 = __builtin_amdgcn_readfirstlane((int)(gid / a.R));
-  const bool one_cell = __all(!live || gid / a.R == cell0);
-  if (live) {
-    if (one_cell)
-      defer = cast_ray<DK, false, 1, true>(a, g, kl, gid, -1, kdef, calls, grid_calls);
-    else
-      defer = cast_ray<DK, false>(a, g, kl, gid, -1, kdef, calls, grid_calls);
-  }
-  const unsigned long long mask = __ballot(defer);
-  if (mask) {
-    const int lane = (int)__lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(dq.count, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (defer) {
-      const uint32_t pos = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-      dq.gid[pos] = gid;
-      dq.k[pos] = kdef;
+  const int64_t total = a.n * a.R;
+  for (int64_t base = (int64_t)blockIdx.x * NT; base < total; base += (int64_t)gridDim.x * NT) {
+    const int64_t gid = base + threadIdx.x;
+    bool defer = false;
+    int32_t kdef = -1;
+    const bool live = gid < total;
+    // whether the wave's rays all belong to one cell (64 | R, or a cell boundary outside the wave)
+    const int cell0 = __builtin_amdgcn_readfirstlane((int)(gid / a.R));
+    const bool one_cell = __all(!live || gid / a.R == cell0);
+    if (live) {
+      if (one_cell)
+        defer = cast_ray<DK, false, 1, true>(a, g, kl, gid, -1, kdef, calls, grid_calls);
+      else
+        defer = cast_ray<DK, false>(a, g, kl, gid, -1, kdef, calls, grid_calls);
+    }
+    const unsigned long long mask = __ballot(defer);
+    if (mask) {
+      const int lane = (int)__lane_id();
+      const int leader = __ffsll((long long)mask) - 1;
+      uint32_t qbase = 0;
+      if (lane == leader) qbase = atomicAdd(dq.count, (uint32_t)__popcll(mask));
+      qbase = __shfl(qbase, leader);
+      if (defer) {
+        const uint32_t pos = qbase + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        dq.gid[pos] = gid;
+        dq.k[pos] = kdef;
+      }
     }
   }
   add_calls(block_calls, calls, grid_calls, nn_calls);
@@ -1022,20 +1027,28 @@ __device__ void incircle_ray(const RayScanArgs &a, const GridView &g, int heuris
 template <int DK>
 __global__ __launch_bounds__(NT) void incircle_rays_kernel(RayScanArgs a, GridView g, int heuristic,
                                                            unsigned long long *nn_calls) {
-  if (a.counters[CNT_BAD_NODES] != 0) return;  // see knn_kernel
+  if (a.counters[CNT_BAD_NODES] != 0) return;  // see knn_kernel; once per workgroup (grid-stride)
   __shared__ unsigned int block_calls[2];
   if (threadIdx.x < 2) block_calls[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t gt = (int64_t)blockIdx.x * NT + threadIdx.x;
-  const int64_t ray = gt / kRayLanes;
-  const int lane = (int)(gt % kRayLanes);
   uint32_t calls = 0;
-  if (ray < a.m) incircle_ray<DK, kRayLanes>(a, g, heuristic, ray, lane, calls);
-  if (lane != 0) calls = 0;
+  // kRayLanes divides NT, so a ray's lanes stay together in every step
+  const int64_t total = a.m * kRayLanes;
+  for (int64_t base = (int64_t)blockIdx.x * NT; base < total; base += (int64_t)gridDim.x * NT) {
+    const int64_t gt = base + threadIdx.x;
+    const int64_t ray = gt / kRayLanes;
+    const int lane = (int)(gt % kRayLanes);
+    uint32_t c = 0;
+    if (ray < a.m) incircle_ray<DK, kRayLanes>(a, g, heuristic, ray, lane, c);
+    if (lane == 0) calls += c;
+  }
   add_calls(block_calls, calls, calls, nn_calls);
 }
 
 unsigned blocks_of(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+// workgroups of the grid-stride ray kernels (several rounds of the chip's
+// resident workgroups, so the tails balance)
+constexpr unsigned kStrideBlocks = 8192;
 
 }  // namespace
 
@@ -1131,7 +1144,7 @@ hipError_t launch_incircle_rays(const RayScanArgs &a, void *scratch, int heurist
   GridView g;
   hipError_t e = build_grid(a.nodes, a.n, a.d, kRayRingBudget, cv, g, s);
   if (e != hipSuccess) return e;
-  const dim3 grid(blocks_of(a.m * kRayLanes)), blk(NT);
+  const dim3 grid(std::min(blocks_of(a.m * kRayLanes), kStrideBlocks)), blk(NT);
   if (a.d <= 2)
     hipLaunchKernelGGL(incircle_rays_kernel<2>, grid, blk, 0, s, a, g, heuristic, nn_calls);
   else if (a.d <= 3)
@@ -1164,7 +1177,7 @@ hipError_t launch_incircle_cells(const CellScanArgs &a, void *scratch, unsigned 
   dq.count = cv.take<uint32_t>(1);
   e = fill_u32(dq.count, 0u, 1, s);
   if (e != hipSuccess) return e;
-  const dim3 grid(blocks_of(rays)), blk(NT);
+  const dim3 grid(std::min(blocks_of(rays), kStrideBlocks)), blk(NT);
   // the grid pass strides over the queue, whose length only the device knows
   const dim3 grid2(std::min<unsigned>(blocks_of(rays * kRayLanes), 16384u));
 #define VG_INCIRCLE_LAUNCH(DKV)                                                                          \
