@@ -1092,7 +1092,8 @@ __device__ __forceinline__ f32x16 scan_block_bf16(const bf16x8 (&A)[KQ], const b
 // masks, ctab the walk's sorted chunk keys.
 template <int KQ, int C, int WAVES, bool GEN, bool SORTED>
 __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t cell, int chunk,
-                                                 bf16x8 *__restrict__ lds, float *red, float *bnd, float *ctab) {
+                                                 bf16x8 *__restrict__ lds, float *red, float *bnd, float *ctab,
+                                                 float *cen) {
   constexpr int NT = WAVES * 64;
   constexpr int NB = NT;
   constexpr int RW = WAVES * C * 32;
@@ -1157,17 +1158,19 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
 
   const int64_t nb0 = a.nbr ? a.nbr_off[cell] : 0;
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
-  // No block centres here: this scan is VALU-bound by its epilogue, and the
-  // centres' per-chunk work and registers (3 instead of 4 waves per SIMD at
-  // d <= 10) cost more than the skipped blocks save (d=10 mixture: 260 ->
-  // 546 ms with them).
-  constexpr bool CEN = false;
+  // Half-block centres (as in the FP32 scan) where four column blocks share
+  // a chunk's centre work: this scan is VALU-bound and its blocks are cheap,
+  // so with fewer rays per wave the per-chunk sums, splits and ballots cost
+  // more than the blocks they remove (uniform clouds at 256 rays per cell:
+  // 14 to 28 % slower with them; d=10 mixture at 1024 rays: 204 -> 184 ms),
+  // and beyond d=10 their registers cost a wave per SIMD.
+  constexpr bool CEN = SORTED && C == 4 && KQ <= 2;
   // The window test of the walk: with four column blocks its registers cost
   // a wave per SIMD (3 instead of 4) and the d=10 mixture scan 25 %.
   constexpr bool WIN = SORTED && C <= 2;
   const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, WIN>(
       a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, reinterpret_cast<uint32_t *>(bnd + NB / 32 + 2 * WAVES),
-      ctab, nullptr, nb0, n_scan, rayw, prune,
+      ctab, cen + 16 * 32, nb0, n_scan, rayw, prune,
       [&](const float (&rt)[DK]) {
         __bf16 rh[DKP], rl[DKP];
 #pragma unroll
@@ -1198,7 +1201,35 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
         }
         return ran;
       },
-      [](const float (&)[DK], int) {}, [](int) { return f32x16{}; },
+      [&](const float (&c)[DK], int part) {
+#pragma unroll
+        for (int k = 0; k < DK; ++k) cen[k * 32 + part] = c[k];
+      },
+      [&](int cb) {
+        // u.c for the chunk's half-block centres, split as the nodes; the
+        // rows past them zero
+        constexpr int ROWS = NB / 16;
+        const int row = lane & 31;
+        __bf16 ch[DKP], cl[DKP];
+#pragma unroll
+        for (int k = 0; k < DKP; ++k) split_bf16(row < ROWS ? cen[k * 32 + row] : 0.f, ch[k], cl[k]);
+        bf16x8 A[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int kk = 16 * q + 8 * h + e;
+              v[h] = kk < DKP ? ch[kk % DKP]
+                              : (kk < 2 * DKP ? ch[kk % DKP] : (kk < 3 * DKP ? cl[kk % DKP] : (__bf16)0.f));
+            }
+            A[q][e] = (lane & 32) ? v[1] : v[0];
+          }
+        }
+        return scan_block_bf16<KQ>(A, ub[cb]);
+      },
       [&](int cb, const float (&cp)[DK]) {
         // u.c' for the window's 32 inverted ball centres, split as the nodes
         __bf16 ch[DKP], cl[DKP];
@@ -1232,9 +1263,10 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ float red[WAVES * 64];
   __shared__ float bnd[WAVES * 2 + WAVES * 2 + WAVES * 2];  // block bounds, chunk thresholds, window masks
   __shared__ float ctab[SORTED ? kChunkTable : 1];  // the walk's chunk keys (chunk_key), sorted
+  __shared__ float cen[SORTED ? 16 * 32 + 32 : 1];  // half-block centres [k][half], radii
   const int64_t cell = blockIdx.x / a.wg_per_cell;
   const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
-  scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd, ctab);
+  scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd, ctab, cen);
 }
 
 template <int C, int WAVES, bool GEN, bool SORTED>
