@@ -1038,6 +1038,19 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   cell_finish<C, DK, NT, GEN>(a, xi, best, second, bidx, nn2, red, lane, rayw, cell, nb0, n_scan);
 }
 
+// Workgroup -> (cell, ray chunk).  A launch over a whole cloud in scan order
+// takes the cells in the order of the sorted copy (cell perm[p] at position
+// p): the workgroups resident at one time then scan nearby cells and share
+// the node chunks they load through L2.  Other launches (index order, or a
+// probe over the first cells of a cloud) take the cells in index order.
+template <bool SORTED>
+__device__ __forceinline__ int64_t item_cell(const CellScanArgs &a, int &chunk) {
+  const int64_t pos = blockIdx.x / a.wg_per_cell;
+  chunk = (int)(blockIdx.x - pos * a.wg_per_cell);
+  if (SORTED && (int64_t)gridDim.x == a.n * a.wg_per_cell) return a.perm[pos];
+  return pos;
+}
+
 // GEN: the directions are drawn from a.seed (a.dirs is null), else read.
 // At least two waves per SIMD: with a budget of 256 registers the compiler
 // keeps the MFMA accumulators in ordinary VGPRs (with the four-wave shapes it
@@ -1052,8 +1065,8 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
   __shared__ float red[WAVES * 64];
   __shared__ float ctab[SORTED ? kChunkTable : 1];  // the walk's chunk keys (chunk_key), sorted
   __shared__ float cen[SORTED ? 16 * 32 + 32 : 1];  // centres [k][part] of (half-)blocks, radii
-  const int64_t cell = blockIdx.x / a.wg_per_cell;
-  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  int chunk;
+  const int64_t cell = item_cell<SORTED>(a, chunk);
   scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, ctab, cen);
 }
 
@@ -1264,8 +1277,8 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ float bnd[WAVES * 2 + WAVES * 2 + WAVES * 2];  // block bounds, chunk thresholds, window masks
   __shared__ float ctab[SORTED ? kChunkTable : 1];  // the walk's chunk keys (chunk_key), sorted
   __shared__ float cen[SORTED ? 16 * 32 + 32 : 1];  // half-block centres [k][half], radii
-  const int64_t cell = blockIdx.x / a.wg_per_cell;
-  const int chunk = blockIdx.x - (int)(cell * a.wg_per_cell);
+  int chunk;
+  const int64_t cell = item_cell<SORTED>(a, chunk);
   scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd, ctab, cen);
 }
 
