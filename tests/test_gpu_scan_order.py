@@ -41,7 +41,10 @@ def _assert_same(a, b):
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("d,n,R,kind", [(2, 5000, 64, "uni"), (3, 20000, 256, "uni"), (3, 3001, 100, "gmm"),
                                         (4, 7777, 33, "uni"), (6, 9000, 256, "uni"), (8, 4000, 128, "gmm"),
-                                        (10, 6000, 1024, "gmm"), (12, 2500, 64, "uni"), (16, 1500, 96, "gmm")])
+                                        (10, 6000, 1024, "gmm"), (12, 2500, 64, "uni"), (16, 1500, 96, "gmm"),
+                                        # 512 rays per workgroup: four column blocks x four waves up to d=6
+                                        (3, 9000, 512, "uni"), (5, 6000, 400, "gmm"), (6, 5000, 512, "uni"),
+                                        (8, 3000, 512, "uni")])
 def test_scan_order_equals_index_order(vg, d, n, R, kind, precision):
     print(f"scan order d={d} n={n} R={R} {kind} {precision}", flush=True)
     dev = torch.device("cuda", 0)
