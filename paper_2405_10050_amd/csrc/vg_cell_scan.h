@@ -1327,6 +1327,9 @@ hipError_t launch_kp_g(const CellScanArgs &a, hipStream_t s, int grid) {
 // rule out, and each chunk's staging and bounds serve 128 rays per wave.
 // (Uniform clouds, N = 5e4: d=3 8.4 -> 6.1 ms, d=4 13.2 -> 9.8 ms, d=6
 // 38.3 -> 33.1 ms; from d = 8 on, where most chunks run, 2 to 4 % slower.)
+// Only while the cloud's 256-node chunks fit the chunk table: beyond it the
+// walk goes outward chunk by chunk, and halving the chunks doubles its length
+// (d=3, N=4e5, 256 rays in 128-node chunks: 37 -> 328 ms).
 template <bool GEN>
 hipError_t launch_kp_c4w4(const CellScanArgs &a, hipStream_t s, int grid) {
   dim3 blk(4 * 64);
@@ -1356,7 +1359,7 @@ hipError_t launch_cells_set(const CellScanArgs &a, bool bf16, int rw, int grid, 
     case 1024: return launch_kp_g<4, 8, GEN, SORTED>(a, s, grid);
     case 512:
       if constexpr (SORTED)
-        if (a.d <= 6) return launch_kp_c4w4<GEN>(a, s, grid);
+        if (a.d <= 6 && a.n <= (int64_t)kChunkTable * 256) return launch_kp_c4w4<GEN>(a, s, grid);
       return launch_kp_g<2, 8, GEN, SORTED>(a, s, grid);
     case 256: return launch_kp_g<2, 4, GEN, SORTED>(a, s, grid);
     case 128: return launch_kp_g<1, 4, GEN, SORTED>(a, s, grid);
