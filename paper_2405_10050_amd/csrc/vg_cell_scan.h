@@ -395,8 +395,8 @@ __device__ __forceinline__ float key_bound(uint32_t key) {
 // these, the rounding of the inverted nodes and of the FP32 or split-BF16
 // products with room to spare.  Closer groups (x_i inside or near the ball)
 // are always needed.
-template <int DK, int C, int NB, int WAVES, bool SORTED, bool CENTRES, bool WIN, class Stage, class Block,
-          class Put, class Centres, class Window>
+template <int DK, int C, int NB, int WAVES, bool SORTED, bool CENTRES, bool WIN, bool BIG, class Stage,
+          class Block, class Put, class Centres, class Window>
 __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, const float (&xi)[DK],
                                            const float (&best)[C], const float (&second)[C], float &nn2,
                                            float *bnd, float *wsm, uint32_t *wmask, float *ctab, float *rho,
@@ -440,13 +440,35 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
     // ones are below it too).  Clouds of more chunks than the table holds
     // walk outwards from x_i's chunk in scan order instead, with each bound
     // computed as the walk reaches it.  The order decides only the speed.
-    const bool table = nch <= kChunkTable;
+    //
+    // BIG (an instance of its own, for clouds of more chunks than the table
+    // holds): each entry is shared by S consecutive chunks and keyed by the
+    // largest of their bounds; the walk takes the entries in that order and,
+    // inside an entry, the chunks whose own bound reaches the threshold, and
+    // it ends at the first entry whose key is below the threshold.  Its state
+    // would cost the other instances registers.
+    const bool table = !BIG && nch <= kChunkTable;
+    const int S = BIG ? (nch + kChunkTable - 1) / kChunkTable : 1;  // chunks per entry
+    const int nent = BIG ? (nch + S - 1) / S : nch;
     uint32_t *ckey = reinterpret_cast<uint32_t *>(ctab);
-    if (table) {
+    if (BIG || table) {
       int p2 = 2;
-      while (p2 < nch) p2 <<= 1;
-      for (int c = tid; c < p2; c += WAVES * 64)
-        ckey[c] = c < nch ? chunk_key(chunk_bound_thread<NB, DK>(a, xi, c), c) : 0u;  // 0: after every chunk
+      while (p2 < nent) p2 <<= 1;
+      if constexpr (BIG) {
+        for (int e = tid; e < p2; e += WAVES * 64) {
+          uint32_t key = 0u;  // 0: after every entry
+          if (e < nent) {
+            float b = 0.f;
+            const int c1 = min(e * S + S, nch);
+            for (int c = e * S; c < c1; ++c) b = fmaxf(b, chunk_bound_thread<NB, DK>(a, xi, c));
+            key = chunk_key(b, e);
+          }
+          ckey[e] = key;
+        }
+      } else {
+        for (int c = tid; c < p2; c += WAVES * 64)
+          ckey[c] = c < nch ? chunk_key(chunk_bound_thread<NB, DK>(a, xi, c), c) : 0u;  // 0: after every chunk
+      }
       __syncthreads();  // uniform: table depends on n only
       // bitonic sort, descending
       for (int k = 2; k <= p2; k <<= 1) {
@@ -464,8 +486,29 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       }
     }
     int spos = 0;  // table: next position in the sorted keys
-    // the walk's next chunk other than x_i's own (-1: none left) and its bound
-    auto next_chunk = [&](float &bnd) -> int {
+    int enext = 0, eend = 0;  // BIG: chunks of the current entry not yet taken
+    // the walk's next chunk other than x_i's own (-1: none left) and its
+    // bound; BIG: only chunks whose bound reaches thr_now
+    auto next_chunk = [&](float &bnd, float thr_now) -> int {
+      if constexpr (BIG) {
+        for (;;) {
+          while (enext < eend) {
+            const int c = enext++;
+            if (c == c0) continue;
+            bnd = chunk_bound<NB, DK>(a, xi, c, lane);
+            if (bnd < thr_now) continue;
+            return c;
+          }
+          if (spos >= nent) return -1;
+          const uint32_t key = __builtin_amdgcn_readfirstlane(ckey[spos++]);
+          if (key_bound(key) < thr_now) {  // so are the later entries
+            spos = nent;
+            return -1;
+          }
+          enext = (int)(key & (uint32_t)(kChunkTable - 1)) * S;
+          eend = min(enext + S, nch);
+        }
+      }
       if (table) {
         while (spos < nch) {
           const uint32_t key = ckey[spos++];
@@ -480,9 +523,12 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       if (c >= 0) bnd = chunk_bound<NB, DK>(a, xi, c, lane);
       return c;
     };
-    auto walk_done = [&]() { return table ? spos >= nch : walk.done(); };
+    auto walk_done = [&]() {
+      if constexpr (BIG) return spos >= nent && enext >= eend;
+      return table ? spos >= nch : walk.done();
+    };
     // a chunk's bound fell below the threshold: in the sorted walk so does
-    // every later one
+    // every later one (BIG: such chunks are skipped inside next_chunk)
     auto below = [&]() {
       if (table) spos = nch;
     };
@@ -515,7 +561,7 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
       slot_chunk = -1;
       while (cnt < WS) {
         float b;
-        const int c = next_chunk(b);
+        const int c = next_chunk(b, thr_now);
         if (c < 0) break;
         if (b < thr_now) {
           if (table) {
@@ -652,14 +698,14 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
         pop();
       } else {
         float b;
-        next = next_chunk(b);
+        next = next_chunk(b, thr);
         while (next >= 0 && b < thr) {
           if (table) {
             below();
             next = -1;
             break;
           }
-          next = next_chunk(b);
+          next = next_chunk(b, thr);
         }
       }
       if (next >= 0) load_node<DK>(a.xs, n, d, (int64_t)next * NB + tid, pre);
@@ -909,7 +955,7 @@ __device__ __forceinline__ f32x16 scan_block(const float (&A)[KP], const float (
 // floats, ctab the sorted chunk keys, cen the half-block centres.  One
 // accumulator set per wave is reused by the column blocks in turn: separate
 // sets would cost the occupancy that hides each block's epilogue.
-template <int KP, int C, int WAVES, bool GEN, bool SORTED>
+template <int KP, int C, int WAVES, bool GEN, bool SORTED, bool BIG = false>
 __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t cell, int chunk,
                                                float *__restrict__ lds, float *red, float *ctab, float *cen) {
   constexpr int NT = WAVES * 64;
@@ -991,7 +1037,7 @@ __device__ __forceinline__ void scan_fp32_item(const CellScanArgs &a, int64_t ce
   const int64_t n_scan = a.nbr ? a.nbr_off[cell + 1] - nb0 : n;
   // block centres (scan order, d >= 3)
   constexpr bool CEN = SORTED && KP >= 2;
-  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, SORTED>(
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, SORTED, BIG>(
       a, cell, xi, best, second, nn2, bnd, wsm, wmask, ctab, cen + 16 * 32, nb0, n_scan, rayw, prune,
       [&](const float (&rt)[DK]) {
 #pragma unroll
@@ -1072,6 +1118,20 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
   scan_fp32_item<KP, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, ctab, cen);
 }
 
+// The scan in scan order of a cloud of more chunks than the chunk table
+// holds (each table entry shared by consecutive chunks, see scan_chunks).
+template <int KP, int C, int WAVES, bool GEN>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVES == 4 && C == 4 ? (KP <= 2 ? 5 : 4) : (WAVES == 4 && KP <= 6 ? 5 : (WAVES == 8 && KP <= 5 ? 4 : 2))))) void cell_scan_fp32_big_kernel(
+    CellScanArgs a) {
+  __shared__ float lds[Fp32Tile<KP, WAVES>::FLOATS + WAVES * 2 + WAVES * 2 + WAVES * 2];
+  __shared__ float red[WAVES * 64];
+  __shared__ float ctab[kChunkTable];
+  __shared__ float cen[16 * 32 + 32];
+  int chunk;
+  const int64_t cell = item_cell<true>(a, chunk);
+  scan_fp32_item<KP, C, WAVES, GEN, true, true>(a, cell, chunk, lds, red, ctab, cen);
+}
+
 // ---------------------------------------------------------------- BF16x3
 // Split-precision variant: a = a_hi + a_lo with a_hi = bf16(a) and
 // a_lo = bf16(a - a_hi); u.r~ ~ sum hi*hi + hi*lo + lo*hi with FP32
@@ -1105,7 +1165,7 @@ __device__ __forceinline__ f32x16 scan_block_bf16(const bf16x8 (&A)[KQ], const b
 // One work item of the BF16x3 scan; lds holds WAVES*64 * KT/8 bf16x8, bnd
 // the NB/32 block bounds, 2 x WAVES chunk thresholds and 2 x WAVES window
 // masks, ctab the walk's sorted chunk keys.
-template <int KQ, int C, int WAVES, bool GEN, bool SORTED>
+template <int KQ, int C, int WAVES, bool GEN, bool SORTED, bool BIG = false>
 __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t cell, int chunk,
                                                  bf16x8 *__restrict__ lds, float *red, float *bnd, float *ctab,
                                                  float *cen) {
@@ -1183,7 +1243,7 @@ __device__ __forceinline__ void scan_bf16x3_item(const CellScanArgs &a, int64_t 
   // The window test of the walk: with four column blocks its registers cost
   // a wave per SIMD (3 instead of 4) and the d=10 mixture scan 25 %.
   constexpr bool WIN = SORTED && C <= 2;
-  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, WIN>(
+  const int blocks = scan_chunks<DK, C, NB, WAVES, SORTED, CEN, WIN, BIG>(
       a, cell, xi, best, second, nn2, bnd, bnd + NB / 32, reinterpret_cast<uint32_t *>(bnd + NB / 32 + 2 * WAVES),
       ctab, cen + 16 * 32, nb0, n_scan, rayw, prune,
       [&](const float (&rt)[DK]) {
@@ -1284,27 +1344,51 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2)))
   scan_bf16x3_item<KQ, C, WAVES, GEN, SORTED>(a, cell, chunk, lds, red, bnd, ctab, cen);
 }
 
-template <int C, int WAVES, bool GEN, bool SORTED>
-hipError_t launch_kq_g(const CellScanArgs &a, hipStream_t s, int grid) {
-  dim3 blk(WAVES * 64);
-  if (a.d <= 5)
-    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<1, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a);
-  else if (a.d <= 10)
-    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<2, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a);
+// The same for clouds of more chunks than the chunk table holds.
+template <int KQ, int C, int WAVES, bool GEN>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(2))) void cell_scan_bf16x3_big_kernel(
+    CellScanArgs a) {
+  __shared__ bf16x8 lds[WAVES * 64 * (Bf16Pack<KQ>::KT / 8)];
+  __shared__ float red[WAVES * 64];
+  __shared__ float bnd[WAVES * 2 + WAVES * 2 + WAVES * 2];
+  __shared__ float ctab[kChunkTable];
+  __shared__ float cen[16 * 32 + 32];
+  int chunk;
+  const int64_t cell = item_cell<true>(a, chunk);
+  scan_bf16x3_item<KQ, C, WAVES, GEN, true, true>(a, cell, chunk, lds, red, bnd, ctab, cen);
+}
+
+template <int KQ, int C, int WAVES, bool GEN, bool SORTED, bool BIG>
+void launch_kq_one(const CellScanArgs &a, hipStream_t s, int grid) {
+  if constexpr (BIG)
+    hipLaunchKernelGGL((cell_scan_bf16x3_big_kernel<KQ, C, WAVES, GEN>), dim3(grid), dim3(WAVES * 64), 0, s, a);
   else
-    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<3, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a);
+    hipLaunchKernelGGL((cell_scan_bf16x3_kernel<KQ, C, WAVES, GEN, SORTED>), dim3(grid), dim3(WAVES * 64), 0, s, a);
+}
+
+template <int C, int WAVES, bool GEN, bool SORTED, bool BIG = false>
+hipError_t launch_kq_g(const CellScanArgs &a, hipStream_t s, int grid) {
+  if (a.d <= 5)
+    launch_kq_one<1, C, WAVES, GEN, SORTED, BIG>(a, s, grid);
+  else if (a.d <= 10)
+    launch_kq_one<2, C, WAVES, GEN, SORTED, BIG>(a, s, grid);
+  else
+    launch_kq_one<3, C, WAVES, GEN, SORTED, BIG>(a, s, grid);
   return hipGetLastError();
 }
 
 
-template <int C, int WAVES, bool GEN, bool SORTED>
+template <int C, int WAVES, bool GEN, bool SORTED, bool BIG = false>
 hipError_t launch_kp_g(const CellScanArgs &a, hipStream_t s, int grid) {
   const int kp = (a.d + 1) / 2;
   dim3 blk(WAVES * 64);
   switch (kp) {
-#define VG_CASE(K)                                                              \
-  case K:                                                                       \
-    hipLaunchKernelGGL((cell_scan_fp32_kernel<K, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a); \
+#define VG_CASE(K)                                                                                        \
+  case K:                                                                                                 \
+    if constexpr (BIG)                                                                                    \
+      hipLaunchKernelGGL((cell_scan_fp32_big_kernel<K, C, WAVES, GEN>), dim3(grid), blk, 0, s, a);        \
+    else                                                                                                  \
+      hipLaunchKernelGGL((cell_scan_fp32_kernel<K, C, WAVES, GEN, SORTED>), dim3(grid), blk, 0, s, a);    \
     break;
     VG_CASE(1)
     VG_CASE(2)
@@ -1342,28 +1426,43 @@ hipError_t launch_kp_c4w4(const CellScanArgs &a, hipStream_t s, int grid) {
   return hipGetLastError();
 }
 
+// A cloud in scan order of more chunks (WAVES * 64 nodes each) than the chunk
+// table holds takes the big-cloud instance of the shape.
+template <int C, int WAVES, bool GEN, bool SORTED>
+hipError_t launch_kp_set(const CellScanArgs &a, hipStream_t s, int grid) {
+  if constexpr (SORTED)
+    if ((a.n + WAVES * 64 - 1) / (WAVES * 64) > kChunkTable) return launch_kp_g<C, WAVES, GEN, true, true>(a, s, grid);
+  return launch_kp_g<C, WAVES, GEN, SORTED>(a, s, grid);
+}
+template <int C, int WAVES, bool GEN, bool SORTED>
+hipError_t launch_kq_set(const CellScanArgs &a, hipStream_t s, int grid) {
+  if constexpr (SORTED)
+    if ((a.n + WAVES * 64 - 1) / (WAVES * 64) > kChunkTable) return launch_kq_g<C, WAVES, GEN, true, true>(a, s, grid);
+  return launch_kq_g<C, WAVES, GEN, SORTED>(a, s, grid);
+}
+
 // Every tile shape of one (GEN, SORTED) instance set; each set is compiled in
 // a translation unit of its own (vg_cell_scan*.hip).
 template <bool GEN, bool SORTED>
 hipError_t launch_cells_set(const CellScanArgs &a, bool bf16, int rw, int grid, hipStream_t s) {
   if (bf16) {
     switch (rw) {
-      case 1024: return launch_kq_g<4, 8, GEN, SORTED>(a, s, grid);
-      case 512: return launch_kq_g<2, 8, GEN, SORTED>(a, s, grid);
-      case 256: return launch_kq_g<2, 4, GEN, SORTED>(a, s, grid);
-      case 128: return launch_kq_g<1, 4, GEN, SORTED>(a, s, grid);
-      default: return launch_kq_g<1, 2, GEN, SORTED>(a, s, grid);
+      case 1024: return launch_kq_set<4, 8, GEN, SORTED>(a, s, grid);
+      case 512: return launch_kq_set<2, 8, GEN, SORTED>(a, s, grid);
+      case 256: return launch_kq_set<2, 4, GEN, SORTED>(a, s, grid);
+      case 128: return launch_kq_set<1, 4, GEN, SORTED>(a, s, grid);
+      default: return launch_kq_set<1, 2, GEN, SORTED>(a, s, grid);
     }
   }
   switch (rw) {
-    case 1024: return launch_kp_g<4, 8, GEN, SORTED>(a, s, grid);
+    case 1024: return launch_kp_set<4, 8, GEN, SORTED>(a, s, grid);
     case 512:
       if constexpr (SORTED)
         if (a.d <= 6 && a.n <= (int64_t)kChunkTable * 256) return launch_kp_c4w4<GEN>(a, s, grid);
-      return launch_kp_g<2, 8, GEN, SORTED>(a, s, grid);
-    case 256: return launch_kp_g<2, 4, GEN, SORTED>(a, s, grid);
-    case 128: return launch_kp_g<1, 4, GEN, SORTED>(a, s, grid);
-    default: return launch_kp_g<1, 2, GEN, SORTED>(a, s, grid);
+      return launch_kp_set<2, 8, GEN, SORTED>(a, s, grid);
+    case 256: return launch_kp_set<2, 4, GEN, SORTED>(a, s, grid);
+    case 128: return launch_kp_set<1, 4, GEN, SORTED>(a, s, grid);
+    default: return launch_kp_set<1, 2, GEN, SORTED>(a, s, grid);
   }
 }
 

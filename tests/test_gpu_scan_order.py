@@ -185,16 +185,18 @@ def test_scan_order_non_unit_directions(vg, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("d", [3, 5])
-def test_scan_order_beyond_the_chunk_table(vg, d, precision):
+@pytest.mark.parametrize("d,kind", [(3, "uni"), (5, "uni"), (4, "gmm")])
+def test_scan_order_beyond_the_chunk_table(vg, d, kind, precision):
     """More chunks than the LDS table of sorted chunk bounds holds (2048):
-    64 rays per cell run 128-node chunks, so N = 300 000 has 2344 and the
-    walk goes outwards in scan order with each bound computed on the way.
+    64 rays per cell run 128-node chunks, so N = 300 000 has 2344, and the
+    big-cloud kernel shares each table entry among two consecutive chunks
+    (keyed by the larger bound, each chunk's own bound checked inside).
     Still the index-order bits."""
-    print(f"beyond table d={d} {precision}", flush=True)
+    print(f"beyond table d={d} {kind} {precision}", flush=True)
     dev = torch.device("cuda", 0)
     n, R = 300_000, 64
-    X = torch.from_numpy(W.uniform_cloud(n, d, seed=90 + d)).to(dev)
+    X = W.gaussian_mixture_cloud(n=n, d=d, seed=90 + d) if kind == "gmm" else W.uniform_cloud(n, d, seed=90 + d)
+    X = torch.from_numpy(X).to(dev)
     a, b = _both(vg, X, precision=precision, seed=91, R=R)
     _assert_same(a, b)
     assert a[3]["scan_pairs"] < 0.2 * b[3]["scan_pairs"]
