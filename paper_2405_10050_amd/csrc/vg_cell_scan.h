@@ -437,16 +437,16 @@ __device__ __forceinline__ int scan_chunks(const CellScanArgs &a, int64_t cell, 
     // largest down: the walk then takes the chunks most likely to hold the
     // rays' winners first, so the thresholds rise sooner, and it ends at the
     // first chunk whose bound is below the workgroup's threshold (all later
-    // ones are below it too).  Clouds of more chunks than the table holds
-    // walk outwards from x_i's chunk in scan order instead, with each bound
-    // computed as the walk reaches it.  The order decides only the speed.
+    // ones are below it too).  The order decides only the speed.
     //
-    // BIG (an instance of its own, for clouds of more chunks than the table
-    // holds): each entry is shared by S consecutive chunks and keyed by the
+    // Clouds of more chunks than the table holds are launched on the BIG
+    // instance: each entry is shared by S consecutive chunks and keyed by the
     // largest of their bounds; the walk takes the entries in that order and,
     // inside an entry, the chunks whose own bound reaches the threshold, and
-    // it ends at the first entry whose key is below the threshold.  Its state
-    // would cost the other instances registers.
+    // it ends at the first entry whose key is below the threshold (its state
+    // would cost the other instances registers).  The other instances, given
+    // such a cloud, walk outwards from x_i's chunk in scan order, with each
+    // bound computed as the walk reaches it.
     const bool table = !BIG && nch <= kChunkTable;
     const int S = BIG ? (nch + kChunkTable - 1) / kChunkTable : 1;  // chunks per entry
     const int nent = BIG ? (nch + S - 1) / S : nch;
