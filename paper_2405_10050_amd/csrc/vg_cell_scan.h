@@ -1448,7 +1448,17 @@ hipError_t launch_cells_set(const CellScanArgs &a, bool bf16, int rw, int grid, 
   if (bf16) {
     switch (rw) {
       case 1024: return launch_kq_set<4, 8, GEN, SORTED>(a, s, grid);
-      case 512: return launch_kq_set<2, 8, GEN, SORTED>(a, s, grid);
+      case 512:
+        // d <= 4 in scan order: four column blocks x four waves, as in the
+        // FP32 scan (uniform clouds, N = 5e4: d=3 7.2 -> 5.9 ms, d=4 11.6 ->
+        // 10.3 ms; from d = 6 on, where four column blocks also turn the
+        // centre bound on, -17 to +10 % by cloud, so those keep two x eight)
+        if constexpr (SORTED)
+          if (a.d <= 4 && a.n <= (int64_t)kChunkTable * 256) {
+            launch_kq_one<1, 4, 4, GEN, true, false>(a, s, grid);
+            return hipGetLastError();
+          }
+        return launch_kq_set<2, 8, GEN, SORTED>(a, s, grid);
       case 256: return launch_kq_set<2, 4, GEN, SORTED>(a, s, grid);
       case 128: return launch_kq_set<1, 4, GEN, SORTED>(a, s, grid);
       default: return launch_kq_set<1, 2, GEN, SORTED>(a, s, grid);
